@@ -1,0 +1,144 @@
+"""Seeded synthetic workloads for the SPDE-driven covariance model.
+
+This module only synthesises inputs: the grid and parameter configuration of
+each workload, the observed sample y, and the Gaussian draws of the fixed
+sketching test matrices.  It contains no step of the likelihood method
+(no peeling, factorisation or trace); both the HIP library's tests and the
+CPU oracle take their inputs from here.
+
+Model (paper Sec. 2.1, eq. "cov model" with a linear map, so the linearised
+covariance is exact):  y = sigma * A^{-1} B^{-1} w + tau * eps,
+    B = kappa^2 I - Lap,   A = I - alpha Lap,
+with Lap the 3-point (1D) or 5-point (2D) Dirichlet Laplacian on the open
+unit interval/square, h = 1/(N+1), and w, eps ~ N(0, I).  B is the
+finite-difference analogue of the Whittle operator (1/l^2 - Delta) of the
+paper's Matern SPDE (Sec. 5.1, eq. "SPDE") with kappa = 1/l.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, replace
+import math
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+PARAM_NAMES = ("kappa", "alpha", "tau2", "sigma2")
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    dim: int            # 1 or 2
+    N: int              # grid side (1D: number of points)
+    leaf: int           # target leaf size; levels = floor(log2(n / leaf))
+    rank: int           # off-diagonal target rank r
+    oversample: int     # extra sketch columns used once, when the sketch is created
+    kappa: float
+    alpha: float
+    tau2: float
+    sigma2: float
+    free: tuple         # free parameters, in gradient / Fisher order
+    data_seed: int
+    sketch_seed: int
+
+    @property
+    def n(self) -> int:
+        return self.N if self.dim == 1 else self.N * self.N
+
+    @property
+    def h(self) -> float:
+        return 1.0 / (self.N + 1)
+
+    @property
+    def levels(self) -> int:
+        return int(math.floor(math.log2(self.n / self.leaf)))
+
+    @property
+    def ell(self) -> int:
+        return self.rank + self.oversample
+
+    @property
+    def theta_full(self) -> np.ndarray:
+        return np.array([self.kappa, self.alpha, self.tau2, self.sigma2], dtype=np.float64)
+
+    @property
+    def free_idx(self) -> tuple:
+        return tuple(PARAM_NAMES.index(f) for f in self.free)
+
+    @property
+    def theta(self) -> np.ndarray:
+        return self.theta_full[list(self.free_idx)]
+
+    def with_theta(self, theta) -> "Workload":
+        vals = dict(zip(self.free, [float(t) for t in theta]))
+        return replace(self, **vals)
+
+
+# sigma^2 of the 256^2 workload at the generating parameters.  The workload is
+# the 128^2 model on a 256^2 grid "with K scaled by sigma^2", so its true value
+# is the unscaled model's, 1.  (A unit-marginal-variance scaling, ~5.3e8, makes
+# the rank-48 approximation indefinite on the 64^2 analogue.)
+SIGMA2_256 = 1.0
+
+WORKLOADS = {
+    # 1D, n=1024: the small plain-FP64 case.
+    "1d_n1024": Workload("1d_n1024", 1, 1024, 64, 16, 10, 10.0, 0.01, 1e-4, 1.0,
+                         ("kappa", "tau2"), 1, 101),
+    # 2D 128x128 (n=16384), theta = (kappa, alpha, tau2).
+    "2d_n16384": Workload("2d_n16384", 2, 128, 256, 32, 10, 20.0, 2e-4, 1e-3, 1.0,
+                          ("kappa", "alpha", "tau2"), 2, 102),
+    # 2D 256x256 (n=65536), theta = (kappa, alpha, tau2, sigma2): the headline case.
+    "2d_n65536": Workload("2d_n65536", 2, 256, 256, 48, 10, 20.0, 2e-4, 1e-3, SIGMA2_256,
+                          ("kappa", "alpha", "tau2", "sigma2"), 3, 103),
+    # Same model on a 64x64 grid (n=4096): the dense-oracle-sized companion.
+    "2d_n4096": Workload("2d_n4096", 2, 64, 256, 48, 10, 20.0, 2e-4, 1e-3, SIGMA2_256,
+                         ("kappa", "alpha", "tau2", "sigma2"), 3, 103),
+}
+
+
+def small_workload(dim=2, N=32, leaf=64, rank=16, oversample=10, free=("kappa", "alpha", "tau2", "sigma2"),
+                   kappa=20.0, alpha=2e-4, tau2=1e-3, sigma2=1.0e3, data_seed=7, sketch_seed=70,
+                   name=None) -> Workload:
+    """A small workload with the shape of the headline one, for parity tests."""
+    return Workload(name or f"{dim}d_N{N}_leaf{leaf}_r{rank}", dim, N, leaf, rank, oversample,
+                    kappa, alpha, tau2, sigma2, tuple(free), data_seed, sketch_seed)
+
+
+def _lap(dim: int, N: int) -> sp.csc_matrix:
+    h = 1.0 / (N + 1)
+    e = np.ones(N)
+    t1 = sp.diags([-e[:-1], 2 * e, -e[:-1]], [-1, 0, 1]) / (h * h)
+    if dim == 1:
+        return t1.tocsc()
+    i1 = sp.identity(N)
+    # grid index = iy * N + ix  (x fastest)
+    return (sp.kron(i1, t1) + sp.kron(t1, i1)).tocsc()
+
+
+def sample_y(w: Workload) -> np.ndarray:
+    """One draw y = sigma A^-1 B^-1 w + tau eps in natural grid order (x fastest).
+
+    w then eps are drawn from numpy.random.default_rng(data_seed), in that order.
+    """
+    rng = np.random.default_rng(w.data_seed)
+    wv = rng.standard_normal(w.n)
+    ev = rng.standard_normal(w.n)
+    T = _lap(w.dim, w.N)
+    I = sp.identity(w.n, format="csc")
+    A = (I + w.alpha * T).tocsc()
+    B = (w.kappa ** 2 * I + T).tocsc()
+    v = spla.spsolve(B, wv)
+    v = spla.spsolve(A, v)
+    return math.sqrt(w.sigma2) * v + math.sqrt(w.tau2) * ev
+
+
+def sketch_draws(w: Workload) -> np.ndarray:
+    """Gaussian draws for the fixed sketching matrices: shape (levels, ell, n).
+
+    omega[l-1, j, i] is the draw for tree position i (rows in tree order), sketch
+    column j, at level l.  Only rows of right children at depth l are used by the
+    method; the others are ignored.  Drawn once from default_rng(sketch_seed).
+    """
+    rng = np.random.default_rng(w.sketch_seed)
+    return rng.standard_normal((w.levels, w.ell, w.n))
