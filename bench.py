@@ -1,0 +1,128 @@
+"""Benchmark: H-MLE iterations/s on one MI355X.
+
+One step = one likelihood iteration of the hot path on the 256x256 SPDE workload
+(n = 65536, leaf 256, 8 levels, rank 48, theta = (kappa, alpha, tau2, sigma2)):
+build K~ and the derivative matrices by randomized peeling, factor, log|K~|,
+log-likelihood + NLL gradient (exact traces), and the 4x4 expected Fisher matrix.
+Inputs (sample y, sketch draws, fixed test matrices) are resident in HBM before
+the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "H-MLE iters/s (build+factor+logdet+grad+FIM) at n=65536; % HBM/MFMA roofline"
+
+
+def cpu_baseline(sample_key="2d_n4096", full_n=65536):
+    """Time the CPU oracle on one iteration of a smaller grid with the same model."""
+    import numpy as np
+    from synth import WORKLOADS, sample_y, sketch_draws
+    from oracle import peeling
+    from oracle.exact import likelihood_gradient_fisher
+    from oracle.model import Tree, dense_covariance, to_tree_order
+
+    w = WORKLOADS[sample_key]
+    y = sample_y(w)
+    om = sketch_draws(w)
+    t0 = time.perf_counter()
+    K, dKs = dense_covariance(w.dim, w.N, w.theta_full, w.free)
+    tree = Tree(w.dim, w.N, w.levels)
+    Kt = to_tree_order(tree, K)
+    dKt = [to_tree_order(tree, d) for d in dKs]
+    V = peeling.sketch_create(Kt, tree, om, w.rank)
+    rep = peeling.build(Kt, dKt, tree, om, V)
+    likelihood_gradient_fisher(rep["Kt"], rep["dKts"], to_tree_order(tree, y))
+    dt = time.perf_counter() - t0
+    scale = (full_n / w.n) ** 3
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": 1.0 / (dt * scale),
+        "unit": "iters/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"one oracle iteration (dense assembly, peeling replay, dense L/grad/FIM) on the "
+                  f"{w.N}x{w.N} grid (n={w.n}) took {dt:.2f} s; extrapolated to n={full_n} by n^3 "
+                  f"(x{scale:.0f})",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="2d_n65536")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
+                                   "but not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2303_10102_amd import hmle
+    from synth import WORKLOADS, sample_y, sketch_draws
+
+    w = WORKLOADS[args.workload]
+    print(f"[bench] workload {w.name}: n={w.n} levels={w.levels} leaf={w.leaf} rank={w.rank}", file=sys.stderr,
+          flush=True)
+    y = torch.from_numpy(sample_y(w)).cuda()
+    om = torch.from_numpy(sketch_draws(w)).cuda()
+    m = hmle.Model(w.dim, w.N, w.leaf, device=0)
+    t0 = time.perf_counter()
+    s = hmle.Sketch(m, om, w.rank, w.oversample, w.theta_full)
+    torch.cuda.synchronize()
+    t_sketch = time.perf_counter() - t0
+    del om
+    H = hmle.HMatrix(s, w.free)
+    theta = w.theta_full
+    print(f"[bench] sketch created in {t_sketch:.2f} s; warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        ll, g, fim = H.iteration(theta, y)
+    torch.cuda.synchronize()
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ll, g, fim = H.iteration(theta, y)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = 1e3 * dt / args.steps
+    rec = {
+        "metric": METRIC,
+        "value": args.steps / dt,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: 2D SPDE {w.N}x{w.N} grid, n={w.n}, leaf {w.leaf}, {w.levels} levels, "
+                               f"rank {w.rank} (+{w.oversample} once), theta=(kappa,alpha,tau2,sigma2)",
+                   "n": w.n, "rank": w.rank, "leaf": w.leaf, "params": list(w.free)},
+        "loglik": ll,
+        "grad_nll": [float(v) for v in g],
+        "fim_diag": [float(fim[i, i]) for i in range(len(g))],
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

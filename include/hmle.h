@@ -1,0 +1,141 @@
+/*
+ * hmle.h -- C ABI of the MI355X hierarchical-matrix maximum-likelihood library.
+ *
+ * What it computes (Chen & Anitescu, "Scalable Physics-based Maximum Likelihood
+ * Estimation using Hierarchical Matrices"):
+ *   K(theta) = sigma2 * A^{-1} B^{-1} B^{-T} A^{-T} + tau2 * I           (Sec. 2.1, eq. "cov model")
+ *   with B = kappa^2 I - Lap, A = I - alpha Lap on a Dirichlet grid (Sec. 5.1, eq. "SPDE"
+ *   analogue), accessed only through products with blocks of vectors;
+ *   K~(theta) ~ K(theta) in HODLR form built by randomized peeling            (Sec. 3.1-3.2, Alg. 1)
+ *   K~_j = dK~/dtheta_j in the same format, by differentiating the peeling     (Sec. 3.3, Alg. 2)
+ *   log|K~|, K~^{-1} y via the leaf-times-low-rank-updates factorisation       (Sec. 3.1, eq. "one way factor"; App. C)
+ *   L~, grad(-L~), and I~_ij = 1/2 tr(K~^{-1} K~_i K~^{-1} K~_j)              (Sec. 4, eqs. "log-like approximated",
+ *                                                                              "score approximated", "fisher info approximated")
+ * with exact traces of HODLR products (Sec. 4.2, App. B) -- no stochastic estimator.
+ *
+ * Conventions
+ *   * Every call returns hm_status; nothing throws across the ABI.  On failure
+ *     hm_last_error() describes the cause.
+ *   * Device buffers are plain device pointers (hipMalloc'd or from any caching
+ *     allocator) owned by the caller; the library never frees them.  Host
+ *     buffers are plain host pointers owned by the caller.
+ *   * All device work is enqueued on the stream given to hm_model_create; calls
+ *     that return host scalars synchronise that stream once before returning.
+ *   * Vectors y, x passed to solve / loglik are in natural grid order
+ *     (row-major, x fastest).  Sketch draws are indexed by tree position.
+ *   * The full parameter vector is theta_full[4] = (kappa, alpha, tau2, sigma2);
+ *     the "free" parameters (gradient / Fisher order) are chosen by index.
+ *   * Not thread-safe per handle: calls on one handle must not overlap.
+ */
+#ifndef HMLE_H
+#define HMLE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HM_OK = 0,
+  HM_E_INVAL = 1,      /* bad sizes, unsupported shape, bad parameter (tau2 <= 0, ...) */
+  HM_E_NOMEM = 2,      /* device allocation failed */
+  HM_E_NOT_SPD = 3,    /* a leaf Cholesky pivot <= 0, or det(I + V^T U) <= 0 at a node */
+  HM_E_RANK = 4,       /* every sketch block of a level has rank 0 */
+  HM_E_NONFINITE = 5,  /* NaN/Inf in theta or detected on the device */
+  HM_E_STATE = 6,      /* call out of order (e.g. fisher before factor) */
+  HM_E_DEVICE = 7      /* HIP runtime error */
+} hm_status;
+
+typedef struct hm_model hm_model;   /* grid, tree ordering, transform tables, stream */
+typedef struct hm_sketch hm_sketch; /* fixed test matrices (drawn once, Sec. 3.3) + frozen compression */
+typedef struct hm_H hm_H;           /* K~(theta), K~_j(theta), factorisation, per-iteration workspace */
+
+/* Last error message of the calling thread (static storage, valid until the next call). */
+const char* hm_last_error(void);
+
+/* ---------------------------------------------------------------- model ---
+ * hm_model_create: the stencil covariance model on a dim-D grid of side N
+ * (n = N for dim 1, N*N for dim 2; h = 1/(N+1), Dirichlet boundary).
+ * leaf: target leaf size; levels = floor(log2(n/leaf)) (Sec. 5.2 rule).
+ * The tree is the recursive coordinate bisection of the grid (Sec. 5.2, KD-tree
+ * ordering): split the longer side (x on ties), left child gets floor(side/2).
+ * This build requires every split to be even (uniform leaves): else HM_E_INVAL.
+ * device: HIP device ordinal; stream: hipStream_t to enqueue on (NULL = default).
+ */
+hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm_model** out);
+void hm_model_destroy(hm_model* m);
+/* n, levels, leaf size (uniform). Any pointer may be NULL. */
+hm_status hm_model_info(const hm_model* m, int* n, int* levels, int* leaf);
+/* Copy the tree->grid permutation (n ints, perm[tree_pos] = grid index) to a host buffer. */
+hm_status hm_model_perm(const hm_model* m, int* perm_host);
+
+/* K-apply of the physics model (the only access to K the method uses, Sec. 3.2):
+ * Y = op(theta) X with op = K (which=0), dK/dkappa (1), dK/dalpha (2).
+ * X, Y: device, n x c column-major in TREE order with leading dimensions ldx, ldy >= n.
+ * Exact direct stencil solves (sine transform along x, tridiagonal solves along y). */
+hm_status hm_kapply(hm_model* m, const double* theta_full, const double* X, int ldx, int c, double* Y,
+                    int ldy, int which);
+
+/* --------------------------------------------------------------- sketch ---
+ * hm_sketch_create: fix the test matrices for all later iterations (Sec. 3.3:
+ * sampling matrices drawn once and kept fixed).  omega: device, levels x ell x n
+ * doubles (omega[((l-1)*ell + j)*n + i] = draw for tree row i, column j, level l),
+ * ell = rank + oversample, N(0,1) entries supplied by the caller; only rows of right
+ * children at depth l are read; the buffer may be freed after the call.
+ * At theta0 each block is sketched with ell columns; the right singular vectors of
+ * that sample keep k = min(rank, #{s_i > 1e-10 s_1}) columns (each signed so that
+ * its largest-magnitude entry is positive), and Omega_b V becomes the block's fixed
+ * k-column test matrix (reading of Alg. 1 step 3 with oversampling).
+ * Fails with HM_E_RANK if a whole level has rank 0. */
+hm_status hm_sketch_create(hm_model* m, const double* omega, int rank, int oversample,
+                           const double* theta0_full, hm_sketch** out);
+void hm_sketch_destroy(hm_sketch* s);
+/* kept rank per block: k_host[2^levels - 1], heap order of the block's parent node
+ * (root 0; children of node x are 2x+1, 2x+2); *kc = panel width (max kept rank). */
+hm_status hm_sketch_ranks(const hm_sketch* s, int* k_host, int* kc);
+
+/* ------------------------------------------------------------------ H ---
+ * hm_H_create: allocate K~ and its p derivative matrices for the free parameters
+ * free_idx[0..p-1] (indices into theta_full, distinct, p <= 4).  All device memory
+ * of the iteration is allocated here; build/factor/... allocate nothing. */
+hm_status hm_H_create(hm_sketch* s, int p, const int* free_idx, hm_H** out);
+void hm_H_destroy(hm_H* H);
+
+/* Build K~(theta) and K~_j(theta) by randomized peeling and its forward-mode
+ * derivative (Sec. 3.2-3.3).  theta_full: host[4]; tau2 > 0, kappa > 0, alpha >= 0,
+ * sigma2 > 0 required (else HM_E_INVAL). */
+hm_status hm_build(hm_H* H, const double* theta_full);
+/* Factor K~ = D (I + U^(tau) V^(tau)T) ... (I + U^(1) V^(1)T) (eq. "one way factor", App. C):
+ * leaf Cholesky + per-node Woodbury factors.  HM_E_NOT_SPD if K~ is not SPD. */
+hm_status hm_factor(hm_H* H);
+/* log|K~| (Sylvester's identity over the factors, Sec. 3.1). Host scalar. */
+hm_status hm_logdet(hm_H* H, double* out);
+/* x = K~^{-1} y (Woodbury, Sec. 3.1) with one step of FP64 refinement against the
+ * H-matvec.  y, x: device, n doubles, natural grid order; may alias. */
+hm_status hm_solve(hm_H* H, const double* y, double* x);
+/* L~ (eq. "log-like approximated", including -n/2 log 2pi) and the NLL gradient
+ * grad[j] = 1/2 tr(K~^{-1} K~_j) - 1/2 y^T K~^{-1} K~_j K~^{-1} y (= -S~_j,
+ * eq. "score approximated").  y: device, grid order.  loglik, grad: host (grad may be NULL). */
+hm_status hm_loglik_grad(hm_H* H, const double* y, double* loglik, double* grad);
+/* Expected Fisher information I~_ij = 1/2 tr(K~^{-1}K~_i K~^{-1}K~_j)
+ * (eq. "fisher info approximated"), exact for the HODLR matrices (App. B).
+ * fim: host, p*p row-major (symmetric); each (i,j) is computed independently. */
+hm_status hm_fisher(hm_H* H, double* fim);
+/* One likelihood iteration: build + factor + logdet + loglik/grad + fisher. */
+hm_status hm_iteration(hm_H* H, const double* theta_full, const double* y, double* loglik,
+                       double* grad, double* fim);
+
+/* Export the representation for inspection (tests):
+ * what=0: panel set of K~, n x (levels*kc), rows in tree order;
+ * what=1+j: panel tangents of K~_j for the j-th free parameter that needs a
+ *           derivative sketch (kappa, alpha), same shape;
+ * what=10: leaf blocks of K~, leaves x nl x nl (leaf-major, column-major);
+ * what=11+j: leaf blocks of K~_j (real parameters), same shape.
+ * dst: device buffer of sufficient size. */
+hm_status hm_export(hm_H* H, int what, double* dst);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HMLE_H */

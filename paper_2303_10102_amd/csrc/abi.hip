@@ -1,0 +1,726 @@
+// C ABI of the H-MLE library: handles, validation, state machine, orchestration.
+// Every call returns hm_status; errors never cross the ABI as exceptions.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hm_build.h"
+#include "hm_factor.h"
+#include "hm_internal.h"
+#include "hm_trace.h"
+
+namespace hm {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+const char* get_error() { return g_err.c_str(); }
+
+constexpr int NSCAL = 512;
+
+// One likelihood iteration's state.  All device memory is allocated in hm_H_create.
+struct HState {
+  Sketch* s = nullptr;
+  Model* m = nullptr;
+  int p = 0;
+  int pidx[4] = {0, 0, 0, 0};
+  int nreal = 0;
+  int realidx[2] = {-1, -1};   // parameter kind (0 kappa, 1 alpha) of each real derivative
+  int realpos[4] = {-1, -1, -1, -1};  // free position -> real derivative slot
+  double theta[4] = {0, 0, 0, 0};
+  int state = 0;               // 0 empty, 1 built, 2 factored, 3 parameters prepared
+  int kc = 0;
+  PanelSet ps;                 // F and the real panel tangents
+  double* D = nullptr;
+  double* dDr[2] = {nullptr, nullptr};
+  FactorCtx f;
+  ParamBufs pb[4];
+  LevelBufs lb;
+  NodeBufs nb;
+  double* gtr[4] = {nullptr, nullptr, nullptr, nullptr};
+  double* node_scratch = nullptr;
+  double* ytree = nullptr;
+  double* z = nullptr;
+  double* r = nullptr;
+  double* v = nullptr;
+  double* d_scal = nullptr;
+  double* d_part = nullptr;
+  double* h_scal = nullptr;
+  std::vector<void*> allocs;
+};
+
+static hm_status dalloc(HState* h, double** p, size_t doubles) {
+  void* q = nullptr;
+  if (hipMalloc(&q, std::max<size_t>(doubles, 1) * sizeof(double)) != hipSuccess) {
+    set_error("device allocation of " + std::to_string(doubles * 8) + " bytes failed");
+    return HM_E_NOMEM;
+  }
+  h->allocs.push_back(q);
+  *p = (double*)q;
+  return HM_OK;
+}
+
+static bool finite4(const double* t) {
+  for (int i = 0; i < 4; ++i)
+    if (!std::isfinite(t[i])) return false;
+  return true;
+}
+
+static hm_status check_theta(const double* t) {
+  if (!t) {
+    set_error("theta is NULL");
+    return HM_E_INVAL;
+  }
+  if (!finite4(t)) {
+    set_error("theta has a non-finite entry");
+    return HM_E_NONFINITE;
+  }
+  if (!(t[0] > 0.0) || !(t[1] >= 0.0) || !(t[2] > 0.0) || !(t[3] > 0.0)) {
+    set_error("theta must satisfy kappa > 0, alpha >= 0, tau2 > 0, sigma2 > 0");
+    return HM_E_INVAL;
+  }
+  return HM_OK;
+}
+
+static hm_status read_flags(Model* m, int* flags) {
+  HM_HIP(hipStreamSynchronize(m->stream));
+  HM_HIP(hipMemcpy(flags, m->d_flags, sizeof(int), hipMemcpyDeviceToHost));
+  return HM_OK;
+}
+
+static hm_status clear_flags(Model* m) {
+  HM_HIP(hipMemsetAsync(m->d_flags, 0, sizeof(int), m->stream));
+  return HM_OK;
+}
+
+// y_tree[t] = y_grid[perm[t]]  /  y_grid[perm[t]] = y_tree[t]
+__global__ void k_permute(const double* in, double* out, const int* perm, int n, int to_tree) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  if (to_tree) out[t] = in[perm[t]];
+  else out[perm[t]] = in[t];
+}
+__global__ void k_add(double* y, const double* x, int n) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) y[t] += x[t];
+}
+
+static hm_status permute(Model* m, const double* in, double* out, int to_tree) {
+  hipLaunchKernelGGL(k_permute, dim3(ceil_div(m->n, 256)), dim3(256), 0, m->stream, in, out, m->d_perm, m->n,
+                     to_tree);
+  HM_LAUNCH_CHECK();
+  return HM_OK;
+}
+
+// z = K~^{-1} ytree with one refinement step against the H-matvec residual
+static hm_status solve_refined(HState* h) {
+  Model* m = h->m;
+  const int n = m->n;
+  HM_CHECK(hsolve(h->f, h->ytree, h->z));
+  HM_HIP(hipMemcpyAsync(h->r, h->ytree, n * sizeof(double), hipMemcpyDeviceToDevice, m->stream));
+  HM_CHECK(hmatvec(h->f, h->D, h->ps.F, nullptr, h->z, 1, h->r, -1.0, 1.0));   // r = y - K~ z
+  HM_CHECK(hsolve(h->f, h->r, h->v));
+  hipLaunchKernelGGL(k_add, dim3(ceil_div(n, 256)), dim3(256), 0, m->stream, h->z, h->v, n);
+  HM_LAUNCH_CHECK();
+  return HM_OK;
+}
+
+// scalar slots in d_scal
+enum : int { SC_LOGDET = 0, SC_YZ = 1, SC_QUAD = 2, SC_LTR = 6, SC_NTR = 10, SC_FIM = 16 };
+
+static hm_status prepare_params(HState* h) {
+  if (h->state >= 3) return HM_OK;
+  Model* m = h->m;
+  const int n = m->n, kc = h->kc, levels = m->levels;
+  bool any_real = false;
+  for (int q = 0; q < h->p; ++q) any_real |= (h->pb[q].kind <= 1);
+  if (any_real && levels >= 2) {
+    // t_c = F_c^T G[c, blocks < depth(c)] shared by every real parameter's Xi
+    const long ts = (long)kc * (levels - 1) * kc;
+    ReduceJob r{h->ps.F, n, cs_block(kc), h->f.G, n, cs_prefix(kc), 2, levels, h->f.nT, ts, sel_all()};
+    HM_CHECK(tree_reduce(m, r));
+  }
+  for (int q = 0; q < h->p; ++q) HM_CHECK(param_prepare(h->f, h->pb[q], h->theta, h->f.nT));
+  HM_CHECK(node_prep(h->f));
+  h->state = 3;
+  return HM_OK;
+}
+
+}  // namespace hm
+
+using namespace hm;
+
+struct hm_model {
+  Model m;
+};
+struct hm_sketch {
+  Sketch s;
+};
+struct hm_H {
+  HState h;
+};
+
+extern "C" {
+
+const char* hm_last_error(void) { return get_error(); }
+
+hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm_model** out) {
+  if (!out) {
+    set_error("out is NULL");
+    return HM_E_INVAL;
+  }
+  *out = nullptr;
+  if ((dim != 1 && dim != 2) || N < 2 || leaf < 1) {
+    set_error("need dim in {1,2}, N >= 2, leaf >= 1");
+    return HM_E_INVAL;
+  }
+  const long n = (dim == 2) ? (long)N * N : N;
+  if (n > (1L << 26)) {
+    set_error("grid too large");
+    return HM_E_INVAL;
+  }
+  int levels = (int)std::floor(std::log2((double)n / leaf) + 1e-12);
+  if (levels < 1 || levels > 20) {
+    set_error("need n >= 2*leaf");
+    return HM_E_INVAL;
+  }
+  // every bisection must split evenly (uniform leaves)
+  {
+    long w = N, hh = (dim == 2) ? N : 1;
+    for (int d = 0; d < levels; ++d) {
+      if (w >= hh) {
+        if (w % 2) { set_error("non-uniform bisection (odd side) is not supported"); return HM_E_INVAL; }
+        w /= 2;
+      } else {
+        if (hh % 2) { set_error("non-uniform bisection (odd side) is not supported"); return HM_E_INVAL; }
+        hh /= 2;
+      }
+    }
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return HM_E_DEVICE;
+  }
+  hm_model* hm_ = new hm_model();
+  Model* m = &hm_->m;
+  m->device = device;
+  m->stream = (hipStream_t)stream;
+  m->dim = dim;
+  m->N = N;
+  m->n = (int)n;
+  m->levels = levels;
+  m->nleaves = 1 << levels;
+  m->nl = (int)(n >> levels);
+  m->Np = (dim == 2) ? N : 1;
+  m->L = N;
+  m->h = 1.0 / (N + 1);
+  m->cmax = std::max(m->nl, 80);
+  bool ok = true;
+  auto A = [&](void** p, size_t bytes) { ok = ok && hipMalloc(p, std::max<size_t>(bytes, 8)) == hipSuccess; };
+  A((void**)&m->d_perm, n * sizeof(int));
+  A((void**)&m->d_iperm, n * sizeof(int));
+  A((void**)&m->d_mu, (size_t)N * sizeof(double));
+  if (dim == 2) A((void**)&m->d_dst, (size_t)N * N * sizeof(double));
+  A((void**)&m->d_thomas, 4 * (size_t)m->L * m->Np * sizeof(double));
+  A((void**)&m->d_ws, 4 * (size_t)n * m->cmax * sizeof(double));
+  A((void**)&m->d_flags, sizeof(int));
+  A((void**)&m->d_ident, (size_t)n * m->nl * sizeof(double));
+  if (!ok) {
+    set_error("device allocation failed in hm_model_create");
+    hm_model_destroy(hm_);
+    return HM_E_NOMEM;
+  }
+  hm_status st = model_tables(m);
+  if (st == HM_OK) st = make_identity_stack(m);
+  if (st == HM_OK && hipMemsetAsync(m->d_flags, 0, sizeof(int), m->stream) != hipSuccess) st = HM_E_DEVICE;
+  if (st == HM_OK && hipStreamSynchronize(m->stream) != hipSuccess) {
+    set_error("hm_model_create: device error");
+    st = HM_E_DEVICE;
+  }
+  if (st != HM_OK) {
+    hm_model_destroy(hm_);
+    return st;
+  }
+  *out = hm_;
+  return HM_OK;
+}
+
+void hm_model_destroy(hm_model* mm) {
+  if (!mm) return;
+  Model* m = &mm->m;
+  void* ps[] = {m->d_perm, m->d_iperm, m->d_dst, m->d_mu, m->d_thomas, m->d_ws, m->d_flags, m->d_ident, m->d_red};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  delete mm;
+}
+
+hm_status hm_model_info(const hm_model* mm, int* n, int* levels, int* leaf) {
+  if (!mm) {
+    set_error("model is NULL");
+    return HM_E_INVAL;
+  }
+  if (n) *n = mm->m.n;
+  if (levels) *levels = mm->m.levels;
+  if (leaf) *leaf = mm->m.nl;
+  return HM_OK;
+}
+
+hm_status hm_model_perm(const hm_model* mm, int* perm_host) {
+  if (!mm || !perm_host) {
+    set_error("NULL argument");
+    return HM_E_INVAL;
+  }
+  const Model* m = &mm->m;
+  HM_HIP(hipStreamSynchronize(m->stream));
+  HM_HIP(hipMemcpy(perm_host, m->d_perm, m->n * sizeof(int), hipMemcpyDeviceToHost));
+  return HM_OK;
+}
+
+hm_status hm_kapply(hm_model* mm, const double* theta_full, const double* X, int ldx, int c, double* Y, int ldy,
+                    int which) {
+  if (!mm || !X || !Y) {
+    set_error("NULL argument");
+    return HM_E_INVAL;
+  }
+  Model* m = &mm->m;
+  HM_CHECK(check_theta(theta_full));
+  if (c < 0 || ldx < m->n || ldy < m->n || which < 0 || which > 2) {
+    set_error("hm_kapply: bad c, leading dimension or operator");
+    return HM_E_INVAL;
+  }
+  return kapply(m, theta_full, X, ldx, c, which == 0 ? Y : nullptr, which == 1 ? Y : nullptr,
+                which == 2 ? Y : nullptr, ldy);
+}
+
+hm_status hm_sketch_create(hm_model* mm, const double* omega, int rank, int oversample, const double* theta0_full,
+                           hm_sketch** out) {
+  if (!mm || !omega || !out) {
+    set_error("NULL argument");
+    return HM_E_INVAL;
+  }
+  *out = nullptr;
+  HM_CHECK(check_theta(theta0_full));
+  if (rank < 1 || rank > 64 || oversample < 0 || rank + oversample > 80) {
+    set_error("need 1 <= rank <= 64 and rank + oversample <= 80");
+    return HM_E_INVAL;
+  }
+  Model* m = &mm->m;
+  if (rank + oversample > (m->n >> m->levels)) {
+    set_error("rank + oversample exceeds the leaf size");
+    return HM_E_INVAL;
+  }
+  hm_sketch* hs = new hm_sketch();
+  Sketch* s = &hs->s;
+  s->m = m;
+  s->rank = rank;
+  s->oversample = oversample;
+  s->ell = rank + oversample;
+  const int nint = (1 << m->levels) - 1;
+  if (hipMalloc(&s->d_k, nint * sizeof(int)) != hipSuccess) {
+    delete hs;
+    set_error("device allocation failed");
+    return HM_E_NOMEM;
+  }
+  hm_status st = clear_flags(m);
+  if (st == HM_OK) st = sketch_build(s, omega, theta0_full);
+  if (st != HM_OK) {
+    hm_sketch_destroy(hs);
+    return st;
+  }
+  *out = hs;
+  return HM_OK;
+}
+
+void hm_sketch_destroy(hm_sketch* hs) {
+  if (!hs) return;
+  if (hs->s.d_XR) (void)hipFree(hs->s.d_XR);
+  if (hs->s.d_k) (void)hipFree(hs->s.d_k);
+  delete hs;
+}
+
+hm_status hm_sketch_ranks(const hm_sketch* hs, int* k_host, int* kc) {
+  if (!hs) {
+    set_error("sketch is NULL");
+    return HM_E_INVAL;
+  }
+  if (k_host) std::copy(hs->s.kblk.begin(), hs->s.kblk.end(), k_host);
+  if (kc) *kc = hs->s.kc;
+  return HM_OK;
+}
+
+void hm_H_destroy(hm_H* hh) {
+  if (!hh) return;
+  for (void* p : hh->h.allocs) (void)hipFree(p);
+  if (hh->h.h_scal) (void)hipHostFree(hh->h.h_scal);
+  delete hh;
+}
+
+hm_status hm_H_create(hm_sketch* hs, int p, const int* free_idx, hm_H** out) {
+  if (!hs || !out || (p > 0 && !free_idx) || p < 0 || p > 4) {
+    set_error("bad arguments to hm_H_create");
+    return HM_E_INVAL;
+  }
+  *out = nullptr;
+  hm_H* hh = new hm_H();
+  HState* h = &hh->h;
+  h->s = &hs->s;
+  h->m = hs->s.m;
+  Model* m = h->m;
+  h->p = p;
+  h->kc = hs->s.kc;
+  bool seen[4] = {false, false, false, false};
+  for (int q = 0; q < p; ++q) {
+    int k = free_idx[q];
+    if (k < 0 || k > 3 || seen[k]) {
+      delete hh;
+      set_error("free_idx entries must be distinct values in 0..3");
+      return HM_E_INVAL;
+    }
+    seen[k] = true;
+    h->pidx[q] = k;
+    h->pb[q].kind = k;
+    if (k <= 1) {
+      h->realpos[q] = h->nreal;
+      h->realidx[h->nreal++] = k;
+    }
+  }
+  const int n = m->n, kc = h->kc, levels = m->levels, nl = m->nl;
+  const size_t pset = (size_t)n * levels * kc;
+  const size_t lset = (size_t)m->nleaves * nl * nl;
+  const size_t nodes = (size_t)(2 << levels) - 1;
+  const size_t nint = (size_t)(1 << levels) - 1;
+  const size_t s2 = (size_t)kc * kc, m2 = 4 * s2;
+  const size_t nk = (size_t)n * kc;
+  hm_status st = HM_OK;
+#define AL(ptr, cnt) \
+  if (st == HM_OK) st = dalloc(h, &(ptr), (cnt))
+  h->ps.bw = kc;
+  AL(h->ps.F, pset);
+  AL(h->D, lset);
+  for (int j = 0; j < h->nreal; ++j) {
+    AL(h->ps.dF[j], pset);
+    AL(h->dDr[j], lset);
+  }
+  // factorisation
+  FactorCtx& f = h->f;
+  f.m = m;
+  f.kc = kc;
+  f.F = h->ps.F;
+  f.D = h->D;
+  AL(f.G, pset);
+  AL(f.Dinv, lset);
+  AL(f.work_leaf, lset);
+  AL(f.Nn, nint * m2);
+  AL(f.Sn, nodes * s2);
+  AL(f.logdet_leaf, (size_t)m->nleaves);
+  AL(f.logdet_node, nint);
+  const size_t wT = (size_t)kc * std::max(1, levels - 1) * kc;
+  AL(f.nT, nodes * wT);
+  AL(f.nU, nodes * 2 * wT);
+  AL(f.Ncc, nodes * s2);
+  AL(f.Nx, nodes * s2);
+  AL(f.tmp_panel, pset);
+  // per-parameter buffers
+  for (int q = 0; q < p; ++q) {
+    ParamBufs& pb = h->pb[q];
+    if (pb.kind <= 1) {
+      pb.dF = h->ps.dF[h->realpos[q]];
+      pb.dD = h->dDr[h->realpos[q]];
+    } else {
+      AL(pb.dF, pset);
+      AL(pb.dD, lset);
+    }
+    AL(pb.Xi, pset);
+    AL(pb.dG, pset);
+    AL(pb.Gh, pset);
+    AL(pb.Hh, pset);
+    AL(pb.Y, lset);
+    AL(pb.Yt, lset);
+    AL(pb.E, nodes * s2);
+    AL(pb.Psi, nodes * s2);
+    AL(pb.W, nodes * s2);
+    AL(pb.Vt, nodes * s2);
+    AL(pb.PsiP, nint * m2);
+    AL(pb.Lam, nint * m2);
+    AL(h->gtr[q], nint);
+  }
+  AL(h->node_scratch, (size_t)std::max<size_t>(1, nint / 2 + 1) * m2);
+  // construction workspace
+  LevelBufs& b = h->lb;
+  AL(b.Y, nk);
+  AL(b.XS, nk);
+  AL(b.Z, nk);
+  AL(b.Qt, nk);
+  for (int j = 0; j < h->nreal; ++j) {
+    AL(b.dY[j], nk);
+    AL(b.XdS[j], nk);
+    AL(b.dZ[j], nk);
+    AL(b.Zq[j], nk);
+  }
+  AL(b.Zl, (size_t)n * nl);
+  for (int j = 0; j < h->nreal; ++j) AL(b.dZl[j], (size_t)n * nl);
+  NodeBufs& nb = h->nb;
+  const size_t tw = (size_t)kc * std::max(kc, nl);
+  AL(nb.t, nodes * tw);
+  for (int j = 0; j < h->nreal; ++j) AL(nb.dt[j], nodes * tw);
+  double** smalls[] = {&nb.g, &nb.r1, &nb.r1i, &nb.r2, &nb.r2i, &nb.r3, &nb.r3i, &nb.rinv, &nb.w, &nb.mfold};
+  for (double** q : smalls) AL(*q, nodes * s2);
+  AL(h->ytree, (size_t)n);
+  AL(h->z, (size_t)n);
+  AL(h->r, (size_t)n);
+  AL(h->v, (size_t)n);
+  AL(h->d_scal, (size_t)NSCAL);
+  AL(h->d_part, (size_t)1024 * 16);
+#undef AL
+  if (st == HM_OK && hipHostMalloc((void**)&h->h_scal, NSCAL * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    set_error("pinned host allocation failed");
+    st = HM_E_NOMEM;
+  }
+  if (st == HM_OK) {
+    // partial buffer of tree_reduce: the largest (leaves x depths x wa x wx) used per iteration
+    size_t need = (size_t)m->nleaves * levels * kc * std::max(kc, nl);
+    need = std::max(need, (size_t)m->nleaves * std::max(1, levels - 1) * kc * std::max(1, levels - 1) * kc);
+    need = std::max(need, (size_t)m->nleaves * levels * kc * kc);
+    st = ensure_reduce_ws(m, need);
+  }
+  if (st != HM_OK) {
+    hm_H_destroy(hh);
+    return st;
+  }
+  *out = hh;
+  return HM_OK;
+}
+
+hm_status hm_build(hm_H* hh, const double* theta_full) {
+  if (!hh) {
+    set_error("H is NULL");
+    return HM_E_INVAL;
+  }
+  HState* h = &hh->h;
+  HM_CHECK(check_theta(theta_full));
+  Model* m = h->m;
+  h->state = 0;
+  std::memcpy(h->theta, theta_full, sizeof(h->theta));
+  HM_CHECK(clear_flags(m));
+  const int n = m->n, kc = h->kc;
+  for (int l = 1; l <= m->levels; ++l) {
+    const double* XR = h->s->d_XR + (size_t)(l - 1) * kc * n;
+    HM_CHECK(level_step(m, h->theta, h->ps, l, XR, kc, h->s->d_k, h->nreal, h->realidx, h->lb, h->nb));
+  }
+  HM_CHECK(leaf_pass(m, h->theta, h->ps, h->nreal, h->realidx, h->lb, h->nb, h->D, h->dDr));
+  h->state = 1;
+  return HM_OK;
+}
+
+hm_status hm_factor(hm_H* hh) {
+  if (!hh) {
+    set_error("H is NULL");
+    return HM_E_INVAL;
+  }
+  HState* h = &hh->h;
+  if (h->state < 1) {
+    set_error("hm_factor before hm_build");
+    return HM_E_STATE;
+  }
+  Model* m = h->m;
+  HM_CHECK(factorize(h->f));
+  // log|K~| = sum of leaf and node parts
+  HM_CHECK(sum_scalar(m, h->f.logdet_leaf, m->nleaves, 0, h->d_scal + 100, h->d_part));
+  HM_CHECK(sum_scalar(m, h->f.logdet_node, (1 << m->levels) - 1, 0, h->d_scal + 101, h->d_part));
+  int flags = 0;
+  HM_CHECK(read_flags(m, &flags));
+  if (flags & (DF_NOT_SPD_LEAF | DF_NOT_SPD_NODE)) {
+    set_error(std::string("K~ is not positive definite (") +
+              ((flags & DF_NOT_SPD_LEAF) ? "leaf Cholesky" : "node determinant") + ")");
+    h->state = 1;
+    return HM_E_NOT_SPD;
+  }
+  if (flags & DF_QR_FAIL) {
+    set_error("a sketch QR failed during construction (rank-deficient sample)");
+    h->state = 1;
+    return HM_E_RANK;
+  }
+  HM_HIP(hipMemcpy(h->h_scal, h->d_scal + 100, 2 * sizeof(double), hipMemcpyDeviceToHost));
+  h->state = 2;
+  return HM_OK;
+}
+
+hm_status hm_logdet(hm_H* hh, double* out) {
+  if (!hh || !out) {
+    set_error("NULL argument");
+    return HM_E_INVAL;
+  }
+  HState* h = &hh->h;
+  if (h->state < 2) {
+    set_error("hm_logdet before hm_factor");
+    return HM_E_STATE;
+  }
+  HM_HIP(hipStreamSynchronize(h->m->stream));
+  HM_HIP(hipMemcpy(h->h_scal, h->d_scal + 100, 2 * sizeof(double), hipMemcpyDeviceToHost));
+  *out = h->h_scal[0] + h->h_scal[1];
+  return HM_OK;
+}
+
+hm_status hm_solve(hm_H* hh, const double* y, double* x) {
+  if (!hh || !y || !x) {
+    set_error("NULL argument");
+    return HM_E_INVAL;
+  }
+  HState* h = &hh->h;
+  if (h->state < 2) {
+    set_error("hm_solve before hm_factor");
+    return HM_E_STATE;
+  }
+  Model* m = h->m;
+  HM_CHECK(permute(m, y, h->ytree, 1));
+  HM_CHECK(solve_refined(h));
+  HM_CHECK(permute(m, h->z, x, 0));
+  return HM_OK;
+}
+
+hm_status hm_loglik_grad(hm_H* hh, const double* y, double* loglik, double* grad) {
+  if (!hh || !y || !loglik) {
+    set_error("NULL argument");
+    return HM_E_INVAL;
+  }
+  HState* h = &hh->h;
+  if (h->state < 2) {
+    set_error("hm_loglik_grad before hm_factor");
+    return HM_E_STATE;
+  }
+  Model* m = h->m;
+  const int n = m->n;
+  HM_CHECK(permute(m, y, h->ytree, 1));
+  HM_CHECK(solve_refined(h));
+  const double* yv[1] = {h->ytree};
+  const double* zv[1] = {h->z};
+  HM_CHECK(dots(m, yv, 1, zv, 1, n, h->d_scal + SC_YZ, h->d_part));
+  if (grad && h->p > 0) {
+    HM_CHECK(prepare_params(h));
+    for (int q = 0; q < h->p; ++q) {
+      ParamBufs& pb = h->pb[q];
+      // z^T K~_j z
+      HM_CHECK(hmatvec(h->f, pb.dD, h->ps.F, pb.dF, h->z, 1, h->v, 1.0, 0.0));
+      const double* vv[1] = {h->v};
+      HM_CHECK(dots(m, zv, 1, vv, 1, n, h->d_scal + SC_QUAD + q, h->d_part));
+      // tr(K~^{-1} K~_j) = sum_L tr(Y_L) - sum_P <N_P, PsiP>
+      HM_CHECK(sum_scalar(m, pb.Y, (long)m->nleaves * m->nl, m->nl, h->d_scal + SC_LTR + q, h->d_part));
+      HM_CHECK(node_psi(h->f, pb, h->gtr[q]));
+      HM_CHECK(sum_scalar(m, h->gtr[q], (1 << m->levels) - 1, 0, h->d_scal + SC_NTR + q, h->d_part));
+    }
+  }
+  HM_HIP(hipStreamSynchronize(m->stream));
+  HM_HIP(hipMemcpy(h->h_scal, h->d_scal, 128 * sizeof(double), hipMemcpyDeviceToHost));
+  const double logdet = h->h_scal[100] + h->h_scal[101];
+  const double yz = h->h_scal[SC_YZ];
+  *loglik = -0.5 * n * std::log(2.0 * M_PI) - 0.5 * logdet - 0.5 * yz;
+  if (!std::isfinite(*loglik)) {
+    set_error("non-finite log-likelihood");
+    return HM_E_NONFINITE;
+  }
+  if (grad) {
+    for (int q = 0; q < h->p; ++q) {
+      const double tr = h->h_scal[SC_LTR + q] - h->h_scal[SC_NTR + q];
+      grad[q] = 0.5 * tr - 0.5 * h->h_scal[SC_QUAD + q];
+    }
+  }
+  return HM_OK;
+}
+
+hm_status hm_fisher(hm_H* hh, double* fim) {
+  if (!hh || !fim) {
+    set_error("NULL argument");
+    return HM_E_INVAL;
+  }
+  HState* h = &hh->h;
+  if (h->state < 2) {
+    set_error("hm_fisher before hm_factor");
+    return HM_E_STATE;
+  }
+  Model* m = h->m;
+  const int p = h->p;
+  if (p == 0) return HM_OK;
+  HM_CHECK(prepare_params(h));
+  for (int q = 0; q < p; ++q) {
+    HM_CHECK(tangent_sweep(h->f, h->pb[q]));
+    HM_CHECK(node_psi(h->f, h->pb[q], h->gtr[q]));
+    HM_CHECK(node_lam(h->f, h->pb[q], h->node_scratch));
+    HM_CHECK(panel_products(h->f, h->pb[q]));
+  }
+  const int n = m->n, kc = h->kc, levels = m->levels;
+  const long pset = (long)n * levels * kc;
+  const long lset = (long)m->nleaves * m->nl * m->nl;
+  const long s2 = (long)kc * kc;
+  const long nint = (1 << levels) - 1, nodes = (2L << levels) - 1;
+  const double *A[4], *B[4];
+  double* out = h->d_scal + SC_FIM;
+  // term 0: 1/2 <Y^i, Yt^j>
+  for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Y; B[q] = h->pb[q].Yt; }
+  HM_CHECK(dots(m, A, p, B, p, lset, out + 0 * 16, h->d_part));
+  // term 1: -1/2 <Lam^i, PsiP^j>
+  for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Lam; B[q] = h->pb[q].PsiP; }
+  HM_CHECK(dots(m, A, p, B, p, nint * 4 * s2, out + 1 * 16, h->d_part));
+  // term 2: <Gh^i, Xi^j>
+  for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Gh; B[q] = h->pb[q].Xi; }
+  HM_CHECK(dots(m, A, p, B, p, pset, out + 2 * 16, h->d_part));
+  // term 3: <Hh^i, dF^j>
+  for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Hh; B[q] = h->pb[q].dF; }
+  HM_CHECK(dots(m, A, p, B, p, pset, out + 3 * 16, h->d_part));
+  // term 4: <Vt^i, E^j> over non-root nodes
+  for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Vt + s2; B[q] = h->pb[q].E + s2; }
+  HM_CHECK(dots(m, A, p, B, p, (nodes - 1) * s2, out + 4 * 16, h->d_part));
+  HM_HIP(hipStreamSynchronize(m->stream));
+  HM_HIP(hipMemcpy(h->h_scal + SC_FIM, out, 5 * 16 * sizeof(double), hipMemcpyDeviceToHost));
+  const double* t = h->h_scal + SC_FIM;
+  for (int i = 0; i < p; ++i)
+    for (int j = 0; j < p; ++j) {
+      const int q = i * p + j;
+      fim[q] = 0.5 * t[q] - 0.5 * t[16 + q] + t[32 + q] + t[48 + q] + t[64 + q];
+      if (!std::isfinite(fim[q])) {
+        set_error("non-finite Fisher information");
+        return HM_E_NONFINITE;
+      }
+    }
+  return HM_OK;
+}
+
+hm_status hm_iteration(hm_H* hh, const double* theta_full, const double* y, double* loglik, double* grad,
+                       double* fim) {
+  HM_CHECK(hm_build(hh, theta_full));
+  HM_CHECK(hm_factor(hh));
+  HM_CHECK(hm_loglik_grad(hh, y, loglik, grad));
+  if (fim) HM_CHECK(hm_fisher(hh, fim));
+  return HM_OK;
+}
+
+hm_status hm_export(hm_H* hh, int what, double* dst) {
+  if (!hh || !dst) {
+    set_error("NULL argument");
+    return HM_E_INVAL;
+  }
+  HState* h = &hh->h;
+  if (h->state < 1) {
+    set_error("hm_export before hm_build");
+    return HM_E_STATE;
+  }
+  Model* m = h->m;
+  const size_t pset = (size_t)m->n * m->levels * h->kc;
+  const size_t lset = (size_t)m->nleaves * m->nl * m->nl;
+  const double* src = nullptr;
+  size_t cnt = 0;
+  if (what == 0) { src = h->ps.F; cnt = pset; }
+  else if (what >= 1 && what <= 2 && what - 1 < h->nreal) { src = h->ps.dF[what - 1]; cnt = pset; }
+  else if (what == 10) { src = h->D; cnt = lset; }
+  else if (what >= 11 && what <= 12 && what - 11 < h->nreal) { src = h->dDr[what - 11]; cnt = lset; }
+  else {
+    set_error("hm_export: unknown item");
+    return HM_E_INVAL;
+  }
+  HM_HIP(hipMemcpyAsync(dst, src, cnt * sizeof(double), hipMemcpyDeviceToDevice, m->stream));
+  HM_HIP(hipStreamSynchronize(m->stream));
+  return HM_OK;
+}
+
+}  // extern "C"

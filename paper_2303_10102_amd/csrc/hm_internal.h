@@ -1,0 +1,161 @@
+// Internal declarations of the HIP H-MLE library (not part of the public ABI).
+//
+// Data layout in HBM (all FP64, column-major, rows in tree order):
+//   * A "panel set" is an n x (levels*kc) matrix; column block d-1 holds the
+//     depth-d panels F_c of every node c at depth d (the nodes of one depth
+//     partition the rows, so one n x kc block holds all of them).
+//   * Leaf blocks are stored leaf-major: leaf L occupies nl*nl contiguous
+//     doubles (column-major nl x nl) at offset L*nl*nl.
+//   * Per-node small matrices are stored by heap index (root 0, children of
+//     x are 2x+1 and 2x+2) with a fixed stride per node.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/hmle.h"
+
+namespace hm {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+const char* get_error();
+
+#define HM_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      hm::set_error(std::string("HIP error ") + hipGetErrorString(e_) + " at " + \
+                    __FILE__ + ":" + std::to_string(__LINE__));                   \
+      return HM_E_DEVICE;                                                         \
+    }                                                                             \
+  } while (0)
+
+#define HM_CHECK(st)                 \
+  do {                               \
+    hm_status s_ = (st);             \
+    if (s_ != HM_OK) return s_;      \
+  } while (0)
+
+#define HM_LAUNCH_CHECK() HM_HIP(hipGetLastError())
+
+// device-side status flags (bit mask), read back at scalar-returning calls
+enum DevFlag : int { DF_NOT_SPD_LEAF = 1, DF_NOT_SPD_NODE = 2, DF_QR_FAIL = 4, DF_NONFINITE = 8,
+                     DF_JACOBI = 16 };
+
+// ---------------------------------------------------------------------------
+// model, sketch, H
+// ---------------------------------------------------------------------------
+struct Model {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int dim = 2, N = 0, n = 0, levels = 0, nl = 0, nleaves = 0;
+  int Np = 1;           // number of x-modes per line family (N in 2D, 1 in 1D)
+  int L = 0;            // length of a y-line (N)
+  double h = 0.0;
+  int* d_perm = nullptr;    // tree position -> grid index
+  int* d_iperm = nullptr;   // grid index -> tree position
+  double* d_dst = nullptr;  // N x N orthonormal DST-I (2D)
+  double* d_mu = nullptr;   // Np mode eigenvalues of -Lap_x (0 in 1D)
+  // Thomas factor coefficients for A_p and B_p, layout [i*Np + p]
+  double* d_thomas = nullptr;   // 4 * L * Np: cA, imA, cB, imB
+  double thomas_key[2] = {-1.0, -1.0};  // (kappa, alpha) the coefficients belong to
+  // K-apply workspace (grid / mode space), sized for cmax columns
+  int cmax = 0;
+  double* d_ws = nullptr;       // 4 * n * cmax
+  int* d_flags = nullptr;       // device status flags
+  double* d_ident = nullptr;    // stacked identities n x nl (tree order), for the leaf pass
+  double* d_red = nullptr;      // per-leaf partials of tree_reduce
+  size_t red_doubles = 0;
+};
+// grow the tree_reduce partial buffer (setup calls only; never inside an iteration)
+hm_status ensure_reduce_ws(Model* m, size_t doubles);
+
+struct Sketch {
+  Model* m = nullptr;
+  int rank = 0, oversample = 0, ell = 0;
+  int kc = 0;                 // column width of every panel block (max kept rank)
+  std::vector<int> kblk;      // kept rank per block (heap index of the parent), size 2^levels - 1
+  double* d_XR = nullptr;     // n x (levels*kc): level-l test matrix Omega V (right-children rows)
+  int* d_k = nullptr;         // device copy of kblk
+};
+
+
+// ---------------------------------------------------------------------------
+// kernels / host helpers shared across translation units
+// ---------------------------------------------------------------------------
+inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+// K-apply: outputs (any may be null) = {K, dK/dkappa, dK/dalpha} X, tree order in and out.
+// X: n x c (ld ldx); outputs n x c (ld ldo). c <= m->cmax.
+hm_status kapply(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK,
+                 double* outKap, double* outAlp, int ldo);
+
+// Generic FP64 GEMM, column-major: C = alpha*op(A)*op(B) + beta*C, batched by strides.
+hm_status gemm(hipStream_t st, bool ta, bool tb, int M, int Nc, int K, double alpha, const double* A,
+               int lda, long sA, const double* B, int ldb, long sB, double beta, double* C, int ldc,
+               long sC, int batch);
+
+// Column ranges that depend on the tree depth d of the node being processed:
+//   cols(d) = [base + (d-1)*stride, base + (d-1)*stride + w0 + (d-1)*grow)
+struct ColSpec {
+  int base, stride, w0, grow;
+  __host__ __device__ int c0(int d) const { return base + (d - 1) * stride; }
+  __host__ __device__ int w(int d) const { return w0 + (d - 1) * grow; }
+};
+inline ColSpec cs_fixed(int base, int w) { return ColSpec{base, 0, w, 0}; }
+inline ColSpec cs_block(int bw) { return ColSpec{0, bw, bw, 0}; }           // block d of width bw
+inline ColSpec cs_block_at(int base, int bw) { return ColSpec{base, bw, bw, 0}; }
+inline ColSpec cs_prefix(int bw) { return ColSpec{0, 0, 0, bw}; }          // blocks 1..d-1
+inline ColSpec cs_prefix_incl(int bw) { return ColSpec{0, 0, bw, bw}; }    // blocks 1..d
+
+// Leaf selection: rows of leaves whose ancestor at depth sel_depth is a left (1) or
+// right (2) child; 0 selects every leaf.
+struct LeafSel { int mode, depth; };
+inline LeafSel sel_all() { return LeafSel{0, 1}; }
+
+// For every node c at depth d in [d0,d1]:  out_c = A[c rows, ac(d)]^T X[c rows, xc(d)]
+// (wa x wx(d) column-major, ld wa, stored at out + heap(c)*out_stride).  Rows of
+// unselected leaves count as zero.
+struct ReduceJob {
+  const double* A; int lda; ColSpec ac;
+  const double* X; int ldx; ColSpec xc;
+  int d0, d1;
+  double* out; long out_stride;
+  LeafSel sel;
+};
+hm_status tree_reduce(Model* m, const ReduceJob& j);
+
+// For every row i of a selected leaf L:
+//   Y[i, yc(d)] = beta*Y + alpha * sum_{d in [d0,d1]} A[i, ac(d)] * T_{s(c_d)}[r0 + 0:wk, 0:wy(d)]
+// where c_d is L's ancestor at depth d, s(c) = c (tmode 0), its sibling (1) or its
+// parent (2); r0 = half_off if tmode==2 and c is a right child, else 0.  wk = ac.w0.
+// T blocks: T + heap(s(c))*t_stride, ld ldt.  beta is applied once per element of
+// the union of yc(d) over the segments.
+struct ExpandJob {
+  const double* A; int lda; ColSpec ac;
+  double* Y; int ldy; ColSpec yc;
+  const double* T; long t_stride; int ldt; int tmode; int half_off;
+  int d0, d1;
+  double alpha, beta;
+  LeafSel sel;
+};
+hm_status tree_expand(Model* m, const ExpandJob& j);
+
+// out[L rows, 0:w] (+)= Dm_L * X[L rows, 0:w], Dm leaf-major
+hm_status leaf_gemm(Model* m, const double* Dm, const double* X, int ldx, double* Y, int ldy, int w,
+                    double alpha, double beta, int leaf_lo, int leaf_hi);
+
+// per-node small dense kernels (small.hip); nodes heap0 + i*hstep, i < cnt
+hm_status chol_inv_nodes(Model* m, const double* G, long gstride, double* R, double* Rinv, long rstride,
+                         int k, const int* d_kblk, int heap0, int hstep, int cnt, int shift, long mrows);
+hm_status alg2_fold_nodes(Model* m, const double* W, double* M, long stride, int k, int heap0, int cnt);
+hm_status node_lu(Model* m, const double* S, long sstride, double* Nout, long nstride, double* logdet, int k,
+                  int heap0, int cnt);
+hm_status model_tables(Model* m);
+
+}  // namespace hm

@@ -1,0 +1,135 @@
+// Leaf blocks: extraction from the stacked-identity sample, Cholesky, log-det,
+// explicit inverses.
+//
+// The leaf blocks of K~ are read from (K - sum_l H_l) [I; I; ...] (Sec. 3.2,
+// eq. "leaf sample") and symmetrised.  The factorisation K~ = Dbar * prod(I + U V^T)
+// starts by factoring out the block-diagonal Dbar of leaf blocks (App. C, eq.
+// "factor out leaf"); its log-determinant is 2 sum log diag(chol(D_L)).
+#include <cmath>
+
+#include "hm_internal.h"
+
+namespace hm {
+
+// D_L = (Z_L + Z_L^T)/2 with Z rows in tree order (ld ldz), leaf-major output.
+__global__ void k_leaf_sym(const double* Z, int ldz, double* D, int nl, double scale) {
+  const int L = blockIdx.y;
+  const long r0 = (long)L * nl;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nl * nl) return;
+  const int i = e % nl, j = e / nl;
+  const double a = Z[r0 + i + (long)j * ldz], b = Z[r0 + j + (long)i * ldz];
+  D[(long)L * nl * nl + e] = 0.5 * scale * (a + b);
+}
+
+hm_status leaf_sym(Model* m, const double* Z, int ldz, double* D) {
+  const int nl = m->nl;
+  hipLaunchKernelGGL(k_leaf_sym, dim3(ceil_div(nl * nl, 256), m->nleaves), dim3(256), 0, m->stream, Z, ldz, D, nl,
+                     1.0);
+  HM_LAUNCH_CHECK();
+  return HM_OK;
+}
+
+constexpr int CNB = 32;      // Cholesky block width
+constexpr int NLMAX = 512;   // largest leaf handled
+
+// In-place blocked Cholesky (lower) of W (nl x nl, column-major), one leaf per
+// workgroup.  logdet[L] = 2 sum log L_ii.  A non-positive pivot sets a flag and
+// is replaced by 1 so the kernel still completes.
+__global__ void __launch_bounds__(256) k_leaf_chol(double* W, int nl, double* logdet, int* flags) {
+  __shared__ double panel[NLMAX * CNB];  // rows jb..nl-1 of the current block column
+  const int L = blockIdx.x;
+  double* A = W + (long)L * nl * nl;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double lsum = 0.0;  // accumulated by thread 0
+  int bad = 0;
+  for (int jb = 0; jb < nl; jb += CNB) {
+    const int nb = min(CNB, nl - jb);
+    const int rows = nl - jb;
+    // stage the block column (rows jb..nl-1, cols jb..jb+nb-1) into LDS, row-major in t
+    for (int e = tid; e < rows * nb; e += nt) {
+      int i = e % rows, t = e / rows;
+      panel[i * CNB + t] = A[(jb + i) + (long)(jb + t) * nl];
+    }
+    __syncthreads();
+    // unblocked factorisation of the diagonal block + triangular solve of the rest:
+    for (int t = 0; t < nb; ++t) {
+      if (tid == 0) {
+        double d = panel[t * CNB + t];
+        if (!(d > 0.0)) { bad = 1; d = 1.0; }
+        d = sqrt(d);
+        panel[t * CNB + t] = d;
+        lsum += 2.0 * log(d);
+      }
+      __syncthreads();
+      const double piv = panel[t * CNB + t];
+      for (int i = t + 1 + tid; i < rows; i += nt) panel[i * CNB + t] /= piv;
+      __syncthreads();
+      // update columns t+1..nb-1 of the block column
+      for (int e = tid; e < (rows - t - 1) * (nb - t - 1); e += nt) {
+        int i = t + 1 + e % (rows - t - 1), u = t + 1 + e / (rows - t - 1);
+        if (i >= u) panel[i * CNB + u] -= panel[i * CNB + t] * panel[u * CNB + t];
+      }
+      __syncthreads();
+    }
+    // write back the factored block column (lower part)
+    for (int e = tid; e < rows * nb; e += nt) {
+      int i = e % rows, t = e / rows;
+      A[(jb + i) + (long)(jb + t) * nl] = (i >= t) ? panel[i * CNB + t] : 0.0;
+    }
+    // trailing update: A[i,l] -= sum_t P[i,t] P[l,t] for jb+nb <= l <= i
+    const int r2 = nl - jb - nb;
+    for (int e = tid; e < r2 * r2; e += nt) {
+      int i = e % r2, l = e / r2;
+      if (i < l) continue;
+      double s = 0.0;
+      const double* pi = panel + (nb + i) * CNB;
+      const double* pl = panel + (nb + l) * CNB;
+      for (int t = 0; t < nb; ++t) s += pi[t] * pl[t];
+      A[(jb + nb + i) + (long)(jb + nb + l) * nl] -= s;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    logdet[L] = lsum;
+    if (bad) atomicOr(flags, (int)DF_NOT_SPD_LEAF);
+  }
+}
+
+// Linv = L^{-1} (lower), one column per thread.
+__global__ void k_leaf_trinv(const double* Lf, double* Li, int nl) {
+  const int L = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nl) return;
+  const double* A = Lf + (long)L * nl * nl;
+  double* X = Li + (long)L * nl * nl + (long)j * nl;
+  for (int i = 0; i < j; ++i) X[i] = 0.0;
+  X[j] = 1.0 / A[j + (long)j * nl];
+  for (int i = j + 1; i < nl; ++i) {
+    double s = 0.0;
+    for (int l = j; l < i; ++l) s += A[i + (long)l * nl] * X[l];
+    X[i] = -s / A[i + (long)i * nl];
+  }
+}
+
+// Dinv_L = L^{-T} L^{-1};  logdet_leaf[L] = log det D_L.  work: nleaves*nl*nl doubles.
+hm_status leaf_factor(Model* m, const double* D, double* Dinv, double* logdet_leaf, double* work) {
+  const int nl = m->nl;
+  if (nl > NLMAX) {
+    set_error("leaf size exceeds 512");
+    return HM_E_INVAL;
+  }
+  const long sz = (long)m->nleaves * nl * nl;
+  HM_HIP(hipMemcpyAsync(work, D, sz * sizeof(double), hipMemcpyDeviceToDevice, m->stream));
+  hipLaunchKernelGGL(k_leaf_chol, dim3(m->nleaves), dim3(256), 0, m->stream, work, nl, logdet_leaf, m->d_flags);
+  HM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_leaf_trinv, dim3(ceil_div(nl, 64), m->nleaves), dim3(64), 0, m->stream, work, Dinv, nl);
+  HM_LAUNCH_CHECK();
+  // Dinv currently holds L^{-1}; form L^{-T} L^{-1} into work, then copy back
+  HM_CHECK(gemm(m->stream, true, false, nl, nl, nl, 1.0, Dinv, nl, (long)nl * nl, Dinv, nl, (long)nl * nl, 0.0,
+                work, nl, (long)nl * nl, m->nleaves));
+  HM_HIP(hipMemcpyAsync(Dinv, work, sz * sizeof(double), hipMemcpyDeviceToDevice, m->stream));
+  return HM_OK;
+}
+
+}  // namespace hm

@@ -1,0 +1,324 @@
+// Tree-structured panel products on the HODLR row partition.
+//
+// Every product the method needs between tall panels (n rows, tree order) and
+// per-node small matrices reduces to two shapes over the binary tree:
+//   reduce:  out_c = A[c rows, .]^T X[c rows, .]      for all nodes c of some depths
+//   expand:  Y[i, .] += sum_d A[i, .] T_{node(i,d)}    for every row i
+// Both are computed leaf by leaf (one GEMM tile per leaf and column tile, the
+// leaf is the natural row block: all nodes are unions of leaves), so a launch
+// always has (#leaves x #column tiles) independent workgroups; reduce then sums
+// the per-leaf partials up the tree.  Plus a batched GEMM with the leaf blocks,
+// and a plain strided batched GEMM.
+#include "hm_internal.h"
+#include "gemm_core.h"
+
+namespace hm {
+
+__device__ __forceinline__ bool leaf_selected(int L, int levels, int mode, int depth) {
+  if (mode == 0) return true;
+  int anc = L >> (levels - depth);
+  bool left = (anc & 1) == 0;
+  return mode == 1 ? left : !left;
+}
+
+// ----------------------------------------------------------------------------
+// generic strided batched GEMM (column-major)
+// ----------------------------------------------------------------------------
+template <bool TA>
+struct LdA {
+  const double* p; int ld, m0, M;
+  static constexpr bool kfast = TA;
+  __device__ double operator()(int i, int k) const {
+    int r = m0 + i;
+    if (r >= M) return 0.0;
+    return TA ? p[k + (long)r * ld] : p[r + (long)k * ld];
+  }
+};
+template <bool TB>
+struct LdB {
+  const double* p; int ld, n0, Nc;
+  static constexpr bool kfast = !TB;
+  __device__ double operator()(int k, int j) const {
+    int c = n0 + j;
+    if (c >= Nc) return 0.0;
+    return TB ? p[c + (long)k * ld] : p[k + (long)c * ld];
+  }
+};
+struct StC {
+  double* p; int ld, m0, n0, M, Nc; double alpha, beta;
+  __device__ void operator()(int i, int j, double v) const {
+    int r = m0 + i, c = n0 + j;
+    if (r >= M || c >= Nc) return;
+    double* q = p + r + (long)c * ld;
+    *q = (beta == 0.0) ? alpha * v : alpha * v + beta * (*q);
+  }
+};
+
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_gemm(int M, int Nc, int K, double alpha, const double* A, int lda,
+                                              long sA, const double* B, int ldb, long sB, double beta,
+                                              double* C, int ldc, long sC) {
+  __shared__ double smem[GCfg::LDS_DOUBLES];
+  int b = blockIdx.z;
+  int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  LdA<TA> la{A + b * sA, lda, m0, M};
+  LdB<TB> lb{B + b * sB, ldb, n0, Nc};
+  double acc[GTM][GTN];
+  tile_zero<GBM, GBN, GTM, GTN>(acc);
+  tile_gemm_acc<GBM, GBN, GBK, GTM, GTN>(la, lb, 0, K, acc, smem);
+  tile_store<GBM, GBN, GBK, GTM, GTN>(StC{C + b * sC, ldc, m0, n0, M, Nc, alpha, beta}, acc);
+}
+
+hm_status gemm(hipStream_t st, bool ta, bool tb, int M, int Nc, int K, double alpha, const double* A,
+               int lda, long sA, const double* B, int ldb, long sB, double beta, double* C, int ldc,
+               long sC, int batch) {
+  if (M <= 0 || Nc <= 0 || batch <= 0) return HM_OK;
+  dim3 grid(ceil_div(M, GBM), ceil_div(Nc, GBN), batch);
+  if (!ta && !tb)
+    hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(GCfg::NT), 0, st, M, Nc, K, alpha, A, lda, sA, B,
+                       ldb, sB, beta, C, ldc, sC);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(GCfg::NT), 0, st, M, Nc, K, alpha, A, lda, sA, B,
+                       ldb, sB, beta, C, ldc, sC);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(GCfg::NT), 0, st, M, Nc, K, alpha, A, lda, sA, B,
+                       ldb, sB, beta, C, ldc, sC);
+  else
+    hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(GCfg::NT), 0, st, M, Nc, K, alpha, A, lda, sA, B,
+                       ldb, sB, beta, C, ldc, sC);
+  HM_LAUNCH_CHECK();
+  return HM_OK;
+}
+
+// ----------------------------------------------------------------------------
+// reduce: per-leaf partial products, then sums over the leaves of each node
+// ----------------------------------------------------------------------------
+struct RedLA {
+  const double* p; int ld; int m0, wa;
+  static constexpr bool kfast = true;
+  __device__ double operator()(int i, int k) const {
+    int c = m0 + i;
+    return c < wa ? p[k + (long)c * ld] : 0.0;
+  }
+};
+struct RedLB {
+  const double* p; int ld; int n0, wx;
+  static constexpr bool kfast = true;
+  __device__ double operator()(int k, int j) const {
+    int c = n0 + j;
+    return c < wx ? p[k + (long)c * ld] : 0.0;
+  }
+};
+
+struct RedArgs {
+  const double* A; int lda; ColSpec ac;
+  const double* X; int ldx; ColSpec xc;
+  int d0, d1, levels, nl;
+  double* out; long out_stride;
+  double* partial; long pstride;  // per (leaf, depth) stride = wa * max wx
+  int sel_mode, sel_depth;
+};
+
+__global__ void __launch_bounds__(256) k_reduce_partial(RedArgs a) {
+  __shared__ double smem[GCfg::LDS_DOUBLES];
+  const int ndep = a.d1 - a.d0 + 1;
+  const int L = blockIdx.z / ndep;
+  const int d = a.d0 + blockIdx.z % ndep;
+  if (!leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) return;
+  const int wa = a.ac.w0, wx = a.xc.w(d);
+  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  if (m0 >= wa || n0 >= wx) return;
+  const long r0 = (long)L * a.nl;
+  const int ac0 = a.ac.c0(d), xc0 = a.xc.c0(d);
+  RedLA la{a.A + r0 + (long)ac0 * a.lda, a.lda, m0, wa};
+  RedLB lb{a.X + r0 + (long)xc0 * a.ldx, a.ldx, n0, wx};
+  double acc[GTM][GTN];
+  tile_zero<GBM, GBN, GTM, GTN>(acc);
+  tile_gemm_acc<GBM, GBN, GBK, GTM, GTN>(la, lb, 0, a.nl, acc, smem);
+  double* dst;
+  if (d == a.levels) {
+    int heap = (1 << d) - 1 + L;
+    dst = a.out + heap * a.out_stride;
+  } else {
+    dst = a.partial + ((long)L * ndep + (d - a.d0)) * a.pstride;
+  }
+  tile_store<GBM, GBN, GBK, GTM, GTN>(StC{dst, wa, m0, n0, wa, wx, 1.0, 0.0}, acc);
+}
+
+__global__ void k_reduce_tree(RedArgs a, int d) {
+  // grid.x: element chunks, grid.y: node index at depth d
+  const int ndep = a.d1 - a.d0 + 1;
+  const int idx = blockIdx.y;
+  const int wa = a.ac.w0, wx = a.xc.w(d);
+  const int ne = wa * wx;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const int span = 1 << (a.levels - d);
+  const int L0 = idx * span;
+  double s = 0.0;
+  for (int L = L0; L < L0 + span; ++L) {
+    if (!leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) continue;
+    s += a.partial[((long)L * ndep + (d - a.d0)) * a.pstride + e];
+  }
+  const int heap = (1 << d) - 1 + idx;
+  a.out[heap * a.out_stride + e] = s;
+}
+
+hm_status ensure_reduce_ws(Model* m, size_t doubles) {
+  if (doubles <= m->red_doubles) return HM_OK;
+  if (m->d_red) HM_HIP(hipFree(m->d_red));
+  m->d_red = nullptr;
+  m->red_doubles = 0;
+  if (hipMalloc(&m->d_red, doubles * sizeof(double)) != hipSuccess) {
+    set_error("tree_reduce workspace allocation failed");
+    return HM_E_NOMEM;
+  }
+  m->red_doubles = doubles;
+  return HM_OK;
+}
+
+hm_status tree_reduce(Model* m, const ReduceJob& j) {
+  if (j.d0 < 1 || j.d1 > m->levels || j.d0 > j.d1) {
+    set_error("tree_reduce: bad depth range");
+    return HM_E_INVAL;
+  }
+  const int ndep = j.d1 - j.d0 + 1;
+  int wxmax = 0;
+  for (int d = j.d0; d <= j.d1; ++d) wxmax = std::max(wxmax, j.xc.w(d));
+  const int wa = j.ac.w0;
+  if (wa <= 0 || wxmax <= 0) return HM_OK;
+  RedArgs a{j.A, j.lda, j.ac, j.X, j.ldx, j.xc, j.d0, j.d1, m->levels, m->nl, j.out, j.out_stride,
+            m->d_red, (long)wa * wxmax, j.sel.mode, j.sel.depth};
+  size_t need = (size_t)m->nleaves * ndep * wa * wxmax;
+  if (need > m->red_doubles) {
+    set_error("tree_reduce: partial workspace too small (" + std::to_string(need) + " > " +
+              std::to_string(m->red_doubles) + ")");
+    return HM_E_INVAL;
+  }
+  dim3 grid(ceil_div(wa, GBM), ceil_div(wxmax, GBN), m->nleaves * ndep);
+  hipLaunchKernelGGL(k_reduce_partial, grid, dim3(GCfg::NT), 0, m->stream, a);
+  HM_LAUNCH_CHECK();
+  for (int d = j.d0; d <= std::min(j.d1, m->levels - 1); ++d) {
+    int ne = wa * j.xc.w(d);
+    if (ne <= 0) continue;
+    dim3 g2(ceil_div(ne, 256), 1 << d);
+    hipLaunchKernelGGL(k_reduce_tree, g2, dim3(256), 0, m->stream, a, d);
+    HM_LAUNCH_CHECK();
+  }
+  return HM_OK;
+}
+
+// ----------------------------------------------------------------------------
+// expand: Y[i, yc(d)] = beta Y + alpha sum_d A[i, ac(d)] T_{s(c_d)}
+// ----------------------------------------------------------------------------
+struct ExpLA {
+  const double* p; int ld, m0, nl;
+  static constexpr bool kfast = false;
+  __device__ double operator()(int i, int k) const {
+    int r = m0 + i;
+    return r < nl ? p[r + (long)k * ld] : 0.0;
+  }
+};
+struct ExpLB {
+  const double* p; int ld; int jt, wy;  // jt = tile column offset relative to yc0
+  static constexpr bool kfast = true;
+  __device__ double operator()(int k, int j) const {
+    int cc = jt + j;
+    return (cc >= 0 && cc < wy) ? p[k + (long)cc * ld] : 0.0;
+  }
+};
+struct ExpSt {
+  double* p; int ld; int m0, j0, nl, yhi; double alpha, beta;
+  __device__ void operator()(int i, int j, double v) const {
+    int r = m0 + i, c = j0 + j;
+    if (r >= nl || c >= yhi) return;
+    double* q = p + r + (long)c * ld;
+    *q = (beta == 0.0) ? alpha * v : alpha * v + beta * (*q);
+  }
+};
+
+struct ExpArgs {
+  const double* A; int lda; ColSpec ac;
+  double* Y; int ldy; ColSpec yc;
+  const double* T; long t_stride; int ldt; int tmode; int half_off;
+  int d0, d1, levels, nl;
+  double alpha, beta;
+  int ylo, yhi;  // union of the output columns
+  int sel_mode, sel_depth;
+};
+
+__global__ void __launch_bounds__(256) k_expand(ExpArgs a) {
+  __shared__ double smem[GCfg::LDS_DOUBLES];
+  const int L = blockIdx.z;
+  if (!leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) return;
+  const int m0 = blockIdx.x * GBM;
+  const int j0 = a.ylo + blockIdx.y * GBN;  // absolute first column of this tile
+  const long r0 = (long)L * a.nl;
+  const int wk = a.ac.w0;
+  double acc[GTM][GTN];
+  tile_zero<GBM, GBN, GTM, GTN>(acc);
+  for (int d = a.d0; d <= a.d1; ++d) {
+    const int yc0 = a.yc.c0(d), wy = a.yc.w(d);
+    if (wy <= 0 || j0 >= yc0 + wy || j0 + GBN <= yc0) continue;
+    int c = L >> (a.levels - d);           // index of the ancestor at depth d
+    int heap = (1 << d) - 1 + c;
+    int sel = heap, roff = 0;
+    if (a.tmode == 1) sel = (heap & 1) ? heap + 1 : heap - 1;
+    else if (a.tmode == 2) { sel = (heap - 1) >> 1; roff = (c & 1) ? a.half_off : 0; }
+    ExpLA la{a.A + r0 + (long)a.ac.c0(d) * a.lda, a.lda, m0, a.nl};
+    ExpLB lb{a.T + sel * a.t_stride + roff, a.ldt, j0 - yc0, wy};
+    tile_gemm_acc<GBM, GBN, GBK, GTM, GTN>(la, lb, 0, wk, acc, smem);
+  }
+  ExpSt st{a.Y + r0, a.ldy, m0, j0, a.nl, a.yhi, a.alpha, a.beta};
+  tile_store<GBM, GBN, GBK, GTM, GTN>(st, acc);
+}
+
+hm_status tree_expand(Model* m, const ExpandJob& j) {
+  if (j.d0 < 1 || j.d1 > m->levels || j.d0 > j.d1) {
+    set_error("tree_expand: bad depth range");
+    return HM_E_INVAL;
+  }
+  int ylo = 1 << 30, yhi = -1;
+  for (int d = j.d0; d <= j.d1; ++d) {
+    if (j.yc.w(d) <= 0) continue;
+    ylo = std::min(ylo, j.yc.c0(d));
+    yhi = std::max(yhi, j.yc.c0(d) + j.yc.w(d));
+  }
+  if (yhi <= ylo) return HM_OK;
+  ExpArgs a{j.A, j.lda, j.ac, j.Y, j.ldy, j.yc, j.T, j.t_stride, j.ldt, j.tmode, j.half_off,
+            j.d0, j.d1, m->levels, m->nl, j.alpha, j.beta, ylo, yhi, j.sel.mode, j.sel.depth};
+  dim3 grid(ceil_div(m->nl, GBM), ceil_div(yhi - ylo, GBN), m->nleaves);
+  hipLaunchKernelGGL(k_expand, grid, dim3(GCfg::NT), 0, m->stream, a);
+  HM_LAUNCH_CHECK();
+  return HM_OK;
+}
+
+// ----------------------------------------------------------------------------
+// leaf-block GEMM: Y[L rows, 0:w] = beta Y + alpha Dm_L X[L rows, 0:w]
+// ----------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_leaf_gemm(const double* Dm, const double* X, int ldx, double* Y,
+                                                   int ldy, int w, int nl, double alpha, double beta,
+                                                   int leaf_lo) {
+  __shared__ double smem[GCfg::LDS_DOUBLES];
+  const int L = leaf_lo + blockIdx.z;
+  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  const long r0 = (long)L * nl;
+  LdA<false> la{Dm + (long)L * nl * nl, nl, m0, nl};
+  LdB<false> lb{X + r0, ldx, n0, w};
+  double acc[GTM][GTN];
+  tile_zero<GBM, GBN, GTM, GTN>(acc);
+  tile_gemm_acc<GBM, GBN, GBK, GTM, GTN>(la, lb, 0, nl, acc, smem);
+  tile_store<GBM, GBN, GBK, GTM, GTN>(StC{Y + r0, ldy, m0, n0, nl, w, alpha, beta}, acc);
+}
+
+hm_status leaf_gemm(Model* m, const double* Dm, const double* X, int ldx, double* Y, int ldy, int w,
+                    double alpha, double beta, int leaf_lo, int leaf_hi) {
+  if (w <= 0 || leaf_hi <= leaf_lo) return HM_OK;
+  dim3 grid(ceil_div(m->nl, GBM), ceil_div(w, GBN), leaf_hi - leaf_lo);
+  hipLaunchKernelGGL(k_leaf_gemm, grid, dim3(GCfg::NT), 0, m->stream, Dm, X, ldx, Y, ldy, w, m->nl, alpha,
+                     beta, leaf_lo);
+  HM_LAUNCH_CHECK();
+  return HM_OK;
+}
+
+}  // namespace hm

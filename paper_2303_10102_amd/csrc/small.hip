@@ -1,0 +1,234 @@
+// Per-node small dense kernels (one workgroup per tree node, operands in LDS).
+//
+//  * k_chol_inv     Cholesky G = R^T R of a k x k Gram matrix (optionally shifted),
+//                   with R and R^{-1}; the building block of the shifted Cholesky-QR
+//                   used for Alg. 1 step 3 (QR with positive diagonal).
+//  * k_alg2_fold    M = triu(W) + strict_tril(W)^T for Alg. 2 (W = Q^T dB R^{-1}):
+//                   dQ = dB R^{-1} - Q M.
+//  * k_node_lu      N_P = (J + S_P)^{-1} and log det(I + V^T U) for the Woodbury
+//                   factor of node P (Sec. 3.1, App. C; Sylvester's identity).
+#include <cmath>
+
+#include "hm_internal.h"
+
+namespace hm {
+
+constexpr int KMAX = 64;    // largest panel width handled in LDS
+constexpr int MMAX = 128;   // 2*KMAX
+
+// ---------------------------------------------------------------------------
+// Cholesky + triangular inverse of G (k x k, ld k), one node per workgroup.
+// shift: if nonzero, G + s I with s = 11 (m k + k (k+1)) u ||.||_F^2, m = rows of
+// the sketched block (shifted Cholesky-QR of Fukaya et al.); ||Y||_F^2 = tr(G).
+// Zero columns (k_P < k) are kept as identity so padding stays exactly zero.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_chol_inv(const double* G, long gstride, double* R, double* Rinv,
+                                                  long rstride, int k, const int* kblk, int heap0, int hstep,
+                                                  int shift, long mrows, int* flags) {
+  __shared__ double A[KMAX * KMAX];
+  const int node = heap0 + blockIdx.x * hstep;
+  // kept rank of the block whose left child is this node (kblk indexed by parent)
+  const int kp = kblk ? kblk[(node - 1) >> 1] : k;
+  const double* g = G + node * gstride;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < k * k; e += nt) {
+    int i = e % k, j = e / k;
+    double v = g[e];
+    if (i >= kp || j >= kp) v = (i == j) ? 1.0 : 0.0;
+    A[e] = v;
+  }
+  __syncthreads();
+  if (shift) {
+    __shared__ double tr;
+    if (tid == 0) {
+      double t = 0.0;
+      for (int i = 0; i < kp; ++i) t += A[i + i * k];
+      tr = 11.0 * ((double)mrows * kp + (double)kp * (kp + 1)) * 1.1102230246251565e-16 * t;
+    }
+    __syncthreads();
+    for (int i = tid; i < kp; i += nt) A[i + i * k] += tr;
+    __syncthreads();
+  }
+  // right-looking Cholesky, lower factor in A (column-major)
+  __shared__ int bad;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (tid == 0) {
+      double d = A[j + j * k];
+      if (!(d > 0.0)) { bad = 1; d = 1.0; }
+      A[j + j * k] = sqrt(d);
+    }
+    __syncthreads();
+    const double piv = A[j + j * k];
+    for (int i = j + 1 + tid; i < k; i += nt) A[i + j * k] /= piv;
+    __syncthreads();
+    const int r = k - j - 1;
+    for (int e = tid; e < r * r; e += nt) {
+      int i = j + 1 + e % r, l = j + 1 + e / r;
+      if (i >= l) A[i + l * k] -= A[i + j * k] * A[l + j * k];
+    }
+    __syncthreads();
+  }
+  if (bad && tid == 0) atomicOr(flags, (int)DF_QR_FAIL);
+  // R = L^T (upper), Rinv = (L^{-1})^T; column c of L^{-1} by forward substitution
+  double* Ro = R + node * rstride;
+  double* Ri = Rinv + node * rstride;
+  for (int e = tid; e < k * k; e += nt) {
+    int i = e % k, j = e / k;
+    Ro[e] = (i <= j) ? A[j + i * k] : 0.0;  // R(i,j) = L(j,i)
+  }
+  for (int c = tid; c < k; c += nt) {
+    // x = L^{-1} e_c, rows c..k-1;  Rinv(c, i) = x_i  (Rinv = (L^{-1})^T, upper)
+    for (int i = 0; i < c; ++i) Ri[c + i * k] = 0.0;
+    for (int i = c; i < k; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int l = c; l < i; ++l) s -= A[i + l * k] * Ri[c + l * k];
+      Ri[c + i * k] = s / A[i + i * k];
+    }
+  }
+}
+
+// M = triu(W) + strict_tril(W)^T, W k x k (ld k) per node; zero outside k_P.
+__global__ void k_alg2_fold(const double* W, double* M, long stride, int k, int heap0) {
+  const int node = heap0 + blockIdx.x;
+  const double* w = W + node * stride;
+  double* mm = M + node * stride;
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    int i = e % k, j = e / k;
+    mm[e] = (i <= j) ? w[i + j * k] + ((i < j) ? w[j + i * k] : 0.0) : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Node factor: M_P = I + J S_P = [[I, S_b], [S_a, I]] (2k x 2k), LU with partial
+// pivoting; N_P = M_P^{-1} J = (J + S_P)^{-1}; logdet_P = log det M_P (> 0 required).
+// S_c (k x k, ld k) at S + heap(c)*sstride for the children a = 2P+1, b = 2P+2.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_node_lu(const double* S, long sstride, double* Nout, long nstride,
+                                                 double* logdet, int k, int heap0, int* flags) {
+  __shared__ double A[MMAX * MMAX];
+  __shared__ int piv[MMAX];
+  __shared__ double red_v[256];
+  __shared__ int red_i[256];
+  const int P = heap0 + blockIdx.x;
+  const int a = 2 * P + 1, b = 2 * P + 2;
+  const int m = 2 * k;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < m * m; e += nt) {
+    int i = e % m, j = e / m;
+    double v = (i == j) ? 1.0 : 0.0;
+    if (i < k && j >= k) v = S[b * sstride + i + (j - k) * k];       // top-right: S_b
+    if (i >= k && j < k) v = S[a * sstride + (i - k) + j * k];       // bottom-left: S_a
+    A[e] = v;
+  }
+  __syncthreads();
+  __shared__ double sgn, lsum;
+  if (tid == 0) { sgn = 1.0; lsum = 0.0; }
+  __syncthreads();
+  for (int j = 0; j < m; ++j) {
+    // pivot search over rows j..m-1
+    double best = -1.0;
+    int bi = j;
+    for (int i = j + tid; i < m; i += nt) {
+      double v = fabs(A[i + j * m]);
+      if (v > best) { best = v; bi = i; }
+    }
+    red_v[tid] = best;
+    red_i[tid] = bi;
+    __syncthreads();
+    for (int off = nt / 2; off > 0; off >>= 1) {
+      if (tid < off) {
+        if (red_v[tid + off] > red_v[tid] ||
+            (red_v[tid + off] == red_v[tid] && red_i[tid + off] < red_i[tid])) {
+          red_v[tid] = red_v[tid + off];
+          red_i[tid] = red_i[tid + off];
+        }
+      }
+      __syncthreads();
+    }
+    const int pr = red_i[0];
+    if (tid == 0) piv[j] = pr;
+    if (pr != j) {
+      for (int c = tid; c < m; c += nt) {
+        double t = A[j + c * m];
+        A[j + c * m] = A[pr + c * m];
+        A[pr + c * m] = t;
+      }
+    }
+    __syncthreads();
+    const double d = A[j + j * m];
+    if (tid == 0) {
+      if (pr != j) sgn = -sgn;
+      if (d < 0.0) sgn = -sgn;
+      lsum += log(fabs(d));
+    }
+    if (d != 0.0)
+      for (int i = j + 1 + tid; i < m; i += nt) A[i + j * m] /= d;
+    __syncthreads();
+    const int r = m - j - 1;
+    for (int e = tid; e < r * r; e += nt) {
+      int i = j + 1 + e % r, c = j + 1 + e / r;
+      A[i + c * m] -= A[i + j * m] * A[j + c * m];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    logdet[P] = lsum;
+    if (!(sgn > 0.0) || !isfinite(lsum)) atomicOr(flags, (int)DF_NOT_SPD_NODE);
+  }
+  // inverse: column c of M^{-1} solves L U x = P e_c; N = M^{-1} J (swap column halves)
+  double* No = Nout + P * nstride;
+  for (int c = tid; c < m; c += nt) {
+    const int nc = (c < k) ? c + k : c - k;  // destination column in N
+    double* x = No + (long)nc * m;
+    // apply row permutation to e_c
+    for (int i = 0; i < m; ++i) x[i] = (i == c) ? 1.0 : 0.0;
+    for (int i = 0; i < m; ++i) {
+      int q = piv[i];
+      if (q != i) { double t = x[i]; x[i] = x[q]; x[q] = t; }
+    }
+    for (int i = 0; i < m; ++i) {               // unit lower
+      double s = x[i];
+      for (int l = 0; l < i; ++l) s -= A[i + l * m] * x[l];
+      x[i] = s;
+    }
+    for (int i = m - 1; i >= 0; --i) {          // upper
+      double s = x[i];
+      for (int l = i + 1; l < m; ++l) s -= A[i + l * m] * x[l];
+      x[i] = s / A[i + i * m];
+    }
+  }
+}
+
+hm_status chol_inv_nodes(Model* m, const double* G, long gstride, double* R, double* Rinv, long rstride,
+                         int k, const int* d_kblk, int heap0, int hstep, int cnt, int shift, long mrows) {
+  if (k > KMAX) {
+    set_error("panel width exceeds the per-node LDS limit (64)");
+    return HM_E_INVAL;
+  }
+  hipLaunchKernelGGL(k_chol_inv, dim3(cnt), dim3(256), 0, m->stream, G, gstride, R, Rinv, rstride, k, d_kblk,
+                     heap0, hstep, shift, mrows, m->d_flags);
+  HM_LAUNCH_CHECK();
+  return HM_OK;
+}
+
+hm_status alg2_fold_nodes(Model* m, const double* W, double* M, long stride, int k, int heap0, int cnt) {
+  hipLaunchKernelGGL(k_alg2_fold, dim3(cnt), dim3(256), 0, m->stream, W, M, stride, k, heap0);
+  HM_LAUNCH_CHECK();
+  return HM_OK;
+}
+
+hm_status node_lu(Model* m, const double* S, long sstride, double* Nout, long nstride, double* logdet, int k,
+                  int heap0, int cnt) {
+  if (2 * k > MMAX) {
+    set_error("panel width exceeds the per-node LDS limit (64)");
+    return HM_E_INVAL;
+  }
+  hipLaunchKernelGGL(k_node_lu, dim3(cnt), dim3(256), 0, m->stream, S, sstride, Nout, nstride, logdet, k, heap0,
+                     m->d_flags);
+  HM_LAUNCH_CHECK();
+  return HM_OK;
+}
+
+}  // namespace hm

@@ -1,0 +1,235 @@
+"""Thin ctypes binding of libhmle.so (the C ABI declared in include/hmle.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Device buffers are torch tensors on the GPU (float64, contiguous); a tensor of
+shape (c, n) is an n x c column-major block with leading dimension n.
+The library must be built (paper_2303_10102_amd.build); importing this module
+without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+
+import numpy as np
+
+LIBPATH = Path(__file__).resolve().with_name("libhmle.so")
+PARAM_NAMES = ("kappa", "alpha", "tau2", "sigma2")
+
+_lib = None
+
+
+class HmleError(RuntimeError):
+    def __init__(self, func, status, msg):
+        super().__init__(f"{func} failed with status {status}: {msg}")
+        self.status = status
+
+
+STATUS = {0: "HM_OK", 1: "HM_E_INVAL", 2: "HM_E_NOMEM", 3: "HM_E_NOT_SPD", 4: "HM_E_RANK",
+          5: "HM_E_NONFINITE", 6: "HM_E_STATE", 7: "HM_E_DEVICE"}
+
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+_I = C.c_int
+
+_SIGS = {
+    "hm_last_error": ([], C.c_char_p),
+    "hm_model_create": ([_I, _P, _I, _I, _I, C.POINTER(_P)], _I),
+    "hm_model_destroy": ([_P], None),
+    "hm_model_info": ([_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)], _I),
+    "hm_model_perm": ([_P, C.POINTER(_I)], _I),
+    "hm_kapply": ([_P, _D, _P, _I, _I, _P, _I, _I], _I),
+    "hm_sketch_create": ([_P, _P, _I, _I, _D, C.POINTER(_P)], _I),
+    "hm_sketch_destroy": ([_P], None),
+    "hm_sketch_ranks": ([_P, C.POINTER(_I), C.POINTER(_I)], _I),
+    "hm_H_create": ([_P, _I, C.POINTER(_I), C.POINTER(_P)], _I),
+    "hm_H_destroy": ([_P], None),
+    "hm_build": ([_P, _D], _I),
+    "hm_factor": ([_P], _I),
+    "hm_logdet": ([_P, _D], _I),
+    "hm_solve": ([_P, _P, _P], _I),
+    "hm_loglik_grad": ([_P, _P, _D, _D], _I),
+    "hm_fisher": ([_P, _D], _I),
+    "hm_iteration": ([_P, _D, _P, _D, _D, _D], _I),
+    "hm_export": ([_P, _I, _P], _I),
+}
+
+
+def lib():
+    """Load libhmle.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not LIBPATH.exists():
+            raise RuntimeError(f"{LIBPATH} is missing: build it with paper_2303_10102_amd.build.build()")
+        L = C.CDLL(str(LIBPATH))
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(func, st):
+    if st != 0:
+        msg = lib().hm_last_error().decode(errors="replace")
+        raise HmleError(func, STATUS.get(st, st), msg)
+
+
+def _theta(t):
+    arr = (C.c_double * 4)(*[float(x) for x in t])
+    return arr
+
+
+def _ptr(t):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Model:
+    """SPDE stencil covariance model on a dim-D Dirichlet grid of side N."""
+
+    def __init__(self, dim, N, leaf, device=0, stream=None):
+        import torch
+        self.device = torch.device("cuda", device)
+        h = _P()
+        with torch.cuda.device(device):
+            _check("hm_model_create", lib().hm_model_create(device, _stream_handle(stream), dim, N, leaf, C.byref(h)))
+        self._h = h
+        n, lv, lf = _I(), _I(), _I()
+        _check("hm_model_info", lib().hm_model_info(h, C.byref(n), C.byref(lv), C.byref(lf)))
+        self.dim, self.N, self.n, self.levels, self.leaf = dim, N, n.value, lv.value, lf.value
+
+    def perm(self):
+        out = (C.c_int * self.n)()
+        _check("hm_model_perm", lib().hm_model_perm(self._h, out))
+        return np.frombuffer(out, dtype=np.int32).copy()
+
+    def kapply(self, theta_full, X, which=0):
+        """Y = op X for X a (c, n) float64 CUDA tensor in tree order; op = K, dK/dkappa, dK/dalpha."""
+        import torch
+        c, n = X.shape
+        Y = torch.empty_like(X)
+        _check("hm_kapply", lib().hm_kapply(self._h, _theta(theta_full), _ptr(X), n, c, _ptr(Y), n, which))
+        return Y
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hm_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Sketch:
+    """Fixed test matrices and frozen compression (created once at theta0)."""
+
+    def __init__(self, model, omega, rank, oversample, theta0_full):
+        h = _P()
+        _check("hm_sketch_create", lib().hm_sketch_create(model._h, _ptr(omega), rank, oversample,
+                                                          _theta(theta0_full), C.byref(h)))
+        self._h, self.model = h, model
+
+    def ranks(self):
+        nint = (1 << self.model.levels) - 1
+        k = (C.c_int * nint)()
+        kc = _I()
+        _check("hm_sketch_ranks", lib().hm_sketch_ranks(self._h, k, C.byref(kc)))
+        return np.frombuffer(k, dtype=np.int32).copy(), kc.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hm_sketch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HMatrix:
+    """K~(theta) with derivative matrices for the free parameters, factorisation and traces."""
+
+    def __init__(self, sketch, free):
+        idx = [PARAM_NAMES.index(f) if isinstance(f, str) else int(f) for f in free]
+        arr = (C.c_int * max(1, len(idx)))(*idx)
+        h = _P()
+        _check("hm_H_create", lib().hm_H_create(sketch._h, len(idx), arr, C.byref(h)))
+        self._h, self.sketch, self.p = h, sketch, len(idx)
+        self.model = sketch.model
+
+    def build(self, theta_full):
+        _check("hm_build", lib().hm_build(self._h, _theta(theta_full)))
+
+    def factor(self):
+        _check("hm_factor", lib().hm_factor(self._h))
+
+    def logdet(self):
+        out = C.c_double()
+        _check("hm_logdet", lib().hm_logdet(self._h, C.byref(out)))
+        return out.value
+
+    def solve(self, y):
+        import torch
+        x = torch.empty_like(y)
+        _check("hm_solve", lib().hm_solve(self._h, _ptr(y), _ptr(x)))
+        return x
+
+    def loglik_grad(self, y):
+        ll = C.c_double()
+        g = (C.c_double * max(1, self.p))()
+        _check("hm_loglik_grad", lib().hm_loglik_grad(self._h, _ptr(y), C.byref(ll), g))
+        return ll.value, np.array(g[:self.p])
+
+    def fisher(self):
+        f = (C.c_double * max(1, self.p * self.p))()
+        _check("hm_fisher", lib().hm_fisher(self._h, f))
+        return np.array(f[:self.p * self.p]).reshape(self.p, self.p)
+
+    def iteration(self, theta_full, y):
+        ll = C.c_double()
+        g = (C.c_double * max(1, self.p))()
+        f = (C.c_double * max(1, self.p * self.p))()
+        _check("hm_iteration", lib().hm_iteration(self._h, _theta(theta_full), _ptr(y), C.byref(ll), g, f))
+        return ll.value, np.array(g[:self.p]), np.array(f[:self.p * self.p]).reshape(self.p, self.p)
+
+    def export(self, what):
+        import torch
+        m = self.model
+        _, kc = self.sketch.ranks()
+        if what in (0, 1, 2):
+            shape = (m.levels * kc, m.n)
+        else:
+            shape = (1 << m.levels, m.leaf, m.leaf)
+        out = torch.empty(shape, dtype=torch.float64, device=m.device)
+        _check("hm_export", lib().hm_export(self._h, what, _ptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hm_H_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,91 @@
+"""Shared test cases: seeded workloads, oracle results (CPU) and GPU handles.
+
+Oracle values come only from oracle/ applied to synth/ inputs; GPU values only
+from the HIP library.  The two meet only in the comparisons of the tests.
+"""
+from __future__ import annotations
+
+import functools
+
+import numpy as np
+
+from synth import WORKLOADS, small_workload, sample_y, sketch_draws
+
+CASES = {
+    # the 1D workload itself (n = 1024, leaf 64, 4 levels, rank 16 + 10)
+    "1d_n1024": WORKLOADS["1d_n1024"],
+    # 2D 32x32, leaf 64 (4 levels, 16 leaves), rank 16 + 10, physics-dominated scale
+    "2d_n1024": small_workload(N=32, leaf=64, rank=16, sigma2=1.0e3, name="2d_n1024"),
+    # 2D 64x64 with the headline workload's leaf size and rank
+    "2d_n4096": WORKLOADS["2d_n4096"],
+}
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_case(key):
+    from oracle import peeling
+    from oracle.exact import likelihood_gradient_fisher
+    from oracle.model import Tree, dense_covariance, to_tree_order
+
+    w = CASES[key]
+    y = sample_y(w)
+    K, dKs = dense_covariance(w.dim, w.N, w.theta_full, w.free)
+    tree = Tree(w.dim, w.N, w.levels)
+    Kt = to_tree_order(tree, K)
+    dKt = [to_tree_order(tree, d) for d in dKs]
+    om = sketch_draws(w)
+    V = peeling.sketch_create(Kt, tree, om, w.rank)
+    rep = peeling.build(Kt, dKt, tree, om, V)
+    res = likelihood_gradient_fisher(rep["Kt"], rep["dKts"], to_tree_order(tree, y))
+    return dict(w=w, y=y, Kt=Kt, dKt=dKt, tree=tree, om=om, V=V, rep=rep, res=res)
+
+
+def densify(F, leaves, levels, kc, n, dF=None):
+    """Dense matrix of a HODLR representation exported by the library.
+
+    F, dF: (levels*kc, n) tensors/arrays (column c of the n x levels*kc panel set);
+    leaves: (nleaves, nl, nl) with leaves[L] the column-major block (so block = leaves[L].T).
+    Off-diagonal block of sibling pair (a, b) at depth l: F_a F_b^T, or
+    dF_a F_b^T + F_a dF_b^T for a derivative matrix.
+    """
+    F = np.asarray(F).T
+    dFm = None if dF is None else np.asarray(dF).T
+    K = np.zeros((n, n))
+    for l in range(1, levels + 1):
+        blk = F[:, (l - 1) * kc:l * kc]
+        dblk = None if dFm is None else dFm[:, (l - 1) * kc:l * kc]
+        sz = n >> l
+        for P in range(1 << (l - 1)):
+            a = slice(2 * P * sz, (2 * P + 1) * sz)
+            b = slice((2 * P + 1) * sz, (2 * P + 2) * sz)
+            if dblk is None:
+                m = blk[a] @ blk[b].T
+            else:
+                m = dblk[a] @ blk[b].T + blk[a] @ dblk[b].T
+            K[a, b] = m
+            K[b, a] = m.T
+    lv = np.asarray(leaves)
+    nl = lv.shape[1]
+    for L in range(lv.shape[0]):
+        K[L * nl:(L + 1) * nl, L * nl:(L + 1) * nl] = lv[L].T
+    return K
+
+
+def gpu_case(key):
+    import torch
+
+    from paper_2303_10102_amd import hmle
+
+    w = CASES[key] if isinstance(key, str) else key
+    m = hmle.Model(w.dim, w.N, w.leaf)
+    om = torch.from_numpy(sketch_draws(w)).to("cuda")
+    s = hmle.Sketch(m, om, w.rank, w.oversample, w.theta_full)
+    del om
+    H = hmle.HMatrix(s, w.free)
+    return w, m, s, H
+
+
+def rel_err(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))

@@ -1,0 +1,45 @@
+"""The C-ABI library loads on the CPU host and exports every declared symbol."""
+import re
+from pathlib import Path
+
+import pytest
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+def declared_functions():
+    src = (ROOT / "include" / "hmle.h").read_text()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(hm_[a-zA-Z0-9_]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("hm_model_create", "hm_sketch_create", "hm_H_create", "hm_build", "hm_factor",
+                     "hm_logdet", "hm_solve", "hm_loglik_grad", "hm_fisher", "hm_kapply"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2303_10102_amd import hmle
+    if not hmle.LIBPATH.exists():
+        pytest.skip("libhmle.so not built")
+    L = hmle.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(declared_functions()) == set(hmle.exported_symbols())
+
+
+def test_errors_are_reported_without_a_device():
+    from paper_2303_10102_amd import hmle
+    if not hmle.LIBPATH.exists():
+        pytest.skip("libhmle.so not built")
+    import ctypes as C
+    L = hmle.lib()
+    out = C.c_void_p()
+    # invalid arguments are rejected before any device call
+    assert L.hm_model_create(0, None, 3, 16, 4, C.byref(out)) == 1
+    assert b"dim" in L.hm_last_error()
+    assert L.hm_model_create(0, None, 2, 15, 16, C.byref(out)) == 1    # odd side -> non-uniform tree
+    assert L.hm_factor(None) == 1
