@@ -39,8 +39,8 @@ struct HState {
   ParamBufs pb[4];
   LevelBufs lb;
   NodeBufs nb;
-  double* gtr[4] = {nullptr, nullptr, nullptr, nullptr};
-  double* node_scratch = nullptr;
+  double* node_t = nullptr;    // per internal node (2kc)^2 scratch
+  double* node_s = nullptr;    // per node kc^2 scratch
   double* ytree = nullptr;
   double* z = nullptr;
   double* r = nullptr;
@@ -213,8 +213,6 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
   m->levels = levels;
   m->nleaves = 1 << levels;
   m->nl = (int)(n >> levels);
-  m->Np = (dim == 2) ? N : 1;
-  m->L = N;
   m->h = 1.0 / (N + 1);
   m->cmax = std::max(m->nl, 80);
   bool ok = true;
@@ -222,9 +220,9 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
   A((void**)&m->d_perm, n * sizeof(int));
   A((void**)&m->d_iperm, n * sizeof(int));
   A((void**)&m->d_mu, (size_t)N * sizeof(double));
-  if (dim == 2) A((void**)&m->d_dst, (size_t)N * N * sizeof(double));
-  A((void**)&m->d_thomas, 4 * (size_t)m->L * m->Np * sizeof(double));
-  A((void**)&m->d_ws, 4 * (size_t)n * m->cmax * sizeof(double));
+  A((void**)&m->d_dst, (size_t)N * N * sizeof(double));
+  A((void**)&m->d_lam, 3 * (size_t)n * sizeof(double));
+  A((void**)&m->d_ws, 3 * (size_t)n * m->cmax * sizeof(double));
   A((void**)&m->d_flags, sizeof(int));
   A((void**)&m->d_ident, (size_t)n * m->nl * sizeof(double));
   if (!ok) {
@@ -250,7 +248,7 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
 void hm_model_destroy(hm_model* mm) {
   if (!mm) return;
   Model* m = &mm->m;
-  void* ps[] = {m->d_perm, m->d_iperm, m->d_dst, m->d_mu, m->d_thomas, m->d_ws, m->d_flags, m->d_ident, m->d_red};
+  void* ps[] = {m->d_perm, m->d_iperm, m->d_dst, m->d_mu, m->d_lam, m->d_ws, m->d_flags, m->d_ident, m->d_red};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   delete mm;
@@ -444,9 +442,9 @@ hm_status hm_H_create(hm_sketch* hs, int p, const int* free_idx, hm_H** out) {
     AL(pb.Vt, nodes * s2);
     AL(pb.PsiP, nint * m2);
     AL(pb.Lam, nint * m2);
-    AL(h->gtr[q], nint);
   }
-  AL(h->node_scratch, (size_t)std::max<size_t>(1, nint / 2 + 1) * m2);
+  AL(h->node_t, nint * m2);
+  AL(h->node_s, nodes * s2);
   // construction workspace
   LevelBufs& b = h->lb;
   AL(b.Y, nk);
@@ -607,9 +605,14 @@ hm_status hm_loglik_grad(hm_H* hh, const double* y, double* loglik, double* grad
       HM_CHECK(dots(m, zv, 1, vv, 1, n, h->d_scal + SC_QUAD + q, h->d_part));
       // tr(K~^{-1} K~_j) = sum_L tr(Y_L) - sum_P <N_P, PsiP>
       HM_CHECK(sum_scalar(m, pb.Y, (long)m->nleaves * m->nl, m->nl, h->d_scal + SC_LTR + q, h->d_part));
-      HM_CHECK(node_psi(h->f, pb, h->gtr[q]));
-      HM_CHECK(sum_scalar(m, h->gtr[q], (1 << m->levels) - 1, 0, h->d_scal + SC_NTR + q, h->d_part));
+      HM_CHECK(node_psi(h->f, pb, h->node_s));
     }
+    // node part of every trace: <N_P, PsiP^j> summed over internal nodes
+    const long ms = 4L * h->kc * h->kc;
+    const double* nv[1] = {h->f.Nn};
+    const double* pv[4];
+    for (int q = 0; q < h->p; ++q) pv[q] = h->pb[q].PsiP;
+    HM_CHECK(dots(m, nv, 1, pv, h->p, ((1L << m->levels) - 1) * ms, h->d_scal + SC_NTR, h->d_part));
   }
   HM_HIP(hipStreamSynchronize(m->stream));
   HM_HIP(hipMemcpy(h->h_scal, h->d_scal, 128 * sizeof(double), hipMemcpyDeviceToHost));
@@ -645,8 +648,8 @@ hm_status hm_fisher(hm_H* hh, double* fim) {
   HM_CHECK(prepare_params(h));
   for (int q = 0; q < p; ++q) {
     HM_CHECK(tangent_sweep(h->f, h->pb[q]));
-    HM_CHECK(node_psi(h->f, h->pb[q], h->gtr[q]));
-    HM_CHECK(node_lam(h->f, h->pb[q], h->node_scratch));
+    HM_CHECK(node_psi(h->f, h->pb[q], h->node_s));
+    HM_CHECK(node_lam(h->f, h->pb[q], h->node_t, h->node_s));
     HM_CHECK(panel_products(h->f, h->pb[q]));
   }
   const int n = m->n, kc = h->kc, levels = m->levels;

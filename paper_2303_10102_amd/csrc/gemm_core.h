@@ -91,8 +91,100 @@ __device__ __forceinline__ void tile_store(const ST& st, const double (&acc)[TM]
     for (int j = 0; j < TN; ++j) st(tr + i * C::RS, tc + j * C::CS, acc[i][j]);
 }
 
-// Standard configuration used by the panel kernels.
+// Standard configuration used by the panel kernels: 64 x 64 tiles, 256 threads.
 constexpr int GBM = 64, GBN = 64, GBK = 16, GTM = 4, GTN = 4;
 using GCfg = TileCfg<GBM, GBN, GBK, GTM, GTN>;
+
+// ---------------------------------------------------------------------------
+// Matrix-core path (CDNA3/CDNA4 v_mfma_f64_16x16x4_f64).  The 64 x 64 tile is
+// split over the 4 wavefronts of the workgroup, each owning a 32 x 32 quadrant
+// made of 2 x 2 blocks of 16 x 16.  Operand lane layout of the instruction:
+// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator element
+// v of lane l is D[4 v + l / 16][l % 16].  Same LDS staging as the FMA path.
+// ---------------------------------------------------------------------------
+#ifndef HM_MFMA
+#define HM_MFMA 1
+#endif
+typedef double hm_v4d __attribute__((ext_vector_type(4)));
+
+#if HM_MFMA
+struct TileAcc {
+  hm_v4d c[2][2];
+};
+__device__ __forceinline__ void tile_zero(TileAcc& acc) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc.c[a][b] = hm_v4d{0.0, 0.0, 0.0, 0.0};
+}
+template <class LA, class LB>
+__device__ __forceinline__ void tile_gemm(const LA& la, const LB& lb, int k0, int k1, TileAcc& acc, double* smem) {
+  constexpr int BM = GBM, BN = GBN, BK = GBK, NT = GCfg::NT;
+  double* As = smem;
+  double* Bs = smem + GCfg::LDS_A;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int kb = k0; kb < k1; kb += BK) {
+#pragma unroll
+    for (int e0 = 0; e0 < BM * BK; e0 += NT) {
+      int e = e0 + tid;
+      int i, kk;
+      if (LA::kfast) { kk = e % BK; i = e / BK; } else { i = e % BM; kk = e / BM; }
+      int k = kb + kk;
+      As[kk * (BM + 1) + i] = (k < k1) ? la(i, k) : 0.0;
+    }
+#pragma unroll
+    for (int e0 = 0; e0 < BN * BK; e0 += NT) {
+      int e = e0 + tid;
+      int j, kk;
+      if (LB::kfast) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
+      int k = kb + kk;
+      Bs[kk * (BN + 1) + j] = (k < k1) ? lb(k, j) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + lk;
+      const double a0 = As[kr * (BM + 1) + wr + li];
+      const double a1 = As[kr * (BM + 1) + wr + 16 + li];
+      const double b0 = Bs[kr * (BN + 1) + wc + li];
+      const double b1 = Bs[kr * (BN + 1) + wc + 16 + li];
+      acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc.c[0][0], 0, 0, 0);
+      acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.c[0][1], 0, 0, 0);
+      acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.c[1][0], 0, 0, 0);
+      acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc.c[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+}
+template <class ST>
+__device__ __forceinline__ void tile_store(const ST& st, const TileAcc& acc) {
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) st(wr + a * 16 + 4 * v + lk, wc + b * 16 + li, acc.c[a][b][v]);
+}
+#else
+struct TileAcc {
+  double c[GTM][GTN];
+};
+__device__ __forceinline__ void tile_zero(TileAcc& acc) { tile_zero<GBM, GBN, GTM, GTN>(acc.c); }
+template <class LA, class LB>
+__device__ __forceinline__ void tile_gemm(const LA& la, const LB& lb, int k0, int k1, TileAcc& acc, double* smem) {
+  tile_gemm_acc<GBM, GBN, GBK, GTM, GTN>(la, lb, k0, k1, acc.c, smem);
+}
+template <class ST>
+__device__ __forceinline__ void tile_store(const ST& st, const TileAcc& acc) {
+  tile_store<GBM, GBN, GBK, GTM, GTN>(st, acc.c);
+}
+#endif
 
 }  // namespace hm

@@ -54,19 +54,16 @@ struct Model {
   int device = 0;
   hipStream_t stream = nullptr;
   int dim = 2, N = 0, n = 0, levels = 0, nl = 0, nleaves = 0;
-  int Np = 1;           // number of x-modes per line family (N in 2D, 1 in 1D)
-  int L = 0;            // length of a y-line (N)
   double h = 0.0;
   int* d_perm = nullptr;    // tree position -> grid index
   int* d_iperm = nullptr;   // grid index -> tree position
-  double* d_dst = nullptr;  // N x N orthonormal DST-I (2D)
-  double* d_mu = nullptr;   // Np mode eigenvalues of -Lap_x (0 in 1D)
-  // Thomas factor coefficients for A_p and B_p, layout [i*Np + p]
-  double* d_thomas = nullptr;   // 4 * L * Np: cA, imA, cB, imB
-  double thomas_key[2] = {-1.0, -1.0};  // (kappa, alpha) the coefficients belong to
-  // K-apply workspace (grid / mode space), sized for cmax columns
+  double* d_dst = nullptr;  // N x N orthonormal DST-I
+  double* d_mu = nullptr;   // N eigenvalues of the 1D -Laplacian
+  double* d_lam = nullptr;  // per-mode multipliers of K, dK/dkappa, dK/dalpha (3 * n)
+  double lam_key[4] = {-1.0, -1.0, -1.0, -1.0};  // theta they belong to
+  // K-apply workspace (mode space), sized for cmax columns
   int cmax = 0;
-  double* d_ws = nullptr;       // 4 * n * cmax
+  double* d_ws = nullptr;       // 3 * n * cmax
   int* d_flags = nullptr;       // device status flags
   double* d_ident = nullptr;    // stacked identities n x nl (tree order), for the leaf pass
   double* d_red = nullptr;      // per-leaf partials of tree_reduce

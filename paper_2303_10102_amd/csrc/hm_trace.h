@@ -10,8 +10,8 @@ hm_status sum_scalar(Model* m, const double* x, long len, int diag_nl, double* o
 hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double theta[4], const double* tF_prefix);
 hm_status tangent_sweep(FactorCtx& f, ParamBufs& pb);
 hm_status node_prep(FactorCtx& f);
-hm_status node_psi(FactorCtx& f, ParamBufs& pb, double* gtr);
-hm_status node_lam(FactorCtx& f, ParamBufs& pb, double* scratch);
+hm_status node_psi(FactorCtx& f, ParamBufs& pb, double* xtmp);
+hm_status node_lam(FactorCtx& f, ParamBufs& pb, double* tbuf, double* dsbuf);
 hm_status panel_products(FactorCtx& f, ParamBufs& pb);
 
 }  // namespace hm

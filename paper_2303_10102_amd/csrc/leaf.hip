@@ -96,19 +96,58 @@ __global__ void __launch_bounds__(256) k_leaf_chol(double* W, int nl, double* lo
   }
 }
 
-// Linv = L^{-1} (lower), one column per thread.
-__global__ void k_leaf_trinv(const double* Lf, double* Li, int nl) {
-  const int L = blockIdx.y;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nl) return;
-  const double* A = Lf + (long)L * nl * nl;
-  double* X = Li + (long)L * nl * nl + (long)j * nl;
-  for (int i = 0; i < j; ++i) X[i] = 0.0;
-  X[j] = 1.0 / A[j + (long)j * nl];
-  for (int i = j + 1; i < nl; ++i) {
-    double s = 0.0;
-    for (int l = j; l < i; ++l) s += A[i + (long)l * nl] * X[l];
-    X[i] = -s / A[i + (long)i * nl];
+// U = L^{-T} (upper, column-major), i.e. L^{-1} stored row-major: U[j + i*nl] = (L^{-1})(i, j).
+// Blocked forward substitution on the identity, one leaf per workgroup.  For
+// block row ib (rows r0..r0+nb): R = E - L[r0:, 0:r0] X[0:r0, :], X[r0:, :] = L_ii^{-1} R.
+// Thread j owns column j; the block row of L is staged in LDS (read as
+// broadcasts), earlier rows of X are read back from U (coalesced over j).
+constexpr int TB = 32;
+__global__ void __launch_bounds__(256) k_leaf_trinv(const double* Lf, double* U, int nl) {
+  __shared__ double Lp[TB * NLMAX];   // Lp[r * nl + c] = L(r0 + r, c), c < r0 + nb
+  __shared__ double Ti[TB * TB];      // (L_ii)^{-1}, row-major
+  const int Lidx = blockIdx.x;
+  const double* A = Lf + (long)Lidx * nl * nl;
+  double* X = U + (long)Lidx * nl * nl;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int r0 = 0; r0 < nl; r0 += TB) {
+    const int nb = min(TB, nl - r0);
+    const int w = r0 + nb;
+    for (int e = tid; e < nb * w; e += nt) {
+      int r = e / w, c = e % w;
+      Lp[r * nl + c] = A[(r0 + r) + (long)c * nl];
+    }
+    __syncthreads();
+    // inverse of the diagonal block: column t of Ti^T ... thread t solves L_ii x = e_t
+    if (tid < nb) {
+      const int t = tid;
+      for (int r = 0; r < nb; ++r) {
+        double v = (r == t) ? 1.0 : 0.0;
+        for (int q = t; q < r; ++q) v -= Lp[r * nl + r0 + q] * Ti[q * TB + t];
+        Ti[r * TB + t] = (r < t) ? 0.0 : v / Lp[r * nl + r0 + r];
+      }
+    }
+    __syncthreads();
+    for (int j = tid; j < nl; j += nt) {
+      double acc[TB];
+#pragma unroll
+      for (int r = 0; r < TB; ++r) acc[r] = (r < nb && r0 + r == j) ? 1.0 : 0.0;
+      if (j < r0) {
+        for (int c = j; c < r0; ++c) {
+          const double x = X[j + (long)c * nl];
+#pragma unroll
+          for (int r = 0; r < TB; ++r)
+            if (r < nb) acc[r] -= Lp[r * nl + c] * x;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < TB; ++r) {
+        if (r >= nb) break;
+        double v = 0.0;
+        for (int t = 0; t < nb; ++t) v += Ti[r * TB + t] * acc[t];
+        X[j + (long)(r0 + r) * nl] = (j <= r0 + r) ? v : 0.0;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -123,10 +162,10 @@ hm_status leaf_factor(Model* m, const double* D, double* Dinv, double* logdet_le
   HM_HIP(hipMemcpyAsync(work, D, sz * sizeof(double), hipMemcpyDeviceToDevice, m->stream));
   hipLaunchKernelGGL(k_leaf_chol, dim3(m->nleaves), dim3(256), 0, m->stream, work, nl, logdet_leaf, m->d_flags);
   HM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_leaf_trinv, dim3(ceil_div(nl, 64), m->nleaves), dim3(64), 0, m->stream, work, Dinv, nl);
+  hipLaunchKernelGGL(k_leaf_trinv, dim3(m->nleaves), dim3(256), 0, m->stream, work, Dinv, nl);
   HM_LAUNCH_CHECK();
-  // Dinv currently holds L^{-1}; form L^{-T} L^{-1} into work, then copy back
-  HM_CHECK(gemm(m->stream, true, false, nl, nl, nl, 1.0, Dinv, nl, (long)nl * nl, Dinv, nl, (long)nl * nl, 0.0,
+  // Dinv currently holds U = L^{-T}; form U U^T = L^{-T} L^{-1} into work, then copy back
+  HM_CHECK(gemm(m->stream, false, true, nl, nl, nl, 1.0, Dinv, nl, (long)nl * nl, Dinv, nl, (long)nl * nl, 0.0,
                 work, nl, (long)nl * nl, m->nleaves));
   HM_HIP(hipMemcpyAsync(Dinv, work, sz * sizeof(double), hipMemcpyDeviceToDevice, m->stream));
   return HM_OK;

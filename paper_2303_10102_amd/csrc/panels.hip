@@ -63,10 +63,10 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int Nc, int K, double alpha
   int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
   LdA<TA> la{A + b * sA, lda, m0, M};
   LdB<TB> lb{B + b * sB, ldb, n0, Nc};
-  double acc[GTM][GTN];
-  tile_zero<GBM, GBN, GTM, GTN>(acc);
-  tile_gemm_acc<GBM, GBN, GBK, GTM, GTN>(la, lb, 0, K, acc, smem);
-  tile_store<GBM, GBN, GBK, GTM, GTN>(StC{C + b * sC, ldc, m0, n0, M, Nc, alpha, beta}, acc);
+  TileAcc acc;
+  tile_zero(acc);
+  tile_gemm(la, lb, 0, K, acc, smem);
+  tile_store(StC{C + b * sC, ldc, m0, n0, M, Nc, alpha, beta}, acc);
 }
 
 hm_status gemm(hipStream_t st, bool ta, bool tb, int M, int Nc, int K, double alpha, const double* A,
@@ -132,9 +132,9 @@ __global__ void __launch_bounds__(256) k_reduce_partial(RedArgs a) {
   const int ac0 = a.ac.c0(d), xc0 = a.xc.c0(d);
   RedLA la{a.A + r0 + (long)ac0 * a.lda, a.lda, m0, wa};
   RedLB lb{a.X + r0 + (long)xc0 * a.ldx, a.ldx, n0, wx};
-  double acc[GTM][GTN];
-  tile_zero<GBM, GBN, GTM, GTN>(acc);
-  tile_gemm_acc<GBM, GBN, GBK, GTM, GTN>(la, lb, 0, a.nl, acc, smem);
+  TileAcc acc;
+  tile_zero(acc);
+  tile_gemm(la, lb, 0, a.nl, acc, smem);
   double* dst;
   if (d == a.levels) {
     int heap = (1 << d) - 1 + L;
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(256) k_reduce_partial(RedArgs a) {
   } else {
     dst = a.partial + ((long)L * ndep + (d - a.d0)) * a.pstride;
   }
-  tile_store<GBM, GBN, GBK, GTM, GTN>(StC{dst, wa, m0, n0, wa, wx, 1.0, 0.0}, acc);
+  tile_store(StC{dst, wa, m0, n0, wa, wx, 1.0, 0.0}, acc);
 }
 
 __global__ void k_reduce_tree(RedArgs a, int d) {
@@ -255,8 +255,8 @@ __global__ void __launch_bounds__(256) k_expand(ExpArgs a) {
   const int j0 = a.ylo + blockIdx.y * GBN;  // absolute first column of this tile
   const long r0 = (long)L * a.nl;
   const int wk = a.ac.w0;
-  double acc[GTM][GTN];
-  tile_zero<GBM, GBN, GTM, GTN>(acc);
+  TileAcc acc;
+  tile_zero(acc);
   for (int d = a.d0; d <= a.d1; ++d) {
     const int yc0 = a.yc.c0(d), wy = a.yc.w(d);
     if (wy <= 0 || j0 >= yc0 + wy || j0 + GBN <= yc0) continue;
@@ -267,10 +267,10 @@ __global__ void __launch_bounds__(256) k_expand(ExpArgs a) {
     else if (a.tmode == 2) { sel = (heap - 1) >> 1; roff = (c & 1) ? a.half_off : 0; }
     ExpLA la{a.A + r0 + (long)a.ac.c0(d) * a.lda, a.lda, m0, a.nl};
     ExpLB lb{a.T + sel * a.t_stride + roff, a.ldt, j0 - yc0, wy};
-    tile_gemm_acc<GBM, GBN, GBK, GTM, GTN>(la, lb, 0, wk, acc, smem);
+    tile_gemm(la, lb, 0, wk, acc, smem);
   }
   ExpSt st{a.Y + r0, a.ldy, m0, j0, a.nl, a.yhi, a.alpha, a.beta};
-  tile_store<GBM, GBN, GBK, GTM, GTN>(st, acc);
+  tile_store(st, acc);
 }
 
 hm_status tree_expand(Model* m, const ExpandJob& j) {
@@ -305,10 +305,10 @@ __global__ void __launch_bounds__(256) k_leaf_gemm(const double* Dm, const doubl
   const long r0 = (long)L * nl;
   LdA<false> la{Dm + (long)L * nl * nl, nl, m0, nl};
   LdB<false> lb{X + r0, ldx, n0, w};
-  double acc[GTM][GTN];
-  tile_zero<GBM, GBN, GTM, GTN>(acc);
-  tile_gemm_acc<GBM, GBN, GBK, GTM, GTN>(la, lb, 0, nl, acc, smem);
-  tile_store<GBM, GBN, GBK, GTM, GTN>(StC{Y + r0, ldy, m0, n0, nl, w, alpha, beta}, acc);
+  TileAcc acc;
+  tile_zero(acc);
+  tile_gemm(la, lb, 0, nl, acc, smem);
+  tile_store(StC{Y + r0, ldy, m0, n0, nl, w, alpha, beta}, acc);
 }
 
 hm_status leaf_gemm(Model* m, const double* Dm, const double* X, int ldx, double* Y, int ldy, int w,

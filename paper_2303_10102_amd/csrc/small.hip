@@ -6,7 +6,8 @@
 //  * k_alg2_fold    M = triu(W) + strict_tril(W)^T for Alg. 2 (W = Q^T dB R^{-1}):
 //                   dQ = dB R^{-1} - Q M.
 //  * k_node_lu      N_P = (J + S_P)^{-1} and log det(I + V^T U) for the Woodbury
-//                   factor of node P (Sec. 3.1, App. C; Sylvester's identity).
+//                   factor of node P (Sec. 3.1, App. C; Sylvester's identity), via
+//                   the k x k Schur complement I - S_a S_b.
 #include <cmath>
 
 #include "hm_internal.h"
@@ -14,7 +15,6 @@
 namespace hm {
 
 constexpr int KMAX = 64;    // largest panel width handled in LDS
-constexpr int MMAX = 128;   // 2*KMAX
 
 // ---------------------------------------------------------------------------
 // Cholesky + triangular inverse of G (k x k, ld k), one node per workgroup.
@@ -101,75 +101,76 @@ __global__ void k_alg2_fold(const double* W, double* M, long stride, int k, int 
 }
 
 // ---------------------------------------------------------------------------
-// Node factor: M_P = I + J S_P = [[I, S_b], [S_a, I]] (2k x 2k), LU with partial
-// pivoting; N_P = M_P^{-1} J = (J + S_P)^{-1}; logdet_P = log det M_P (> 0 required).
-// S_c (k x k, ld k) at S + heap(c)*sstride for the children a = 2P+1, b = 2P+2.
+// Node factor.  M_P = I + J S_P = [[I, S_b], [S_a, I]] with S_c = F_c^T G_c.  With
+// the Schur complement Sig = I - S_a S_b (for SPD K~_P its eigenvalues lie in
+// (0, 1]):  det M_P = det Sig  and
+//   M_P^{-1} = [[I + S_b Sig^{-1} S_a, -S_b Sig^{-1}], [-Sig^{-1} S_a, Sig^{-1}]],
+//   N_P = M_P^{-1} J = [[-S_b Sig^{-1}, I + S_b Sig^{-1} S_a], [Sig^{-1}, -Sig^{-1} S_a]] = (J + S_P)^{-1}.
+// logdet_P = log det M_P (> 0 required, else the node is flagged not SPD).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_node_lu(const double* S, long sstride, double* Nout, long nstride,
                                                  double* logdet, int k, int heap0, int* flags) {
-  __shared__ double A[MMAX * MMAX];
-  __shared__ int piv[MMAX];
-  __shared__ double red_v[256];
-  __shared__ int red_i[256];
+  __shared__ double Sa[KMAX * KMAX];
+  __shared__ double Sb[KMAX * KMAX];
+  __shared__ double A[KMAX * KMAX];     // Sig, then its LU factors
+  __shared__ double Si[KMAX * KMAX];    // Sig^{-1}
+  __shared__ int piv[KMAX];
+  __shared__ double sgn, lsum;
   const int P = heap0 + blockIdx.x;
   const int a = 2 * P + 1, b = 2 * P + 2;
-  const int m = 2 * k;
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int e = tid; e < m * m; e += nt) {
-    int i = e % m, j = e / m;
-    double v = (i == j) ? 1.0 : 0.0;
-    if (i < k && j >= k) v = S[b * sstride + i + (j - k) * k];       // top-right: S_b
-    if (i >= k && j < k) v = S[a * sstride + (i - k) + j * k];       // bottom-left: S_a
-    A[e] = v;
+  const int kk = k * k;
+  for (int e = tid; e < kk; e += nt) {
+    Sa[e] = S[a * sstride + e];
+    Sb[e] = S[b * sstride + e];
   }
   __syncthreads();
-  __shared__ double sgn, lsum;
+  for (int e = tid; e < kk; e += nt) {
+    int i = e % k, j = e / k;
+    double v = (i == j) ? 1.0 : 0.0;
+    for (int l = 0; l < k; ++l) v -= Sa[i + l * k] * Sb[l + j * k];
+    A[e] = v;
+  }
   if (tid == 0) { sgn = 1.0; lsum = 0.0; }
   __syncthreads();
-  for (int j = 0; j < m; ++j) {
-    // pivot search over rows j..m-1
-    double best = -1.0;
-    int bi = j;
-    for (int i = j + tid; i < m; i += nt) {
-      double v = fabs(A[i + j * m]);
-      if (v > best) { best = v; bi = i; }
-    }
-    red_v[tid] = best;
-    red_i[tid] = bi;
-    __syncthreads();
-    for (int off = nt / 2; off > 0; off >>= 1) {
-      if (tid < off) {
-        if (red_v[tid + off] > red_v[tid] ||
-            (red_v[tid + off] == red_v[tid] && red_i[tid + off] < red_i[tid])) {
-          red_v[tid] = red_v[tid + off];
-          red_i[tid] = red_i[tid + off];
-        }
+  // LU with partial pivoting; the pivot search is done by the first wavefront
+  for (int j = 0; j < k; ++j) {
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = j;
+      for (int i = j + tid; i < k; i += 64) {
+        double v = fabs(A[i + j * k]);
+        if (v > best) { best = v; bi = i; }
       }
-      __syncthreads();
-    }
-    const int pr = red_i[0];
-    if (tid == 0) piv[j] = pr;
-    if (pr != j) {
-      for (int c = tid; c < m; c += nt) {
-        double t = A[j + c * m];
-        A[j + c * m] = A[pr + c * m];
-        A[pr + c * m] = t;
+      for (int off = 32; off > 0; off >>= 1) {
+        double ob = __shfl_xor(best, off, 64);
+        int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
       }
+      if (tid == 0) piv[j] = bi;
     }
     __syncthreads();
-    const double d = A[j + j * m];
+    const int pr = piv[j];
+    if (pr != j)
+      for (int c = tid; c < k; c += nt) {
+        double t = A[j + c * k];
+        A[j + c * k] = A[pr + c * k];
+        A[pr + c * k] = t;
+      }
+    __syncthreads();
+    const double d = A[j + j * k];
     if (tid == 0) {
       if (pr != j) sgn = -sgn;
       if (d < 0.0) sgn = -sgn;
       lsum += log(fabs(d));
     }
     if (d != 0.0)
-      for (int i = j + 1 + tid; i < m; i += nt) A[i + j * m] /= d;
+      for (int i = j + 1 + tid; i < k; i += nt) A[i + j * k] /= d;
     __syncthreads();
-    const int r = m - j - 1;
+    const int r = k - j - 1;
     for (int e = tid; e < r * r; e += nt) {
       int i = j + 1 + e % r, c = j + 1 + e / r;
-      A[i + c * m] -= A[i + j * m] * A[j + c * m];
+      A[i + c * k] -= A[i + j * k] * A[j + c * k];
     }
     __syncthreads();
   }
@@ -177,27 +178,47 @@ __global__ void __launch_bounds__(256) k_node_lu(const double* S, long sstride, 
     logdet[P] = lsum;
     if (!(sgn > 0.0) || !isfinite(lsum)) atomicOr(flags, (int)DF_NOT_SPD_NODE);
   }
-  // inverse: column c of M^{-1} solves L U x = P e_c; N = M^{-1} J (swap column halves)
-  double* No = Nout + P * nstride;
-  for (int c = tid; c < m; c += nt) {
-    const int nc = (c < k) ? c + k : c - k;  // destination column in N
-    double* x = No + (long)nc * m;
-    // apply row permutation to e_c
-    for (int i = 0; i < m; ++i) x[i] = (i == c) ? 1.0 : 0.0;
-    for (int i = 0; i < m; ++i) {
+  // Sig^{-1}: column c solves L U x = P e_c
+  for (int c = tid; c < k; c += nt) {
+    double* x = Si + c * k;
+    for (int i = 0; i < k; ++i) x[i] = (i == c) ? 1.0 : 0.0;
+    for (int i = 0; i < k; ++i) {
       int q = piv[i];
       if (q != i) { double t = x[i]; x[i] = x[q]; x[q] = t; }
     }
-    for (int i = 0; i < m; ++i) {               // unit lower
+    for (int i = 0; i < k; ++i) {
       double s = x[i];
-      for (int l = 0; l < i; ++l) s -= A[i + l * m] * x[l];
+      for (int l = 0; l < i; ++l) s -= A[i + l * k] * x[l];
       x[i] = s;
     }
-    for (int i = m - 1; i >= 0; --i) {          // upper
+    for (int i = k - 1; i >= 0; --i) {
       double s = x[i];
-      for (int l = i + 1; l < m; ++l) s -= A[i + l * m] * x[l];
-      x[i] = s / A[i + i * m];
+      for (int l = i + 1; l < k; ++l) s -= A[i + l * k] * x[l];
+      x[i] = s / A[i + i * k];
     }
+  }
+  __syncthreads();
+  // P1 = S_b Sig^{-1} -> A (LU no longer needed)
+  for (int e = tid; e < kk; e += nt) {
+    int i = e % k, j = e / k;
+    double v = 0.0;
+    for (int l = 0; l < k; ++l) v += Sb[i + l * k] * Si[l + j * k];
+    A[e] = v;
+  }
+  __syncthreads();
+  const int m = 2 * k;
+  double* No = Nout + P * nstride;
+  for (int e = tid; e < kk; e += nt) {
+    int i = e % k, j = e / k;
+    double n12 = (i == j) ? 1.0 : 0.0, n22 = 0.0;
+    for (int l = 0; l < k; ++l) {
+      n12 += A[i + l * k] * Sa[l + j * k];
+      n22 -= Si[i + l * k] * Sa[l + j * k];
+    }
+    No[i + (long)j * m] = -A[e];                 // N11 = -S_b Sig^{-1}
+    No[i + (long)(k + j) * m] = n12;             // N12 = I + S_b Sig^{-1} S_a
+    No[(k + i) + (long)j * m] = Si[e];           // N21 = Sig^{-1}
+    No[(k + i) + (long)(k + j) * m] = n22;       // N22 = -Sig^{-1} S_a
   }
 }
 
@@ -221,7 +242,7 @@ hm_status alg2_fold_nodes(Model* m, const double* W, double* M, long stride, int
 
 hm_status node_lu(Model* m, const double* S, long sstride, double* Nout, long nstride, double* logdet, int k,
                   int heap0, int cnt) {
-  if (2 * k > MMAX) {
+  if (k > KMAX) {
     set_error("panel width exceeds the per-node LDS limit (64)");
     return HM_E_INVAL;
   }

@@ -100,11 +100,17 @@ __global__ void __launch_bounds__(256) k_dots_partial(DotArgs a, double* partial
   }
 }
 __global__ void k_dots_final(const double* partial, int nblocks, int nq, double* out) {
-  int q = threadIdx.x;
-  if (q >= nq) return;
+  __shared__ double red[256];
+  const int q = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partial[(long)b * 16 + q];
-  out[q] = s;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += partial[(long)b * 16 + q];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[q] = red[0];
 }
 
 hm_status dots(Model* m, const double* const* A, int na, const double* const* B, int nb, long len, double* out,
@@ -118,7 +124,7 @@ hm_status dots(Model* m, const double* const* A, int na, const double* const* B,
   int nblk = (int)std::min<long>(DOT_BLOCKS, std::max<long>(1, ceil_div(len, 256)));
   hipLaunchKernelGGL(k_dots_partial, dim3(nblk), dim3(256), 0, m->stream, a, partial);
   HM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(64), 0, m->stream, partial, nblk, na * nb, out);
+  hipLaunchKernelGGL(k_dots_final, dim3(na * nb), dim3(256), 0, m->stream, partial, nblk, na * nb, out);
   HM_LAUNCH_CHECK();
   return HM_OK;
 }
@@ -147,130 +153,111 @@ hm_status sum_scalar(Model* m, const double* x, long len, int diag_nl, double* o
   int nblk = (int)std::min<long>(DOT_BLOCKS, std::max<long>(1, ceil_div(len, 256)));
   hipLaunchKernelGGL(k_sum_partial, dim3(nblk), dim3(256), 0, m->stream, x, len, diag_nl, partial);
   HM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(64), 0, m->stream, partial, nblk, 1, out);
+  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(256), 0, m->stream, partial, nblk, 1, out);
   HM_LAUNCH_CHECK();
   return HM_OK;
 }
 
 // ---------------------------------------------------------------------------
-// per-node preparation: Ncc_c = N_P[c,c], Nx_c = N_P[c,sib] S_sib (children of P)
+// Per-node small products.  Every internal node P (heap 0..nint-1, children
+// a = 2P+1, b = 2P+2) is one batch entry of a strided batched GEMM, so each
+// product is a single launch over the whole tree.
+//   N_P blocks: N11 = N[0:k,0:k] (at N), N12 = N[0:k,k:2k] (at N + k*m),
+//               N21 = N[k:2k,0:k] (at N + k), N22 (at N + k + k*m); m = 2k, ld m.
 // ---------------------------------------------------------------------------
-__global__ void k_node_prep(const double* Nn, const double* Sn, double* Ncc, double* Nx, int kc, int heap0) {
-  const int P = heap0 + blockIdx.x;
-  const int m2 = 2 * kc;
+// out_a = N11, out_b = N22 (copies); all internal nodes
+__global__ void k_node_diag(const double* Nn, double* Ncc, int kc, int nint) {
   const long s2 = (long)kc * kc;
+  const int m2 = 2 * kc;
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nint * s2) return;
+  int P = (int)(e / s2);
+  int r = (int)(e % s2), i = r % kc, j = r / kc;
   const double* N = Nn + (long)P * m2 * m2;
-  const int a = 2 * P + 1, b = 2 * P + 2;
-  for (int e = threadIdx.x; e < kc * kc; e += blockDim.x) {
-    int i = e % kc, j = e / kc;
-    Ncc[a * s2 + e] = N[i + (long)j * m2];
-    Ncc[b * s2 + e] = N[(kc + i) + (long)(kc + j) * m2];
-    double sa = 0.0, sb = 0.0;
-    for (int l = 0; l < kc; ++l) {
-      sa += N[i + (long)(kc + l) * m2] * Sn[b * s2 + l + (long)j * kc];      // N[a,b] S_b
-      sb += N[(kc + i) + (long)l * m2] * Sn[a * s2 + l + (long)j * kc];      // N[b,a] S_a
-    }
-    Nx[a * s2 + e] = sa;
-    Nx[b * s2 + e] = sb;
-  }
+  Ncc[(2L * P + 1) * s2 + r] = N[i + (long)j * m2];
+  Ncc[(2L * P + 2) * s2 + r] = N[(kc + i) + (long)(kc + j) * m2];
 }
 
-// ---------------------------------------------------------------------------
-// per-node assembly for one parameter (one workgroup per internal node P):
-//   k_node_psi: X_ab = E_a^T S_b + S_a E_b,  PsiP = [[Psi_a, X_ab], [X_ab^T, Psi_b]],
-//               gtr_P = <N_P, PsiP>
-//   k_node_lam: dS_c = E_c + W_c^T,  Lam = N diag(dS_a, dS_b) N,
-//               Vt_a = (N[a,b] W_b)^T,  Vt_b = (N[b,a] W_a)^T.
-// ---------------------------------------------------------------------------
-constexpr int AKMAX = 64;
-__global__ void __launch_bounds__(256) k_node_psi(const double* Nn, const double* Sn, const double* E,
-                                                  const double* Psi, double* PsiP, double* gtr, int kc, int heap0) {
-  __shared__ double Xs[AKMAX * AKMAX];
-  __shared__ double red[256];
-  const int P = heap0 + blockIdx.x;
-  const int a = 2 * P + 1, b = 2 * P + 2;
+// PsiP = [[Psi_a, X_P], [X_P^T, Psi_b]] for all internal nodes
+__global__ void k_node_psi_assemble(const double* Psi, const double* X, double* PsiP, int kc, int nint) {
+  const long s2 = (long)kc * kc;
   const int m2 = 2 * kc;
-  const long s2 = (long)kc * kc, ms = (long)m2 * m2;
-  const double* N = Nn + P * ms;
-  const double *Ea = E + a * s2, *Eb = E + b * s2, *Sa = Sn + a * s2, *Sb = Sn + b * s2;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int e = tid; e < kc * kc; e += nt) {
-    int i = e % kc, j = e / kc;
-    double x = 0.0;
-    for (int l = 0; l < kc; ++l)
-      x += Ea[l + (long)i * kc] * Sb[l + (long)j * kc] + Sa[i + (long)l * kc] * Eb[l + (long)j * kc];
-    Xs[e] = x;
-  }
-  __syncthreads();
-  double* PP = PsiP + P * ms;
-  double g = 0.0;
-  for (int e = tid; e < m2 * m2; e += nt) {
-    int i = e % m2, j = e / m2;
-    double v;
-    if (i < kc && j < kc) v = Psi[a * s2 + i + (long)j * kc];
-    else if (i >= kc && j >= kc) v = Psi[b * s2 + (i - kc) + (long)(j - kc) * kc];
-    else if (i < kc) v = Xs[i + (j - kc) * kc];
-    else v = Xs[j + (i - kc) * kc];
-    PP[e] = v;
-    g += N[e] * v;
-  }
-  red[tid] = g;
-  __syncthreads();
-  for (int off = nt / 2; off > 0; off >>= 1) {
-    if (tid < off) red[tid] += red[tid + off];
-    __syncthreads();
-  }
-  if (tid == 0) gtr[P] = red[0];
+  const long ms = (long)m2 * m2;
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nint * ms) return;
+  int P = (int)(e / ms);
+  int r = (int)(e % ms), i = r % m2, j = r / m2;
+  double v;
+  if (i < kc && j < kc) v = Psi[(2L * P + 1) * s2 + i + (long)j * kc];
+  else if (i >= kc && j >= kc) v = Psi[(2L * P + 2) * s2 + (i - kc) + (long)(j - kc) * kc];
+  else if (i < kc) v = X[P * s2 + i + (long)(j - kc) * kc];
+  else v = X[P * s2 + j + (long)(i - kc) * kc];
+  PsiP[e] = v;
 }
 
-__global__ void __launch_bounds__(256) k_node_lam(const double* Nn, const double* E, const double* W, double* Lam,
-                                                  double* Vt, double* scratch, int kc, int heap0) {
-  __shared__ double dSa[AKMAX * AKMAX];
-  __shared__ double dSb[AKMAX * AKMAX];
-  const int P = heap0 + blockIdx.x;
-  const int a = 2 * P + 1, b = 2 * P + 2;
-  const int m2 = 2 * kc;
+// dS_c = E_c + W_c^T for all non-root nodes
+__global__ void k_node_dS(const double* E, const double* W, double* dS, int kc, long nodes) {
+  const long s2 = (long)kc * kc;
+  long e = s2 + (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nodes * s2) return;
+  long c = e / s2;
+  int r = (int)(e % s2), i = r % kc, j = r / kc;
+  dS[e] = E[e] + W[c * s2 + j + (long)i * kc];
+}
+
+hm_status node_prep(FactorCtx& f) {
+  Model* m = f.m;
+  const int kc = f.kc, m2 = 2 * kc;
   const long s2 = (long)kc * kc, ms = (long)m2 * m2;
-  const double* N = Nn + P * ms;
-  const double *Ea = E + a * s2, *Eb = E + b * s2, *Wa = W + a * s2, *Wb = W + b * s2;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int e = tid; e < kc * kc; e += nt) {
-    int i = e % kc, j = e / kc;
-    dSa[e] = Ea[e] + Wa[j + (long)i * kc];
-    dSb[e] = Eb[e] + Wb[j + (long)i * kc];
-  }
-  __syncthreads();
-  // T = N diag(dS_a, dS_b)
-  double* T = scratch + (long)blockIdx.x * ms;
-  for (int e = tid; e < m2 * m2; e += nt) {
-    int i = e % m2, j = e / m2;
-    double v = 0.0;
-    if (j < kc) {
-      for (int l = 0; l < kc; ++l) v += N[i + (long)l * m2] * dSa[l + j * kc];
-    } else {
-      for (int l = 0; l < kc; ++l) v += N[i + (long)(kc + l) * m2] * dSb[l + (j - kc) * kc];
-    }
-    T[e] = v;
-  }
-  __syncthreads();
-  double* Lp = Lam + P * ms;
-  for (int e = tid; e < m2 * m2; e += nt) {
-    int i = e % m2, j = e / m2;
-    double v = 0.0;
-    for (int l = 0; l < m2; ++l) v += T[i + (long)l * m2] * N[l + (long)j * m2];
-    Lp[e] = v;
-  }
-  // Vt_a(i,j) = sum_l W_b(l,i) N[b,a](l,j);  Vt_b(i,j) = sum_l W_a(l,i) N[a,b](l,j)
-  for (int e = tid; e < kc * kc; e += nt) {
-    int i = e % kc, j = e / kc;
-    double va = 0.0, vb = 0.0;
-    for (int l = 0; l < kc; ++l) {
-      va += Wb[l + (long)i * kc] * N[(kc + l) + (long)j * m2];
-      vb += Wa[l + (long)i * kc] * N[l + (long)(kc + j) * m2];
-    }
-    Vt[a * s2 + e] = va;
-    Vt[b * s2 + e] = vb;
-  }
+  const int nint = (1 << m->levels) - 1;
+  hipLaunchKernelGGL(k_node_diag, dim3(ceil_div(nint * s2, 256)), dim3(256), 0, m->stream, f.Nn, f.Ncc, kc, nint);
+  HM_LAUNCH_CHECK();
+  // Nx_a = N12 S_b,  Nx_b = N21 S_a
+  HM_CHECK(gemm(m->stream, false, false, kc, kc, kc, 1.0, f.Nn + (long)kc * m2, m2, ms, f.Sn + 2 * s2, kc, 2 * s2,
+                0.0, f.Nx + s2, kc, 2 * s2, nint));
+  HM_CHECK(gemm(m->stream, false, false, kc, kc, kc, 1.0, f.Nn + kc, m2, ms, f.Sn + s2, kc, 2 * s2, 0.0,
+                f.Nx + 2 * s2, kc, 2 * s2, nint));
+  return HM_OK;
+}
+
+// PsiP^j for every internal node (X_ab = E_a^T S_b + S_a E_b)
+hm_status node_psi(FactorCtx& f, ParamBufs& pb, double* xtmp) {
+  Model* m = f.m;
+  const int kc = f.kc;
+  const long s2 = (long)kc * kc, ms = 4 * s2;
+  const int nint = (1 << m->levels) - 1;
+  HM_CHECK(gemm(m->stream, true, false, kc, kc, kc, 1.0, pb.E + s2, kc, 2 * s2, f.Sn + 2 * s2, kc, 2 * s2, 0.0,
+                xtmp, kc, s2, nint));
+  HM_CHECK(gemm(m->stream, false, false, kc, kc, kc, 1.0, f.Sn + s2, kc, 2 * s2, pb.E + 2 * s2, kc, 2 * s2, 1.0,
+                xtmp, kc, s2, nint));
+  hipLaunchKernelGGL(k_node_psi_assemble, dim3(ceil_div(nint * ms, 256)), dim3(256), 0, m->stream, pb.Psi, xtmp,
+                     pb.PsiP, kc, nint);
+  HM_LAUNCH_CHECK();
+  return HM_OK;
+}
+
+// Lam^j = N diag(dS_a, dS_b) N and Vt^j for every internal node
+hm_status node_lam(FactorCtx& f, ParamBufs& pb, double* tbuf, double* dsbuf) {
+  Model* m = f.m;
+  const int kc = f.kc, m2 = 2 * kc;
+  const long s2 = (long)kc * kc, ms = (long)m2 * m2;
+  const int nint = (1 << m->levels) - 1;
+  const long nodes = (2L << m->levels) - 1;
+  hipLaunchKernelGGL(k_node_dS, dim3(ceil_div((nodes - 1) * s2, 256)), dim3(256), 0, m->stream, pb.E, pb.W, dsbuf,
+                     kc, nodes);
+  HM_LAUNCH_CHECK();
+  // T = [N[:,0:k] dS_a, N[:,k:2k] dS_b]
+  HM_CHECK(gemm(m->stream, false, false, m2, kc, kc, 1.0, f.Nn, m2, ms, dsbuf + s2, kc, 2 * s2, 0.0, tbuf, m2, ms,
+                nint));
+  HM_CHECK(gemm(m->stream, false, false, m2, kc, kc, 1.0, f.Nn + (long)kc * m2, m2, ms, dsbuf + 2 * s2, kc, 2 * s2,
+                0.0, tbuf + (long)kc * m2, m2, ms, nint));
+  HM_CHECK(gemm(m->stream, false, false, m2, m2, m2, 1.0, tbuf, m2, ms, f.Nn, m2, ms, 0.0, pb.Lam, m2, ms, nint));
+  // Vt_a = W_b^T N21,  Vt_b = W_a^T N12
+  HM_CHECK(gemm(m->stream, true, false, kc, kc, kc, 1.0, pb.W + 2 * s2, kc, 2 * s2, f.Nn + kc, m2, ms, 0.0,
+                pb.Vt + s2, kc, 2 * s2, nint));
+  HM_CHECK(gemm(m->stream, true, false, kc, kc, kc, 1.0, pb.W + s2, kc, 2 * s2, f.Nn + (long)kc * m2, m2, ms, 0.0,
+                pb.Vt + 2 * s2, kc, 2 * s2, nint));
+  return HM_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -342,40 +329,6 @@ hm_status tangent_sweep(FactorCtx& f, ParamBufs& pb) {
   const long s2 = (long)kc * kc;
   ReduceJob rw{pb.dG, n, cs_block(kc), f.F, n, cs_block(kc), 1, levels, pb.W, s2, sel_all()};
   HM_CHECK(tree_reduce(m, rw));
-  return HM_OK;
-}
-
-hm_status node_prep(FactorCtx& f) {
-  Model* m = f.m;
-  for (int d = 0; d < m->levels; ++d) {
-    hipLaunchKernelGGL(k_node_prep, dim3(1 << d), dim3(256), 0, m->stream, f.Nn, f.Sn, f.Ncc, f.Nx, f.kc,
-                       (1 << d) - 1);
-    HM_LAUNCH_CHECK();
-  }
-  return HM_OK;
-}
-
-hm_status node_psi(FactorCtx& f, ParamBufs& pb, double* gtr) {
-  Model* m = f.m;
-  if (f.kc > AKMAX) {
-    set_error("panel width exceeds 64");
-    return HM_E_INVAL;
-  }
-  for (int d = 0; d < m->levels; ++d) {
-    hipLaunchKernelGGL(k_node_psi, dim3(1 << d), dim3(256), 0, m->stream, f.Nn, f.Sn, pb.E, pb.Psi, pb.PsiP, gtr,
-                       f.kc, (1 << d) - 1);
-    HM_LAUNCH_CHECK();
-  }
-  return HM_OK;
-}
-
-hm_status node_lam(FactorCtx& f, ParamBufs& pb, double* scratch) {
-  Model* m = f.m;
-  for (int d = 0; d < m->levels; ++d) {
-    hipLaunchKernelGGL(k_node_lam, dim3(1 << d), dim3(256), 0, m->stream, f.Nn, pb.E, pb.W, pb.Lam, pb.Vt, scratch,
-                       f.kc, (1 << d) - 1);
-    HM_LAUNCH_CHECK();
-  }
   return HM_OK;
 }
 
