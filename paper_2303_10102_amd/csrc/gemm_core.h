@@ -94,6 +94,8 @@ __device__ __forceinline__ void tile_store(const ST& st, const double (&acc)[TM]
 // Standard configuration used by the panel kernels: 64 x 64 tiles, 256 threads.
 constexpr int GBM = 64, GBN = 64, GBK = 16, GTM = 4, GTN = 4;
 using GCfg = TileCfg<GBM, GBN, GBK, GTM, GTN>;
+// LDS doubles a kernel must reserve for tile_gemm (two slabs)
+constexpr int GSMEM = 2 * GCfg::LDS_DOUBLES;
 
 // ---------------------------------------------------------------------------
 // Matrix-core path (CDNA3/CDNA4 v_mfma_f64_16x16x4_f64).  The 64 x 64 tile is
@@ -117,33 +119,64 @@ __device__ __forceinline__ void tile_zero(TileAcc& acc) {
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc.c[a][b] = hm_v4d{0.0, 0.0, 0.0, 0.0};
 }
+// Double-buffered: the next K-slab is fetched into registers while the current
+// one is consumed from LDS, so one barrier per slab and global latency hidden
+// behind the matrix-core work.  smem must hold 2 * GCfg::LDS_DOUBLES.
 template <class LA, class LB>
 __device__ __forceinline__ void tile_gemm(const LA& la, const LB& lb, int k0, int k1, TileAcc& acc, double* smem) {
   constexpr int BM = GBM, BN = GBN, BK = GBK, NT = GCfg::NT;
-  double* As = smem;
-  double* Bs = smem + GCfg::LDS_A;
+  constexpr int NA = BM * BK / NT, NB = BN * BK / NT;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
-  for (int kb = k0; kb < k1; kb += BK) {
+  double ra[NA], rb[NB];
+  auto fetch = [&](int kb) {
 #pragma unroll
-    for (int e0 = 0; e0 < BM * BK; e0 += NT) {
-      int e = e0 + tid;
+    for (int q = 0; q < NA; ++q) {
+      int e = q * NT + tid;
       int i, kk;
       if (LA::kfast) { kk = e % BK; i = e / BK; } else { i = e % BM; kk = e / BM; }
       int k = kb + kk;
-      As[kk * (BM + 1) + i] = (k < k1) ? la(i, k) : 0.0;
+      ra[q] = (k < k1) ? la(i, k) : 0.0;
     }
 #pragma unroll
-    for (int e0 = 0; e0 < BN * BK; e0 += NT) {
-      int e = e0 + tid;
+    for (int q = 0; q < NB; ++q) {
+      int e = q * NT + tid;
       int j, kk;
       if (LB::kfast) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
       int k = kb + kk;
-      Bs[kk * (BN + 1) + j] = (k < k1) ? lb(k, j) : 0.0;
+      rb[q] = (k < k1) ? lb(k, j) : 0.0;
     }
-    __syncthreads();
+  };
+  auto stash = [&](double* buf) {
+    double* As = buf;
+    double* Bs = buf + GCfg::LDS_A;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      int e = q * NT + tid;
+      int i, kk;
+      if (LA::kfast) { kk = e % BK; i = e / BK; } else { i = e % BM; kk = e / BM; }
+      As[kk * (BM + 1) + i] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      int e = q * NT + tid;
+      int j, kk;
+      if (LB::kfast) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
+      Bs[kk * (BN + 1) + j] = rb[q];
+    }
+  };
+  if (k0 >= k1) return;
+  fetch(k0);
+  stash(smem);
+  __syncthreads();
+  int cur = 0;
+  for (int kb = k0; kb < k1; kb += BK) {
+    const bool more = kb + BK < k1;
+    if (more) fetch(kb + BK);
+    const double* As = smem + cur * GCfg::LDS_DOUBLES;
+    const double* Bs = As + GCfg::LDS_A;
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + lk;
@@ -156,7 +189,9 @@ __device__ __forceinline__ void tile_gemm(const LA& la, const LB& lb, int k0, in
       acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.c[1][0], 0, 0, 0);
       acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc.c[1][1], 0, 0, 0);
     }
+    if (more) stash(smem + (cur ^ 1) * GCfg::LDS_DOUBLES);
     __syncthreads();
+    cur ^= 1;
   }
 }
 template <class ST>
@@ -177,6 +212,7 @@ struct TileAcc {
   double c[GTM][GTN];
 };
 __device__ __forceinline__ void tile_zero(TileAcc& acc) { tile_zero<GBM, GBN, GTM, GTN>(acc.c); }
+constexpr int GSMEM_FMA = GCfg::LDS_DOUBLES;
 template <class LA, class LB>
 __device__ __forceinline__ void tile_gemm(const LA& la, const LB& lb, int k0, int k1, TileAcc& acc, double* smem) {
   tile_gemm_acc<GBM, GBN, GBK, GTM, GTN>(la, lb, k0, k1, acc.c, smem);

@@ -85,24 +85,40 @@ struct DstLS {  // S (N x N, symmetric), rows m0..
     return p < N ? S[p + (long)k * N] : 0.0;
   }
 };
+// Column r of the transform operand is (col, y) = (r / Ny, r % Ny).  AM selects
+// how that split is computed: 0 general division, 1 a tile of GBN columns lies
+// inside one grid column (Ny % GBN == 0: col fixed per tile), 2 one-dimensional (Ny == 1).
+template <int AM>
+__device__ __forceinline__ void split_col(int r, int Ny, int colt, int yt, int j, int& col, int& y) {
+  if (AM == 2) { col = r; y = 0; }
+  else if (AM == 1) { col = colt; y = yt + j; }
+  else { col = r / Ny; y = r - col * Ny; }
+}
+template <int AM>
 struct DstLGather {  // B(x, r) = X[col*ldx + iperm[y*N + x]],  r = col*Ny + y
-  const double* X; int ldx; const int* iperm; int N, Ny, n0, R;
+  const double* X; int ldx; const int* iperm; int N, Ny, n0, R, colt, yt;
   static constexpr bool kfast = true;
   __device__ double operator()(int k, int j) const {
     int r = n0 + j;
     if (r >= R) return 0.0;
-    int col = r / Ny, y = r - col * Ny;
+    int col, y;
+    split_col<AM>(r, Ny, colt, yt, j, col, y);
     return X[(long)col * ldx + iperm[y * N + k]];
   }
 };
+template <int AM>
 struct DstLMode {  // B(p, r) = W[p + r*N] (optionally scaled by lam[p + (r % Ny)*N])
-  const double* W; const double* lam; int N, Ny, n0, R;
+  const double* W; const double* lam; int N, Ny, n0, R, colt, yt;
   static constexpr bool kfast = true;
   __device__ double operator()(int k, int j) const {
     int r = n0 + j;
     if (r >= R) return 0.0;
     double v = W[k + (long)r * N];
-    if (lam) v *= lam[k + (long)(r % Ny) * N];
+    if (lam) {
+      int col, y;
+      split_col<AM>(r, Ny, colt, yt, j, col, y);
+      v *= lam[k + (long)y * N];
+    }
     return v;
   }
 };
@@ -113,12 +129,14 @@ struct DstStMode {
     if (pp < N && r < R) p[pp + (long)r * N] = v;
   }
 };
+template <int AM>
 struct DstStScatter {
-  double* Y; int ldy; const int* iperm; int N, Ny, m0, n0, R;
+  double* Y; int ldy; const int* iperm; int N, Ny, m0, n0, R, colt, yt;
   __device__ void operator()(int i, int j, double v) const {
     int x = m0 + i, r = n0 + j;
     if (x >= N || r >= R) return;
-    int col = r / Ny, y = r - col * Ny;
+    int col, y;
+    split_col<AM>(r, Ny, colt, yt, j, col, y);
     Y[(long)col * ldy + iperm[y * N + x]] = v;
   }
 };
@@ -145,13 +163,15 @@ struct DyLB {
 };
 
 // Xh(p, r) = sum_x S(p,x) X[col*ldx + iperm[y*N + x]],  r = col*Ny + y
+template <int AM>
 __global__ void __launch_bounds__(256) k_dst_fwd(const double* S, const double* X, int ldx, const int* iperm,
                                                  double* Xh, int N, int Ny, int ncol) {
-  __shared__ double smem[GCfg::LDS_DOUBLES];
+  __shared__ double smem[GSMEM];
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
   const int R = ncol * Ny;
+  const int colt = (AM == 1) ? n0 / Ny : 0, yt = (AM == 1) ? n0 - colt * Ny : 0;
   DstLS la{S, N, m0};
-  DstLGather lb{X, ldx, iperm, N, Ny, n0, R};
+  DstLGather<AM> lb{X, ldx, iperm, N, Ny, n0, R, colt, yt};
   TileAcc acc;
   tile_zero(acc);
   tile_gemm(la, lb, 0, N, acc, smem);
@@ -162,7 +182,7 @@ __global__ void __launch_bounds__(256) k_dst_fwd(const double* S, const double* 
 // C_c = (lam o M_c) S for every column block c (2D only)
 __global__ void __launch_bounds__(256) k_dst_y(const double* S, const double* M, const double* lam, double* C,
                                                int N) {
-  __shared__ double smem[GCfg::LDS_DOUBLES];
+  __shared__ double smem[GSMEM];
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
   const long off = (long)blockIdx.z * N * N;
   DyLA la{M + off, lam, N, m0};
@@ -175,17 +195,19 @@ __global__ void __launch_bounds__(256) k_dst_y(const double* S, const double* M,
 }
 
 // Y[col*ldy + iperm[y*N + x]] = sum_p S(x,p) (lam o W)(p, r)
+template <int AM>
 __global__ void __launch_bounds__(256) k_dst_inv(const double* S, const double* W, const double* lam,
                                                  const int* iperm, double* Y, int ldy, int N, int Ny, int ncol) {
-  __shared__ double smem[GCfg::LDS_DOUBLES];
+  __shared__ double smem[GSMEM];
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
   const int R = ncol * Ny;
+  const int colt = (AM == 1) ? n0 / Ny : 0, yt = (AM == 1) ? n0 - colt * Ny : 0;
   DstLS la{S, N, m0};
-  DstLMode lb{W, lam, N, Ny, n0, R};
+  DstLMode<AM> lb{W, lam, N, Ny, n0, R, colt, yt};
   TileAcc acc;
   tile_zero(acc);
   tile_gemm(la, lb, 0, N, acc, smem);
-  DstStScatter st{Y, ldy, iperm, N, Ny, m0, n0, R};
+  DstStScatter<AM> st{Y, ldy, iperm, N, Ny, m0, n0, R, colt, yt};
   tile_store(st, acc);
 }
 
@@ -216,7 +238,13 @@ hm_status kapply(Model* m, const double theta[4], const double* X, int ldx, int 
     const int cc = std::min(m->cmax, c - c0);
     const double* Xc = X + (long)c0 * ldx;
     dim3 gx(ceil_div(N, GBM), ceil_div((long)cc * Ny, GBN));
-    hipLaunchKernelGGL(k_dst_fwd, gx, dim3(GCfg::NT), 0, m->stream, m->d_dst, Xc, ldx, m->d_iperm, Xh, N, Ny, cc);
+    const int am = (Ny == 1) ? 2 : (Ny % GBN == 0 ? 1 : 0);
+    if (am == 2)
+      hipLaunchKernelGGL((k_dst_fwd<2>), gx, dim3(GCfg::NT), 0, m->stream, m->d_dst, Xc, ldx, m->d_iperm, Xh, N, Ny, cc);
+    else if (am == 1)
+      hipLaunchKernelGGL((k_dst_fwd<1>), gx, dim3(GCfg::NT), 0, m->stream, m->d_dst, Xc, ldx, m->d_iperm, Xh, N, Ny, cc);
+    else
+      hipLaunchKernelGGL((k_dst_fwd<0>), gx, dim3(GCfg::NT), 0, m->stream, m->d_dst, Xc, ldx, m->d_iperm, Xh, N, Ny, cc);
     HM_LAUNCH_CHECK();
     dim3 gy(ceil_div(N, GBM), ceil_div(N, GBN), cc);
     if (m->dim == 2) {
@@ -230,11 +258,15 @@ hm_status kapply(Model* m, const double theta[4], const double* X, int ldx, int 
       if (m->dim == 2) {
         hipLaunchKernelGGL(k_dst_y, gy, dim3(GCfg::NT), 0, m->stream, m->d_dst, X2, lam, X3, N);
         HM_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_dst_inv, gx, dim3(GCfg::NT), 0, m->stream, m->d_dst, X3, (const double*)nullptr,
-                           m->d_iperm, Yc, ldo, N, Ny, cc);
+        if (am == 1)
+          hipLaunchKernelGGL((k_dst_inv<1>), gx, dim3(GCfg::NT), 0, m->stream, m->d_dst, X3, (const double*)nullptr,
+                             m->d_iperm, Yc, ldo, N, Ny, cc);
+        else
+          hipLaunchKernelGGL((k_dst_inv<0>), gx, dim3(GCfg::NT), 0, m->stream, m->d_dst, X3, (const double*)nullptr,
+                             m->d_iperm, Yc, ldo, N, Ny, cc);
       } else {
-        hipLaunchKernelGGL(k_dst_inv, gx, dim3(GCfg::NT), 0, m->stream, m->d_dst, Xh, lam, m->d_iperm, Yc, ldo, N,
-                           Ny, cc);
+        hipLaunchKernelGGL((k_dst_inv<2>), gx, dim3(GCfg::NT), 0, m->stream, m->d_dst, Xh, lam, m->d_iperm, Yc, ldo,
+                           N, Ny, cc);
       }
       HM_LAUNCH_CHECK();
     }

@@ -132,11 +132,18 @@ __global__ void __launch_bounds__(256) k_leaf_trinv(const double* Lf, double* U,
 #pragma unroll
       for (int r = 0; r < TB; ++r) acc[r] = (r < nb && r0 + r == j) ? 1.0 : 0.0;
       if (j < r0) {
-        for (int c = j; c < r0; ++c) {
-          const double x = X[j + (long)c * nl];
+        // columns c in [j, r0): batches of 8 independent loads, then the updates
+        for (int c0 = j; c0 < r0; c0 += 8) {
+          double xr[8];
 #pragma unroll
-          for (int r = 0; r < TB; ++r)
-            if (r < nb) acc[r] -= Lp[r * nl + c] * x;
+          for (int t = 0; t < 8; ++t) xr[t] = (c0 + t < r0) ? X[j + (long)(c0 + t) * nl] : 0.0;
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int c = min(c0 + t, r0 - 1);
+#pragma unroll
+            for (int r = 0; r < TB; ++r)
+              if (r < nb) acc[r] -= Lp[r * nl + c] * xr[t];
+          }
         }
       }
 #pragma unroll

@@ -58,7 +58,7 @@ template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) k_gemm(int M, int Nc, int K, double alpha, const double* A, int lda,
                                               long sA, const double* B, int ldb, long sB, double beta,
                                               double* C, int ldc, long sC) {
-  __shared__ double smem[GCfg::LDS_DOUBLES];
+  __shared__ double smem[GSMEM];
   int b = blockIdx.z;
   int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
   LdA<TA> la{A + b * sA, lda, m0, M};
@@ -120,7 +120,7 @@ struct RedArgs {
 };
 
 __global__ void __launch_bounds__(256) k_reduce_partial(RedArgs a) {
-  __shared__ double smem[GCfg::LDS_DOUBLES];
+  __shared__ double smem[GSMEM];
   const int ndep = a.d1 - a.d0 + 1;
   const int L = blockIdx.z / ndep;
   const int d = a.d0 + blockIdx.z % ndep;
@@ -145,10 +145,18 @@ __global__ void __launch_bounds__(256) k_reduce_partial(RedArgs a) {
   tile_store(StC{dst, wa, m0, n0, wa, wx, 1.0, 0.0}, acc);
 }
 
-__global__ void k_reduce_tree(RedArgs a, int d) {
-  // grid.x: element chunks, grid.y: node index at depth d
+// Sum the per-leaf partials into every node of depths d0..min(d1, levels-1):
+// grid.y enumerates those nodes (depth-major), grid.x element chunks.
+__global__ void k_reduce_tree(RedArgs a, int dlast) {
   const int ndep = a.d1 - a.d0 + 1;
-  const int idx = blockIdx.y;
+  // node enumeration: depth d contributes 2^d nodes, starting at depth d0
+  int t = blockIdx.y;
+  int d = a.d0;
+  while (d < dlast && t >= (1 << d)) {
+    t -= (1 << d);
+    ++d;
+  }
+  const int idx = t;
   const int wa = a.ac.w0, wx = a.xc.w(d);
   const int ne = wa * wx;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -198,12 +206,18 @@ hm_status tree_reduce(Model* m, const ReduceJob& j) {
   dim3 grid(ceil_div(wa, GBM), ceil_div(wxmax, GBN), m->nleaves * ndep);
   hipLaunchKernelGGL(k_reduce_partial, grid, dim3(GCfg::NT), 0, m->stream, a);
   HM_LAUNCH_CHECK();
-  for (int d = j.d0; d <= std::min(j.d1, m->levels - 1); ++d) {
-    int ne = wa * j.xc.w(d);
-    if (ne <= 0) continue;
-    dim3 g2(ceil_div(ne, 256), 1 << d);
-    hipLaunchKernelGGL(k_reduce_tree, g2, dim3(256), 0, m->stream, a, d);
-    HM_LAUNCH_CHECK();
+  const int dlast = std::min(j.d1, m->levels - 1);
+  if (dlast >= j.d0) {
+    int nodes = 0, nemax = 0;
+    for (int d = j.d0; d <= dlast; ++d) {
+      nodes += 1 << d;
+      nemax = std::max(nemax, wa * j.xc.w(d));
+    }
+    if (nemax > 0) {
+      dim3 g2(ceil_div(nemax, 256), nodes);
+      hipLaunchKernelGGL(k_reduce_tree, g2, dim3(256), 0, m->stream, a, dlast);
+      HM_LAUNCH_CHECK();
+    }
   }
   return HM_OK;
 }
@@ -248,7 +262,7 @@ struct ExpArgs {
 };
 
 __global__ void __launch_bounds__(256) k_expand(ExpArgs a) {
-  __shared__ double smem[GCfg::LDS_DOUBLES];
+  __shared__ double smem[GSMEM];
   const int L = blockIdx.z;
   if (!leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) return;
   const int m0 = blockIdx.x * GBM;
@@ -299,7 +313,7 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
 __global__ void __launch_bounds__(256) k_leaf_gemm(const double* Dm, const double* X, int ldx, double* Y,
                                                    int ldy, int w, int nl, double alpha, double beta,
                                                    int leaf_lo) {
-  __shared__ double smem[GCfg::LDS_DOUBLES];
+  __shared__ double smem[GSMEM];
   const int L = leaf_lo + blockIdx.z;
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
   const long r0 = (long)L * nl;

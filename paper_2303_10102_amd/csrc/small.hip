@@ -71,7 +71,8 @@ __global__ void __launch_bounds__(256) k_chol_inv(const double* G, long gstride,
     __syncthreads();
   }
   if (bad && tid == 0) atomicOr(flags, (int)DF_QR_FAIL);
-  // R = L^T (upper), Rinv = (L^{-1})^T; column c of L^{-1} by forward substitution
+  // R = L^T (upper), Rinv = (L^{-1})^T; column c of L^{-1} by forward substitution in LDS
+  __shared__ double X[KMAX * KMAX];   // X[c + i*k] = (L^{-1})(i, c)
   double* Ro = R + node * rstride;
   double* Ri = Rinv + node * rstride;
   for (int e = tid; e < k * k; e += nt) {
@@ -79,14 +80,15 @@ __global__ void __launch_bounds__(256) k_chol_inv(const double* G, long gstride,
     Ro[e] = (i <= j) ? A[j + i * k] : 0.0;  // R(i,j) = L(j,i)
   }
   for (int c = tid; c < k; c += nt) {
-    // x = L^{-1} e_c, rows c..k-1;  Rinv(c, i) = x_i  (Rinv = (L^{-1})^T, upper)
-    for (int i = 0; i < c; ++i) Ri[c + i * k] = 0.0;
+    for (int i = 0; i < c; ++i) X[c + i * k] = 0.0;
     for (int i = c; i < k; ++i) {
       double s = (i == c) ? 1.0 : 0.0;
-      for (int l = c; l < i; ++l) s -= A[i + l * k] * Ri[c + l * k];
-      Ri[c + i * k] = s / A[i + i * k];
+      for (int l = c; l < i; ++l) s -= A[i + l * k] * X[c + l * k];
+      X[c + i * k] = s / A[i + i * k];
     }
   }
+  __syncthreads();
+  for (int e = tid; e < k * k; e += nt) Ri[e] = X[e];   // Rinv(c, i) = (L^{-1})(i, c)
 }
 
 // M = triu(W) + strict_tril(W)^T, W k x k (ld k) per node; zero outside k_P.
