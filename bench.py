@@ -22,6 +22,41 @@ if ROOT not in sys.path:
 
 METRIC = "H-MLE iters/s (build+factor+logdet+grad+FIM) at n=65536; % HBM/MFMA roofline"
 
+# MI355X published peaks
+PEAK_FP64_TFLOPS = 78.6     # FP64 (matrix and vector)
+PEAK_HBM_GBS = 8000.0
+
+DOMINANT = "expand"         # kernel family timed live: hm::k_expand (panel expand over the tree)
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_expand_2d_n65536_pmc.md")
+KERNEL_SOURCES = ["paper_2303_10102_amd/csrc/panels.hip", "paper_2303_10102_amd/csrc/gemm_core.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
+    summary, or None when absent or taken on different kernel sources."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    vals = {}
+    for line in open(PMC_SUMMARY):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
 
 def cpu_baseline(sample_key="2d_n4096", full_n=65536):
     """Time the CPU oracle on one iteration of a smaller grid with the same model."""
@@ -63,6 +98,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="2d_n65536")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 512 MiB streaming kernel (reference dispatch for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
@@ -91,12 +128,22 @@ def main():
     for _ in range(args.warmup):
         ll, g, fim = H.iteration(theta, y)
     torch.cuda.synchronize()
+    if args.copy_calibration:
+        # a plain streaming kernel of known traffic: reads 512 MiB, writes 512 MiB
+        a = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    m.profile_enable(DOMINANT)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ll, g, fim = H.iteration(theta, y)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    prof = m.profile_read()
+    m.profile_enable(None)
     ms = 1e3 * dt / args.steps
     rec = {
         "metric": METRIC,
@@ -114,10 +161,24 @@ def main():
         "config": {"workload": f"{w.name}: 2D SPDE {w.N}x{w.N} grid, n={w.n}, leaf {w.leaf}, {w.levels} levels, "
                                f"rank {w.rank} (+{w.oversample} once), theta=(kappa,alpha,tau2,sigma2)",
                    "n": w.n, "rank": w.rank, "leaf": w.leaf, "params": list(w.free)},
+        "roofline": None,
         "loglik": ll,
         "grad_nll": [float(v) for v in g],
         "fim_diag": [float(fim[i, i]) for i in range(len(g))],
     }
+    if prof["launches"] > 0 and prof["ms"] > 0:
+        per_launch_flops = prof["flops"] / prof["launches"]
+        avg_s = prof["ms"] / 1e3 / prof["launches"]
+        achieved = per_launch_flops / avg_s / 1e12
+        traffic = measured_traffic()
+        rec["roofline"] = {
+            "bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+            "kernel": "hm::k_expand", "launches_per_step": prof["launches"] / args.steps,
+            "avg_launch_us": 1e6 * avg_s, "alg_flops_per_launch": per_launch_flops,
+            "alg_bytes_per_launch": prof["bytes"] / prof["launches"],
+            "share_of_step": prof["ms"] / args.steps / ms,
+        }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline()

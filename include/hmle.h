@@ -73,7 +73,7 @@ hm_status hm_model_perm(const hm_model* m, int* perm_host);
 /* K-apply of the physics model (the only access to K the method uses, Sec. 3.2):
  * Y = op(theta) X with op = K (which=0), dK/dkappa (1), dK/dalpha (2).
  * X, Y: device, n x c column-major in TREE order with leading dimensions ldx, ldy >= n.
- * Exact direct stencil solves (sine transform along x, tridiagonal solves along y). */
+ * Exact direct solves of the Dirichlet stencils (orthonormal sine transforms along x and y). */
 hm_status hm_kapply(hm_model* m, const double* theta_full, const double* X, int ldx, int c, double* Y,
                     int ldy, int which);
 
@@ -134,6 +134,18 @@ hm_status hm_iteration(hm_H* H, const double* theta_full, const double* y, doubl
  * what=11+j: leaf blocks of K~_j (real parameters), same shape.
  * dst: device buffer of sufficient size. */
 hm_status hm_export(hm_H* H, int what, double* dst);
+
+/* ------------------------------------------------------------- profiling ---
+ * Roofline instrumentation.  hm_profile_enable(m, family) brackets every later
+ * launch of one kernel family with HIP events on the model's stream and records
+ * the launch's algorithmic flop and byte counts (the useful work of the launch,
+ * not tile padding).  family: 0 panel expand (Y += A T over the tree), 1 panel
+ * reduce (A^T X per node), 2 sine-transform passes of the K-apply, 4 leaf-block
+ * GEMM; -1 switches profiling off.  Enabling clears earlier records.
+ * hm_profile_read synchronises the stream and returns the totals since enabling:
+ * summed event time (ms), number of launches, flops and bytes (any pointer may be NULL). */
+hm_status hm_profile_enable(hm_model* m, int family);
+hm_status hm_profile_read(hm_model* m, double* ms, long long* launches, double* flops, double* bytes);
 
 #ifdef __cplusplus
 }

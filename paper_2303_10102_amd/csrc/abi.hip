@@ -248,6 +248,7 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
 void hm_model_destroy(hm_model* mm) {
   if (!mm) return;
   Model* m = &mm->m;
+  for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
   void* ps[] = {m->d_perm, m->d_iperm, m->d_dst, m->d_mu, m->d_lam, m->d_ws, m->d_flags, m->d_ident, m->d_red};
   for (void* p : ps)
     if (p) (void)hipFree(p);
@@ -723,6 +724,40 @@ hm_status hm_export(hm_H* hh, int what, double* dst) {
   }
   HM_HIP(hipMemcpyAsync(dst, src, cnt * sizeof(double), hipMemcpyDeviceToDevice, m->stream));
   HM_HIP(hipStreamSynchronize(m->stream));
+  return HM_OK;
+}
+
+hm_status hm_profile_enable(hm_model* mm, int family) {
+  if (!mm || family < -1 || family >= PF_COUNT) {
+    set_error("bad profiling family");
+    return HM_E_INVAL;
+  }
+  Model* m = &mm->m;
+  HM_HIP(hipStreamSynchronize(m->stream));
+  m->prof.clear();
+  m->ev_used = 0;
+  m->prof_family = family;
+  return HM_OK;
+}
+
+hm_status hm_profile_read(hm_model* mm, double* ms, long long* launches, double* flops, double* bytes) {
+  if (!mm) {
+    set_error("model is NULL");
+    return HM_E_INVAL;
+  }
+  Model* m = &mm->m;
+  HM_HIP(hipStreamSynchronize(m->stream));
+  double t = 0.0, fl = 0.0, by = 0.0;
+  for (const ProfRec& r : m->prof) {
+    float e = 0.0f;
+    if (r.a && r.b && hipEventElapsedTime(&e, r.a, r.b) == hipSuccess) t += e;
+    fl += r.flops;
+    by += r.bytes;
+  }
+  if (ms) *ms = t;
+  if (launches) *launches = (long long)m->prof.size();
+  if (flops) *flops = fl;
+  if (bytes) *bytes = by;
   return HM_OK;
 }
 

@@ -50,6 +50,16 @@ enum DevFlag : int { DF_NOT_SPD_LEAF = 1, DF_NOT_SPD_NODE = 2, DF_QR_FAIL = 4, D
 // ---------------------------------------------------------------------------
 // model, sketch, H
 // ---------------------------------------------------------------------------
+// Kernel-family instrumentation (roofline measurement): launches of the enabled
+// family are bracketed by HIP events on the model stream; each record carries the
+// launch's algorithmic flop and byte counts.
+enum ProfFamily : int { PF_NONE = -1, PF_EXPAND = 0, PF_REDUCE = 1, PF_DST = 2, PF_GEMM = 3, PF_LEAFGEMM = 4,
+                        PF_COUNT = 5 };
+struct ProfRec {
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+
 struct Model {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -68,7 +78,15 @@ struct Model {
   double* d_ident = nullptr;    // stacked identities n x nl (tree order), for the leaf pass
   double* d_red = nullptr;      // per-leaf partials of tree_reduce
   size_t red_doubles = 0;
+  int prof_family = PF_NONE;
+  std::vector<ProfRec> prof;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
 };
+// profiling helpers (no-ops unless the family is enabled)
+bool prof_on(Model* m, int family);
+void prof_begin(Model* m, int family);
+void prof_end(Model* m, int family, double flops, double bytes);
 // grow the tree_reduce partial buffer (setup calls only; never inside an iteration)
 hm_status ensure_reduce_ws(Model* m, size_t doubles);
 

@@ -234,6 +234,14 @@ hm_status kapply(Model* m, const double theta[4], const double* X, int ldx, int 
   double* X2 = m->d_ws + (long)n * m->cmax;    // x- and y-transformed (2D)
   double* X3 = m->d_ws + 2L * n * m->cmax;     // scaled and y-inverse-transformed (2D)
   double* outs[3] = {outK, outKap, outAlp};
+  const bool pf = prof_on(m, PF_DST);
+  int nout = 0;
+  for (int q = 0; q < 3; ++q) nout += outs[q] ? 1 : 0;
+  // algorithmic work of the transforms: every N x N transform of one column costs 2 N^2 Ny
+  // flops per direction; 2D: 2 (forward) + 2 per output, 1D: 1 + 1 per output
+  const double per_col = (m->dim == 2) ? (2.0 + 2.0 * nout) * 2.0 * N * (double)N * N
+                                       : (1.0 + nout) * 2.0 * N * (double)N;
+  if (pf) prof_begin(m, PF_DST);
   for (int c0 = 0; c0 < c; c0 += m->cmax) {
     const int cc = std::min(m->cmax, c - c0);
     const double* Xc = X + (long)c0 * ldx;
@@ -270,6 +278,11 @@ hm_status kapply(Model* m, const double theta[4], const double* X, int ldx, int 
       }
       HM_LAUNCH_CHECK();
     }
+  }
+  if (pf) {
+    // bytes: each transform pass reads and writes the n x c block once, plus the N x N table
+    const double passes = (m->dim == 2) ? (2.0 + 2.0 * nout) : (1.0 + nout);
+    prof_end(m, PF_DST, per_col * c, passes * (16.0 * n * (double)c + 8.0 * N * (double)N));
   }
   return HM_OK;
 }

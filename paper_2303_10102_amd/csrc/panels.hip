@@ -14,6 +14,34 @@
 
 namespace hm {
 
+bool prof_on(Model* m, int family) { return m->prof_family == family; }
+static hipEvent_t prof_event(Model* m) {
+  if (m->ev_used == m->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    m->ev_pool.push_back(e);
+  }
+  return m->ev_pool[m->ev_used++];
+}
+void prof_begin(Model* m, int family) {
+  if (!prof_on(m, family)) return;
+  ProfRec r{prof_event(m), prof_event(m), 0.0, 0.0};
+  if (r.a) (void)hipEventRecord(r.a, m->stream);
+  m->prof.push_back(r);
+}
+void prof_end(Model* m, int family, double flops, double bytes) {
+  if (!prof_on(m, family) || m->prof.empty()) return;
+  ProfRec& r = m->prof.back();
+  if (r.b) (void)hipEventRecord(r.b, m->stream);
+  r.flops = flops;
+  r.bytes = bytes;
+}
+
+static int count_selected(int nleaves, int levels, LeafSel sel) {
+  if (sel.mode == 0) return nleaves;
+  return nleaves / 2;  // one side of every node at the selection depth
+}
+
 __device__ __forceinline__ bool leaf_selected(int L, int levels, int mode, int depth) {
   if (mode == 0) return true;
   int anc = L >> (levels - depth);
@@ -204,8 +232,19 @@ hm_status tree_reduce(Model* m, const ReduceJob& j) {
     return HM_E_INVAL;
   }
   dim3 grid(ceil_div(wa, GBM), ceil_div(wxmax, GBN), m->nleaves * ndep);
+  const bool pf = prof_on(m, PF_REDUCE);
+  if (pf) prof_begin(m, PF_REDUCE);
   hipLaunchKernelGGL(k_reduce_partial, grid, dim3(GCfg::NT), 0, m->stream, a);
   HM_LAUNCH_CHECK();
+  if (pf) {
+    const double rows = (double)count_selected(m->nleaves, m->levels, j.sel) * m->nl;
+    double fl = 0.0, by = 0.0;
+    for (int d = j.d0; d <= j.d1; ++d) {
+      fl += 2.0 * rows * wa * j.xc.w(d);
+      by += 8.0 * (rows * wa + rows * j.xc.w(d) + (rows / m->nl) * wa * j.xc.w(d));
+    }
+    prof_end(m, PF_REDUCE, fl, by);
+  }
   const int dlast = std::min(j.d1, m->levels - 1);
   if (dlast >= j.d0) {
     int nodes = 0, nemax = 0;
@@ -302,8 +341,24 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
   ExpArgs a{j.A, j.lda, j.ac, j.Y, j.ldy, j.yc, j.T, j.t_stride, j.ldt, j.tmode, j.half_off,
             j.d0, j.d1, m->levels, m->nl, j.alpha, j.beta, ylo, yhi, j.sel.mode, j.sel.depth};
   dim3 grid(ceil_div(m->nl, GBM), ceil_div(yhi - ylo, GBN), m->nleaves);
+  const bool pf = prof_on(m, PF_EXPAND);
+  if (pf) prof_begin(m, PF_EXPAND);
   hipLaunchKernelGGL(k_expand, grid, dim3(GCfg::NT), 0, m->stream, a);
   HM_LAUNCH_CHECK();
+  if (pf) {
+    const int wk = j.ac.w0;
+    const double rows = (double)count_selected(m->nleaves, m->levels, j.sel) * m->nl;
+    const double nsel = rows / m->nl;
+    double fl = 0.0, by = 0.0;
+    for (int d = j.d0; d <= j.d1; ++d) {
+      const int wy = j.yc.w(d);
+      if (wy <= 0) continue;
+      fl += 2.0 * rows * wk * wy;
+      by += 8.0 * (rows * wk + std::min(nsel, (double)(1 << d)) * wk * wy);
+    }
+    by += 8.0 * rows * (yhi - ylo) * (j.beta == 0.0 ? 1.0 : 2.0);
+    prof_end(m, PF_EXPAND, fl, by);
+  }
   return HM_OK;
 }
 
@@ -329,9 +384,16 @@ hm_status leaf_gemm(Model* m, const double* Dm, const double* X, int ldx, double
                     double alpha, double beta, int leaf_lo, int leaf_hi) {
   if (w <= 0 || leaf_hi <= leaf_lo) return HM_OK;
   dim3 grid(ceil_div(m->nl, GBM), ceil_div(w, GBN), leaf_hi - leaf_lo);
+  const bool pf = prof_on(m, PF_LEAFGEMM);
+  if (pf) prof_begin(m, PF_LEAFGEMM);
   hipLaunchKernelGGL(k_leaf_gemm, grid, dim3(GCfg::NT), 0, m->stream, Dm, X, ldx, Y, ldy, w, m->nl, alpha,
                      beta, leaf_lo);
   HM_LAUNCH_CHECK();
+  if (pf) {
+    const double L = leaf_hi - leaf_lo, nl = m->nl;
+    prof_end(m, PF_LEAFGEMM, 2.0 * L * nl * nl * w,
+             8.0 * (L * nl * nl + L * nl * w * (beta == 0.0 ? 2.0 : 3.0)));
+  }
   return HM_OK;
 }
 

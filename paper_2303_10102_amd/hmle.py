@@ -52,7 +52,10 @@ _SIGS = {
     "hm_fisher": ([_P, _D], _I),
     "hm_iteration": ([_P, _D, _P, _D, _D, _D], _I),
     "hm_export": ([_P, _I, _P], _I),
+    "hm_profile_enable": ([_P, _I], _I),
+    "hm_profile_read": ([_P, _D, C.POINTER(C.c_longlong), _D, _D], _I),
 }
+PROFILE_FAMILIES = {"expand": 0, "reduce": 1, "dst": 2, "leaf_gemm": 4}
 
 
 def lib():
@@ -124,6 +127,17 @@ class Model:
         Y = torch.empty_like(X)
         _check("hm_kapply", lib().hm_kapply(self._h, _theta(theta_full), _ptr(X), n, c, _ptr(Y), n, which))
         return Y
+
+    def profile_enable(self, family):
+        """Time every launch of a kernel family ('expand', 'reduce', 'dst', 'leaf_gemm'; None = off)."""
+        fam = -1 if family is None else PROFILE_FAMILIES[family]
+        _check("hm_profile_enable", lib().hm_profile_enable(self._h, fam))
+
+    def profile_read(self):
+        ms, fl, by = C.c_double(), C.c_double(), C.c_double()
+        n = C.c_longlong()
+        _check("hm_profile_read", lib().hm_profile_read(self._h, C.byref(ms), C.byref(n), C.byref(fl), C.byref(by)))
+        return dict(ms=ms.value, launches=n.value, flops=fl.value, bytes=by.value)
 
     def close(self):
         if getattr(self, "_h", None):
