@@ -89,3 +89,44 @@ def rel_err(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def hmatvec(F, leaves, levels, kc, x, dF=None, dleaves=None):
+    """K~ x (or K~_j x when dF, dleaves are given) from an exported representation.
+
+    Plain NumPy on the host, in tree order; x has shape (n,) or (n, c).  Used where
+    a dense matrix would not fit: the off-diagonal block of sibling pair (a, b) at
+    depth l is F_a F_b^T (or dF_a F_b^T + F_a dF_b^T), the diagonal blocks are the leaves.
+    """
+    F = np.asarray(F).T
+    x = np.asarray(x, dtype=np.float64)
+    vec = x.ndim == 1
+    X = x.reshape(x.shape[0], -1)
+    n = X.shape[0]
+    Y = np.zeros_like(X)
+    dFm = None if dF is None else np.asarray(dF).T
+    for l in range(1, levels + 1):
+        sz = n >> l
+        P = 1 << (l - 1)
+        blk = F[:, (l - 1) * kc:l * kc].reshape(P, 2, sz, kc)
+        Xb = X.reshape(P, 2, sz, -1)
+        Yb = Y.reshape(P, 2, sz, -1)
+        # F_b^T x_b and F_a^T x_a for every pair
+        tb = np.einsum("psk,psc->pkc", blk[:, 1], Xb[:, 1])
+        ta = np.einsum("psk,psc->pkc", blk[:, 0], Xb[:, 0])
+        if dFm is None:
+            Yb[:, 0] += np.einsum("psk,pkc->psc", blk[:, 0], tb)
+            Yb[:, 1] += np.einsum("psk,pkc->psc", blk[:, 1], ta)
+        else:
+            dblk = dFm[:, (l - 1) * kc:l * kc].reshape(P, 2, sz, kc)
+            dtb = np.einsum("psk,psc->pkc", dblk[:, 1], Xb[:, 1])
+            dta = np.einsum("psk,psc->pkc", dblk[:, 0], Xb[:, 0])
+            # rows of a: (dF_a F_b^T + F_a dF_b^T) x_b ; rows of b: the transpose applied to x_a
+            Yb[:, 0] += np.einsum("psk,pkc->psc", dblk[:, 0], tb) + np.einsum("psk,pkc->psc", blk[:, 0], dtb)
+            Yb[:, 1] += np.einsum("psk,pkc->psc", blk[:, 1], dta) + np.einsum("psk,pkc->psc", dblk[:, 1], ta)
+    lv = np.asarray(leaves if dleaves is None else dleaves)
+    nb, nl = lv.shape[0], lv.shape[1]
+    Xl = X.reshape(nb, nl, -1)
+    # lv[L] is the column-major block, i.e. its transpose as a row-major array
+    Y += np.einsum("Lji,Ljc->Lic", lv, Xl).reshape(n, -1)
+    return Y[:, 0] if vec else Y

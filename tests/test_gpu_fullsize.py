@@ -1,0 +1,193 @@
+"""GPU checks at full size: the 256 x 256 workload (n = 65536, leaf 256, 8 levels,
+rank 48, theta = (kappa, alpha, tau2, sigma2)) in the launch configuration the
+benchmark times, and the 128 x 128 workload (n = 16384, 6 levels, rank 32,
+theta = (kappa, alpha, tau2)).
+
+A dense oracle does not fit at this size, so the checks are
+  * sampled outputs the oracle computes one by one: K X, dK/dkappa X, dK/dalpha X
+    for unit and random columns by sparse solves (oracle.model.apply_covariance);
+  * properties that hold at any size, with quantities taken from the exported
+    representation by a plain host H-matvec (tests._cases.hmatvec):
+      - solve residual  ||y - K~ x|| / ||y||  (refined FP64 solve);
+      - L~ = -n/2 log 2pi - 1/2 log|K~| - 1/2 y^T z with z from the solve;
+      - scale homogeneity of the exact HODLR algebra (K~_tau2 = I,
+        sigma2 K~_sigma2 = K~ - tau2 I):
+            sigma2 g_sigma2 + tau2 g_tau2 = n/2 - 1/2 y^T z,
+            sum_{s,t in scale} theta_s theta_t I~_st = n/2,
+            sum_{s in scale} theta_s I~_js = 1/2 tr(K~^{-1} K~_j) = g_j + 1/2 z^T K~_j z,
+        the last one pinning the kappa / alpha traces against host quadratic forms;
+      - Fisher matrix symmetric positive semidefinite;
+      - central finite differences of L~ (relative step 1e-6, same sketch) against
+        the forward-mode gradient within the quotient's rounding bound, and a
+        Richardson-extrapolated quotient at relative step 1e-4 to 1e-6 relative;
+  * the approximation itself against the exact closed form (oracle.spectral):
+    reported, with a sanity bound only (the rank-48 error is not pinned).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from tests._cases import hmatvec, rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", params=["2d_n16384", "2d_n65536"])
+def full(request):
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2303_10102_amd import hmle
+    from synth import WORKLOADS, sample_y, sketch_draws
+
+    w = WORKLOADS[request.param]
+    print(f"\n[full-size {w.name}: n={w.n}]", flush=True)
+    m = hmle.Model(w.dim, w.N, w.leaf)
+    om = torch.from_numpy(sketch_draws(w)).cuda()
+    s = hmle.Sketch(m, om, w.rank, w.oversample, w.theta_full)
+    del om
+    H = hmle.HMatrix(s, w.free)
+    y = sample_y(w)
+    yd = torch.from_numpy(y).cuda()
+    ll, g, fim = H.iteration(w.theta_full, yd)
+    ld = H.logdet()
+    x = H.solve(yd).cpu().numpy()
+    yield dict(w=w, m=m, s=s, H=H, y=y, yd=yd, ll=ll, g=g, fim=fim, logdet=ld, x=x)
+    H.close()
+    s.close()
+    m.close()
+
+
+@pytest.mark.parametrize("which", [0, 1, 2])
+def test_kapply_sampled_columns(full, which):
+    from oracle.model import apply_covariance
+    w, m = full["w"], full["m"]
+    perm = m.perm()                       # tree position -> grid index
+    rng = np.random.default_rng(21 + which)
+    cols = [0, 1, w.n // 2 - 1, w.n // 2, w.n - 1] + list(rng.integers(0, w.n, 4))
+    Xg = np.zeros((w.n, len(cols) + 3))   # grid order
+    for c, t in enumerate(cols):
+        Xg[perm[t], c] = 1.0
+    Xg[:, len(cols):] = rng.standard_normal((w.n, 3))
+    Xt = Xg[perm]                         # tree order
+    Y = m.kapply(w.theta_full, torch.from_numpy(np.ascontiguousarray(Xt.T)).cuda(), which).cpu().numpy().T
+    ref = apply_covariance(w.dim, w.N, w.theta_full, Xg, ("K", "kappa", "alpha")[which])[perm]
+    for c in range(Xg.shape[1]):
+        e = rel_err(Y[:, c], ref[:, c])
+        assert e < 1e-11, (c, e)
+
+
+def _export(full):
+    H, s, m = full["H"], full["s"], full["m"]
+    _, kc = s.ranks()
+    F = H.export(0).cpu().numpy()
+    D = H.export(10).cpu().numpy()
+    return F, D, m.levels, kc
+
+
+def test_solve_residual_and_loglik(full):
+    w, y, x = full["w"], full["y"], full["x"]
+    perm = full["m"].perm()
+    F, D, levels, kc = _export(full)
+    r = y[perm] - hmatvec(F, D, levels, kc, x[perm])
+    res = np.linalg.norm(r) / np.linalg.norm(y)
+    print(f"solve residual {res:.3e}")
+    assert res < 1e-12
+    yz = float(y @ x)
+    ll = -0.5 * w.n * math.log(2 * math.pi) - 0.5 * full["logdet"] - 0.5 * yz
+    assert abs(ll - full["ll"]) <= 1e-12 * abs(ll)
+
+
+def test_scale_homogeneity(full):
+    w, g, fim, y, x = full["w"], full["g"], full["fim"], full["y"], full["x"]
+    free = list(w.free)
+    if "sigma2" not in free or "tau2" not in free:
+        pytest.skip("needs both scale parameters free")
+    it, isg = free.index("tau2"), free.index("sigma2")
+    tau2, sigma2 = w.tau2, w.sigma2
+    yz = float(y @ x)
+    lhs = sigma2 * g[isg] + tau2 * g[it]
+    assert abs(lhs - (0.5 * w.n - 0.5 * yz)) <= 1e-10 * 0.5 * w.n
+    q = (tau2 * tau2 * fim[it, it] + 2 * tau2 * sigma2 * fim[it, isg] + sigma2 * sigma2 * fim[isg, isg])
+    assert abs(q - 0.5 * w.n) <= 1e-10 * 0.5 * w.n
+
+    perm = full["m"].perm()
+    z = x[perm]
+    F, D, levels, kc = _export(full)
+    H = full["H"]
+    # half traces from the Fisher rows, against g_j + 1/2 z^T K~_j z
+    quad = {"tau2": float(z @ z), "sigma2": (float(y @ x) - tau2 * float(z @ z)) / sigma2}
+    for j, name in enumerate([f for f in free if f in ("kappa", "alpha")]):
+        dF = H.export(1 + j).cpu().numpy()
+        dD = H.export(11 + j).cpu().numpy()
+        quad[name] = float(z @ hmatvec(F, D, levels, kc, z, dF=dF, dleaves=dD))
+    for j, name in enumerate(free):
+        half_tr = tau2 * fim[j, it] + sigma2 * fim[j, isg]
+        ref = g[j] + 0.5 * quad[name]
+        scale = max(abs(half_tr), 0.5 * abs(quad[name]), abs(g[j]))
+        print(f"{name}: 1/2 tr from FIM {half_tr!r}  g + z^T K_j z / 2 {ref!r}")
+        assert abs(half_tr - ref) <= 1e-9 * scale, name
+
+
+def test_fisher_symmetric_psd(full):
+    fim = full["fim"]
+    assert rel_err(fim, fim.T) < 1e-10
+    d = np.sqrt(np.diag(fim))
+    corr = fim / np.outer(d, d)           # scale-free: entries differ by 1e13
+    ev = np.linalg.eigvalsh(0.5 * (corr + corr.T))
+    assert ev.min() >= -1e-10
+
+
+def test_gradient_central_differences(full):
+    """Central differences of L~ with the sketch held fixed, against the forward-mode
+    gradient.  At relative step 1e-6 the quotient is dominated by the rounding of L~
+    for the parameters with a tiny score (alpha = 2e-4 gives h = 2e-10), so the bound
+    there is the rounding bound 2 dL / (2 h) with dL = 32 u (|L~| + |log|K~||/2 + y^T z/2);
+    a Richardson-extrapolated quotient at relative step 1e-4 (truncation O(h^4))
+    then checks every component to 1e-6 relative plus its own rounding bound."""
+    w, H, yd, g = full["w"], full["H"], full["yd"], full["g"]
+    th = np.array(w.theta_full, dtype=np.float64)
+    free = list(w.free)
+    u = np.finfo(np.float64).eps / 2
+    dL = 32 * u * (abs(full["ll"]) + 0.5 * abs(full["logdet"]) + 0.5 * abs(float(full["y"] @ full["x"])))
+
+    def quotient(k, h):
+        vals = []
+        for sgn in (1.0, -1.0):
+            t = th.copy()
+            t[k] += sgn * h
+            H.build(t)
+            H.factor()
+            vals.append(H.loglik_grad(yd)[0])
+        return -(vals[0] - vals[1]) / (2 * h)          # derivative of -L~
+
+    res = []
+    try:
+        for j, name in enumerate(free):
+            k = ("kappa", "alpha", "tau2", "sigma2").index(name)
+            h1, h2 = 1e-6 * th[k], 1e-4 * th[k]
+            d1 = quotient(k, h1)
+            rich = (4 * quotient(k, h2) - quotient(k, 2 * h2)) / 3
+            res.append((name, h1, h2, d1, rich))
+    finally:
+        H.iteration(w.theta_full, yd)                   # leave the handle at theta
+    for j, (name, h1, h2, d1, rich) in enumerate(res):
+        tol1 = 1e-6 * abs(g[j]) + dL / h1
+        tol2 = 1e-6 * abs(g[j]) + 2 * dL / h2
+        print(f"{name}: forward-mode {g[j]!r}  FD(1e-6) {d1!r} (bound {tol1:.1e})  "
+              f"Richardson(1e-4) {rich!r} (bound {tol2:.1e})")
+        assert abs(d1 - g[j]) <= tol1, name
+        assert abs(rich - g[j]) <= tol2, name
+
+
+def test_approximation_against_closed_form(full):
+    from oracle.spectral import spectral_quantities
+    w = full["w"]
+    ex = spectral_quantities(w.dim, w.N, w.theta_full, full["y"], w.free)
+    eps_l = abs(full["ll"] - ex["loglik"]) / abs(ex["loglik"])
+    dg = full["g"] - ex["grad_nll"]
+    eta_g = math.sqrt(float(dg @ np.linalg.solve(ex["fim"], dg)))
+    print(f"eps_L {eps_l:.2e}  eta_g {eta_g:.2e}  grad {full['g']} exact {ex['grad_nll']}")
+    assert eps_l < 1e-7
+    assert eta_g < 1.0
