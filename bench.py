@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="2d_n65536")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=5,
+                    help="also time the L~ + gradient iteration by reverse mode (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 512 MiB streaming kernel (reference dispatch for HBM counters)")
     args = ap.parse_args()
@@ -179,6 +181,19 @@ def main():
             "alg_bytes_per_launch": prof["bytes"] / prof["launches"],
             "share_of_step": prof["ms"] / args.steps / ms,
         }
+    if args.adjoint_steps > 0:
+        # L~ and gradient only, by the adjoint (no derivative matrices, no Fisher)
+        H.loglik_grad_adjoint(theta, y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.adjoint_steps):
+            lla, ga = H.loglik_grad_adjoint(theta, y)
+        torch.cuda.synchronize()
+        da = time.perf_counter() - t0
+        rec["adjoint_loglik_grad"] = {"iters_per_s": args.adjoint_steps / da,
+                                      "ms_per_iter": 1e3 * da / args.adjoint_steps,
+                                      "steps": args.adjoint_steps,
+                                      "grad_nll": [float(v) for v in ga]}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline()

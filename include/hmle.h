@@ -126,6 +126,19 @@ hm_status hm_fisher(hm_H* H, double* fim);
 hm_status hm_iteration(hm_H* H, const double* theta_full, const double* y, double* loglik,
                        double* grad, double* fim);
 
+/* L~ and the NLL gradient for the free parameters by reverse mode (adjoint):
+ * builds K~(theta) only (no derivative matrices), factors it, and runs the
+ * construction backwards with the sketches held fixed (Sec. 3.3), so grad is the
+ * gradient of the same smooth L~(theta) that hm_loglik_grad differentiates
+ * forward (eq. "score approximated") -- equal up to rounding -- at a cost that
+ * does not grow with the number of parameters.  The test matrices of each level are
+ * recomputed from the stored panels and the fixed sketch, not stored.
+ * theta_full: host[4]; y: device, n doubles, grid order; loglik: host; grad: host[p]
+ * or NULL (then only L~).  Leaves H factored at theta without derivative matrices:
+ * hm_loglik_grad with grad and hm_fisher then return HM_E_STATE until hm_build. */
+hm_status hm_loglik_grad_adjoint(hm_H* H, const double* theta_full, const double* y, double* loglik,
+                                 double* grad);
+
 /* Export the representation for inspection (tests):
  * what=0: panel set of K~, n x (levels*kc), rows in tree order;
  * what=1+j: panel tangents of K~_j for the j-th free parameter that needs a

@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "hm_adjoint.h"
 #include "hm_build.h"
 #include "hm_factor.h"
 #include "hm_internal.h"
@@ -31,6 +32,7 @@ struct HState {
   int realpos[4] = {-1, -1, -1, -1};  // free position -> real derivative slot
   double theta[4] = {0, 0, 0, 0};
   int state = 0;               // 0 empty, 1 built, 2 factored, 3 parameters prepared
+  bool have_deriv = false;     // K~_j of the real parameters built at theta (hm_build, not the adjoint)
   int kc = 0;
   PanelSet ps;                 // F and the real panel tangents
   double* D = nullptr;
@@ -39,6 +41,7 @@ struct HState {
   ParamBufs pb[4];
   LevelBufs lb;
   NodeBufs nb;
+  AdjBufs adj;
   double* node_t = nullptr;    // per internal node (2kc)^2 scratch
   double* node_s = nullptr;    // per node kc^2 scratch
   double* ytree = nullptr;
@@ -128,7 +131,16 @@ static hm_status solve_refined(HState* h) {
 }
 
 // scalar slots in d_scal
-enum : int { SC_LOGDET = 0, SC_YZ = 1, SC_QUAD = 2, SC_LTR = 6, SC_NTR = 10, SC_FIM = 16 };
+enum : int { SC_LOGDET = 0, SC_YZ = 1, SC_QUAD = 2, SC_LTR = 6, SC_NTR = 10, SC_FIM = 16, SC_ADJ = 110 };
+
+static hm_status need_deriv(HState* h, const char* who) {
+  if (h->nreal > 0 && !h->have_deriv) {
+    set_error(std::string(who) + ": the derivative matrices were not built at this theta "
+              "(hm_loglik_grad_adjoint builds K~ only); call hm_build first");
+    return HM_E_STATE;
+  }
+  return HM_OK;
+}
 
 static hm_status prepare_params(HState* h) {
   if (h->state >= 3) return HM_OK;
@@ -466,6 +478,13 @@ hm_status hm_H_create(hm_sketch* hs, int p, const int* free_idx, hm_H** out) {
   for (int j = 0; j < h->nreal; ++j) AL(nb.dt[j], nodes * tw);
   double** smalls[] = {&nb.g, &nb.r1, &nb.r1i, &nb.r2, &nb.r2i, &nb.r3, &nb.r3i, &nb.rinv, &nb.w, &nb.mfold};
   for (double** q : smalls) AL(*q, nodes * s2);
+  // reverse sweep
+  AL(h->adj.Fb, pset);
+  AL(h->adj.Gs, pset);
+  AL(h->adj.Zb, (size_t)n * nl);
+  AL(h->adj.wmode, (size_t)n);
+  AL(h->adj.tmpK, nk);
+  AL(h->adj.uT, nodes * tw);
   AL(h->ytree, (size_t)n);
   AL(h->z, (size_t)n);
   AL(h->r, (size_t)n);
@@ -510,6 +529,7 @@ hm_status hm_build(hm_H* hh, const double* theta_full) {
   }
   HM_CHECK(leaf_pass(m, h->theta, h->ps, h->nreal, h->realidx, h->lb, h->nb, h->D, h->dDr));
   h->state = 1;
+  h->have_deriv = true;
   return HM_OK;
 }
 
@@ -597,6 +617,7 @@ hm_status hm_loglik_grad(hm_H* hh, const double* y, double* loglik, double* grad
   const double* zv[1] = {h->z};
   HM_CHECK(dots(m, yv, 1, zv, 1, n, h->d_scal + SC_YZ, h->d_part));
   if (grad && h->p > 0) {
+    HM_CHECK(need_deriv(h, "hm_loglik_grad"));
     HM_CHECK(prepare_params(h));
     for (int q = 0; q < h->p; ++q) {
       ParamBufs& pb = h->pb[q];
@@ -646,6 +667,7 @@ hm_status hm_fisher(hm_H* hh, double* fim) {
   Model* m = h->m;
   const int p = h->p;
   if (p == 0) return HM_OK;
+  HM_CHECK(need_deriv(h, "hm_fisher"));
   HM_CHECK(prepare_params(h));
   for (int q = 0; q < p; ++q) {
     HM_CHECK(tangent_sweep(h->f, h->pb[q]));
@@ -696,6 +718,67 @@ hm_status hm_iteration(hm_H* hh, const double* theta_full, const double* y, doub
   HM_CHECK(hm_factor(hh));
   HM_CHECK(hm_loglik_grad(hh, y, loglik, grad));
   if (fim) HM_CHECK(hm_fisher(hh, fim));
+  return HM_OK;
+}
+
+hm_status hm_loglik_grad_adjoint(hm_H* hh, const double* theta_full, const double* y, double* loglik,
+                                 double* grad) {
+  if (!hh || !y || !loglik) {
+    set_error("NULL argument");
+    return HM_E_INVAL;
+  }
+  HState* h = &hh->h;
+  HM_CHECK(check_theta(theta_full));
+  Model* m = h->m;
+  const int n = m->n, kc = h->kc;
+  // K~ only: the reverse sweep needs no derivative matrices
+  h->state = 0;
+  h->have_deriv = false;
+  std::memcpy(h->theta, theta_full, sizeof(h->theta));
+  HM_CHECK(clear_flags(m));
+  for (int l = 1; l <= m->levels; ++l) {
+    const double* XR = h->s->d_XR + (size_t)(l - 1) * kc * n;
+    HM_CHECK(level_step(m, h->theta, h->ps, l, XR, kc, h->s->d_k, 0, nullptr, h->lb, h->nb));
+  }
+  HM_CHECK(leaf_pass(m, h->theta, h->ps, 0, nullptr, h->lb, h->nb, h->D, nullptr));
+  h->state = 1;
+  HM_CHECK(hm_factor(hh));
+  HM_CHECK(permute(m, y, h->ytree, 1));
+  HM_CHECK(solve_refined(h));
+  const double* yv[1] = {h->ytree};
+  const double* zv[1] = {h->z};
+  HM_CHECK(dots(m, yv, 1, zv, 1, n, h->d_scal + SC_YZ, h->d_part));
+  if (grad && h->p > 0) {
+    HM_CHECK(node_prep(h->f));
+    HM_CHECK(adjoint_init(h->f, h->z, h->adj));
+    HM_CHECK(adjoint_sweep(m, h->theta, h->s, h->ps, h->lb, h->nb, h->adj));
+    const long NN = n;
+    const double* wv[1] = {h->adj.wmode};
+    const double* lv[3] = {m->d_lam, m->d_lam + NN, m->d_lam + 2 * NN};
+    HM_CHECK(dots(m, wv, 1, lv, 3, NN, h->d_scal + SC_ADJ, h->d_part));
+    HM_CHECK(sum_scalar(m, h->adj.wmode, NN, 0, h->d_scal + SC_ADJ + 3, h->d_part));
+  }
+  HM_HIP(hipStreamSynchronize(m->stream));
+  HM_HIP(hipMemcpy(h->h_scal, h->d_scal, 128 * sizeof(double), hipMemcpyDeviceToHost));
+  const double logdet = h->h_scal[100] + h->h_scal[101];
+  *loglik = -0.5 * n * std::log(2.0 * M_PI) - 0.5 * logdet - 0.5 * h->h_scal[SC_YZ];
+  if (!std::isfinite(*loglik)) {
+    set_error("non-finite log-likelihood");
+    return HM_E_NONFINITE;
+  }
+  if (grad) {
+    // w-weighted mode sums: <w, e>, <w, de/dkappa>, <w, de/dalpha>, sum w
+    const double* t = h->h_scal + SC_ADJ;
+    const double tau2 = h->theta[2], sigma2 = h->theta[3];
+    const double tb[4] = {t[1], t[2], t[3], (t[0] - tau2 * t[3]) / sigma2};
+    for (int q = 0; q < h->p; ++q) {
+      grad[q] = tb[h->pidx[q]];
+      if (!std::isfinite(grad[q])) {
+        set_error("non-finite gradient");
+        return HM_E_NONFINITE;
+      }
+    }
+  }
   return HM_OK;
 }
 

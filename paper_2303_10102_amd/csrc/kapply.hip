@@ -299,3 +299,73 @@ hm_status model_tables(Model* m) {
 }
 
 }  // namespace hm
+
+namespace hm {
+
+// wmode[m] += sum_c (S P X)[m, c] (S P Ybar)[m, c]: the per-mode weights of the
+// K-apply's vector-Jacobian product.  For Y = K(theta) X (X independent of theta),
+//   <Ybar, dK/dtheta_j X> = sum_m de_m/dtheta_j * wmode[m],
+// since every operator of the family is P^T S diag(.) S P with the same S.
+__global__ void k_mode_dot(const double* A, const double* B, long NN, int cc, double* wmode) {
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= NN) return;
+  double s = 0.0;
+  for (int c = 0; c < cc; ++c) s += A[e + c * NN] * B[e + c * NN];
+  wmode[e] += s;
+}
+
+template <int AM>
+static void launch_fwd(Model* m, dim3 g, const double* X, int ldx, double* out, int N, int Ny, int cc) {
+  hipLaunchKernelGGL((k_dst_fwd<AM>), g, dim3(GCfg::NT), 0, m->stream, m->d_dst, X, ldx, m->d_iperm, out, N, Ny,
+                     cc);
+}
+
+hm_status kvjp(Model* m, const double theta[4], const double* X, int ldx, const double* Yb, int ldb, int c,
+               double* wmode) {
+  if (c <= 0) return HM_OK;
+  HM_CHECK(ensure_scale(m, theta));
+  const int n = m->n, N = m->N;
+  const int Ny = (m->dim == 2) ? N : 1;
+  const long NN = (long)N * Ny;
+  double* W0 = m->d_ws;
+  double* W1 = m->d_ws + (long)n * m->cmax;
+  double* W2 = m->d_ws + 2L * n * m->cmax;
+  const int am = (Ny == 1) ? 2 : (Ny % GBN == 0 ? 1 : 0);
+  for (int c0 = 0; c0 < c; c0 += m->cmax) {
+    const int cc = std::min(m->cmax, c - c0);
+    dim3 gx(ceil_div(N, GBM), ceil_div((long)cc * Ny, GBN));
+    dim3 gy(ceil_div(N, GBM), ceil_div(N, GBN), cc);
+    const double* Xc = X + (long)c0 * ldx;
+    const double* Bc = Yb + (long)c0 * ldb;
+    const double *ha, *hb;
+    auto fwd = [&](const double* src, int ld, double* dst) {
+      if (am == 2) launch_fwd<2>(m, gx, src, ld, dst, N, Ny, cc);
+      else if (am == 1) launch_fwd<1>(m, gx, src, ld, dst, N, Ny, cc);
+      else launch_fwd<0>(m, gx, src, ld, dst, N, Ny, cc);
+    };
+    if (m->dim == 2) {
+      fwd(Xc, ldx, W0);
+      HM_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_dst_y, gy, dim3(GCfg::NT), 0, m->stream, m->d_dst, W0, (const double*)nullptr, W1, N);
+      HM_LAUNCH_CHECK();
+      fwd(Bc, ldb, W2);
+      HM_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_dst_y, gy, dim3(GCfg::NT), 0, m->stream, m->d_dst, W2, (const double*)nullptr, W0, N);
+      HM_LAUNCH_CHECK();
+      ha = W1;
+      hb = W0;
+    } else {
+      fwd(Xc, ldx, W0);
+      HM_LAUNCH_CHECK();
+      fwd(Bc, ldb, W1);
+      HM_LAUNCH_CHECK();
+      ha = W0;
+      hb = W1;
+    }
+    hipLaunchKernelGGL(k_mode_dot, dim3(ceil_div(NN, 256)), dim3(256), 0, m->stream, ha, hb, NN, cc, wmode);
+    HM_LAUNCH_CHECK();
+  }
+  return HM_OK;
+}
+
+}  // namespace hm

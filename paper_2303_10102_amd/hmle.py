@@ -51,6 +51,7 @@ _SIGS = {
     "hm_loglik_grad": ([_P, _P, _D, _D], _I),
     "hm_fisher": ([_P, _D], _I),
     "hm_iteration": ([_P, _D, _P, _D, _D, _D], _I),
+    "hm_loglik_grad_adjoint": ([_P, _D, _P, _D, _D], _I),
     "hm_export": ([_P, _I, _P], _I),
     "hm_profile_enable": ([_P, _I], _I),
     "hm_profile_read": ([_P, _D, C.POINTER(C.c_longlong), _D, _D], _I),
@@ -188,6 +189,7 @@ class HMatrix:
         h = _P()
         _check("hm_H_create", lib().hm_H_create(sketch._h, len(idx), arr, C.byref(h)))
         self._h, self.sketch, self.p = h, sketch, len(idx)
+        self.free_idx = tuple(idx)
         self.model = sketch.model
 
     def build(self, theta_full):
@@ -225,6 +227,14 @@ class HMatrix:
         _check("hm_iteration", lib().hm_iteration(self._h, _theta(theta_full), _ptr(y), C.byref(ll), g, f))
         return ll.value, np.array(g[:self.p]), np.array(f[:self.p * self.p]).reshape(self.p, self.p)
 
+    def loglik_grad_adjoint(self, theta_full, y):
+        """(L~, NLL gradient) by reverse mode through factorisation and construction."""
+        ll = C.c_double()
+        g = (C.c_double * max(1, self.p))()
+        _check("hm_loglik_grad_adjoint",
+               lib().hm_loglik_grad_adjoint(self._h, _theta(theta_full), _ptr(y), C.byref(ll), g))
+        return ll.value, np.array(g[:self.p])
+
     def export(self, what):
         import torch
         m = self.model
@@ -247,3 +257,46 @@ class HMatrix:
             self.close()
         except Exception:
             pass
+
+
+def _make_loglik_function():
+    import torch
+
+    class HLogLik(torch.autograd.Function):
+        """L~(theta, y) as a differentiable torch function; backward is the adjoint.
+
+        apply(H, theta, y, theta_full):
+          H          HMatrix (its sketch fixes the test matrices, Sec. 3.3)
+          theta      float64 CPU tensor of H's p free parameters, in H's order
+          y          float64 CUDA tensor (n,), grid order
+          theta_full the 4 parameters (kappa, alpha, tau2, sigma2) the others are taken from
+        Returns a 0-d float64 CPU tensor.  d/dtheta comes from hm_loglik_grad_adjoint,
+        d/dy = -K~^{-1} y from the same factorisation.
+        """
+
+        @staticmethod
+        def forward(ctx, H, theta, y, theta_full):
+            full = [float(t) for t in theta_full]
+            th = theta.detach().cpu().double().reshape(-1)
+            if th.numel() != H.p:
+                raise ValueError(f"theta has {th.numel()} entries, H has {H.p} free parameters")
+            for q, k in enumerate(H.free_idx):
+                full[k] = float(th[q])
+            ll, g = H.loglik_grad_adjoint(full, y.detach())
+            ctx.dtheta = torch.from_numpy(-g)
+            ctx.z = H.solve(y.detach()) if ctx.needs_input_grad[2] else None
+            return torch.tensor(ll, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gout):
+            gt = gy = None
+            if ctx.needs_input_grad[1]:
+                gt = gout.detach().cpu().double() * ctx.dtheta
+            if ctx.needs_input_grad[2]:
+                gy = -gout.detach().to(ctx.z.device, torch.float64) * ctx.z
+            return None, gt, gy, None
+
+    return HLogLik
+
+
+HLogLik = _make_loglik_function()
