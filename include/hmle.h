@@ -67,6 +67,9 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
 void hm_model_destroy(hm_model* m);
 /* n, levels, leaf size (uniform). Any pointer may be NULL. */
 hm_status hm_model_info(const hm_model* m, int* n, int* levels, int* leaf);
+/* Move all later work of the model (and of its sketches and H handles) to another
+ * stream; waits for the work already queued on the old one. */
+hm_status hm_model_set_stream(hm_model* m, void* stream);
 /* Copy the tree->grid permutation (n ints, perm[tree_pos] = grid index) to a host buffer. */
 hm_status hm_model_perm(const hm_model* m, int* perm_host);
 
@@ -125,6 +128,17 @@ hm_status hm_fisher(hm_H* H, double* fim);
 /* One likelihood iteration: build + factor + logdet + loglik/grad + fisher. */
 hm_status hm_iteration(hm_H* H, const double* theta_full, const double* y, double* loglik,
                        double* grad, double* fim);
+
+/* Many independent fields in one call (batched H-MLE iteration): the same work as
+ * hm_iteration for every handle hs[f] (each built on its own model), enqueued on
+ * each model's stream without host synchronisation and collected at the end, so
+ * fields on different streams run concurrently; results equal those of separate
+ * hm_iteration calls.  thetas: host, nf x 4 row-major; ys[f]: device sample of
+ * field f (grid order); loglik: host[nf]; grad: host, the fields' p_f entries
+ * concatenated (or NULL); fim: host, the p_f x p_f blocks concatenated (or NULL).
+ * A handle may appear once.  On failure the message names the first failing field. */
+hm_status hm_iteration_batched(int nf, hm_H* const* hs, const double* thetas, const double* const* ys,
+                               double* loglik, double* grad, double* fim);
 
 /* L~ and the NLL gradient for the free parameters by reverse mode (adjoint):
  * builds K~(theta) only (no derivative matrices), factors it, and runs the

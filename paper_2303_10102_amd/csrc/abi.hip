@@ -51,6 +51,7 @@ struct HState {
   double* d_scal = nullptr;
   double* d_part = nullptr;
   double* h_scal = nullptr;
+  int* h_flags = nullptr;      // pinned copy of the model's device flags
   std::vector<void*> allocs;
 };
 
@@ -87,14 +88,13 @@ static hm_status check_theta(const double* t) {
   return HM_OK;
 }
 
-static hm_status read_flags(Model* m, int* flags) {
-  HM_HIP(hipStreamSynchronize(m->stream));
-  HM_HIP(hipMemcpy(flags, m->d_flags, sizeof(int), hipMemcpyDeviceToHost));
-  return HM_OK;
+__global__ void k_zero_int(int* p) {
+  if (threadIdx.x == 0) *p = 0;
 }
-
+// device status flags are cleared by a kernel (no memset node in captured work)
 static hm_status clear_flags(Model* m) {
-  HM_HIP(hipMemsetAsync(m->d_flags, 0, sizeof(int), m->stream));
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, m->stream, m->d_flags);
+  HM_LAUNCH_CHECK();
   return HM_OK;
 }
 
@@ -157,6 +157,184 @@ static hm_status prepare_params(HState* h) {
   for (int q = 0; q < h->p; ++q) HM_CHECK(param_prepare(h->f, h->pb[q], h->theta, h->f.nT));
   HM_CHECK(node_prep(h->f));
   h->state = 3;
+  return HM_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Iteration phases.  *_enqueue only enqueue device work on the model's stream
+// (no host synchronisation), so several handles on different streams overlap;
+// fetch_scalars queues the copy of the scalar slots and the device flags to
+// pinned host memory; the *_collect / sync_check steps synchronise and check.
+// ---------------------------------------------------------------------------
+static hm_status fetch_scalars(HState* h, int first, int count) {
+  Model* m = h->m;
+  HM_HIP(hipMemcpyAsync(h->h_scal + first, h->d_scal + first, count * sizeof(double), hipMemcpyDeviceToHost,
+                        m->stream));
+  HM_HIP(hipMemcpyAsync(h->h_flags, m->d_flags, sizeof(int), hipMemcpyDeviceToHost, m->stream));
+  return HM_OK;
+}
+
+// after fetch_scalars: wait, then report construction/factorisation failures
+static hm_status sync_check(HState* h, bool factored) {
+  HM_HIP(hipStreamSynchronize(h->m->stream));
+  const int flags = *h->h_flags;
+  if (factored && (flags & (DF_NOT_SPD_LEAF | DF_NOT_SPD_NODE))) {
+    set_error(std::string("K~ is not positive definite (") +
+              ((flags & DF_NOT_SPD_LEAF) ? "leaf Cholesky" : "node determinant") + ")");
+    h->state = 1;
+    return HM_E_NOT_SPD;
+  }
+  if (flags & DF_QR_FAIL) {
+    set_error("a sketch QR failed during construction (rank-deficient sample)");
+    h->state = 1;
+    return HM_E_RANK;
+  }
+  return HM_OK;
+}
+
+static hm_status build_enqueue(HState* h, const double* theta_full, bool deriv) {
+  HM_CHECK(check_theta(theta_full));
+  Model* m = h->m;
+  h->state = 0;
+  h->have_deriv = false;
+  std::memcpy(h->theta, theta_full, sizeof(h->theta));
+  HM_CHECK(clear_flags(m));
+  const int n = m->n, kc = h->kc;
+  const int nr = deriv ? h->nreal : 0;
+  for (int l = 1; l <= m->levels; ++l) {
+    const double* XR = h->s->d_XR + (size_t)(l - 1) * kc * n;
+    HM_CHECK(level_step(m, h->theta, h->ps, l, XR, kc, h->s->d_k, nr, h->realidx, h->lb, h->nb));
+  }
+  HM_CHECK(leaf_pass(m, h->theta, h->ps, nr, h->realidx, h->lb, h->nb, h->D, deriv ? h->dDr : nullptr));
+  h->state = 1;
+  h->have_deriv = deriv;
+  return HM_OK;
+}
+
+static hm_status factor_enqueue(HState* h) {
+  Model* m = h->m;
+  HM_CHECK(factorize(h->f));
+  // log|K~| = sum of leaf and node parts
+  HM_CHECK(sum_scalar(m, h->f.logdet_leaf, m->nleaves, 0, h->d_scal + 100, h->d_part));
+  HM_CHECK(sum_scalar(m, h->f.logdet_node, (1 << m->levels) - 1, 0, h->d_scal + 101, h->d_part));
+  h->state = 2;
+  return HM_OK;
+}
+
+static hm_status loglik_enqueue(HState* h, const double* y, bool want_grad) {
+  Model* m = h->m;
+  const int n = m->n;
+  HM_CHECK(permute(m, y, h->ytree, 1));
+  HM_CHECK(solve_refined(h));
+  const double* yv[1] = {h->ytree};
+  const double* zv[1] = {h->z};
+  HM_CHECK(dots(m, yv, 1, zv, 1, n, h->d_scal + SC_YZ, h->d_part));
+  if (!want_grad || h->p == 0) return HM_OK;
+  HM_CHECK(prepare_params(h));
+  for (int q = 0; q < h->p; ++q) {
+    ParamBufs& pb = h->pb[q];
+    // z^T K~_j z
+    HM_CHECK(hmatvec(h->f, pb.dD, h->ps.F, pb.dF, h->z, 1, h->v, 1.0, 0.0));
+    const double* vv[1] = {h->v};
+    HM_CHECK(dots(m, zv, 1, vv, 1, n, h->d_scal + SC_QUAD + q, h->d_part));
+    // tr(K~^{-1} K~_j) = sum_L tr(Y_L) - sum_P <N_P, PsiP>
+    HM_CHECK(sum_scalar(m, pb.Y, (long)m->nleaves * m->nl, m->nl, h->d_scal + SC_LTR + q, h->d_part));
+    HM_CHECK(node_psi(h->f, pb, h->node_s));
+  }
+  // node part of every trace: <N_P, PsiP^j> summed over internal nodes
+  const long ms = 4L * h->kc * h->kc;
+  const double* nv[1] = {h->f.Nn};
+  const double* pv[4];
+  for (int q = 0; q < h->p; ++q) pv[q] = h->pb[q].PsiP;
+  HM_CHECK(dots(m, nv, 1, pv, h->p, ((1L << m->levels) - 1) * ms, h->d_scal + SC_NTR, h->d_part));
+  return HM_OK;
+}
+
+static hm_status loglik_collect(HState* h, double* loglik, double* grad) {
+  const int n = h->m->n;
+  const double logdet = h->h_scal[100] + h->h_scal[101];
+  const double yz = h->h_scal[SC_YZ];
+  *loglik = -0.5 * n * std::log(2.0 * M_PI) - 0.5 * logdet - 0.5 * yz;
+  if (!std::isfinite(*loglik)) {
+    set_error("non-finite log-likelihood");
+    return HM_E_NONFINITE;
+  }
+  if (grad) {
+    for (int q = 0; q < h->p; ++q) {
+      const double tr = h->h_scal[SC_LTR + q] - h->h_scal[SC_NTR + q];
+      grad[q] = 0.5 * tr - 0.5 * h->h_scal[SC_QUAD + q];
+    }
+  }
+  return HM_OK;
+}
+
+static hm_status fisher_enqueue(HState* h) {
+  Model* m = h->m;
+  const int p = h->p;
+  HM_CHECK(prepare_params(h));
+  for (int q = 0; q < p; ++q) {
+    HM_CHECK(tangent_sweep(h->f, h->pb[q]));
+    HM_CHECK(node_psi(h->f, h->pb[q], h->node_s));
+    HM_CHECK(node_lam(h->f, h->pb[q], h->node_t, h->node_s));
+    HM_CHECK(panel_products(h->f, h->pb[q]));
+  }
+  const int n = m->n, kc = h->kc, levels = m->levels;
+  const long pset = (long)n * levels * kc;
+  const long lset = (long)m->nleaves * m->nl * m->nl;
+  const long s2 = (long)kc * kc;
+  const long nint = (1 << levels) - 1, nodes = (2L << levels) - 1;
+  const double *A[4], *B[4];
+  double* out = h->d_scal + SC_FIM;
+  // term 0: 1/2 <Y^i, Yt^j>
+  for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Y; B[q] = h->pb[q].Yt; }
+  HM_CHECK(dots(m, A, p, B, p, lset, out + 0 * 16, h->d_part));
+  // term 1: -1/2 <Lam^i, PsiP^j>
+  for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Lam; B[q] = h->pb[q].PsiP; }
+  HM_CHECK(dots(m, A, p, B, p, nint * 4 * s2, out + 1 * 16, h->d_part));
+  // term 2: <Gh^i, Xi^j>
+  for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Gh; B[q] = h->pb[q].Xi; }
+  HM_CHECK(dots(m, A, p, B, p, pset, out + 2 * 16, h->d_part));
+  // term 3: <Hh^i, dF^j>
+  for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Hh; B[q] = h->pb[q].dF; }
+  HM_CHECK(dots(m, A, p, B, p, pset, out + 3 * 16, h->d_part));
+  // term 4: <Vt^i, E^j> over non-root nodes
+  for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Vt + s2; B[q] = h->pb[q].E + s2; }
+  HM_CHECK(dots(m, A, p, B, p, (nodes - 1) * s2, out + 4 * 16, h->d_part));
+  return HM_OK;
+}
+
+static hm_status fisher_collect(HState* h, double* fim) {
+  const int p = h->p;
+  const double* t = h->h_scal + SC_FIM;
+  for (int i = 0; i < p; ++i)
+    for (int j = 0; j < p; ++j) {
+      const int q = i * p + j;
+      fim[q] = 0.5 * t[q] - 0.5 * t[16 + q] + t[32 + q] + t[48 + q] + t[64 + q];
+      if (!std::isfinite(fim[q])) {
+        set_error("non-finite Fisher information");
+        return HM_E_NONFINITE;
+      }
+    }
+  return HM_OK;
+}
+
+// One whole iteration without a host synchronisation (build, factor, L~ and
+// gradient, Fisher), ending with the copy of the scalars to pinned memory.
+static hm_status iteration_enqueue(HState* h, const double* theta_full, const double* y, bool want_grad,
+                                   bool want_fim) {
+  HM_CHECK(build_enqueue(h, theta_full, true));
+  HM_CHECK(factor_enqueue(h));
+  HM_CHECK(loglik_enqueue(h, y, want_grad));
+  if (want_fim && h->p > 0) HM_CHECK(fisher_enqueue(h));
+  HM_CHECK(fetch_scalars(h, 0, 128));
+  return HM_OK;
+}
+
+static hm_status iteration_collect(HState* h, double* loglik, double* grad, double* fim) {
+  HM_CHECK(sync_check(h, true));
+  HM_CHECK(loglik_collect(h, loglik, grad));
+  if (fim && h->p > 0) HM_CHECK(fisher_collect(h, fim));
   return HM_OK;
 }
 
@@ -244,7 +422,7 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
   }
   hm_status st = model_tables(m);
   if (st == HM_OK) st = make_identity_stack(m);
-  if (st == HM_OK && hipMemsetAsync(m->d_flags, 0, sizeof(int), m->stream) != hipSuccess) st = HM_E_DEVICE;
+  if (st == HM_OK) st = clear_flags(m);
   if (st == HM_OK && hipStreamSynchronize(m->stream) != hipSuccess) {
     set_error("hm_model_create: device error");
     st = HM_E_DEVICE;
@@ -275,6 +453,17 @@ hm_status hm_model_info(const hm_model* mm, int* n, int* levels, int* leaf) {
   if (n) *n = mm->m.n;
   if (levels) *levels = mm->m.levels;
   if (leaf) *leaf = mm->m.nl;
+  return HM_OK;
+}
+
+hm_status hm_model_set_stream(hm_model* mm, void* stream) {
+  if (!mm) {
+    set_error("model is NULL");
+    return HM_E_INVAL;
+  }
+  Model* m = &mm->m;
+  HM_HIP(hipStreamSynchronize(m->stream));
+  m->stream = (hipStream_t)stream;
   return HM_OK;
 }
 
@@ -365,6 +554,7 @@ void hm_H_destroy(hm_H* hh) {
   if (!hh) return;
   for (void* p : hh->h.allocs) (void)hipFree(p);
   if (hh->h.h_scal) (void)hipHostFree(hh->h.h_scal);
+  if (hh->h.h_flags) (void)hipHostFree(hh->h.h_flags);
   delete hh;
 }
 
@@ -492,7 +682,8 @@ hm_status hm_H_create(hm_sketch* hs, int p, const int* free_idx, hm_H** out) {
   AL(h->d_scal, (size_t)NSCAL);
   AL(h->d_part, (size_t)1024 * 16);
 #undef AL
-  if (st == HM_OK && hipHostMalloc((void**)&h->h_scal, NSCAL * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+  if (st == HM_OK && (hipHostMalloc((void**)&h->h_scal, NSCAL * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+                      hipHostMalloc((void**)&h->h_flags, sizeof(int), hipHostMallocDefault) != hipSuccess)) {
     set_error("pinned host allocation failed");
     st = HM_E_NOMEM;
   }
@@ -516,21 +707,7 @@ hm_status hm_build(hm_H* hh, const double* theta_full) {
     set_error("H is NULL");
     return HM_E_INVAL;
   }
-  HState* h = &hh->h;
-  HM_CHECK(check_theta(theta_full));
-  Model* m = h->m;
-  h->state = 0;
-  std::memcpy(h->theta, theta_full, sizeof(h->theta));
-  HM_CHECK(clear_flags(m));
-  const int n = m->n, kc = h->kc;
-  for (int l = 1; l <= m->levels; ++l) {
-    const double* XR = h->s->d_XR + (size_t)(l - 1) * kc * n;
-    HM_CHECK(level_step(m, h->theta, h->ps, l, XR, kc, h->s->d_k, h->nreal, h->realidx, h->lb, h->nb));
-  }
-  HM_CHECK(leaf_pass(m, h->theta, h->ps, h->nreal, h->realidx, h->lb, h->nb, h->D, h->dDr));
-  h->state = 1;
-  h->have_deriv = true;
-  return HM_OK;
+  return build_enqueue(&hh->h, theta_full, true);
 }
 
 hm_status hm_factor(hm_H* hh) {
@@ -543,26 +720,9 @@ hm_status hm_factor(hm_H* hh) {
     set_error("hm_factor before hm_build");
     return HM_E_STATE;
   }
-  Model* m = h->m;
-  HM_CHECK(factorize(h->f));
-  // log|K~| = sum of leaf and node parts
-  HM_CHECK(sum_scalar(m, h->f.logdet_leaf, m->nleaves, 0, h->d_scal + 100, h->d_part));
-  HM_CHECK(sum_scalar(m, h->f.logdet_node, (1 << m->levels) - 1, 0, h->d_scal + 101, h->d_part));
-  int flags = 0;
-  HM_CHECK(read_flags(m, &flags));
-  if (flags & (DF_NOT_SPD_LEAF | DF_NOT_SPD_NODE)) {
-    set_error(std::string("K~ is not positive definite (") +
-              ((flags & DF_NOT_SPD_LEAF) ? "leaf Cholesky" : "node determinant") + ")");
-    h->state = 1;
-    return HM_E_NOT_SPD;
-  }
-  if (flags & DF_QR_FAIL) {
-    set_error("a sketch QR failed during construction (rank-deficient sample)");
-    h->state = 1;
-    return HM_E_RANK;
-  }
-  HM_HIP(hipMemcpy(h->h_scal, h->d_scal + 100, 2 * sizeof(double), hipMemcpyDeviceToHost));
-  h->state = 2;
+  HM_CHECK(factor_enqueue(h));
+  HM_CHECK(fetch_scalars(h, 0, 128));
+  HM_CHECK(sync_check(h, true));
   return HM_OK;
 }
 
@@ -576,9 +736,9 @@ hm_status hm_logdet(hm_H* hh, double* out) {
     set_error("hm_logdet before hm_factor");
     return HM_E_STATE;
   }
+  HM_CHECK(fetch_scalars(h, 100, 2));
   HM_HIP(hipStreamSynchronize(h->m->stream));
-  HM_HIP(hipMemcpy(h->h_scal, h->d_scal + 100, 2 * sizeof(double), hipMemcpyDeviceToHost));
-  *out = h->h_scal[0] + h->h_scal[1];
+  *out = h->h_scal[100] + h->h_scal[101];
   return HM_OK;
 }
 
@@ -609,49 +769,11 @@ hm_status hm_loglik_grad(hm_H* hh, const double* y, double* loglik, double* grad
     set_error("hm_loglik_grad before hm_factor");
     return HM_E_STATE;
   }
-  Model* m = h->m;
-  const int n = m->n;
-  HM_CHECK(permute(m, y, h->ytree, 1));
-  HM_CHECK(solve_refined(h));
-  const double* yv[1] = {h->ytree};
-  const double* zv[1] = {h->z};
-  HM_CHECK(dots(m, yv, 1, zv, 1, n, h->d_scal + SC_YZ, h->d_part));
-  if (grad && h->p > 0) {
-    HM_CHECK(need_deriv(h, "hm_loglik_grad"));
-    HM_CHECK(prepare_params(h));
-    for (int q = 0; q < h->p; ++q) {
-      ParamBufs& pb = h->pb[q];
-      // z^T K~_j z
-      HM_CHECK(hmatvec(h->f, pb.dD, h->ps.F, pb.dF, h->z, 1, h->v, 1.0, 0.0));
-      const double* vv[1] = {h->v};
-      HM_CHECK(dots(m, zv, 1, vv, 1, n, h->d_scal + SC_QUAD + q, h->d_part));
-      // tr(K~^{-1} K~_j) = sum_L tr(Y_L) - sum_P <N_P, PsiP>
-      HM_CHECK(sum_scalar(m, pb.Y, (long)m->nleaves * m->nl, m->nl, h->d_scal + SC_LTR + q, h->d_part));
-      HM_CHECK(node_psi(h->f, pb, h->node_s));
-    }
-    // node part of every trace: <N_P, PsiP^j> summed over internal nodes
-    const long ms = 4L * h->kc * h->kc;
-    const double* nv[1] = {h->f.Nn};
-    const double* pv[4];
-    for (int q = 0; q < h->p; ++q) pv[q] = h->pb[q].PsiP;
-    HM_CHECK(dots(m, nv, 1, pv, h->p, ((1L << m->levels) - 1) * ms, h->d_scal + SC_NTR, h->d_part));
-  }
-  HM_HIP(hipStreamSynchronize(m->stream));
-  HM_HIP(hipMemcpy(h->h_scal, h->d_scal, 128 * sizeof(double), hipMemcpyDeviceToHost));
-  const double logdet = h->h_scal[100] + h->h_scal[101];
-  const double yz = h->h_scal[SC_YZ];
-  *loglik = -0.5 * n * std::log(2.0 * M_PI) - 0.5 * logdet - 0.5 * yz;
-  if (!std::isfinite(*loglik)) {
-    set_error("non-finite log-likelihood");
-    return HM_E_NONFINITE;
-  }
-  if (grad) {
-    for (int q = 0; q < h->p; ++q) {
-      const double tr = h->h_scal[SC_LTR + q] - h->h_scal[SC_NTR + q];
-      grad[q] = 0.5 * tr - 0.5 * h->h_scal[SC_QUAD + q];
-    }
-  }
-  return HM_OK;
+  if (grad && h->p > 0) HM_CHECK(need_deriv(h, "hm_loglik_grad"));
+  HM_CHECK(loglik_enqueue(h, y, grad != nullptr));
+  HM_CHECK(fetch_scalars(h, 0, 128));
+  HM_HIP(hipStreamSynchronize(h->m->stream));
+  return loglik_collect(h, loglik, grad);
 }
 
 hm_status hm_fisher(hm_H* hh, double* fim) {
@@ -664,61 +786,67 @@ hm_status hm_fisher(hm_H* hh, double* fim) {
     set_error("hm_fisher before hm_factor");
     return HM_E_STATE;
   }
-  Model* m = h->m;
-  const int p = h->p;
-  if (p == 0) return HM_OK;
+  if (h->p == 0) return HM_OK;
   HM_CHECK(need_deriv(h, "hm_fisher"));
-  HM_CHECK(prepare_params(h));
-  for (int q = 0; q < p; ++q) {
-    HM_CHECK(tangent_sweep(h->f, h->pb[q]));
-    HM_CHECK(node_psi(h->f, h->pb[q], h->node_s));
-    HM_CHECK(node_lam(h->f, h->pb[q], h->node_t, h->node_s));
-    HM_CHECK(panel_products(h->f, h->pb[q]));
-  }
-  const int n = m->n, kc = h->kc, levels = m->levels;
-  const long pset = (long)n * levels * kc;
-  const long lset = (long)m->nleaves * m->nl * m->nl;
-  const long s2 = (long)kc * kc;
-  const long nint = (1 << levels) - 1, nodes = (2L << levels) - 1;
-  const double *A[4], *B[4];
-  double* out = h->d_scal + SC_FIM;
-  // term 0: 1/2 <Y^i, Yt^j>
-  for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Y; B[q] = h->pb[q].Yt; }
-  HM_CHECK(dots(m, A, p, B, p, lset, out + 0 * 16, h->d_part));
-  // term 1: -1/2 <Lam^i, PsiP^j>
-  for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Lam; B[q] = h->pb[q].PsiP; }
-  HM_CHECK(dots(m, A, p, B, p, nint * 4 * s2, out + 1 * 16, h->d_part));
-  // term 2: <Gh^i, Xi^j>
-  for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Gh; B[q] = h->pb[q].Xi; }
-  HM_CHECK(dots(m, A, p, B, p, pset, out + 2 * 16, h->d_part));
-  // term 3: <Hh^i, dF^j>
-  for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Hh; B[q] = h->pb[q].dF; }
-  HM_CHECK(dots(m, A, p, B, p, pset, out + 3 * 16, h->d_part));
-  // term 4: <Vt^i, E^j> over non-root nodes
-  for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Vt + s2; B[q] = h->pb[q].E + s2; }
-  HM_CHECK(dots(m, A, p, B, p, (nodes - 1) * s2, out + 4 * 16, h->d_part));
-  HM_HIP(hipStreamSynchronize(m->stream));
-  HM_HIP(hipMemcpy(h->h_scal + SC_FIM, out, 5 * 16 * sizeof(double), hipMemcpyDeviceToHost));
-  const double* t = h->h_scal + SC_FIM;
-  for (int i = 0; i < p; ++i)
-    for (int j = 0; j < p; ++j) {
-      const int q = i * p + j;
-      fim[q] = 0.5 * t[q] - 0.5 * t[16 + q] + t[32 + q] + t[48 + q] + t[64 + q];
-      if (!std::isfinite(fim[q])) {
-        set_error("non-finite Fisher information");
-        return HM_E_NONFINITE;
-      }
-    }
-  return HM_OK;
+  HM_CHECK(fisher_enqueue(h));
+  HM_CHECK(fetch_scalars(h, 0, 128));
+  HM_HIP(hipStreamSynchronize(h->m->stream));
+  return fisher_collect(h, fim);
 }
 
 hm_status hm_iteration(hm_H* hh, const double* theta_full, const double* y, double* loglik, double* grad,
                        double* fim) {
-  HM_CHECK(hm_build(hh, theta_full));
-  HM_CHECK(hm_factor(hh));
-  HM_CHECK(hm_loglik_grad(hh, y, loglik, grad));
-  if (fim) HM_CHECK(hm_fisher(hh, fim));
-  return HM_OK;
+  if (!hh || !y || !loglik) {
+    set_error("NULL argument");
+    return HM_E_INVAL;
+  }
+  HState* h = &hh->h;
+  HM_CHECK(iteration_enqueue(h, theta_full, y, grad != nullptr, fim != nullptr));
+  return iteration_collect(h, loglik, grad, fim);
+}
+
+hm_status hm_iteration_batched(int nf, hm_H* const* hs, const double* thetas, const double* const* ys,
+                               double* loglik, double* grad, double* fim) {
+  if (nf < 0 || (nf > 0 && (!hs || !thetas || !ys || !loglik))) {
+    set_error("bad arguments to hm_iteration_batched");
+    return HM_E_INVAL;
+  }
+  for (int f = 0; f < nf; ++f) {
+    if (!hs[f] || !ys[f]) {
+      set_error("hm_iteration_batched: field " + std::to_string(f) + " has a NULL handle or sample");
+      return HM_E_INVAL;
+    }
+    for (int g = 0; g < f; ++g)
+      if (hs[g] == hs[f]) {
+        set_error("hm_iteration_batched: a handle appears twice");
+        return HM_E_INVAL;
+      }
+  }
+  // enqueue every field on its own model's stream, then collect; no host
+  // synchronisation until the collect phase, so the streams run concurrently
+  for (int f = 0; f < nf; ++f) {
+    hm_status st = iteration_enqueue(&hs[f]->h, thetas + 4L * f, ys[f], grad != nullptr, fim != nullptr);
+    if (st != HM_OK) {
+      set_error("field " + std::to_string(f) + ": " + get_error());
+      for (int g = 0; g < f; ++g) (void)hipStreamSynchronize(hs[g]->h.m->stream);
+      return st;
+    }
+  }
+  hm_status first = HM_OK;
+  std::string msg;
+  long go = 0, fo = 0;
+  for (int f = 0; f < nf; ++f) {
+    HState* h = &hs[f]->h;
+    hm_status st = iteration_collect(h, loglik + f, grad ? grad + go : nullptr, fim ? fim + fo : nullptr);
+    if (st != HM_OK && first == HM_OK) {
+      first = st;
+      msg = "field " + std::to_string(f) + ": " + get_error();
+    }
+    go += h->p;
+    fo += (long)h->p * h->p;
+  }
+  if (first != HM_OK) set_error(msg);
+  return first;
 }
 
 hm_status hm_loglik_grad_adjoint(hm_H* hh, const double* theta_full, const double* y, double* loglik,
@@ -728,21 +856,11 @@ hm_status hm_loglik_grad_adjoint(hm_H* hh, const double* theta_full, const doubl
     return HM_E_INVAL;
   }
   HState* h = &hh->h;
-  HM_CHECK(check_theta(theta_full));
   Model* m = h->m;
-  const int n = m->n, kc = h->kc;
+  const int n = m->n;
   // K~ only: the reverse sweep needs no derivative matrices
-  h->state = 0;
-  h->have_deriv = false;
-  std::memcpy(h->theta, theta_full, sizeof(h->theta));
-  HM_CHECK(clear_flags(m));
-  for (int l = 1; l <= m->levels; ++l) {
-    const double* XR = h->s->d_XR + (size_t)(l - 1) * kc * n;
-    HM_CHECK(level_step(m, h->theta, h->ps, l, XR, kc, h->s->d_k, 0, nullptr, h->lb, h->nb));
-  }
-  HM_CHECK(leaf_pass(m, h->theta, h->ps, 0, nullptr, h->lb, h->nb, h->D, nullptr));
-  h->state = 1;
-  HM_CHECK(hm_factor(hh));
+  HM_CHECK(build_enqueue(h, theta_full, false));
+  HM_CHECK(factor_enqueue(h));
   HM_CHECK(permute(m, y, h->ytree, 1));
   HM_CHECK(solve_refined(h));
   const double* yv[1] = {h->ytree};
@@ -758,8 +876,8 @@ hm_status hm_loglik_grad_adjoint(hm_H* hh, const double* theta_full, const doubl
     HM_CHECK(dots(m, wv, 1, lv, 3, NN, h->d_scal + SC_ADJ, h->d_part));
     HM_CHECK(sum_scalar(m, h->adj.wmode, NN, 0, h->d_scal + SC_ADJ + 3, h->d_part));
   }
-  HM_HIP(hipStreamSynchronize(m->stream));
-  HM_HIP(hipMemcpy(h->h_scal, h->d_scal, 128 * sizeof(double), hipMemcpyDeviceToHost));
+  HM_CHECK(fetch_scalars(h, 0, 128));
+  HM_CHECK(sync_check(h, true));
   const double logdet = h->h_scal[100] + h->h_scal[101];
   *loglik = -0.5 * n * std::log(2.0 * M_PI) - 0.5 * logdet - 0.5 * h->h_scal[SC_YZ];
   if (!std::isfinite(*loglik)) {

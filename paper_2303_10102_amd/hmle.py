@@ -37,6 +37,7 @@ _SIGS = {
     "hm_model_create": ([_I, _P, _I, _I, _I, C.POINTER(_P)], _I),
     "hm_model_destroy": ([_P], None),
     "hm_model_info": ([_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)], _I),
+    "hm_model_set_stream": ([_P, _P], _I),
     "hm_model_perm": ([_P, C.POINTER(_I)], _I),
     "hm_kapply": ([_P, _D, _P, _I, _I, _P, _I, _I], _I),
     "hm_sketch_create": ([_P, _P, _I, _I, _D, C.POINTER(_P)], _I),
@@ -51,6 +52,7 @@ _SIGS = {
     "hm_loglik_grad": ([_P, _P, _D, _D], _I),
     "hm_fisher": ([_P, _D], _I),
     "hm_iteration": ([_P, _D, _P, _D, _D, _D], _I),
+    "hm_iteration_batched": ([_I, C.POINTER(_P), _D, C.POINTER(_P), _D, _D, _D], _I),
     "hm_loglik_grad_adjoint": ([_P, _D, _P, _D, _D], _I),
     "hm_export": ([_P, _I, _P], _I),
     "hm_profile_enable": ([_P, _I], _I),
@@ -115,6 +117,11 @@ class Model:
         n, lv, lf = _I(), _I(), _I()
         _check("hm_model_info", lib().hm_model_info(h, C.byref(n), C.byref(lv), C.byref(lf)))
         self.dim, self.N, self.n, self.levels, self.leaf = dim, N, n.value, lv.value, lf.value
+
+    def set_stream(self, stream):
+        """Move the model's later work to another torch stream (None = current stream)."""
+        _check("hm_model_set_stream", lib().hm_model_set_stream(self._h, _stream_handle(stream)))
+        self.stream = stream
 
     def perm(self):
         out = (C.c_int * self.n)()
@@ -257,6 +264,125 @@ class HMatrix:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Independent fields iterated together (hm_iteration_batched).
+
+    Every field is an HMatrix on a Model of its own.  The schedule decides how many
+    streams run concurrently, which field goes on which stream and the enqueue order:
+    fields are taken longest first (by measured or estimated cost) and placed on the
+    least-loaded stream; the enqueue order interleaves the streams so that each one
+    starts at once.  `tune` measures every field alone and times the batch under
+    each candidate stream count, keeping the fastest.
+    """
+
+    def __init__(self, Hs):
+        import torch
+        self.Hs = list(Hs)
+        models = [H.model for H in self.Hs]
+        if len({id(m) for m in models}) != len(models):
+            raise ValueError("every field needs a Model of its own (one stream per model)")
+        self.device = models[0].device if models else torch.device("cuda", 0)
+        # estimated cost per iteration ~ n kc^2 levels^2 (panel products over the tree)
+        self.cost = []
+        for H in self.Hs:
+            _, kc = H.sketch.ranks()
+            m = H.model
+            self.cost.append(float(m.n) * kc * kc * m.levels * m.levels)
+        self.order = list(range(len(self.Hs)))
+        self.nstreams = 0
+        self.streams = []
+        self.set_schedule(1)
+
+    def set_schedule(self, nstreams, cost=None):
+        import torch
+        cost = self.cost if cost is None else list(cost)
+        nstreams = max(1, min(int(nstreams), max(1, len(self.Hs))))
+        if nstreams != self.nstreams:
+            self.streams = [torch.cuda.Stream(device=self.device) for _ in range(nstreams)]
+            self.nstreams = nstreams
+        load = [0.0] * nstreams
+        lanes = [[] for _ in range(nstreams)]
+        for f in sorted(range(len(self.Hs)), key=lambda i: -cost[i]):
+            s = min(range(nstreams), key=lambda q: load[q])
+            load[s] += cost[f]
+            lanes[s].append(f)
+            self.Hs[f].model.set_stream(self.streams[s])
+        order = []
+        for r in range(max((len(x) for x in lanes), default=0)):
+            for q in range(nstreams):
+                if r < len(lanes[q]):
+                    order.append(lanes[q][r])
+        self.order = order
+        self.lanes = lanes
+        return lanes
+
+    def iteration(self, thetas, ys, want_grad=True, want_fim=True):
+        """One iteration of every field: (loglik[nf], [grad_f], [fim_f]) in field order."""
+        import torch
+        nf = len(self.Hs)
+        th = np.ascontiguousarray(np.asarray(thetas, dtype=np.float64).reshape(nf, 4))
+        order = self.order
+        hs = (_P * max(1, nf))(*[self.Hs[f]._h for f in order])
+        yp = (_P * max(1, nf))(*[_ptr(ys[f]) for f in order])
+        tho = np.ascontiguousarray(th[order])
+        ps = [self.Hs[f].p for f in order]
+        ll = (C.c_double * max(1, nf))()
+        g = (C.c_double * max(1, sum(ps))) () if want_grad else None
+        fm = (C.c_double * max(1, sum(p * p for p in ps)))() if want_fim else None
+        torch.cuda.current_stream(self.device).synchronize()   # samples written on the current stream
+        _check("hm_iteration_batched",
+               lib().hm_iteration_batched(nf, hs, tho.ctypes.data_as(_D), yp, ll,
+                                          g if want_grad else None, fm if want_fim else None))
+        lls = np.zeros(nf)
+        grads = [None] * nf
+        fims = [None] * nf
+        go = fo = 0
+        for pos, f in enumerate(order):
+            p = ps[pos]
+            lls[f] = ll[pos]
+            if want_grad:
+                grads[f] = np.array(g[go:go + p])
+            if want_fim:
+                fims[f] = np.array(fm[fo:fo + p * p]).reshape(p, p)
+            go += p
+            fo += p * p
+        return lls, grads, fims
+
+    def tune(self, thetas, ys, candidates=(1, 2, 4, 8), reps=1):
+        """Pick the stream count by timing; returns the measurements."""
+        import time
+        import torch
+        nf = len(self.Hs)
+        th = np.asarray(thetas, dtype=np.float64).reshape(nf, 4)
+        solo = []
+        for f, H in enumerate(self.Hs):
+            H.model.set_stream(None)
+            H.iteration(th[f], ys[f])                      # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                H.iteration(th[f], ys[f])
+            torch.cuda.synchronize()
+            solo.append((time.perf_counter() - t0) / reps)
+        self.nstreams = 0
+        timings = {}
+        for ns in candidates:
+            if ns > max(1, nf):
+                continue
+            self.set_schedule(ns, cost=solo)
+            self.iteration(th, ys)                          # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                self.iteration(th, ys)
+            torch.cuda.synchronize()
+            timings[ns] = (time.perf_counter() - t0) / reps
+        best = min(timings, key=timings.get)
+        self.set_schedule(best, cost=solo)
+        self.cost = solo
+        return dict(solo_s=solo, sequential_s=float(sum(solo)), batch_s=timings, best_streams=best)
 
 
 def _make_loglik_function():

@@ -1,6 +1,6 @@
 """Seeded synthetic inputs shared by the HIP library's tests and the CPU oracle."""
 from .workloads import (PARAM_NAMES, Workload, WORKLOADS, small_workload, sample_y,
-                        sketch_draws, SIGMA2_256)
+                        sketch_draws, SIGMA2_256, BATCH_SIDES, batched_fields)
 
 __all__ = ["PARAM_NAMES", "Workload", "WORKLOADS", "small_workload", "sample_y",
-           "sketch_draws", "SIGMA2_256"]
+           "sketch_draws", "SIGMA2_256", "BATCH_SIDES", "batched_fields"]

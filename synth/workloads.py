@@ -105,6 +105,30 @@ def small_workload(dim=2, N=32, leaf=64, rank=16, oversample=10, free=("kappa", 
                     kappa, alpha, tau2, sigma2, tuple(free), data_seed, sketch_seed)
 
 
+BATCH_SIDES = (64, 96, 128, 192, 256)
+
+
+def batched_fields(count: int = 64, seed: int = 4, sides=BATCH_SIDES, leaf: int = 256, rank: int = 32,
+                   oversample: int = 10) -> list:
+    """Independent 2D fields of uneven size and parameters (the batched workload).
+
+    Per field i = 0..count-1, drawn from numpy.random.default_rng(seed) in this
+    order: grid side uniform over `sides`, kappa ~ U[5, 40], alpha ~ U[1e-4, 5e-4],
+    log tau2 ~ U[log 1e-4, log 1e-2]; sigma2 = 1; theta = (kappa, alpha, tau2) free;
+    data seed 1000 + i, sketch seed 2000 + i.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        side = int(sides[int(rng.integers(0, len(sides)))])
+        kappa = float(rng.uniform(5.0, 40.0))
+        alpha = float(rng.uniform(1e-4, 5e-4))
+        tau2 = float(math.exp(rng.uniform(math.log(1e-4), math.log(1e-2))))
+        out.append(Workload(f"field{i:02d}_N{side}", 2, side, leaf, rank, oversample, kappa, alpha, tau2, 1.0,
+                            ("kappa", "alpha", "tau2"), 1000 + i, 2000 + i))
+    return out
+
+
 def _lap(dim: int, N: int) -> sp.csc_matrix:
     h = 1.0 / (N + 1)
     e = np.ones(N)
