@@ -91,6 +91,51 @@ def cpu_baseline(sample_key="2d_n4096", full_n=65536):
     }
 
 
+def batched_run(steps, count=64):
+    """The batched workload: `count` independent fields (sides 64..256, per-field theta),
+    one iteration of every field per step, streams chosen by the autotuner."""
+    import numpy as np
+    import torch
+    from paper_2303_10102_amd import hmle
+    from synth import batched_fields, sample_y, sketch_draws
+
+    fields = batched_fields(count=count)
+    t0 = time.perf_counter()
+    objs = []
+    for i, w in enumerate(fields):
+        m = hmle.Model(w.dim, w.N, w.leaf, device=0)
+        om = torch.from_numpy(sketch_draws(w)).cuda()
+        s = hmle.Sketch(m, om, w.rank, w.oversample, w.theta_full)
+        del om
+        objs.append((m, s, hmle.HMatrix(s, w.free)))
+        if i % 8 == 7:
+            print(f"[bench] batched: {i + 1}/{len(fields)} fields set up", file=sys.stderr, flush=True)
+    ys = [torch.from_numpy(sample_y(w)).cuda() for w in fields]
+    thetas = np.stack([w.theta_full for w in fields])
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    b = hmle.Batch([o[2] for o in objs])
+    tune = b.tune(thetas, ys, candidates=(1, 2, 4, 8))
+    print(f"[bench] batched: tuned {tune['batch_s']} -> {tune['best_streams']} streams", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ll, g, fim = b.iteration(thetas, ys)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    out = {
+        "workload": f"{len(fields)} fields, sides {sorted(set(w.N for w in fields))}, total n = "
+                    f"{sum(w.n for w in fields)}, rank {fields[0].rank}, theta = (kappa, alpha, tau2) per field",
+        "batch_iters_per_s": 1.0 / dt, "field_iters_per_s": len(fields) / dt, "ms_per_batch_iter": 1e3 * dt,
+        "sequential_ms": 1e3 * tune["sequential_s"], "speedup_vs_sequential": tune["sequential_s"] / dt,
+        "streams": tune["best_streams"], "tuning_ms": {str(k): 1e3 * v for k, v in tune["batch_s"].items()},
+        "steps": steps, "setup_s": setup, "all_finite": bool(np.all(np.isfinite(ll))),
+    }
+    for m, s, H in objs:
+        H.close(); s.close(); m.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +143,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="2d_n65536")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched", action="store_true",
+                    help="also run the 64-field batched workload (adds about a minute of setup)")
+    ap.add_argument("--mixed-steps", type=int, default=5,
+                    help="also time the mixed-precision policy and report both paths' errors (0 = skip)")
     ap.add_argument("--adjoint-steps", type=int, default=5,
                     help="also time the L~ + gradient iteration by reverse mode (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -181,6 +230,28 @@ def main():
             "alg_bytes_per_launch": prof["bytes"] / prof["launches"],
             "share_of_step": prof["ms"] / args.steps / ms,
         }
+    if args.mixed_steps > 0:
+        # the mixed-precision policy on the same workload, and both paths' error against
+        # the exact closed form of the model (spectral oracle)
+        from oracle.spectral import spectral_quantities
+        ex = spectral_quantities(w.dim, w.N, w.theta_full, y.cpu().numpy(), w.free)
+        H.set_precision("mixed32")
+        llm, gm, fm = H.iteration(theta, y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.mixed_steps):
+            llm, gm, fm = H.iteration(theta, y)
+        torch.cuda.synchronize()
+        dm = (time.perf_counter() - t0) / args.mixed_steps
+        H.set_precision("fp64")
+        H.iteration(theta, y)
+        d = np.sqrt(np.diag(ex["fim"]))
+        err = lambda l_, g_, f_: {"eps_L": abs(l_ - ex["loglik"]) / abs(ex["loglik"]),
+                                  "grad_max_err_in_sd": float(np.max(np.abs(g_ - ex["grad_nll"]) / d)),
+                                  "fim_max_err_corr": float(np.max(np.abs(f_ - ex["fim"]) / np.outer(d, d)))}
+        rec["mixed32"] = {"ms_per_iter": 1e3 * dm, "speedup_vs_fp64": ms / (1e3 * dm),
+                          "steps": args.mixed_steps, "error_fp64_vs_exact": err(ll, g, fim),
+                          "error_mixed_vs_exact": err(llm, gm, fm)}
     if args.adjoint_steps > 0:
         # L~ and gradient only, by the adjoint (no derivative matrices, no Fisher)
         H.loglik_grad_adjoint(theta, y)
@@ -194,6 +265,11 @@ def main():
                                       "ms_per_iter": 1e3 * da / args.adjoint_steps,
                                       "steps": args.adjoint_steps,
                                       "grad_nll": [float(v) for v in ga]}
+    if args.batched:
+        del H, s, m
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        rec["batched"] = batched_run(max(1, args.steps // 2))
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline()

@@ -140,6 +140,16 @@ hm_status hm_iteration(hm_H* H, const double* theta_full, const double* y, doubl
 hm_status hm_iteration_batched(int nf, hm_H* const* hs, const double* thetas, const double* const* ys,
                                double* loglik, double* grad, double* fim);
 
+/* Precision policy of H (the paper computes in double; this is a reading of where
+ * lower precision may enter).  0 = FP64 throughout (default).  1 = mixed: the panel
+ * products of the coarser-level subtraction, of the Woodbury panel updates, of the
+ * solve sweep and of the trace / Fisher terms run as FP32 MFMA with FP32
+ * accumulation (operands rounded from the FP64 storage); the K-apply, QR and Alg. 2,
+ * leaf Cholesky and inverse, per-node factors, the log-determinant sum, the solve's
+ * refinement residuals (FP64 H-matvec, two steps) and every scalar reduction stay
+ * FP64.  Invalidates the current factors (state returns to empty). */
+hm_status hm_H_set_precision(hm_H* H, int precision);
+
 /* L~ and the NLL gradient for the free parameters by reverse mode (adjoint):
  * builds K~(theta) only (no derivative matrices), factors it, and runs the
  * construction backwards with the sketches held fixed (Sec. 3.3), so grad is the

@@ -33,6 +33,7 @@ struct HState {
   double theta[4] = {0, 0, 0, 0};
   int state = 0;               // 0 empty, 1 built, 2 factored, 3 parameters prepared
   bool have_deriv = false;     // K~_j of the real parameters built at theta (hm_build, not the adjoint)
+  int precision = 0;           // 0 FP64; 1 mixed: FP32 MFMA panel products where the policy allows
   int kc = 0;
   PanelSet ps;                 // F and the real panel tangents
   double* D = nullptr;
@@ -117,16 +118,20 @@ static hm_status permute(Model* m, const double* in, double* out, int to_tree) {
   return HM_OK;
 }
 
-// z = K~^{-1} ytree with one refinement step against the H-matvec residual
+// z = K~^{-1} ytree with refinement steps against the FP64 H-matvec residual
+// (one step; two when the solve sweep runs with FP32 panels)
 static hm_status solve_refined(HState* h) {
   Model* m = h->m;
   const int n = m->n;
   HM_CHECK(hsolve(h->f, h->ytree, h->z));
-  HM_HIP(hipMemcpyAsync(h->r, h->ytree, n * sizeof(double), hipMemcpyDeviceToDevice, m->stream));
-  HM_CHECK(hmatvec(h->f, h->D, h->ps.F, nullptr, h->z, 1, h->r, -1.0, 1.0));   // r = y - K~ z
-  HM_CHECK(hsolve(h->f, h->r, h->v));
-  hipLaunchKernelGGL(k_add, dim3(ceil_div(n, 256)), dim3(256), 0, m->stream, h->z, h->v, n);
-  HM_LAUNCH_CHECK();
+  const int steps = m->mixed ? 2 : 1;
+  for (int it = 0; it < steps; ++it) {
+    HM_HIP(hipMemcpyAsync(h->r, h->ytree, n * sizeof(double), hipMemcpyDeviceToDevice, m->stream));
+    HM_CHECK(hmatvec(h->f, h->D, h->ps.F, nullptr, h->z, 1, h->r, -1.0, 1.0));   // r = y - K~ z (FP64)
+    HM_CHECK(hsolve(h->f, h->r, h->v));
+    hipLaunchKernelGGL(k_add, dim3(ceil_div(n, 256)), dim3(256), 0, m->stream, h->z, h->v, n);
+    HM_LAUNCH_CHECK();
+  }
   return HM_OK;
 }
 
@@ -194,6 +199,7 @@ static hm_status sync_check(HState* h, bool factored) {
 }
 
 static hm_status build_enqueue(HState* h, const double* theta_full, bool deriv) {
+  h->m->mixed = h->precision;
   HM_CHECK(check_theta(theta_full));
   Model* m = h->m;
   h->state = 0;
@@ -213,6 +219,7 @@ static hm_status build_enqueue(HState* h, const double* theta_full, bool deriv) 
 }
 
 static hm_status factor_enqueue(HState* h) {
+  h->m->mixed = h->precision;
   Model* m = h->m;
   HM_CHECK(factorize(h->f));
   // log|K~| = sum of leaf and node parts
@@ -223,6 +230,7 @@ static hm_status factor_enqueue(HState* h) {
 }
 
 static hm_status loglik_enqueue(HState* h, const double* y, bool want_grad) {
+  h->m->mixed = h->precision;
   Model* m = h->m;
   const int n = m->n;
   HM_CHECK(permute(m, y, h->ytree, 1));
@@ -270,6 +278,7 @@ static hm_status loglik_collect(HState* h, double* loglik, double* grad) {
 }
 
 static hm_status fisher_enqueue(HState* h) {
+  h->m->mixed = h->precision;
   Model* m = h->m;
   const int p = h->p;
   HM_CHECK(prepare_params(h));
@@ -753,6 +762,7 @@ hm_status hm_solve(hm_H* hh, const double* y, double* x) {
     return HM_E_STATE;
   }
   Model* m = h->m;
+  m->mixed = h->precision;
   HM_CHECK(permute(m, y, h->ytree, 1));
   HM_CHECK(solve_refined(h));
   HM_CHECK(permute(m, h->z, x, 0));
@@ -847,6 +857,17 @@ hm_status hm_iteration_batched(int nf, hm_H* const* hs, const double* thetas, co
   }
   if (first != HM_OK) set_error(msg);
   return first;
+}
+
+hm_status hm_H_set_precision(hm_H* hh, int precision) {
+  if (!hh || precision < 0 || precision > 1) {
+    set_error("precision must be 0 (FP64) or 1 (mixed FP32 panel products)");
+    return HM_E_INVAL;
+  }
+  hh->h.precision = precision;
+  hh->h.state = 0;   // factors of the other precision are not reused
+  hh->h.have_deriv = false;
+  return HM_OK;
 }
 
 hm_status hm_loglik_grad_adjoint(hm_H* hh, const double* theta_full, const double* y, double* loglik,

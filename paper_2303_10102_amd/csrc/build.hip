@@ -111,6 +111,7 @@ static hm_status mask_cols(Model* m, double* Y, int w, int l, const int* kblk, i
 hm_status subtract_coarser(Model* m, const PanelSet& ps, int l, const double* X, int w, LeafSel xsel,
                            LeafSel ysel, double* Y, double* const* dY, int nr, const NodeBufs& nb) {
   if (l <= 1) return HM_OK;
+  PrecScope prec(m);   // coarser-level subtraction: FP32 under the mixed policy
   const int bw = ps.bw;
   const long ts = (long)bw * w;
   ReduceJob r{ps.F, m->n, cs_block(bw), X, m->n, cs_fixed(0, w), 1, l - 1, nb.t, ts, xsel};

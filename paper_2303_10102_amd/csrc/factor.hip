@@ -50,6 +50,7 @@ hm_status factorize(FactorCtx& f) {
     HM_CHECK(tree_reduce(m, rs));
     HM_CHECK(node_lu(m, f.Sn, s2, f.Nn, 4 * s2, f.logdet_node, kc, (1 << d) - 1, 1 << d));
     if (d >= 1) {
+      PrecScope prec(m);   // Woodbury panel updates: FP32 under the mixed policy
       ReduceJob rt{f.F, n, cs_block(kc), f.G, n, cs_prefix(kc), d + 1, d + 1, f.nT, ts, sel_all()};
       HM_CHECK(tree_reduce(m, rt));
       HM_CHECK(node_apply_N(m, f.Nn, f.nT, ts, f.nU, us, kc, d * kc, d));
@@ -66,6 +67,7 @@ hm_status hsolve(FactorCtx& f, const double* x, double* z) {
   Model* m = f.m;
   const int n = m->n, kc = f.kc, levels = m->levels;
   HM_CHECK(leaf_gemm(m, f.Dinv, x, n, z, n, 1, 1.0, 0.0, 0, m->nleaves));
+  PrecScope prec(m);   // solve sweep: FP32 panels under the mixed policy (refined in FP64 by the caller)
   const long ts = kc, us = 2L * kc;
   for (int d = levels - 1; d >= 0; --d) {
     ReduceJob r{f.F, n, cs_block(kc), z, n, cs_fixed(0, 1), d + 1, d + 1, f.nT, ts, sel_all()};

@@ -78,10 +78,22 @@ struct Model {
   double* d_ident = nullptr;    // stacked identities n x nl (tree order), for the leaf pass
   double* d_red = nullptr;      // per-leaf partials of tree_reduce
   size_t red_doubles = 0;
+  // precision policy of the panel products (tree_reduce / tree_expand):
+  // mixed = 1 allows FP32 MFMA in the phases that open a PrecScope; panel_prec is
+  // the precision in effect (0 FP64, 1 FP32 operands with FP32 accumulation).
+  int mixed = 0;
+  int panel_prec = 0;
   int prof_family = PF_NONE;
   std::vector<ProfRec> prof;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
+};
+// Marks a phase whose panel products may run in FP32 when the mixed policy is on.
+struct PrecScope {
+  Model* m;
+  int saved;
+  explicit PrecScope(Model* mm) : m(mm), saved(mm->panel_prec) { m->panel_prec = m->mixed ? 1 : 0; }
+  ~PrecScope() { m->panel_prec = saved; }
 };
 // profiling helpers (no-ops unless the family is enabled)
 bool prof_on(Model* m, int family);

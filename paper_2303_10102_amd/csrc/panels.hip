@@ -147,6 +147,7 @@ struct RedArgs {
   int sel_mode, sel_depth;
 };
 
+template <int P>
 __global__ void __launch_bounds__(256) k_reduce_partial(RedArgs a) {
   __shared__ double smem[GSMEM];
   const int ndep = a.d1 - a.d0 + 1;
@@ -160,9 +161,6 @@ __global__ void __launch_bounds__(256) k_reduce_partial(RedArgs a) {
   const int ac0 = a.ac.c0(d), xc0 = a.xc.c0(d);
   RedLA la{a.A + r0 + (long)ac0 * a.lda, a.lda, m0, wa};
   RedLB lb{a.X + r0 + (long)xc0 * a.ldx, a.ldx, n0, wx};
-  TileAcc acc;
-  tile_zero(acc);
-  tile_gemm(la, lb, 0, a.nl, acc, smem);
   double* dst;
   if (d == a.levels) {
     int heap = (1 << d) - 1 + L;
@@ -170,7 +168,17 @@ __global__ void __launch_bounds__(256) k_reduce_partial(RedArgs a) {
   } else {
     dst = a.partial + ((long)L * ndep + (d - a.d0)) * a.pstride;
   }
-  tile_store(StC{dst, wa, m0, n0, wa, wx, 1.0, 0.0}, acc);
+  if constexpr (P == 1) {
+    TileAcc32 acc;
+    tile_zero(acc);
+    tile_gemm(la, lb, 0, a.nl, acc, reinterpret_cast<float*>(smem));
+    tile_store(StC{dst, wa, m0, n0, wa, wx, 1.0, 0.0}, acc);
+  } else {
+    TileAcc acc;
+    tile_zero(acc);
+    tile_gemm(la, lb, 0, a.nl, acc, smem);
+    tile_store(StC{dst, wa, m0, n0, wa, wx, 1.0, 0.0}, acc);
+  }
 }
 
 // Sum the per-leaf partials into every node of depths d0..min(d1, levels-1):
@@ -234,7 +242,10 @@ hm_status tree_reduce(Model* m, const ReduceJob& j) {
   dim3 grid(ceil_div(wa, GBM), ceil_div(wxmax, GBN), m->nleaves * ndep);
   const bool pf = prof_on(m, PF_REDUCE);
   if (pf) prof_begin(m, PF_REDUCE);
-  hipLaunchKernelGGL(k_reduce_partial, grid, dim3(GCfg::NT), 0, m->stream, a);
+  if (m->panel_prec == 1)
+    hipLaunchKernelGGL(k_reduce_partial<1>, grid, dim3(GCfg::NT), 0, m->stream, a);
+  else
+    hipLaunchKernelGGL(k_reduce_partial<0>, grid, dim3(GCfg::NT), 0, m->stream, a);
   HM_LAUNCH_CHECK();
   if (pf) {
     const double rows = (double)count_selected(m->nleaves, m->levels, j.sel) * m->nl;
@@ -300,15 +311,13 @@ struct ExpArgs {
   int sel_mode, sel_depth;
 };
 
-__global__ void __launch_bounds__(256) k_expand(ExpArgs a) {
-  __shared__ double smem[GSMEM];
+template <class ACC, class SM>
+__device__ __forceinline__ void expand_body(const ExpArgs& a, ACC& acc, SM* smem) {
   const int L = blockIdx.z;
-  if (!leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) return;
   const int m0 = blockIdx.x * GBM;
   const int j0 = a.ylo + blockIdx.y * GBN;  // absolute first column of this tile
   const long r0 = (long)L * a.nl;
   const int wk = a.ac.w0;
-  TileAcc acc;
   tile_zero(acc);
   for (int d = a.d0; d <= a.d1; ++d) {
     const int yc0 = a.yc.c0(d), wy = a.yc.w(d);
@@ -324,6 +333,19 @@ __global__ void __launch_bounds__(256) k_expand(ExpArgs a) {
   }
   ExpSt st{a.Y + r0, a.ldy, m0, j0, a.nl, a.yhi, a.alpha, a.beta};
   tile_store(st, acc);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_expand(ExpArgs a) {
+  __shared__ double smem[GSMEM];
+  if (!leaf_selected(blockIdx.z, a.levels, a.sel_mode, a.sel_depth)) return;
+  if constexpr (P == 1) {
+    TileAcc32 acc;
+    expand_body(a, acc, reinterpret_cast<float*>(smem));
+  } else {
+    TileAcc acc;
+    expand_body(a, acc, smem);
+  }
 }
 
 hm_status tree_expand(Model* m, const ExpandJob& j) {
@@ -343,7 +365,10 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
   dim3 grid(ceil_div(m->nl, GBM), ceil_div(yhi - ylo, GBN), m->nleaves);
   const bool pf = prof_on(m, PF_EXPAND);
   if (pf) prof_begin(m, PF_EXPAND);
-  hipLaunchKernelGGL(k_expand, grid, dim3(GCfg::NT), 0, m->stream, a);
+  if (m->panel_prec == 1)
+    hipLaunchKernelGGL(k_expand<1>, grid, dim3(GCfg::NT), 0, m->stream, a);
+  else
+    hipLaunchKernelGGL(k_expand<0>, grid, dim3(GCfg::NT), 0, m->stream, a);
   HM_LAUNCH_CHECK();
   if (pf) {
     const int wk = j.ac.w0;

@@ -52,6 +52,7 @@ _SIGS = {
     "hm_loglik_grad": ([_P, _P, _D, _D], _I),
     "hm_fisher": ([_P, _D], _I),
     "hm_iteration": ([_P, _D, _P, _D, _D, _D], _I),
+    "hm_H_set_precision": ([_P, _I], _I),
     "hm_iteration_batched": ([_I, C.POINTER(_P), _D, C.POINTER(_P), _D, _D, _D], _I),
     "hm_loglik_grad_adjoint": ([_P, _D, _P, _D, _D], _I),
     "hm_export": ([_P, _I, _P], _I),
@@ -198,6 +199,12 @@ class HMatrix:
         self._h, self.sketch, self.p = h, sketch, len(idx)
         self.free_idx = tuple(idx)
         self.model = sketch.model
+
+    def set_precision(self, precision):
+        """'fp64' (default) or 'mixed32' (FP32 MFMA panel products under the FP64 policy)."""
+        code = {"fp64": 0, "mixed32": 1}[precision]
+        _check("hm_H_set_precision", lib().hm_H_set_precision(self._h, code))
+        self.precision = precision
 
     def build(self, theta_full):
         _check("hm_build", lib().hm_build(self._h, _theta(theta_full)))

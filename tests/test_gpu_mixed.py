@@ -1,0 +1,49 @@
+"""GPU: the mixed-precision policy (FP32 MFMA panel products, FP64 elsewhere).
+
+Accuracy is judged against the exact closed form (oracle.spectral) with the
+acceptance rule for the mixed path: each metric's error is at most twice the FP64
+H-path's error, or below a floor of 1e-8 relative for L~ and 1e-6 for the gradient
+and the Fisher matrix, whichever is larger.  Gradient errors are measured per
+component in units of sqrt(I_jj) and Fisher errors in correlation units
+I_ij / sqrt(I_ii I_jj) (the entries span twelve orders of magnitude).
+"""
+import numpy as np
+import pytest
+
+from tests._cases import CASES, gpu_case
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+FLOOR = {"L": 1e-8, "g": 1e-6, "I": 1e-6}
+
+
+def _metrics(ll, g, fim, ex):
+    d = np.sqrt(np.diag(ex["fim"]))
+    return {"L": abs(ll - ex["loglik"]) / abs(ex["loglik"]),
+            "g": float(np.max(np.abs(g - ex["grad_nll"]) / d)),
+            "I": float(np.max(np.abs(fim - ex["fim"]) / np.outer(d, d)))}
+
+
+@pytest.mark.parametrize("key", ["1d_n1024", "2d_n4096", "2d_n65536"])
+def test_mixed_accuracy(key):
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from oracle.spectral import spectral_quantities
+    from synth import WORKLOADS, sample_y
+    w = CASES.get(key) or WORKLOADS[key]
+    print(f"\n[mixed {key}]", flush=True)
+    _, m, s, H = gpu_case(w)
+    y = sample_y(w)
+    yd = torch.from_numpy(y).cuda()
+    ex = spectral_quantities(w.dim, w.N, w.theta_full, y, w.free)
+    res = {}
+    for prec in ("fp64", "mixed32"):
+        H.set_precision(prec)
+        ll, g, fim = H.iteration(w.theta_full, yd)
+        res[prec] = _metrics(ll, g, fim, ex)
+        print(prec, res[prec])
+        assert np.allclose(fim, fim.T, rtol=1e-10, atol=0)
+    for k in ("L", "g", "I"):
+        assert res["mixed32"][k] <= max(2.0 * res["fp64"][k], FLOOR[k]), k
+    H.close(); s.close(); m.close()
