@@ -225,7 +225,7 @@ def main():
         rec["roofline"] = {
             "bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-            "kernel": "hm::k_expand", "launches_per_step": prof["launches"] / args.steps,
+            "kernel": "hm::k_expand_direct", "launches_per_step": prof["launches"] / args.steps,
             "avg_launch_us": 1e6 * avg_s, "alg_flops_per_launch": per_launch_flops,
             "alg_bytes_per_launch": prof["bytes"] / prof["launches"],
             "share_of_step": prof["ms"] / args.steps / ms,

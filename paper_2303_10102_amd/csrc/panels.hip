@@ -181,9 +181,108 @@ __global__ void __launch_bounds__(256) k_reduce_partial(RedArgs a) {
   }
 }
 
+// FP64 reduce with both tall operands fed straight into the matrix cores.  For
+// out = A^T X the MFMA's k index runs over rows; lane l of k-group l/16 takes the
+// four consecutive rows 4 (l/16) .. 4 (l/16) + 3 of a 16-row group, one per
+// MFMA step, so each lane reads 32 contiguous bytes of one column and a 16-lane
+// column group covers 128 contiguous bytes.  The output tile is MB x NB blocks of
+// 16 x 16 (sized to the real widths, not padded to 64).  Two wavefronts split the
+// leaf's rows and combine through LDS.
+template <int MB, int NB>
+__global__ void __launch_bounds__(128) k_reduce_direct(RedArgs a) {
+  __shared__ double red[MB * NB * 4 * 64];
+  const int ndep = a.d1 - a.d0 + 1;
+  const int L = blockIdx.z / ndep;
+  const int d = a.d0 + blockIdx.z % ndep;
+  if (!leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) return;
+  const int wa = a.ac.w0, wx = a.xc.w(d);
+  const int m0 = blockIdx.x * (16 * MB), n0 = blockIdx.y * (16 * NB);
+  if (m0 >= wa || n0 >= wx) return;
+  const long r0 = (long)L * a.nl;
+  const double* Ab = a.A + r0 + (long)(a.ac.c0(d) + m0) * a.lda;
+  const double* Xb = a.X + r0 + (long)(a.xc.c0(d) + n0) * a.ldx;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int hrows = ((a.nl + 31) / 32) * 16;   // rows per wavefront, a multiple of 16
+  const int rbeg = wave * hrows, rend = min(a.nl, rbeg + hrows);
+  hm_v4d acc[MB][NB];
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = hm_v4d{0.0, 0.0, 0.0, 0.0};
+  const double* Ac[MB];
+  const double* Xc[NB];
+  bool aok[MB], xok[NB];
+#pragma unroll
+  for (int i = 0; i < MB; ++i) {
+    aok[i] = m0 + 16 * i + li < wa;
+    Ac[i] = Ab + (long)(16 * i + li) * a.lda;
+  }
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    xok[j] = n0 + 16 * j + li < wx;
+    Xc[j] = Xb + (long)(16 * j + li) * a.ldx;
+  }
+  for (int g = rbeg; g < rend; g += 16) {
+    const int rr = g + 4 * lk;
+    double av[MB][4], xv[NB][4];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) av[i][q] = (aok[i] && rr + q < rend) ? Ac[i][rr + q] : 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xv[j][q] = (xok[j] && rr + q < rend) ? Xc[j][rr + q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][q], xv[j][q], acc[i][j], 0, 0, 0);
+  }
+  if (wave == 1) {
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[((i * NB + j) * 4 + v) * 64 + lane] = acc[i][j][v];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  double* dst;
+  if (d == a.levels) {
+    dst = a.out + ((1 << d) - 1 + L) * a.out_stride;
+  } else {
+    dst = a.partial + ((long)L * ndep + (d - a.d0)) * a.pstride;
+  }
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int mm = m0 + 16 * i + 4 * v + lk, nn = n0 + 16 * j + li;
+        if (mm < wa && nn < wx) dst[mm + (long)nn * wa] = acc[i][j][v] + red[((i * NB + j) * 4 + v) * 64 + lane];
+      }
+}
+
+template <int MB>
+static void launch_reduce_direct(Model* m, int nb, dim3 grid, const RedArgs& a) {
+  if (nb == 1) hipLaunchKernelGGL((k_reduce_direct<MB, 1>), grid, dim3(128), 0, m->stream, a);
+  else if (nb == 2) hipLaunchKernelGGL((k_reduce_direct<MB, 2>), grid, dim3(128), 0, m->stream, a);
+  else hipLaunchKernelGGL((k_reduce_direct<MB, 3>), grid, dim3(128), 0, m->stream, a);
+}
+
 // Sum the per-leaf partials into every node of depths d0..min(d1, levels-1):
-// grid.y enumerates those nodes (depth-major), grid.x element chunks.
-__global__ void k_reduce_tree(RedArgs a, int dlast) {
+// grid.y enumerates those nodes (depth-major), grid.x element chunks of 64.  The
+// four wavefronts of a block split the node's leaves (each issuing eight
+// independent loads per step), then combine through LDS; partials of unselected
+// leaves are never read.
+__global__ void __launch_bounds__(256) k_reduce_tree(RedArgs a, int dlast) {
+  __shared__ double red[4][64];
   const int ndep = a.d1 - a.d0 + 1;
   // node enumeration: depth d contributes 2^d nodes, starting at depth d0
   int t = blockIdx.y;
@@ -195,17 +294,76 @@ __global__ void k_reduce_tree(RedArgs a, int dlast) {
   const int idx = t;
   const int wa = a.ac.w0, wx = a.xc.w(d);
   const int ne = wa * wx;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ne) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  if (blockIdx.x * 64 >= ne) return;
   const int span = 1 << (a.levels - d);
   const int L0 = idx * span;
+  const long stride = (long)ndep * a.pstride;
+  const double* base = a.partial + (long)(d - a.d0) * a.pstride + e;
   double s = 0.0;
-  for (int L = L0; L < L0 + span; ++L) {
-    if (!leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) continue;
-    s += a.partial[((long)L * ndep + (d - a.d0)) * a.pstride + e];
+  if (e < ne) {
+    // wave wv takes leaves L0 + wv, L0 + wv + 4, ...
+    double acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+    int L = L0 + wv;
+    const int Lend = L0 + span;
+    for (; L + 28 < Lend; L += 32) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int Lq = L + 4 * q;
+        if (leaf_selected(Lq, a.levels, a.sel_mode, a.sel_depth)) acc[q] += base[(long)Lq * stride];
+      }
+    }
+    for (; L < Lend; L += 4)
+      if (leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) acc[0] += base[(long)L * stride];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += acc[q];
   }
-  const int heap = (1 << d) - 1 + idx;
-  a.out[heap * a.out_stride + e] = s;
+  red[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && e < ne) {
+    const int heap = (1 << d) - 1 + idx;
+    a.out[heap * a.out_stride + e] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+  }
+}
+
+// Reduce against the stacked identity S (the leaf pass): A[c]^T S[c] is the sum over
+// the leaves of c of A's leaf blocks (transposed), no product needed.  Per (leaf,
+// depth) the block is copied, through an LDS transpose when `trans`, into the same
+// partial layout the product path writes (element (i, j) at i + j * rows_out);
+// k_reduce_tree then sums the partials over each node.
+__global__ void __launch_bounds__(256) k_leaf_blocks(const double* P, int ldp, ColSpec pc, int d0, int d1,
+                                                     int levels, int nl, int w, int trans, double* out,
+                                                     long out_stride, double* partial, long pstride) {
+  __shared__ double tile[64][65];
+  const int ndep = d1 - d0 + 1;
+  const int L = blockIdx.z / ndep;
+  const int d = d0 + blockIdx.z % ndep;
+  const int j0 = blockIdx.x * 64, m0 = blockIdx.y * 64;
+  const double* src = P + (long)L * nl + (long)pc.c0(d) * ldp;
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    const int jj = e % 64, cc = e / 64;
+    const int j = j0 + jj, mm = m0 + cc;
+    tile[cc][jj] = (j < nl && mm < w) ? src[j + (long)mm * ldp] : 0.0;
+  }
+  __syncthreads();
+  double* dst = (d == levels) ? out + ((1 << d) - 1 + L) * out_stride
+                              : partial + ((long)L * ndep + (d - d0)) * pstride;
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    if (trans) {   // out block w x nl: element (mm, j) at mm + j w
+      const int cc = e % 64, jj = e / 64;
+      const int j = j0 + jj, mm = m0 + cc;
+      if (j < nl && mm < w) dst[mm + (long)j * w] = tile[cc][jj];
+    } else {       // out block nl x w: element (j, mm) at j + mm nl
+      const int jj = e % 64, cc = e / 64;
+      const int j = j0 + jj, mm = m0 + cc;
+      if (j < nl && mm < w) dst[j + (long)mm * nl] = tile[cc][jj];
+    }
+  }
 }
 
 hm_status ensure_reduce_ws(Model* m, size_t doubles) {
@@ -239,18 +397,47 @@ hm_status tree_reduce(Model* m, const ReduceJob& j) {
               std::to_string(m->red_doubles) + ")");
     return HM_E_INVAL;
   }
-  dim3 grid(ceil_div(wa, GBM), ceil_div(wxmax, GBN), m->nleaves * ndep);
   const bool pf = prof_on(m, PF_REDUCE);
   if (pf) prof_begin(m, PF_REDUCE);
-  if (m->panel_prec == 1)
+  auto is_ident = [&](const double* p, const ColSpec& c) {
+    return p == m->d_ident && c.base == 0 && c.stride == 0 && c.w0 == m->nl && c.grow == 0;
+  };
+  const bool xid = is_ident(j.X, j.xc) && j.sel.mode == 0;
+  const bool aid = is_ident(j.A, j.ac) && j.sel.mode == 0 && j.xc.grow == 0;
+  if (xid || aid) {
+    // sums of leaf blocks (no product): A[c]^T S[c] (xid) or S[c]^T X[c] (aid)
+    const double* P = xid ? j.A : j.X;
+    const int ldp = xid ? j.lda : j.ldx;
+    const ColSpec pc = xid ? j.ac : j.xc;
+    const int w = xid ? wa : j.xc.w0;
+    dim3 g(ceil_div(m->nl, 64), ceil_div(w, 64), m->nleaves * ndep);
+    hipLaunchKernelGGL(k_leaf_blocks, g, dim3(256), 0, m->stream, P, ldp, pc, j.d0, j.d1, m->levels, m->nl, w,
+                       xid ? 1 : 0, j.out, j.out_stride, m->d_red, (long)wa * wxmax);
+  } else if (m->panel_prec == 1) {
+    dim3 grid(ceil_div(wa, GBM), ceil_div(wxmax, GBN), m->nleaves * ndep);
     hipLaunchKernelGGL(k_reduce_partial<1>, grid, dim3(GCfg::NT), 0, m->stream, a);
-  else
-    hipLaunchKernelGGL(k_reduce_partial<0>, grid, dim3(GCfg::NT), 0, m->stream, a);
+  } else {
+    // output tile sized to the widths: MB x NB blocks of 16
+    auto blocks = [](int w) {   // up to 3 x 3 blocks per tile keeps two wavefronts per SIMD
+      const int nbk = ceil_div(w, 16);
+      if (nbk <= 3) return nbk;
+      return (nbk % 3 == 0) ? 3 : (nbk % 2 == 0 ? 2 : 3);
+    };
+    const int mb = blocks(wa), nb = blocks(wxmax);
+    dim3 grid(ceil_div(wa, 16 * mb), ceil_div(wxmax, 16 * nb), m->nleaves * ndep);
+    if (mb == 1) launch_reduce_direct<1>(m, nb, grid, a);
+    else if (mb == 2) launch_reduce_direct<2>(m, nb, grid, a);
+    else launch_reduce_direct<3>(m, nb, grid, a);
+  }
   HM_LAUNCH_CHECK();
   if (pf) {
     const double rows = (double)count_selected(m->nleaves, m->levels, j.sel) * m->nl;
     double fl = 0.0, by = 0.0;
     for (int d = j.d0; d <= j.d1; ++d) {
+      if (xid || aid) {   // a copy of the non-identity operand's leaf blocks
+        by += 16.0 * rows * (xid ? wa : j.xc.w(d));
+        continue;
+      }
       fl += 2.0 * rows * wa * j.xc.w(d);
       by += 8.0 * (rows * wa + rows * j.xc.w(d) + (rows / m->nl) * wa * j.xc.w(d));
     }
@@ -264,7 +451,7 @@ hm_status tree_reduce(Model* m, const ReduceJob& j) {
       nemax = std::max(nemax, wa * j.xc.w(d));
     }
     if (nemax > 0) {
-      dim3 g2(ceil_div(nemax, 256), nodes);
+      dim3 g2(ceil_div(nemax, 64), nodes);
       hipLaunchKernelGGL(k_reduce_tree, g2, dim3(256), 0, m->stream, a, dlast);
       HM_LAUNCH_CHECK();
     }
@@ -348,6 +535,136 @@ __global__ void __launch_bounds__(256) k_expand(ExpArgs a) {
   }
 }
 
+// FP64 expand with the tall operand fed straight into the matrix cores.  The
+// product is formed transposed, D = T^T A^T (16 output columns x 16 rows per
+// MFMA block), so that
+//   * the B operand of v_mfma_f64_16x16x4 (lane l: row l%16, k l/16) is read from
+//     the column-major panel without LDS: each group of 16 lanes reads 128
+//     contiguous bytes of one column;
+//   * the small per-node block T goes through LDS, once per workgroup and unit;
+//   * the accumulator (lane l, element v: output column 4v + l/16, row l%16) is
+//     stored as 128-byte runs of one output column.
+// Work is a sequence of units (segment d, 32-deep k chunk).  The panel and T
+// loads of the next unit are issued before the current unit is computed, and the
+// workgroup barriers wait on LDS traffic only, so those loads stay in flight.
+// Workgroup: 4 wavefronts x 16 rows = 64 rows of one leaf, 64 output columns.
+constexpr int EXK = 32;   // k chunk of one unit
+constexpr int EXT = EXK * 64 / 256;   // T elements staged per thread and unit
+
+__device__ __forceinline__ void lds_barrier() {
+  // LDS stores of this wavefront complete, then the workgroup barrier; global loads
+  // in flight are not waited for
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+__device__ __forceinline__ bool exp_seg_active(const ExpArgs& a, int d, int j0) {
+  const int yc0 = a.yc.c0(d), wy = a.yc.w(d);
+  return wy > 0 && j0 < yc0 + wy && j0 + 64 > yc0;
+}
+// next unit after (d, k0); d < d0 means "before the first"
+__device__ __forceinline__ bool exp_next_unit(const ExpArgs& a, int j0, int& d, int& k0) {
+  if (d >= a.d0) {
+    k0 += EXK;
+    if (k0 < a.ac.w0) return true;
+  }
+  for (++d; d <= a.d1; ++d)
+    if (exp_seg_active(a, d, j0)) {
+      k0 = 0;
+      return true;
+    }
+  return false;
+}
+__device__ __forceinline__ const double* exp_T(const ExpArgs& a, int L, int d) {
+  const int c = L >> (a.levels - d);
+  const int heap = (1 << d) - 1 + c;
+  int sel = heap, roff = 0;
+  if (a.tmode == 1) sel = (heap & 1) ? heap + 1 : heap - 1;
+  else if (a.tmode == 2) { sel = (heap - 1) >> 1; roff = (c & 1) ? a.half_off : 0; }
+  return a.T + sel * a.t_stride + roff;
+}
+
+template <int NB>
+__global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
+  __shared__ double Ts[EXK * 65];
+  const int L = blockIdx.z;
+  if (!leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) return;
+  const int m0 = blockIdx.x * 64;
+  const int j0 = a.ylo + blockIdx.y * 64;
+  const long r0 = (long)L * a.nl;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int row = m0 + wave * 16 + li;
+  const bool rok = row < a.nl;
+  const int wk = a.ac.w0;
+  const int ldt = a.ldt;
+  hm_v4d acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = hm_v4d{0.0, 0.0, 0.0, 0.0};
+
+  double ac[EXK / 4], an[EXK / 4], tr[EXT];
+  auto load_A = [&](int d, int k0, double (&av)[EXK / 4]) {
+    const double* Ar = a.A + r0 + row + (long)a.ac.c0(d) * a.lda;
+#pragma unroll
+    for (int s = 0; s < EXK / 4; ++s) {
+      const int k = k0 + 4 * s + lk;
+      av[s] = (rok && k < wk) ? Ar[(long)k * a.lda] : 0.0;
+    }
+  };
+
+  int d = a.d0 - 1, k0 = 0;
+  bool have = exp_next_unit(a, j0, d, k0);
+  if (have) load_A(d, k0, ac);
+  while (have) {
+    // T block of this unit (small, cached): loads issued before the next unit's panel loads
+    const double* T = exp_T(a, L, d);
+    const int cbase = j0 - a.yc.c0(d), wy = a.yc.w(d);
+    {
+      const int kk = tid % EXK, cc0 = tid / EXK;
+      const bool kok = k0 + kk < wk;
+      const double* Tk = T + (k0 + kk);
+#pragma unroll
+      for (int q = 0; q < EXT; ++q) {
+        const int col = cbase + cc0 + (256 / EXK) * q;
+        tr[q] = (kok && col >= 0 && col < wy) ? Tk[(long)col * ldt] : 0.0;
+      }
+    }
+    int dn = d, kn0 = k0;
+    const bool more = exp_next_unit(a, j0, dn, kn0);
+    if (more) load_A(dn, kn0, an);
+    const int kn = min(EXK, wk - k0);
+    lds_barrier();   // previous unit's reads of Ts are done
+#pragma unroll
+    for (int q = 0; q < EXT; ++q) Ts[(tid % EXK) * 65 + tid / EXK + (256 / EXK) * q] = tr[q];
+    lds_barrier();
+#pragma unroll
+    for (int s = 0; s < EXK / 4; ++s) {
+      if (4 * s < kn) {
+        const int kk = 4 * s + lk;
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ts[kk * 65 + b * 16 + li], ac[s], acc[b], 0, 0, 0);
+      }
+    }
+    if (!more) break;
+#pragma unroll
+    for (int s = 0; s < EXK / 4; ++s) ac[s] = an[s];
+    d = dn;
+    k0 = kn0;
+  }
+  if (!rok) return;
+  double* Yr = a.Y + r0 + row;
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int col = j0 + b * 16 + 4 * v + lk;
+      if (col < a.yhi) {
+        double* q = Yr + (long)col * a.ldy;
+        *q = (a.beta == 0.0) ? a.alpha * acc[b][v] : a.alpha * acc[b][v] + a.beta * (*q);
+      }
+    }
+}
+
 hm_status tree_expand(Model* m, const ExpandJob& j) {
   if (j.d0 < 1 || j.d1 > m->levels || j.d0 > j.d1) {
     set_error("tree_expand: bad depth range");
@@ -365,10 +682,19 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
   dim3 grid(ceil_div(m->nl, GBM), ceil_div(yhi - ylo, GBN), m->nleaves);
   const bool pf = prof_on(m, PF_EXPAND);
   if (pf) prof_begin(m, PF_EXPAND);
+  // output blocks of 16 columns a tile needs (a launch narrower than 64 columns
+  // runs fewer MFMA blocks)
+  const int nb = (yhi - ylo >= 64) ? 4 : ceil_div(yhi - ylo, 16);
   if (m->panel_prec == 1)
     hipLaunchKernelGGL(k_expand<1>, grid, dim3(GCfg::NT), 0, m->stream, a);
+  else if (nb == 1)
+    hipLaunchKernelGGL(k_expand_direct<1>, grid, dim3(GCfg::NT), 0, m->stream, a);
+  else if (nb == 2)
+    hipLaunchKernelGGL(k_expand_direct<2>, grid, dim3(GCfg::NT), 0, m->stream, a);
+  else if (nb == 3)
+    hipLaunchKernelGGL(k_expand_direct<3>, grid, dim3(GCfg::NT), 0, m->stream, a);
   else
-    hipLaunchKernelGGL(k_expand<0>, grid, dim3(GCfg::NT), 0, m->stream, a);
+    hipLaunchKernelGGL(k_expand_direct<4>, grid, dim3(GCfg::NT), 0, m->stream, a);
   HM_LAUNCH_CHECK();
   if (pf) {
     const int wk = j.ac.w0;
