@@ -43,6 +43,7 @@ struct HState {
   LevelBufs lb;
   NodeBufs nb;
   AdjBufs adj;
+  double* GtG = nullptr;       // G_c^T G_c per node (shared by the scale parameters)
   double* node_t = nullptr;    // per internal node (2kc)^2 scratch
   double* node_s = nullptr;    // per node kc^2 scratch
   double* ytree = nullptr;
@@ -159,7 +160,12 @@ static hm_status prepare_params(HState* h) {
     ReduceJob r{h->ps.F, n, cs_block(kc), h->f.G, n, cs_prefix(kc), 2, levels, h->f.nT, ts, sel_all()};
     HM_CHECK(tree_reduce(m, r));
   }
-  for (int q = 0; q < h->p; ++q) HM_CHECK(param_prepare(h->f, h->pb[q], h->theta, h->f.nT));
+  if (h->GtG) {
+    const long s2 = (long)kc * kc;
+    ReduceJob g{h->f.G, n, cs_block(kc), h->f.G, n, cs_block(kc), 1, levels, h->GtG, s2, sel_all()};
+    HM_CHECK(tree_reduce(m, g));
+  }
+  for (int q = 0; q < h->p; ++q) HM_CHECK(param_prepare(h->f, h->pb[q], h->theta, h->f.nT, h->GtG));
   HM_CHECK(node_prep(h->f));
   h->state = 3;
   return HM_OK;
@@ -282,8 +288,19 @@ static hm_status fisher_enqueue(HState* h) {
   Model* m = h->m;
   const int p = h->p;
   HM_CHECK(prepare_params(h));
-  for (int q = 0; q < p; ++q) {
-    HM_CHECK(tangent_sweep(h->f, h->pb[q]));
+  // tau2 before sigma2: sigma2's tangent sweep is a combination of tau2's
+  int qt = -1;
+  for (int q = 0; q < p; ++q)
+    if (h->pb[q].kind == 2) qt = q;
+  int order[4], no = 0;
+  for (int q = 0; q < p; ++q)
+    if (h->pb[q].kind != 3) order[no++] = q;
+  for (int q = 0; q < p; ++q)
+    if (h->pb[q].kind == 3) order[no++] = q;
+  for (int i = 0; i < p; ++i) {
+    const int q = order[i];
+    if (h->pb[q].kind == 3 && qt >= 0) HM_CHECK(scale_sweep(h->f, h->pb[q], h->pb[qt], h->theta));
+    else HM_CHECK(tangent_sweep(h->f, h->pb[q]));
     HM_CHECK(node_psi(h->f, h->pb[q], h->node_s));
     HM_CHECK(node_lam(h->f, h->pb[q], h->node_t, h->node_s));
     HM_CHECK(panel_products(h->f, h->pb[q]));
@@ -632,7 +649,10 @@ hm_status hm_H_create(hm_sketch* hs, int p, const int* free_idx, hm_H** out) {
   AL(f.Ncc, nodes * s2);
   AL(f.Nx, nodes * s2);
   AL(f.tmp_panel, pset);
-  // per-parameter buffers
+  // per-parameter buffers (the scale parameters alias what they share with K~)
+  bool any_scale = false;
+  for (int q = 0; q < p; ++q) any_scale |= (h->pb[q].kind >= 2);
+  if (any_scale) AL(h->GtG, nodes * s2);
   for (int q = 0; q < p; ++q) {
     ParamBufs& pb = h->pb[q];
     if (pb.kind <= 1) {
@@ -642,14 +662,21 @@ hm_status hm_H_create(hm_sketch* hs, int p, const int* free_idx, hm_H** out) {
       AL(pb.dF, pset);
       AL(pb.dD, lset);
     }
-    AL(pb.Xi, pset);
+    if (pb.kind == 2) {          // Xi = G, Y = Yt = Dinv, Psi = G^T G
+      pb.Xi = f.G;
+      pb.Y = pb.Yt = f.Dinv;
+      pb.Psi = h->GtG;
+    } else {
+      AL(pb.Xi, pset);
+      AL(pb.Y, lset);
+      if (pb.kind == 3) pb.Yt = pb.Y;   // Dinv dD = dD Dinv for dD = (D - tau2 I)/sigma2
+      else AL(pb.Yt, lset);
+      AL(pb.Psi, nodes * s2);
+    }
     AL(pb.dG, pset);
     AL(pb.Gh, pset);
     AL(pb.Hh, pset);
-    AL(pb.Y, lset);
-    AL(pb.Yt, lset);
     AL(pb.E, nodes * s2);
-    AL(pb.Psi, nodes * s2);
     AL(pb.W, nodes * s2);
     AL(pb.Vt, nodes * s2);
     AL(pb.PsiP, nint * m2);

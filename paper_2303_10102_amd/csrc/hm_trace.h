@@ -7,7 +7,9 @@ namespace hm {
 hm_status dots(Model* m, const double* const* A, int na, const double* const* B, int nb, long len, double* out,
                double* partial);
 hm_status sum_scalar(Model* m, const double* x, long len, int diag_nl, double* out, double* partial);
-hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double theta[4], const double* tF_prefix);
+hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double theta[4], const double* tF_prefix,
+                        const double* GtG);
+hm_status scale_sweep(FactorCtx& f, ParamBufs& ps, const ParamBufs& pt, const double theta[4]);
 hm_status tangent_sweep(FactorCtx& f, ParamBufs& pb);
 hm_status node_prep(FactorCtx& f);
 hm_status node_psi(FactorCtx& f, ParamBufs& pb, double* xtmp);

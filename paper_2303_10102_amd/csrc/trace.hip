@@ -263,34 +263,47 @@ hm_status node_lam(FactorCtx& f, ParamBufs& pb, double* tbuf, double* dsbuf) {
 // ---------------------------------------------------------------------------
 // per-parameter work
 // ---------------------------------------------------------------------------
-hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double theta[4], const double* tF_prefix) {
+hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double theta[4], const double* tF_prefix,
+                        const double* GtG) {
   Model* m = f.m;
   PrecScope prec(m);   // trace panels: FP32 under the mixed policy
   const int n = m->n, kc = f.kc, levels = m->levels;
   const long pcnt = (long)n * levels * kc;
   const long s2 = (long)kc * kc;
+  const long ncnt = ((2L << levels) - 2) * s2;   // per-node arrays, non-root nodes (from offset s2)
   const double tau2 = theta[2], sigma2 = theta[3];
-  if (pb.kind == 2) {  // K~_tau2 = I: no panels, identity leaves, Xi = G
+  if (pb.kind == 2) {
+    // K~_tau2 = I: no panels, identity leaves.  Xi = G, Y = Yt = Dinv and Psi = G^T G are
+    // aliases set at creation; E = dF^T G = 0.
     HM_CHECK(fill(m, pb.dF, pcnt, 0.0));
     HM_CHECK(leaf_affine(m, pb.dD, nullptr, 0.0, 1.0));
-    HM_CHECK(lin2(m, pb.Xi, f.G, nullptr, pcnt, 1.0, 0.0));
-  } else if (pb.kind == 3) {  // K~_sigma2 = (K~ - tau2 I)/sigma2: dF = F/(2 sigma2), Xi = (F - tau2 G)/sigma2
+    HM_CHECK(fill(m, pb.E + s2, ncnt, 0.0));
+    return HM_OK;
+  }
+  if (pb.kind == 3) {
+    // K~_sigma2 = (K~ - tau2 I)/sigma2: dF = F/(2 sigma2), dD = (D - tau2 I)/sigma2,
+    // Xi = (F - tau2 G)/sigma2, Y = Yt = Dinv dD = (I - tau2 Dinv)/sigma2 (Yt aliases Y),
+    // E = dF^T G = S/(2 sigma2), Psi = G^T Xi = (S - tau2 G^T G)/sigma2  (S = F^T G, symmetric)
     HM_CHECK(lin2(m, pb.dF, f.F, nullptr, pcnt, 0.5 / sigma2, 0.0));
     HM_CHECK(leaf_affine(m, pb.dD, f.D, 1.0 / sigma2, -tau2 / sigma2));
     HM_CHECK(lin2(m, pb.Xi, f.F, f.G, pcnt, 1.0 / sigma2, -tau2 / sigma2));
-  } else {  // Xi_c = B_cc G_c: leaves plus every sibling pair strictly inside c
-    HM_CHECK(leaf_gemm(m, pb.dD, f.G, n, pb.Xi, n, levels * kc, 1.0, 0.0, 0, m->nleaves));
-    if (levels >= 2) {
-      const long ts = (long)kc * (levels - 1) * kc;
-      ReduceJob rd{pb.dF, n, cs_block(kc), f.G, n, cs_prefix(kc), 2, levels, f.nU, ts, sel_all()};
-      HM_CHECK(tree_reduce(m, rd));
-      ExpandJob e1{pb.dF, n, cs_block(kc), pb.Xi, n, cs_prefix(kc), tF_prefix, ts, kc, 1, 0, 2, levels, 1.0, 1.0,
-                   sel_all()};
-      HM_CHECK(tree_expand(m, e1));
-      ExpandJob e2{f.F, n, cs_block(kc), pb.Xi, n, cs_prefix(kc), f.nU, ts, kc, 1, 0, 2, levels, 1.0, 1.0,
-                   sel_all()};
-      HM_CHECK(tree_expand(m, e2));
-    }
+    HM_CHECK(leaf_affine(m, pb.Y, f.Dinv, -tau2 / sigma2, 1.0 / sigma2));
+    HM_CHECK(lin2(m, pb.E + s2, f.Sn + s2, nullptr, ncnt, 0.5 / sigma2, 0.0));
+    HM_CHECK(lin2(m, pb.Psi + s2, f.Sn + s2, GtG + s2, ncnt, 1.0 / sigma2, -tau2 / sigma2));
+    return HM_OK;
+  }
+  // Xi_c = B_cc G_c: leaves plus every sibling pair strictly inside c
+  HM_CHECK(leaf_gemm(m, pb.dD, f.G, n, pb.Xi, n, levels * kc, 1.0, 0.0, 0, m->nleaves));
+  if (levels >= 2) {
+    const long ts = (long)kc * (levels - 1) * kc;
+    ReduceJob rd{pb.dF, n, cs_block(kc), f.G, n, cs_prefix(kc), 2, levels, f.nU, ts, sel_all()};
+    HM_CHECK(tree_reduce(m, rd));
+    ExpandJob e1{pb.dF, n, cs_block(kc), pb.Xi, n, cs_prefix(kc), tF_prefix, ts, kc, 1, 0, 2, levels, 1.0, 1.0,
+                 sel_all()};
+    HM_CHECK(tree_expand(m, e1));
+    ExpandJob e2{f.F, n, cs_block(kc), pb.Xi, n, cs_prefix(kc), f.nU, ts, kc, 1, 0, 2, levels, 1.0, 1.0,
+                 sel_all()};
+    HM_CHECK(tree_expand(m, e2));
   }
   // leaf products Y = Dinv dD, Yt = dD Dinv
   const int nl = m->nl;
@@ -304,6 +317,21 @@ hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double theta[4], cons
   HM_CHECK(tree_reduce(m, re));
   ReduceJob rp{f.G, n, cs_block(kc), pb.Xi, n, cs_block(kc), 1, levels, pb.Psi, s2, sel_all()};
   HM_CHECK(tree_reduce(m, rp));
+  return HM_OK;
+}
+
+// sigma2 from tau2: with H_c = K~_c^{-1} G_c, dG_tau2 = -H and
+//   dG_sigma2 = K~_c^{-1}(F/(2 sigma2) - (F - tau2 G)/sigma2) = -G/(2 sigma2) - (tau2/sigma2) dG_tau2,
+//   W_sigma2 = dG_sigma2^T F = -S/(2 sigma2) - (tau2/sigma2) W_tau2.
+hm_status scale_sweep(FactorCtx& f, ParamBufs& ps, const ParamBufs& pt, const double theta[4]) {
+  Model* m = f.m;
+  const int n = m->n, kc = f.kc, levels = m->levels;
+  const long pcnt = (long)n * levels * kc;
+  const long s2 = (long)kc * kc;
+  const long ncnt = ((2L << levels) - 2) * s2;   // non-root nodes
+  const double tau2 = theta[2], sigma2 = theta[3];
+  HM_CHECK(lin2(m, ps.dG, f.G, pt.dG, pcnt, -0.5 / sigma2, -tau2 / sigma2));
+  HM_CHECK(lin2(m, ps.W + s2, f.Sn + s2, pt.W + s2, ncnt, -0.5 / sigma2, -tau2 / sigma2));
   return HM_OK;
 }
 

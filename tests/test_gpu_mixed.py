@@ -42,8 +42,11 @@ def test_mixed_accuracy(key):
         H.set_precision(prec)
         ll, g, fim = H.iteration(w.theta_full, yd)
         res[prec] = _metrics(ll, g, fim, ex)
-        print(prec, res[prec])
-        assert np.allclose(fim, fim.T, rtol=1e-10, atol=0)
+        d = np.sqrt(np.abs(np.diag(fim)))
+        asym = float(np.max(np.abs(fim - fim.T) / np.outer(d, d)))
+        print(prec, res[prec], "asymmetry", asym)
+        # each (i, j) is computed independently: symmetric to the path's rounding
+        assert asym <= (1e-12 if prec == "fp64" else FLOOR["I"])
     for k in ("L", "g", "I"):
         assert res["mixed32"][k] <= max(2.0 * res["fp64"][k], FLOOR[k]), k
     H.close(); s.close(); m.close()
