@@ -196,7 +196,7 @@ hm_status adjoint_sweep(Model* m, const double theta[4], const Sketch* s, const 
     // ---- pass 2: C = ((K - sum H) X_S)[right rows]
     HM_CHECK(kvjp(m, theta, XS, n, Zb, n, kc, a.wmode));
     HM_CHECK(subtract_adjoint(m, ps.F, kc, l, XS, kc, left, Zb, right, a.Fb, -1.0, nb.t, a.uT));
-    HM_CHECK(kapply(m, theta, Zb, n, kc, a.tmpK, nullptr, nullptr, n));
+    HM_CHECK(kapply_sel(m, theta, Zb, n, kc, a.tmpK, nullptr, nullptr, n, right, left));
     HM_CHECK(subtract_coarser(m, ps, l, Zb, kc, right, left, a.tmpK, nullptr, 0, nb));
     HM_CHECK(side_select(m, Fbl, a.tmpK, Qb, kc, l, s->d_k, 1));
     // ---- QR: Y_bar = (Q_bar - Q sym(Q^T Q_bar)) R^{-T} on every left child at depth l

@@ -202,7 +202,7 @@ hm_status level_step(Model* m, const double theta[4], const PanelSet& ps, int l,
   double *kap, *alp;
   // ---- pass 1: sample the column space of each block
   tangent_outputs(dY, &kap, &alp);
-  HM_CHECK(kapply(m, theta, XR, n, w, b.Y, kap, alp, n));
+  HM_CHECK(kapply_sel(m, theta, XR, n, w, b.Y, kap, alp, n, right, left));
   HM_CHECK(subtract_coarser(m, ps, l, XR, w, right, left, b.Y, nr ? dY : nullptr, nr, nb));
   HM_CHECK(mask_cols(m, b.Y, w, l, kblk, 1));
   HM_CHECK(fill(m, b.XS, (long)n * w, 0.0));
@@ -215,8 +215,9 @@ hm_status level_step(Model* m, const double theta[4], const PanelSet& ps, int l,
   // ---- pass 2: C = B^T Q on the right-children rows
   double* dZ[2] = {b.dZ[0], b.dZ[1]};
   tangent_outputs(dZ, &kap, &alp);
-  HM_CHECK(kapply(m, theta, b.XS, n, w, b.Z, kap, alp, n));
-  for (int j = 0; j < nr; ++j) HM_CHECK(kapply(m, theta, b.XdS[j], n, w, b.Zq[j], nullptr, nullptr, n));
+  HM_CHECK(kapply_sel(m, theta, b.XS, n, w, b.Z, kap, alp, n, left, right));
+  for (int j = 0; j < nr; ++j)
+    HM_CHECK(kapply_sel(m, theta, b.XdS[j], n, w, b.Zq[j], nullptr, nullptr, n, left, right));
   HM_CHECK(subtract_coarser(m, ps, l, b.XS, w, left, right, b.Z, nr ? dZ : nullptr, nr, nb));
   for (int j = 0; j < nr; ++j)
     HM_CHECK(subtract_coarser(m, ps, l, b.XdS[j], w, left, right, b.Zq[j], nullptr, 0, nb));

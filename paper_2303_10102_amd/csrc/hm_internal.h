@@ -145,6 +145,12 @@ inline ColSpec cs_prefix_incl(int bw) { return ColSpec{0, 0, bw, bw}; }    // bl
 struct LeafSel { int mode, depth; };
 inline LeafSel sel_all() { return LeafSel{0, 1}; }
 
+// K-apply for an input that vanishes outside the rows of in_sel, whose output is
+// needed only on the rows of out_sel (one side of a split, or all rows); output
+// rows outside out_sel are left unwritten.  Same result on the needed rows.
+hm_status kapply_sel(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK,
+                     double* outKap, double* outAlp, int ldo, LeafSel in_sel, LeafSel out_sel);
+
 // For every node c at depth d in [d0,d1]:  out_c = A[c rows, ac(d)]^T X[c rows, xc(d)]
 // (wa x wx(d) column-major, ld wa, stored at out + heap(c)*out_stride).  Rows of
 // unselected leaves count as zero.
