@@ -6,7 +6,9 @@
 // starts by factoring out the block-diagonal Dbar of leaf blocks (App. C, eq.
 // "factor out leaf"); its log-determinant is 2 sum log diag(chol(D_L)).
 #include <cmath>
+#include <vector>
 
+#include "hm_build.h"
 #include "hm_internal.h"
 
 namespace hm {
@@ -33,147 +35,152 @@ hm_status leaf_sym(Model* m, const double* Z, int ldz, double* D) {
 constexpr int CNB = 32;      // Cholesky block width
 constexpr int NLMAX = 512;   // largest leaf handled
 
-// In-place blocked Cholesky (lower) of W (nl x nl, column-major), one leaf per
-// workgroup.  logdet[L] = 2 sum log L_ii.  A non-positive pivot sets a flag and
-// is replaced by 1 so the kernel still completes.
-__global__ void __launch_bounds__(256) k_leaf_chol(double* W, int nl, double* logdet, int* flags) {
-  __shared__ double panel[NLMAX * CNB];  // rows jb..nl-1 of the current block column
+// Right-looking blocked Cholesky of every leaf, one block column per launch:
+// k_chol_panel factors the diagonal block and solves the rows below it (the
+// panel is held in LDS); the trailing update A22 -= L21 L21^T is a batched
+// MFMA GEMM over all leaves.  logdet[L] accumulates 2 sum log L_ii; a
+// non-positive pivot sets a flag and is replaced by 1 so the kernel completes.
+__global__ void __launch_bounds__(256) k_chol_panel(double* W, int nl, int jb, double* logdet, int* flags) {
+  __shared__ double panel[NLMAX * (CNB + 1)];   // rows jb..nl-1 of the block column
   const int L = blockIdx.x;
   double* A = W + (long)L * nl * nl;
   const int tid = threadIdx.x, nt = blockDim.x;
-  double lsum = 0.0;  // accumulated by thread 0
+  const int nb = min(CNB, nl - jb);
+  const int rows = nl - jb;
+  constexpr int LD = CNB + 1;
+  for (int e = tid; e < rows * nb; e += nt) {
+    int i = e % rows, t = e / rows;
+    panel[i * LD + t] = A[(jb + i) + (long)(jb + t) * nl];
+  }
+  __syncthreads();
+  double lsum = 0.0;
   int bad = 0;
-  for (int jb = 0; jb < nl; jb += CNB) {
-    const int nb = min(CNB, nl - jb);
-    const int rows = nl - jb;
-    // stage the block column (rows jb..nl-1, cols jb..jb+nb-1) into LDS, row-major in t
-    for (int e = tid; e < rows * nb; e += nt) {
-      int i = e % rows, t = e / rows;
-      panel[i * CNB + t] = A[(jb + i) + (long)(jb + t) * nl];
+  for (int t = 0; t < nb; ++t) {
+    if (tid == 0) {
+      double d = panel[t * LD + t];
+      if (!(d > 0.0)) { bad = 1; d = 1.0; }
+      d = sqrt(d);
+      panel[t * LD + t] = d;
+      lsum += 2.0 * log(d);
     }
     __syncthreads();
-    // unblocked factorisation of the diagonal block + triangular solve of the rest:
-    for (int t = 0; t < nb; ++t) {
-      if (tid == 0) {
-        double d = panel[t * CNB + t];
-        if (!(d > 0.0)) { bad = 1; d = 1.0; }
-        d = sqrt(d);
-        panel[t * CNB + t] = d;
-        lsum += 2.0 * log(d);
-      }
-      __syncthreads();
-      const double piv = panel[t * CNB + t];
-      for (int i = t + 1 + tid; i < rows; i += nt) panel[i * CNB + t] /= piv;
-      __syncthreads();
-      // update columns t+1..nb-1 of the block column
-      for (int e = tid; e < (rows - t - 1) * (nb - t - 1); e += nt) {
-        int i = t + 1 + e % (rows - t - 1), u = t + 1 + e / (rows - t - 1);
-        if (i >= u) panel[i * CNB + u] -= panel[i * CNB + t] * panel[u * CNB + t];
-      }
-      __syncthreads();
-    }
-    // write back the factored block column (lower part)
-    for (int e = tid; e < rows * nb; e += nt) {
-      int i = e % rows, t = e / rows;
-      A[(jb + i) + (long)(jb + t) * nl] = (i >= t) ? panel[i * CNB + t] : 0.0;
-    }
-    // trailing update: A[i,l] -= sum_t P[i,t] P[l,t] for jb+nb <= l <= i
-    const int r2 = nl - jb - nb;
-    for (int e = tid; e < r2 * r2; e += nt) {
-      int i = e % r2, l = e / r2;
-      if (i < l) continue;
-      double s = 0.0;
-      const double* pi = panel + (nb + i) * CNB;
-      const double* pl = panel + (nb + l) * CNB;
-      for (int t = 0; t < nb; ++t) s += pi[t] * pl[t];
-      A[(jb + nb + i) + (long)(jb + nb + l) * nl] -= s;
+    const double piv = panel[t * LD + t];
+    for (int i = t + 1 + tid; i < rows; i += nt) panel[i * LD + t] /= piv;
+    __syncthreads();
+    const int rr = rows - t - 1, cc = nb - t - 1;
+    for (int e = tid; e < rr * cc; e += nt) {
+      int i = t + 1 + e % rr, u = t + 1 + e / rr;
+      if (i >= u) panel[i * LD + u] -= panel[i * LD + t] * panel[u * LD + t];
     }
     __syncthreads();
   }
+  for (int e = tid; e < rows * nb; e += nt) {
+    int i = e % rows, t = e / rows;
+    A[(jb + i) + (long)(jb + t) * nl] = (i >= t) ? panel[i * LD + t] : 0.0;
+  }
   if (tid == 0) {
-    logdet[L] = lsum;
+    logdet[L] = (jb == 0 ? 0.0 : logdet[L]) + lsum;
     if (bad) atomicOr(flags, (int)DF_NOT_SPD_LEAF);
   }
 }
 
-// U = L^{-T} (upper, column-major), i.e. L^{-1} stored row-major: U[j + i*nl] = (L^{-1})(i, j).
-// Blocked forward substitution on the identity, one leaf per workgroup.  For
-// block row ib (rows r0..r0+nb): R = E - L[r0:, 0:r0] X[0:r0, :], X[r0:, :] = L_ii^{-1} R.
-// Thread j owns column j; the block row of L is staged in LDS (read as
-// broadcasts), earlier rows of X are read back from U (coalesced over j).
-constexpr int TB = 32;
-__global__ void __launch_bounds__(256) k_leaf_trinv(const double* Lf, double* U, int nl) {
-  __shared__ double Lp[TB * NLMAX];   // Lp[r * nl + c] = L(r0 + r, c), c < r0 + nb
-  __shared__ double Ti[TB * TB];      // (L_ii)^{-1}, row-major
-  const int Lidx = blockIdx.x;
-  const double* A = Lf + (long)Lidx * nl * nl;
-  double* X = U + (long)Lidx * nl * nl;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int r0 = 0; r0 < nl; r0 += TB) {
-    const int nb = min(TB, nl - r0);
-    const int w = r0 + nb;
-    for (int e = tid; e < nb * w; e += nt) {
-      int r = e / w, c = e % w;
-      Lp[r * nl + c] = A[(r0 + r) + (long)c * nl];
+// Inverse of each CNB x CNB diagonal block of the lower factor, written into the
+// same position of Linv.  One workgroup per (block, leaf); thread c < nb solves
+// column c by forward substitution with the block in LDS.
+__global__ void __launch_bounds__(64) k_tri_inv_diag(const double* Lf, double* Linv, int nl) {
+  __shared__ double B[CNB * (CNB + 1)];
+  __shared__ double X[CNB * (CNB + 1)];
+  const int k = blockIdx.x, L = blockIdx.y;
+  const int o = k * CNB;
+  const int nb = min(CNB, nl - o);
+  const double* A = Lf + (long)L * nl * nl + o + (long)o * nl;
+  double* Y = Linv + (long)L * nl * nl + o + (long)o * nl;
+  constexpr int LD = CNB + 1;
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    int i = e % nb, j = e / nb;
+    B[i + j * LD] = A[i + (long)j * nl];
+  }
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c < nb) {
+    for (int i = 0; i < nb; ++i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      for (int q = c; q < i; ++q) v -= B[i + q * LD] * X[q + c * LD];
+      X[i + c * LD] = (i < c) ? 0.0 : v / B[i + i * LD];
     }
-    __syncthreads();
-    // inverse of the diagonal block: column t of Ti^T ... thread t solves L_ii x = e_t
-    if (tid < nb) {
-      const int t = tid;
-      for (int r = 0; r < nb; ++r) {
-        double v = (r == t) ? 1.0 : 0.0;
-        for (int q = t; q < r; ++q) v -= Lp[r * nl + r0 + q] * Ti[q * TB + t];
-        Ti[r * TB + t] = (r < t) ? 0.0 : v / Lp[r * nl + r0 + r];
-      }
-    }
-    __syncthreads();
-    for (int j = tid; j < nl; j += nt) {
-      double acc[TB];
-#pragma unroll
-      for (int r = 0; r < TB; ++r) acc[r] = (r < nb && r0 + r == j) ? 1.0 : 0.0;
-      if (j < r0) {
-        // columns c in [j, r0): batches of 8 independent loads, then the updates
-        for (int c0 = j; c0 < r0; c0 += 8) {
-          double xr[8];
-#pragma unroll
-          for (int t = 0; t < 8; ++t) xr[t] = (c0 + t < r0) ? X[j + (long)(c0 + t) * nl] : 0.0;
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const int c = min(c0 + t, r0 - 1);
-#pragma unroll
-            for (int r = 0; r < TB; ++r)
-              if (r < nb) acc[r] -= Lp[r * nl + c] * xr[t];
-          }
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < TB; ++r) {
-        if (r >= nb) break;
-        double v = 0.0;
-        for (int t = 0; t < nb; ++t) v += Ti[r * TB + t] * acc[t];
-        X[j + (long)(r0 + r) * nl] = (j <= r0 + r) ? v : 0.0;
-      }
-    }
-    __syncthreads();
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    int i = e % nb, j = e / nb;
+    Y[i + (long)j * nl] = X[i + j * LD];
   }
 }
 
 // Dinv_L = L^{-T} L^{-1};  logdet_leaf[L] = log det D_L.  work: nleaves*nl*nl doubles.
+// The inverse of the lower factor is assembled bottom-up from the diagonal-block
+// inverses: for adjacent groups g0 (rows o..o+s0) and g1 (o+s0..o+s0+s1),
+//   inv([[A, 0], [B, C]]) = [[A^-1, 0], [-C^-1 B A^-1, C^-1]]   (two batched GEMMs per merge).
 hm_status leaf_factor(Model* m, const double* D, double* Dinv, double* logdet_leaf, double* work) {
   const int nl = m->nl;
   if (nl > NLMAX) {
     set_error("leaf size exceeds 512");
     return HM_E_INVAL;
   }
-  const long sz = (long)m->nleaves * nl * nl;
+  const long ls = (long)nl * nl;
+  const long sz = (long)m->nleaves * ls;
+  const int nlv = m->nleaves;
   HM_HIP(hipMemcpyAsync(work, D, sz * sizeof(double), hipMemcpyDeviceToDevice, m->stream));
-  hipLaunchKernelGGL(k_leaf_chol, dim3(m->nleaves), dim3(256), 0, m->stream, work, nl, logdet_leaf, m->d_flags);
+  for (int jb = 0; jb < nl; jb += CNB) {
+    hipLaunchKernelGGL(k_chol_panel, dim3(nlv), dim3(256), 0, m->stream, work, nl, jb, logdet_leaf, m->d_flags);
+    HM_LAUNCH_CHECK();
+    const int j2 = jb + CNB;
+    if (j2 < nl) {
+      const int r2 = nl - j2;
+      const double* L21 = work + j2 + (long)jb * nl;
+      HM_CHECK(gemm(m->stream, false, true, r2, r2, CNB, -1.0, L21, nl, ls, L21, nl, ls, 1.0,
+                    work + j2 + (long)j2 * nl, nl, ls, nlv));
+    }
+  }
+  // Linv (lower) in Dinv
+  HM_CHECK(fill(m, Dinv, sz, 0.0));
+  const int nblk = ceil_div(nl, CNB);
+  hipLaunchKernelGGL(k_tri_inv_diag, dim3(nblk, nlv), dim3(64), 0, m->stream, work, Dinv, nl);
   HM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_leaf_trinv, dim3(m->nleaves), dim3(256), 0, m->stream, work, Dinv, nl);
-  HM_LAUNCH_CHECK();
-  // Dinv currently holds U = L^{-T}; form U U^T = L^{-T} L^{-1} into work, then copy back
-  HM_CHECK(gemm(m->stream, false, true, nl, nl, nl, 1.0, Dinv, nl, (long)nl * nl, Dinv, nl, (long)nl * nl, 0.0,
-                work, nl, (long)nl * nl, m->nleaves));
+  // groups: [start, size); merge neighbours pairwise until one group spans the leaf
+  std::vector<int> gs, gz;
+  for (int k = 0; k < nblk; ++k) {
+    gs.push_back(k * CNB);
+    gz.push_back(std::min(CNB, nl - k * CNB));
+  }
+  double* T = m->d_ws;   // scratch for B A^{-1}: needs nleaves * s1 * s0 <= nleaves * nl^2 / 4
+  const long tneed = (long)nlv * (nl / 2 + CNB) * (nl / 2 + CNB);
+  if (tneed > 3L * m->n * m->cmax) {
+    set_error("leaf_factor: scratch too small");
+    return HM_E_INVAL;
+  }
+  while (gs.size() > 1) {
+    std::vector<int> ns, nz;
+    for (size_t g = 0; g + 1 < gs.size(); g += 2) {
+      const int o = gs[g], s0 = gz[g], s1 = gz[g + 1];
+      const long tst = (long)s1 * s0;
+      // T = B A^{-1}:  B = L[o+s0 : o+s0+s1, o : o+s0],  A^{-1} = Linv[o : o+s0, o : o+s0]
+      HM_CHECK(gemm(m->stream, false, false, s1, s0, s0, 1.0, work + (o + s0) + (long)o * nl, nl, ls,
+                    Dinv + o + (long)o * nl, nl, ls, 0.0, T, s1, tst, nlv));
+      // Linv[o+s0 :, o : o+s0] = -C^{-1} T
+      HM_CHECK(gemm(m->stream, false, false, s1, s0, s1, -1.0, Dinv + (o + s0) + (long)(o + s0) * nl, nl, ls, T,
+                    s1, tst, 0.0, Dinv + (o + s0) + (long)o * nl, nl, ls, nlv));
+      ns.push_back(o);
+      nz.push_back(s0 + s1);
+    }
+    if (gs.size() % 2) {
+      ns.push_back(gs.back());
+      nz.push_back(gz.back());
+    }
+    gs.swap(ns);
+    gz.swap(nz);
+  }
+  // Dinv = Linv^T Linv (into work, then back)
+  HM_CHECK(gemm(m->stream, true, false, nl, nl, nl, 1.0, Dinv, nl, ls, Dinv, nl, ls, 0.0, work, nl, ls, nlv));
   HM_HIP(hipMemcpyAsync(Dinv, work, sz * sizeof(double), hipMemcpyDeviceToDevice, m->stream));
   return HM_OK;
 }
