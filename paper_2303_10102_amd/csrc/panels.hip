@@ -557,18 +557,18 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-__device__ __forceinline__ bool exp_seg_active(const ExpArgs& a, int d, int j0) {
+__device__ __forceinline__ bool exp_seg_active(const ExpArgs& a, int d, int j0, int tw) {
   const int yc0 = a.yc.c0(d), wy = a.yc.w(d);
-  return wy > 0 && j0 < yc0 + wy && j0 + 64 > yc0;
+  return wy > 0 && j0 < yc0 + wy && j0 + tw > yc0;
 }
 // next unit after (d, k0); d < d0 means "before the first"
-__device__ __forceinline__ bool exp_next_unit(const ExpArgs& a, int j0, int& d, int& k0) {
+__device__ __forceinline__ bool exp_next_unit(const ExpArgs& a, int j0, int tw, int& d, int& k0) {
   if (d >= a.d0) {
     k0 += EXK;
     if (k0 < a.ac.w0) return true;
   }
   for (++d; d <= a.d1; ++d)
-    if (exp_seg_active(a, d, j0)) {
+    if (exp_seg_active(a, d, j0, tw)) {
       k0 = 0;
       return true;
     }
@@ -588,8 +588,9 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
   __shared__ double Ts[EXK * 65];
   const int L = blockIdx.z;
   if (!leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) return;
+  constexpr int TW = 16 * NB;   // tile width in output columns
   const int m0 = blockIdx.x * 64;
-  const int j0 = a.ylo + blockIdx.y * 64;
+  const int j0 = a.ylo + blockIdx.y * TW;
   const long r0 = (long)L * a.nl;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
@@ -612,7 +613,7 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
   };
 
   int d = a.d0 - 1, k0 = 0;
-  bool have = exp_next_unit(a, j0, d, k0);
+  bool have = exp_next_unit(a, j0, TW, d, k0);
   if (have) load_A(d, k0, ac);
   while (have) {
     // T block of this unit (small, cached): loads issued before the next unit's panel loads
@@ -624,12 +625,13 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
       const double* Tk = T + (k0 + kk);
 #pragma unroll
       for (int q = 0; q < EXT; ++q) {
-        const int col = cbase + cc0 + (256 / EXK) * q;
-        tr[q] = (kok && col >= 0 && col < wy) ? Tk[(long)col * ldt] : 0.0;
+        const int cc = cc0 + (256 / EXK) * q;
+        const int col = cbase + cc;
+        tr[q] = (kok && cc < TW && col >= 0 && col < wy) ? Tk[(long)col * ldt] : 0.0;
       }
     }
     int dn = d, kn0 = k0;
-    const bool more = exp_next_unit(a, j0, dn, kn0);
+    const bool more = exp_next_unit(a, j0, TW, dn, kn0);
     if (more) load_A(dn, kn0, an);
     const int kn = min(EXK, wk - k0);
     lds_barrier();   // previous unit's reads of Ts are done
@@ -679,12 +681,21 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
   if (yhi <= ylo) return HM_OK;
   ExpArgs a{j.A, j.lda, j.ac, j.Y, j.ldy, j.yc, j.T, j.t_stride, j.ldt, j.tmode, j.half_off,
             j.d0, j.d1, m->levels, m->nl, j.alpha, j.beta, ylo, yhi, j.sel.mode, j.sel.depth};
-  dim3 grid(ceil_div(m->nl, GBM), ceil_div(yhi - ylo, GBN), m->nleaves);
   const bool pf = prof_on(m, PF_EXPAND);
   if (pf) prof_begin(m, PF_EXPAND);
-  // output blocks of 16 columns a tile needs (a launch narrower than 64 columns
-  // runs fewer MFMA blocks)
-  const int nb = (yhi - ylo >= 64) ? 4 : ceil_div(yhi - ylo, 16);
+  // output blocks of 16 columns per tile: a launch narrower than 64 columns runs
+  // fewer MFMA blocks; a wide output made of panel blocks (cs_block / cs_prefix of a
+  // width that is a multiple of 16) is tiled at that width, so no tile straddles two
+  // blocks with different segment sets
+  int nb;
+  if (yhi - ylo <= 64) {
+    nb = ceil_div(yhi - ylo, 16);
+  } else {
+    const int bw = (j.yc.stride > 0 && j.yc.stride == j.yc.w0 && j.yc.grow == 0) ? j.yc.w0
+                   : (j.yc.w0 == 0 && j.yc.stride == 0 && j.yc.grow > 0 ? j.yc.grow : 0);
+    nb = (bw > 0 && bw % 16 == 0 && bw <= 64 && j.yc.base % bw == 0) ? bw / 16 : 4;
+  }
+  dim3 grid(ceil_div(m->nl, GBM), ceil_div(yhi - ylo, m->panel_prec == 1 ? GBN : 16 * nb), m->nleaves);
   if (m->panel_prec == 1)
     hipLaunchKernelGGL(k_expand<1>, grid, dim3(GCfg::NT), 0, m->stream, a);
   else if (nb == 1)

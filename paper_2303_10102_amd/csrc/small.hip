@@ -82,9 +82,17 @@ __global__ void __launch_bounds__(256) k_chol_inv(const double* G, long gstride,
   for (int c = tid; c < k; c += nt) {
     for (int i = 0; i < c; ++i) X[c + i * k] = 0.0;
     for (int i = c; i < k; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int l = c; l < i; ++l) s -= A[i + l * k] * X[c + l * k];
-      X[c + i * k] = s / A[i + i * k];
+      // four independent partial sums break the FMA dependency chain
+      double s0 = (i == c) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int l = c;
+      for (; l + 3 < i; l += 4) {
+        s0 -= A[i + l * k] * X[c + l * k];
+        s1 -= A[i + (l + 1) * k] * X[c + (l + 1) * k];
+        s2 -= A[i + (l + 2) * k] * X[c + (l + 2) * k];
+        s3 -= A[i + (l + 3) * k] * X[c + (l + 3) * k];
+      }
+      for (; l < i; ++l) s0 -= A[i + l * k] * X[c + l * k];
+      X[c + i * k] = ((s0 + s1) + (s2 + s3)) / A[i + i * k];
     }
   }
   __syncthreads();
@@ -189,14 +197,28 @@ __global__ void __launch_bounds__(256) k_node_lu(const double* S, long sstride, 
       if (q != i) { double t = x[i]; x[i] = x[q]; x[q] = t; }
     }
     for (int i = 0; i < k; ++i) {
-      double s = x[i];
-      for (int l = 0; l < i; ++l) s -= A[i + l * k] * x[l];
-      x[i] = s;
+      double s0 = x[i], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int l = 0;
+      for (; l + 3 < i; l += 4) {
+        s0 -= A[i + l * k] * x[l];
+        s1 -= A[i + (l + 1) * k] * x[l + 1];
+        s2 -= A[i + (l + 2) * k] * x[l + 2];
+        s3 -= A[i + (l + 3) * k] * x[l + 3];
+      }
+      for (; l < i; ++l) s0 -= A[i + l * k] * x[l];
+      x[i] = (s0 + s1) + (s2 + s3);
     }
     for (int i = k - 1; i >= 0; --i) {
-      double s = x[i];
-      for (int l = i + 1; l < k; ++l) s -= A[i + l * k] * x[l];
-      x[i] = s / A[i + i * k];
+      double s0 = x[i], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int l = i + 1;
+      for (; l + 3 < k; l += 4) {
+        s0 -= A[i + l * k] * x[l];
+        s1 -= A[i + (l + 1) * k] * x[l + 1];
+        s2 -= A[i + (l + 2) * k] * x[l + 2];
+        s3 -= A[i + (l + 3) * k] * x[l + 3];
+      }
+      for (; l < k; ++l) s0 -= A[i + l * k] * x[l];
+      x[i] = ((s0 + s1) + (s2 + s3)) / A[i + i * k];
     }
   }
   __syncthreads();
