@@ -188,9 +188,9 @@ __global__ void __launch_bounds__(256) k_reduce_partial(RedArgs a) {
 // column group covers 128 contiguous bytes.  The output tile is MB x NB blocks of
 // 16 x 16 (sized to the real widths, not padded to 64).  Two wavefronts split the
 // leaf's rows and combine through LDS.
-template <int MB, int NB>
-__global__ void __launch_bounds__(128) k_reduce_direct(RedArgs a) {
-  __shared__ double red[MB * NB * 4 * 64];
+template <int MB, int NB, int NW>
+__global__ void __launch_bounds__(64 * NW) k_reduce_direct(RedArgs a) {
+  __shared__ double red[(NW - 1) * MB * NB * 4 * 64];
   const int ndep = a.d1 - a.d0 + 1;
   const int L = blockIdx.z / ndep;
   const int d = a.d0 + blockIdx.z % ndep;
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(128) k_reduce_direct(RedArgs a) {
   const double* Xb = a.X + r0 + (long)(a.xc.c0(d) + n0) * a.ldx;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
-  const int hrows = ((a.nl + 31) / 32) * 16;   // rows per wavefront, a multiple of 16
+  const int hrows = ((a.nl + 16 * NW - 1) / (16 * NW)) * 16;   // rows per wavefront, a multiple of 16
   const int rbeg = wave * hrows, rend = min(a.nl, rbeg + hrows);
   hm_v4d acc[MB][NB];
 #pragma unroll
@@ -242,13 +242,14 @@ __global__ void __launch_bounds__(128) k_reduce_direct(RedArgs a) {
         for (int j = 0; j < NB; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][q], xv[j][q], acc[i][j], 0, 0, 0);
   }
-  if (wave == 1) {
+  if (wave > 0) {
+    double* slot = red + (wave - 1) * (MB * NB * 4 * 64);
 #pragma unroll
     for (int i = 0; i < MB; ++i)
 #pragma unroll
       for (int j = 0; j < NB; ++j)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) red[((i * NB + j) * 4 + v) * 64 + lane] = acc[i][j][v];
+        for (int v = 0; v < 4; ++v) slot[((i * NB + j) * 4 + v) * 64 + lane] = acc[i][j][v];
   }
   __syncthreads();
   if (wave != 0) return;
@@ -265,15 +266,18 @@ __global__ void __launch_bounds__(128) k_reduce_direct(RedArgs a) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int mm = m0 + 16 * i + 4 * v + lk, nn = n0 + 16 * j + li;
-        if (mm < wa && nn < wx) dst[mm + (long)nn * wa] = acc[i][j][v] + red[((i * NB + j) * 4 + v) * 64 + lane];
+        double t = acc[i][j][v];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) t += red[(w - 1) * (MB * NB * 4 * 64) + ((i * NB + j) * 4 + v) * 64 + lane];
+        if (mm < wa && nn < wx) dst[mm + (long)nn * wa] = t;
       }
 }
 
-template <int MB>
+template <int MB, int NW>
 static void launch_reduce_direct(Model* m, int nb, dim3 grid, const RedArgs& a) {
-  if (nb == 1) hipLaunchKernelGGL((k_reduce_direct<MB, 1>), grid, dim3(128), 0, m->stream, a);
-  else if (nb == 2) hipLaunchKernelGGL((k_reduce_direct<MB, 2>), grid, dim3(128), 0, m->stream, a);
-  else hipLaunchKernelGGL((k_reduce_direct<MB, 3>), grid, dim3(128), 0, m->stream, a);
+  if (nb == 1) hipLaunchKernelGGL((k_reduce_direct<MB, 1, NW>), grid, dim3(64 * NW), 0, m->stream, a);
+  else if (nb == 2) hipLaunchKernelGGL((k_reduce_direct<MB, 2, NW>), grid, dim3(64 * NW), 0, m->stream, a);
+  else hipLaunchKernelGGL((k_reduce_direct<MB, 3, NW>), grid, dim3(64 * NW), 0, m->stream, a);
 }
 
 // Sum the per-leaf partials into every node of depths d0..min(d1, levels-1):
@@ -425,9 +429,19 @@ hm_status tree_reduce(Model* m, const ReduceJob& j) {
     };
     const int mb = blocks(wa), nb = blocks(wxmax);
     dim3 grid(ceil_div(wa, 16 * mb), ceil_div(wxmax, 16 * nb), m->nleaves * ndep);
-    if (mb == 1) launch_reduce_direct<1>(m, nb, grid, a);
-    else if (mb == 2) launch_reduce_direct<2>(m, nb, grid, a);
-    else launch_reduce_direct<3>(m, nb, grid, a);
+    // few workgroups (e.g. one depth of per-leaf products): split each leaf's rows
+    // over four wavefronts instead of two
+    const long wgs = (long)grid.x * grid.y * grid.z;
+    const bool four = wgs < 4L * 256;
+    if (four) {
+      if (mb == 1) launch_reduce_direct<1, 4>(m, nb, grid, a);
+      else if (mb == 2) launch_reduce_direct<2, 4>(m, nb, grid, a);
+      else launch_reduce_direct<3, 4>(m, nb, grid, a);
+    } else {
+      if (mb == 1) launch_reduce_direct<1, 2>(m, nb, grid, a);
+      else if (mb == 2) launch_reduce_direct<2, 2>(m, nb, grid, a);
+      else launch_reduce_direct<3, 2>(m, nb, grid, a);
+    }
   }
   HM_LAUNCH_CHECK();
   if (pf) {
