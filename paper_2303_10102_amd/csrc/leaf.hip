@@ -14,20 +14,33 @@
 namespace hm {
 
 // D_L = (Z_L + Z_L^T)/2 with Z rows in tree order (ld ldz), leaf-major output.
-__global__ void k_leaf_sym(const double* Z, int ldz, double* D, int nl, double scale) {
-  const int L = blockIdx.y;
+// 32 x 32 tiles: the tile and its mirror are staged through LDS so both reads and
+// the write are coalesced.
+__global__ void __launch_bounds__(256) k_leaf_sym(const double* Z, int ldz, double* D, int nl, double scale) {
+  __shared__ double t0[32][33], t1[32][33];
+  const int L = blockIdx.z;
   const long r0 = (long)L * nl;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nl * nl) return;
-  const int i = e % nl, j = e / nl;
-  const double a = Z[r0 + i + (long)j * ldz], b = Z[r0 + j + (long)i * ldz];
-  D[(long)L * nl * nl + e] = 0.5 * scale * (a + b);
+  const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int q = ty; q < 32; q += 8) {
+    const int i = i0 + tx, j = j0 + q;        // element (i, j) of the tile
+    t0[q][tx] = (i < nl && j < nl) ? Z[r0 + i + (long)j * ldz] : 0.0;
+    const int i2 = j0 + tx, j2 = i0 + q;      // element (j0 + tx, i0 + q) of the mirror tile
+    t1[q][tx] = (i2 < nl && j2 < nl) ? Z[r0 + i2 + (long)j2 * ldz] : 0.0;
+  }
+  __syncthreads();
+  double* Dl = D + (long)L * nl * nl;
+  for (int q = ty; q < 32; q += 8) {
+    const int i = i0 + tx, j = j0 + q;
+    // Z(j, i) = mirror tile element (row j - j0 = q, column i - i0 = tx) = t1[tx][q]
+    if (i < nl && j < nl) Dl[i + (long)j * nl] = 0.5 * scale * (t0[q][tx] + t1[tx][q]);
+  }
 }
 
 hm_status leaf_sym(Model* m, const double* Z, int ldz, double* D) {
   const int nl = m->nl;
-  hipLaunchKernelGGL(k_leaf_sym, dim3(ceil_div(nl * nl, 256), m->nleaves), dim3(256), 0, m->stream, Z, ldz, D, nl,
-                     1.0);
+  hipLaunchKernelGGL(k_leaf_sym, dim3(ceil_div(nl, 32), ceil_div(nl, 32), m->nleaves), dim3(256), 0, m->stream, Z,
+                     ldz, D, nl, 1.0);
   HM_LAUNCH_CHECK();
   return HM_OK;
 }
