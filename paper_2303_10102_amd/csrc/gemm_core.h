@@ -208,107 +208,32 @@ __device__ __forceinline__ void tile_store(const ST& st, const TileAcc& acc) {
       for (int v = 0; v < 4; ++v) st(wr + a * 16 + 4 * v + lk, wc + b * 16 + li, acc.c[a][b][v]);
 }
 // ---------------------------------------------------------------------------
-// FP32 variant for the mixed-precision panel products: operands are converted
-// to FP32 when staged into LDS, v_mfma_f32_16x16x4_f32 accumulates in FP32 and
-// the store converts back.  Same tiling; the accumulator layout of this
-// instruction differs from the FP64 one: element v of lane l is D[4 (l / 16) + v][l % 16].
-// smem must hold 2 * GCfg::LDS_DOUBLES floats.
+// Precision trait of the panel kernels that feed MFMA operands directly:
+// P = 0 FP64 (v_mfma_f64_16x16x4_f64), P = 1 FP32 operands with FP32 accumulation
+// (v_mfma_f32_16x16x4_f32) for the mixed-precision policy.  Both take lane l's
+// operands as A[l % 16][l / 16] and B[l / 16][l % 16]; their accumulators differ:
+// element v of lane l is D[4 v + l / 16][l % 16] (FP64) and D[4 (l / 16) + v][l % 16] (FP32).
 // ---------------------------------------------------------------------------
 typedef float hm_v4f __attribute__((ext_vector_type(4)));
-struct TileAcc32 {
-  hm_v4f c[2][2];
+template <int P>
+struct MfmaPrec;
+template <>
+struct MfmaPrec<0> {
+  using T = double;
+  using V = hm_v4d;
+  static __device__ __forceinline__ V zero() { return V{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ V mfma(T a, T b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  // row of the 16 x 16 block held by accumulator element v of a lane in k-group lk
+  static __device__ __forceinline__ int row(int v, int lk) { return 4 * v + lk; }
 };
-__device__ __forceinline__ void tile_zero(TileAcc32& acc) {
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc.c[a][b] = hm_v4f{0.0f, 0.0f, 0.0f, 0.0f};
-}
-template <class LA, class LB>
-__device__ __forceinline__ void tile_gemm(const LA& la, const LB& lb, int k0, int k1, TileAcc32& acc, float* smem) {
-  constexpr int BM = GBM, BN = GBN, BK = GBK, NT = GCfg::NT;
-  constexpr int NA = BM * BK / NT, NB = BN * BK / NT;
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  const int li = lane & 15, lk = lane >> 4;
-  float ra[NA], rb[NB];
-  auto fetch = [&](int kb) {
-#pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      int e = q * NT + tid;
-      int i, kk;
-      if (LA::kfast) { kk = e % BK; i = e / BK; } else { i = e % BM; kk = e / BM; }
-      int k = kb + kk;
-      ra[q] = (k < k1) ? (float)la(i, k) : 0.0f;
-    }
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      int e = q * NT + tid;
-      int j, kk;
-      if (LB::kfast) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
-      int k = kb + kk;
-      rb[q] = (k < k1) ? (float)lb(k, j) : 0.0f;
-    }
-  };
-  auto stash = [&](float* buf) {
-    float* As = buf;
-    float* Bs = buf + GCfg::LDS_A;
-#pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      int e = q * NT + tid;
-      int i, kk;
-      if (LA::kfast) { kk = e % BK; i = e / BK; } else { i = e % BM; kk = e / BM; }
-      As[kk * (BM + 1) + i] = ra[q];
-    }
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      int e = q * NT + tid;
-      int j, kk;
-      if (LB::kfast) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
-      Bs[kk * (BN + 1) + j] = rb[q];
-    }
-  };
-  if (k0 >= k1) return;
-  fetch(k0);
-  stash(smem);
-  __syncthreads();
-  int cur = 0;
-  for (int kb = k0; kb < k1; kb += BK) {
-    const bool more = kb + BK < k1;
-    if (more) fetch(kb + BK);
-    const float* As = smem + cur * GCfg::LDS_DOUBLES;
-    const float* Bs = As + GCfg::LDS_A;
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      const int kr = kk + lk;
-      const float a0 = As[kr * (BM + 1) + wr + li];
-      const float a1 = As[kr * (BM + 1) + wr + 16 + li];
-      const float b0 = Bs[kr * (BN + 1) + wc + li];
-      const float b1 = Bs[kr * (BN + 1) + wc + 16 + li];
-      acc.c[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc.c[0][0], 0, 0, 0);
-      acc.c[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc.c[0][1], 0, 0, 0);
-      acc.c[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc.c[1][0], 0, 0, 0);
-      acc.c[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc.c[1][1], 0, 0, 0);
-    }
-    if (more) stash(smem + (cur ^ 1) * GCfg::LDS_DOUBLES);
-    __syncthreads();
-    cur ^= 1;
-  }
-}
-template <class ST>
-__device__ __forceinline__ void tile_store(const ST& st, const TileAcc32& acc) {
-  const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  const int li = lane & 15, lk = lane >> 4;
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) st(wr + a * 16 + 4 * lk + v, wc + b * 16 + li, (double)acc.c[a][b][v]);
-}
+template <>
+struct MfmaPrec<1> {
+  using T = float;
+  using V = hm_v4f;
+  static __device__ __forceinline__ V zero() { return V{0.0f, 0.0f, 0.0f, 0.0f}; }
+  static __device__ __forceinline__ V mfma(T a, T b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ __forceinline__ int row(int v, int lk) { return 4 * lk + v; }
+};
 #else
 struct TileAcc {
   double c[GTM][GTN];

@@ -121,23 +121,6 @@ hm_status gemm(hipStream_t st, bool ta, bool tb, int M, int Nc, int K, double al
 // ----------------------------------------------------------------------------
 // reduce: per-leaf partial products, then sums over the leaves of each node
 // ----------------------------------------------------------------------------
-struct RedLA {
-  const double* p; int ld; int m0, wa;
-  static constexpr bool kfast = true;
-  __device__ double operator()(int i, int k) const {
-    int c = m0 + i;
-    return c < wa ? p[k + (long)c * ld] : 0.0;
-  }
-};
-struct RedLB {
-  const double* p; int ld; int n0, wx;
-  static constexpr bool kfast = true;
-  __device__ double operator()(int k, int j) const {
-    int c = n0 + j;
-    return c < wx ? p[k + (long)c * ld] : 0.0;
-  }
-};
-
 struct RedArgs {
   const double* A; int lda; ColSpec ac;
   const double* X; int ldx; ColSpec xc;
@@ -147,49 +130,18 @@ struct RedArgs {
   int sel_mode, sel_depth;
 };
 
-template <int P>
-__global__ void __launch_bounds__(256) k_reduce_partial(RedArgs a) {
-  __shared__ double smem[GSMEM];
-  const int ndep = a.d1 - a.d0 + 1;
-  const int L = blockIdx.z / ndep;
-  const int d = a.d0 + blockIdx.z % ndep;
-  if (!leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) return;
-  const int wa = a.ac.w0, wx = a.xc.w(d);
-  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
-  if (m0 >= wa || n0 >= wx) return;
-  const long r0 = (long)L * a.nl;
-  const int ac0 = a.ac.c0(d), xc0 = a.xc.c0(d);
-  RedLA la{a.A + r0 + (long)ac0 * a.lda, a.lda, m0, wa};
-  RedLB lb{a.X + r0 + (long)xc0 * a.ldx, a.ldx, n0, wx};
-  double* dst;
-  if (d == a.levels) {
-    int heap = (1 << d) - 1 + L;
-    dst = a.out + heap * a.out_stride;
-  } else {
-    dst = a.partial + ((long)L * ndep + (d - a.d0)) * a.pstride;
-  }
-  if constexpr (P == 1) {
-    TileAcc32 acc;
-    tile_zero(acc);
-    tile_gemm(la, lb, 0, a.nl, acc, reinterpret_cast<float*>(smem));
-    tile_store(StC{dst, wa, m0, n0, wa, wx, 1.0, 0.0}, acc);
-  } else {
-    TileAcc acc;
-    tile_zero(acc);
-    tile_gemm(la, lb, 0, a.nl, acc, smem);
-    tile_store(StC{dst, wa, m0, n0, wa, wx, 1.0, 0.0}, acc);
-  }
-}
-
-// FP64 reduce with both tall operands fed straight into the matrix cores.  For
+// Reduce with both tall operands fed straight into the matrix cores (P = 0 FP64,
+// P = 1 FP32 operands and accumulation for the mixed-precision policy).  For
 // out = A^T X the MFMA's k index runs over rows; lane l of k-group l/16 takes the
 // four consecutive rows 4 (l/16) .. 4 (l/16) + 3 of a 16-row group, one per
 // MFMA step, so each lane reads 32 contiguous bytes of one column and a 16-lane
 // column group covers 128 contiguous bytes.  The output tile is MB x NB blocks of
 // 16 x 16 (sized to the real widths, not padded to 64).  Two wavefronts split the
 // leaf's rows and combine through LDS.
-template <int MB, int NB, int NW>
+template <int P, int MB, int NB, int NW>
 __global__ void __launch_bounds__(64 * NW) k_reduce_direct(RedArgs a) {
+  using MP = MfmaPrec<P>;
+  using T = typename MP::T;
   __shared__ double red[(NW - 1) * MB * NB * 4 * 64];
   const int ndep = a.d1 - a.d0 + 1;
   const int L = blockIdx.z / ndep;
@@ -205,11 +157,11 @@ __global__ void __launch_bounds__(64 * NW) k_reduce_direct(RedArgs a) {
   const int li = lane & 15, lk = lane >> 4;
   const int hrows = ((a.nl + 16 * NW - 1) / (16 * NW)) * 16;   // rows per wavefront, a multiple of 16
   const int rbeg = wave * hrows, rend = min(a.nl, rbeg + hrows);
-  hm_v4d acc[MB][NB];
+  typename MP::V acc[MB][NB];
 #pragma unroll
   for (int i = 0; i < MB; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) acc[i][j] = hm_v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NB; ++j) acc[i][j] = MP::zero();
   const double* Ac[MB];
   const double* Xc[NB];
   bool aok[MB], xok[NB];
@@ -225,22 +177,21 @@ __global__ void __launch_bounds__(64 * NW) k_reduce_direct(RedArgs a) {
   }
   for (int g = rbeg; g < rend; g += 16) {
     const int rr = g + 4 * lk;
-    double av[MB][4], xv[NB][4];
+    T av[MB][4], xv[NB][4];
 #pragma unroll
     for (int i = 0; i < MB; ++i)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) av[i][q] = (aok[i] && rr + q < rend) ? Ac[i][rr + q] : 0.0;
+      for (int q = 0; q < 4; ++q) av[i][q] = (aok[i] && rr + q < rend) ? (T)Ac[i][rr + q] : (T)0;
 #pragma unroll
     for (int j = 0; j < NB; ++j)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) xv[j][q] = (xok[j] && rr + q < rend) ? Xc[j][rr + q] : 0.0;
+      for (int q = 0; q < 4; ++q) xv[j][q] = (xok[j] && rr + q < rend) ? (T)Xc[j][rr + q] : (T)0;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int i = 0; i < MB; ++i)
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][q], xv[j][q], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < NB; ++j) acc[i][j] = MP::mfma(av[i][q], xv[j][q], acc[i][j]);
   }
   if (wave > 0) {
     double* slot = red + (wave - 1) * (MB * NB * 4 * 64);
@@ -265,7 +216,7 @@ __global__ void __launch_bounds__(64 * NW) k_reduce_direct(RedArgs a) {
     for (int j = 0; j < NB; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int mm = m0 + 16 * i + 4 * v + lk, nn = n0 + 16 * j + li;
+        const int mm = m0 + 16 * i + MP::row(v, lk), nn = n0 + 16 * j + li;
         double t = acc[i][j][v];
 #pragma unroll
         for (int w = 1; w < NW; ++w) t += red[(w - 1) * (MB * NB * 4 * 64) + ((i * NB + j) * 4 + v) * 64 + lane];
@@ -273,11 +224,23 @@ __global__ void __launch_bounds__(64 * NW) k_reduce_direct(RedArgs a) {
       }
 }
 
-template <int MB, int NW>
+template <int P, int MB, int NW>
 static void launch_reduce_direct(Model* m, int nb, dim3 grid, const RedArgs& a) {
-  if (nb == 1) hipLaunchKernelGGL((k_reduce_direct<MB, 1, NW>), grid, dim3(64 * NW), 0, m->stream, a);
-  else if (nb == 2) hipLaunchKernelGGL((k_reduce_direct<MB, 2, NW>), grid, dim3(64 * NW), 0, m->stream, a);
-  else hipLaunchKernelGGL((k_reduce_direct<MB, 3, NW>), grid, dim3(64 * NW), 0, m->stream, a);
+  if (nb == 1) hipLaunchKernelGGL((k_reduce_direct<P, MB, 1, NW>), grid, dim3(64 * NW), 0, m->stream, a);
+  else if (nb == 2) hipLaunchKernelGGL((k_reduce_direct<P, MB, 2, NW>), grid, dim3(64 * NW), 0, m->stream, a);
+  else hipLaunchKernelGGL((k_reduce_direct<P, MB, 3, NW>), grid, dim3(64 * NW), 0, m->stream, a);
+}
+template <int P>
+static void launch_reduce_prec(Model* m, int mb, int nb, bool four, dim3 grid, const RedArgs& a) {
+  if (four) {
+    if (mb == 1) launch_reduce_direct<P, 1, 4>(m, nb, grid, a);
+    else if (mb == 2) launch_reduce_direct<P, 2, 4>(m, nb, grid, a);
+    else launch_reduce_direct<P, 3, 4>(m, nb, grid, a);
+  } else {
+    if (mb == 1) launch_reduce_direct<P, 1, 2>(m, nb, grid, a);
+    else if (mb == 2) launch_reduce_direct<P, 2, 2>(m, nb, grid, a);
+    else launch_reduce_direct<P, 3, 2>(m, nb, grid, a);
+  }
 }
 
 // Sum the per-leaf partials into every node of depths d0..min(d1, levels-1):
@@ -417,9 +380,6 @@ hm_status tree_reduce(Model* m, const ReduceJob& j) {
     dim3 g(ceil_div(m->nl, 64), ceil_div(w, 64), m->nleaves * ndep);
     hipLaunchKernelGGL(k_leaf_blocks, g, dim3(256), 0, m->stream, P, ldp, pc, j.d0, j.d1, m->levels, m->nl, w,
                        xid ? 1 : 0, j.out, j.out_stride, m->d_red, (long)wa * wxmax);
-  } else if (m->panel_prec == 1) {
-    dim3 grid(ceil_div(wa, GBM), ceil_div(wxmax, GBN), m->nleaves * ndep);
-    hipLaunchKernelGGL(k_reduce_partial<1>, grid, dim3(GCfg::NT), 0, m->stream, a);
   } else {
     // output tile sized to the widths: MB x NB blocks of 16
     auto blocks = [](int w) {   // up to 3 x 3 blocks per tile keeps two wavefronts per SIMD
@@ -433,15 +393,8 @@ hm_status tree_reduce(Model* m, const ReduceJob& j) {
     // over four wavefronts instead of two
     const long wgs = (long)grid.x * grid.y * grid.z;
     const bool four = wgs < 4L * 256;
-    if (four) {
-      if (mb == 1) launch_reduce_direct<1, 4>(m, nb, grid, a);
-      else if (mb == 2) launch_reduce_direct<2, 4>(m, nb, grid, a);
-      else launch_reduce_direct<3, 4>(m, nb, grid, a);
-    } else {
-      if (mb == 1) launch_reduce_direct<1, 2>(m, nb, grid, a);
-      else if (mb == 2) launch_reduce_direct<2, 2>(m, nb, grid, a);
-      else launch_reduce_direct<3, 2>(m, nb, grid, a);
-    }
+    if (m->panel_prec == 1) launch_reduce_prec<1>(m, mb, nb, four, grid, a);
+    else launch_reduce_prec<0>(m, mb, nb, four, grid, a);
   }
   HM_LAUNCH_CHECK();
   if (pf) {
@@ -476,32 +429,6 @@ hm_status tree_reduce(Model* m, const ReduceJob& j) {
 // ----------------------------------------------------------------------------
 // expand: Y[i, yc(d)] = beta Y + alpha sum_d A[i, ac(d)] T_{s(c_d)}
 // ----------------------------------------------------------------------------
-struct ExpLA {
-  const double* p; int ld, m0, nl;
-  static constexpr bool kfast = false;
-  __device__ double operator()(int i, int k) const {
-    int r = m0 + i;
-    return r < nl ? p[r + (long)k * ld] : 0.0;
-  }
-};
-struct ExpLB {
-  const double* p; int ld; int jt, wy;  // jt = tile column offset relative to yc0
-  static constexpr bool kfast = true;
-  __device__ double operator()(int k, int j) const {
-    int cc = jt + j;
-    return (cc >= 0 && cc < wy) ? p[k + (long)cc * ld] : 0.0;
-  }
-};
-struct ExpSt {
-  double* p; int ld; int m0, j0, nl, yhi; double alpha, beta;
-  __device__ void operator()(int i, int j, double v) const {
-    int r = m0 + i, c = j0 + j;
-    if (r >= nl || c >= yhi) return;
-    double* q = p + r + (long)c * ld;
-    *q = (beta == 0.0) ? alpha * v : alpha * v + beta * (*q);
-  }
-};
-
 struct ExpArgs {
   const double* A; int lda; ColSpec ac;
   double* Y; int ldy; ColSpec yc;
@@ -512,44 +439,8 @@ struct ExpArgs {
   int sel_mode, sel_depth;
 };
 
-template <class ACC, class SM>
-__device__ __forceinline__ void expand_body(const ExpArgs& a, ACC& acc, SM* smem) {
-  const int L = blockIdx.z;
-  const int m0 = blockIdx.x * GBM;
-  const int j0 = a.ylo + blockIdx.y * GBN;  // absolute first column of this tile
-  const long r0 = (long)L * a.nl;
-  const int wk = a.ac.w0;
-  tile_zero(acc);
-  for (int d = a.d0; d <= a.d1; ++d) {
-    const int yc0 = a.yc.c0(d), wy = a.yc.w(d);
-    if (wy <= 0 || j0 >= yc0 + wy || j0 + GBN <= yc0) continue;
-    int c = L >> (a.levels - d);           // index of the ancestor at depth d
-    int heap = (1 << d) - 1 + c;
-    int sel = heap, roff = 0;
-    if (a.tmode == 1) sel = (heap & 1) ? heap + 1 : heap - 1;
-    else if (a.tmode == 2) { sel = (heap - 1) >> 1; roff = (c & 1) ? a.half_off : 0; }
-    ExpLA la{a.A + r0 + (long)a.ac.c0(d) * a.lda, a.lda, m0, a.nl};
-    ExpLB lb{a.T + sel * a.t_stride + roff, a.ldt, j0 - yc0, wy};
-    tile_gemm(la, lb, 0, wk, acc, smem);
-  }
-  ExpSt st{a.Y + r0, a.ldy, m0, j0, a.nl, a.yhi, a.alpha, a.beta};
-  tile_store(st, acc);
-}
-
-template <int P>
-__global__ void __launch_bounds__(256) k_expand(ExpArgs a) {
-  __shared__ double smem[GSMEM];
-  if (!leaf_selected(blockIdx.z, a.levels, a.sel_mode, a.sel_depth)) return;
-  if constexpr (P == 1) {
-    TileAcc32 acc;
-    expand_body(a, acc, reinterpret_cast<float*>(smem));
-  } else {
-    TileAcc acc;
-    expand_body(a, acc, smem);
-  }
-}
-
-// FP64 expand with the tall operand fed straight into the matrix cores.  The
+// Expand with the tall operand fed straight into the matrix cores (P = 0 FP64,
+// P = 1 FP32 operands and accumulation for the mixed-precision policy).  The
 // product is formed transposed, D = T^T A^T (16 output columns x 16 rows per
 // MFMA block), so that
 //   * the B operand of v_mfma_f64_16x16x4 (lane l: row l%16, k l/16) is read from
@@ -597,9 +488,11 @@ __device__ __forceinline__ const double* exp_T(const ExpArgs& a, int L, int d) {
   return a.T + sel * a.t_stride + roff;
 }
 
-template <int NB>
+template <int P, int NB>
 __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
-  __shared__ double Ts[EXK * 65];
+  using MP = MfmaPrec<P>;
+  using T = typename MP::T;
+  __shared__ T Ts[EXK * 65];
   const int L = blockIdx.z;
   if (!leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) return;
   constexpr int TW = 16 * NB;   // tile width in output columns
@@ -612,17 +505,17 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
   const bool rok = row < a.nl;
   const int wk = a.ac.w0;
   const int ldt = a.ldt;
-  hm_v4d acc[NB];
+  typename MP::V acc[NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) acc[b] = hm_v4d{0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < NB; ++b) acc[b] = MP::zero();
 
-  double ac[EXK / 4], an[EXK / 4], tr[EXT];
-  auto load_A = [&](int d, int k0, double (&av)[EXK / 4]) {
+  T ac[EXK / 4], an[EXK / 4], tr[EXT];
+  auto load_A = [&](int d, int k0, T (&av)[EXK / 4]) {
     const double* Ar = a.A + r0 + row + (long)a.ac.c0(d) * a.lda;
 #pragma unroll
     for (int s = 0; s < EXK / 4; ++s) {
       const int k = k0 + 4 * s + lk;
-      av[s] = (rok && k < wk) ? Ar[(long)k * a.lda] : 0.0;
+      av[s] = (rok && k < wk) ? (T)Ar[(long)k * a.lda] : (T)0;
     }
   };
 
@@ -631,17 +524,17 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
   if (have) load_A(d, k0, ac);
   while (have) {
     // T block of this unit (small, cached): loads issued before the next unit's panel loads
-    const double* T = exp_T(a, L, d);
+    const double* Tb = exp_T(a, L, d);
     const int cbase = j0 - a.yc.c0(d), wy = a.yc.w(d);
     {
       const int kk = tid % EXK, cc0 = tid / EXK;
       const bool kok = k0 + kk < wk;
-      const double* Tk = T + (k0 + kk);
+      const double* Tk = Tb + (k0 + kk);
 #pragma unroll
       for (int q = 0; q < EXT; ++q) {
         const int cc = cc0 + (256 / EXK) * q;
         const int col = cbase + cc;
-        tr[q] = (kok && cc < TW && col >= 0 && col < wy) ? Tk[(long)col * ldt] : 0.0;
+        tr[q] = (kok && cc < TW && col >= 0 && col < wy) ? (T)Tk[(long)col * ldt] : (T)0;
       }
     }
     int dn = d, kn0 = k0;
@@ -657,8 +550,7 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
       if (4 * s < kn) {
         const int kk = 4 * s + lk;
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ts[kk * 65 + b * 16 + li], ac[s], acc[b], 0, 0, 0);
+        for (int b = 0; b < NB; ++b) acc[b] = MP::mfma(Ts[kk * 65 + b * 16 + li], ac[s], acc[b]);
       }
     }
     if (!more) break;
@@ -673,12 +565,21 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
   for (int b = 0; b < NB; ++b)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int col = j0 + b * 16 + 4 * v + lk;
+      const int col = j0 + b * 16 + MP::row(v, lk);
       if (col < a.yhi) {
         double* q = Yr + (long)col * a.ldy;
-        *q = (a.beta == 0.0) ? a.alpha * acc[b][v] : a.alpha * acc[b][v] + a.beta * (*q);
+        const double r = (double)acc[b][v];
+        *q = (a.beta == 0.0) ? a.alpha * r : a.alpha * r + a.beta * (*q);
       }
     }
+}
+
+template <int P>
+static void launch_expand_direct(Model* m, int nb, dim3 grid, const ExpArgs& a) {
+  if (nb == 1) hipLaunchKernelGGL((k_expand_direct<P, 1>), grid, dim3(GCfg::NT), 0, m->stream, a);
+  else if (nb == 2) hipLaunchKernelGGL((k_expand_direct<P, 2>), grid, dim3(GCfg::NT), 0, m->stream, a);
+  else if (nb == 3) hipLaunchKernelGGL((k_expand_direct<P, 3>), grid, dim3(GCfg::NT), 0, m->stream, a);
+  else hipLaunchKernelGGL((k_expand_direct<P, 4>), grid, dim3(GCfg::NT), 0, m->stream, a);
 }
 
 hm_status tree_expand(Model* m, const ExpandJob& j) {
@@ -709,17 +610,9 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
                    : (j.yc.w0 == 0 && j.yc.stride == 0 && j.yc.grow > 0 ? j.yc.grow : 0);
     nb = (bw > 0 && bw % 16 == 0 && bw <= 64 && j.yc.base % bw == 0) ? bw / 16 : 4;
   }
-  dim3 grid(ceil_div(m->nl, GBM), ceil_div(yhi - ylo, m->panel_prec == 1 ? GBN : 16 * nb), m->nleaves);
-  if (m->panel_prec == 1)
-    hipLaunchKernelGGL(k_expand<1>, grid, dim3(GCfg::NT), 0, m->stream, a);
-  else if (nb == 1)
-    hipLaunchKernelGGL(k_expand_direct<1>, grid, dim3(GCfg::NT), 0, m->stream, a);
-  else if (nb == 2)
-    hipLaunchKernelGGL(k_expand_direct<2>, grid, dim3(GCfg::NT), 0, m->stream, a);
-  else if (nb == 3)
-    hipLaunchKernelGGL(k_expand_direct<3>, grid, dim3(GCfg::NT), 0, m->stream, a);
-  else
-    hipLaunchKernelGGL(k_expand_direct<4>, grid, dim3(GCfg::NT), 0, m->stream, a);
+  dim3 grid(ceil_div(m->nl, GBM), ceil_div(yhi - ylo, 16 * nb), m->nleaves);
+  if (m->panel_prec == 1) launch_expand_direct<1>(m, nb, grid, a);
+  else launch_expand_direct<0>(m, nb, grid, a);
   HM_LAUNCH_CHECK();
   if (pf) {
     const int wk = j.ac.w0;
