@@ -488,7 +488,7 @@ __device__ __forceinline__ const double* exp_T(const ExpArgs& a, int L, int d) {
   return a.T + sel * a.t_stride + roff;
 }
 
-template <int P, int NB>
+template <int P, int NB, int RB>
 __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
   using MP = MfmaPrec<P>;
   using T = typename MP::T;
@@ -496,26 +496,37 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
   const int L = blockIdx.z;
   if (!leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) return;
   constexpr int TW = 16 * NB;   // tile width in output columns
-  const int m0 = blockIdx.x * 64;
+  const int m0 = blockIdx.x * (64 * RB);
   const int j0 = a.ylo + blockIdx.y * TW;
   const long r0 = (long)L * a.nl;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
-  const int row = m0 + wave * 16 + li;
-  const bool rok = row < a.nl;
+  // RB row blocks of 16 per wavefront: every T value read from LDS feeds RB MFMAs
+  int row[RB];
+  bool rok[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    row[r] = m0 + wave * (16 * RB) + 16 * r + li;
+    rok[r] = row[r] < a.nl;
+  }
   const int wk = a.ac.w0;
   const int ldt = a.ldt;
-  typename MP::V acc[NB];
+  typename MP::V acc[RB][NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) acc[b] = MP::zero();
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[r][b] = MP::zero();
 
-  T ac[EXK / 4], an[EXK / 4], tr[EXT];
-  auto load_A = [&](int d, int k0, T (&av)[EXK / 4]) {
-    const double* Ar = a.A + r0 + row + (long)a.ac.c0(d) * a.lda;
+  T ac[RB][EXK / 4], an[RB][EXK / 4], tr[EXT];
+  auto load_A = [&](int d, int k0, T (&av)[RB][EXK / 4]) {
 #pragma unroll
-    for (int s = 0; s < EXK / 4; ++s) {
-      const int k = k0 + 4 * s + lk;
-      av[s] = (rok && k < wk) ? (T)Ar[(long)k * a.lda] : (T)0;
+    for (int r = 0; r < RB; ++r) {
+      const double* Ar = a.A + r0 + row[r] + (long)a.ac.c0(d) * a.lda;
+#pragma unroll
+      for (int s = 0; s < EXK / 4; ++s) {
+        const int k = k0 + 4 * s + lk;
+        av[r][s] = (rok[r] && k < wk) ? (T)Ar[(long)k * a.lda] : (T)0;
+      }
     }
   };
 
@@ -550,36 +561,45 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
       if (4 * s < kn) {
         const int kk = 4 * s + lk;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) acc[b] = MP::mfma(Ts[kk * 65 + b * 16 + li], ac[s], acc[b]);
+        for (int b = 0; b < NB; ++b) {
+          const T tv = Ts[kk * 65 + b * 16 + li];
+#pragma unroll
+          for (int r = 0; r < RB; ++r) acc[r][b] = MP::mfma(tv, ac[r][s], acc[r][b]);
+        }
       }
     }
     if (!more) break;
 #pragma unroll
-    for (int s = 0; s < EXK / 4; ++s) ac[s] = an[s];
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int s = 0; s < EXK / 4; ++s) ac[r][s] = an[r][s];
     d = dn;
     k0 = kn0;
   }
-  if (!rok) return;
-  double* Yr = a.Y + r0 + row;
 #pragma unroll
-  for (int b = 0; b < NB; ++b)
+  for (int r = 0; r < RB; ++r) {
+    if (!rok[r]) continue;
+    double* Yr = a.Y + r0 + row[r];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int col = j0 + b * 16 + MP::row(v, lk);
-      if (col < a.yhi) {
-        double* q = Yr + (long)col * a.ldy;
-        const double r = (double)acc[b][v];
-        *q = (a.beta == 0.0) ? a.alpha * r : a.alpha * r + a.beta * (*q);
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = j0 + b * 16 + MP::row(v, lk);
+        if (col < a.yhi) {
+          double* q = Yr + (long)col * a.ldy;
+          const double x = (double)acc[r][b][v];
+          *q = (a.beta == 0.0) ? a.alpha * x : a.alpha * x + a.beta * (*q);
+        }
       }
-    }
+  }
 }
 
-template <int P>
+template <int P, int RB>
 static void launch_expand_direct(Model* m, int nb, dim3 grid, const ExpArgs& a) {
-  if (nb == 1) hipLaunchKernelGGL((k_expand_direct<P, 1>), grid, dim3(GCfg::NT), 0, m->stream, a);
-  else if (nb == 2) hipLaunchKernelGGL((k_expand_direct<P, 2>), grid, dim3(GCfg::NT), 0, m->stream, a);
-  else if (nb == 3) hipLaunchKernelGGL((k_expand_direct<P, 3>), grid, dim3(GCfg::NT), 0, m->stream, a);
-  else hipLaunchKernelGGL((k_expand_direct<P, 4>), grid, dim3(GCfg::NT), 0, m->stream, a);
+  if (nb == 1) hipLaunchKernelGGL((k_expand_direct<P, 1, RB>), grid, dim3(GCfg::NT), 0, m->stream, a);
+  else if (nb == 2) hipLaunchKernelGGL((k_expand_direct<P, 2, RB>), grid, dim3(GCfg::NT), 0, m->stream, a);
+  else if (nb == 3) hipLaunchKernelGGL((k_expand_direct<P, 3, RB>), grid, dim3(GCfg::NT), 0, m->stream, a);
+  else hipLaunchKernelGGL((k_expand_direct<P, 4, RB>), grid, dim3(GCfg::NT), 0, m->stream, a);
 }
 
 hm_status tree_expand(Model* m, const ExpandJob& j) {
@@ -610,9 +630,16 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
                    : (j.yc.w0 == 0 && j.yc.stride == 0 && j.yc.grow > 0 ? j.yc.grow : 0);
     nb = (bw > 0 && bw % 16 == 0 && bw <= 64 && j.yc.base % bw == 0) ? bw / 16 : 4;
   }
-  dim3 grid(ceil_div(m->nl, GBM), ceil_div(yhi - ylo, 16 * nb), m->nleaves);
-  if (m->panel_prec == 1) launch_expand_direct<1>(m, nb, grid, a);
-  else launch_expand_direct<0>(m, nb, grid, a);
+  // two row blocks per wavefront (128 rows per workgroup) when the leaves are tall enough
+  const int rb = (m->nl >= 128) ? 2 : 1;
+  dim3 grid(ceil_div(m->nl, 64 * rb), ceil_div(yhi - ylo, 16 * nb), m->nleaves);
+  if (m->panel_prec == 1) {
+    if (rb == 2) launch_expand_direct<1, 2>(m, nb, grid, a);
+    else launch_expand_direct<1, 1>(m, nb, grid, a);
+  } else {
+    if (rb == 2) launch_expand_direct<0, 2>(m, nb, grid, a);
+    else launch_expand_direct<0, 1>(m, nb, grid, a);
+  }
   HM_LAUNCH_CHECK();
   if (pf) {
     const int wk = j.ac.w0;
