@@ -25,7 +25,7 @@ def _metrics(ll, g, fim, ex):
             "I": float(np.max(np.abs(fim - ex["fim"]) / np.outer(d, d)))}
 
 
-@pytest.mark.parametrize("key", ["1d_n1024", "2d_n4096", "2d_n65536"])
+@pytest.mark.parametrize("key", ["1d_n1024", "2d_n4096", "2d_n16384", "2d_n65536"])
 def test_mixed_accuracy(key):
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
