@@ -83,6 +83,11 @@ struct Model {
   // the precision in effect (0 FP64, 1 FP32 operands with FP32 accumulation).
   int mixed = 0;
   int panel_prec = 0;
+  // kernel variants of the panel products, chosen per model by hm_model_autotune
+  // (defaults: two row blocks per wavefront in the expand when leaves have >= 128
+  // rows; four-wavefront row split in the reduce below 1024 workgroups)
+  int tune_expand_rb = 0;        // 0 = default rule, else 1 or 2
+  long tune_reduce_nw4 = 1024;   // reduce launches with fewer workgroups split rows over 4 wavefronts
   int prof_family = PF_NONE;
   std::vector<ProfRec> prof;
   std::vector<hipEvent_t> ev_pool;
@@ -190,5 +195,7 @@ hm_status alg2_fold_nodes(Model* m, const double* W, double* M, long stride, int
 hm_status node_lu(Model* m, const double* S, long sstride, double* Nout, long nstride, double* logdet, int k,
                   int heap0, int cnt);
 hm_status model_tables(Model* m);
+// time the panel-kernel variants on this model's shapes (panel width kc) and keep the fastest
+hm_status autotune(Model* m, int kc, double* report);
 
 }  // namespace hm

@@ -392,7 +392,7 @@ hm_status tree_reduce(Model* m, const ReduceJob& j) {
     // few workgroups (e.g. one depth of per-leaf products): split each leaf's rows
     // over four wavefronts instead of two
     const long wgs = (long)grid.x * grid.y * grid.z;
-    const bool four = wgs < 4L * 256;
+    const bool four = wgs < m->tune_reduce_nw4;
     if (m->panel_prec == 1) launch_reduce_prec<1>(m, mb, nb, four, grid, a);
     else launch_reduce_prec<0>(m, mb, nb, four, grid, a);
   }
@@ -631,7 +631,7 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
     nb = (bw > 0 && bw % 16 == 0 && bw <= 64 && j.yc.base % bw == 0) ? bw / 16 : 4;
   }
   // two row blocks per wavefront (128 rows per workgroup) when the leaves are tall enough
-  const int rb = (m->nl >= 128) ? 2 : 1;
+  const int rb = m->tune_expand_rb ? m->tune_expand_rb : ((m->nl >= 128) ? 2 : 1);
   dim3 grid(ceil_div(m->nl, 64 * rb), ceil_div(yhi - ylo, 16 * nb), m->nleaves);
   if (m->panel_prec == 1) {
     if (rb == 2) launch_expand_direct<1, 2>(m, nb, grid, a);

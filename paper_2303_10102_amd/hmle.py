@@ -38,6 +38,8 @@ _SIGS = {
     "hm_model_destroy": ([_P], None),
     "hm_model_info": ([_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)], _I),
     "hm_model_set_stream": ([_P, _P], _I),
+    "hm_model_autotune": ([_P, _I, _D], _I),
+    "hm_model_tuning": ([_P, C.POINTER(_I), C.POINTER(C.c_longlong), _I], _I),
     "hm_model_perm": ([_P, C.POINTER(_I)], _I),
     "hm_kapply": ([_P, _D, _P, _I, _I, _P, _I, _I], _I),
     "hm_sketch_create": ([_P, _P, _I, _I, _D, C.POINTER(_P)], _I),
@@ -123,6 +125,24 @@ class Model:
         """Move the model's later work to another torch stream (None = current stream)."""
         _check("hm_model_set_stream", lib().hm_model_set_stream(self._h, _stream_handle(stream)))
         self.stream = stream
+
+    def autotune(self, kc):
+        """Time the panel-kernel variants on this model's shapes and keep the fastest."""
+        rep = (C.c_double * 7)()
+        _check("hm_model_autotune", lib().hm_model_autotune(self._h, int(kc), rep))
+        return dict(expand_ms={1: rep[0], 2: rep[1]},
+                    reduce_ms={"never": rep[2], "below_1024": rep[3], "always": rep[4]},
+                    expand_rows=int(rep[5]), reduce_split_below=int(rep[6]))
+
+    def tuning(self, expand_rows=None, reduce_split_below=None):
+        """Read the chosen kernel variants, or set them (both arguments given)."""
+        rb, thr = _I(0), C.c_longlong(0)
+        if expand_rows is None:
+            _check("hm_model_tuning", lib().hm_model_tuning(self._h, C.byref(rb), C.byref(thr), 0))
+            return rb.value, thr.value
+        rb.value, thr.value = int(expand_rows), int(reduce_split_below)
+        _check("hm_model_tuning", lib().hm_model_tuning(self._h, C.byref(rb), C.byref(thr), 1))
+        return rb.value, thr.value
 
     def perm(self):
         out = (C.c_int * self.n)()
@@ -356,6 +376,21 @@ class Batch:
             go += p
             fo += p * p
         return lls, grads, fims
+
+    def tune_kernels(self):
+        """Autotune the panel-kernel variants once per distinct field shape and copy the
+        choice to every field of that shape; returns the per-shape reports."""
+        reports, chosen = {}, {}
+        for H in self.Hs:
+            m = H.model
+            _, kc = H.sketch.ranks()
+            key = (m.dim, m.N, m.leaf, kc)
+            if key not in chosen:
+                reports[key] = m.autotune(kc)
+                chosen[key] = m.tuning()
+            else:
+                m.tuning(*chosen[key])
+        return reports
 
     def tune(self, thetas, ys, candidates=(1, 2, 4, 8), reps=1):
         """Pick the stream count by timing; returns the measurements."""

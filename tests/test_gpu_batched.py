@@ -66,6 +66,23 @@ def test_batched_field_against_oracle(batch):
     assert rel_err(fim[f], r["fim"]) < 1e-6
 
 
+def test_batch_tune_kernels(batch):
+    fields, objs, Hs, ys, thetas, b = batch
+    reps = b.tune_kernels()
+    shapes = {}
+    for H in Hs:
+        _, kc = H.sketch.ranks()
+        shapes.setdefault((H.model.dim, H.model.N, H.model.leaf, kc), []).append(H.model.tuning())
+    assert set(reps) == set(shapes)
+    for key, choices in shapes.items():
+        assert all(c == choices[0] for c in choices), key
+        assert choices[0] == (reps[key]["expand_rows"], reps[key]["reduce_split_below"])
+    ll, g, fim = b.iteration(thetas, ys)
+    for f, H in enumerate(Hs):
+        l1, g1, f1 = H.iteration(thetas[f], ys[f])
+        assert rel_err(ll[f], l1) <= 1e-12
+
+
 def test_batch_tune(batch):
     fields, objs, Hs, ys, thetas, b = batch
     res = b.tune(thetas, ys, candidates=(1, 2, 4))
