@@ -437,6 +437,7 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
   A((void**)&m->d_iperm, n * sizeof(int));
   A((void**)&m->d_mu, (size_t)N * sizeof(double));
   A((void**)&m->d_dst, (size_t)N * N * sizeof(double));
+  if (N % 2 == 0) A((void**)&m->d_dsth, (size_t)N * N * sizeof(double));
   A((void**)&m->d_lam, 3 * (size_t)n * sizeof(double));
   A((void**)&m->d_ws, 3 * (size_t)n * m->cmax * sizeof(double));
   A((void**)&m->d_flags, sizeof(int));
@@ -465,7 +466,7 @@ void hm_model_destroy(hm_model* mm) {
   if (!mm) return;
   Model* m = &mm->m;
   for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
-  void* ps[] = {m->d_perm, m->d_iperm, m->d_dst, m->d_mu, m->d_lam, m->d_ws, m->d_flags, m->d_ident, m->d_red};
+  void* ps[] = {m->d_perm, m->d_iperm, m->d_dst, m->d_dsth, m->d_mu, m->d_lam, m->d_ws, m->d_flags, m->d_ident, m->d_red};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   delete mm;

@@ -119,9 +119,11 @@ __device__ __forceinline__ void tile_zero(TileAcc& acc) {
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc.c[a][b] = hm_v4d{0.0, 0.0, 0.0, 0.0};
 }
-// Double-buffered: the next K-slab is fetched into registers while the current
-// one is consumed from LDS, so one barrier per slab and global latency hidden
-// behind the matrix-core work.  smem must hold 2 * GCfg::LDS_DOUBLES.
+// Pipelined: two K-slabs ahead are in flight in registers while the current one is
+// consumed from LDS (double-buffered), so one barrier per slab and two global
+// round trips overlap each slab's matrix-core work.  The slab loop is unrolled by
+// two so that the two register sets alternate statically (a register copy would
+// wait for its loads).  smem must hold 2 * GCfg::LDS_DOUBLES.
 template <class LA, class LB>
 __device__ __forceinline__ void tile_gemm(const LA& la, const LB& lb, int k0, int k1, TileAcc& acc, double* smem) {
   constexpr int BM = GBM, BN = GBN, BK = GBK, NT = GCfg::NT;
@@ -130,15 +132,17 @@ __device__ __forceinline__ void tile_gemm(const LA& la, const LB& lb, int k0, in
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
-  double ra[NA], rb[NB];
-  auto fetch = [&](int kb) {
+  struct Regs {
+    double a[NA], b[NB];
+  };
+  auto fetch = [&](int kb, Regs& r) {
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       int e = q * NT + tid;
       int i, kk;
       if (LA::kfast) { kk = e % BK; i = e / BK; } else { i = e % BM; kk = e / BM; }
       int k = kb + kk;
-      ra[q] = (k < k1) ? la(i, k) : 0.0;
+      r.a[q] = (k < k1) ? la(i, k) : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -146,10 +150,10 @@ __device__ __forceinline__ void tile_gemm(const LA& la, const LB& lb, int k0, in
       int j, kk;
       if (LB::kfast) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
       int k = kb + kk;
-      rb[q] = (k < k1) ? lb(k, j) : 0.0;
+      r.b[q] = (k < k1) ? lb(k, j) : 0.0;
     }
   };
-  auto stash = [&](double* buf) {
+  auto stash = [&](const Regs& r, double* buf) {
     double* As = buf;
     double* Bs = buf + GCfg::LDS_A;
 #pragma unroll
@@ -157,26 +161,19 @@ __device__ __forceinline__ void tile_gemm(const LA& la, const LB& lb, int k0, in
       int e = q * NT + tid;
       int i, kk;
       if (LA::kfast) { kk = e % BK; i = e / BK; } else { i = e % BM; kk = e / BM; }
-      As[kk * (BM + 1) + i] = ra[q];
+      As[kk * (BM + 1) + i] = r.a[q];
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       int e = q * NT + tid;
       int j, kk;
       if (LB::kfast) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
-      Bs[kk * (BN + 1) + j] = rb[q];
+      Bs[kk * (BN + 1) + j] = r.b[q];
     }
   };
-  if (k0 >= k1) return;
-  fetch(k0);
-  stash(smem);
-  __syncthreads();
-  int cur = 0;
-  for (int kb = k0; kb < k1; kb += BK) {
-    const bool more = kb + BK < k1;
-    if (more) fetch(kb + BK);
-    const double* As = smem + cur * GCfg::LDS_DOUBLES;
-    const double* Bs = As + GCfg::LDS_A;
+  auto compute = [&](const double* buf) {
+    const double* As = buf;
+    const double* Bs = buf + GCfg::LDS_A;
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + lk;
@@ -184,18 +181,57 @@ __device__ __forceinline__ void tile_gemm(const LA& la, const LB& lb, int k0, in
       const double a1 = As[kr * (BM + 1) + wr + 16 + li];
       const double b0 = Bs[kr * (BN + 1) + wc + li];
       const double b1 = Bs[kr * (BN + 1) + wc + 16 + li];
-      acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc.c[0][0], 0, 0, 0);
-      acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.c[0][1], 0, 0, 0);
-      acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.c[1][0], 0, 0, 0);
-      acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc.c[1][1], 0, 0, 0);
+      // operands swapped: each block accumulates the transpose (see tile_store)
+      acc.c[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, acc.c[0][0], 0, 0, 0);
+      acc.c[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, acc.c[0][1], 0, 0, 0);
+      acc.c[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, acc.c[1][0], 0, 0, 0);
+      acc.c[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, acc.c[1][1], 0, 0, 0);
     }
-    if (more) stash(smem + (cur ^ 1) * GCfg::LDS_DOUBLES);
+  };
+  if (k0 >= k1) return;
+  double* buf0 = smem;
+  double* buf1 = smem + GCfg::LDS_DOUBLES;
+  Regs r1, r2;
+  fetch(k0, r1);
+  stash(r1, buf0);
+  if (k0 + BK < k1) fetch(k0 + BK, r1);
+  __syncthreads();
+  // invariant at the top of a step for slab kb: slab kb in LDS, slab kb + BK in flight
+  for (int kb = k0; kb < k1; kb += 2 * BK) {
+    // slab kb from buf0; slab kb + BK (r1) to buf1; slab kb + 2 BK fetched into r2
+    if (kb + 2 * BK < k1) fetch(kb + 2 * BK, r2);
+    compute(buf0);
+    if (kb + BK >= k1) break;
+    stash(r1, buf1);
     __syncthreads();
-    cur ^= 1;
+    // slab kb + BK from buf1; slab kb + 2 BK (r2) to buf0; slab kb + 3 BK fetched into r1
+    if (kb + 3 * BK < k1) fetch(kb + 3 * BK, r1);
+    compute(buf1);
+    if (kb + 2 * BK >= k1) break;
+    stash(r2, buf0);
+    __syncthreads();
   }
+  // the last slab's LDS reads are done before a caller reuses smem
+  __syncthreads();
 }
 template <class ST>
 __device__ __forceinline__ void tile_store(const ST& st, const TileAcc& acc) {
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  // block (a, b) holds its transpose: element v of lane l is C[row l % 16][col 4 v + l / 16],
+  // so the 16 lanes of a group write 16 consecutive rows (one column-major run)
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) st(wr + a * 16 + li, wc + b * 16 + 4 * v + lk, acc.c[a][b][v]);
+}
+// Store of two accumulators of the same tile: st(i, j, e, o)
+template <class ST>
+__device__ __forceinline__ void tile_store2(const ST& st, const TileAcc& e, const TileAcc& o) {
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
@@ -205,7 +241,8 @@ __device__ __forceinline__ void tile_store(const ST& st, const TileAcc& acc) {
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) st(wr + a * 16 + 4 * v + lk, wc + b * 16 + li, acc.c[a][b][v]);
+      for (int v = 0; v < 4; ++v)
+        st(wr + a * 16 + li, wc + b * 16 + 4 * v + lk, e.c[a][b][v], o.c[a][b][v]);
 }
 // ---------------------------------------------------------------------------
 // Precision trait of the panel kernels that feed MFMA operands directly:
@@ -247,6 +284,14 @@ __device__ __forceinline__ void tile_gemm(const LA& la, const LB& lb, int k0, in
 template <class ST>
 __device__ __forceinline__ void tile_store(const ST& st, const TileAcc& acc) {
   tile_store<GBM, GBN, GBK, GTM, GTN>(st, acc.c);
+}
+template <class ST>
+__device__ __forceinline__ void tile_store2(const ST& st, const TileAcc& e, const TileAcc& o) {
+  const int tr = threadIdx.x / GCfg::CS, tc = threadIdx.x % GCfg::CS;
+#pragma unroll
+  for (int i = 0; i < GTM; ++i)
+#pragma unroll
+    for (int j = 0; j < GTN; ++j) st(tr + i * GCfg::RS, tc + j * GCfg::CS, e.c[i][j], o.c[i][j]);
 }
 #endif
 

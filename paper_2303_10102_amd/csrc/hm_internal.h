@@ -68,6 +68,7 @@ struct Model {
   int* d_perm = nullptr;    // tree position -> grid index
   int* d_iperm = nullptr;   // grid index -> tree position
   double* d_dst = nullptr;  // N x N orthonormal DST-I
+  double* d_dsth = nullptr; // N even: its even/odd halves P0, P1, Q0, Q1 (each N/2 x N/2)
   double* d_mu = nullptr;   // N eigenvalues of the 1D -Laplacian
   double* d_lam = nullptr;  // per-mode multipliers of K, dK/dkappa, dK/dalpha (3 * n)
   double lam_key[4] = {-1.0, -1.0, -1.0, -1.0};  // theta they belong to

@@ -59,6 +59,29 @@ __global__ void k_tables(double* S, double* mu, int N, int dim) {
   }
 }
 
+// Even/odd halves of S for even N (H = N / 2).  The DST-I matrix obeys
+// S(p, N-1-x) = (-1)^p S(p, x): on an axis that is transformed whole, the forward
+// transform folds the input (a point plus its mirror for even modes, minus it for
+// odd modes) and sums over H points only; the inverse forms the even-mode and
+// odd-mode sums at the first H points and unfolds them (sum at x, difference at
+// N-1-x).  Both halve the transform's multiply-adds.
+//   P_par[i + k H] = S(2i + par, k),   Q_par[x + k H] = S(x, 2k + par),   i, k, x < H
+// stored as P0, P1, Q0, Q1 at offsets 0, H^2, 2 H^2, 3 H^2.
+__global__ void k_tables_half(double* Ph, int N) {
+  const int H = N / 2;
+  const long HH = (long)H * H;
+  long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 4 * HH) return;
+  const int t = (int)(e / HH);
+  const long f = e % HH;
+  const int a = (int)(f % H), b = (int)(f / H), par = t & 1;
+  // P: row mode 2a + par, point b;  Q: point a, mode 2b + par
+  const int mode = (t < 2) ? 2 * a + par : 2 * b + par;
+  const int x = (t < 2) ? b : a;
+  const long m = (long)(mode + 1) * (x + 1) % (2L * (N + 1));
+  Ph[e] = sqrt(2.0 / (N + 1)) * sinpi((double)m / (double)(N + 1));
+}
+
 // Per-mode multipliers for K, dK/dkappa, dK/dalpha: lam[o*N*Ny + p + q*N]
 __global__ void k_mode_scale(double* lam, const double* mu, int N, int Ny, double kappa, double alpha,
                              double tau2, double sigma2) {
@@ -258,6 +281,184 @@ __global__ void __launch_bounds__(256) k_dst_inv(const double* S, const double* 
   tile_store(st, acc);
 }
 
+// ---- folded transforms (even N, the transformed axis whole) ------------------
+struct HalfA {  // A(i, k) = Tab[m0 + i + k H] for m0 + i < H   (P_par or Q_par)
+  const double* T; int H, m0;
+  static constexpr bool kfast = false;
+  __device__ double operator()(int i, int k) const {
+    const int r = m0 + i;
+    return r < H ? T[r + (long)k * H] : 0.0;
+  }
+};
+struct HalfB {  // B(k, j) = Tab[k + (n0 + j) H] for n0 + j < H
+  const double* T; int H, n0;
+  static constexpr bool kfast = true;
+  __device__ double operator()(int k, int j) const {
+    const int c = n0 + j;
+    return c < H ? T[k + (long)c * H] : 0.0;
+  }
+};
+template <int AM>
+struct DstLGatherFold {  // B(k, j) = X(x = k) + sgn X(x = N-1-k) of column r = n0 + j
+  const double* X; int ldx; const int* iperm; int N, Ny, n0, R, colt, yt; AxisMap ym; double sgn;
+  static constexpr bool kfast = true;
+  __device__ double operator()(int k, int j) const {
+    const int r = n0 + j;
+    if (r >= R) return 0.0;
+    int col, y;
+    split_col<AM>(r, Ny, colt, yt, j, col, y);
+    const double* Xc = X + (long)col * ldx;
+    const int* ip = iperm + (long)ym(y) * N;
+    return Xc[ip[k]] + sgn * Xc[ip[N - 1 - k]];
+  }
+};
+struct DyLAFold {  // A(i, k) = M(p, k) + sgn M(p, N-1-k), p = m0 + i
+  const double* M; int N, m0; double sgn;
+  static constexpr bool kfast = false;
+  __device__ double operator()(int i, int k) const {
+    const int p = m0 + i;
+    if (p >= N) return 0.0;
+    return M[p + (long)k * N] + sgn * M[p + (long)(N - 1 - k) * N];
+  }
+};
+struct DyLApar {  // A(i, k) = (lam o M)(p, 2k + par), p = m0 + i
+  const double* M; const double* lam; int N, m0, par;
+  static constexpr bool kfast = false;
+  __device__ double operator()(int i, int k) const {
+    const int p = m0 + i;
+    if (p >= N) return 0.0;
+    const long e = p + (long)(2 * k + par) * N;
+    return lam ? M[e] * lam[e] : M[e];
+  }
+};
+template <int AM>
+struct DstLModePar {  // B(k, j) = W(2k + par, r) (times lam(2k + par, ymap(y')) when lam), r = n0 + j
+  const double* W; const double* lam; int N, Ny, n0, R, colt, yt, par; AxisMap ym;
+  static constexpr bool kfast = true;
+  __device__ double operator()(int k, int j) const {
+    const int r = n0 + j;
+    if (r >= R) return 0.0;
+    const int p = 2 * k + par;
+    double v = W[p + (long)r * N];
+    if (lam) {
+      int col, y;
+      split_col<AM>(r, Ny, colt, yt, j, col, y);
+      v *= lam[p + (long)ym(y) * N];
+    }
+    return v;
+  }
+};
+struct DstStModePar {  // Xh(2(m0 + i) + par, r)
+  double* p; int N, H, m0, n0, R, par;
+  __device__ void operator()(int i, int j, double v) const {
+    const int ii = m0 + i, r = n0 + j;
+    if (ii < H && r < R) p[2 * ii + par + (long)r * N] = v;
+  }
+};
+struct DyStColPar {  // C(p, 2(n0 + j) + par)
+  double* C; int N, H, m0, n0, par;
+  __device__ void operator()(int i, int j, double v) const {
+    const int pp = m0 + i, jj = n0 + j;
+    if (pp < N && jj < H) C[pp + (long)(2 * jj + par) * N] = v;
+  }
+};
+struct DyStUnfold {  // C(p, y') = e + o, C(p, N-1-y') = e - o, y' = n0 + j < H
+  double* C; int N, H, m0, n0;
+  __device__ void operator()(int i, int j, double e, double o) const {
+    const int pp = m0 + i, y = n0 + j;
+    if (pp < N && y < H) {
+      C[pp + (long)y * N] = e + o;
+      C[pp + (long)(N - 1 - y) * N] = e - o;
+    }
+  }
+};
+template <int AM>
+struct DstStScatterUnfold {  // Y at (x, r) = e + o and (N-1-x, r) = e - o, x = m0 + i < H
+  double* Y; int ldy; const int* iperm; int N, Ny, H, m0, n0, R, colt, yt; AxisMap ym;
+  __device__ void operator()(int i, int j, double e, double o) const {
+    const int x = m0 + i, r = n0 + j;
+    if (x >= H || r >= R) return;
+    int col, y;
+    split_col<AM>(r, Ny, colt, yt, j, col, y);
+    double* Yc = Y + (long)col * ldy;
+    const int* ip = iperm + (long)ym(y) * N;
+    Yc[ip[x]] = e + o;
+    Yc[ip[N - 1 - x]] = e - o;
+  }
+};
+
+// forward x, x whole: Xh(2i + par, r) = sum_{x < H} P_par(i, x) (X(x) +- X(N-1-x))
+// grid.x: 2 * ht tiles (parity major), grid.y: column tiles
+template <int AM>
+__global__ void __launch_bounds__(256) k_dst_fwd_fold(const double* Ph, const double* X, int ldx, const int* iperm,
+                                                      double* Xh, int N, int Ny, int ncol, AxisMap ym) {
+  __shared__ double smem[GSMEM];
+  const int H = N / 2, ht = (H + GBM - 1) / GBM;
+  const int par = (int)blockIdx.x >= ht ? 1 : 0;
+  const int m0 = ((int)blockIdx.x - par * ht) * GBM, n0 = blockIdx.y * GBN;
+  const int R = ncol * Ny;
+  const int colt = (AM == 1) ? n0 / Ny : 0, yt = (AM == 1) ? n0 - colt * Ny : 0;
+  HalfA la{Ph + (long)par * H * H, H, m0};
+  DstLGatherFold<AM> lb{X, ldx, iperm, N, Ny, n0, R, colt, yt, ym, par ? -1.0 : 1.0};
+  TileAcc acc;
+  tile_zero(acc);
+  tile_gemm(la, lb, 0, H, acc, smem);
+  tile_store(DstStModePar{Xh, N, H, m0, n0, R, par}, acc);
+}
+
+// forward y, y whole: C_c(p, 2j + par) = sum_{y < H} (M_c(p, y) +- M_c(p, N-1-y)) Q_par(y, j)
+// grid.y: 2 * ht tiles (parity major)
+__global__ void __launch_bounds__(256) k_dst_yf_fold(const double* Ph, const double* M, double* C, int N) {
+  __shared__ double smem[GSMEM];
+  const int H = N / 2, ht = (H + GBN - 1) / GBN;
+  const int par = (int)blockIdx.y >= ht ? 1 : 0;
+  const int m0 = blockIdx.x * GBM, n0 = ((int)blockIdx.y - par * ht) * GBN;
+  const long NN = (long)N * N;
+  DyLAFold la{M + blockIdx.z * NN, N, m0, par ? -1.0 : 1.0};
+  HalfB lb{Ph + (long)(2 + par) * H * H, H, n0};
+  TileAcc acc;
+  tile_zero(acc);
+  tile_gemm(la, lb, 0, H, acc, smem);
+  tile_store(DyStColPar{C + blockIdx.z * NN, N, H, m0, n0, par}, acc);
+}
+
+// inverse y, y whole: e = sum_k (lam o M_c)(p, 2k) P0(k, y'), o = the odd modes with P1;
+// C_c(p, y') = e + o, C_c(p, N-1-y') = e - o for y' < H
+__global__ void __launch_bounds__(256) k_dst_yi_fold(const double* Ph, const double* M, const double* lam,
+                                                     double* C, int N) {
+  __shared__ double smem[GSMEM];
+  const int H = N / 2;
+  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  const long NN = (long)N * N, HH = (long)H * H;
+  const double* Mz = M + blockIdx.z * NN;
+  TileAcc e, o;
+  tile_zero(e);
+  tile_zero(o);
+  tile_gemm(DyLApar{Mz, lam, N, m0, 0}, HalfB{Ph, H, n0}, 0, H, e, smem);
+  tile_gemm(DyLApar{Mz, lam, N, m0, 1}, HalfB{Ph + HH, H, n0}, 0, H, o, smem);
+  tile_store2(DyStUnfold{C + blockIdx.z * NN, N, H, m0, n0}, e, o);
+}
+
+// inverse x, x whole: e = sum_k Q0(x, k) W(2k, r), o = sum_k Q1(x, k) W(2k+1, r) (W scaled
+// by lam when given, the 1D case); Y(x) = e + o, Y(N-1-x) = e - o for x < H
+template <int AM>
+__global__ void __launch_bounds__(256) k_dst_inv_fold(const double* Ph, const double* W, const double* lam,
+                                                      const int* iperm, double* Y, int ldy, int N, int Ny,
+                                                      int ncol, AxisMap ym) {
+  __shared__ double smem[GSMEM];
+  const int H = N / 2;
+  const long HH = (long)H * H;
+  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  const int R = ncol * Ny;
+  const int colt = (AM == 1) ? n0 / Ny : 0, yt = (AM == 1) ? n0 - colt * Ny : 0;
+  TileAcc e, o;
+  tile_zero(e);
+  tile_zero(o);
+  tile_gemm(HalfA{Ph + 2 * HH, H, m0}, DstLModePar<AM>{W, lam, N, Ny, n0, R, colt, yt, 0, ym}, 0, H, e, smem);
+  tile_gemm(HalfA{Ph + 3 * HH, H, m0}, DstLModePar<AM>{W, lam, N, Ny, n0, R, colt, yt, 1, ym}, 0, H, o, smem);
+  tile_store2(DstStScatterUnfold<AM>{Y, ldy, iperm, N, Ny, H, m0, n0, R, colt, yt, ym}, e, o);
+}
+
 static hm_status ensure_scale(Model* m, const double theta[4]) {
   bool same = true;
   for (int i = 0; i < 4; ++i) same = same && (m->lam_key[i] == theta[i]);
@@ -300,6 +501,70 @@ static void launch_inv(Model* m, dim3 g, const double* W, const double* lam, dou
                      cc, Mx, xm, ym);
 }
 
+// Transform launches for one block of cc columns.  An axis transformed whole (map
+// W = 0) of even length runs folded (half the multiply-adds); a compact half, or
+// an odd N, runs the plain GEMM over the points it has.
+static int amode(int ny) { return ny == 1 ? 2 : (ny % GBN == 0 ? 1 : 0); }
+static inline bool folds(const Model* m, AxisMap am) { return m->d_dsth && am.W == 0; }
+
+// Xh (N x cc*Ny) = S_x applied to the gathered columns (x compact per xm, y per ym)
+static void x_forward(Model* m, const double* X, int ldx, double* Xh, int cc, int Ny, AxisMap xm, AxisMap ym) {
+  const int N = m->N, am = amode(Ny);
+  if (folds(m, xm)) {
+    const int H = N / 2;
+    dim3 g(2 * ceil_div(H, GBM), ceil_div((long)cc * Ny, GBN));
+    if (am == 2) hipLaunchKernelGGL((k_dst_fwd_fold<2>), g, dim3(GCfg::NT), 0, m->stream, m->d_dsth, X, ldx, m->d_iperm, Xh, N, Ny, cc, ym);
+    else if (am == 1) hipLaunchKernelGGL((k_dst_fwd_fold<1>), g, dim3(GCfg::NT), 0, m->stream, m->d_dsth, X, ldx, m->d_iperm, Xh, N, Ny, cc, ym);
+    else hipLaunchKernelGGL((k_dst_fwd_fold<0>), g, dim3(GCfg::NT), 0, m->stream, m->d_dsth, X, ldx, m->d_iperm, Xh, N, Ny, cc, ym);
+    return;
+  }
+  const int Kx = xm.extent(N);
+  dim3 g(ceil_div(N, GBM), ceil_div((long)cc * Ny, GBN));
+  if (am == 2) launch_fwd<2>(m, g, X, ldx, Xh, N, Ny, cc, Kx, xm, ym);
+  else if (am == 1) launch_fwd<1>(m, g, X, ldx, Xh, N, Ny, cc, Kx, xm, ym);
+  else launch_fwd<0>(m, g, X, ldx, Xh, N, Ny, cc, Kx, xm, ym);
+}
+// C_c (N x N) = M_c (N x Nyin, compact per ym) transformed along y, for cc columns
+static void y_forward(Model* m, const double* M, double* C, int cc, AxisMap ym) {
+  const int N = m->N;
+  if (folds(m, ym)) {
+    dim3 g(ceil_div(N, GBM), 2 * ceil_div(N / 2, GBN), cc);
+    hipLaunchKernelGGL(k_dst_yf_fold, g, dim3(GCfg::NT), 0, m->stream, m->d_dsth, M, C, N);
+    return;
+  }
+  dim3 g(ceil_div(N, GBM), ceil_div(N, GBN), cc);
+  hipLaunchKernelGGL(k_dst_yf, g, dim3(GCfg::NT), 0, m->stream, m->d_dst, M, C, N, ym.extent(N), ym);
+}
+// C_c (N x Nyout, compact per ym) = (lam o M_c) transformed back along y
+static void y_inverse(Model* m, const double* M, const double* lam, double* C, int cc, AxisMap ym) {
+  const int N = m->N;
+  if (folds(m, ym)) {
+    dim3 g(ceil_div(N, GBM), ceil_div(N / 2, GBN), cc);
+    hipLaunchKernelGGL(k_dst_yi_fold, g, dim3(GCfg::NT), 0, m->stream, m->d_dsth, M, lam, C, N);
+    return;
+  }
+  const int Nyo = ym.extent(N);
+  dim3 g(ceil_div(N, GBM), ceil_div(Nyo, GBN), cc);
+  hipLaunchKernelGGL(k_dst_yi, g, dim3(GCfg::NT), 0, m->stream, m->d_dst, M, lam, C, N, Nyo, ym);
+}
+// Y (scattered to tree order; x compact per xm) = S_x applied to W (N x cc*Ny), scaled by lam if given
+static void x_inverse(Model* m, const double* W, const double* lam, double* Y, int ldy, int cc, int Ny, AxisMap xm,
+                      AxisMap ym) {
+  const int N = m->N, am = amode(Ny);
+  if (folds(m, xm)) {
+    dim3 g(ceil_div(N / 2, GBM), ceil_div((long)cc * Ny, GBN));
+    if (am == 2) hipLaunchKernelGGL((k_dst_inv_fold<2>), g, dim3(GCfg::NT), 0, m->stream, m->d_dsth, W, lam, m->d_iperm, Y, ldy, N, Ny, cc, ym);
+    else if (am == 1) hipLaunchKernelGGL((k_dst_inv_fold<1>), g, dim3(GCfg::NT), 0, m->stream, m->d_dsth, W, lam, m->d_iperm, Y, ldy, N, Ny, cc, ym);
+    else hipLaunchKernelGGL((k_dst_inv_fold<0>), g, dim3(GCfg::NT), 0, m->stream, m->d_dsth, W, lam, m->d_iperm, Y, ldy, N, Ny, cc, ym);
+    return;
+  }
+  const int Mx = xm.extent(N);
+  dim3 g(ceil_div(Mx, GBM), ceil_div((long)cc * Ny, GBN));
+  if (am == 2) launch_inv<2>(m, g, W, lam, Y, ldy, N, Ny, cc, Mx, xm, ym);
+  else if (am == 1) launch_inv<1>(m, g, W, lam, Y, ldy, N, Ny, cc, Mx, xm, ym);
+  else launch_inv<0>(m, g, W, lam, Y, ldy, N, Ny, cc, Mx, xm, ym);
+}
+
 hm_status kapply_sel(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK,
                      double* outKap, double* outAlp, int ldo, LeafSel in_sel, LeafSel out_sel) {
   if (c <= 0) return HM_OK;
@@ -320,40 +585,31 @@ hm_status kapply_sel(Model* m, const double theta[4], const double* X, int ldx, 
   const bool pf = prof_on(m, PF_DST);
   int nout = 0;
   for (int q = 0; q < 3; ++q) nout += outs[q] ? 1 : 0;
-  // algorithmic work of the transform GEMMs actually run, per column
-  const double fl_fwd = 2.0 * N * Kx * Nyi + (two ? 2.0 * N * Nyi * (double)N : 0.0);
-  const double fl_out = (two ? 2.0 * N * N * (double)Nyo : 0.0) + 2.0 * Mx * N * (double)Nyo;
+  // work of the transform GEMMs actually run, per column (a folded axis halves its GEMM)
+  const double fx_in = folds(m, xin) ? 0.5 : 1.0, fy_in = folds(m, yin) ? 0.5 : 1.0;
+  const double fx_out = folds(m, xout) ? 0.5 : 1.0, fy_out = folds(m, yout) ? 0.5 : 1.0;
+  const double fl_fwd = fx_in * 2.0 * N * Kx * Nyi + (two ? fy_in * 2.0 * N * Nyi * (double)N : 0.0);
+  const double fl_out = (two ? fy_out * 2.0 * N * N * (double)Nyo : 0.0) + fx_out * 2.0 * Mx * N * (double)Nyo;
   const double per_col = fl_fwd + nout * fl_out;
   if (pf) prof_begin(m, PF_DST);
-  auto amode = [](int ny) { return ny == 1 ? 2 : (ny % GBN == 0 ? 1 : 0); };
   for (int c0 = 0; c0 < c; c0 += m->cmax) {
     const int cc = std::min(m->cmax, c - c0);
-    const double* Xc = X + (long)c0 * ldx;
-    dim3 gx(ceil_div(N, GBM), ceil_div((long)cc * Nyi, GBN));
-    const int ami = amode(Nyi);
-    if (ami == 2) launch_fwd<2>(m, gx, Xc, ldx, Xh, N, Nyi, cc, Kx, xin, yin);
-    else if (ami == 1) launch_fwd<1>(m, gx, Xc, ldx, Xh, N, Nyi, cc, Kx, xin, yin);
-    else launch_fwd<0>(m, gx, Xc, ldx, Xh, N, Nyi, cc, Kx, xin, yin);
+    x_forward(m, X + (long)c0 * ldx, ldx, Xh, cc, Nyi, xin, yin);
     HM_LAUNCH_CHECK();
     if (two) {
-      dim3 gy(ceil_div(N, GBM), ceil_div(N, GBN), cc);
-      hipLaunchKernelGGL(k_dst_yf, gy, dim3(GCfg::NT), 0, m->stream, m->d_dst, Xh, X2, N, Nyi, yin);
+      y_forward(m, Xh, X2, cc, yin);
       HM_LAUNCH_CHECK();
     }
-    const int amo = amode(Nyo);
     for (int q = 0; q < 3; ++q) {
       if (!outs[q]) continue;
       const double* lam = m->d_lam + q * NN;
       double* Yc = outs[q] + (long)c0 * ldo;
-      dim3 gi(ceil_div(Mx, GBM), ceil_div((long)cc * Nyo, GBN));
       if (two) {
-        dim3 gy(ceil_div(N, GBM), ceil_div(Nyo, GBN), cc);
-        hipLaunchKernelGGL(k_dst_yi, gy, dim3(GCfg::NT), 0, m->stream, m->d_dst, X2, lam, X3, N, Nyo, yout);
+        y_inverse(m, X2, lam, X3, cc, yout);
         HM_LAUNCH_CHECK();
-        if (amo == 1) launch_inv<1>(m, gi, X3, nullptr, Yc, ldo, N, Nyo, cc, Mx, xout, yout);
-        else launch_inv<0>(m, gi, X3, nullptr, Yc, ldo, N, Nyo, cc, Mx, xout, yout);
+        x_inverse(m, X3, nullptr, Yc, ldo, cc, Nyo, xout, yout);
       } else {
-        launch_inv<2>(m, gi, Xh, lam, Yc, ldo, N, 1, cc, Mx, xout, yout);
+        x_inverse(m, Xh, lam, Yc, ldo, cc, 1, xout, yout);
       }
       HM_LAUNCH_CHECK();
     }
@@ -380,6 +636,10 @@ hm_status model_tables(Model* m) {
   hipLaunchKernelGGL(k_tables, dim3(ceil_div((long)N * N, 256)), dim3(256), 0, m->stream, m->d_dst, m->d_mu, N,
                      m->dim);
   HM_LAUNCH_CHECK();
+  if (m->d_dsth) {
+    hipLaunchKernelGGL(k_tables_half, dim3(ceil_div((long)N * N, 256)), dim3(256), 0, m->stream, m->d_dsth, N);
+    HM_LAUNCH_CHECK();
+  }
   return HM_OK;
 }
 
@@ -409,35 +669,27 @@ hm_status kvjp(Model* m, const double theta[4], const double* X, int ldx, const 
   double* W0 = m->d_ws;
   double* W1 = m->d_ws + (long)n * m->cmax;
   double* W2 = m->d_ws + 2L * n * m->cmax;
-  const int am = (Ny == 1) ? 2 : (Ny % GBN == 0 ? 1 : 0);
   const AxisMap id{0, 0};
   for (int c0 = 0; c0 < c; c0 += m->cmax) {
     const int cc = std::min(m->cmax, c - c0);
-    dim3 gx(ceil_div(N, GBM), ceil_div((long)cc * Ny, GBN));
-    dim3 gy(ceil_div(N, GBM), ceil_div(N, GBN), cc);
     const double* Xc = X + (long)c0 * ldx;
     const double* Bc = Yb + (long)c0 * ldb;
     const double *ha, *hb;
-    auto fwd = [&](const double* src, int ld, double* dst) {
-      if (am == 2) launch_fwd<2>(m, gx, src, ld, dst, N, Ny, cc, N, id, id);
-      else if (am == 1) launch_fwd<1>(m, gx, src, ld, dst, N, Ny, cc, N, id, id);
-      else launch_fwd<0>(m, gx, src, ld, dst, N, Ny, cc, N, id, id);
-    };
     if (m->dim == 2) {
-      fwd(Xc, ldx, W0);
+      x_forward(m, Xc, ldx, W0, cc, Ny, id, id);
       HM_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_dst_yf, gy, dim3(GCfg::NT), 0, m->stream, m->d_dst, W0, W1, N, N, id);
+      y_forward(m, W0, W1, cc, id);
       HM_LAUNCH_CHECK();
-      fwd(Bc, ldb, W2);
+      x_forward(m, Bc, ldb, W2, cc, Ny, id, id);
       HM_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_dst_yf, gy, dim3(GCfg::NT), 0, m->stream, m->d_dst, W2, W0, N, N, id);
+      y_forward(m, W2, W0, cc, id);
       HM_LAUNCH_CHECK();
       ha = W1;
       hb = W0;
     } else {
-      fwd(Xc, ldx, W0);
+      x_forward(m, Xc, ldx, W0, cc, Ny, id, id);
       HM_LAUNCH_CHECK();
-      fwd(Bc, ldb, W1);
+      x_forward(m, Bc, ldb, W1, cc, Ny, id, id);
       HM_LAUNCH_CHECK();
       ha = W0;
       hb = W1;
