@@ -79,18 +79,26 @@ __global__ void k_transpose_nodes(const double* R, double* RT, long stride, int 
 struct OutLA {
   const double* p; int ld, m0, nl;
   static constexpr bool kfast = false;
-  __device__ double operator()(int i, int k) const {
-    int r = m0 + i;
-    return r < nl ? p[r + (long)k * ld] : 0.0;
+  static constexpr int NR = 1;
+  __device__ bool load(int i, int k, double (&r)[1]) const {
+    const int row = m0 + i;
+    const bool ok = row < nl;
+    r[0] = p[(ok ? row : 0) + (long)k * ld];
+    return ok;
   }
+  __device__ double fin(const double (&r)[1]) const { return r[0]; }
 };
 struct OutLB {
   const double* p; int ld, n0, nl;
   static constexpr bool kfast = false;
-  __device__ double operator()(int k, int j) const {
-    int c = n0 + j;
-    return c < nl ? p[c + (long)k * ld] : 0.0;
+  static constexpr int NR = 1;
+  __device__ bool load(int k, int j, double (&r)[1]) const {
+    const int c = n0 + j;
+    const bool ok = c < nl;
+    r[0] = p[(ok ? c : 0) + (long)k * ld];
+    return ok;
   }
+  __device__ double fin(const double (&r)[1]) const { return r[0]; }
 };
 struct LeafAdjSt {
   double* Zb; const double* Dinv; const double* z; int ldz, nl, m0, n0; long r0;

@@ -1,115 +1,45 @@
-// FP64 tile-GEMM core shared by all panel/leaf/transform kernels.
+// FP64 tile-GEMM core shared by the transform, leaf and generic GEMM kernels.
 //
-// A workgroup of NT = (BM/TM)*(BN/TN) threads computes a BM x BN tile of
-// C = sum_k A(i,k) B(k,j).  Operands are fetched through loader functors so the
-// same core serves plain column-major GEMMs, per-leaf panel products with tree
-// addressing, and the sine transform with the tree<->grid gather fused into the
-// load.  Tiles are staged through LDS; each thread keeps a TM x TN register
-// tile whose rows/columns are strided by BM/TM and BN/TN (conflict-free LDS
-// reads for 8-byte elements).
+// A workgroup of 256 threads (4 wavefronts) computes a 64 x 64 tile of
+// C = sum_k A(i,k) B(k,j) on the matrix cores.  Operands are fetched through
+// loader functors, so the same core serves plain column-major GEMMs, per-leaf
+// products and the sine transforms with the tree<->grid reordering computed in
+// the load.  K-slabs of 16 are staged through double-buffered LDS.
+//
+// Loader protocol (A indexed (i, k), B indexed (k, j)):
+//   static constexpr bool kfast;   consecutive k adjacent in memory
+//   static constexpr int NR;       raw values loaded per element
+//   bool load(int, int, double (&raw)[NR]) const;
+//       issues the loads only, always at a valid address (an element outside the
+//       operand reads a dummy one) and returns whether the element is inside;
+//   double fin(const double (&raw)[NR]) const;
+//       the element from its raw values (products, sums), evaluated when the
+//       slab is written to LDS.
+// Keeping the arithmetic out of the load phase and the loads free of branches
+// lets every load of a slab be in flight at once.
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace hm {
 
-template <int BM, int BN, int BK, int TM, int TN>
-struct TileCfg {
-  static constexpr int NT = (BM / TM) * (BN / TN);
-  static constexpr int RS = BM / TM;   // row stride of a thread's register tile
-  static constexpr int CS = BN / TN;   // column stride
-  static constexpr int LDS_A = BK * (BM + 1);
-  static constexpr int LDS_B = BK * (BN + 1);
+constexpr int GBM = 64, GBN = 64, GBK = 16;
+struct GCfg {
+  static constexpr int NT = 256;
+  static constexpr int LDS_A = GBK * (GBM + 1);
+  static constexpr int LDS_B = GBK * (GBN + 1);
   static constexpr int LDS_DOUBLES = LDS_A + LDS_B;
 };
-
-// LA: double operator()(int i, int k) const  -- i in [0,BM) tile row, k global
-//     static constexpr bool kfast            -- consecutive k adjacent in memory
-// LB: double operator()(int k, int j) const  -- j in [0,BN) tile column
-template <int BM, int BN, int BK, int TM, int TN, class LA, class LB>
-__device__ __forceinline__ void tile_gemm_acc(const LA& la, const LB& lb, int k0, int k1,
-                                              double (&acc)[TM][TN], double* smem) {
-  using C = TileCfg<BM, BN, BK, TM, TN>;
-  double* As = smem;             // [BK][BM+1]
-  double* Bs = smem + C::LDS_A;  // [BK][BN+1]
-  const int tid = threadIdx.x;
-  const int tr = tid / C::CS;
-  const int tc = tid % C::CS;
-  for (int kb = k0; kb < k1; kb += BK) {
-    // ---- stage A tile
-#pragma unroll
-    for (int e0 = 0; e0 < BM * BK; e0 += C::NT) {
-      int e = e0 + tid;
-      int i, kk;
-      if (LA::kfast) { kk = e % BK; i = e / BK; } else { i = e % BM; kk = e / BM; }
-      int k = kb + kk;
-      As[kk * (BM + 1) + i] = (k < k1) ? la(i, k) : 0.0;
-    }
-    // ---- stage B tile
-#pragma unroll
-    for (int e0 = 0; e0 < BN * BK; e0 += C::NT) {
-      int e = e0 + tid;
-      int j, kk;
-      if (LB::kfast) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
-      int k = kb + kk;
-      Bs[kk * (BN + 1) + j] = (k < k1) ? lb(k, j) : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < BK; ++kk) {
-      double a[TM], b[TN];
-#pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = As[kk * (BM + 1) + tr + i * C::RS];
-#pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = Bs[kk * (BN + 1) + tc + j * C::CS];
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-    }
-    __syncthreads();
-  }
-}
-
-template <int BM, int BN, int TM, int TN>
-__device__ __forceinline__ void tile_zero(double (&acc)[TM][TN]) {
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) acc[i][j] = 0.0;
-}
-
-// ST: void operator()(int i, int j, double v) const  (tile-relative; does its own bounds)
-template <int BM, int BN, int BK, int TM, int TN, class ST>
-__device__ __forceinline__ void tile_store(const ST& st, const double (&acc)[TM][TN]) {
-  using C = TileCfg<BM, BN, BK, TM, TN>;
-  const int tid = threadIdx.x;
-  const int tr = tid / C::CS;
-  const int tc = tid % C::CS;
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) st(tr + i * C::RS, tc + j * C::CS, acc[i][j]);
-}
-
-// Standard configuration used by the panel kernels: 64 x 64 tiles, 256 threads.
-constexpr int GBM = 64, GBN = 64, GBK = 16, GTM = 4, GTN = 4;
-using GCfg = TileCfg<GBM, GBN, GBK, GTM, GTN>;
 // LDS doubles a kernel must reserve for tile_gemm (two slabs)
 constexpr int GSMEM = 2 * GCfg::LDS_DOUBLES;
 
 // ---------------------------------------------------------------------------
-// Matrix-core path (CDNA3/CDNA4 v_mfma_f64_16x16x4_f64).  The 64 x 64 tile is
-// split over the 4 wavefronts of the workgroup, each owning a 32 x 32 quadrant
-// made of 2 x 2 blocks of 16 x 16.  Operand lane layout of the instruction:
-// lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator element
-// v of lane l is D[4 v + l / 16][l % 16].  Same LDS staging as the FMA path.
+// Matrix-core path (v_mfma_f64_16x16x4_f64).  The 64 x 64 tile is split over the
+// 4 wavefronts, each owning a 32 x 32 quadrant made of 2 x 2 blocks of 16 x 16.
+// Operand lane layout of the instruction: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; accumulator element v of lane l is D[4 v + l / 16][l % 16].
 // ---------------------------------------------------------------------------
-#ifndef HM_MFMA
-#define HM_MFMA 1
-#endif
 typedef double hm_v4d __attribute__((ext_vector_type(4)));
 
-#if HM_MFMA
 struct TileAcc {
   hm_v4d c[2][2];
 };
@@ -123,7 +53,7 @@ __device__ __forceinline__ void tile_zero(TileAcc& acc) {
 // consumed from LDS (double-buffered), so one barrier per slab and two global
 // round trips overlap each slab's matrix-core work.  The slab loop is unrolled by
 // two so that the two register sets alternate statically (a register copy would
-// wait for its loads).  smem must hold 2 * GCfg::LDS_DOUBLES.
+// wait for its loads).  smem must hold GSMEM doubles.
 template <class LA, class LB>
 __device__ __forceinline__ void tile_gemm(const LA& la, const LB& lb, int k0, int k1, TileAcc& acc, double* smem) {
   constexpr int BM = GBM, BN = GBN, BK = GBK, NT = GCfg::NT;
@@ -133,24 +63,33 @@ __device__ __forceinline__ void tile_gemm(const LA& la, const LB& lb, int k0, in
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
   struct Regs {
-    double a[NA], b[NB];
+    double a[NA][LA::NR], b[NB][LB::NR];
+    bool va[NA], vb[NB];
+  };
+  auto a_index = [&](int q, int& i, int& kk) {
+    const int e = q * NT + tid;
+    if (LA::kfast) { kk = e % BK; i = e / BK; } else { i = e % BM; kk = e / BM; }
+  };
+  auto b_index = [&](int q, int& j, int& kk) {
+    const int e = q * NT + tid;
+    if (LB::kfast) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
   };
   auto fetch = [&](int kb, Regs& r) {
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
-      int e = q * NT + tid;
       int i, kk;
-      if (LA::kfast) { kk = e % BK; i = e / BK; } else { i = e % BM; kk = e / BM; }
-      int k = kb + kk;
-      r.a[q] = (k < k1) ? la(i, k) : 0.0;
+      a_index(q, i, kk);
+      const int k = kb + kk;
+      const bool kin = k < k1;
+      r.va[q] = la.load(i, kin ? k : k0, r.a[q]) && kin;
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-      int e = q * NT + tid;
       int j, kk;
-      if (LB::kfast) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
-      int k = kb + kk;
-      r.b[q] = (k < k1) ? lb(k, j) : 0.0;
+      b_index(q, j, kk);
+      const int k = kb + kk;
+      const bool kin = k < k1;
+      r.vb[q] = lb.load(kin ? k : k0, j, r.b[q]) && kin;
     }
   };
   auto stash = [&](const Regs& r, double* buf) {
@@ -158,17 +97,15 @@ __device__ __forceinline__ void tile_gemm(const LA& la, const LB& lb, int k0, in
     double* Bs = buf + GCfg::LDS_A;
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
-      int e = q * NT + tid;
       int i, kk;
-      if (LA::kfast) { kk = e % BK; i = e / BK; } else { i = e % BM; kk = e / BM; }
-      As[kk * (BM + 1) + i] = r.a[q];
+      a_index(q, i, kk);
+      As[kk * (BM + 1) + i] = r.va[q] ? la.fin(r.a[q]) : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-      int e = q * NT + tid;
       int j, kk;
-      if (LB::kfast) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
-      Bs[kk * (BN + 1) + j] = r.b[q];
+      b_index(q, j, kk);
+      Bs[kk * (BN + 1) + j] = r.vb[q] ? lb.fin(r.b[q]) : 0.0;
     }
   };
   auto compute = [&](const double* buf) {
@@ -214,6 +151,7 @@ __device__ __forceinline__ void tile_gemm(const LA& la, const LB& lb, int k0, in
   // the last slab's LDS reads are done before a caller reuses smem
   __syncthreads();
 }
+// ST: void operator()(int i, int j, double v) const  (tile-relative; does its own bounds)
 template <class ST>
 __device__ __forceinline__ void tile_store(const ST& st, const TileAcc& acc) {
   const int tid = threadIdx.x;
@@ -271,28 +209,5 @@ struct MfmaPrec<1> {
   static __device__ __forceinline__ V mfma(T a, T b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
   static __device__ __forceinline__ int row(int v, int lk) { return 4 * lk + v; }
 };
-#else
-struct TileAcc {
-  double c[GTM][GTN];
-};
-__device__ __forceinline__ void tile_zero(TileAcc& acc) { tile_zero<GBM, GBN, GTM, GTN>(acc.c); }
-constexpr int GSMEM_FMA = GCfg::LDS_DOUBLES;
-template <class LA, class LB>
-__device__ __forceinline__ void tile_gemm(const LA& la, const LB& lb, int k0, int k1, TileAcc& acc, double* smem) {
-  tile_gemm_acc<GBM, GBN, GBK, GTM, GTN>(la, lb, k0, k1, acc.c, smem);
-}
-template <class ST>
-__device__ __forceinline__ void tile_store(const ST& st, const TileAcc& acc) {
-  tile_store<GBM, GBN, GBK, GTM, GTN>(st, acc.c);
-}
-template <class ST>
-__device__ __forceinline__ void tile_store2(const ST& st, const TileAcc& e, const TileAcc& o) {
-  const int tr = threadIdx.x / GCfg::CS, tc = threadIdx.x % GCfg::CS;
-#pragma unroll
-  for (int i = 0; i < GTM; ++i)
-#pragma unroll
-    for (int j = 0; j < GTN; ++j) st(tr + i * GCfg::RS, tc + j * GCfg::CS, e.c[i][j], o.c[i][j]);
-}
-#endif
 
 }  // namespace hm

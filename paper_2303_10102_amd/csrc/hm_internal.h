@@ -60,6 +60,32 @@ struct ProfRec {
   double flops, bytes;
 };
 
+// Grid point (x, y) -> tree position, the closed form of the uniform bisection
+// (splits alternate x, y, x, ... from the root; leaves wl x hl): the leaf index
+// interleaves the bits of x / wl and y / hl in split order, and
+//   t = leaf * nl + (x mod wl) + (y mod hl) * wl.
+// One-dimensional models keep grid order.  The quotients use reciprocal
+// multipliers ceil(2^32 / w), exact for coordinates and extents up to 2^16.
+struct TreeIdx {
+  int two, wl, hl, nl, sx, sy;
+  unsigned mx, my;
+  __host__ __device__ static unsigned spread(unsigned v) {   // bit b -> bit 2b (16 bits)
+    v &= 0xFFFFu;
+    v = (v | (v << 8)) & 0x00FF00FFu;
+    v = (v | (v << 4)) & 0x0F0F0F0Fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+  }
+  __device__ __forceinline__ int operator()(int x, int y) const {
+    if (!two) return x;
+    const unsigned xh = __umulhi((unsigned)x, mx), yh = __umulhi((unsigned)y, my);
+    const unsigned L = (spread(xh) << sx) | (spread(yh) << sy);
+    return (int)(L * (unsigned)nl + ((unsigned)x - xh * wl) + ((unsigned)y - yh * hl) * wl);
+  }
+};
+TreeIdx make_tree_idx(int dim, int N, int levels);
+
 struct Model {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -67,6 +93,7 @@ struct Model {
   double h = 0.0;
   int* d_perm = nullptr;    // tree position -> grid index
   int* d_iperm = nullptr;   // grid index -> tree position
+  TreeIdx tix{};            // closed form of iperm for the transforms
   double* d_dst = nullptr;  // N x N orthonormal DST-I
   double* d_dsth = nullptr; // N even: its even/odd halves P0, P1, Q0, Q1 (each N/2 x N/2)
   double* d_mu = nullptr;   // N eigenvalues of the 1D -Laplacian

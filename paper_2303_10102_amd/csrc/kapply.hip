@@ -98,7 +98,7 @@ __global__ void k_mode_scale(double* lam, const double* mu, int N, int Ny, doubl
 }
 
 // ---------------------------------------------------------------------------
-// sine transforms with fused tree<->grid permutation
+// sine transforms with the tree<->grid reordering computed in the loads
 //
 // Axis maps.  A sketch pass at depth l reads an input that is zero outside one
 // side (left or right children) of the depth-l split and needs the output only on
@@ -107,13 +107,25 @@ __global__ void k_mode_scale(double* lam, const double* mu, int N, int Ny, doubl
 // (the chunks of parity par); W = 0 is the whole axis.  The transforms then run
 // over the compact half: the forward x-transform sums only the input's x, the
 // y-transforms only the input's / needed y, the inverse x-transform writes only
-// the needed x.
+// the needed x.  The quotient uses a reciprocal multiplier: for t < 2^16 and
+// W <= 2^16, t / W = umulhi(t, ceil(2^32 / W)) exactly.
 // ---------------------------------------------------------------------------
 struct AxisMap {
   int W, par;
-  __host__ __device__ int operator()(int t) const { return W ? (t / W) * 2 * W + par * W + t % W : t; }
+  unsigned mw;
+  __host__ __device__ int operator()(int t) const {
+#ifdef __HIP_DEVICE_COMPILE__
+    if (!W) return t;
+    const int q = (int)__umulhi((unsigned)t, mw);
+    return q * 2 * W + par * W + (t - q * W);
+#else
+    return W ? (t / W) * 2 * W + par * W + t % W : t;
+#endif
+  }
   __host__ __device__ int extent(int n) const { return W ? n / 2 : n; }
 };
+static inline unsigned recip32(int w) { return w > 0 ? (unsigned)((0x100000000ULL + (unsigned)w - 1) / (unsigned)w) : 0u; }
+static inline AxisMap axis_map(int W, int par) { return AxisMap{W, par, recip32(W)}; }
 
 // Column r of a transform operand is (col, y') = (r / Ny, r % Ny) over the compact
 // y range Ny.  AM: 0 general division, 1 a tile of GBN columns lies inside one
@@ -124,48 +136,78 @@ __device__ __forceinline__ void split_col(int r, int Ny, int colt, int yt, int j
   else if (AM == 1) { col = colt; y = yt + j; }
   else { col = r / Ny; y = r - col * Ny; }
 }
+// Column geometry shared by the loaders and stores that address tree-ordered data:
+// columns r = n0 + j < R of the compact (col, y') enumeration; an index past R maps
+// to (0, 0) so that its dummy load stays inside the operand.
+template <int AM>
+struct ColGeo {
+  int Ny, n0, R, colt, yt;
+  __device__ __forceinline__ bool at(int j, int& col, int& y) const {
+    const int r = n0 + j;
+    if (r >= R) { col = 0; y = 0; return false; }
+    split_col<AM>(r, Ny, colt, yt, j, col, y);
+    return true;
+  }
+};
+template <int AM>
+__device__ __forceinline__ ColGeo<AM> col_geo(int Ny, int n0, int ncol) {
+  const int colt = (AM == 1) ? n0 / Ny : 0, yt = (AM == 1) ? n0 - colt * Ny : 0;
+  return ColGeo<AM>{Ny, n0, ncol * Ny, colt, yt};
+}
+
 struct DstLS {  // A(i, k) = S(m0 + i, xmap(k))   (S symmetric, N x N)
   const double* S; int N, m0; AxisMap xm;
   static constexpr bool kfast = false;
-  __device__ double operator()(int i, int k) const {
-    int p = m0 + i;
-    return p < N ? S[p + (long)xm(k) * N] : 0.0;
+  static constexpr int NR = 1;
+  __device__ bool load(int i, int k, double (&r)[1]) const {
+    const int p = m0 + i;
+    const bool ok = p < N;
+    r[0] = S[(ok ? p : 0) + (long)xm(k) * N];
+    return ok;
   }
+  __device__ double fin(const double (&r)[1]) const { return r[0]; }
 };
-struct DstLSrow {  // A(i, k) = S(xmap(m0 + i), k) for i < Mx
+struct DstLSrow {  // A(i, k) = S(xmap(m0 + i), k) for m0 + i < Mx
   const double* S; int N, m0, Mx; AxisMap xm;
   static constexpr bool kfast = false;
-  __device__ double operator()(int i, int k) const {
-    int r = m0 + i;
-    return r < Mx ? S[xm(r) + (long)k * N] : 0.0;
+  static constexpr int NR = 1;
+  __device__ bool load(int i, int k, double (&r)[1]) const {
+    const int x = m0 + i;
+    const bool ok = x < Mx;
+    r[0] = S[xm(ok ? x : 0) + (long)k * N];
+    return ok;
   }
+  __device__ double fin(const double (&r)[1]) const { return r[0]; }
 };
 template <int AM>
-struct DstLGather {  // B(k, j) = X[col*ldx + iperm[ymap(y')*N + xmap(k)]]
-  const double* X; int ldx; const int* iperm; int N, Ny, n0, R, colt, yt; AxisMap xm, ym;
+struct DstLGather {  // B(k, j) = X[col ldx + tree(xmap(k), ymap(y'))]
+  const double* X; int ldx; TreeIdx tix; ColGeo<AM> cg; AxisMap xm, ym;
   static constexpr bool kfast = true;
-  __device__ double operator()(int k, int j) const {
-    int r = n0 + j;
-    if (r >= R) return 0.0;
+  static constexpr int NR = 1;
+  __device__ bool load(int k, int j, double (&r)[1]) const {
     int col, y;
-    split_col<AM>(r, Ny, colt, yt, j, col, y);
-    return X[(long)col * ldx + iperm[ym(y) * N + xm(k)]];
+    const bool ok = cg.at(j, col, y);
+    r[0] = X[(long)col * ldx + tix(xm(k), ym(y))];
+    return ok;
   }
+  __device__ double fin(const double (&r)[1]) const { return r[0]; }
 };
-template <int AM>
-struct DstLMode {  // B(p, r) = W[p + r*N] (optionally scaled by lam[p + ymap(y')*N], 1D: lam[p])
-  const double* W; const double* lam; int N, Ny, n0, R, colt, yt; AxisMap ym;
+template <int AM, bool LAM>
+struct DstLMode {  // B(p, r) = W[p + r N], times lam[p + ymap(y') N] when LAM (1D: lam[p])
+  const double* W; const double* lam; int N; ColGeo<AM> cg; AxisMap ym;
   static constexpr bool kfast = true;
-  __device__ double operator()(int k, int j) const {
-    int r = n0 + j;
-    if (r >= R) return 0.0;
-    double v = W[k + (long)r * N];
-    if (lam) {
-      int col, y;
-      split_col<AM>(r, Ny, colt, yt, j, col, y);
-      v *= lam[k + (long)ym(y) * N];
-    }
-    return v;
+  static constexpr int NR = LAM ? 2 : 1;
+  __device__ bool load(int k, int j, double (&r)[NR]) const {
+    int col, y;
+    const bool ok = cg.at(j, col, y);
+    const int rr = ok ? cg.n0 + j : 0;
+    r[0] = W[k + (long)rr * N];
+    if constexpr (LAM) r[1] = lam[k + (long)ym(y) * N];
+    return ok;
+  }
+  __device__ double fin(const double (&r)[NR]) const {
+    if constexpr (LAM) return r[0] * r[1];
+    else return r[0];
   }
 };
 struct DstStMode {
@@ -176,63 +218,75 @@ struct DstStMode {
   }
 };
 template <int AM>
-struct DstStScatter {  // Y[col*ldy + iperm[ymap(y')*N + xmap(i)]]
-  double* Y; int ldy; const int* iperm; int N, Ny, m0, n0, Mx, R, colt, yt; AxisMap xm, ym;
+struct DstStScatter {  // Y[col ldy + tree(xmap(x'), ymap(y'))]
+  double* Y; int ldy; TreeIdx tix; ColGeo<AM> cg; int m0, Mx; AxisMap xm, ym;
   __device__ void operator()(int i, int j, double v) const {
-    int xi = m0 + i, r = n0 + j;
-    if (xi >= Mx || r >= R) return;
+    const int xi = m0 + i;
     int col, y;
-    split_col<AM>(r, Ny, colt, yt, j, col, y);
-    Y[(long)col * ldy + iperm[ym(y) * N + xm(xi)]] = v;
+    if (xi >= Mx || !cg.at(j, col, y)) return;
+    Y[(long)col * ldy + tix(xm(xi), ym(y))] = v;
   }
 };
 // y-direction transforms of every column's N x Nyin block M (rows p, cols y'):
 //   forward  C_c(p, q)  = sum_{y'} M_c(p, y') S(ymap(y'), q)          (Nyin compact, q full)
 //   inverse  C_c(p, y') = sum_q (lam o M_c)(p, q) S(q, ymap(y'))      (q full, y' compact)
+template <bool LAM>
 struct DyLA {
   const double* M; const double* lam; int N, m0;
   static constexpr bool kfast = false;
-  __device__ double operator()(int i, int k) const {
-    int p = m0 + i;
-    if (p >= N) return 0.0;
-    double v = M[p + (long)k * N];
-    if (lam) v *= lam[p + (long)k * N];
-    return v;
+  static constexpr int NR = LAM ? 2 : 1;
+  __device__ bool load(int i, int k, double (&r)[NR]) const {
+    const int p = m0 + i;
+    const bool ok = p < N;
+    const long e = (ok ? p : 0) + (long)k * N;
+    r[0] = M[e];
+    if constexpr (LAM) r[1] = lam[e];
+    return ok;
+  }
+  __device__ double fin(const double (&r)[NR]) const {
+    if constexpr (LAM) return r[0] * r[1];
+    else return r[0];
   }
 };
 struct DyLBfwd {  // B(k, j) = S(ymap(k), n0 + j)
   const double* S; int N, n0; AxisMap ym;
   static constexpr bool kfast = true;
-  __device__ double operator()(int k, int j) const {
-    int q = n0 + j;
-    return q < N ? S[ym(k) + (long)q * N] : 0.0;
+  static constexpr int NR = 1;
+  __device__ bool load(int k, int j, double (&r)[1]) const {
+    const int q = n0 + j;
+    const bool ok = q < N;
+    r[0] = S[ym(k) + (long)(ok ? q : 0) * N];
+    return ok;
   }
+  __device__ double fin(const double (&r)[1]) const { return r[0]; }
 };
-struct DyLBinv {  // B(k, j) = S(k, ymap(n0 + j)) for j < Nout
+struct DyLBinv {  // B(k, j) = S(k, ymap(n0 + j)) for n0 + j < Nout
   const double* S; int N, n0, Nout; AxisMap ym;
   static constexpr bool kfast = true;
-  __device__ double operator()(int k, int j) const {
-    int c = n0 + j;
-    return c < Nout ? S[k + (long)ym(c) * N] : 0.0;
+  static constexpr int NR = 1;
+  __device__ bool load(int k, int j, double (&r)[1]) const {
+    const int c = n0 + j;
+    const bool ok = c < Nout;
+    r[0] = S[k + (long)ym(ok ? c : 0) * N];
+    return ok;
   }
+  __device__ double fin(const double (&r)[1]) const { return r[0]; }
 };
 
-// Xh(p, r) = sum_{x'} S(p, xmap(x')) X[col*ldx + iperm[ymap(y')*N + xmap(x')]],  r = col*Ny + y'
+// Xh(p, r) = sum_{x'} S(p, xmap(x')) X[col ldx + tree(xmap(x'), ymap(y'))],  r = col Ny + y'
 template <int AM>
-__global__ void __launch_bounds__(256) k_dst_fwd(const double* S, const double* X, int ldx, const int* iperm,
+__global__ void __launch_bounds__(256) k_dst_fwd(const double* S, const double* X, int ldx, TreeIdx tix,
                                                  double* Xh, int N, int Ny, int ncol, int Kx, AxisMap xm,
                                                  AxisMap ym) {
   __shared__ double smem[GSMEM];
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
-  const int R = ncol * Ny;
-  const int colt = (AM == 1) ? n0 / Ny : 0, yt = (AM == 1) ? n0 - colt * Ny : 0;
+  const ColGeo<AM> cg = col_geo<AM>(Ny, n0, ncol);
   DstLS la{S, N, m0, xm};
-  DstLGather<AM> lb{X, ldx, iperm, N, Ny, n0, R, colt, yt, xm, ym};
+  DstLGather<AM> lb{X, ldx, tix, cg, xm, ym};
   TileAcc acc;
   tile_zero(acc);
   tile_gemm(la, lb, 0, Kx, acc, smem);
-  DstStMode st{Xh, N, m0, n0, R};
-  tile_store(st, acc);
+  tile_store(DstStMode{Xh, N, m0, n0, cg.R}, acc);
 }
 
 // forward y: C_c = M_c S[ymap(.), :]  (M_c: N x Nyin at c*N*Nyin; C_c: N x N at c*N*N)
@@ -240,7 +294,7 @@ __global__ void __launch_bounds__(256) k_dst_yf(const double* S, const double* M
                                                 AxisMap ym) {
   __shared__ double smem[GSMEM];
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
-  DyLA la{M + (long)blockIdx.z * N * Nyin, nullptr, N, m0};
+  DyLA<false> la{M + (long)blockIdx.z * N * Nyin, nullptr, N, m0};
   DyLBfwd lb{S, N, n0, ym};
   TileAcc acc;
   tile_zero(acc);
@@ -254,7 +308,7 @@ __global__ void __launch_bounds__(256) k_dst_yi(const double* S, const double* M
                                                 int N, int Nyout, AxisMap ym) {
   __shared__ double smem[GSMEM];
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
-  DyLA la{M + (long)blockIdx.z * N * N, lam, N, m0};
+  DyLA<true> la{M + (long)blockIdx.z * N * N, lam, N, m0};
   DyLBinv lb{S, N, n0, Nyout, ym};
   TileAcc acc;
   tile_zero(acc);
@@ -263,89 +317,108 @@ __global__ void __launch_bounds__(256) k_dst_yi(const double* S, const double* M
   tile_store(st, acc);
 }
 
-// Y[col*ldy + iperm[ymap(y')*N + xmap(x')]] = sum_p S(xmap(x'), p) (lam o W)(p, r)
-template <int AM>
-__global__ void __launch_bounds__(256) k_dst_inv(const double* S, const double* W, const double* lam,
-                                                 const int* iperm, double* Y, int ldy, int N, int Ny, int ncol,
-                                                 int Mx, AxisMap xm, AxisMap ym) {
+// Y[col ldy + tree(xmap(x'), ymap(y'))] = sum_p S(xmap(x'), p) (lam o W)(p, r)
+template <int AM, bool LAM>
+__global__ void __launch_bounds__(256) k_dst_inv(const double* S, const double* W, const double* lam, TreeIdx tix,
+                                                 double* Y, int ldy, int N, int Ny, int ncol, int Mx, AxisMap xm,
+                                                 AxisMap ym) {
   __shared__ double smem[GSMEM];
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
-  const int R = ncol * Ny;
-  const int colt = (AM == 1) ? n0 / Ny : 0, yt = (AM == 1) ? n0 - colt * Ny : 0;
+  const ColGeo<AM> cg = col_geo<AM>(Ny, n0, ncol);
   DstLSrow la{S, N, m0, Mx, xm};
-  DstLMode<AM> lb{W, lam, N, Ny, n0, R, colt, yt, ym};
+  DstLMode<AM, LAM> lb{W, lam, N, cg, ym};
   TileAcc acc;
   tile_zero(acc);
   tile_gemm(la, lb, 0, N, acc, smem);
-  DstStScatter<AM> st{Y, ldy, iperm, N, Ny, m0, n0, Mx, R, colt, yt, xm, ym};
-  tile_store(st, acc);
+  tile_store(DstStScatter<AM>{Y, ldy, tix, cg, m0, Mx, xm, ym}, acc);
 }
 
 // ---- folded transforms (even N, the transformed axis whole) ------------------
 struct HalfA {  // A(i, k) = Tab[m0 + i + k H] for m0 + i < H   (P_par or Q_par)
   const double* T; int H, m0;
   static constexpr bool kfast = false;
-  __device__ double operator()(int i, int k) const {
-    const int r = m0 + i;
-    return r < H ? T[r + (long)k * H] : 0.0;
+  static constexpr int NR = 1;
+  __device__ bool load(int i, int k, double (&r)[1]) const {
+    const int row = m0 + i;
+    const bool ok = row < H;
+    r[0] = T[(ok ? row : 0) + (long)k * H];
+    return ok;
   }
+  __device__ double fin(const double (&r)[1]) const { return r[0]; }
 };
 struct HalfB {  // B(k, j) = Tab[k + (n0 + j) H] for n0 + j < H
   const double* T; int H, n0;
   static constexpr bool kfast = true;
-  __device__ double operator()(int k, int j) const {
+  static constexpr int NR = 1;
+  __device__ bool load(int k, int j, double (&r)[1]) const {
     const int c = n0 + j;
-    return c < H ? T[k + (long)c * H] : 0.0;
+    const bool ok = c < H;
+    r[0] = T[k + (long)(ok ? c : 0) * H];
+    return ok;
   }
+  __device__ double fin(const double (&r)[1]) const { return r[0]; }
 };
 template <int AM>
 struct DstLGatherFold {  // B(k, j) = X(x = k) + sgn X(x = N-1-k) of column r = n0 + j
-  const double* X; int ldx; const int* iperm; int N, Ny, n0, R, colt, yt; AxisMap ym; double sgn;
+  const double* X; int ldx; TreeIdx tix; ColGeo<AM> cg; int N; AxisMap ym; double sgn;
   static constexpr bool kfast = true;
-  __device__ double operator()(int k, int j) const {
-    const int r = n0 + j;
-    if (r >= R) return 0.0;
+  static constexpr int NR = 2;
+  __device__ bool load(int k, int j, double (&r)[2]) const {
     int col, y;
-    split_col<AM>(r, Ny, colt, yt, j, col, y);
+    const bool ok = cg.at(j, col, y);
     const double* Xc = X + (long)col * ldx;
-    const int* ip = iperm + (long)ym(y) * N;
-    return Xc[ip[k]] + sgn * Xc[ip[N - 1 - k]];
+    const int yy = ym(y);
+    r[0] = Xc[tix(k, yy)];
+    r[1] = Xc[tix(N - 1 - k, yy)];
+    return ok;
   }
+  __device__ double fin(const double (&r)[2]) const { return r[0] + sgn * r[1]; }
 };
 struct DyLAFold {  // A(i, k) = M(p, k) + sgn M(p, N-1-k), p = m0 + i
   const double* M; int N, m0; double sgn;
   static constexpr bool kfast = false;
-  __device__ double operator()(int i, int k) const {
+  static constexpr int NR = 2;
+  __device__ bool load(int i, int k, double (&r)[2]) const {
     const int p = m0 + i;
-    if (p >= N) return 0.0;
-    return M[p + (long)k * N] + sgn * M[p + (long)(N - 1 - k) * N];
+    const bool ok = p < N;
+    const int pp = ok ? p : 0;
+    r[0] = M[pp + (long)k * N];
+    r[1] = M[pp + (long)(N - 1 - k) * N];
+    return ok;
   }
+  __device__ double fin(const double (&r)[2]) const { return r[0] + sgn * r[1]; }
 };
 struct DyLApar {  // A(i, k) = (lam o M)(p, 2k + par), p = m0 + i
   const double* M; const double* lam; int N, m0, par;
   static constexpr bool kfast = false;
-  __device__ double operator()(int i, int k) const {
+  static constexpr int NR = 2;
+  __device__ bool load(int i, int k, double (&r)[2]) const {
     const int p = m0 + i;
-    if (p >= N) return 0.0;
-    const long e = p + (long)(2 * k + par) * N;
-    return lam ? M[e] * lam[e] : M[e];
+    const bool ok = p < N;
+    const long e = (ok ? p : 0) + (long)(2 * k + par) * N;
+    r[0] = M[e];
+    r[1] = lam[e];
+    return ok;
   }
+  __device__ double fin(const double (&r)[2]) const { return r[0] * r[1]; }
 };
-template <int AM>
-struct DstLModePar {  // B(k, j) = W(2k + par, r) (times lam(2k + par, ymap(y')) when lam), r = n0 + j
-  const double* W; const double* lam; int N, Ny, n0, R, colt, yt, par; AxisMap ym;
+template <int AM, bool LAM>
+struct DstLModePar {  // B(k, j) = W(2k + par, r) (times lam(2k + par, ymap(y')) when LAM), r = n0 + j
+  const double* W; const double* lam; int N, par; ColGeo<AM> cg; AxisMap ym;
   static constexpr bool kfast = true;
-  __device__ double operator()(int k, int j) const {
-    const int r = n0 + j;
-    if (r >= R) return 0.0;
+  static constexpr int NR = LAM ? 2 : 1;
+  __device__ bool load(int k, int j, double (&r)[NR]) const {
+    int col, y;
+    const bool ok = cg.at(j, col, y);
+    const int rr = ok ? cg.n0 + j : 0;
     const int p = 2 * k + par;
-    double v = W[p + (long)r * N];
-    if (lam) {
-      int col, y;
-      split_col<AM>(r, Ny, colt, yt, j, col, y);
-      v *= lam[p + (long)ym(y) * N];
-    }
-    return v;
+    r[0] = W[p + (long)rr * N];
+    if constexpr (LAM) r[1] = lam[p + (long)ym(y) * N];
+    return ok;
+  }
+  __device__ double fin(const double (&r)[NR]) const {
+    if constexpr (LAM) return r[0] * r[1];
+    else return r[0];
   }
 };
 struct DstStModePar {  // Xh(2(m0 + i) + par, r)
@@ -374,36 +447,34 @@ struct DyStUnfold {  // C(p, y') = e + o, C(p, N-1-y') = e - o, y' = n0 + j < H
 };
 template <int AM>
 struct DstStScatterUnfold {  // Y at (x, r) = e + o and (N-1-x, r) = e - o, x = m0 + i < H
-  double* Y; int ldy; const int* iperm; int N, Ny, H, m0, n0, R, colt, yt; AxisMap ym;
+  double* Y; int ldy; TreeIdx tix; ColGeo<AM> cg; int N, H, m0; AxisMap ym;
   __device__ void operator()(int i, int j, double e, double o) const {
-    const int x = m0 + i, r = n0 + j;
-    if (x >= H || r >= R) return;
+    const int x = m0 + i;
     int col, y;
-    split_col<AM>(r, Ny, colt, yt, j, col, y);
+    if (x >= H || !cg.at(j, col, y)) return;
     double* Yc = Y + (long)col * ldy;
-    const int* ip = iperm + (long)ym(y) * N;
-    Yc[ip[x]] = e + o;
-    Yc[ip[N - 1 - x]] = e - o;
+    const int yy = ym(y);
+    Yc[tix(x, yy)] = e + o;
+    Yc[tix(N - 1 - x, yy)] = e - o;
   }
 };
 
 // forward x, x whole: Xh(2i + par, r) = sum_{x < H} P_par(i, x) (X(x) +- X(N-1-x))
 // grid.x: 2 * ht tiles (parity major), grid.y: column tiles
 template <int AM>
-__global__ void __launch_bounds__(256) k_dst_fwd_fold(const double* Ph, const double* X, int ldx, const int* iperm,
+__global__ void __launch_bounds__(256) k_dst_fwd_fold(const double* Ph, const double* X, int ldx, TreeIdx tix,
                                                       double* Xh, int N, int Ny, int ncol, AxisMap ym) {
   __shared__ double smem[GSMEM];
   const int H = N / 2, ht = (H + GBM - 1) / GBM;
   const int par = (int)blockIdx.x >= ht ? 1 : 0;
   const int m0 = ((int)blockIdx.x - par * ht) * GBM, n0 = blockIdx.y * GBN;
-  const int R = ncol * Ny;
-  const int colt = (AM == 1) ? n0 / Ny : 0, yt = (AM == 1) ? n0 - colt * Ny : 0;
+  const ColGeo<AM> cg = col_geo<AM>(Ny, n0, ncol);
   HalfA la{Ph + (long)par * H * H, H, m0};
-  DstLGatherFold<AM> lb{X, ldx, iperm, N, Ny, n0, R, colt, yt, ym, par ? -1.0 : 1.0};
+  DstLGatherFold<AM> lb{X, ldx, tix, cg, N, ym, par ? -1.0 : 1.0};
   TileAcc acc;
   tile_zero(acc);
   tile_gemm(la, lb, 0, H, acc, smem);
-  tile_store(DstStModePar{Xh, N, H, m0, n0, R, par}, acc);
+  tile_store(DstStModePar{Xh, N, H, m0, n0, cg.R, par}, acc);
 }
 
 // forward y, y whole: C_c(p, 2j + par) = sum_{y < H} (M_c(p, y) +- M_c(p, N-1-y)) Q_par(y, j)
@@ -440,23 +511,22 @@ __global__ void __launch_bounds__(256) k_dst_yi_fold(const double* Ph, const dou
 }
 
 // inverse x, x whole: e = sum_k Q0(x, k) W(2k, r), o = sum_k Q1(x, k) W(2k+1, r) (W scaled
-// by lam when given, the 1D case); Y(x) = e + o, Y(N-1-x) = e - o for x < H
-template <int AM>
+// by lam when LAM, the 1D case); Y(x) = e + o, Y(N-1-x) = e - o for x < H
+template <int AM, bool LAM>
 __global__ void __launch_bounds__(256) k_dst_inv_fold(const double* Ph, const double* W, const double* lam,
-                                                      const int* iperm, double* Y, int ldy, int N, int Ny,
-                                                      int ncol, AxisMap ym) {
+                                                      TreeIdx tix, double* Y, int ldy, int N, int Ny, int ncol,
+                                                      AxisMap ym) {
   __shared__ double smem[GSMEM];
   const int H = N / 2;
   const long HH = (long)H * H;
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
-  const int R = ncol * Ny;
-  const int colt = (AM == 1) ? n0 / Ny : 0, yt = (AM == 1) ? n0 - colt * Ny : 0;
+  const ColGeo<AM> cg = col_geo<AM>(Ny, n0, ncol);
   TileAcc e, o;
   tile_zero(e);
   tile_zero(o);
-  tile_gemm(HalfA{Ph + 2 * HH, H, m0}, DstLModePar<AM>{W, lam, N, Ny, n0, R, colt, yt, 0, ym}, 0, H, e, smem);
-  tile_gemm(HalfA{Ph + 3 * HH, H, m0}, DstLModePar<AM>{W, lam, N, Ny, n0, R, colt, yt, 1, ym}, 0, H, o, smem);
-  tile_store2(DstStScatterUnfold<AM>{Y, ldy, iperm, N, Ny, H, m0, n0, R, colt, yt, ym}, e, o);
+  tile_gemm(HalfA{Ph + 2 * HH, H, m0}, DstLModePar<AM, LAM>{W, lam, N, 0, cg, ym}, 0, H, e, smem);
+  tile_gemm(HalfA{Ph + 3 * HH, H, m0}, DstLModePar<AM, LAM>{W, lam, N, 1, cg, ym}, 0, H, o, smem);
+  tile_store2(DstStScatterUnfold<AM>{Y, ldy, tix, cg, N, H, m0, ym}, e, o);
 }
 
 static hm_status ensure_scale(Model* m, const double theta[4]) {
@@ -474,8 +544,8 @@ static hm_status ensure_scale(Model* m, const double theta[4]) {
 // Axis map of the rows selected by sel (one side of the depth-sel.depth split):
 // simulate the bisection to find the split axis and the children's extent on it.
 static void side_maps(const Model* m, LeafSel sel, AxisMap& xm, AxisMap& ym) {
-  xm = AxisMap{0, 0};
-  ym = AxisMap{0, 0};
+  xm = axis_map(0, 0);
+  ym = axis_map(0, 0);
   if (sel.mode == 0) return;
   int w = m->N, h = (m->dim == 2) ? m->N : 1;
   bool xsplit = true;
@@ -483,22 +553,9 @@ static void side_maps(const Model* m, LeafSel sel, AxisMap& xm, AxisMap& ym) {
     if (w >= h) { w /= 2; xsplit = true; }
     else { h /= 2; xsplit = false; }
   }
-  const AxisMap am{xsplit ? w : h, sel.mode == 2 ? 1 : 0};
+  const AxisMap am = axis_map(xsplit ? w : h, sel.mode == 2 ? 1 : 0);
   if (xsplit) xm = am;
   else ym = am;
-}
-
-template <int AM>
-static void launch_fwd(Model* m, dim3 g, const double* X, int ldx, double* out, int N, int Ny, int cc, int Kx,
-                       AxisMap xm, AxisMap ym) {
-  hipLaunchKernelGGL((k_dst_fwd<AM>), g, dim3(GCfg::NT), 0, m->stream, m->d_dst, X, ldx, m->d_iperm, out, N, Ny,
-                     cc, Kx, xm, ym);
-}
-template <int AM>
-static void launch_inv(Model* m, dim3 g, const double* W, const double* lam, double* Y, int ldy, int N, int Ny,
-                       int cc, int Mx, AxisMap xm, AxisMap ym) {
-  hipLaunchKernelGGL((k_dst_inv<AM>), g, dim3(GCfg::NT), 0, m->stream, m->d_dst, W, lam, m->d_iperm, Y, ldy, N, Ny,
-                     cc, Mx, xm, ym);
 }
 
 // Transform launches for one block of cc columns.  An axis transformed whole (map
@@ -506,6 +563,7 @@ static void launch_inv(Model* m, dim3 g, const double* W, const double* lam, dou
 // an odd N, runs the plain GEMM over the points it has.
 static int amode(int ny) { return ny == 1 ? 2 : (ny % GBN == 0 ? 1 : 0); }
 static inline bool folds(const Model* m, AxisMap am) { return m->d_dsth && am.W == 0; }
+#define HM_DST_LAUNCH(kern, g, ...) hipLaunchKernelGGL(kern, g, dim3(GCfg::NT), 0, m->stream, __VA_ARGS__)
 
 // Xh (N x cc*Ny) = S_x applied to the gathered columns (x compact per xm, y per ym)
 static void x_forward(Model* m, const double* X, int ldx, double* Xh, int cc, int Ny, AxisMap xm, AxisMap ym) {
@@ -513,57 +571,62 @@ static void x_forward(Model* m, const double* X, int ldx, double* Xh, int cc, in
   if (folds(m, xm)) {
     const int H = N / 2;
     dim3 g(2 * ceil_div(H, GBM), ceil_div((long)cc * Ny, GBN));
-    if (am == 2) hipLaunchKernelGGL((k_dst_fwd_fold<2>), g, dim3(GCfg::NT), 0, m->stream, m->d_dsth, X, ldx, m->d_iperm, Xh, N, Ny, cc, ym);
-    else if (am == 1) hipLaunchKernelGGL((k_dst_fwd_fold<1>), g, dim3(GCfg::NT), 0, m->stream, m->d_dsth, X, ldx, m->d_iperm, Xh, N, Ny, cc, ym);
-    else hipLaunchKernelGGL((k_dst_fwd_fold<0>), g, dim3(GCfg::NT), 0, m->stream, m->d_dsth, X, ldx, m->d_iperm, Xh, N, Ny, cc, ym);
+    if (am == 2) HM_DST_LAUNCH((k_dst_fwd_fold<2>), g, m->d_dsth, X, ldx, m->tix, Xh, N, Ny, cc, ym);
+    else if (am == 1) HM_DST_LAUNCH((k_dst_fwd_fold<1>), g, m->d_dsth, X, ldx, m->tix, Xh, N, Ny, cc, ym);
+    else HM_DST_LAUNCH((k_dst_fwd_fold<0>), g, m->d_dsth, X, ldx, m->tix, Xh, N, Ny, cc, ym);
     return;
   }
   const int Kx = xm.extent(N);
   dim3 g(ceil_div(N, GBM), ceil_div((long)cc * Ny, GBN));
-  if (am == 2) launch_fwd<2>(m, g, X, ldx, Xh, N, Ny, cc, Kx, xm, ym);
-  else if (am == 1) launch_fwd<1>(m, g, X, ldx, Xh, N, Ny, cc, Kx, xm, ym);
-  else launch_fwd<0>(m, g, X, ldx, Xh, N, Ny, cc, Kx, xm, ym);
+  if (am == 2) HM_DST_LAUNCH((k_dst_fwd<2>), g, m->d_dst, X, ldx, m->tix, Xh, N, Ny, cc, Kx, xm, ym);
+  else if (am == 1) HM_DST_LAUNCH((k_dst_fwd<1>), g, m->d_dst, X, ldx, m->tix, Xh, N, Ny, cc, Kx, xm, ym);
+  else HM_DST_LAUNCH((k_dst_fwd<0>), g, m->d_dst, X, ldx, m->tix, Xh, N, Ny, cc, Kx, xm, ym);
 }
 // C_c (N x N) = M_c (N x Nyin, compact per ym) transformed along y, for cc columns
 static void y_forward(Model* m, const double* M, double* C, int cc, AxisMap ym) {
   const int N = m->N;
   if (folds(m, ym)) {
     dim3 g(ceil_div(N, GBM), 2 * ceil_div(N / 2, GBN), cc);
-    hipLaunchKernelGGL(k_dst_yf_fold, g, dim3(GCfg::NT), 0, m->stream, m->d_dsth, M, C, N);
+    HM_DST_LAUNCH(k_dst_yf_fold, g, m->d_dsth, M, C, N);
     return;
   }
   dim3 g(ceil_div(N, GBM), ceil_div(N, GBN), cc);
-  hipLaunchKernelGGL(k_dst_yf, g, dim3(GCfg::NT), 0, m->stream, m->d_dst, M, C, N, ym.extent(N), ym);
+  HM_DST_LAUNCH(k_dst_yf, g, m->d_dst, M, C, N, ym.extent(N), ym);
 }
 // C_c (N x Nyout, compact per ym) = (lam o M_c) transformed back along y
 static void y_inverse(Model* m, const double* M, const double* lam, double* C, int cc, AxisMap ym) {
   const int N = m->N;
   if (folds(m, ym)) {
     dim3 g(ceil_div(N, GBM), ceil_div(N / 2, GBN), cc);
-    hipLaunchKernelGGL(k_dst_yi_fold, g, dim3(GCfg::NT), 0, m->stream, m->d_dsth, M, lam, C, N);
+    HM_DST_LAUNCH(k_dst_yi_fold, g, m->d_dsth, M, lam, C, N);
     return;
   }
   const int Nyo = ym.extent(N);
   dim3 g(ceil_div(N, GBM), ceil_div(Nyo, GBN), cc);
-  hipLaunchKernelGGL(k_dst_yi, g, dim3(GCfg::NT), 0, m->stream, m->d_dst, M, lam, C, N, Nyo, ym);
+  HM_DST_LAUNCH(k_dst_yi, g, m->d_dst, M, lam, C, N, Nyo, ym);
 }
-// Y (scattered to tree order; x compact per xm) = S_x applied to W (N x cc*Ny), scaled by lam if given
+// Y (scattered to tree order; x compact per xm) = S_x applied to W (N x cc*Ny), scaled
+// by lam if given (one-dimensional models only)
 static void x_inverse(Model* m, const double* W, const double* lam, double* Y, int ldy, int cc, int Ny, AxisMap xm,
                       AxisMap ym) {
   const int N = m->N, am = amode(Ny);
+  const TreeIdx tix = m->tix;
   if (folds(m, xm)) {
     dim3 g(ceil_div(N / 2, GBM), ceil_div((long)cc * Ny, GBN));
-    if (am == 2) hipLaunchKernelGGL((k_dst_inv_fold<2>), g, dim3(GCfg::NT), 0, m->stream, m->d_dsth, W, lam, m->d_iperm, Y, ldy, N, Ny, cc, ym);
-    else if (am == 1) hipLaunchKernelGGL((k_dst_inv_fold<1>), g, dim3(GCfg::NT), 0, m->stream, m->d_dsth, W, lam, m->d_iperm, Y, ldy, N, Ny, cc, ym);
-    else hipLaunchKernelGGL((k_dst_inv_fold<0>), g, dim3(GCfg::NT), 0, m->stream, m->d_dsth, W, lam, m->d_iperm, Y, ldy, N, Ny, cc, ym);
+    if (am == 2 && lam) HM_DST_LAUNCH((k_dst_inv_fold<2, true>), g, m->d_dsth, W, lam, tix, Y, ldy, N, Ny, cc, ym);
+    else if (am == 2) HM_DST_LAUNCH((k_dst_inv_fold<2, false>), g, m->d_dsth, W, lam, tix, Y, ldy, N, Ny, cc, ym);
+    else if (am == 1) HM_DST_LAUNCH((k_dst_inv_fold<1, false>), g, m->d_dsth, W, lam, tix, Y, ldy, N, Ny, cc, ym);
+    else HM_DST_LAUNCH((k_dst_inv_fold<0, false>), g, m->d_dsth, W, lam, tix, Y, ldy, N, Ny, cc, ym);
     return;
   }
   const int Mx = xm.extent(N);
   dim3 g(ceil_div(Mx, GBM), ceil_div((long)cc * Ny, GBN));
-  if (am == 2) launch_inv<2>(m, g, W, lam, Y, ldy, N, Ny, cc, Mx, xm, ym);
-  else if (am == 1) launch_inv<1>(m, g, W, lam, Y, ldy, N, Ny, cc, Mx, xm, ym);
-  else launch_inv<0>(m, g, W, lam, Y, ldy, N, Ny, cc, Mx, xm, ym);
+  if (am == 2 && lam) HM_DST_LAUNCH((k_dst_inv<2, true>), g, m->d_dst, W, lam, tix, Y, ldy, N, Ny, cc, Mx, xm, ym);
+  else if (am == 2) HM_DST_LAUNCH((k_dst_inv<2, false>), g, m->d_dst, W, lam, tix, Y, ldy, N, Ny, cc, Mx, xm, ym);
+  else if (am == 1) HM_DST_LAUNCH((k_dst_inv<1, false>), g, m->d_dst, W, lam, tix, Y, ldy, N, Ny, cc, Mx, xm, ym);
+  else HM_DST_LAUNCH((k_dst_inv<0, false>), g, m->d_dst, W, lam, tix, Y, ldy, N, Ny, cc, Mx, xm, ym);
 }
+#undef HM_DST_LAUNCH
 
 hm_status kapply_sel(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK,
                      double* outKap, double* outAlp, int ldo, LeafSel in_sel, LeafSel out_sel) {
@@ -628,7 +691,23 @@ hm_status kapply(Model* m, const double theta[4], const double* X, int ldx, int 
   return kapply_sel(m, theta, X, ldx, c, outK, outKap, outAlp, ldo, sel_all(), sel_all());
 }
 
+TreeIdx make_tree_idx(int dim, int N, int levels) {
+  TreeIdx t{};
+  t.two = (dim == 2);
+  if (!t.two) return t;
+  const int cx = (levels + 1) / 2, cy = levels / 2;   // x splits first
+  t.wl = N >> cx;
+  t.hl = N >> cy;
+  t.nl = t.wl * t.hl;
+  t.sx = (levels % 2) ? 0 : 1;   // the last split is x when levels is odd
+  t.sy = 1 - t.sx;
+  t.mx = recip32(t.wl);
+  t.my = recip32(t.hl);
+  return t;
+}
+
 hm_status model_tables(Model* m) {
+  m->tix = make_tree_idx(m->dim, m->N, m->levels);
   const int n = m->n, N = m->N;
   hipLaunchKernelGGL(k_perm, dim3(ceil_div(n, 256)), dim3(256), 0, m->stream, m->d_perm, m->d_iperm, n, N,
                      m->dim, m->levels, m->nl);
@@ -669,7 +748,7 @@ hm_status kvjp(Model* m, const double theta[4], const double* X, int ldx, const 
   double* W0 = m->d_ws;
   double* W1 = m->d_ws + (long)n * m->cmax;
   double* W2 = m->d_ws + 2L * n * m->cmax;
-  const AxisMap id{0, 0};
+  const AxisMap id = axis_map(0, 0);
   for (int c0 = 0; c0 < c; c0 += m->cmax) {
     const int cc = std::min(m->cmax, c - c0);
     const double* Xc = X + (long)c0 * ldx;

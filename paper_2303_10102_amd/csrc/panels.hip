@@ -56,21 +56,29 @@ template <bool TA>
 struct LdA {
   const double* p; int ld, m0, M;
   static constexpr bool kfast = TA;
-  __device__ double operator()(int i, int k) const {
-    int r = m0 + i;
-    if (r >= M) return 0.0;
-    return TA ? p[k + (long)r * ld] : p[r + (long)k * ld];
+  static constexpr int NR = 1;
+  __device__ bool load(int i, int k, double (&v)[1]) const {
+    const int r0 = m0 + i;
+    const bool ok = r0 < M;
+    const int r = ok ? r0 : 0;
+    v[0] = TA ? p[k + (long)r * ld] : p[r + (long)k * ld];
+    return ok;
   }
+  __device__ double fin(const double (&v)[1]) const { return v[0]; }
 };
 template <bool TB>
 struct LdB {
   const double* p; int ld, n0, Nc;
   static constexpr bool kfast = !TB;
-  __device__ double operator()(int k, int j) const {
-    int c = n0 + j;
-    if (c >= Nc) return 0.0;
-    return TB ? p[c + (long)k * ld] : p[k + (long)c * ld];
+  static constexpr int NR = 1;
+  __device__ bool load(int k, int j, double (&v)[1]) const {
+    const int c0 = n0 + j;
+    const bool ok = c0 < Nc;
+    const int c = ok ? c0 : 0;
+    v[0] = TB ? p[c + (long)k * ld] : p[k + (long)c * ld];
+    return ok;
   }
+  __device__ double fin(const double (&v)[1]) const { return v[0]; }
 };
 struct StC {
   double* p; int ld, m0, n0, M, Nc; double alpha, beta;
