@@ -102,10 +102,19 @@ struct OutLB {
 };
 struct LeafAdjSt {
   double* Zb; const double* Dinv; const double* z; int ldz, nl, m0, n0; long r0;
-  __device__ void operator()(int i, int j, double v) const {
-    int r = m0 + i, c = n0 + j;
+  static constexpr int NP = 3;
+  __device__ void pre(int i, int j, double (&o)[3]) const {
+    const int r = m0 + i, c = n0 + j;
+    const bool ok = r < nl && c < nl;
+    const int rr = ok ? r : 0, cc = ok ? c : 0;
+    o[0] = Dinv[rr + (long)cc * nl];
+    o[1] = z[r0 + rr];
+    o[2] = z[r0 + cc];
+  }
+  __device__ void put(int i, int j, double v, const double (&o)[3]) const {
+    const int r = m0 + i, c = n0 + j;
     if (r >= nl || c >= nl) return;
-    Zb[r0 + r + (long)c * ldz] = 0.5 * (Dinv[r + (long)c * nl] - v - z[r0 + r] * z[r0 + c]);
+    Zb[r0 + r + (long)c * ldz] = 0.5 * (o[0] - v - o[1] * o[2]);
   }
 };
 __global__ void __launch_bounds__(256) k_leaf_adjoint(const double* Gs, const double* G, int ldg, int K,
@@ -119,7 +128,7 @@ __global__ void __launch_bounds__(256) k_leaf_adjoint(const double* Gs, const do
   TileAcc acc;
   tile_zero(acc);
   tile_gemm(la, lb, 0, K, acc, smem);
-  tile_store(LeafAdjSt{Zb, Dinv + (long)L * nl * nl, z, ldg, nl, m0, n0, r0}, acc);
+  tile_store_pre(LeafAdjSt{Zb, Dinv + (long)L * nl * nl, z, ldg, nl, m0, n0, r0}, acc);
 }
 
 static hm_status side_select(Model* m, const double* A, const double* B, double* out, int w, int l, const int* kblk,

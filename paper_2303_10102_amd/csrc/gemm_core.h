@@ -167,6 +167,31 @@ __device__ __forceinline__ void tile_store(const ST& st, const TileAcc& acc) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) st(wr + a * 16 + li, wc + b * 16 + 4 * v + lk, acc.c[a][b][v]);
 }
+// Store that reads before it writes (C = alpha AB + beta C and the like):
+//   static constexpr int NP;  bool pre(int i, int j, double (&o)[NP]) const  -- issue the
+//   loads the element needs (valid addresses only); void put(int i, int j, double v,
+//   const double (&o)[NP]) const -- combine and store (does its own bounds).
+// All loads of the tile are issued before the first store, so they are in flight together.
+template <class ST>
+__device__ __forceinline__ void tile_store_pre(const ST& st, const TileAcc& acc) {
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  double o[2][2][4][ST::NP];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) st.pre(wr + a * 16 + li, wc + b * 16 + 4 * v + lk, o[a][b][v]);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) st.put(wr + a * 16 + li, wc + b * 16 + 4 * v + lk, acc.c[a][b][v], o[a][b][v]);
+}
 // Store of two accumulators of the same tile: st(i, j, e, o)
 template <class ST>
 __device__ __forceinline__ void tile_store2(const ST& st, const TileAcc& e, const TileAcc& o) {

@@ -80,13 +80,19 @@ struct LdB {
   }
   __device__ double fin(const double (&v)[1]) const { return v[0]; }
 };
-struct StC {
+struct StC {  // C = alpha v + beta C (C not read when beta == 0)
   double* p; int ld, m0, n0, M, Nc; double alpha, beta;
-  __device__ void operator()(int i, int j, double v) const {
-    int r = m0 + i, c = n0 + j;
+  static constexpr int NP = 1;
+  __device__ void pre(int i, int j, double (&o)[1]) const {
+    if (beta == 0.0) return;
+    const int r = m0 + i, c = n0 + j;
+    const bool ok = r < M && c < Nc;
+    o[0] = p[(ok ? r : m0) + (long)(ok ? c : n0) * ld];
+  }
+  __device__ void put(int i, int j, double v, const double (&o)[1]) const {
+    const int r = m0 + i, c = n0 + j;
     if (r >= M || c >= Nc) return;
-    double* q = p + r + (long)c * ld;
-    *q = (beta == 0.0) ? alpha * v : alpha * v + beta * (*q);
+    p[r + (long)c * ld] = (beta == 0.0) ? alpha * v : alpha * v + beta * o[0];
   }
 };
 
@@ -102,7 +108,7 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int Nc, int K, double alpha
   TileAcc acc;
   tile_zero(acc);
   tile_gemm(la, lb, 0, K, acc, smem);
-  tile_store(StC{C + b * sC, ldc, m0, n0, M, Nc, alpha, beta}, acc);
+  tile_store_pre(StC{C + b * sC, ldc, m0, n0, M, Nc, alpha, beta}, acc);
 }
 
 hm_status gemm(hipStream_t st, bool ta, bool tb, int M, int Nc, int K, double alpha, const double* A,
@@ -500,7 +506,7 @@ template <int P, int NB, int RB>
 __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
   using MP = MfmaPrec<P>;
   using T = typename MP::T;
-  __shared__ T Ts[EXK * 65];
+  __shared__ T Ts[2][EXK * 65];
   const int L = blockIdx.z;
   if (!leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) return;
   constexpr int TW = 16 * NB;   // tile width in output columns
@@ -509,13 +515,15 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
   const long r0 = (long)L * a.nl;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
-  // RB row blocks of 16 per wavefront: every T value read from LDS feeds RB MFMAs
-  int row[RB];
+  // RB row blocks of 16 per wavefront: every T value read from LDS feeds RB MFMAs.
+  // Rows past the leaf read row 0 (a valid address) and are never stored.
+  int row[RB], rowc[RB];
   bool rok[RB];
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
     row[r] = m0 + wave * (16 * RB) + 16 * r + li;
     rok[r] = row[r] < a.nl;
+    rowc[r] = rok[r] ? row[r] : 0;
   }
   const int wk = a.ac.w0;
   const int ldt = a.ldt;
@@ -525,64 +533,107 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[r][b] = MP::zero();
 
-  T ac[RB][EXK / 4], an[RB][EXK / 4], tr[EXT];
-  auto load_A = [&](int d, int k0, T (&av)[RB][EXK / 4]) {
+  // Raw loads of one unit (segment d, k chunk k0), free of branches: an element
+  // outside the operand reads a valid address and is zeroed where it is used, so
+  // every load of the unit is in flight at once and the waits count exactly.
+  struct Unit {
+    double av[RB][EXK / 4];
+    double tv[EXT];
+  };
+  const int kk_t = tid % EXK, cc_t = tid / EXK;   // this thread's T elements: (kk_t, cc_t + 8 q)
+  auto load_unit = [&](int d, int k0, Unit& u) {
+    const double* Ab = a.A + r0 + (long)a.ac.c0(d) * a.lda;
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      const double* Ar = a.A + r0 + row[r] + (long)a.ac.c0(d) * a.lda;
+    for (int r = 0; r < RB; ++r)
 #pragma unroll
       for (int s = 0; s < EXK / 4; ++s) {
         const int k = k0 + 4 * s + lk;
-        av[r][s] = (rok[r] && k < wk) ? (T)Ar[(long)k * a.lda] : (T)0;
+        u.av[r][s] = Ab[rowc[r] + (long)(k < wk ? k : 0) * a.lda];
       }
-    }
-  };
-
-  int d = a.d0 - 1, k0 = 0;
-  bool have = exp_next_unit(a, j0, TW, d, k0);
-  if (have) load_A(d, k0, ac);
-  while (have) {
-    // T block of this unit (small, cached): loads issued before the next unit's panel loads
     const double* Tb = exp_T(a, L, d);
     const int cbase = j0 - a.yc.c0(d), wy = a.yc.w(d);
-    {
-      const int kk = tid % EXK, cc0 = tid / EXK;
-      const bool kok = k0 + kk < wk;
-      const double* Tk = Tb + (k0 + kk);
+    const int k = k0 + kk_t;
 #pragma unroll
-      for (int q = 0; q < EXT; ++q) {
-        const int cc = cc0 + (256 / EXK) * q;
-        const int col = cbase + cc;
-        tr[q] = (kok && cc < TW && col >= 0 && col < wy) ? (T)Tk[(long)col * ldt] : (T)0;
-      }
+    for (int q = 0; q < EXT; ++q) {
+      const int col = cbase + cc_t + (256 / EXK) * q;
+      const bool ok = k < wk && col >= 0 && col < wy;
+      u.tv[q] = Tb[(ok ? k : 0) + (long)(ok ? col : 0) * ldt];
     }
-    int dn = d, kn0 = k0;
-    const bool more = exp_next_unit(a, j0, TW, dn, kn0);
-    if (more) load_A(dn, kn0, an);
-    const int kn = min(EXK, wk - k0);
-    lds_barrier();   // previous unit's reads of Ts are done
+  };
+  auto stash_T = [&](const Unit& u, int d, int k0, T* buf) {
+    const int cbase = j0 - a.yc.c0(d), wy = a.yc.w(d);
+    const bool kok = k0 + kk_t < wk;
 #pragma unroll
-    for (int q = 0; q < EXT; ++q) Ts[(tid % EXK) * 65 + tid / EXK + (256 / EXK) * q] = tr[q];
-    lds_barrier();
+    for (int q = 0; q < EXT; ++q) {
+      const int cc = cc_t + (256 / EXK) * q;
+      const int col = cbase + cc;
+      const bool ok = kok && cc < TW && col >= 0 && col < wy;
+      buf[kk_t * 65 + cc] = ok ? (T)u.tv[q] : (T)0;
+    }
+  };
+  auto mfma_unit = [&](const Unit& u, int k0, const T* buf) {
+    const int kn = min(EXK, wk - k0);
 #pragma unroll
     for (int s = 0; s < EXK / 4; ++s) {
       if (4 * s < kn) {
         const int kk = 4 * s + lk;
+        const bool kok = kk < kn;
+        T av[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) av[r] = kok ? (T)u.av[r][s] : (T)0;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          const T tv = Ts[kk * 65 + b * 16 + li];
+          const T tv = buf[kk * 65 + b * 16 + li];
 #pragma unroll
-          for (int r = 0; r < RB; ++r) acc[r][b] = MP::mfma(tv, ac[r][s], acc[r][b]);
+          for (int r = 0; r < RB; ++r) acc[r][b] = MP::mfma(tv, av[r], acc[r][b]);
         }
       }
     }
-    if (!more) break;
+  };
+
+  // Two register sets alternate (the loop is unrolled by two) and T is staged in a
+  // double-buffered LDS block: while unit u is computed, unit u + 1 is loading, and
+  // one barrier per unit suffices (a wavefront passing the barrier of unit u has
+  // finished computing unit u - 1, whose buffer unit u + 1 overwrites).
+  int d = a.d0 - 1, k0 = 0;
+  if (exp_next_unit(a, j0, TW, d, k0)) {
+    Unit U0, U1;
+    load_unit(d, k0, U0);
+    while (true) {
+      int dn = d, kn0 = k0;
+      const bool more = exp_next_unit(a, j0, TW, dn, kn0);
+      load_unit(more ? dn : d, more ? kn0 : k0, U1);   // the last step re-reads its own unit
+      stash_T(U0, d, k0, Ts[0]);
+      lds_barrier();
+      mfma_unit(U0, k0, Ts[0]);
+      if (!more) break;
+      d = dn;
+      k0 = kn0;
+      dn = d;
+      kn0 = k0;
+      const bool more2 = exp_next_unit(a, j0, TW, dn, kn0);
+      load_unit(more2 ? dn : d, more2 ? kn0 : k0, U0);
+      stash_T(U1, d, k0, Ts[1]);
+      lds_barrier();
+      mfma_unit(U1, k0, Ts[1]);
+      if (!more2) break;
+      d = dn;
+      k0 = kn0;
+    }
+  }
+  // Y = alpha * acc + beta * Y: every old value is loaded before the first store
+  double old[RB][NB][4];
+  const bool rmw = a.beta != 0.0;
+  if (rmw) {
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
-      for (int s = 0; s < EXK / 4; ++s) ac[r][s] = an[r][s];
-    d = dn;
-    k0 = kn0;
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = j0 + b * 16 + MP::row(v, lk);
+          old[r][b][v] = a.Y[r0 + rowc[r] + (long)(col < a.yhi ? col : j0) * a.ldy];
+        }
   }
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
@@ -594,9 +645,8 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
       for (int v = 0; v < 4; ++v) {
         const int col = j0 + b * 16 + MP::row(v, lk);
         if (col < a.yhi) {
-          double* q = Yr + (long)col * a.ldy;
-          const double x = (double)acc[r][b][v];
-          *q = (a.beta == 0.0) ? a.alpha * x : a.alpha * x + a.beta * (*q);
+          const double x = a.alpha * (double)acc[r][b][v];
+          Yr[(long)col * a.ldy] = rmw ? x + a.beta * old[r][b][v] : x;
         }
       }
   }
@@ -681,7 +731,7 @@ __global__ void __launch_bounds__(256) k_leaf_gemm(const double* Dm, const doubl
   TileAcc acc;
   tile_zero(acc);
   tile_gemm(la, lb, 0, nl, acc, smem);
-  tile_store(StC{Y + r0, ldy, m0, n0, nl, w, alpha, beta}, acc);
+  tile_store_pre(StC{Y + r0, ldy, m0, n0, nl, w, alpha, beta}, acc);
 }
 
 hm_status leaf_gemm(Model* m, const double* Dm, const double* X, int ldx, double* Y, int ldy, int w,
