@@ -115,6 +115,7 @@ def batched_run(steps, count=64):
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     b = hmle.Batch([o[2] for o in objs])
+    b.tune_kernels()
     tune = b.tune(thetas, ys, candidates=(1, 2, 4, 8))
     print(f"[bench] batched: tuned {tune['batch_s']} -> {tune['best_streams']} streams", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -175,7 +176,9 @@ def main():
     del om
     H = hmle.HMatrix(s, w.free)
     theta = w.theta_full
-    print(f"[bench] sketch created in {t_sketch:.2f} s; warmup {args.warmup}", file=sys.stderr, flush=True)
+    tuning = m.autotune(s.ranks()[1])   # setup: pick the panel-kernel variants for this shape
+    print(f"[bench] sketch created in {t_sketch:.2f} s; kernel tuning {tuning}; warmup {args.warmup}",
+          file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         ll, g, fim = H.iteration(theta, y)
     torch.cuda.synchronize()
@@ -213,6 +216,8 @@ def main():
                                f"rank {w.rank} (+{w.oversample} once), theta=(kappa,alpha,tau2,sigma2)",
                    "n": w.n, "rank": w.rank, "leaf": w.leaf, "params": list(w.free)},
         "roofline": None,
+        "kernel_tuning": {"expand_rows_per_wave": tuning["expand_rows"],
+                          "reduce_four_waves_below_wgs": tuning["reduce_split_below"]},
         "loglik": ll,
         "grad_nll": [float(v) for v in g],
         "fim_diag": [float(fim[i, i]) for i in range(len(g))],

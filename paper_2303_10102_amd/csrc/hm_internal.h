@@ -114,7 +114,7 @@ struct Model {
   // kernel variants of the panel products, chosen per model by hm_model_autotune
   // (defaults: two row blocks per wavefront in the expand when leaves have >= 128
   // rows; four-wavefront row split in the reduce below 1024 workgroups)
-  int tune_expand_rb = 0;        // 0 = default rule, else 1 or 2
+  int tune_expand_rb = 0;        // 0 = default (1 row block per wavefront), else 1 or 2
   long tune_reduce_nw4 = 1024;   // reduce launches with fewer workgroups split rows over 4 wavefronts
   int prof_family = PF_NONE;
   std::vector<ProfRec> prof;

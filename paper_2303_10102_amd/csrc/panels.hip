@@ -688,8 +688,9 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
                    : (j.yc.w0 == 0 && j.yc.stride == 0 && j.yc.grow > 0 ? j.yc.grow : 0);
     nb = (bw > 0 && bw % 16 == 0 && bw <= 64 && j.yc.base % bw == 0) ? bw / 16 : 4;
   }
-  // two row blocks per wavefront (128 rows per workgroup) when the leaves are tall enough
-  const int rb = m->tune_expand_rb ? m->tune_expand_rb : ((m->nl >= 128) ? 2 : 1);
+  // one row block per wavefront (64 rows per workgroup, four workgroups per leaf of
+  // 256) unless the autotuner chose two (128 rows: each T value feeds two MFMAs)
+  const int rb = m->tune_expand_rb ? m->tune_expand_rb : 1;
   dim3 grid(ceil_div(m->nl, 64 * rb), ceil_div(yhi - ylo, 16 * nb), m->nleaves);
   if (m->panel_prec == 1) {
     if (rb == 2) launch_expand_direct<1, 2>(m, nb, grid, a);
