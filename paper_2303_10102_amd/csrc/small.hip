@@ -49,54 +49,47 @@ __global__ void __launch_bounds__(256) k_chol_inv(const double* G, long gstride,
     for (int i = tid; i < kp; i += nt) A[i + i * k] += tr;
     __syncthreads();
   }
-  // right-looking Cholesky, lower factor in A (column-major)
-  __shared__ int bad;
-  if (tid == 0) bad = 0;
+  // Right-looking Cholesky fused with the forward elimination of L Y = I, one barrier
+  // per column.  Step j reads column j of the Schur-updated A (final after step j-1)
+  // and row j of Y, and writes only columns / rows past j, so nothing it reads is
+  // written in the same step.  With d_j = A(j, j), l_ij = A(i, j) / sqrt(d_j):
+  //   A(i, l) -= A(i, j) A(l, j) / d_j          (j < l <= i)
+  //   Y(i, c) -= A(i, j) / d_j * Y(j, c)        (i > j, c <= j)
+  // and L^{-1}(i, c) = Y(i, c) / sqrt(d_i).  A pivot that is not positive is flagged
+  // and taken as 1.
+  __shared__ double Y[KMAX * KMAX];
+  for (int e = tid; e < k * k; e += nt) Y[e] = (e % k == e / k) ? 1.0 : 0.0;
   __syncthreads();
+  // Lane i of every wavefront owns row i (k <= 64); wavefront w takes the columns
+  // congruent to w modulo the wavefront count, so the pivot-row operand is a broadcast.
+  bool bad = false;
+  const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
   for (int j = 0; j < k; ++j) {
-    if (tid == 0) {
-      double d = A[j + j * k];
-      if (!(d > 0.0)) { bad = 1; d = 1.0; }
-      A[j + j * k] = sqrt(d);
-    }
-    __syncthreads();
-    const double piv = A[j + j * k];
-    for (int i = j + 1 + tid; i < k; i += nt) A[i + j * k] /= piv;
-    __syncthreads();
-    const int r = k - j - 1;
-    for (int e = tid; e < r * r; e += nt) {
-      int i = j + 1 + e % r, l = j + 1 + e / r;
-      if (i >= l) A[i + l * k] -= A[i + j * k] * A[l + j * k];
+    double d = A[j + j * k];
+    if (!(d > 0.0)) { bad = true; d = 1.0; }
+    const double rd = 1.0 / d;
+    const int i = lane;
+    if (i > j && i < k) {
+      const double f = A[i + j * k] * rd;
+      for (int l = j + 1 + wave; l <= i; l += nw) A[i + l * k] -= f * A[l + j * k];
+      for (int c = wave; c <= j; c += nw) Y[i + c * k] -= f * Y[j + c * k];
     }
     __syncthreads();
   }
   if (bad && tid == 0) atomicOr(flags, (int)DF_QR_FAIL);
-  // R = L^T (upper), Rinv = (L^{-1})^T; column c of L^{-1} by forward substitution in LDS
-  __shared__ double X[KMAX * KMAX];   // X[c + i*k] = (L^{-1})(i, c)
+  // R = L^T (upper), Rinv = (L^{-1})^T
   double* Ro = R + node * rstride;
   double* Ri = Rinv + node * rstride;
   for (int e = tid; e < k * k; e += nt) {
-    int i = e % k, j = e / k;
-    Ro[e] = (i <= j) ? A[j + i * k] : 0.0;  // R(i,j) = L(j,i)
+    const int i = e % k, j = e / k;
+    double dj = A[j + j * k], di = A[i + i * k];
+    if (!(dj > 0.0)) dj = 1.0;
+    if (!(di > 0.0)) di = 1.0;
+    // R(i, j) = L(j, i) for i <= j
+    Ro[e] = (i < j) ? A[j + i * k] / sqrt(di) : (i == j ? sqrt(di) : 0.0);
+    // Rinv(i, j) = L^{-1}(j, i) = Y(j, i) / sqrt(d_j) for j >= i
+    Ri[e] = (j >= i) ? Y[j + i * k] / sqrt(dj) : 0.0;
   }
-  for (int c = tid; c < k; c += nt) {
-    for (int i = 0; i < c; ++i) X[c + i * k] = 0.0;
-    for (int i = c; i < k; ++i) {
-      // four independent partial sums break the FMA dependency chain
-      double s0 = (i == c) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      int l = c;
-      for (; l + 3 < i; l += 4) {
-        s0 -= A[i + l * k] * X[c + l * k];
-        s1 -= A[i + (l + 1) * k] * X[c + (l + 1) * k];
-        s2 -= A[i + (l + 2) * k] * X[c + (l + 2) * k];
-        s3 -= A[i + (l + 3) * k] * X[c + (l + 3) * k];
-      }
-      for (; l < i; ++l) s0 -= A[i + l * k] * X[c + l * k];
-      X[c + i * k] = ((s0 + s1) + (s2 + s3)) / A[i + i * k];
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < k * k; e += nt) Ri[e] = X[e];   // Rinv(c, i) = (L^{-1})(i, c)
 }
 
 // M = triu(W) + strict_tril(W)^T, W k x k (ld k) per node; zero outside k_P.
@@ -122,10 +115,9 @@ __global__ void __launch_bounds__(256) k_node_lu(const double* S, long sstride, 
                                                  double* logdet, int k, int heap0, int* flags) {
   __shared__ double Sa[KMAX * KMAX];
   __shared__ double Sb[KMAX * KMAX];
-  __shared__ double A[KMAX * KMAX];     // Sig, then its LU factors
-  __shared__ double Si[KMAX * KMAX];    // Sig^{-1}
+  __shared__ double A[KMAX * KMAX];     // Sig, eliminated in place
+  __shared__ double Si[KMAX * KMAX];    // the accumulated row operations, then Sig^{-1}
   __shared__ int piv[KMAX];
-  __shared__ double sgn, lsum;
   const int P = heap0 + blockIdx.x;
   const int a = 2 * P + 1, b = 2 * P + 2;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -141,85 +133,70 @@ __global__ void __launch_bounds__(256) k_node_lu(const double* S, long sstride, 
     for (int l = 0; l < k; ++l) v -= Sa[i + l * k] * Sb[l + j * k];
     A[e] = v;
   }
-  if (tid == 0) { sgn = 1.0; lsum = 0.0; }
+  for (int e = tid; e < kk; e += nt) Si[e] = (e % k == e / k) ? 1.0 : 0.0;
   __syncthreads();
-  // LU with partial pivoting; the pivot search is done by the first wavefront
+  // Gauss-Jordan elimination with partial pivoting on [Sig | I], one barrier per
+  // column.  Every wavefront finds the pivot of column j itself (the largest |A(i, j)|
+  // over rows not yet used, ties to the lower row; lane i holds row i), so no barrier
+  // separates the search from the update; the pivot row p is only read in step j.
+  // All other rows are eliminated: A(i, c) -= A(i, j) / A(p, j) A(p, c) for c > j and
+  // the same on Y = Si, after which Sig^{-1}(j, :) = Y(p_j, :) / A(p_j, j) and
+  // det Sig = sign(pivot permutation) * prod_j A(p_j, j).
+  const int lane = tid & 63;
+  bool used = lane >= k;
+  __shared__ double pval[KMAX];
   for (int j = 0; j < k; ++j) {
-    if (tid < 64) {
-      double best = -1.0;
-      int bi = j;
-      for (int i = j + tid; i < k; i += 64) {
-        double v = fabs(A[i + j * k]);
-        if (v > best) { best = v; bi = i; }
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        double ob = __shfl_xor(best, off, 64);
-        int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      if (tid == 0) piv[j] = bi;
+    double best = -1.0;
+    int bi = KMAX;
+    if (!used) {
+      best = fabs(A[lane + j * k]);
+      if (!(best <= INFINITY)) best = INFINITY;   // NaN ranks first: the order stays total
+      bi = lane;
     }
-    __syncthreads();
-    const int pr = piv[j];
-    if (pr != j)
-      for (int c = tid; c < k; c += nt) {
-        double t = A[j + c * k];
-        A[j + c * k] = A[pr + c * k];
-        A[pr + c * k] = t;
-      }
-    __syncthreads();
-    const double d = A[j + j * k];
-    if (tid == 0) {
-      if (pr != j) sgn = -sgn;
-      if (d < 0.0) sgn = -sgn;
-      lsum += log(fabs(d));
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
     }
-    if (d != 0.0)
-      for (int i = j + 1 + tid; i < k; i += nt) A[i + j * k] /= d;
-    __syncthreads();
-    const int r = k - j - 1;
-    for (int e = tid; e < r * r; e += nt) {
-      int i = j + 1 + e % r, c = j + 1 + e / r;
-      A[i + c * k] -= A[i + j * k] * A[j + c * k];
+    const int p = bi;
+    if (lane == p) used = true;
+    const double pv = A[p + j * k];
+    if (tid == 0) { piv[j] = p; pval[j] = pv; }
+    const double rp = (pv != 0.0) ? 1.0 / pv : 0.0;
+    // lane i owns row i; wavefront w takes columns congruent to w (pivot row: broadcast)
+    if (lane < k && lane != p) {
+      const double f = A[lane + j * k] * rp;
+      const int wave = tid >> 6, nw = nt >> 6;
+      for (int c = j + 1 + wave; c < k; c += nw) A[lane + c * k] -= f * A[p + c * k];
+      for (int c = wave; c < k; c += nw) Si[lane + c * k] -= f * Si[p + c * k];
     }
     __syncthreads();
   }
+  // Sig^{-1}(j, c) = Y(p_j, c) / A(p_j, j), into A (column j of A is read no more)
+  for (int e = tid; e < kk; e += nt) {
+    const int j = e % k, c = e / k;
+    A[e] = Si[piv[j] + c * k] / pval[j];
+  }
+  __syncthreads();
+  for (int e = tid; e < kk; e += nt) Si[e] = A[e];
   if (tid == 0) {
-    logdet[P] = lsum;
-    if (!(sgn > 0.0) || !isfinite(lsum)) atomicOr(flags, (int)DF_NOT_SPD_NODE);
-  }
-  // Sig^{-1}: column c solves L U x = P e_c
-  for (int c = tid; c < k; c += nt) {
-    double* x = Si + c * k;
-    for (int i = 0; i < k; ++i) x[i] = (i == c) ? 1.0 : 0.0;
-    for (int i = 0; i < k; ++i) {
-      int q = piv[i];
-      if (q != i) { double t = x[i]; x[i] = x[q]; x[q] = t; }
+    // log |det| and the sign: pivot signs times the parity of the pivot permutation
+    double ls = 0.0;
+    int neg = 0;
+    for (int j = 0; j < k; ++j) {
+      ls += log(fabs(pval[j]));
+      if (pval[j] < 0.0) ++neg;
     }
-    for (int i = 0; i < k; ++i) {
-      double s0 = x[i], s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      int l = 0;
-      for (; l + 3 < i; l += 4) {
-        s0 -= A[i + l * k] * x[l];
-        s1 -= A[i + (l + 1) * k] * x[l + 1];
-        s2 -= A[i + (l + 2) * k] * x[l + 2];
-        s3 -= A[i + (l + 3) * k] * x[l + 3];
-      }
-      for (; l < i; ++l) s0 -= A[i + l * k] * x[l];
-      x[i] = (s0 + s1) + (s2 + s3);
+    unsigned long long seen = 0ull;   // k <= 64
+    int cycles = 0;
+    for (int j = 0; j < k; ++j) {
+      if ((seen >> j) & 1ull) continue;
+      ++cycles;
+      for (int q = j; !((seen >> q) & 1ull); q = piv[q]) seen |= 1ull << q;
     }
-    for (int i = k - 1; i >= 0; --i) {
-      double s0 = x[i], s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      int l = i + 1;
-      for (; l + 3 < k; l += 4) {
-        s0 -= A[i + l * k] * x[l];
-        s1 -= A[i + (l + 1) * k] * x[l + 1];
-        s2 -= A[i + (l + 2) * k] * x[l + 2];
-        s3 -= A[i + (l + 3) * k] * x[l + 3];
-      }
-      for (; l < k; ++l) s0 -= A[i + l * k] * x[l];
-      x[i] = ((s0 + s1) + (s2 + s3)) / A[i + i * k];
-    }
+    const bool positive = (((k - cycles) + neg) % 2) == 0;
+    logdet[P] = ls;
+    if (!positive || !isfinite(ls)) atomicOr(flags, (int)DF_NOT_SPD_NODE);
   }
   __syncthreads();
   // P1 = S_b Sig^{-1} -> A (LU no longer needed)
