@@ -307,14 +307,13 @@ static hm_status fisher_enqueue(HState* h) {
   }
   const int n = m->n, kc = h->kc, levels = m->levels;
   const long pset = (long)n * levels * kc;
-  const long lset = (long)m->nleaves * m->nl * m->nl;
   const long s2 = (long)kc * kc;
   const long nint = (1 << levels) - 1, nodes = (2L << levels) - 1;
   const double *A[4], *B[4];
   double* out = h->d_scal + SC_FIM;
-  // term 0: 1/2 <Y^i, Yt^j>
-  for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Y; B[q] = h->pb[q].Yt; }
-  HM_CHECK(dots(m, A, p, B, p, lset, out + 0 * 16, h->d_part));
+  // term 0: 1/2 sum_L tr(Y^i_L Y^j_L)  (Y^j transposed is dD_j Dinv)
+  for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Y; B[q] = h->pb[q].Y; }
+  HM_CHECK(dots_leafT(m, A, p, B, p, out + 0 * 16, h->d_part));
   // term 1: -1/2 <Lam^i, PsiP^j>
   for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Lam; B[q] = h->pb[q].PsiP; }
   HM_CHECK(dots(m, A, p, B, p, nint * 4 * s2, out + 1 * 16, h->d_part));
@@ -691,15 +690,13 @@ hm_status hm_H_create(hm_sketch* hs, int p, const int* free_idx, hm_H** out) {
       AL(pb.dF, pset);
       AL(pb.dD, lset);
     }
-    if (pb.kind == 2) {          // Xi = G, Y = Yt = Dinv, Psi = G^T G
+    if (pb.kind == 2) {          // Xi = G, Y = Dinv, Psi = G^T G
       pb.Xi = f.G;
-      pb.Y = pb.Yt = f.Dinv;
+      pb.Y = f.Dinv;
       pb.Psi = h->GtG;
     } else {
       AL(pb.Xi, pset);
       AL(pb.Y, lset);
-      if (pb.kind == 3) pb.Yt = pb.Y;   // Dinv dD = dD Dinv for dD = (D - tau2 I)/sigma2
-      else AL(pb.Yt, lset);
       AL(pb.Psi, nodes * s2);
     }
     AL(pb.dG, pset);

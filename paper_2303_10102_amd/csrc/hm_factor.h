@@ -13,7 +13,6 @@ struct ParamBufs {
   double* Gh = nullptr;    // dG_c N_P[c,c] (panel set)
   double* Hh = nullptr;    // dG_c N_P[c,sib] S_sib (panel set)
   double* Y = nullptr;     // Dinv_L dD_L (leaf-major)
-  double* Yt = nullptr;    // dD_L Dinv_L (leaf-major)
   double* E = nullptr;     // dF_c^T G_c per non-root node (kc^2)
   double* Psi = nullptr;   // G_c^T Xi_c per non-root node (kc^2)
   double* W = nullptr;     // dG_c^T F_c per non-root node (kc^2)

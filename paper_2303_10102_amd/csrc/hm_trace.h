@@ -6,6 +6,9 @@ namespace hm {
 
 hm_status dots(Model* m, const double* const* A, int na, const double* const* B, int nb, long len, double* out,
                double* partial);
+// out[i nb + j] = sum over leaves of tr(A_i[L] B_j[L]) (leaf-major nl x nl blocks)
+hm_status dots_leafT(Model* m, const double* const* A, int na, const double* const* B, int nb, double* out,
+                     double* partial);
 hm_status sum_scalar(Model* m, const double* x, long len, int diag_nl, double* out, double* partial);
 hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double theta[4], const double* tF_prefix,
                         const double* GtG);

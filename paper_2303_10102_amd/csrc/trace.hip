@@ -129,6 +129,79 @@ hm_status dots(Model* m, const double* const* A, int na, const double* const* B,
   return HM_OK;
 }
 
+// Pairwise traces of leaf-major blocks: out[i nb + j] = sum_L tr(A_i[L] B_j[L]) =
+// sum_L sum_{a,b} A_i[L](a, b) B_j[L](b, a).  One 32 x 32 tile (L, a0, b0) per step: the
+// B_j tiles at the transposed position go through LDS, so both operands are read in
+// 256-byte column runs.  Partial sums as in k_dots_partial.
+constexpr int LT = 32;
+__global__ void __launch_bounds__(256) k_dots_leafT_partial(DotArgs a, int nl, int nleaves, double* partial) {
+  __shared__ double red[256];
+  __shared__ double Bt[4][LT][LT + 1];
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  const int tpl = (nl + LT - 1) / LT;             // tiles per leaf side
+  const long ntiles = (long)nleaves * tpl * tpl;
+  const int tx = threadIdx.x % LT, ty = threadIdx.x / LT;   // 32 x 8 threads
+  const long ls = (long)nl * nl;
+  for (long t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int L = (int)(t / ((long)tpl * tpl));
+    const int rem = (int)(t % ((long)tpl * tpl));
+    const int a0 = (rem % tpl) * LT, b0 = (rem / tpl) * LT;
+    // B_j(b0 + r, a0 + c) for r, c < 32 -> Bt[j][r][c]
+    for (int r = ty; r < LT; r += 8) {
+      const int row = b0 + tx, col = a0 + r;    // element (row, col) of B_j, column-major
+      const bool ok = row < nl && col < nl;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j < a.nb) Bt[j][tx][r] = ok ? a.B[j][L * ls + row + (long)col * nl] : 0.0;
+    }
+    __syncthreads();
+    // A_i(a0 + x, b0 + y) pairs with B_j(b0 + y, a0 + x) = Bt[j][y][x]
+    for (int y = ty; y < LT; y += 8) {
+      const int ra = a0 + tx, ca = b0 + y;
+      const bool ok = ra < nl && ca < nl;
+      double av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = (ok && i < a.na) ? a.A[i][L * ls + ra + (long)ca * nl] : 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = (j < a.nb) ? Bt[j][y][tx] : 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i * 4 + j] += av[i] * bv[j];
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < a.na * a.nb; ++q) {
+    int i = q / a.nb, j = q % a.nb;
+    red[threadIdx.x] = acc[i * 4 + j];
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(long)blockIdx.x * 16 + q] = red[0];
+    __syncthreads();
+  }
+}
+hm_status dots_leafT(Model* m, const double* const* A, int na, const double* const* B, int nb, double* out,
+                     double* partial) {
+  DotArgs a{};
+  for (int i = 0; i < na; ++i) a.A[i] = A[i];
+  for (int j = 0; j < nb; ++j) a.B[j] = B[j];
+  a.na = na;
+  a.nb = nb;
+  const int tpl = ceil_div(m->nl, LT);
+  const long ntiles = (long)m->nleaves * tpl * tpl;
+  const int nblk = (int)std::min<long>(DOT_BLOCKS, std::max<long>(1, ntiles));
+  hipLaunchKernelGGL(k_dots_leafT_partial, dim3(nblk), dim3(256), 0, m->stream, a, m->nl, m->nleaves, partial);
+  HM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_dots_final, dim3(na * nb), dim3(256), 0, m->stream, partial, nblk, na * nb, out);
+  HM_LAUNCH_CHECK();
+  return HM_OK;
+}
+
 // sum of the diagonals of the leaf-major blocks; or a plain sum (stride 1) when nl==0
 __global__ void k_sum_partial(const double* x, long len, int nl, double* partial) {
   __shared__ double red[256];
@@ -273,7 +346,7 @@ hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double theta[4], cons
   const long ncnt = ((2L << levels) - 2) * s2;   // per-node arrays, non-root nodes (from offset s2)
   const double tau2 = theta[2], sigma2 = theta[3];
   if (pb.kind == 2) {
-    // K~_tau2 = I: no panels, identity leaves.  Xi = G, Y = Yt = Dinv and Psi = G^T G are
+    // K~_tau2 = I: no panels, identity leaves.  Xi = G, Y = Dinv and Psi = G^T G are
     // aliases set at creation; E = dF^T G = 0.
     HM_CHECK(fill(m, pb.dF, pcnt, 0.0));
     HM_CHECK(leaf_affine(m, pb.dD, nullptr, 0.0, 1.0));
@@ -282,7 +355,7 @@ hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double theta[4], cons
   }
   if (pb.kind == 3) {
     // K~_sigma2 = (K~ - tau2 I)/sigma2: dF = F/(2 sigma2), dD = (D - tau2 I)/sigma2,
-    // Xi = (F - tau2 G)/sigma2, Y = Yt = Dinv dD = (I - tau2 Dinv)/sigma2 (Yt aliases Y),
+    // Xi = (F - tau2 G)/sigma2, Y = Dinv dD = (I - tau2 Dinv)/sigma2,
     // E = dF^T G = S/(2 sigma2), Psi = G^T Xi = (S - tau2 G^T G)/sigma2  (S = F^T G, symmetric)
     HM_CHECK(lin2(m, pb.dF, f.F, nullptr, pcnt, 0.5 / sigma2, 0.0));
     HM_CHECK(leaf_affine(m, pb.dD, f.D, 1.0 / sigma2, -tau2 / sigma2));
@@ -305,12 +378,11 @@ hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double theta[4], cons
                  sel_all()};
     HM_CHECK(tree_expand(m, e2));
   }
-  // leaf products Y = Dinv dD, Yt = dD Dinv
+  // leaf products Y = Dinv dD (dD Dinv = Y^T: both factors are symmetric, so the
+  // Fisher's leaf term tr(Dinv dD_i Dinv dD_j) is a transposed dot of Y_i and Y_j)
   const int nl = m->nl;
   const long ls = (long)nl * nl;
   HM_CHECK(gemm(m->stream, false, false, nl, nl, nl, 1.0, f.Dinv, nl, ls, pb.dD, nl, ls, 0.0, pb.Y, nl, ls,
-                m->nleaves));
-  HM_CHECK(gemm(m->stream, false, false, nl, nl, nl, 1.0, pb.dD, nl, ls, f.Dinv, nl, ls, 0.0, pb.Yt, nl, ls,
                 m->nleaves));
   // E_c = dF_c^T G_c,  Psi_c = G_c^T Xi_c  (all non-root nodes)
   ReduceJob re{pb.dF, n, cs_block(kc), f.G, n, cs_block(kc), 1, levels, pb.E, s2, sel_all()};
