@@ -438,7 +438,7 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
   A((void**)&m->d_dst, (size_t)N * N * sizeof(double));
   if (N % 2 == 0) A((void**)&m->d_dsth, (size_t)N * N * sizeof(double));
   A((void**)&m->d_lam, 3 * (size_t)n * sizeof(double));
-  A((void**)&m->d_ws, 3 * (size_t)n * m->cmax * sizeof(double));
+  A((void**)&m->d_ws, 5 * (size_t)n * m->cmax * sizeof(double));   // transform scratch (X, X^, 3 outputs)
   A((void**)&m->d_flags, sizeof(int));
   A((void**)&m->d_ident, (size_t)n * m->nl * sizeof(double));
   if (!ok) {

@@ -127,6 +127,18 @@ struct AxisMap {
 static inline unsigned recip32(int w) { return w > 0 ? (unsigned)((0x100000000ULL + (unsigned)w - 1) / (unsigned)w) : 0u; }
 static inline AxisMap axis_map(int W, int par) { return AxisMap{W, par, recip32(W)}; }
 
+// The outputs of one K-apply (K X, dK/dkappa X, dK/dalpha X, any subset) share the
+// forward transforms; their inverse transforms run as one launch, output o taking the
+// multipliers lam[o] and writing Y[o] (x inverse) or slot o of the scratch (y inverse).
+struct MultiOut {
+  double* Y[3];
+  const double* lam[3];
+  long in_stride;    // input offset between outputs (0: one shared input)
+  int nq;
+  __device__ __forceinline__ const double* lam_of(int o) const { return o == 0 ? lam[0] : (o == 1 ? lam[1] : lam[2]); }
+  __device__ __forceinline__ double* y_of(int o) const { return o == 0 ? Y[0] : (o == 1 ? Y[1] : Y[2]); }
+};
+
 // Column r of a transform operand is (col, y') = (r / Ny, r % Ny) over the compact
 // y range Ny.  AM: 0 general division, 1 a tile of GBN columns lies inside one
 // grid column (Ny % GBN == 0), 2 one-dimensional (Ny == 1).
@@ -303,30 +315,36 @@ __global__ void __launch_bounds__(256) k_dst_yf(const double* S, const double* M
   tile_store(st, acc);
 }
 
-// inverse y: C_c = (lam o M_c) S[:, ymap(.)]  (M_c: N x N; C_c: N x Nyout at c*N*Nyout)
-__global__ void __launch_bounds__(256) k_dst_yi(const double* S, const double* M, const double* lam, double* C,
-                                                int N, int Nyout, AxisMap ym) {
+// inverse y: C_{o,c} = (lam_o o M_c) S[:, ymap(.)]  (M_c: N x N; C_{o,c}: N x Nyout at
+// o * cslot + c*N*Nyout); grid.z = outputs x columns
+__global__ void __launch_bounds__(256) k_dst_yi(const double* S, const double* M, MultiOut mo, double* C,
+                                                long cslot, int cc, int N, int Nyout, AxisMap ym) {
   __shared__ double smem[GSMEM];
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
-  DyLA<true> la{M + (long)blockIdx.z * N * N, lam, N, m0};
+  const int o = blockIdx.z / cc, c = blockIdx.z % cc;
+  DyLA<true> la{M + (long)c * N * N, mo.lam_of(o), N, m0};
   DyLBinv lb{S, N, n0, Nyout, ym};
   TileAcc acc;
   tile_zero(acc);
   tile_gemm(la, lb, 0, N, acc, smem);
-  DstStMode st{C + (long)blockIdx.z * N * Nyout, N, m0, n0, Nyout};
+  DstStMode st{C + o * cslot + (long)c * N * Nyout, N, m0, n0, Nyout};
   tile_store(st, acc);
 }
 
 // Y[col ldy + tree(xmap(x'), ymap(y'))] = sum_p S(xmap(x'), p) (lam o W)(p, r)
+// grid.y = outputs x column tiles
 template <int AM, bool LAM>
-__global__ void __launch_bounds__(256) k_dst_inv(const double* S, const double* W, const double* lam, TreeIdx tix,
-                                                 double* Y, int ldy, int N, int Ny, int ncol, int Mx, AxisMap xm,
+__global__ void __launch_bounds__(256) k_dst_inv(const double* S, const double* W, MultiOut mo, TreeIdx tix,
+                                                 int ldy, int N, int Ny, int ncol, int Mx, AxisMap xm,
                                                  AxisMap ym) {
   __shared__ double smem[GSMEM];
-  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  const int yt = (ncol * Ny + GBN - 1) / GBN;
+  const int o = blockIdx.y / yt;
+  const int m0 = blockIdx.x * GBM, n0 = (blockIdx.y - o * yt) * GBN;
   const ColGeo<AM> cg = col_geo<AM>(Ny, n0, ncol);
+  double* Y = mo.y_of(o);
   DstLSrow la{S, N, m0, Mx, xm};
-  DstLMode<AM, LAM> lb{W, lam, N, cg, ym};
+  DstLMode<AM, LAM> lb{W + o * mo.in_stride, mo.lam_of(o), N, cg, ym};
   TileAcc acc;
   tile_zero(acc);
   tile_gemm(la, lb, 0, N, acc, smem);
@@ -495,38 +513,45 @@ __global__ void __launch_bounds__(256) k_dst_yf_fold(const double* Ph, const dou
 
 // inverse y, y whole: e = sum_k (lam o M_c)(p, 2k) P0(k, y'), o = the odd modes with P1;
 // C_c(p, y') = e + o, C_c(p, N-1-y') = e - o for y' < H
-__global__ void __launch_bounds__(256) k_dst_yi_fold(const double* Ph, const double* M, const double* lam,
-                                                     double* C, int N) {
+// (grid.z = outputs x columns, as k_dst_yi)
+__global__ void __launch_bounds__(256) k_dst_yi_fold(const double* Ph, const double* M, MultiOut mo, double* C,
+                                                     long cslot, int cc, int N) {
   __shared__ double smem[GSMEM];
   const int H = N / 2;
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  const int q = blockIdx.z / cc, c = blockIdx.z % cc;
   const long NN = (long)N * N, HH = (long)H * H;
-  const double* Mz = M + blockIdx.z * NN;
+  const double* Mz = M + c * NN;
+  const double* lam = mo.lam_of(q);
   TileAcc e, o;
   tile_zero(e);
   tile_zero(o);
   tile_gemm(DyLApar{Mz, lam, N, m0, 0}, HalfB{Ph, H, n0}, 0, H, e, smem);
   tile_gemm(DyLApar{Mz, lam, N, m0, 1}, HalfB{Ph + HH, H, n0}, 0, H, o, smem);
-  tile_store2(DyStUnfold{C + blockIdx.z * NN, N, H, m0, n0}, e, o);
+  tile_store2(DyStUnfold{C + q * cslot + c * NN, N, H, m0, n0}, e, o);
 }
 
 // inverse x, x whole: e = sum_k Q0(x, k) W(2k, r), o = sum_k Q1(x, k) W(2k+1, r) (W scaled
 // by lam when LAM, the 1D case); Y(x) = e + o, Y(N-1-x) = e - o for x < H
+// (grid.y = outputs x column tiles, as k_dst_inv)
 template <int AM, bool LAM>
-__global__ void __launch_bounds__(256) k_dst_inv_fold(const double* Ph, const double* W, const double* lam,
-                                                      TreeIdx tix, double* Y, int ldy, int N, int Ny, int ncol,
-                                                      AxisMap ym) {
+__global__ void __launch_bounds__(256) k_dst_inv_fold(const double* Ph, const double* W, MultiOut mo, TreeIdx tix,
+                                                      int ldy, int N, int Ny, int ncol, AxisMap ym) {
   __shared__ double smem[GSMEM];
   const int H = N / 2;
   const long HH = (long)H * H;
-  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  const int yt = (ncol * Ny + GBN - 1) / GBN;
+  const int q = blockIdx.y / yt;
+  const int m0 = blockIdx.x * GBM, n0 = (blockIdx.y - q * yt) * GBN;
   const ColGeo<AM> cg = col_geo<AM>(Ny, n0, ncol);
+  const double* Wq = W + q * mo.in_stride;
+  const double* lam = mo.lam_of(q);
   TileAcc e, o;
   tile_zero(e);
   tile_zero(o);
-  tile_gemm(HalfA{Ph + 2 * HH, H, m0}, DstLModePar<AM, LAM>{W, lam, N, 0, cg, ym}, 0, H, e, smem);
-  tile_gemm(HalfA{Ph + 3 * HH, H, m0}, DstLModePar<AM, LAM>{W, lam, N, 1, cg, ym}, 0, H, o, smem);
-  tile_store2(DstStScatterUnfold<AM>{Y, ldy, tix, cg, N, H, m0, ym}, e, o);
+  tile_gemm(HalfA{Ph + 2 * HH, H, m0}, DstLModePar<AM, LAM>{Wq, lam, N, 0, cg, ym}, 0, H, e, smem);
+  tile_gemm(HalfA{Ph + 3 * HH, H, m0}, DstLModePar<AM, LAM>{Wq, lam, N, 1, cg, ym}, 0, H, o, smem);
+  tile_store2(DstStScatterUnfold<AM>{mo.y_of(q), ldy, tix, cg, N, H, m0, ym}, e, o);
 }
 
 static hm_status ensure_scale(Model* m, const double theta[4]) {
@@ -593,38 +618,40 @@ static void y_forward(Model* m, const double* M, double* C, int cc, AxisMap ym) 
   dim3 g(ceil_div(N, GBM), ceil_div(N, GBN), cc);
   HM_DST_LAUNCH(k_dst_yf, g, m->d_dst, M, C, N, ym.extent(N), ym);
 }
-// C_c (N x Nyout, compact per ym) = (lam o M_c) transformed back along y
-static void y_inverse(Model* m, const double* M, const double* lam, double* C, int cc, AxisMap ym) {
+// C_{o,c} (N x Nyout, compact per ym; output o at C + o * cslot) = (lam_o o M_c)
+// transformed back along y, all outputs in one launch
+static void y_inverse(Model* m, const double* M, const MultiOut& mo, double* C, long cslot, int cc, AxisMap ym) {
   const int N = m->N;
   if (folds(m, ym)) {
-    dim3 g(ceil_div(N, GBM), ceil_div(N / 2, GBN), cc);
-    HM_DST_LAUNCH(k_dst_yi_fold, g, m->d_dsth, M, lam, C, N);
+    dim3 g(ceil_div(N, GBM), ceil_div(N / 2, GBN), cc * mo.nq);
+    HM_DST_LAUNCH(k_dst_yi_fold, g, m->d_dsth, M, mo, C, cslot, cc, N);
     return;
   }
   const int Nyo = ym.extent(N);
-  dim3 g(ceil_div(N, GBM), ceil_div(Nyo, GBN), cc);
-  HM_DST_LAUNCH(k_dst_yi, g, m->d_dst, M, lam, C, N, Nyo, ym);
+  dim3 g(ceil_div(N, GBM), ceil_div(Nyo, GBN), cc * mo.nq);
+  HM_DST_LAUNCH(k_dst_yi, g, m->d_dst, M, mo, C, cslot, cc, N, Nyo, ym);
 }
-// Y (scattered to tree order; x compact per xm) = S_x applied to W (N x cc*Ny), scaled
-// by lam if given (one-dimensional models only)
-static void x_inverse(Model* m, const double* W, const double* lam, double* Y, int ldy, int cc, int Ny, AxisMap xm,
+// Y_o (scattered to tree order; x compact per xm) = S_x applied to W + o * mo.in_stride
+// (N x cc*Ny), scaled by lam_o when LAM (one-dimensional models); all outputs in one launch
+static void x_inverse(Model* m, const double* W, const MultiOut& mo, bool lam, int ldy, int cc, int Ny, AxisMap xm,
                       AxisMap ym) {
   const int N = m->N, am = amode(Ny);
   const TreeIdx tix = m->tix;
+  const int yt = ceil_div((long)cc * Ny, GBN);
   if (folds(m, xm)) {
-    dim3 g(ceil_div(N / 2, GBM), ceil_div((long)cc * Ny, GBN));
-    if (am == 2 && lam) HM_DST_LAUNCH((k_dst_inv_fold<2, true>), g, m->d_dsth, W, lam, tix, Y, ldy, N, Ny, cc, ym);
-    else if (am == 2) HM_DST_LAUNCH((k_dst_inv_fold<2, false>), g, m->d_dsth, W, lam, tix, Y, ldy, N, Ny, cc, ym);
-    else if (am == 1) HM_DST_LAUNCH((k_dst_inv_fold<1, false>), g, m->d_dsth, W, lam, tix, Y, ldy, N, Ny, cc, ym);
-    else HM_DST_LAUNCH((k_dst_inv_fold<0, false>), g, m->d_dsth, W, lam, tix, Y, ldy, N, Ny, cc, ym);
+    dim3 g(ceil_div(N / 2, GBM), yt * mo.nq);
+    if (am == 2 && lam) HM_DST_LAUNCH((k_dst_inv_fold<2, true>), g, m->d_dsth, W, mo, tix, ldy, N, Ny, cc, ym);
+    else if (am == 2) HM_DST_LAUNCH((k_dst_inv_fold<2, false>), g, m->d_dsth, W, mo, tix, ldy, N, Ny, cc, ym);
+    else if (am == 1) HM_DST_LAUNCH((k_dst_inv_fold<1, false>), g, m->d_dsth, W, mo, tix, ldy, N, Ny, cc, ym);
+    else HM_DST_LAUNCH((k_dst_inv_fold<0, false>), g, m->d_dsth, W, mo, tix, ldy, N, Ny, cc, ym);
     return;
   }
   const int Mx = xm.extent(N);
-  dim3 g(ceil_div(Mx, GBM), ceil_div((long)cc * Ny, GBN));
-  if (am == 2 && lam) HM_DST_LAUNCH((k_dst_inv<2, true>), g, m->d_dst, W, lam, tix, Y, ldy, N, Ny, cc, Mx, xm, ym);
-  else if (am == 2) HM_DST_LAUNCH((k_dst_inv<2, false>), g, m->d_dst, W, lam, tix, Y, ldy, N, Ny, cc, Mx, xm, ym);
-  else if (am == 1) HM_DST_LAUNCH((k_dst_inv<1, false>), g, m->d_dst, W, lam, tix, Y, ldy, N, Ny, cc, Mx, xm, ym);
-  else HM_DST_LAUNCH((k_dst_inv<0, false>), g, m->d_dst, W, lam, tix, Y, ldy, N, Ny, cc, Mx, xm, ym);
+  dim3 g(ceil_div(Mx, GBM), yt * mo.nq);
+  if (am == 2 && lam) HM_DST_LAUNCH((k_dst_inv<2, true>), g, m->d_dst, W, mo, tix, ldy, N, Ny, cc, Mx, xm, ym);
+  else if (am == 2) HM_DST_LAUNCH((k_dst_inv<2, false>), g, m->d_dst, W, mo, tix, ldy, N, Ny, cc, Mx, xm, ym);
+  else if (am == 1) HM_DST_LAUNCH((k_dst_inv<1, false>), g, m->d_dst, W, mo, tix, ldy, N, Ny, cc, Mx, xm, ym);
+  else HM_DST_LAUNCH((k_dst_inv<0, false>), g, m->d_dst, W, mo, tix, ldy, N, Ny, cc, Mx, xm, ym);
 }
 #undef HM_DST_LAUNCH
 
@@ -643,7 +670,7 @@ hm_status kapply_sel(Model* m, const double theta[4], const double* X, int ldx, 
   const int Nyi = two ? yin.extent(N) : 1, Nyo = two ? yout.extent(N) : 1;
   double* Xh = m->d_ws;                        // x-transformed (compact input y)
   double* X2 = m->d_ws + (long)n * m->cmax;    // x- and y-transformed (2D)
-  double* X3 = m->d_ws + 2L * n * m->cmax;     // scaled and y-inverse-transformed (compact output y)
+  double* X3 = m->d_ws + 2L * n * m->cmax;     // scaled and y-inverse-transformed, one slot per output
   double* outs[3] = {outK, outKap, outAlp};
   const bool pf = prof_on(m, PF_DST);
   int nout = 0;
@@ -663,19 +690,26 @@ hm_status kapply_sel(Model* m, const double theta[4], const double* X, int ldx, 
       y_forward(m, Xh, X2, cc, yin);
       HM_LAUNCH_CHECK();
     }
+    MultiOut mo{};
     for (int q = 0; q < 3; ++q) {
       if (!outs[q]) continue;
-      const double* lam = m->d_lam + q * NN;
-      double* Yc = outs[q] + (long)c0 * ldo;
-      if (two) {
-        y_inverse(m, X2, lam, X3, cc, yout);
-        HM_LAUNCH_CHECK();
-        x_inverse(m, X3, nullptr, Yc, ldo, cc, Nyo, xout, yout);
-      } else {
-        x_inverse(m, Xh, lam, Yc, ldo, cc, 1, xout, yout);
-      }
-      HM_LAUNCH_CHECK();
+      mo.Y[mo.nq] = outs[q] + (long)c0 * ldo;
+      mo.lam[mo.nq] = m->d_lam + q * NN;
+      ++mo.nq;
     }
+    if (mo.nq == 0) continue;
+    if (two) {
+      // X3 holds one slot of n * cmax doubles per output
+      const long slot = (long)n * m->cmax;
+      y_inverse(m, X2, mo, X3, slot, cc, yout);
+      HM_LAUNCH_CHECK();
+      mo.in_stride = slot;
+      x_inverse(m, X3, mo, false, ldo, cc, Nyo, xout, yout);
+    } else {
+      mo.in_stride = 0;
+      x_inverse(m, Xh, mo, true, ldo, cc, 1, xout, yout);
+    }
+    HM_LAUNCH_CHECK();
   }
   if (pf) {
     // bytes: each pass reads and writes its n x c block once (compact where the maps halve it), plus S
