@@ -153,7 +153,7 @@ struct RedArgs {
 // 16 x 16 (sized to the real widths, not padded to 64).  Two wavefronts split the
 // leaf's rows and combine through LDS.
 template <int P, int MB, int NB, int NW>
-__global__ void __launch_bounds__(64 * NW) k_reduce_direct(RedArgs a) {
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) k_reduce_direct(RedArgs a) {
   using MP = MfmaPrec<P>;
   using T = typename MP::T;
   __shared__ double red[(NW - 1) * MB * NB * 4 * 64];
@@ -176,36 +176,48 @@ __global__ void __launch_bounds__(64 * NW) k_reduce_direct(RedArgs a) {
   for (int i = 0; i < MB; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[i][j] = MP::zero();
+  // Lane (li, lk) reads rows g + 4 lk .. g + 4 lk + 3 of its columns: 32 contiguous
+  // bytes.  The loads are branch-free (a column past the operand reads the tile's first
+  // column, a row group past the range reads rows 0..3) and zeroed where they are used,
+  // so each chunk's loads go out as wide loads together.
   const double* Ac[MB];
   const double* Xc[NB];
   bool aok[MB], xok[NB];
 #pragma unroll
   for (int i = 0; i < MB; ++i) {
     aok[i] = m0 + 16 * i + li < wa;
-    Ac[i] = Ab + (long)(16 * i + li) * a.lda;
+    Ac[i] = Ab + (long)(aok[i] ? 16 * i + li : 0) * a.lda;
   }
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     xok[j] = n0 + 16 * j + li < wx;
-    Xc[j] = Xb + (long)(16 * j + li) * a.ldx;
+    Xc[j] = Xb + (long)(xok[j] ? 16 * j + li : 0) * a.ldx;
   }
   for (int g = rbeg; g < rend; g += 16) {
     const int rr = g + 4 * lk;
-    T av[MB][4], xv[NB][4];
+    const int rl = (rr + 3 < a.nl) ? rr : 0;   // a group of 4 rows inside the leaf
+    double ar[MB][4], xr[NB][4];
 #pragma unroll
     for (int i = 0; i < MB; ++i)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) av[i][q] = (aok[i] && rr + q < rend) ? (T)Ac[i][rr + q] : (T)0;
+      for (int q = 0; q < 4; ++q) ar[i][q] = Ac[i][rl + q];
 #pragma unroll
     for (int j = 0; j < NB; ++j)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) xv[j][q] = (xok[j] && rr + q < rend) ? (T)Xc[j][rr + q] : (T)0;
+      for (int q = 0; q < 4; ++q) xr[j][q] = Xc[j][rl + q];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 4; ++q) {
+      const bool rok = rr + q < rend;
+      T av[MB], xv[NB];
+#pragma unroll
+      for (int i = 0; i < MB; ++i) av[i] = (aok[i] && rok) ? (T)ar[i][q] : (T)0;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) xv[j] = (xok[j] && rok) ? (T)xr[j][q] : (T)0;
 #pragma unroll
       for (int i = 0; i < MB; ++i)
 #pragma unroll
-        for (int j = 0; j < NB; ++j) acc[i][j] = MP::mfma(av[i][q], xv[j][q], acc[i][j]);
+        for (int j = 0; j < NB; ++j) acc[i][j] = MP::mfma(av[i], xv[j], acc[i][j]);
+    }
   }
   if (wave > 0) {
     double* slot = red + (wave - 1) * (MB * NB * 4 * 64);
