@@ -16,6 +16,25 @@ namespace hm {
 
 constexpr int KMAX = 64;    // largest panel width handled in LDS
 
+// dst[c * ds] -= f * src[c * ss] for c = c0, c0 + step, ... < c1, four updates at a time
+// with every read issued before the writes (callers guarantee dst and src never overlap),
+// so the LDS round trips of one group overlap.
+__device__ __forceinline__ void axpy_strided(double* dst, long ds, const double* src, long ss, double f, int c0,
+                                             int c1, int step) {
+  int c = c0;
+  for (; c + 3 * step < c1; c += 4 * step) {
+    const double s0 = src[c * ss], s1 = src[(c + step) * ss], s2 = src[(c + 2 * step) * ss],
+                 s3 = src[(c + 3 * step) * ss];
+    const double d0 = dst[c * ds], d1 = dst[(c + step) * ds], d2 = dst[(c + 2 * step) * ds],
+                 d3 = dst[(c + 3 * step) * ds];
+    dst[c * ds] = d0 - f * s0;
+    dst[(c + step) * ds] = d1 - f * s1;
+    dst[(c + 2 * step) * ds] = d2 - f * s2;
+    dst[(c + 3 * step) * ds] = d3 - f * s3;
+  }
+  for (; c < c1; c += step) dst[c * ds] -= f * src[c * ss];
+}
+
 // ---------------------------------------------------------------------------
 // Cholesky + triangular inverse of G (k x k, ld k), one node per workgroup.
 // shift: if nonzero, G + s I with s = 11 (m k + k (k+1)) u ||.||_F^2, m = rows of
@@ -71,8 +90,8 @@ __global__ void __launch_bounds__(256) k_chol_inv(const double* G, long gstride,
     const int i = lane;
     if (i > j && i < k) {
       const double f = A[i + j * k] * rd;
-      for (int l = j + 1 + wave; l <= i; l += nw) A[i + l * k] -= f * A[l + j * k];
-      for (int c = wave; c <= j; c += nw) Y[i + c * k] -= f * Y[j + c * k];
+      axpy_strided(A + i, k, A + (long)j * k, 1, f, j + 1 + wave, i + 1, nw);   // column j is not written
+      axpy_strided(Y + i, k, Y + j, k, f, wave, j + 1, nw);                     // row j is not written
     }
     __syncthreads();
   }
@@ -167,8 +186,8 @@ __global__ void __launch_bounds__(256) k_node_lu(const double* S, long sstride, 
     if (lane < k && lane != p) {
       const double f = A[lane + j * k] * rp;
       const int wave = tid >> 6, nw = nt >> 6;
-      for (int c = j + 1 + wave; c < k; c += nw) A[lane + c * k] -= f * A[p + c * k];
-      for (int c = wave; c < k; c += nw) Si[lane + c * k] -= f * Si[p + c * k];
+      axpy_strided(A + lane, k, A + p, k, f, j + 1 + wave, k, nw);   // row p is not written
+      axpy_strided(Si + lane, k, Si + p, k, f, wave, k, nw);
     }
     __syncthreads();
   }
