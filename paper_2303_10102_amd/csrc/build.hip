@@ -215,9 +215,17 @@ hm_status level_step(Model* m, const double theta[4], const PanelSet& ps, int l,
   // ---- pass 2: C = B^T Q on the right-children rows
   double* dZ[2] = {b.dZ[0], b.dZ[1]};
   tangent_outputs(dZ, &kap, &alp);
-  HM_CHECK(kapply_sel(m, theta, b.XS, n, w, b.Z, kap, alp, n, left, right));
+  bool adjacent = nr > 0;   // XS | XdS[j] and Z | Zq[j] laid out one after another
   for (int j = 0; j < nr; ++j)
-    HM_CHECK(kapply_sel(m, theta, b.XdS[j], n, w, b.Zq[j], nullptr, nullptr, n, left, right));
+    adjacent = adjacent && b.XdS[j] == b.XS + (long)(j + 1) * n * w && b.Zq[j] == b.Z + (long)(j + 1) * n * w;
+  if (adjacent) {
+    // one K-apply: K on all (1 + nr) w columns, the tangents on the first w
+    HM_CHECK(kapply_multi(m, theta, b.XS, n, (1 + nr) * w, b.Z, (1 + nr) * w, kap, w, alp, w, n, left, right));
+  } else {
+    HM_CHECK(kapply_sel(m, theta, b.XS, n, w, b.Z, kap, alp, n, left, right));
+    for (int j = 0; j < nr; ++j)
+      HM_CHECK(kapply_sel(m, theta, b.XdS[j], n, w, b.Zq[j], nullptr, nullptr, n, left, right));
+  }
   HM_CHECK(subtract_coarser(m, ps, l, b.XS, w, left, right, b.Z, nr ? dZ : nullptr, nr, nb));
   for (int j = 0; j < nr; ++j)
     HM_CHECK(subtract_coarser(m, ps, l, b.XdS[j], w, left, right, b.Zq[j], nullptr, 0, nb));

@@ -183,6 +183,11 @@ inline LeafSel sel_all() { return LeafSel{0, 1}; }
 // rows outside out_sel are left unwritten.  Same result on the needed rows.
 hm_status kapply_sel(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK,
                      double* outKap, double* outAlp, int ldo, LeafSel in_sel, LeafSel out_sel);
+// The same with per-output column counts: outK gets the first cK columns of K X, outKap /
+// outAlp the first cKap / cAlp columns of the tangents (one pass of forward transforms).
+hm_status kapply_multi(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK, int cK,
+                       double* outKap, int cKap, double* outAlp, int cAlp, int ldo, LeafSel in_sel,
+                       LeafSel out_sel);
 
 // For every node c at depth d in [d0,d1]:  out_c = A[c rows, ac(d)]^T X[c rows, xc(d)]
 // (wa x wx(d) column-major, ld wa, stored at out + heap(c)*out_stride).  Rows of

@@ -130,13 +130,21 @@ static inline AxisMap axis_map(int W, int par) { return AxisMap{W, par, recip32(
 // The outputs of one K-apply (K X, dK/dkappa X, dK/dalpha X, any subset) share the
 // forward transforms; their inverse transforms run as one launch, output o taking the
 // multipliers lam[o] and writing Y[o] (x inverse) or slot o of the scratch (y inverse).
+// Output o covers the first cols[o] columns of the block (a tangent may be wanted for
+// fewer columns than the value); z-slices and column tiles of the launches are laid out
+// output after output (zoff, toff: prefix sums of the columns and of the column tiles).
 struct MultiOut {
   double* Y[3];
   const double* lam[3];
   long in_stride;    // input offset between outputs (0: one shared input)
   int nq;
+  int cols[3], zoff[3], toff[3];
   __device__ __forceinline__ const double* lam_of(int o) const { return o == 0 ? lam[0] : (o == 1 ? lam[1] : lam[2]); }
   __device__ __forceinline__ double* y_of(int o) const { return o == 0 ? Y[0] : (o == 1 ? Y[1] : Y[2]); }
+  __device__ __forceinline__ int pick(int v, const int (&off)[3]) const {
+    return (nq > 2 && v >= off[2]) ? 2 : ((nq > 1 && v >= off[1]) ? 1 : 0);
+  }
+  __device__ __forceinline__ int get(const int (&a)[3], int o) const { return o == 0 ? a[0] : (o == 1 ? a[1] : a[2]); }
 };
 
 // Column r of a transform operand is (col, y') = (r / Ny, r % Ny) over the compact
@@ -318,10 +326,10 @@ __global__ void __launch_bounds__(256) k_dst_yf(const double* S, const double* M
 // inverse y: C_{o,c} = (lam_o o M_c) S[:, ymap(.)]  (M_c: N x N; C_{o,c}: N x Nyout at
 // o * cslot + c*N*Nyout); grid.z = outputs x columns
 __global__ void __launch_bounds__(256) k_dst_yi(const double* S, const double* M, MultiOut mo, double* C,
-                                                long cslot, int cc, int N, int Nyout, AxisMap ym) {
+                                                long cslot, int N, int Nyout, AxisMap ym) {
   __shared__ double smem[GSMEM];
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
-  const int o = blockIdx.z / cc, c = blockIdx.z % cc;
+  const int o = mo.pick(blockIdx.z, mo.zoff), c = blockIdx.z - mo.get(mo.zoff, o);
   DyLA<true> la{M + (long)c * N * N, mo.lam_of(o), N, m0};
   DyLBinv lb{S, N, n0, Nyout, ym};
   TileAcc acc;
@@ -335,12 +343,11 @@ __global__ void __launch_bounds__(256) k_dst_yi(const double* S, const double* M
 // grid.y = outputs x column tiles
 template <int AM, bool LAM>
 __global__ void __launch_bounds__(256) k_dst_inv(const double* S, const double* W, MultiOut mo, TreeIdx tix,
-                                                 int ldy, int N, int Ny, int ncol, int Mx, AxisMap xm,
-                                                 AxisMap ym) {
+                                                 int ldy, int N, int Ny, int Mx, AxisMap xm, AxisMap ym) {
   __shared__ double smem[GSMEM];
-  const int yt = (ncol * Ny + GBN - 1) / GBN;
-  const int o = blockIdx.y / yt;
-  const int m0 = blockIdx.x * GBM, n0 = (blockIdx.y - o * yt) * GBN;
+  const int o = mo.pick(blockIdx.y, mo.toff);
+  const int ncol = mo.get(mo.cols, o);
+  const int m0 = blockIdx.x * GBM, n0 = (blockIdx.y - mo.get(mo.toff, o)) * GBN;
   const ColGeo<AM> cg = col_geo<AM>(Ny, n0, ncol);
   double* Y = mo.y_of(o);
   DstLSrow la{S, N, m0, Mx, xm};
@@ -515,11 +522,11 @@ __global__ void __launch_bounds__(256) k_dst_yf_fold(const double* Ph, const dou
 // C_c(p, y') = e + o, C_c(p, N-1-y') = e - o for y' < H
 // (grid.z = outputs x columns, as k_dst_yi)
 __global__ void __launch_bounds__(256) k_dst_yi_fold(const double* Ph, const double* M, MultiOut mo, double* C,
-                                                     long cslot, int cc, int N) {
+                                                     long cslot, int N) {
   __shared__ double smem[GSMEM];
   const int H = N / 2;
   const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
-  const int q = blockIdx.z / cc, c = blockIdx.z % cc;
+  const int q = mo.pick(blockIdx.z, mo.zoff), c = blockIdx.z - mo.get(mo.zoff, q);
   const long NN = (long)N * N, HH = (long)H * H;
   const double* Mz = M + c * NN;
   const double* lam = mo.lam_of(q);
@@ -536,13 +543,13 @@ __global__ void __launch_bounds__(256) k_dst_yi_fold(const double* Ph, const dou
 // (grid.y = outputs x column tiles, as k_dst_inv)
 template <int AM, bool LAM>
 __global__ void __launch_bounds__(256) k_dst_inv_fold(const double* Ph, const double* W, MultiOut mo, TreeIdx tix,
-                                                      int ldy, int N, int Ny, int ncol, AxisMap ym) {
+                                                      int ldy, int N, int Ny, AxisMap ym) {
   __shared__ double smem[GSMEM];
   const int H = N / 2;
   const long HH = (long)H * H;
-  const int yt = (ncol * Ny + GBN - 1) / GBN;
-  const int q = blockIdx.y / yt;
-  const int m0 = blockIdx.x * GBM, n0 = (blockIdx.y - q * yt) * GBN;
+  const int q = mo.pick(blockIdx.y, mo.toff);
+  const int ncol = mo.get(mo.cols, q);
+  const int m0 = blockIdx.x * GBM, n0 = (blockIdx.y - mo.get(mo.toff, q)) * GBN;
   const ColGeo<AM> cg = col_geo<AM>(Ny, n0, ncol);
   const double* Wq = W + q * mo.in_stride;
   const double* lam = mo.lam_of(q);
@@ -619,45 +626,59 @@ static void y_forward(Model* m, const double* M, double* C, int cc, AxisMap ym) 
   HM_DST_LAUNCH(k_dst_yf, g, m->d_dst, M, C, N, ym.extent(N), ym);
 }
 // C_{o,c} (N x Nyout, compact per ym; output o at C + o * cslot) = (lam_o o M_c)
-// transformed back along y, all outputs in one launch
-static void y_inverse(Model* m, const double* M, const MultiOut& mo, double* C, long cslot, int cc, AxisMap ym) {
+// transformed back along y, c < cols[o], all outputs in one launch
+static void y_inverse(Model* m, const double* M, MultiOut mo, double* C, long cslot, AxisMap ym) {
   const int N = m->N;
+  int z = 0;
+  for (int o = 0; o < mo.nq; ++o) {
+    mo.zoff[o] = z;
+    z += mo.cols[o];
+  }
   if (folds(m, ym)) {
-    dim3 g(ceil_div(N, GBM), ceil_div(N / 2, GBN), cc * mo.nq);
-    HM_DST_LAUNCH(k_dst_yi_fold, g, m->d_dsth, M, mo, C, cslot, cc, N);
+    dim3 g(ceil_div(N, GBM), ceil_div(N / 2, GBN), z);
+    HM_DST_LAUNCH(k_dst_yi_fold, g, m->d_dsth, M, mo, C, cslot, N);
     return;
   }
   const int Nyo = ym.extent(N);
-  dim3 g(ceil_div(N, GBM), ceil_div(Nyo, GBN), cc * mo.nq);
-  HM_DST_LAUNCH(k_dst_yi, g, m->d_dst, M, mo, C, cslot, cc, N, Nyo, ym);
+  dim3 g(ceil_div(N, GBM), ceil_div(Nyo, GBN), z);
+  HM_DST_LAUNCH(k_dst_yi, g, m->d_dst, M, mo, C, cslot, N, Nyo, ym);
 }
-// Y_o (scattered to tree order; x compact per xm) = S_x applied to W + o * mo.in_stride
-// (N x cc*Ny), scaled by lam_o when LAM (one-dimensional models); all outputs in one launch
-static void x_inverse(Model* m, const double* W, const MultiOut& mo, bool lam, int ldy, int cc, int Ny, AxisMap xm,
-                      AxisMap ym) {
+// Y_o (scattered to tree order; x compact per xm) = S_x applied to the first cols[o]
+// column groups of W + o * mo.in_stride (N x cols*Ny), scaled by lam_o when LAM
+// (one-dimensional models); all outputs in one launch
+static void x_inverse(Model* m, const double* W, MultiOut mo, bool lam, int ldy, int Ny, AxisMap xm, AxisMap ym) {
   const int N = m->N, am = amode(Ny);
   const TreeIdx tix = m->tix;
-  const int yt = ceil_div((long)cc * Ny, GBN);
+  int t = 0;
+  for (int o = 0; o < mo.nq; ++o) {
+    mo.toff[o] = t;
+    t += ceil_div((long)mo.cols[o] * Ny, GBN);
+  }
   if (folds(m, xm)) {
-    dim3 g(ceil_div(N / 2, GBM), yt * mo.nq);
-    if (am == 2 && lam) HM_DST_LAUNCH((k_dst_inv_fold<2, true>), g, m->d_dsth, W, mo, tix, ldy, N, Ny, cc, ym);
-    else if (am == 2) HM_DST_LAUNCH((k_dst_inv_fold<2, false>), g, m->d_dsth, W, mo, tix, ldy, N, Ny, cc, ym);
-    else if (am == 1) HM_DST_LAUNCH((k_dst_inv_fold<1, false>), g, m->d_dsth, W, mo, tix, ldy, N, Ny, cc, ym);
-    else HM_DST_LAUNCH((k_dst_inv_fold<0, false>), g, m->d_dsth, W, mo, tix, ldy, N, Ny, cc, ym);
+    dim3 g(ceil_div(N / 2, GBM), t);
+    if (am == 2 && lam) HM_DST_LAUNCH((k_dst_inv_fold<2, true>), g, m->d_dsth, W, mo, tix, ldy, N, Ny, ym);
+    else if (am == 2) HM_DST_LAUNCH((k_dst_inv_fold<2, false>), g, m->d_dsth, W, mo, tix, ldy, N, Ny, ym);
+    else if (am == 1) HM_DST_LAUNCH((k_dst_inv_fold<1, false>), g, m->d_dsth, W, mo, tix, ldy, N, Ny, ym);
+    else HM_DST_LAUNCH((k_dst_inv_fold<0, false>), g, m->d_dsth, W, mo, tix, ldy, N, Ny, ym);
     return;
   }
   const int Mx = xm.extent(N);
-  dim3 g(ceil_div(Mx, GBM), yt * mo.nq);
-  if (am == 2 && lam) HM_DST_LAUNCH((k_dst_inv<2, true>), g, m->d_dst, W, mo, tix, ldy, N, Ny, cc, Mx, xm, ym);
-  else if (am == 2) HM_DST_LAUNCH((k_dst_inv<2, false>), g, m->d_dst, W, mo, tix, ldy, N, Ny, cc, Mx, xm, ym);
-  else if (am == 1) HM_DST_LAUNCH((k_dst_inv<1, false>), g, m->d_dst, W, mo, tix, ldy, N, Ny, cc, Mx, xm, ym);
-  else HM_DST_LAUNCH((k_dst_inv<0, false>), g, m->d_dst, W, mo, tix, ldy, N, Ny, cc, Mx, xm, ym);
+  dim3 g(ceil_div(Mx, GBM), t);
+  if (am == 2 && lam) HM_DST_LAUNCH((k_dst_inv<2, true>), g, m->d_dst, W, mo, tix, ldy, N, Ny, Mx, xm, ym);
+  else if (am == 2) HM_DST_LAUNCH((k_dst_inv<2, false>), g, m->d_dst, W, mo, tix, ldy, N, Ny, Mx, xm, ym);
+  else if (am == 1) HM_DST_LAUNCH((k_dst_inv<1, false>), g, m->d_dst, W, mo, tix, ldy, N, Ny, Mx, xm, ym);
+  else HM_DST_LAUNCH((k_dst_inv<0, false>), g, m->d_dst, W, mo, tix, ldy, N, Ny, Mx, xm, ym);
 }
 #undef HM_DST_LAUNCH
 
-hm_status kapply_sel(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK,
-                     double* outKap, double* outAlp, int ldo, LeafSel in_sel, LeafSel out_sel) {
+hm_status kapply_multi(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK, int cK,
+                       double* outKap, int cKap, double* outAlp, int cAlp, int ldo, LeafSel in_sel,
+                       LeafSel out_sel) {
   if (c <= 0) return HM_OK;
+  if (cK > c || cKap > c || cAlp > c) {
+    set_error("kapply: an output wants more columns than the input has");
+    return HM_E_INVAL;
+  }
   HM_CHECK(ensure_scale(m, theta));
   const int n = m->n, N = m->N;
   const bool two = (m->dim == 2);
@@ -672,9 +693,10 @@ hm_status kapply_sel(Model* m, const double theta[4], const double* X, int ldx, 
   double* X2 = m->d_ws + (long)n * m->cmax;    // x- and y-transformed (2D)
   double* X3 = m->d_ws + 2L * n * m->cmax;     // scaled and y-inverse-transformed, one slot per output
   double* outs[3] = {outK, outKap, outAlp};
+  const int ocols[3] = {outK ? cK : 0, outKap ? cKap : 0, outAlp ? cAlp : 0};
   const bool pf = prof_on(m, PF_DST);
-  int nout = 0;
-  for (int q = 0; q < 3; ++q) nout += outs[q] ? 1 : 0;
+  double nout = 0.0;   // output columns per input column
+  for (int q = 0; q < 3; ++q) nout += (double)ocols[q] / c;
   // work of the transform GEMMs actually run, per column (a folded axis halves its GEMM)
   const double fx_in = folds(m, xin) ? 0.5 : 1.0, fy_in = folds(m, yin) ? 0.5 : 1.0;
   const double fx_out = folds(m, xout) ? 0.5 : 1.0, fy_out = folds(m, yout) ? 0.5 : 1.0;
@@ -692,22 +714,24 @@ hm_status kapply_sel(Model* m, const double theta[4], const double* X, int ldx, 
     }
     MultiOut mo{};
     for (int q = 0; q < 3; ++q) {
-      if (!outs[q]) continue;
+      const int oc = std::min(cc, ocols[q] - c0);   // this output's columns in the block
+      if (!outs[q] || oc <= 0) continue;
       mo.Y[mo.nq] = outs[q] + (long)c0 * ldo;
       mo.lam[mo.nq] = m->d_lam + q * NN;
+      mo.cols[mo.nq] = oc;
       ++mo.nq;
     }
     if (mo.nq == 0) continue;
     if (two) {
       // X3 holds one slot of n * cmax doubles per output
       const long slot = (long)n * m->cmax;
-      y_inverse(m, X2, mo, X3, slot, cc, yout);
+      y_inverse(m, X2, mo, X3, slot, yout);
       HM_LAUNCH_CHECK();
       mo.in_stride = slot;
-      x_inverse(m, X3, mo, false, ldo, cc, Nyo, xout, yout);
+      x_inverse(m, X3, mo, false, ldo, Nyo, xout, yout);
     } else {
       mo.in_stride = 0;
-      x_inverse(m, Xh, mo, true, ldo, cc, 1, xout, yout);
+      x_inverse(m, Xh, mo, true, ldo, 1, xout, yout);
     }
     HM_LAUNCH_CHECK();
   }
@@ -718,6 +742,11 @@ hm_status kapply_sel(Model* m, const double theta[4], const double* X, int ldx, 
     prof_end(m, PF_DST, per_col * c, passes * 16.0 * n * (double)c + 8.0 * N * (double)N);
   }
   return HM_OK;
+}
+
+hm_status kapply_sel(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK,
+                     double* outKap, double* outAlp, int ldo, LeafSel in_sel, LeafSel out_sel) {
+  return kapply_multi(m, theta, X, ldx, c, outK, c, outKap, c, outAlp, c, ldo, in_sel, out_sel);
 }
 
 hm_status kapply(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK,
