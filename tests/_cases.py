@@ -18,6 +18,9 @@ CASES = {
     "2d_n1024": small_workload(N=32, leaf=64, rank=16, sigma2=1.0e3, name="2d_n1024"),
     # 2D 64x64 with the headline workload's leaf size and rank
     "2d_n4096": WORKLOADS["2d_n4096"],
+    # 2D 48x48, leaf 6x6 (6 levels): leaf extents and split widths that are not powers
+    # of two (the transforms' closed-form tree index and axis maps divide by 6, 12, 24)
+    "2d_n2304": small_workload(N=48, leaf=36, rank=12, sigma2=1.0e3, name="2d_n2304"),
 }
 
 

@@ -25,7 +25,7 @@ def _need_gpu():
         pytest.skip("no HIP device")
 
 
-@pytest.fixture(scope="module", params=["1d_n1024", "2d_n1024", "2d_n4096"])
+@pytest.fixture(scope="module", params=["1d_n1024", "2d_n1024", "2d_n4096", "2d_n2304"])
 def case(request):
     _need_gpu()
     key = request.param
