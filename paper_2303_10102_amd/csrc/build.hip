@@ -122,12 +122,13 @@ hm_status subtract_coarser(Model* m, const PanelSet& ps, int l, const double* X,
     for (int j = 0; j < nr; ++j) {
       ReduceJob rd{ps.dF[j], m->n, cs_block(bw), X, m->n, cs_fixed(0, w), 1, l - 1, nb.dt[j], ts, xsel};
       HM_CHECK(tree_reduce(m, rd));
-      ExpandJob e1{ps.dF[j], m->n, cs_block(bw), dY[j], m->n, cs_fixed(0, w), nb.t, ts, bw, 1, 0, 1, l - 1, -1.0,
-                   1.0, ysel};
-      HM_CHECK(tree_expand(m, e1));
-      ExpandJob e2{ps.F, m->n, cs_block(bw), dY[j], m->n, cs_fixed(0, w), nb.dt[j], ts, bw, 1, 0, 1, l - 1, -1.0,
-                   1.0, ysel};
-      HM_CHECK(tree_expand(m, e2));
+      // dY -= dF t + F dt in one launch
+      ExpandJob e{ps.dF[j], m->n, cs_block(bw), dY[j], m->n, cs_fixed(0, w), nb.t, ts, bw, 1, 0, 1, l - 1, -1.0,
+                  1.0, ysel};
+      e.A2 = ps.F;
+      e.T2 = nb.dt[j];
+      e.alpha2 = -1.0;
+      HM_CHECK(tree_expand(m, e));
     }
   }
   return HM_OK;
@@ -177,10 +178,12 @@ static hm_status qr_tangent(Model* m, const double* Q, const double* dY, int w, 
   HM_CHECK(gemm(m->stream, false, false, w, w, w, 1.0, nb.g + heap0 * s2, w, 2 * s2, nb.rinv + heap0 * s2, w,
                 2 * s2, 0.0, nb.w + heap0 * s2, w, 2 * s2, cnt));
   HM_CHECK(alg2_fold_nodes(m, nb.w, nb.mfold, s2, w, heap0, 2 * cnt));
-  ExpandJob e1{dY, m->n, cs_fixed(0, w), out, m->n, cs_fixed(0, w), nb.rinv, s2, w, 0, 0, l, l, 1.0, 0.0, left};
-  HM_CHECK(tree_expand(m, e1));
-  ExpandJob e2{Q, m->n, cs_fixed(0, w), out, m->n, cs_fixed(0, w), nb.mfold, s2, w, 0, 0, l, l, -1.0, 1.0, left};
-  HM_CHECK(tree_expand(m, e2));
+  // out = dY R^{-1} - Q M in one launch
+  ExpandJob e{dY, m->n, cs_fixed(0, w), out, m->n, cs_fixed(0, w), nb.rinv, s2, w, 0, 0, l, l, 1.0, 0.0, left};
+  e.A2 = Q;
+  e.T2 = nb.mfold;
+  e.alpha2 = -1.0;
+  HM_CHECK(tree_expand(m, e));
   return HM_OK;
 }
 

@@ -99,10 +99,11 @@ hm_status hmatvec(FactorCtx& f, const double* Dl, const double* Fp, const double
   }
   ReduceJob rd{dFp, n, cs_block(kc), x, n, cs_fixed(0, w), 1, levels, f.nU, ts, sel_all()};
   HM_CHECK(tree_reduce(m, rd));
-  ExpandJob e1{dFp, n, cs_block(kc), y, n, cs_fixed(0, w), f.nT, ts, kc, 1, 0, 1, levels, alpha, 1.0, sel_all()};
-  HM_CHECK(tree_expand(m, e1));
-  ExpandJob e2{Fp, n, cs_block(kc), y, n, cs_fixed(0, w), f.nU, ts, kc, 1, 0, 1, levels, alpha, 1.0, sel_all()};
-  HM_CHECK(tree_expand(m, e2));
+  ExpandJob e{dFp, n, cs_block(kc), y, n, cs_fixed(0, w), f.nT, ts, kc, 1, 0, 1, levels, alpha, 1.0, sel_all()};
+  e.A2 = Fp;
+  e.T2 = f.nU;
+  e.alpha2 = alpha;
+  HM_CHECK(tree_expand(m, e));
   return HM_OK;
 }
 

@@ -207,6 +207,8 @@ hm_status tree_reduce(Model* m, const ReduceJob& j);
 // parent (2); r0 = half_off if tmode==2 and c is a right child, else 0.  wk = ac.w0.
 // T blocks: T + heap(s(c))*t_stride, ld ldt.  beta is applied once per element of
 // the union of yc(d) over the segments.
+// Optional second source: A2 with blocks T2 (same layout as A, T) adds alpha2 * A2 T2
+// to the same sum, so Y = beta Y + alpha sum A T + alpha2 sum A2 T2 in one launch.
 struct ExpandJob {
   const double* A; int lda; ColSpec ac;
   double* Y; int ldy; ColSpec yc;
@@ -214,6 +216,9 @@ struct ExpandJob {
   int d0, d1;
   double alpha, beta;
   LeafSel sel;
+  const double* A2 = nullptr;
+  const double* T2 = nullptr;
+  double alpha2 = 0.0;
 };
 hm_status tree_expand(Model* m, const ExpandJob& j);
 

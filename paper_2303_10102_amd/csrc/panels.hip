@@ -463,6 +463,7 @@ struct ExpArgs {
   double alpha, beta;
   int ylo, yhi;  // union of the output columns
   int sel_mode, sel_depth;
+  const double* A2; const double* T2; double t2_scale;   // second source (A2 null: none)
 };
 
 // Expand with the tall operand fed straight into the matrix cores (P = 0 FP64,
@@ -492,26 +493,31 @@ __device__ __forceinline__ bool exp_seg_active(const ExpArgs& a, int d, int j0, 
   const int yc0 = a.yc.c0(d), wy = a.yc.w(d);
   return wy > 0 && j0 < yc0 + wy && j0 + tw > yc0;
 }
-// next unit after (d, k0); d < d0 means "before the first"
-__device__ __forceinline__ bool exp_next_unit(const ExpArgs& a, int j0, int tw, int& d, int& k0) {
+// next unit after (src, d, k0); d < d0 means "before the first" of that source.  The
+// units of the second source (if any) follow those of the first.
+__device__ __forceinline__ bool exp_next_unit(const ExpArgs& a, int j0, int tw, int& src, int& d, int& k0) {
   if (d >= a.d0) {
     k0 += EXK;
     if (k0 < a.ac.w0) return true;
   }
-  for (++d; d <= a.d1; ++d)
-    if (exp_seg_active(a, d, j0, tw)) {
-      k0 = 0;
-      return true;
-    }
-  return false;
+  for (;;) {
+    for (++d; d <= a.d1; ++d)
+      if (exp_seg_active(a, d, j0, tw)) {
+        k0 = 0;
+        return true;
+      }
+    if (src != 0 || !a.A2) return false;
+    src = 1;
+    d = a.d0 - 1;
+  }
 }
-__device__ __forceinline__ const double* exp_T(const ExpArgs& a, int L, int d) {
+__device__ __forceinline__ const double* exp_T(const ExpArgs& a, int src, int L, int d) {
   const int c = L >> (a.levels - d);
   const int heap = (1 << d) - 1 + c;
   int sel = heap, roff = 0;
   if (a.tmode == 1) sel = (heap & 1) ? heap + 1 : heap - 1;
   else if (a.tmode == 2) { sel = (heap - 1) >> 1; roff = (c & 1) ? a.half_off : 0; }
-  return a.T + sel * a.t_stride + roff;
+  return (src ? a.T2 : a.T) + sel * a.t_stride + roff;
 }
 
 template <int P, int NB, int RB>
@@ -553,8 +559,8 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
     double tv[EXT];
   };
   const int kk_t = tid % EXK, cc_t = tid / EXK;   // this thread's T elements: (kk_t, cc_t + 8 q)
-  auto load_unit = [&](int d, int k0, Unit& u) {
-    const double* Ab = a.A + r0 + (long)a.ac.c0(d) * a.lda;
+  auto load_unit = [&](int src, int d, int k0, Unit& u) {
+    const double* Ab = (src ? a.A2 : a.A) + r0 + (long)a.ac.c0(d) * a.lda;
 #pragma unroll
     for (int r = 0; r < RB; ++r)
 #pragma unroll
@@ -562,7 +568,7 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
         const int k = k0 + 4 * s + lk;
         u.av[r][s] = Ab[rowc[r] + (long)(k < wk ? k : 0) * a.lda];
       }
-    const double* Tb = exp_T(a, L, d);
+    const double* Tb = exp_T(a, src, L, d);
     const int cbase = j0 - a.yc.c0(d), wy = a.yc.w(d);
     const int k = k0 + kk_t;
 #pragma unroll
@@ -572,15 +578,16 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
       u.tv[q] = Tb[(ok ? k : 0) + (long)(ok ? col : 0) * ldt];
     }
   };
-  auto stash_T = [&](const Unit& u, int d, int k0, T* buf) {
+  auto stash_T = [&](const Unit& u, int src, int d, int k0, T* buf) {
     const int cbase = j0 - a.yc.c0(d), wy = a.yc.w(d);
     const bool kok = k0 + kk_t < wk;
+    const double sc = src ? a.t2_scale : 1.0;
 #pragma unroll
     for (int q = 0; q < EXT; ++q) {
       const int cc = cc_t + (256 / EXK) * q;
       const int col = cbase + cc;
       const bool ok = kok && cc < TW && col >= 0 && col < wy;
-      buf[kk_t * 65 + cc] = ok ? (T)u.tv[q] : (T)0;
+      buf[kk_t * 65 + cc] = ok ? (T)(sc * u.tv[q]) : (T)0;
     }
   };
   auto mfma_unit = [&](const Unit& u, int k0, const T* buf) {
@@ -607,28 +614,30 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
   // double-buffered LDS block: while unit u is computed, unit u + 1 is loading, and
   // one barrier per unit suffices (a wavefront passing the barrier of unit u has
   // finished computing unit u - 1, whose buffer unit u + 1 overwrites).
-  int d = a.d0 - 1, k0 = 0;
-  if (exp_next_unit(a, j0, TW, d, k0)) {
+  int src = 0, d = a.d0 - 1, k0 = 0;
+  if (exp_next_unit(a, j0, TW, src, d, k0)) {
     Unit U0, U1;
-    load_unit(d, k0, U0);
+    load_unit(src, d, k0, U0);
     while (true) {
-      int dn = d, kn0 = k0;
-      const bool more = exp_next_unit(a, j0, TW, dn, kn0);
-      load_unit(more ? dn : d, more ? kn0 : k0, U1);   // the last step re-reads its own unit
-      stash_T(U0, d, k0, Ts[0]);
+      int sn = src, dn = d, kn0 = k0;
+      const bool more = exp_next_unit(a, j0, TW, sn, dn, kn0);
+      if (!more) { sn = src; dn = d; kn0 = k0; }   // the last step re-reads its own unit
+      load_unit(sn, dn, kn0, U1);
+      stash_T(U0, src, d, k0, Ts[0]);
       lds_barrier();
       mfma_unit(U0, k0, Ts[0]);
       if (!more) break;
+      src = sn;
       d = dn;
       k0 = kn0;
-      dn = d;
-      kn0 = k0;
-      const bool more2 = exp_next_unit(a, j0, TW, dn, kn0);
-      load_unit(more2 ? dn : d, more2 ? kn0 : k0, U0);
-      stash_T(U1, d, k0, Ts[1]);
+      const bool more2 = exp_next_unit(a, j0, TW, sn, dn, kn0);
+      if (!more2) { sn = src; dn = d; kn0 = k0; }
+      load_unit(sn, dn, kn0, U0);
+      stash_T(U1, src, d, k0, Ts[1]);
       lds_barrier();
       mfma_unit(U1, k0, Ts[1]);
       if (!more2) break;
+      src = sn;
       d = dn;
       k0 = kn0;
     }
@@ -684,8 +693,13 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
     yhi = std::max(yhi, j.yc.c0(d) + j.yc.w(d));
   }
   if (yhi <= ylo) return HM_OK;
+  if (j.A2 && (!j.T2 || j.alpha == 0.0)) {
+    set_error("tree_expand: a second source needs its T blocks and a nonzero alpha");
+    return HM_E_INVAL;
+  }
   ExpArgs a{j.A, j.lda, j.ac, j.Y, j.ldy, j.yc, j.T, j.t_stride, j.ldt, j.tmode, j.half_off,
-            j.d0, j.d1, m->levels, m->nl, j.alpha, j.beta, ylo, yhi, j.sel.mode, j.sel.depth};
+            j.d0, j.d1, m->levels, m->nl, j.alpha, j.beta, ylo, yhi, j.sel.mode, j.sel.depth,
+            j.A2, j.T2, j.A2 ? j.alpha2 / j.alpha : 0.0};
   const bool pf = prof_on(m, PF_EXPAND);
   if (pf) prof_begin(m, PF_EXPAND);
   // output blocks of 16 columns per tile: a launch narrower than 64 columns runs
@@ -716,12 +730,13 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
     const int wk = j.ac.w0;
     const double rows = (double)count_selected(m->nleaves, m->levels, j.sel) * m->nl;
     const double nsel = rows / m->nl;
+    const double nsrc = j.A2 ? 2.0 : 1.0;   // a second source doubles the products
     double fl = 0.0, by = 0.0;
     for (int d = j.d0; d <= j.d1; ++d) {
       const int wy = j.yc.w(d);
       if (wy <= 0) continue;
-      fl += 2.0 * rows * wk * wy;
-      by += 8.0 * (rows * wk + std::min(nsel, (double)(1 << d)) * wk * wy);
+      fl += nsrc * 2.0 * rows * wk * wy;
+      by += nsrc * 8.0 * (rows * wk + std::min(nsel, (double)(1 << d)) * wk * wy);
     }
     by += 8.0 * rows * (yhi - ylo) * (j.beta == 0.0 ? 1.0 : 2.0);
     prof_end(m, PF_EXPAND, fl, by);

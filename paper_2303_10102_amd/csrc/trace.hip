@@ -371,12 +371,12 @@ hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double theta[4], cons
     const long ts = (long)kc * (levels - 1) * kc;
     ReduceJob rd{pb.dF, n, cs_block(kc), f.G, n, cs_prefix(kc), 2, levels, f.nU, ts, sel_all()};
     HM_CHECK(tree_reduce(m, rd));
-    ExpandJob e1{pb.dF, n, cs_block(kc), pb.Xi, n, cs_prefix(kc), tF_prefix, ts, kc, 1, 0, 2, levels, 1.0, 1.0,
-                 sel_all()};
-    HM_CHECK(tree_expand(m, e1));
-    ExpandJob e2{f.F, n, cs_block(kc), pb.Xi, n, cs_prefix(kc), f.nU, ts, kc, 1, 0, 2, levels, 1.0, 1.0,
-                 sel_all()};
-    HM_CHECK(tree_expand(m, e2));
+    ExpandJob e{pb.dF, n, cs_block(kc), pb.Xi, n, cs_prefix(kc), tF_prefix, ts, kc, 1, 0, 2, levels, 1.0, 1.0,
+                sel_all()};
+    e.A2 = f.F;
+    e.T2 = f.nU;
+    e.alpha2 = 1.0;
+    HM_CHECK(tree_expand(m, e));
   }
   // leaf products Y = Dinv dD (dD Dinv = Y^T: both factors are symmetric, so the
   // Fisher's leaf term tr(Dinv dD_i Dinv dD_j) is a transposed dot of Y_i and Y_j)
