@@ -154,8 +154,8 @@ def main():
                     help="also run one 512 MiB streaming kernel (reference dispatch for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
-                                   "but not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the benchmark runs on one GPU (--gpus 1); the path is not sharded over "
+                                   "several GPUs", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np

@@ -60,7 +60,7 @@ const char* hm_last_error(void);
  * leaf: target leaf size; levels = floor(log2(n/leaf)) (Sec. 5.2 rule).
  * The tree is the recursive coordinate bisection of the grid (Sec. 5.2, KD-tree
  * ordering): split the longer side (x on ties), left child gets floor(side/2).
- * This build requires every split to be even (uniform leaves): else HM_E_INVAL.
+ * The library requires every split to be even (uniform leaves): else HM_E_INVAL.
  * device: HIP device ordinal; stream: hipStream_t to enqueue on (NULL = default).
  */
 hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm_model** out);

@@ -78,7 +78,7 @@ class Workload:
 # sigma^2 of the 256^2 workload at the generating parameters.  The workload is
 # the 128^2 model on a 256^2 grid "with K scaled by sigma^2", so its true value
 # is the unscaled model's, 1.  (A unit-marginal-variance scaling, ~5.3e8, makes
-# the rank-48 approximation indefinite on the 64^2 analogue; see DESIGN.md.)
+# the rank-48 approximation indefinite on the 64^2 analogue.)
 SIGMA2_256 = 1.0
 
 WORKLOADS = {

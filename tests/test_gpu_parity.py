@@ -1,6 +1,6 @@
 """GPU parity: the HIP library against the CPU oracle on the same seeded inputs.
 
-Tolerances (FP64; see the design doc for their derivation):
+Tolerances (FP64, from the rounding of each step's arithmetic):
   K-apply                      1e-11 relative to max |K X|  (direct solves, O(N) rounding)
   K~, leaves and panels        TOL_KT relative to max |K~|  (QR of samples with cond up to ~1e8)
   K~_j                         TOL_DKT relative to max |K~_j| (Alg. 2 divides by R)
