@@ -712,14 +712,14 @@ hm_status hm_H_create(hm_sketch* hs, int p, const int* free_idx, hm_H** out) {
   AL(h->node_s, nodes * s2);
   // construction workspace
   LevelBufs& b = h->lb;
-  AL(b.Y, nk);
+  AL(b.Y, (1 + h->nreal) * nk);   // Y | dY[0] | dY[1] adjacent (one mask launch)
   // XS | XdS[0] | XdS[1] and Z | Zq[0] | Zq[1] adjacent, so the second pass applies K to
   // all of them in one K-apply
   AL(b.XS, (1 + h->nreal) * nk);
   AL(b.Z, (1 + h->nreal) * nk);
   AL(b.Qt, nk);
   for (int j = 0; j < h->nreal; ++j) {
-    AL(b.dY[j], nk);
+    if (b.Y) b.dY[j] = b.Y + (j + 1) * nk;
     if (b.XS) b.XdS[j] = b.XS + (j + 1) * nk;
     AL(b.dZ[j], nk);
     if (b.Z) b.Zq[j] = b.Z + (j + 1) * nk;

@@ -51,25 +51,35 @@ __global__ void k_pattern_omega(const double* om, double* X, int n, int ell, int
 
 // Zero columns >= k_P of Y on the rows of block P's child on side `side`
 // (1 = left, 2 = right) at depth l.  kblk indexed by the parent's heap index.
-__global__ void k_mask_cols(double* Y, int ldy, int n, int w, int l, int levels, int nl, const int* kblk,
-                            int side) {
+// columns c of Y (n x wtot, ld ldy) repeat with period w: block column c % w is masked
+__global__ void k_mask_cols(double* Y, int ldy, int n, int wtot, int w, int l, int levels, int nl,
+                            const int* kblk, int side) {
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long)n * w) return;
+  if (e >= (long)n * wtot) return;
   long i = e % n;
-  int c = (int)(e / n);
+  int cc = (int)(e / n);
+  int c = cc % w;
   bool left = row_is_left(i, l, levels, nl);
   if ((side == 1) != left) return;
   int L = (int)(i / nl);
   int idx = L >> (levels - l);            // node index at depth l
   int parent = ((1 << l) - 1 + idx - 1) >> 1;
-  if (c >= kblk[parent]) Y[i + (long)c * ldy] = 0.0;
+  if (c >= kblk[parent]) Y[i + (long)cc * ldy] = 0.0;
 }
 
-// out[i,c] = left(i) ? A[i,c] : (B[i,c] + (B2 ? B2[i,c] : 0)), masked to k_P columns.
-__global__ void k_merge_lr(const double* A, const double* B, const double* B2, double* out, int ldo, int n, int w,
-                           int l, int levels, int nl, const int* kblk) {
+// out_q[i,c] = left(i) ? A_q[i,c] : (B_q[i,c] + (B2_q ? B2_q[i,c] : 0)), masked to k_P columns,
+// for the jobs q = blockIdx.y (up to three).
+struct MergeJobs {
+  const double* A[3]; const double* B[3]; const double* B2[3]; double* out[3];
+};
+__global__ void k_merge_lr(MergeJobs jb, int ldo, int n, int w, int l, int levels, int nl, const int* kblk) {
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)n * w) return;
+  const int q = blockIdx.y;
+  const double* A = q == 0 ? jb.A[0] : (q == 1 ? jb.A[1] : jb.A[2]);
+  const double* B = q == 0 ? jb.B[0] : (q == 1 ? jb.B[1] : jb.B[2]);
+  const double* B2 = q == 0 ? jb.B2[0] : (q == 1 ? jb.B2[1] : jb.B2[2]);
+  double* out = q == 0 ? jb.out[0] : (q == 1 ? jb.out[1] : jb.out[2]);
   long i = e % n;
   int c = (int)(e / n);
   int L = (int)(i / nl);
@@ -98,9 +108,9 @@ hm_status make_identity_stack(Model* m) {
   return HM_OK;
 }
 
-static hm_status mask_cols(Model* m, double* Y, int w, int l, const int* kblk, int side) {
-  hipLaunchKernelGGL(k_mask_cols, dim3(ceil_div((long)m->n * w, 256)), dim3(256), 0, m->stream, Y, m->n, m->n, w,
-                     l, m->levels, m->nl, kblk, side);
+static hm_status mask_cols(Model* m, double* Y, int wtot, int w, int l, const int* kblk, int side) {
+  hipLaunchKernelGGL(k_mask_cols, dim3(ceil_div((long)m->n * wtot, 256)), dim3(256), 0, m->stream, Y, m->n, m->n,
+                     wtot, w, l, m->levels, m->nl, kblk, side);
   HM_LAUNCH_CHECK();
   return HM_OK;
 }
@@ -109,21 +119,23 @@ static hm_status mask_cols(Model* m, double* Y, int w, int l, const int* kblk, i
 // Y[ysel rows] -= sum_{d=1}^{l-1} H_d X ;  dY_j -= sum_d dH_{j,d} X  (if dY)
 // ---------------------------------------------------------------------------
 hm_status subtract_coarser(Model* m, const PanelSet& ps, int l, const double* X, int w, LeafSel xsel,
-                           LeafSel ysel, double* Y, double* const* dY, int nr, const NodeBufs& nb) {
+                           LeafSel ysel, double* Y, double* const* dY, int nr, const NodeBufs& nb, int wt) {
   if (l <= 1) return HM_OK;
+  if (wt < 0) wt = w;   // the tangents take the first wt columns of X
   PrecScope prec(m);   // coarser-level subtraction: FP32 under the mixed policy
   const int bw = ps.bw;
-  const long ts = (long)bw * w;
+  const long ts = (long)bw * w;   // t_c: bw x w per node; its first wt columns serve the tangents
   ReduceJob r{ps.F, m->n, cs_block(bw), X, m->n, cs_fixed(0, w), 1, l - 1, nb.t, ts, xsel};
   HM_CHECK(tree_reduce(m, r));
   ExpandJob e{ps.F, m->n, cs_block(bw), Y, m->n, cs_fixed(0, w), nb.t, ts, bw, 1, 0, 1, l - 1, -1.0, 1.0, ysel};
   HM_CHECK(tree_expand(m, e));
   if (dY) {
     for (int j = 0; j < nr; ++j) {
-      ReduceJob rd{ps.dF[j], m->n, cs_block(bw), X, m->n, cs_fixed(0, w), 1, l - 1, nb.dt[j], ts, xsel};
+      // dt_c: bw x wt, stored with t's node stride so that one expand reads both
+      ReduceJob rd{ps.dF[j], m->n, cs_block(bw), X, m->n, cs_fixed(0, wt), 1, l - 1, nb.dt[j], ts, xsel};
       HM_CHECK(tree_reduce(m, rd));
       // dY -= dF t + F dt in one launch
-      ExpandJob e{ps.dF[j], m->n, cs_block(bw), dY[j], m->n, cs_fixed(0, w), nb.t, ts, bw, 1, 0, 1, l - 1, -1.0,
+      ExpandJob e{ps.dF[j], m->n, cs_block(bw), dY[j], m->n, cs_fixed(0, wt), nb.t, ts, bw, 1, 0, 1, l - 1, -1.0,
                   1.0, ysel};
       e.A2 = ps.F;
       e.T2 = nb.dt[j];
@@ -207,14 +219,26 @@ hm_status level_step(Model* m, const double theta[4], const PanelSet& ps, int l,
   tangent_outputs(dY, &kap, &alp);
   HM_CHECK(kapply_sel(m, theta, XR, n, w, b.Y, kap, alp, n, right, left));
   HM_CHECK(subtract_coarser(m, ps, l, XR, w, right, left, b.Y, nr ? dY : nullptr, nr, nb));
-  HM_CHECK(mask_cols(m, b.Y, w, l, kblk, 1));
-  HM_CHECK(fill(m, b.XS, (long)n * w, 0.0));
-  HM_CHECK(cholqr3(m, b.Y, w, l, kblk, b.XS, b.Qt, nb));
+  // Y | dY[j] and XS | XdS[j] adjacent: one mask and one clear for all of them
+  bool ycat = true, xcat = true;
   for (int j = 0; j < nr; ++j) {
-    HM_CHECK(mask_cols(m, dY[j], w, l, kblk, 1));
-    HM_CHECK(fill(m, b.XdS[j], (long)n * w, 0.0));
-    HM_CHECK(qr_tangent(m, b.XS, dY[j], w, l, b.XdS[j], nb));
+    ycat = ycat && dY[j] == b.Y + (long)(j + 1) * n * w;
+    xcat = xcat && b.XdS[j] == b.XS + (long)(j + 1) * n * w;
   }
+  if (ycat) {
+    HM_CHECK(mask_cols(m, b.Y, (1 + nr) * w, w, l, kblk, 1));
+  } else {
+    HM_CHECK(mask_cols(m, b.Y, w, w, l, kblk, 1));
+    for (int j = 0; j < nr; ++j) HM_CHECK(mask_cols(m, dY[j], w, w, l, kblk, 1));
+  }
+  if (xcat) {
+    HM_CHECK(fill(m, b.XS, (long)(1 + nr) * n * w, 0.0));
+  } else {
+    HM_CHECK(fill(m, b.XS, (long)n * w, 0.0));
+    for (int j = 0; j < nr; ++j) HM_CHECK(fill(m, b.XdS[j], (long)n * w, 0.0));
+  }
+  HM_CHECK(cholqr3(m, b.Y, w, l, kblk, b.XS, b.Qt, nb));
+  for (int j = 0; j < nr; ++j) HM_CHECK(qr_tangent(m, b.XS, dY[j], w, l, b.XdS[j], nb));
   // ---- pass 2: C = B^T Q on the right-children rows
   double* dZ[2] = {b.dZ[0], b.dZ[1]};
   tangent_outputs(dZ, &kap, &alp);
@@ -222,26 +246,33 @@ hm_status level_step(Model* m, const double theta[4], const PanelSet& ps, int l,
   for (int j = 0; j < nr; ++j)
     adjacent = adjacent && b.XdS[j] == b.XS + (long)(j + 1) * n * w && b.Zq[j] == b.Z + (long)(j + 1) * n * w;
   if (adjacent) {
-    // one K-apply: K on all (1 + nr) w columns, the tangents on the first w
+    // one K-apply: K on all (1 + nr) w columns, the tangents on the first w; one
+    // coarser-level subtraction: the value part on all columns, the tangent part on XS
     HM_CHECK(kapply_multi(m, theta, b.XS, n, (1 + nr) * w, b.Z, (1 + nr) * w, kap, w, alp, w, n, left, right));
+    HM_CHECK(subtract_coarser(m, ps, l, b.XS, (1 + nr) * w, left, right, b.Z, nr ? dZ : nullptr, nr, nb, w));
   } else {
     HM_CHECK(kapply_sel(m, theta, b.XS, n, w, b.Z, kap, alp, n, left, right));
     for (int j = 0; j < nr; ++j)
       HM_CHECK(kapply_sel(m, theta, b.XdS[j], n, w, b.Zq[j], nullptr, nullptr, n, left, right));
+    HM_CHECK(subtract_coarser(m, ps, l, b.XS, w, left, right, b.Z, nr ? dZ : nullptr, nr, nb));
+    for (int j = 0; j < nr; ++j)
+      HM_CHECK(subtract_coarser(m, ps, l, b.XdS[j], w, left, right, b.Zq[j], nullptr, 0, nb));
   }
-  HM_CHECK(subtract_coarser(m, ps, l, b.XS, w, left, right, b.Z, nr ? dZ : nullptr, nr, nb));
-  for (int j = 0; j < nr; ++j)
-    HM_CHECK(subtract_coarser(m, ps, l, b.XdS[j], w, left, right, b.Zq[j], nullptr, 0, nb));
-  // ---- store panels: Q on left rows, C on right rows (masked to k_P columns)
+  // ---- store panels: Q on left rows, C on right rows (masked to k_P columns), one launch
   const long off = (long)(l - 1) * ps.bw * n;
-  hipLaunchKernelGGL(k_merge_lr, dim3(ceil_div((long)n * w, 256)), dim3(256), 0, m->stream, b.XS, b.Z,
-                     (const double*)nullptr, ps.F + off, n, n, w, l, m->levels, m->nl, kblk);
-  HM_LAUNCH_CHECK();
+  MergeJobs jb{};
+  jb.A[0] = b.XS;
+  jb.B[0] = b.Z;
+  jb.out[0] = ps.F + off;
   for (int j = 0; j < nr; ++j) {
-    hipLaunchKernelGGL(k_merge_lr, dim3(ceil_div((long)n * w, 256)), dim3(256), 0, m->stream, b.XdS[j], dZ[j],
-                       b.Zq[j], ps.dF[j] + off, n, n, w, l, m->levels, m->nl, kblk);
-    HM_LAUNCH_CHECK();
+    jb.A[1 + j] = b.XdS[j];
+    jb.B[1 + j] = dZ[j];
+    jb.B2[1 + j] = b.Zq[j];
+    jb.out[1 + j] = ps.dF[j] + off;
   }
+  hipLaunchKernelGGL(k_merge_lr, dim3(ceil_div((long)n * w, 256), 1 + nr), dim3(256), 0, m->stream, jb, n, n, w, l,
+                     m->levels, m->nl, kblk);
+  HM_LAUNCH_CHECK();
   return HM_OK;
 }
 

@@ -35,8 +35,9 @@ struct NodeBufs {
 
 hm_status fill(Model* m, double* p, long cnt, double v);
 hm_status make_identity_stack(Model* m);
+// wt: columns of X that also get the tangent subtraction (default: all w)
 hm_status subtract_coarser(Model* m, const PanelSet& ps, int l, const double* X, int w, LeafSel xsel,
-                           LeafSel ysel, double* Y, double* const* dY, int nr, const NodeBufs& nb);
+                           LeafSel ysel, double* Y, double* const* dY, int nr, const NodeBufs& nb, int wt = -1);
 hm_status level_step(Model* m, const double theta[4], const PanelSet& ps, int l, const double* XR, int w,
                      const int* kblk, int nr, const int* realidx, const LevelBufs& b, const NodeBufs& nb);
 hm_status leaf_pass(Model* m, const double theta[4], const PanelSet& ps, int nr, const int* realidx,
