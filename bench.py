@@ -216,7 +216,7 @@ def main():
                                f"rank {w.rank} (+{w.oversample} once), theta=(kappa,alpha,tau2,sigma2)",
                    "n": w.n, "rank": w.rank, "leaf": w.leaf, "params": list(w.free)},
         "roofline": None,
-        "kernel_tuning": {"expand_rows_per_wave": tuning["expand_rows"],
+        "kernel_tuning": {"expand_variant": tuning["expand_variant"],
                           "reduce_four_waves_below_wgs": tuning["reduce_split_below"]},
         "loglik": ll,
         "grad_nll": [float(v) for v in g],

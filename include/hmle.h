@@ -72,16 +72,19 @@ hm_status hm_model_info(const hm_model* m, int* n, int* levels, int* leaf);
 hm_status hm_model_set_stream(hm_model* m, void* stream);
 /* Kernel-variant autotuner (setup time; allocates and frees its own scratch):
  * times the variants of the panel products on launches of this model's shapes for
- * panel width kc (1..64) -- rows per wavefront of the expand (1 or 2 blocks of 16),
- * the 2- or 4-wavefront row split of the reduce -- and keeps the fastest for all
- * later work of the model.  report: host[7] or NULL: expand ms with 1 and 2 row
- * blocks, reduce ms with the 4-wavefront split never / below 1024 workgroups /
- * always, the chosen rows per wavefront, the chosen workgroup threshold. */
+ * panel width kc (1..64, at most the leaf size) -- the expand's workgroup shape
+ * (1: one 16-row block per wavefront, 4 wavefronts; 2: two row blocks, 4 wavefronts;
+ * 3: one row block, 8 wavefronts) and the 2- or 4-wavefront row split of the reduce --
+ * and keeps the fastest for all later work of the model.  report: host[8] or NULL:
+ * expand ms for variants 1, 2, 3; reduce ms with the 4-wavefront split never / below
+ * 1024 workgroups / always; the chosen expand variant; the chosen workgroup threshold.
+ * HM_E_INVAL for a bad kc; HM_E_NOMEM if the scratch cannot be allocated. */
 hm_status hm_model_autotune(hm_model* m, int kc, double* report);
 /* Read (set = 0) or write (set = 1) the chosen variants, e.g. to copy one model's
- * tuning to others of the same shape.  expand_rows: 0 (built-in rule), 1 or 2;
- * reduce_split_below: workgroup count below which the reduce uses 4 wavefronts. */
-hm_status hm_model_tuning(hm_model* m, int* expand_rows, long long* reduce_split_below, int set);
+ * tuning to others of the same shape.  expand_variant: 0 (built-in default, variant 1)
+ * or 1..3 as above; reduce_split_below: workgroup count below which the reduce uses 4
+ * wavefronts.  HM_E_INVAL for NULL pointers or values out of range. */
+hm_status hm_model_tuning(hm_model* m, int* expand_variant, long long* reduce_split_below, int set);
 /* Copy the tree->grid permutation (n ints, perm[tree_pos] = grid index) to a host buffer. */
 hm_status hm_model_perm(const hm_model* m, int* perm_host);
 

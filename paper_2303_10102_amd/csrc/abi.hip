@@ -501,21 +501,21 @@ hm_status hm_model_autotune(hm_model* mm, int kc, double* report) {
   return autotune(&mm->m, kc, report);
 }
 
-hm_status hm_model_tuning(hm_model* mm, int* expand_rows, long long* reduce_split_below, int set) {
-  if (!mm || !expand_rows || !reduce_split_below) {
+hm_status hm_model_tuning(hm_model* mm, int* expand_variant, long long* reduce_split_below, int set) {
+  if (!mm || !expand_variant || !reduce_split_below) {
     set_error("NULL argument");
     return HM_E_INVAL;
   }
   Model* m = &mm->m;
   if (set) {
-    if (*expand_rows < 0 || *expand_rows > 2 || *reduce_split_below < 0) {
-      set_error("hm_model_tuning: expand_rows in 0..2, reduce_split_below >= 0");
+    if (*expand_variant < 0 || *expand_variant > 3 || *reduce_split_below < 0) {
+      set_error("hm_model_tuning: expand_variant in 0..3, reduce_split_below >= 0");
       return HM_E_INVAL;
     }
-    m->tune_expand_rb = *expand_rows;
+    m->tune_expand_rb = *expand_variant;
     m->tune_reduce_nw4 = (long)*reduce_split_below;
   } else {
-    *expand_rows = m->tune_expand_rb;
+    *expand_variant = m->tune_expand_rb;
     *reduce_split_below = m->tune_reduce_nw4;
   }
   return HM_OK;

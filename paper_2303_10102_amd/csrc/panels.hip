@@ -481,7 +481,7 @@ struct ExpArgs {
 // workgroup barriers wait on LDS traffic only, so those loads stay in flight.
 // Workgroup: 4 wavefronts x 16 rows = 64 rows of one leaf, 64 output columns.
 constexpr int EXK = 32;   // k chunk of one unit
-constexpr int EXT = EXK * 64 / 256;   // T elements staged per thread and unit
+// T elements staged per thread and unit: EXK * 64 / (64 * waves per workgroup)
 
 __device__ __forceinline__ void lds_barrier() {
   // LDS stores of this wavefront complete, then the workgroup barrier; global loads
@@ -520,15 +520,18 @@ __device__ __forceinline__ const double* exp_T(const ExpArgs& a, int src, int L,
   return (src ? a.T2 : a.T) + sel * a.t_stride + roff;
 }
 
-template <int P, int NB, int RB>
-__global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
+template <int P, int NB, int RB, int NWV>
+__global__ void __launch_bounds__(64 * NWV) k_expand_direct(ExpArgs a) {
+  constexpr int NT = 64 * NWV;
+  constexpr int EXT = EXK * 64 / NT;
+  constexpr int CS = NT / EXK;   // T columns staged per pass of the workgroup
   using MP = MfmaPrec<P>;
   using T = typename MP::T;
   __shared__ T Ts[2][EXK * 65];
   const int L = blockIdx.z;
   if (!leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) return;
   constexpr int TW = 16 * NB;   // tile width in output columns
-  const int m0 = blockIdx.x * (64 * RB);
+  const int m0 = blockIdx.x * (16 * RB * NWV);
   const int j0 = a.ylo + blockIdx.y * TW;
   const long r0 = (long)L * a.nl;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -558,7 +561,7 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
     double av[RB][EXK / 4];
     double tv[EXT];
   };
-  const int kk_t = tid % EXK, cc_t = tid / EXK;   // this thread's T elements: (kk_t, cc_t + 8 q)
+  const int kk_t = tid % EXK, cc_t = tid / EXK;   // this thread's T elements: (kk_t, cc_t + CS q)
   auto load_unit = [&](int src, int d, int k0, Unit& u) {
     const double* Ab = (src ? a.A2 : a.A) + r0 + (long)a.ac.c0(d) * a.lda;
 #pragma unroll
@@ -573,7 +576,7 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
     const int k = k0 + kk_t;
 #pragma unroll
     for (int q = 0; q < EXT; ++q) {
-      const int col = cbase + cc_t + (256 / EXK) * q;
+      const int col = cbase + cc_t + CS * q;
       const bool ok = k < wk && col >= 0 && col < wy;
       u.tv[q] = Tb[(ok ? k : 0) + (long)(ok ? col : 0) * ldt];
     }
@@ -584,7 +587,7 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
     const double sc = src ? a.t2_scale : 1.0;
 #pragma unroll
     for (int q = 0; q < EXT; ++q) {
-      const int cc = cc_t + (256 / EXK) * q;
+      const int cc = cc_t + CS * q;
       const int col = cbase + cc;
       const bool ok = kok && cc < TW && col >= 0 && col < wy;
       buf[kk_t * 65 + cc] = ok ? (T)(sc * u.tv[q]) : (T)0;
@@ -673,12 +676,13 @@ __global__ void __launch_bounds__(256) k_expand_direct(ExpArgs a) {
   }
 }
 
-template <int P, int RB>
+template <int P, int RB, int NWV>
 static void launch_expand_direct(Model* m, int nb, dim3 grid, const ExpArgs& a) {
-  if (nb == 1) hipLaunchKernelGGL((k_expand_direct<P, 1, RB>), grid, dim3(GCfg::NT), 0, m->stream, a);
-  else if (nb == 2) hipLaunchKernelGGL((k_expand_direct<P, 2, RB>), grid, dim3(GCfg::NT), 0, m->stream, a);
-  else if (nb == 3) hipLaunchKernelGGL((k_expand_direct<P, 3, RB>), grid, dim3(GCfg::NT), 0, m->stream, a);
-  else hipLaunchKernelGGL((k_expand_direct<P, 4, RB>), grid, dim3(GCfg::NT), 0, m->stream, a);
+  const dim3 blk(64 * NWV);
+  if (nb == 1) hipLaunchKernelGGL((k_expand_direct<P, 1, RB, NWV>), grid, blk, 0, m->stream, a);
+  else if (nb == 2) hipLaunchKernelGGL((k_expand_direct<P, 2, RB, NWV>), grid, blk, 0, m->stream, a);
+  else if (nb == 3) hipLaunchKernelGGL((k_expand_direct<P, 3, RB, NWV>), grid, blk, 0, m->stream, a);
+  else hipLaunchKernelGGL((k_expand_direct<P, 4, RB, NWV>), grid, blk, 0, m->stream, a);
 }
 
 hm_status tree_expand(Model* m, const ExpandJob& j) {
@@ -714,16 +718,20 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
                    : (j.yc.w0 == 0 && j.yc.stride == 0 && j.yc.grow > 0 ? j.yc.grow : 0);
     nb = (bw > 0 && bw % 16 == 0 && bw <= 64 && j.yc.base % bw == 0) ? bw / 16 : 4;
   }
-  // one row block per wavefront (64 rows per workgroup, four workgroups per leaf of
-  // 256) unless the autotuner chose two (128 rows: each T value feeds two MFMAs)
-  const int rb = m->tune_expand_rb ? m->tune_expand_rb : 1;
-  dim3 grid(ceil_div(m->nl, 64 * rb), ceil_div(yhi - ylo, 16 * nb), m->nleaves);
+  // variant: 1 = one row block of 16 per wavefront, 4 wavefronts (64 rows per
+  // workgroup; the default); 2 = two row blocks (128 rows: each T value feeds two MFMAs);
+  // 3 = one row block, 8 wavefronts (128 rows sharing one staged T block)
+  const int var = m->tune_expand_rb ? m->tune_expand_rb : 1;
+  const int rb = (var == 2) ? 2 : 1, nwv = (var == 3) ? 8 : 4;
+  dim3 grid(ceil_div(m->nl, 16 * rb * nwv), ceil_div(yhi - ylo, 16 * nb), m->nleaves);
   if (m->panel_prec == 1) {
-    if (rb == 2) launch_expand_direct<1, 2>(m, nb, grid, a);
-    else launch_expand_direct<1, 1>(m, nb, grid, a);
+    if (var == 2) launch_expand_direct<1, 2, 4>(m, nb, grid, a);
+    else if (var == 3) launch_expand_direct<1, 1, 8>(m, nb, grid, a);
+    else launch_expand_direct<1, 1, 4>(m, nb, grid, a);
   } else {
-    if (rb == 2) launch_expand_direct<0, 2>(m, nb, grid, a);
-    else launch_expand_direct<0, 1>(m, nb, grid, a);
+    if (var == 2) launch_expand_direct<0, 2, 4>(m, nb, grid, a);
+    else if (var == 3) launch_expand_direct<0, 1, 8>(m, nb, grid, a);
+    else launch_expand_direct<0, 1, 4>(m, nb, grid, a);
   }
   HM_LAUNCH_CHECK();
   if (pf) {

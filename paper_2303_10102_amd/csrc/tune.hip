@@ -2,8 +2,8 @@
 //
 // The reduce and expand kernels have variants whose speed depends on the model's
 // shapes (leaf size, panel width, tree depth): the expand can give each wavefront
-// one or two 16-row blocks, and the reduce splits a leaf's rows over two or four
-// wavefronts.  autotune() times each variant on launches of the shapes the
+// one or two 16-row blocks and run four or eight wavefronts per workgroup, and the
+// reduce splits a leaf's rows over two or four wavefronts.  autotune() times each variant on launches of the shapes the
 // iteration issues (a coarser-level subtraction over all depths, the per-node
 // products of one depth), with HIP events on the model's stream, and keeps the
 // fastest.  Setup-time only: it allocates and frees its own scratch.
@@ -23,7 +23,7 @@ hm_status autotune(Model* m, int kc, double* report) {
   const int n = m->n, levels = m->levels;
   if (levels < 2) {   // no coarser-level or Woodbury panel products to time
     if (report)
-      for (int q = 0; q < 7; ++q) report[q] = 0.0;
+      for (int q = 0; q < 8; ++q) report[q] = 0.0;
     return HM_OK;
   }
   const long nodes = (2L << levels) - 1;
@@ -99,10 +99,10 @@ hm_status autotune(Model* m, int kc, double* report) {
   const long saved_nw4 = m->tune_reduce_nw4;
   const int saved_prec = m->panel_prec;
   m->panel_prec = 0;
-  double t_rb[2] = {-1.0, -1.0}, t_nw[3] = {-1.0, -1.0, -1.0};
+  double t_rb[3] = {-1.0, -1.0, -1.0}, t_nw[3] = {-1.0, -1.0, -1.0};
   const long thr[3] = {0L, 1024L, 1L << 40};
   if (st == HM_OK) {
-    for (int v = 0; v < 2; ++v) {
+    for (int v = 0; v < 3; ++v) {
       m->tune_expand_rb = v + 1;
       t_rb[v] = time_ms(run_expand);
     }
@@ -124,7 +124,10 @@ hm_status autotune(Model* m, int kc, double* report) {
     if (t < 0) { set_error("autotune: a timed launch failed"); return HM_E_DEVICE; }
   for (double t : t_nw)
     if (t < 0) { set_error("autotune: a timed launch failed"); return HM_E_DEVICE; }
-  m->tune_expand_rb = (t_rb[1] < t_rb[0]) ? 2 : 1;
+  int bestv = 0;
+  for (int v = 1; v < 3; ++v)
+    if (t_rb[v] < t_rb[bestv]) bestv = v;
+  m->tune_expand_rb = bestv + 1;
   int best = 0;
   for (int v = 1; v < 3; ++v)
     if (t_nw[v] < t_nw[best]) best = v;
@@ -132,11 +135,12 @@ hm_status autotune(Model* m, int kc, double* report) {
   if (report) {
     report[0] = t_rb[0];
     report[1] = t_rb[1];
-    report[2] = t_nw[0];
-    report[3] = t_nw[1];
-    report[4] = t_nw[2];
-    report[5] = m->tune_expand_rb;
-    report[6] = (double)m->tune_reduce_nw4;
+    report[2] = t_rb[2];
+    report[3] = t_nw[0];
+    report[4] = t_nw[1];
+    report[5] = t_nw[2];
+    report[6] = m->tune_expand_rb;
+    report[7] = (double)m->tune_reduce_nw4;
   }
   return HM_OK;
 }

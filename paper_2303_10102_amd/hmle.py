@@ -128,19 +128,19 @@ class Model:
 
     def autotune(self, kc):
         """Time the panel-kernel variants on this model's shapes and keep the fastest."""
-        rep = (C.c_double * 7)()
+        rep = (C.c_double * 8)()
         _check("hm_model_autotune", lib().hm_model_autotune(self._h, int(kc), rep))
-        return dict(expand_ms={1: rep[0], 2: rep[1]},
-                    reduce_ms={"never": rep[2], "below_1024": rep[3], "always": rep[4]},
-                    expand_rows=int(rep[5]), reduce_split_below=int(rep[6]))
+        return dict(expand_ms={1: rep[0], 2: rep[1], 3: rep[2]},
+                    reduce_ms={"never": rep[3], "below_1024": rep[4], "always": rep[5]},
+                    expand_variant=int(rep[6]), reduce_split_below=int(rep[7]))
 
-    def tuning(self, expand_rows=None, reduce_split_below=None):
+    def tuning(self, expand_variant=None, reduce_split_below=None):
         """Read the chosen kernel variants, or set them (both arguments given)."""
         rb, thr = _I(0), C.c_longlong(0)
-        if expand_rows is None:
+        if expand_variant is None:
             _check("hm_model_tuning", lib().hm_model_tuning(self._h, C.byref(rb), C.byref(thr), 0))
             return rb.value, thr.value
-        rb.value, thr.value = int(expand_rows), int(reduce_split_below)
+        rb.value, thr.value = int(expand_variant), int(reduce_split_below)
         _check("hm_model_tuning", lib().hm_model_tuning(self._h, C.byref(rb), C.byref(thr), 1))
         return rb.value, thr.value
 

@@ -76,7 +76,7 @@ def test_batch_tune_kernels(batch):
     assert set(reps) == set(shapes)
     for key, choices in shapes.items():
         assert all(c == choices[0] for c in choices), key
-        assert choices[0] == (reps[key]["expand_rows"], reps[key]["reduce_split_below"])
+        assert choices[0] == (reps[key]["expand_variant"], reps[key]["reduce_split_below"])
     ll, g, fim = b.iteration(thetas, ys)
     for f, H in enumerate(Hs):
         l1, g1, f1 = H.iteration(thetas[f], ys[f])

@@ -1,7 +1,8 @@
 """GPU: the panel-kernel autotuner.
 
-The variants it chooses between (one or two 16-row blocks per wavefront in the
-expand, two or four wavefronts per leaf in the reduce) compute the same sums in a
+The variants it chooses between (one or two 16-row blocks per wavefront and four or
+eight wavefronts per workgroup in the expand, two or four wavefronts per leaf in the
+reduce) compute the same sums in a
 different order, so an iteration after tuning agrees with one under each forced
 variant to rounding; the tuned choice is one of the timed variants and can be read
 back and copied to another model."""
@@ -34,10 +35,10 @@ def test_autotune_report(tuned):
     print(rep)
     times = list(rep["expand_ms"].values()) + list(rep["reduce_ms"].values())
     assert all(np.isfinite(t) and t > 0 for t in times)
-    assert rep["expand_rows"] == min(rep["expand_ms"], key=rep["expand_ms"].get)
+    assert rep["expand_variant"] == min(rep["expand_ms"], key=rep["expand_ms"].get)
     thr = {"never": 0, "below_1024": 1024, "always": 1 << 40}
     assert rep["reduce_split_below"] == thr[min(rep["reduce_ms"], key=rep["reduce_ms"].get)]
-    assert m.tuning() == (rep["expand_rows"], rep["reduce_split_below"])
+    assert m.tuning() == (rep["expand_variant"], rep["reduce_split_below"])
 
 
 def test_variants_agree(tuned):
@@ -45,7 +46,7 @@ def test_variants_agree(tuned):
     saved = m.tuning()
     out = {}
     try:
-        for rb in (1, 2):
+        for rb in (1, 2, 3):
             for thr in (0, 1 << 40):
                 m.tuning(rb, thr)
                 out[(rb, thr)] = H.iteration(w.theta_full, yd)
@@ -62,6 +63,6 @@ def test_tuning_rejects_bad_values(tuned):
     from paper_2303_10102_amd import hmle
     w, m, s, H, yd = tuned
     with pytest.raises(hmle.HmleError):
-        m.tuning(3, 0)
+        m.tuning(4, 0)
     with pytest.raises(hmle.HmleError):
         m.autotune(0)
