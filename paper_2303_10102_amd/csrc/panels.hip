@@ -479,9 +479,9 @@ struct ExpArgs {
 // Work is a sequence of units (segment d, 32-deep k chunk).  The panel and T
 // loads of the next unit are issued before the current unit is computed, and the
 // workgroup barriers wait on LDS traffic only, so those loads stay in flight.
-// Workgroup: 4 wavefronts x 16 rows = 64 rows of one leaf, 64 output columns.
+// Workgroup: NWV wavefronts x RB blocks of 16 rows of one leaf, up to 64 output
+// columns (16 NB); the T block of a unit is staged once for all of them.
 constexpr int EXK = 32;   // k chunk of one unit
-// T elements staged per thread and unit: EXK * 64 / (64 * waves per workgroup)
 
 __device__ __forceinline__ void lds_barrier() {
   // LDS stores of this wavefront complete, then the workgroup barrier; global loads
