@@ -120,8 +120,9 @@ struct LeafAdjSt {
 __global__ void __launch_bounds__(256) k_leaf_adjoint(const double* Gs, const double* G, int ldg, int K,
                                                       const double* Dinv, const double* z, double* Zb, int nl) {
   __shared__ double smem[GSMEM];
-  const int L = blockIdx.z;
-  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  const TileIdx tb = tile_block();
+  const int L = tb.z;
+  const int m0 = tb.x * GBM, n0 = tb.y * GBN;
   const long r0 = (long)L * nl;
   OutLA la{Gs + r0, ldg, m0, nl};
   OutLB lb{G + r0, ldg, n0, nl};

@@ -86,6 +86,30 @@ struct TreeIdx {
 };
 TreeIdx make_tree_idx(int dim, int N, int levels);
 
+// Workgroup placement over the XCDs.  A launch's workgroups go to the eight XCDs in
+// turn by linear id (x fastest, then y, then z), and each XCD has its own L2.
+// xcd_order() renumbers the linear ids so that every XCD receives one contiguous
+// range of logical ids, and tile_block() turns the logical id back into (x, y, z)
+// with x fastest.  Tiles that are neighbours in that order share operand blocks
+// (the row tiles of one column tile; the column tiles, depths and row chunks of one
+// leaf), which then come from one L2 instead of being fetched once per XCD.  The
+// renumbering is a bijection: it moves work between XCDs and changes nothing else.
+constexpr int kXcds = 8;
+__host__ __device__ inline int xcd_order(int b, int n) {
+  const int per = n / kXcds, rem = n % kXcds;
+  const int x = b % kXcds, loc = b / kXcds;
+  return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + loc;
+}
+struct TileIdx {
+  int x, y, z;
+};
+__device__ __forceinline__ TileIdx tile_block() {
+  const int nx = (int)gridDim.x, ny = (int)gridDim.y;
+  const int n = nx * ny * (int)gridDim.z;
+  const int l = xcd_order((int)blockIdx.x + nx * ((int)blockIdx.y + ny * (int)blockIdx.z), n);
+  return TileIdx{l % nx, (l / nx) % ny, l / (nx * ny)};
+}
+
 struct Model {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -112,9 +136,9 @@ struct Model {
   int mixed = 0;
   int panel_prec = 0;
   // kernel variants of the panel products, chosen per model by hm_model_autotune
-  // (defaults: two row blocks per wavefront in the expand when leaves have >= 128
-  // rows; four-wavefront row split in the reduce below 1024 workgroups)
-  int tune_expand_rb = 0;        // 0 = default (1 row block per wavefront), else 1 or 2
+  // (defaults: one row block of 16 on each of four wavefronts in the expand;
+  // four-wavefront row split in the reduce below 1024 workgroups)
+  int tune_expand_rb = 0;        // expand variant: 0 = default (variant 1), else 1, 2 or 3
   long tune_reduce_nw4 = 1024;   // reduce launches with fewer workgroups split rows over 4 wavefronts
   int prof_family = PF_NONE;
   std::vector<ProfRec> prof;

@@ -299,7 +299,8 @@ __global__ void __launch_bounds__(256) k_dst_fwd(const double* S, const double* 
                                                  double* Xh, int N, int Ny, int ncol, int Kx, AxisMap xm,
                                                  AxisMap ym) {
   __shared__ double smem[GSMEM];
-  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  const TileIdx tb = tile_block();
+  const int m0 = tb.x * GBM, n0 = tb.y * GBN;
   const ColGeo<AM> cg = col_geo<AM>(Ny, n0, ncol);
   DstLS la{S, N, m0, xm};
   DstLGather<AM> lb{X, ldx, tix, cg, xm, ym};
@@ -313,13 +314,14 @@ __global__ void __launch_bounds__(256) k_dst_fwd(const double* S, const double* 
 __global__ void __launch_bounds__(256) k_dst_yf(const double* S, const double* M, double* C, int N, int Nyin,
                                                 AxisMap ym) {
   __shared__ double smem[GSMEM];
-  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
-  DyLA<false> la{M + (long)blockIdx.z * N * Nyin, nullptr, N, m0};
+  const TileIdx tb = tile_block();
+  const int m0 = tb.x * GBM, n0 = tb.y * GBN;
+  DyLA<false> la{M + (long)tb.z * N * Nyin, nullptr, N, m0};
   DyLBfwd lb{S, N, n0, ym};
   TileAcc acc;
   tile_zero(acc);
   tile_gemm(la, lb, 0, Nyin, acc, smem);
-  DstStMode st{C + (long)blockIdx.z * N * N, N, m0, n0, N};
+  DstStMode st{C + (long)tb.z * N * N, N, m0, n0, N};
   tile_store(st, acc);
 }
 
@@ -328,8 +330,9 @@ __global__ void __launch_bounds__(256) k_dst_yf(const double* S, const double* M
 __global__ void __launch_bounds__(256) k_dst_yi(const double* S, const double* M, MultiOut mo, double* C,
                                                 long cslot, int N, int Nyout, AxisMap ym) {
   __shared__ double smem[GSMEM];
-  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
-  const int o = mo.pick(blockIdx.z, mo.zoff), c = blockIdx.z - mo.get(mo.zoff, o);
+  const TileIdx tb = tile_block();
+  const int m0 = tb.x * GBM, n0 = tb.y * GBN;
+  const int o = mo.pick(tb.z, mo.zoff), c = tb.z - mo.get(mo.zoff, o);
   DyLA<true> la{M + (long)c * N * N, mo.lam_of(o), N, m0};
   DyLBinv lb{S, N, n0, Nyout, ym};
   TileAcc acc;
@@ -345,9 +348,10 @@ template <int AM, bool LAM>
 __global__ void __launch_bounds__(256) k_dst_inv(const double* S, const double* W, MultiOut mo, TreeIdx tix,
                                                  int ldy, int N, int Ny, int Mx, AxisMap xm, AxisMap ym) {
   __shared__ double smem[GSMEM];
-  const int o = mo.pick(blockIdx.y, mo.toff);
+  const TileIdx tb = tile_block();
+  const int o = mo.pick(tb.y, mo.toff);
   const int ncol = mo.get(mo.cols, o);
-  const int m0 = blockIdx.x * GBM, n0 = (blockIdx.y - mo.get(mo.toff, o)) * GBN;
+  const int m0 = tb.x * GBM, n0 = (tb.y - mo.get(mo.toff, o)) * GBN;
   const ColGeo<AM> cg = col_geo<AM>(Ny, n0, ncol);
   double* Y = mo.y_of(o);
   DstLSrow la{S, N, m0, Mx, xm};
@@ -490,9 +494,10 @@ template <int AM>
 __global__ void __launch_bounds__(256) k_dst_fwd_fold(const double* Ph, const double* X, int ldx, TreeIdx tix,
                                                       double* Xh, int N, int Ny, int ncol, AxisMap ym) {
   __shared__ double smem[GSMEM];
+  const TileIdx tb = tile_block();
   const int H = N / 2, ht = (H + GBM - 1) / GBM;
-  const int par = (int)blockIdx.x >= ht ? 1 : 0;
-  const int m0 = ((int)blockIdx.x - par * ht) * GBM, n0 = blockIdx.y * GBN;
+  const int par = tb.x >= ht ? 1 : 0;
+  const int m0 = (tb.x - par * ht) * GBM, n0 = tb.y * GBN;
   const ColGeo<AM> cg = col_geo<AM>(Ny, n0, ncol);
   HalfA la{Ph + (long)par * H * H, H, m0};
   DstLGatherFold<AM> lb{X, ldx, tix, cg, N, ym, par ? -1.0 : 1.0};
@@ -506,16 +511,17 @@ __global__ void __launch_bounds__(256) k_dst_fwd_fold(const double* Ph, const do
 // grid.y: 2 * ht tiles (parity major)
 __global__ void __launch_bounds__(256) k_dst_yf_fold(const double* Ph, const double* M, double* C, int N) {
   __shared__ double smem[GSMEM];
+  const TileIdx tb = tile_block();
   const int H = N / 2, ht = (H + GBN - 1) / GBN;
-  const int par = (int)blockIdx.y >= ht ? 1 : 0;
-  const int m0 = blockIdx.x * GBM, n0 = ((int)blockIdx.y - par * ht) * GBN;
+  const int par = tb.y >= ht ? 1 : 0;
+  const int m0 = tb.x * GBM, n0 = (tb.y - par * ht) * GBN;
   const long NN = (long)N * N;
-  DyLAFold la{M + blockIdx.z * NN, N, m0, par ? -1.0 : 1.0};
+  DyLAFold la{M + tb.z * NN, N, m0, par ? -1.0 : 1.0};
   HalfB lb{Ph + (long)(2 + par) * H * H, H, n0};
   TileAcc acc;
   tile_zero(acc);
   tile_gemm(la, lb, 0, H, acc, smem);
-  tile_store(DyStColPar{C + blockIdx.z * NN, N, H, m0, n0, par}, acc);
+  tile_store(DyStColPar{C + tb.z * NN, N, H, m0, n0, par}, acc);
 }
 
 // inverse y, y whole: e = sum_k (lam o M_c)(p, 2k) P0(k, y'), o = the odd modes with P1;
@@ -524,9 +530,10 @@ __global__ void __launch_bounds__(256) k_dst_yf_fold(const double* Ph, const dou
 __global__ void __launch_bounds__(256) k_dst_yi_fold(const double* Ph, const double* M, MultiOut mo, double* C,
                                                      long cslot, int N) {
   __shared__ double smem[GSMEM];
+  const TileIdx tb = tile_block();
   const int H = N / 2;
-  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
-  const int q = mo.pick(blockIdx.z, mo.zoff), c = blockIdx.z - mo.get(mo.zoff, q);
+  const int m0 = tb.x * GBM, n0 = tb.y * GBN;
+  const int q = mo.pick(tb.z, mo.zoff), c = tb.z - mo.get(mo.zoff, q);
   const long NN = (long)N * N, HH = (long)H * H;
   const double* Mz = M + c * NN;
   const double* lam = mo.lam_of(q);
@@ -545,11 +552,12 @@ template <int AM, bool LAM>
 __global__ void __launch_bounds__(256) k_dst_inv_fold(const double* Ph, const double* W, MultiOut mo, TreeIdx tix,
                                                       int ldy, int N, int Ny, AxisMap ym) {
   __shared__ double smem[GSMEM];
+  const TileIdx tb = tile_block();
   const int H = N / 2;
   const long HH = (long)H * H;
-  const int q = mo.pick(blockIdx.y, mo.toff);
+  const int q = mo.pick(tb.y, mo.toff);
   const int ncol = mo.get(mo.cols, q);
-  const int m0 = blockIdx.x * GBM, n0 = (blockIdx.y - mo.get(mo.toff, q)) * GBN;
+  const int m0 = tb.x * GBM, n0 = (tb.y - mo.get(mo.toff, q)) * GBN;
   const ColGeo<AM> cg = col_geo<AM>(Ny, n0, ncol);
   const double* Wq = W + q * mo.in_stride;
   const double* lam = mo.lam_of(q);

@@ -48,6 +48,17 @@ __device__ __forceinline__ bool leaf_selected(int L, int levels, int mode, int d
   bool left = (anc & 1) == 0;
   return mode == 1 ? left : !left;
 }
+// The i-th selected leaf in increasing order, i < count_selected(): the selected
+// leaves are every other run of 2^(levels - depth) leaves, starting with the first
+// run (left children, mode 1) or the second (right children, mode 2).
+__device__ __forceinline__ int selected_leaf(int i, int levels, int mode, int depth) {
+  if (mode == 0) return i;
+  const int sh = levels - depth;
+  return ((2 * (i >> sh) + (mode == 2 ? 1 : 0)) << sh) + (i & ((1 << sh) - 1));
+}
+static bool sel_valid(const Model* m, LeafSel sel) {
+  return sel.mode == 0 || ((sel.mode == 1 || sel.mode == 2) && sel.depth >= 1 && sel.depth <= m->levels);
+}
 
 // ----------------------------------------------------------------------------
 // generic strided batched GEMM (column-major)
@@ -101,8 +112,9 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int Nc, int K, double alpha
                                               long sA, const double* B, int ldb, long sB, double beta,
                                               double* C, int ldc, long sC) {
   __shared__ double smem[GSMEM];
-  int b = blockIdx.z;
-  int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  const TileIdx tb = tile_block();
+  int b = tb.z;
+  int m0 = tb.x * GBM, n0 = tb.y * GBN;
   LdA<TA> la{A + b * sA, lda, m0, M};
   LdB<TB> lb{B + b * sB, ldb, n0, Nc};
   TileAcc acc;
@@ -157,12 +169,13 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)
   using MP = MfmaPrec<P>;
   using T = typename MP::T;
   __shared__ double red[(NW - 1) * MB * NB * 4 * 64];
+  // grid.z enumerates (selected leaf, depth), depth fastest
+  const TileIdx tb = tile_block();
   const int ndep = a.d1 - a.d0 + 1;
-  const int L = blockIdx.z / ndep;
-  const int d = a.d0 + blockIdx.z % ndep;
-  if (!leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) return;
+  const int L = selected_leaf(tb.z / ndep, a.levels, a.sel_mode, a.sel_depth);
+  const int d = a.d0 + tb.z % ndep;
   const int wa = a.ac.w0, wx = a.xc.w(d);
-  const int m0 = blockIdx.x * (16 * MB), n0 = blockIdx.y * (16 * NB);
+  const int m0 = tb.x * (16 * MB), n0 = tb.y * (16 * NB);
   if (m0 >= wa || n0 >= wx) return;
   const long r0 = (long)L * a.nl;
   const double* Ab = a.A + r0 + (long)(a.ac.c0(d) + m0) * a.lda;
@@ -377,6 +390,10 @@ hm_status tree_reduce(Model* m, const ReduceJob& j) {
     set_error("tree_reduce: bad depth range");
     return HM_E_INVAL;
   }
+  if (!sel_valid(m, j.sel)) {
+    set_error("tree_reduce: bad leaf selection");
+    return HM_E_INVAL;
+  }
   const int ndep = j.d1 - j.d0 + 1;
   int wxmax = 0;
   for (int d = j.d0; d <= j.d1; ++d) wxmax = std::max(wxmax, j.xc.w(d));
@@ -414,7 +431,8 @@ hm_status tree_reduce(Model* m, const ReduceJob& j) {
       return (nbk % 3 == 0) ? 3 : (nbk % 2 == 0 ? 2 : 3);
     };
     const int mb = blocks(wa), nb = blocks(wxmax);
-    dim3 grid(ceil_div(wa, 16 * mb), ceil_div(wxmax, 16 * nb), m->nleaves * ndep);
+    const int nsel = count_selected(m->nleaves, m->levels, j.sel);
+    dim3 grid(ceil_div(wa, 16 * mb), ceil_div(wxmax, 16 * nb), nsel * ndep);
     // few workgroups (e.g. one depth of per-leaf products): split each leaf's rows
     // over four wavefronts instead of two
     const long wgs = (long)grid.x * grid.y * grid.z;
@@ -528,11 +546,12 @@ __global__ void __launch_bounds__(64 * NWV) k_expand_direct(ExpArgs a) {
   using MP = MfmaPrec<P>;
   using T = typename MP::T;
   __shared__ T Ts[2][EXK * 65];
-  const int L = blockIdx.z;
-  if (!leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) return;
+  // grid.z enumerates the selected leaves
+  const TileIdx tb = tile_block();
+  const int L = selected_leaf(tb.z, a.levels, a.sel_mode, a.sel_depth);
   constexpr int TW = 16 * NB;   // tile width in output columns
-  const int m0 = blockIdx.x * (16 * RB * NWV);
-  const int j0 = a.ylo + blockIdx.y * TW;
+  const int m0 = tb.x * (16 * RB * NWV);
+  const int j0 = a.ylo + tb.y * TW;
   const long r0 = (long)L * a.nl;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
@@ -690,6 +709,10 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
     set_error("tree_expand: bad depth range");
     return HM_E_INVAL;
   }
+  if (!sel_valid(m, j.sel)) {
+    set_error("tree_expand: bad leaf selection");
+    return HM_E_INVAL;
+  }
   int ylo = 1 << 30, yhi = -1;
   for (int d = j.d0; d <= j.d1; ++d) {
     if (j.yc.w(d) <= 0) continue;
@@ -723,7 +746,8 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
   // 3 = one row block, 8 wavefronts (128 rows sharing one staged T block)
   const int var = m->tune_expand_rb ? m->tune_expand_rb : 1;
   const int rb = (var == 2) ? 2 : 1, nwv = (var == 3) ? 8 : 4;
-  dim3 grid(ceil_div(m->nl, 16 * rb * nwv), ceil_div(yhi - ylo, 16 * nb), m->nleaves);
+  const int nsel = count_selected(m->nleaves, m->levels, j.sel);
+  dim3 grid(ceil_div(m->nl, 16 * rb * nwv), ceil_div(yhi - ylo, 16 * nb), nsel);
   if (m->panel_prec == 1) {
     if (var == 2) launch_expand_direct<1, 2, 4>(m, nb, grid, a);
     else if (var == 3) launch_expand_direct<1, 1, 8>(m, nb, grid, a);
@@ -759,8 +783,9 @@ __global__ void __launch_bounds__(256) k_leaf_gemm(const double* Dm, const doubl
                                                    int ldy, int w, int nl, double alpha, double beta,
                                                    int leaf_lo) {
   __shared__ double smem[GSMEM];
-  const int L = leaf_lo + blockIdx.z;
-  const int m0 = blockIdx.x * GBM, n0 = blockIdx.y * GBN;
+  const TileIdx tb = tile_block();
+  const int L = leaf_lo + tb.z;
+  const int m0 = tb.x * GBM, n0 = tb.y * GBN;
   const long r0 = (long)L * nl;
   LdA<false> la{Dm + (long)L * nl * nl, nl, m0, nl};
   LdB<false> lb{X + r0, ldx, n0, w};
