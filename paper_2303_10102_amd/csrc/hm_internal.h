@@ -51,13 +51,17 @@ enum DevFlag : int { DF_NOT_SPD_LEAF = 1, DF_NOT_SPD_NODE = 2, DF_QR_FAIL = 4, D
 // model, sketch, H
 // ---------------------------------------------------------------------------
 // Kernel-family instrumentation (roofline measurement): launches of the enabled
-// family are bracketed by HIP events on the model stream; each record carries the
-// launch's algorithmic flop and byte counts.
+// family are timed by HIP events on the model stream; each record carries the
+// launch's algorithmic flop and byte counts.  The expand family passes its events to
+// the launch itself (hipExtLaunchKernel), which sets them to the kernel's own start
+// and end, with no marker packets between the kernels; the other families record
+// the events before and after their launches.
 enum ProfFamily : int { PF_NONE = -1, PF_EXPAND = 0, PF_REDUCE = 1, PF_DST = 2, PF_GEMM = 3, PF_LEAFGEMM = 4,
                         PF_COUNT = 5 };
 struct ProfRec {
   hipEvent_t a, b;
   double flops, bytes;
+  bool by_launch;   // a and b are set by the kernel launch
 };
 
 // Grid point (x, y) -> tree position, the closed form of the uniform bisection
@@ -155,6 +159,8 @@ struct PrecScope {
 // profiling helpers (no-ops unless the family is enabled)
 bool prof_on(Model* m, int family);
 void prof_begin(Model* m, int family);
+// a record whose two events the caller hands to hipExtLaunchKernel (null when off)
+void prof_begin_launch(Model* m, int family, hipEvent_t& a, hipEvent_t& b);
 void prof_end(Model* m, int family, double flops, double bytes);
 // grow the tree_reduce partial buffer (setup calls only; never inside an iteration)
 hm_status ensure_reduce_ws(Model* m, size_t doubles);

@@ -9,6 +9,8 @@
 // always has (#leaves x #column tiles) independent workgroups; reduce then sums
 // the per-leaf partials up the tree.  Plus a batched GEMM with the leaf blocks,
 // and a plain strided batched GEMM.
+#include <hip/hip_ext.h>
+
 #include "hm_internal.h"
 #include "gemm_core.h"
 
@@ -25,14 +27,23 @@ static hipEvent_t prof_event(Model* m) {
 }
 void prof_begin(Model* m, int family) {
   if (!prof_on(m, family)) return;
-  ProfRec r{prof_event(m), prof_event(m), 0.0, 0.0};
+  ProfRec r{prof_event(m), prof_event(m), 0.0, 0.0, false};
   if (r.a) (void)hipEventRecord(r.a, m->stream);
+  m->prof.push_back(r);
+}
+void prof_begin_launch(Model* m, int family, hipEvent_t& a, hipEvent_t& b) {
+  a = b = nullptr;
+  if (!prof_on(m, family)) return;
+  ProfRec r{prof_event(m), prof_event(m), 0.0, 0.0, true};
+  if (!r.a || !r.b) r.a = r.b = nullptr;   // no events: the launch is not timed
+  a = r.a;
+  b = r.b;
   m->prof.push_back(r);
 }
 void prof_end(Model* m, int family, double flops, double bytes) {
   if (!prof_on(m, family) || m->prof.empty()) return;
   ProfRec& r = m->prof.back();
-  if (r.b) (void)hipEventRecord(r.b, m->stream);
+  if (r.b && !r.by_launch) (void)hipEventRecord(r.b, m->stream);
   r.flops = flops;
   r.bytes = bytes;
 }
@@ -695,13 +706,14 @@ __global__ void __launch_bounds__(64 * NWV) k_expand_direct(ExpArgs a) {
   }
 }
 
+// ea, eb (may be null): events set to the kernel's start and end
 template <int P, int RB, int NWV>
-static void launch_expand_direct(Model* m, int nb, dim3 grid, const ExpArgs& a) {
+static void launch_expand_direct(Model* m, int nb, dim3 grid, const ExpArgs& a, hipEvent_t ea, hipEvent_t eb) {
   const dim3 blk(64 * NWV);
-  if (nb == 1) hipLaunchKernelGGL((k_expand_direct<P, 1, RB, NWV>), grid, blk, 0, m->stream, a);
-  else if (nb == 2) hipLaunchKernelGGL((k_expand_direct<P, 2, RB, NWV>), grid, blk, 0, m->stream, a);
-  else if (nb == 3) hipLaunchKernelGGL((k_expand_direct<P, 3, RB, NWV>), grid, blk, 0, m->stream, a);
-  else hipLaunchKernelGGL((k_expand_direct<P, 4, RB, NWV>), grid, blk, 0, m->stream, a);
+  if (nb == 1) hipExtLaunchKernelGGL((k_expand_direct<P, 1, RB, NWV>), grid, blk, 0, m->stream, ea, eb, 0, a);
+  else if (nb == 2) hipExtLaunchKernelGGL((k_expand_direct<P, 2, RB, NWV>), grid, blk, 0, m->stream, ea, eb, 0, a);
+  else if (nb == 3) hipExtLaunchKernelGGL((k_expand_direct<P, 3, RB, NWV>), grid, blk, 0, m->stream, ea, eb, 0, a);
+  else hipExtLaunchKernelGGL((k_expand_direct<P, 4, RB, NWV>), grid, blk, 0, m->stream, ea, eb, 0, a);
 }
 
 hm_status tree_expand(Model* m, const ExpandJob& j) {
@@ -728,7 +740,8 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
             j.d0, j.d1, m->levels, m->nl, j.alpha, j.beta, ylo, yhi, j.sel.mode, j.sel.depth,
             j.A2, j.T2, j.A2 ? j.alpha2 / j.alpha : 0.0};
   const bool pf = prof_on(m, PF_EXPAND);
-  if (pf) prof_begin(m, PF_EXPAND);
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (pf) prof_begin_launch(m, PF_EXPAND, ea, eb);
   // output blocks of 16 columns per tile: a launch narrower than 64 columns runs
   // fewer MFMA blocks; a wide output made of panel blocks (cs_block / cs_prefix of a
   // width that is a multiple of 16) is tiled at that width, so no tile straddles two
@@ -749,13 +762,13 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
   const int nsel = count_selected(m->nleaves, m->levels, j.sel);
   dim3 grid(ceil_div(m->nl, 16 * rb * nwv), ceil_div(yhi - ylo, 16 * nb), nsel);
   if (m->panel_prec == 1) {
-    if (var == 2) launch_expand_direct<1, 2, 4>(m, nb, grid, a);
-    else if (var == 3) launch_expand_direct<1, 1, 8>(m, nb, grid, a);
-    else launch_expand_direct<1, 1, 4>(m, nb, grid, a);
+    if (var == 2) launch_expand_direct<1, 2, 4>(m, nb, grid, a, ea, eb);
+    else if (var == 3) launch_expand_direct<1, 1, 8>(m, nb, grid, a, ea, eb);
+    else launch_expand_direct<1, 1, 4>(m, nb, grid, a, ea, eb);
   } else {
-    if (var == 2) launch_expand_direct<0, 2, 4>(m, nb, grid, a);
-    else if (var == 3) launch_expand_direct<0, 1, 8>(m, nb, grid, a);
-    else launch_expand_direct<0, 1, 4>(m, nb, grid, a);
+    if (var == 2) launch_expand_direct<0, 2, 4>(m, nb, grid, a, ea, eb);
+    else if (var == 3) launch_expand_direct<0, 1, 8>(m, nb, grid, a, ea, eb);
+    else launch_expand_direct<0, 1, 4>(m, nb, grid, a, ea, eb);
   }
   HM_LAUNCH_CHECK();
   if (pf) {
