@@ -173,10 +173,11 @@ struct RedArgs {
 // four consecutive rows 4 (l/16) .. 4 (l/16) + 3 of a 16-row group, one per
 // MFMA step, so each lane reads 32 contiguous bytes of one column and a 16-lane
 // column group covers 128 contiguous bytes.  The output tile is MB x NB blocks of
-// 16 x 16 (sized to the real widths, not padded to 64).  Two wavefronts split the
-// leaf's rows and combine through LDS.
+// 16 x 16 (sized to the real widths, not padded to 64).  NW wavefronts (two, or four
+// for launches of few workgroups) split the leaf's rows and combine through LDS; two
+// wavefronts per SIMD leave room for two row groups of operands in flight.
 template <int P, int MB, int NB, int NW>
-__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) k_reduce_direct(RedArgs a) {
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2))) k_reduce_direct(RedArgs a) {
   using MP = MfmaPrec<P>;
   using T = typename MP::T;
   __shared__ double red[(NW - 1) * MB * NB * 4 * 64];
@@ -191,7 +192,8 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)
   const long r0 = (long)L * a.nl;
   const double* Ab = a.A + r0 + (long)(a.ac.c0(d) + m0) * a.lda;
   const double* Xb = a.X + r0 + (long)(a.xc.c0(d) + n0) * a.ldx;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the wavefront index is uniform, so the row loop runs on scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int hrows = ((a.nl + 16 * NW - 1) / (16 * NW)) * 16;   // rows per wavefront, a multiple of 16
   const int rbeg = wave * hrows, rend = min(a.nl, rbeg + hrows);
@@ -217,30 +219,55 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3)
     xok[j] = n0 + 16 * j + li < wx;
     Xc[j] = Xb + (long)(xok[j] ? 16 * j + li : 0) * a.ldx;
   }
-  for (int g = rbeg; g < rend; g += 16) {
-    const int rr = g + 4 * lk;
-    const int rl = (rr + 3 < a.nl) ? rr : 0;   // a group of 4 rows inside the leaf
+  // Two register sets alternate (the row-group loop is unrolled by two): the loads of
+  // the next group are issued before the current one is multiplied, so each wavefront
+  // keeps one group in flight while the matrix cores work.  An odd group count runs
+  // one empty group (every row out of range, operands zero); the loop's last loads
+  // re-read the final group and are not used.
+  struct Grp {
     double ar[MB][4], xr[NB][4];
+  };
+  const int ngrp = (rend - rbeg + 15) >> 4;
+  auto load_grp = [&](int t, Grp& u) {
+    const int rr = rbeg + 16 * min(t, ngrp - 1) + 4 * lk;
+    const long rl = (rr + 3 < a.nl) ? rr : 0;   // a group of 4 rows inside the leaf
 #pragma unroll
-    for (int i = 0; i < MB; ++i)
+    for (int i = 0; i < MB; ++i) {
+      const double* pa = Ac[i] + rl;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) ar[i][q] = Ac[i][rl + q];
+      for (int q = 0; q < 4; ++q) u.ar[i][q] = pa[q];
+    }
 #pragma unroll
-    for (int j = 0; j < NB; ++j)
+    for (int j = 0; j < NB; ++j) {
+      const double* px = Xc[j] + rl;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) xr[j][q] = Xc[j][rl + q];
+      for (int q = 0; q < 4; ++q) u.xr[j][q] = px[q];
+    }
+  };
+  auto mma_grp = [&](int t, const Grp& u) {
+    const int rr = rbeg + 16 * t + 4 * lk;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const bool rok = rr + q < rend;
       T av[MB], xv[NB];
 #pragma unroll
-      for (int i = 0; i < MB; ++i) av[i] = (aok[i] && rok) ? (T)ar[i][q] : (T)0;
+      for (int i = 0; i < MB; ++i) av[i] = (aok[i] && rok) ? (T)u.ar[i][q] : (T)0;
 #pragma unroll
-      for (int j = 0; j < NB; ++j) xv[j] = (xok[j] && rok) ? (T)xr[j][q] : (T)0;
+      for (int j = 0; j < NB; ++j) xv[j] = (xok[j] && rok) ? (T)u.xr[j][q] : (T)0;
 #pragma unroll
       for (int i = 0; i < MB; ++i)
 #pragma unroll
         for (int j = 0; j < NB; ++j) acc[i][j] = MP::mfma(av[i], xv[j], acc[i][j]);
+    }
+  };
+  if (ngrp > 0) {
+    Grp U0, U1;
+    load_grp(0, U0);
+    for (int t = 0; t < ngrp; t += 2) {
+      load_grp(t + 1, U1);
+      mma_grp(t, U0);
+      load_grp(t + 2, U0);
+      mma_grp(t + 1, U1);
     }
   }
   if (wave > 0) {
