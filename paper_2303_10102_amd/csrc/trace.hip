@@ -76,16 +76,39 @@ __global__ void __launch_bounds__(256) k_dots_partial(DotArgs a, double* partial
   double acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < a.len; e += (long)gridDim.x * blockDim.x) {
-    double av[4], bv[4];
+  // Four grid strides per step, with loads free of branches so that all of them are in
+  // flight together: operands past na / nb read the first one, elements past len read
+  // the step's first element, and both are zeroed at use.
+  constexpr int U = 4;
+  const double* Ap[4];
+  const double* Bp[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) av[i] = (i < a.na) ? a.A[i][e] : 0.0;
+  for (int i = 0; i < 4; ++i) {
+    Ap[i] = a.A[i < a.na ? i : 0];
+    Bp[i] = a.B[i < a.nb ? i : 0];
+  }
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long e0 = (long)blockIdx.x * blockDim.x + threadIdx.x; e0 < a.len; e0 += U * stride) {
+    double av[U][4], bv[U][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bv[j] = (j < a.nb) ? a.B[j][e] : 0.0;
+    for (int u = 0; u < U; ++u) {
+      const long e = e0 + u * stride;
+      const long ec = e < a.len ? e : e0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i) av[u][i] = Ap[i][ec];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i * 4 + j] += av[i] * bv[j];
+      for (int j = 0; j < 4; ++j) bv[u][j] = Bp[j][ec];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = e0 + u * stride < a.len;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double x = (ok && i < a.na) ? av[u][i] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i * 4 + j] += x * bv[u][j];
+      }
+    }
   }
   for (int q = 0; q < a.na * a.nb; ++q) {
     int i = q / a.nb, j = q % a.nb;
@@ -144,28 +167,52 @@ __global__ void __launch_bounds__(256) k_dots_leafT_partial(DotArgs a, int nl, i
   const long ntiles = (long)nleaves * tpl * tpl;
   const int tx = threadIdx.x % LT, ty = threadIdx.x / LT;   // 32 x 8 threads
   const long ls = (long)nl * nl;
+  // operands past na / nb read the first one (zeroed at use), so the loads of a step
+  // carry no branches and all of them, A's and B's, are in flight together
+  const double* Ap[4];
+  const double* Bp[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    Ap[i] = a.A[i < a.na ? i : 0];
+    Bp[i] = a.B[i < a.nb ? i : 0];
+  }
+  constexpr int RS = LT / 8;   // rows of a tile per thread
   for (long t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int L = (int)(t / ((long)tpl * tpl));
     const int rem = (int)(t % ((long)tpl * tpl));
     const int a0 = (rem % tpl) * LT, b0 = (rem / tpl) * LT;
-    // B_j(b0 + r, a0 + c) for r, c < 32 -> Bt[j][r][c]
-    for (int r = ty; r < LT; r += 8) {
-      const int row = b0 + tx, col = a0 + r;    // element (row, col) of B_j, column-major
-      const bool ok = row < nl && col < nl;
+    const long lb = L * ls;
+    double bt[4][RS], at[4][RS];
+    bool okb[RS], oka[RS];
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
+      const int r = ty + 8 * s;
+      // B_j(b0 + tx, a0 + r), to Bt[j][tx][r]
+      const int row = b0 + tx, col = a0 + r;
+      okb[s] = row < nl && col < nl;
+      const long ob = lb + (okb[s] ? row + (long)col * nl : 0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bt[j][s] = Bp[j][ob];
+      // A_i(a0 + tx, b0 + r), which pairs with B_j(b0 + r, a0 + tx) = Bt[j][r][tx]
+      const int ra = a0 + tx, ca = b0 + r;
+      oka[s] = ra < nl && ca < nl;
+      const long oa = lb + (oka[s] ? ra + (long)ca * nl : 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) at[i][s] = Ap[i][oa];
+    }
+#pragma unroll
+    for (int s = 0; s < RS; ++s)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        if (j < a.nb) Bt[j][tx][r] = ok ? a.B[j][L * ls + row + (long)col * nl] : 0.0;
-    }
+        if (j < a.nb) Bt[j][tx][ty + 8 * s] = okb[s] ? bt[j][s] : 0.0;
     __syncthreads();
-    // A_i(a0 + x, b0 + y) pairs with B_j(b0 + y, a0 + x) = Bt[j][y][x]
-    for (int y = ty; y < LT; y += 8) {
-      const int ra = a0 + tx, ca = b0 + y;
-      const bool ok = ra < nl && ca < nl;
+#pragma unroll
+    for (int s = 0; s < RS; ++s) {
       double av[4], bv[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = (ok && i < a.na) ? a.A[i][L * ls + ra + (long)ca * nl] : 0.0;
+      for (int i = 0; i < 4; ++i) av[i] = (oka[s] && i < a.na) ? at[i][s] : 0.0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = (j < a.nb) ? Bt[j][y][tx] : 0.0;
+      for (int j = 0; j < 4; ++j) bv[j] = (j < a.nb) ? Bt[j][ty + 8 * s][tx] : 0.0;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
