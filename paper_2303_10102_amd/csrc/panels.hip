@@ -177,7 +177,7 @@ struct RedArgs {
 // for launches of few workgroups) split the leaf's rows and combine through LDS; two
 // wavefronts per SIMD leave room for two row groups of operands in flight.
 template <int P, int MB, int NB, int NW>
-__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, 2))) k_reduce_direct(RedArgs a) {
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, MB * NB > 4 ? 2 : 4))) k_reduce_direct(RedArgs a) {
   using MP = MfmaPrec<P>;
   using T = typename MP::T;
   __shared__ double red[(NW - 1) * MB * NB * 4 * 64];

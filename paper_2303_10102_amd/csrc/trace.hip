@@ -155,16 +155,20 @@ hm_status dots(Model* m, const double* const* A, int na, const double* const* B,
 // Pairwise traces of leaf-major blocks: out[i nb + j] = sum_L tr(A_i[L] B_j[L]) =
 // sum_L sum_{a,b} A_i[L](a, b) B_j[L](b, a).  One 32 x 32 tile (L, a0, b0) per step: the
 // B_j tiles at the transposed position go through LDS, so both operands are read in
-// 256-byte column runs.  Partial sums as in k_dots_partial.
+// 256-byte column runs.  Partial sums as in k_dots_partial.  sym (B_j = A_j for every j):
+// the tile pair (a0, b0), (b0, a0) is visited once, a0 <= b0, since the pair's second tile
+// contributes to (i, j) what the first contributes to (j, i); every block is read once.
 constexpr int LT = 32;
-__global__ void __launch_bounds__(256) k_dots_leafT_partial(DotArgs a, int nl, int nleaves, double* partial) {
+__global__ void __launch_bounds__(256) k_dots_leafT_partial(DotArgs a, int nl, int nleaves, int sym,
+                                                            double* partial) {
   __shared__ double red[256];
   __shared__ double Bt[4][LT][LT + 1];
   double acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0.0;
   const int tpl = (nl + LT - 1) / LT;             // tiles per leaf side
-  const long ntiles = (long)nleaves * tpl * tpl;
+  const int tpp = sym ? tpl * (tpl + 1) / 2 : tpl * tpl;   // tiles (pairs) per leaf
+  const long ntiles = (long)nleaves * tpp;
   const int tx = threadIdx.x % LT, ty = threadIdx.x / LT;   // 32 x 8 threads
   const long ls = (long)nl * nl;
   // operands past na / nb read the first one (zeroed at use), so the loads of a step
@@ -178,9 +182,21 @@ __global__ void __launch_bounds__(256) k_dots_leafT_partial(DotArgs a, int nl, i
   }
   constexpr int RS = LT / 8;   // rows of a tile per thread
   for (long t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int L = (int)(t / ((long)tpl * tpl));
-    const int rem = (int)(t % ((long)tpl * tpl));
-    const int a0 = (rem % tpl) * LT, b0 = (rem / tpl) * LT;
+    const int L = (int)(t / tpp);
+    int rem = (int)(t % tpp), ta, tb;
+    if (sym) {   // pairs ta <= tb, ordered by tb
+      tb = 0;
+      while (rem > tb) {
+        rem -= tb + 1;
+        ++tb;
+      }
+      ta = rem;
+    } else {
+      ta = rem % tpl;
+      tb = rem / tpl;
+    }
+    const int a0 = ta * LT, b0 = tb * LT;
+    const bool twice = sym && ta != tb;
     const long lb = L * ls;
     double bt[4][RS], at[4][RS];
     bool okb[RS], oka[RS];
@@ -216,7 +232,7 @@ __global__ void __launch_bounds__(256) k_dots_leafT_partial(DotArgs a, int nl, i
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i * 4 + j] += av[i] * bv[j];
+        for (int j = 0; j < 4; ++j) acc[i * 4 + j] += av[i] * bv[j] + (twice ? av[j] * bv[i] : 0.0);
     }
     __syncthreads();
   }
@@ -239,10 +255,13 @@ hm_status dots_leafT(Model* m, const double* const* A, int na, const double* con
   for (int j = 0; j < nb; ++j) a.B[j] = B[j];
   a.na = na;
   a.nb = nb;
+  bool sym = na == nb;
+  for (int i = 0; i < na && sym; ++i) sym = A[i] == B[i];
   const int tpl = ceil_div(m->nl, LT);
-  const long ntiles = (long)m->nleaves * tpl * tpl;
+  const long ntiles = (long)m->nleaves * (sym ? tpl * (tpl + 1) / 2 : tpl * tpl);
   const int nblk = (int)std::min<long>(DOT_BLOCKS, std::max<long>(1, ntiles));
-  hipLaunchKernelGGL(k_dots_leafT_partial, dim3(nblk), dim3(256), 0, m->stream, a, m->nl, m->nleaves, partial);
+  hipLaunchKernelGGL(k_dots_leafT_partial, dim3(nblk), dim3(256), 0, m->stream, a, m->nl, m->nleaves, sym ? 1 : 0,
+                     partial);
   HM_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_dots_final, dim3(na * nb), dim3(256), 0, m->stream, partial, nblk, na * nb, out);
   HM_LAUNCH_CHECK();
