@@ -72,7 +72,9 @@ hm_status hm_model_info(const hm_model* m, int* n, int* levels, int* leaf);
 hm_status hm_model_set_stream(hm_model* m, void* stream);
 /* Kernel-variant autotuner (setup time; allocates and frees its own scratch):
  * times the variants of the panel products on launches of this model's shapes for
- * panel width kc (1..64, at most the leaf size) -- the expand's workgroup shape
+ * panel width kc (1..64, at most the leaf size): a coarser-level subtraction, the
+ * leaf pass's subtraction (leaf-size width), the per-node products of every depth and
+ * the Cholesky-QR products over one side of every node.  The variants are the expand's workgroup shape
  * (1: one 16-row block per wavefront, 4 wavefronts; 2: two row blocks, 4 wavefronts;
  * 3: one row block, 8 wavefronts) and the 2- or 4-wavefront row split of the reduce --
  * and keeps the fastest for all later work of the model.  report: host[8] or NULL:

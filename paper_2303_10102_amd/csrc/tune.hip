@@ -3,10 +3,11 @@
 // The reduce and expand kernels have variants whose speed depends on the model's
 // shapes (leaf size, panel width, tree depth): the expand can give each wavefront
 // one or two 16-row blocks and run four or eight wavefronts per workgroup, and the
-// reduce splits a leaf's rows over two or four wavefronts.  autotune() times each variant on launches of the shapes the
-// iteration issues (a coarser-level subtraction over all depths, the per-node
-// products of one depth), with HIP events on the model's stream, and keeps the
-// fastest.  Setup-time only: it allocates and frees its own scratch.
+// reduce splits a leaf's rows over two or four wavefronts.  autotune() times each
+// variant on launches of the shapes the iteration issues (a coarser-level subtraction
+// over all depths, the leaf pass's wide subtraction, the per-node products of one
+// depth, the Cholesky-QR products over one side of every node), with HIP events on the
+// model's stream, and keeps the fastest.  Setup-time only: it allocates and frees its own scratch.
 #include <algorithm>
 #include <vector>
 
@@ -40,11 +41,12 @@ hm_status autotune(Model* m, int kc, double* report) {
     allocs.push_back(p);
     return (double*)p;
   };
-  const size_t cnts[5] = {(size_t)n * levels * kc, (size_t)n * levels * kc, (size_t)n * kc, (size_t)nodes * ts,
-                          (size_t)nodes * 2 * ts};
-  double* bufs[5];
-  for (int q = 0; q < 5; ++q) bufs[q] = alloc(cnts[q]);
-  double *F = bufs[0], *G = bufs[1], *X = bufs[2], *T = bufs[3], *U = bufs[4];
+  const int nl = m->nl;
+  const size_t cnts[7] = {(size_t)n * levels * kc, (size_t)n * levels * kc, (size_t)n * kc, (size_t)nodes * ts,
+                          (size_t)nodes * 2 * ts,   (size_t)n * nl,           (size_t)nodes * kc * nl};
+  double* bufs[7];
+  for (int q = 0; q < 7; ++q) bufs[q] = alloc(cnts[q]);
+  double *F = bufs[0], *G = bufs[1], *X = bufs[2], *T = bufs[3], *U = bufs[4], *Yw = bufs[5], *Tw = bufs[6];
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ok) ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
   auto cleanup = [&]() {
@@ -58,18 +60,28 @@ hm_status autotune(Model* m, int kc, double* report) {
     return HM_E_NOMEM;
   }
   hm_status st = ensure_reduce_ws(m, (size_t)m->nleaves * (levels - 1) * s2);
-  for (int q = 0; q < 5 && st == HM_OK; ++q) st = fill(m, bufs[q], (long)cnts[q], 1.0 / (1 + q));
+  for (int q = 0; q < 7 && st == HM_OK; ++q) st = fill(m, bufs[q], (long)cnts[q], 1.0 / (1 + q));
   // launches of the iteration's shapes: the coarser-level subtraction over depths
-  // 1..levels-1 (one column block of width kc), and per depth the Woodbury products
-  // (kc x kc node blocks, prefix panels of width (d-1) kc)
+  // 1..levels-1 (one column block of width kc), the leaf pass's subtraction over all
+  // depths (leaf-size width), per depth the Woodbury products (kc x kc node blocks,
+  // prefix panels of width (d-1) kc), and per depth the three Cholesky-QR products
+  // Q = Y R^{-1} over the left children's rows (half the leaves)
   auto run_expand = [&]() -> hm_status {
     ExpandJob sub{F, n, cs_block(kc), X, n, cs_fixed(0, kc), T, s2, kc, 1, 0, 1, levels - 1, -1.0, 1.0,
                   sel_all()};
     HM_CHECK(tree_expand(m, sub));
+    ExpandJob wide{F, n, cs_block(kc), Yw, n, cs_fixed(0, nl), Tw, (long)kc * nl, kc, 1, 0, 1, levels, -1.0, 1.0,
+                   sel_all()};
+    HM_CHECK(tree_expand(m, wide));
     for (int d = 2; d <= levels; ++d) {
       ExpandJob e{F, n, cs_block(kc), G, n, cs_prefix(kc), U, 2 * ts, 2 * kc, 2, kc, d, d, -1.0, 1.0, sel_all()};
       HM_CHECK(tree_expand(m, e));
     }
+    for (int l = 1; l < levels; ++l)
+      for (int pass = 0; pass < 3; ++pass) {
+        ExpandJob q{F, n, cs_fixed(0, kc), G, n, cs_fixed(0, kc), T, s2, kc, 0, 0, l, l, 1.0, 0.0, LeafSel{1, l}};
+        HM_CHECK(tree_expand(m, q));
+      }
     return HM_OK;
   };
   auto run_reduce = [&]() -> hm_status {
