@@ -119,7 +119,7 @@ struct StC {  // C = alpha v + beta C (C not read when beta == 0)
 };
 
 template <bool TA, bool TB>
-__global__ void __launch_bounds__(256) k_gemm(int M, int Nc, int K, double alpha, const double* A, int lda,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_gemm(int M, int Nc, int K, double alpha, const double* A, int lda,
                                               long sA, const double* B, int ldb, long sB, double beta,
                                               double* C, int ldc, long sC) {
   __shared__ double smem[GSMEM];
@@ -819,7 +819,7 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
 // ----------------------------------------------------------------------------
 // leaf-block GEMM: Y[L rows, 0:w] = beta Y + alpha Dm_L X[L rows, 0:w]
 // ----------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_leaf_gemm(const double* Dm, const double* X, int ldx, double* Y,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_leaf_gemm(const double* Dm, const double* X, int ldx, double* Y,
                                                    int ldy, int w, int nl, double alpha, double beta,
                                                    int leaf_lo) {
   __shared__ double smem[GSMEM];
