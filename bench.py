@@ -32,11 +32,13 @@ KERNEL_SOURCES = ["paper_2303_10102_amd/csrc/panels.hip", "paper_2303_10102_amd/
 
 
 def kernel_source_hash():
+    """Hash of the dominant kernel's sources with all whitespace removed (a change of
+    layout alone keeps it; any change of a token changes it)."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+            h.update(b"".join(fh.read().split()))
     return h.hexdigest()[:16]
 
 

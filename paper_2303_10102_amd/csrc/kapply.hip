@@ -295,9 +295,10 @@ struct DyLBinv {  // B(k, j) = S(k, ymap(n0 + j)) for n0 + j < Nout
 
 // Xh(p, r) = sum_{x'} S(p, xmap(x')) X[col ldx + tree(xmap(x'), ymap(y'))],  r = col Ny + y'
 template <int AM>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_dst_fwd(const double* S, const double* X, int ldx, TreeIdx tix,
-                                                 double* Xh, int N, int Ny, int ncol, int Kx, AxisMap xm,
-                                                 AxisMap ym) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_dst_fwd(const double* S, const double* X, int ldx, TreeIdx tix,
+          double* Xh, int N, int Ny, int ncol, int Kx, AxisMap xm,
+          AxisMap ym) {
   __shared__ double smem[GSMEM];
   const TileIdx tb = tile_block();
   const int m0 = tb.x * GBM, n0 = tb.y * GBN;
@@ -311,8 +312,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 }
 
 // forward y: C_c = M_c S[ymap(.), :]  (M_c: N x Nyin at c*N*Nyin; C_c: N x N at c*N*N)
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_dst_yf(const double* S, const double* M, double* C, int N, int Nyin,
-                                                AxisMap ym) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_dst_yf(const double* S, const double* M, double* C, int N, int Nyin,
+         AxisMap ym) {
   __shared__ double smem[GSMEM];
   const TileIdx tb = tile_block();
   const int m0 = tb.x * GBM, n0 = tb.y * GBN;
@@ -327,8 +329,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 
 // inverse y: C_{o,c} = (lam_o o M_c) S[:, ymap(.)]  (M_c: N x N; C_{o,c}: N x Nyout at
 // o * cslot + c*N*Nyout); grid.z = outputs x columns
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_dst_yi(const double* S, const double* M, MultiOut mo, double* C,
-                                                long cslot, int N, int Nyout, AxisMap ym) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_dst_yi(const double* S, const double* M, MultiOut mo, double* C,
+         long cslot, int N, int Nyout, AxisMap ym) {
   __shared__ double smem[GSMEM];
   const TileIdx tb = tile_block();
   const int m0 = tb.x * GBM, n0 = tb.y * GBN;
@@ -345,8 +348,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 // Y[col ldy + tree(xmap(x'), ymap(y'))] = sum_p S(xmap(x'), p) (lam o W)(p, r)
 // grid.y = outputs x column tiles
 template <int AM, bool LAM>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_dst_inv(const double* S, const double* W, MultiOut mo, TreeIdx tix,
-                                                 int ldy, int N, int Ny, int Mx, AxisMap xm, AxisMap ym) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_dst_inv(const double* S, const double* W, MultiOut mo, TreeIdx tix,
+          int ldy, int N, int Ny, int Mx, AxisMap xm, AxisMap ym) {
   __shared__ double smem[GSMEM];
   const TileIdx tb = tile_block();
   const int o = mo.pick(tb.y, mo.toff);
@@ -491,8 +495,9 @@ struct DstStScatterUnfold {  // Y at (x, r) = e + o and (N-1-x, r) = e - o, x = 
 // forward x, x whole: Xh(2i + par, r) = sum_{x < H} P_par(i, x) (X(x) +- X(N-1-x))
 // grid.x: 2 * ht tiles (parity major), grid.y: column tiles
 template <int AM>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_dst_fwd_fold(const double* Ph, const double* X, int ldx, TreeIdx tix,
-                                                      double* Xh, int N, int Ny, int ncol, AxisMap ym) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_dst_fwd_fold(const double* Ph, const double* X, int ldx, TreeIdx tix,
+               double* Xh, int N, int Ny, int ncol, AxisMap ym) {
   __shared__ double smem[GSMEM];
   const TileIdx tb = tile_block();
   const int H = N / 2, ht = (H + GBM - 1) / GBM;
@@ -509,7 +514,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 
 // forward y, y whole: C_c(p, 2j + par) = sum_{y < H} (M_c(p, y) +- M_c(p, N-1-y)) Q_par(y, j)
 // grid.y: 2 * ht tiles (parity major)
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_dst_yf_fold(const double* Ph, const double* M, double* C, int N) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_dst_yf_fold(const double* Ph, const double* M, double* C, int N) {
   __shared__ double smem[GSMEM];
   const TileIdx tb = tile_block();
   const int H = N / 2, ht = (H + GBN - 1) / GBN;
@@ -527,8 +533,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 // inverse y, y whole: e = sum_k (lam o M_c)(p, 2k) P0(k, y'), o = the odd modes with P1;
 // C_c(p, y') = e + o, C_c(p, N-1-y') = e - o for y' < H
 // (grid.z = outputs x columns, as k_dst_yi)
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_dst_yi_fold(const double* Ph, const double* M, MultiOut mo, double* C,
-                                                     long cslot, int N) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_dst_yi_fold(const double* Ph, const double* M, MultiOut mo, double* C,
+              long cslot, int N) {
   __shared__ double smem[GSMEM];
   const TileIdx tb = tile_block();
   const int H = N / 2;
@@ -549,8 +556,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 // by lam when LAM, the 1D case); Y(x) = e + o, Y(N-1-x) = e - o for x < H
 // (grid.y = outputs x column tiles, as k_dst_inv)
 template <int AM, bool LAM>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_dst_inv_fold(const double* Ph, const double* W, MultiOut mo, TreeIdx tix,
-                                                      int ldy, int N, int Ny, AxisMap ym) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_dst_inv_fold(const double* Ph, const double* W, MultiOut mo, TreeIdx tix,
+               int ldy, int N, int Ny, AxisMap ym) {
   __shared__ double smem[GSMEM];
   const TileIdx tb = tile_block();
   const int H = N / 2;

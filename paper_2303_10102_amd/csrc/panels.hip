@@ -119,9 +119,10 @@ struct StC {  // C = alpha v + beta C (C not read when beta == 0)
 };
 
 template <bool TA, bool TB>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_gemm(int M, int Nc, int K, double alpha, const double* A, int lda,
-                                              long sA, const double* B, int ldb, long sB, double beta,
-                                              double* C, int ldc, long sC) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_gemm(int M, int Nc, int K, double alpha, const double* A, int lda,
+       long sA, const double* B, int ldb, long sB, double beta,
+       double* C, int ldc, long sC) {
   __shared__ double smem[GSMEM];
   const TileIdx tb = tile_block();
   int b = tb.z;
@@ -177,7 +178,8 @@ struct RedArgs {
 // for launches of few workgroups) split the leaf's rows and combine through LDS; two
 // wavefronts per SIMD leave room for two row groups of operands in flight.
 template <int P, int MB, int NB, int NW>
-__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, MB * NB > 4 ? 2 : 4))) k_reduce_direct(RedArgs a) {
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, MB * NB > 4 ? 2 : 4)))
+k_reduce_direct(RedArgs a) {
   using MP = MfmaPrec<P>;
   using T = typename MP::T;
   __shared__ double red[(NW - 1) * MB * NB * 4 * 64];
@@ -819,9 +821,10 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
 // ----------------------------------------------------------------------------
 // leaf-block GEMM: Y[L rows, 0:w] = beta Y + alpha Dm_L X[L rows, 0:w]
 // ----------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_leaf_gemm(const double* Dm, const double* X, int ldx, double* Y,
-                                                   int ldy, int w, int nl, double alpha, double beta,
-                                                   int leaf_lo) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_leaf_gemm(const double* Dm, const double* X, int ldx, double* Y,
+            int ldy, int w, int nl, double alpha, double beta,
+            int leaf_lo) {
   __shared__ double smem[GSMEM];
   const TileIdx tb = tile_block();
   const int L = leaf_lo + tb.z;
