@@ -5,6 +5,7 @@ from the HIP library.  The two meet only in the comparisons of the tests.
 """
 from __future__ import annotations
 
+import dataclasses
 import functools
 
 import numpy as np
@@ -21,6 +22,17 @@ CASES = {
     # 2D 48x48, leaf 6x6 (6 levels): leaf extents and split widths that are not powers
     # of two (the transforms' closed-form tree index and axis maps divide by 6, 12, 24)
     "2d_n2304": small_workload(N=48, leaf=36, rank=12, sigma2=1.0e3, name="2d_n2304"),
+    # the 1D workload with sigma2 = 1e4 and (kappa, tau2) free: a finite, well-separated
+    # maximum of L (kappa is not identifiable at sigma2 = 1), and K~ = K since the
+    # off-diagonal blocks have rank 4 < the sketch rank
+    "1d_mle": dataclasses.replace(WORKLOADS["1d_n1024"], sigma2=1.0e4, name="1d_mle"),
+    # the 128^2 workload in a physics-dominated regime (sigma2 = 1.6e4: the field's mean
+    # variance about 0.12 of the nugget's, as in the 32^2 parity case) with
+    # (kappa, tau2, sigma2) free; the exact likelihood has a finite maximum there
+    "2d_mle_128": dataclasses.replace(WORKLOADS["2d_n16384"], sigma2=1.6e4, free=("kappa", "tau2", "sigma2"),
+                                      name="2d_mle_128"),
+    # 2D 32^2 with (kappa, tau2) free: small enough for the dense exact likelihood
+    "2d_mle_32": small_workload(N=32, leaf=64, rank=16, sigma2=1.0e3, free=("kappa", "tau2"), name="2d_mle_32"),
 }
 
 
@@ -133,3 +145,19 @@ def hmatvec(F, leaves, levels, kc, x, dF=None, dleaves=None):
     # lv[L] is the column-major block, i.e. its transpose as a row-major array
     Y += np.einsum("Lji,Ljc->Lic", lv, Xl).reshape(n, -1)
     return Y[:, 0] if vec else Y
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_mle(key, start_factor=1.3, evaluator="dense"):
+    """The oracle's maximum-likelihood fit of case `key` on the exact likelihood, from
+    theta_true scaled by start_factor in every free parameter; evaluator "dense"
+    (assembled K, any grid) or "spectral" (closed form in the DST-I eigenbasis, 2D/1D
+    Dirichlet grids of any size)."""
+    from oracle.mle import exact_evaluator, fisher_scoring, spectral_evaluator
+
+    w = CASES[key]
+    y = sample_y(w)
+    make = exact_evaluator if evaluator == "dense" else spectral_evaluator
+    ev = make(w.dim, w.N, w.theta_full, w.free, y)
+    th0 = np.asarray(w.theta, dtype=np.float64) * start_factor
+    return fisher_scoring(ev, th0)
