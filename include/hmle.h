@@ -110,6 +110,14 @@ hm_status hm_kapply(hm_model* m, const double* theta_full, const double* X, int 
  * Fails with HM_E_RANK if a whole level has rank 0. */
 hm_status hm_sketch_create(hm_model* m, const double* omega, int rank, int oversample,
                            const double* theta0_full, hm_sketch** out);
+/* As hm_sketch_create with the truncation tolerance given: each block keeps
+ * k = min(rank, #{s_i > rank_tol s_1}) columns, so the ranks adapt per block to a
+ * relative accuracy (a tolerance-driven rank, the adaptive strategy of Sec. 3.1 and
+ * the paper's concluding remarks); rank stays the cap and sets the panel width when
+ * some block reaches it.  hm_sketch_create is rank_tol = 1e-10.  rank_tol in [0, 1),
+ * else HM_E_INVAL. */
+hm_status hm_sketch_create_tol(hm_model* m, const double* omega, int rank, int oversample, double rank_tol,
+                               const double* theta0_full, hm_sketch** out);
 void hm_sketch_destroy(hm_sketch* s);
 /* kept rank per block: k_host[2^levels - 1], heap order of the block's parent node
  * (root 0; children of node x are 2x+1, 2x+2); *kc = panel width (max kept rank). */

@@ -550,11 +550,20 @@ hm_status hm_kapply(hm_model* mm, const double* theta_full, const double* X, int
 
 hm_status hm_sketch_create(hm_model* mm, const double* omega, int rank, int oversample, const double* theta0_full,
                            hm_sketch** out) {
+  return hm_sketch_create_tol(mm, omega, rank, oversample, 1e-10, theta0_full, out);
+}
+
+hm_status hm_sketch_create_tol(hm_model* mm, const double* omega, int rank, int oversample, double rank_tol,
+                               const double* theta0_full, hm_sketch** out) {
   if (!mm || !omega || !out) {
     set_error("NULL argument");
     return HM_E_INVAL;
   }
   *out = nullptr;
+  if (!(rank_tol >= 0.0 && rank_tol < 1.0)) {
+    set_error("rank_tol must lie in [0, 1)");
+    return HM_E_INVAL;
+  }
   HM_CHECK(check_theta(theta0_full));
   if (rank < 1 || rank > 64 || oversample < 0 || rank + oversample > 80) {
     set_error("need 1 <= rank <= 64 and rank + oversample <= 80");
@@ -569,6 +578,7 @@ hm_status hm_sketch_create(hm_model* mm, const double* omega, int rank, int over
   Sketch* s = &hs->s;
   s->m = m;
   s->rank = rank;
+  s->rank_tol = rank_tol;
   s->oversample = oversample;
   s->ell = rank + oversample;
   const int nint = (1 << m->levels) - 1;

@@ -21,8 +21,8 @@
 
 namespace hm {
 
-hm_status sketch_compress(Model* m, const double* Y, int ldy, int ell, int l, int rank, double* W, double* R,
-                          double* V, int kc, int* d_k, double* d_sig);
+hm_status sketch_compress(Model* m, const double* Y, int ldy, int ell, int l, int rank, double tol, double* W,
+                          double* R, double* V, int kc, int* d_k, double* d_sig);
 hm_status leaf_sym(Model* m, const double* Z, int ldz, double* D);
 
 __global__ void k_fill(double* p, long cnt, double v) {
@@ -360,7 +360,8 @@ hm_status sketch_build(Sketch* s, const double* omega, const double theta0[4]) {
     if ((st = subtract_coarser(m, ps, l, Xl, ell, LeafSel{2, l}, LeafSel{1, l}, Yl, nullptr, 0, nb)) != HM_OK)
       break;
     const int heap0 = (1 << (l - 1)) - 1;
-    if ((st = sketch_compress(m, Yl, n, ell, l, r, Wqr, Rq, Vb + (size_t)heap0 * ell * r, r, s->d_k + heap0,
+    if ((st = sketch_compress(m, Yl, n, ell, l, r, s->rank_tol, Wqr, Rq, Vb + (size_t)heap0 * ell * r, r,
+                              s->d_k + heap0,
                               sig + (size_t)heap0 * ell)) != HM_OK)
       break;
     // compressed test matrix: X[b rows] = Omega_b V_P

@@ -168,6 +168,7 @@ hm_status ensure_reduce_ws(Model* m, size_t doubles);
 struct Sketch {
   Model* m = nullptr;
   int rank = 0, oversample = 0, ell = 0;
+  double rank_tol = 1e-10;    // kept singular values of a block's sample exceed rank_tol * sigma_1
   int kc = 0;                 // column width of every panel block (max kept rank)
   std::vector<int> kblk;      // kept rank per block (heap index of the parent), size 2^levels - 1
   double* d_XR = nullptr;     // n x (levels*kc): level-l test matrix Omega V (right-children rows)

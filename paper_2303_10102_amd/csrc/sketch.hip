@@ -5,7 +5,8 @@
 // block is sampled with ell = r + p_os columns; its sample Y = Q R is
 // Householder-factored, R's right singular vectors V (one-sided Jacobi, high
 // relative accuracy for small singular values) keep
-// k = min(r, #{sigma_i > 1e-10 sigma_1}) columns ordered by decreasing sigma,
+// k = min(r, #{sigma_i > tol sigma_1}) columns ordered by decreasing sigma (tol
+// 1e-10 by default, or the caller's tolerance for ranks adapted per block),
 // each signed so that its largest-magnitude entry is positive.  Omega V is then
 // the block's fixed test matrix (the sampling matrices are drawn once and kept
 // fixed, Sec. 3.3), so Alg. 1 and Alg. 2 see a full-column-rank sample.
@@ -190,8 +191,8 @@ __global__ void __launch_bounds__(256) k_jacobi_svd(const double* R, int ell, in
   }
 }
 
-hm_status sketch_compress(Model* m, const double* Y, int ldy, int ell, int l, int rank, double* W, double* R,
-                          double* V, int kc, int* d_k, double* d_sig) {
+hm_status sketch_compress(Model* m, const double* Y, int ldy, int ell, int l, int rank, double tol, double* W,
+                          double* R, double* V, int kc, int* d_k, double* d_sig) {
   if (ell > ELLMAX) {
     set_error("rank + oversample exceeds 80");
     return HM_E_INVAL;
@@ -199,7 +200,7 @@ hm_status sketch_compress(Model* m, const double* Y, int ldy, int ell, int l, in
   const int nb = 1 << (l - 1);
   hipLaunchKernelGGL(k_house_qr, dim3(nb), dim3(256), 0, m->stream, Y, ldy, W, R, ell, l, m->n);
   HM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_jacobi_svd, dim3(nb), dim3(256), 0, m->stream, R, ell, rank, 1e-10, V, kc, d_k, d_sig,
+  hipLaunchKernelGGL(k_jacobi_svd, dim3(nb), dim3(256), 0, m->stream, R, ell, rank, tol, V, kc, d_k, d_sig,
                      m->d_flags);
   HM_LAUNCH_CHECK();
   return HM_OK;

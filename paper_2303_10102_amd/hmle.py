@@ -43,6 +43,7 @@ _SIGS = {
     "hm_model_perm": ([_P, C.POINTER(_I)], _I),
     "hm_kapply": ([_P, _D, _P, _I, _I, _P, _I, _I], _I),
     "hm_sketch_create": ([_P, _P, _I, _I, _D, C.POINTER(_P)], _I),
+    "hm_sketch_create_tol": ([_P, _P, _I, _I, C.c_double, _D, C.POINTER(_P)], _I),
     "hm_sketch_destroy": ([_P], None),
     "hm_sketch_ranks": ([_P, C.POINTER(_I), C.POINTER(_I)], _I),
     "hm_H_create": ([_P, _I, C.POINTER(_I), C.POINTER(_P)], _I),
@@ -183,10 +184,17 @@ class Model:
 class Sketch:
     """Fixed test matrices and frozen compression (created once at theta0)."""
 
-    def __init__(self, model, omega, rank, oversample, theta0_full):
+    def __init__(self, model, omega, rank, oversample, theta0_full, rank_tol=None):
+        """rank_tol: None for the default truncation (1e-10), else the relative singular
+        value below which a block's sample directions are dropped (hm_sketch_create_tol)."""
         h = _P()
-        _check("hm_sketch_create", lib().hm_sketch_create(model._h, _ptr(omega), rank, oversample,
-                                                          _theta(theta0_full), C.byref(h)))
+        if rank_tol is None:
+            _check("hm_sketch_create", lib().hm_sketch_create(model._h, _ptr(omega), rank, oversample,
+                                                              _theta(theta0_full), C.byref(h)))
+        else:
+            _check("hm_sketch_create_tol", lib().hm_sketch_create_tol(model._h, _ptr(omega), rank, oversample,
+                                                                      float(rank_tol), _theta(theta0_full),
+                                                                      C.byref(h)))
         self._h, self.model = h, model
 
     def ranks(self):

@@ -150,3 +150,20 @@ def test_level1_block_is_range_finder_projection():
     Om = om[0][:, b].T @ V[0][0]
     Qref, _ = peeling.qr_positive(B @ Om)
     assert np.allclose(np.abs(Q.T @ Qref), np.eye(Q.shape[1]), atol=1e-10)
+
+
+def test_compress_tolerance_keeps_the_leading_directions():
+    # a sample with prescribed singular values: Y = U diag(s) W^T (orthonormal U, W);
+    # the tolerance keeps the directions with s_i > tol s_1 (capped at the rank), and
+    # they span the leading right singular vectors W[:, :k]
+    rng = np.random.default_rng(5)
+    s = np.array([1.0, 0.5, 0.2, 0.05, 0.012, 0.008, 1e-3, 1e-5])
+    U, _ = np.linalg.qr(rng.standard_normal((40, s.size)))
+    W, _ = np.linalg.qr(rng.standard_normal((s.size, s.size)))
+    Y = U @ np.diag(s) @ W.T
+    for tol, rank, k in ((1e-2, 8, 5), (1e-2, 3, 3), (1e-4, 8, 7), (0.0, 8, 8), (0.3, 8, 2)):
+        V = peeling.compress(Y, rank, tol)
+        assert V.shape == (s.size, k)
+        # same subspace: the projector onto span(V) equals the one onto W[:, :k]
+        P1, P2 = V @ V.T, W[:, :k] @ W[:, :k].T
+        assert np.max(np.abs(P1 - P2)) < 1e-12
