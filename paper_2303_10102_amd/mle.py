@@ -107,3 +107,43 @@ def fit(H, y, theta_full, max_iter=200, tol=1e-6, max_log_step=2.0, min_step=2.0
     return dict(theta=th, theta_full=full(phi), free=free, loglik=ll, grad_nll=g, fim=fim, se=se,
                 ci95=np.stack([th - 1.96 * se, th + 1.96 * se], axis=1), decrement=dec, converged=converged,
                 iterations=it, evaluations=evals, seconds=time.perf_counter() - t0, history=history)
+
+
+def fit_schedule(model, omega, y, theta_full, free, ranks, oversample, rank_tol=None, **fit_kw):
+    """Fits at increasing off-diagonal ranks, each stage starting from the previous
+    estimate with its sketch re-created there (sketch refresh): cheap low-rank
+    iterations far from the optimum, the target rank near it (the strategy the paper
+    suggests for its experiments).
+
+    model: Model; omega: device tensor (levels, ell_max, n) of N(0,1) draws with
+    ell_max >= max(ranks) + oversample (stage r uses its first r + oversample columns);
+    y: device vector; theta_full: starting parameters; free: parameter names.  Returns
+    the last stage's fit with "stages" (per stage: rank, kept panel width, seconds of
+    sketch creation, the fit) and "seconds" (all stages, sketch creation included)."""
+    from .hmle import HMatrix, Sketch
+
+    theta = np.array(theta_full, dtype=np.float64)
+    stages, total, res = [], 0.0, None
+    for r in ranks:
+        ell = r + oversample
+        if ell > omega.shape[1]:
+            raise ValueError("omega has fewer columns than rank + oversample")
+        t0 = time.perf_counter()
+        om = omega[:, :ell, :].contiguous()
+        s = Sketch(model, om, r, oversample, theta, rank_tol)
+        del om
+        H = HMatrix(s, free)
+        t_sketch = time.perf_counter() - t0
+        try:
+            res = fit(H, y, theta, **fit_kw)
+        finally:
+            H.close()
+            kc = s.ranks()[1]
+            s.close()
+        theta = res["theta_full"]
+        total += t_sketch + res["seconds"]
+        stages.append(dict(rank=r, kc=kc, sketch_seconds=t_sketch, fit=res))
+    out = dict(res)
+    out["stages"] = stages
+    out["seconds"] = total
+    return out
