@@ -14,6 +14,8 @@ Modules
                eigenbasis of the Dirichlet stencils (independent of `model`).
   peeling   -- dense replay of the randomized peeling construction (Sec. 3.2,
                Alg. 1) and of its derivative (Sec. 3.3, Alg. 2), giving K~ and K~_j.
+  mle       -- maximum-likelihood fits by Fisher scoring on the exact likelihood
+               (dense or closed form; Sec. 2, eqs. "score", "fisher info", "CLT").
 
 Every function cites the passage it follows.  Parity status is listed per
 module; every function here is pinned by a test in tests/test_oracle_*.py.
