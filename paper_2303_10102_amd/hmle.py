@@ -301,6 +301,27 @@ class HMatrix:
             pass
 
 
+def place_fields(cost, nstreams):
+    """Longest-first placement of fields on streams: fields in decreasing cost, each on
+    the stream with the least cost so far (ties to the lower stream).  Returns (lanes,
+    order): lanes[q] lists stream q's fields in enqueue order, and order interleaves the
+    lanes (first field of every stream, then the second, ...), so that every stream has
+    work at once."""
+    nstreams = max(1, int(nstreams))
+    load = [0.0] * nstreams
+    lanes = [[] for _ in range(nstreams)]
+    for f in sorted(range(len(cost)), key=lambda i: -cost[i]):
+        q = min(range(nstreams), key=lambda j: load[j])
+        load[q] += cost[f]
+        lanes[q].append(f)
+    order = []
+    for r in range(max((len(x) for x in lanes), default=0)):
+        for q in range(nstreams):
+            if r < len(lanes[q]):
+                order.append(lanes[q][r])
+    return lanes, order
+
+
 class Batch:
     """Independent fields iterated together (hm_iteration_batched).
 
@@ -337,18 +358,10 @@ class Batch:
         if nstreams != self.nstreams:
             self.streams = [torch.cuda.Stream(device=self.device) for _ in range(nstreams)]
             self.nstreams = nstreams
-        load = [0.0] * nstreams
-        lanes = [[] for _ in range(nstreams)]
-        for f in sorted(range(len(self.Hs)), key=lambda i: -cost[i]):
-            s = min(range(nstreams), key=lambda q: load[q])
-            load[s] += cost[f]
-            lanes[s].append(f)
-            self.Hs[f].model.set_stream(self.streams[s])
-        order = []
-        for r in range(max((len(x) for x in lanes), default=0)):
-            for q in range(nstreams):
-                if r < len(lanes[q]):
-                    order.append(lanes[q][r])
+        lanes, order = place_fields(cost, nstreams)
+        for q, lane in enumerate(lanes):
+            for f in lane:
+                self.Hs[f].model.set_stream(self.streams[q])
         self.order = order
         self.lanes = lanes
         return lanes

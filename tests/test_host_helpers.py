@@ -1,5 +1,7 @@
-"""Host-side test helpers checked on the CPU: the H-matvec used by the full-size
-GPU checks agrees with the dense matrix of the same representation."""
+"""Host-side logic checked on the CPU: the H-matvec used by the full-size GPU checks
+agrees with the dense matrix of the same representation, and the batched workload's
+longest-first placement of fields on streams (hmle.place_fields) is a balanced,
+complete assignment."""
 import numpy as np
 
 from tests._cases import densify, hmatvec
@@ -30,3 +32,26 @@ def test_densify_block_layout():
     K = densify(F, lv, 1, 1, n)
     assert np.array_equal(K[:2, 2:], np.outer([1.0, 2.0], [3.0, 4.0]))
     assert np.array_equal(K[2:, :2], np.outer([3.0, 4.0], [1.0, 2.0]))
+
+
+def test_place_fields_longest_first():
+    from paper_2303_10102_amd.hmle import place_fields
+    rng = np.random.default_rng(3)
+    cost = list(rng.uniform(1.0, 100.0, size=23))
+    for ns in (1, 2, 4, 8):
+        lanes, order = place_fields(cost, ns)
+        assert len(lanes) == ns
+        assert sorted(order) == list(range(len(cost)))            # every field once
+        assert sorted(f for lane in lanes for f in lane) == list(range(len(cost)))
+        loads = [sum(cost[f] for f in lane) for lane in lanes]
+        # longest-processing-time bound: no stream exceeds the mean load by more than the
+        # largest single cost
+        assert max(loads) <= sum(cost) / ns + max(cost) + 1e-9
+        for lane in lanes:                                        # each lane longest first
+            assert all(cost[a] >= cost[b] for a, b in zip(lane, lane[1:]))
+        # the enqueue order starts every stream before any stream's second field
+        firsts = {lane[0] for lane in lanes if lane}
+        assert set(order[:len(firsts)]) == firsts
+    # more streams than fields: the extra streams stay empty
+    lanes, order = place_fields([5.0, 1.0], 4)
+    assert lanes == [[0], [1], [], []] and order == [0, 1]
