@@ -25,9 +25,12 @@ Readings (the paper is silent or loose on these):
     sketched with ell = r + p_os columns, the right singular vectors V of that
     sample are computed, and V keeps k = min(r, #{sigma_i > 1e-10 sigma_1})
     columns, each signed so that its entry of largest magnitude is positive.
-    Omega V is then the block's fixed test matrix for every later theta (the
-    paper's "draw once and keep fixed"), so Alg. 1 and Alg. 2 apply with k
-    columns and R is invertible.
+    Column j of every block of a level is scaled by one common factor (the
+    geometric mean of s_1 / s_j over the level's blocks that keep it).  Omega V is
+    then the block's fixed test matrix for every later theta (the paper's "draw
+    once and keep fixed"), so Alg. 1 and Alg. 2 apply with k columns and R is
+    invertible.  The common scale changes no block of K~ or K~_j (Q is that of the
+    unscaled sample) and keeps R well conditioned where the blocks' spectra are alike.
   * QR sign gauge: diag(R) > 0.
   * Leaf blocks read from the stacked-identity sample are symmetrised, (D + D^T)/2.
   * Columns of all blocks at one level share one patterned matrix (one batched
@@ -71,7 +74,8 @@ def qr_tangent(Q: np.ndarray, R: np.ndarray, dB: np.ndarray) -> np.ndarray:
 
 
 def compress(Yl: np.ndarray, rank: int, tol: float = 1e-10) -> np.ndarray:
-    """Frozen compression of an oversampled sketch (reading of Alg. 1 step 3)."""
+    """Frozen compression of an oversampled sketch (reading of Alg. 1 step 3): the
+    kept right singular vectors of the sample (orthonormal columns)."""
     _, s, Vt = np.linalg.svd(Yl, full_matrices=False)
     if s.size == 0 or s[0] == 0.0:
         return np.zeros((Yl.shape[1], 0))
@@ -82,6 +86,26 @@ def compress(Yl: np.ndarray, rank: int, tol: float = 1e-10) -> np.ndarray:
         if V[i, j] < 0:
             V[:, j] = -V[:, j]
     return V
+
+
+def sample_spectrum(Yl: np.ndarray) -> np.ndarray:
+    """Singular values of a block's oversampled sketch, decreasing."""
+    return np.linalg.svd(Yl, compute_uv=False)
+
+
+def level_scale(spectra, ks) -> np.ndarray:
+    """Column scale shared by every block of one level: d_j = exp(mean over the blocks
+    that keep column j of log(s_1 / s_j)).  The blocks of a level share the columns of
+    one patterned test matrix, so only a scale common to all of them leaves every
+    block's sample, and hence Q and K~, unchanged (a per-block scale would change the
+    crosstalk between blocks, eqs. "lvl2 sample1/2"); it makes R well conditioned
+    when the blocks' spectra are alike."""
+    kmax = max(ks) if ks else 0
+    d = np.ones(kmax)
+    for j in range(kmax):
+        logs = [np.log(s[0] / s[j]) for s, k in zip(spectra, ks) if k > j]
+        d[j] = np.exp(np.mean(logs))
+    return d
 
 
 def _blocks(tree: Tree, l: int):
@@ -137,8 +161,10 @@ def _level_step(Kr, tree, l, XR, ks, dKrs=()):
     return out
 
 
-def sketch_create(K: np.ndarray, tree: Tree, omega: np.ndarray, rank: int, tol: float = 1e-10):
-    """Create the frozen per-block compressions V[l-1][i] (ell x k_P) at theta_0."""
+def sketch_create(K: np.ndarray, tree: Tree, omega: np.ndarray, rank: int, tol: float = 1e-10,
+                  scaled: bool = True):
+    """Create the frozen per-block compressions V[l-1][i] (ell x k_P) at theta_0
+    (columns scaled by the level's common factors unless scaled=False; see level_scale)."""
     H = np.zeros_like(K)
     V_all = []
     for l in range(1, tree.levels + 1):
@@ -147,6 +173,10 @@ def sketch_create(K: np.ndarray, tree: Tree, omega: np.ndarray, rank: int, tol: 
         full = [np.eye(ell)] * len(tree.nodes[l - 1])
         Yl = Kr @ patterned_right(tree, l, omega[l - 1], full)
         Vs = [compress(Yl[a], rank, tol) for (i, a, b) in _blocks(tree, l)]
+        if scaled:
+            d = level_scale([sample_spectrum(Yl[a]) for (i, a, b) in _blocks(tree, l)],
+                            [V.shape[1] for V in Vs])
+            Vs = [V * d[None, :V.shape[1]] for V in Vs]
         V_all.append(Vs)
         XR = patterned_right(tree, l, omega[l - 1], Vs)
         ks = [V.shape[1] for V in Vs]

@@ -971,10 +971,12 @@ hm_status hm_loglik_grad_adjoint(hm_H* hh, const double* theta_full, const doubl
     return HM_E_NONFINITE;
   }
   if (grad) {
-    // w-weighted mode sums: <w, e>, <w, de/dkappa>, <w, de/dalpha>, sum w
+    // w-weighted mode sums: <w, lambda>, <w, dlambda/dkappa>, <w, dlambda/dalpha>, sum w
+    // (lambda: the physics part of the mode multiplier, sigma2 times the unit-scale one,
+    // so de/dsigma2 = lambda / sigma2; de/dtau2 = 1)
     const double* t = h->h_scal + SC_ADJ;
-    const double tau2 = h->theta[2], sigma2 = h->theta[3];
-    const double tb[4] = {t[1], t[2], t[3], (t[0] - tau2 * t[3]) / sigma2};
+    const double sigma2 = h->theta[3];
+    const double tb[4] = {t[1], t[2], t[3], t[0] / sigma2};
     for (int q = 0; q < h->p; ++q) {
       grad[q] = tb[h->pidx[q]];
       if (!std::isfinite(grad[q])) {

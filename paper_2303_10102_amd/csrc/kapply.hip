@@ -82,7 +82,8 @@ __global__ void k_tables_half(double* Ph, int N) {
   Ph[e] = sqrt(2.0 / (N + 1)) * sinpi((double)m / (double)(N + 1));
 }
 
-// Per-mode multipliers for K, dK/dkappa, dK/dalpha: lam[o*N*Ny + p + q*N]
+// Per-mode multipliers of the physics part of K (sigma2 A^-1 B^-2 A^-1; the nugget is
+// added row by row, see kapply_multi), dK/dkappa, dK/dalpha: lam[o*N*Ny + p + q*N]
 __global__ void k_mode_scale(double* lam, const double* mu, int N, int Ny, double kappa, double alpha,
                              double tau2, double sigma2) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -92,7 +93,7 @@ __global__ void k_mode_scale(double* lam, const double* mu, int N, int Ny, doubl
   double a = 1.0 + alpha * m, b = kappa * kappa + m;
   double l = sigma2 / (a * a * b * b);
   const long NN = (long)N * Ny;
-  lam[e] = l + tau2;
+  lam[e] = l;   // physics only: the nugget tau2 X is added outside the transforms
   lam[NN + e] = -4.0 * kappa * l / b;
   lam[2 * NN + e] = -2.0 * m * l / a;
 }
@@ -687,6 +688,19 @@ static void x_inverse(Model* m, const double* W, MultiOut mo, bool lam, int ldy,
 }
 #undef HM_DST_LAUNCH
 
+// Y[t, j] += tau2 X[t, j] for the rows t of the leaves selected by (mode, depth), j < c.
+__global__ void k_nugget(double* Y, int ldy, const double* X, int ldx, int n, int nl, int c, double tau2,
+                         int levels, int mode, int depth) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * c) return;
+  const int t = (int)(e % n), j = (int)(e / n);
+  if (mode != 0) {
+    const int anc = (t / nl) >> (levels - depth);
+    if (((anc & 1) == 0) != (mode == 1)) return;
+  }
+  Y[t + (long)j * ldy] += tau2 * X[t + (long)j * ldx];
+}
+
 hm_status kapply_multi(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK, int cK,
                        double* outKap, int cKap, double* outAlp, int cAlp, int ldo, LeafSel in_sel,
                        LeafSel out_sel) {
@@ -749,6 +763,18 @@ hm_status kapply_multi(Model* m, const double theta[4], const double* X, int ldx
       mo.in_stride = 0;
       x_inverse(m, Xh, mo, true, ldo, 1, xout, yout);
     }
+    HM_LAUNCH_CHECK();
+  }
+  // The nugget tau2 I acts row by row, so it is added to the value output here rather
+  // than as a mode multiplier: through the transforms its rounding (relative to the
+  // largest entry of a column) would swamp the small far-field products the sketches
+  // sample.  An input confined to one side of a split and an output wanted on the
+  // other side get no nugget term at all.
+  const bool disjoint = in_sel.mode != 0 && out_sel.mode != 0 && in_sel.depth == out_sel.depth &&
+                        in_sel.mode != out_sel.mode;
+  if (outK && cK > 0 && !disjoint) {
+    hipLaunchKernelGGL(k_nugget, dim3(ceil_div((long)n * cK, 256)), dim3(256), 0, m->stream, outK, ldo, X, ldx, n,
+                       m->nl, cK, theta[2], m->levels, out_sel.mode, out_sel.depth);
     HM_LAUNCH_CHECK();
   }
   if (pf) {

@@ -7,9 +7,15 @@
 // relative accuracy for small singular values) keep
 // k = min(r, #{sigma_i > tol sigma_1}) columns ordered by decreasing sigma (tol
 // 1e-10 by default, or the caller's tolerance for ranks adapted per block),
-// each signed so that its largest-magnitude entry is positive.  Omega V is then
-// the block's fixed test matrix (the sampling matrices are drawn once and kept
-// fixed, Sec. 3.3), so Alg. 1 and Alg. 2 see a full-column-rank sample.
+// each signed so that its largest-magnitude entry is positive.  Column j of every
+// block of a level is then scaled by one common factor d_j = exp(mean over the
+// blocks keeping column j of log(sigma_1 / sigma_j)).  Omega V is the block's fixed
+// test matrix (the sampling matrices are drawn once and kept fixed, Sec. 3.3), so
+// Alg. 1 and Alg. 2 see a full-column-rank sample.  The blocks of a level share the
+// columns of one patterned test matrix, so a scale common to all of them changes no
+// block's sample beyond that scale: Q (diag R > 0), and so K~ and K~_j, are those of
+// the unscaled directions, while R -- which Alg. 2 divides by -- is close to a
+// multiple of an orthogonal matrix when the blocks' spectra are alike.
 #include <cmath>
 
 #include "hm_internal.h"
@@ -191,6 +197,28 @@ __global__ void __launch_bounds__(256) k_jacobi_svd(const double* R, int ell, in
   }
 }
 
+// Common column scale of one level (see the header): V of nb blocks (ell x kc each,
+// stride ell*kc), sorted singular values sig (ell per block), kept ranks k.
+__global__ void __launch_bounds__(64) k_level_scale(double* V, const double* sig, const int* kk, int nb, int ell,
+                                                    int kc) {
+  __shared__ double d[ELLMAX];
+  for (int j = threadIdx.x; j < kc; j += blockDim.x) {
+    double acc = 0.0;
+    int cnt = 0;
+    for (int b = 0; b < nb; ++b)
+      if (kk[b] > j) {
+        acc += log(sig[(long)b * ell] / sig[(long)b * ell + j]);
+        ++cnt;
+      }
+    d[j] = cnt ? exp(acc / cnt) : 1.0;
+  }
+  __syncthreads();
+  for (long e = threadIdx.x; e < (long)nb * ell * kc; e += blockDim.x) {
+    const int j = (int)((e / ell) % kc);
+    V[e] *= d[j];
+  }
+}
+
 hm_status sketch_compress(Model* m, const double* Y, int ldy, int ell, int l, int rank, double tol, double* W,
                           double* R, double* V, int kc, int* d_k, double* d_sig) {
   if (ell > ELLMAX) {
@@ -202,6 +230,8 @@ hm_status sketch_compress(Model* m, const double* Y, int ldy, int ell, int l, in
   HM_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_jacobi_svd, dim3(nb), dim3(256), 0, m->stream, R, ell, rank, tol, V, kc, d_k, d_sig,
                      m->d_flags);
+  HM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_level_scale, dim3(1), dim3(64), 0, m->stream, V, d_sig, d_k, nb, ell, kc);
   HM_LAUNCH_CHECK();
   return HM_OK;
 }

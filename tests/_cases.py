@@ -106,6 +106,39 @@ def rel_err(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
+def grad_err_sd(g, ref, fim_ref):
+    """Per-entry gradient error in units of the score's standard deviation:
+    max_j |g_j - ref_j| / sqrt(I_jj).  The entries of g span many orders of magnitude
+    (the scale parameters' scores dwarf kappa's), so an error relative to the largest
+    entry would not see the small ones; this unit is scale free per parameter."""
+    g, ref = np.asarray(g, dtype=np.float64), np.asarray(ref, dtype=np.float64)
+    sd = np.sqrt(np.diag(np.asarray(fim_ref, dtype=np.float64)))
+    return float(np.max(np.abs(g - ref) / sd))
+
+
+def fim_err_corr(fim, ref):
+    """Per-entry Fisher error in correlation units: max_ij |I_ij - ref_ij| / sqrt(ref_ii ref_jj)."""
+    fim, ref = np.asarray(fim, dtype=np.float64), np.asarray(ref, dtype=np.float64)
+    d = np.sqrt(np.diag(ref))
+    return float(np.max(np.abs(fim - ref) / np.outer(d, d)))
+
+
+def dense_derivatives(w, Kt, dK_real):
+    """Derivative matrices of a dense K~ for the free parameters of workload w, in its
+    order: kappa, alpha from dK_real (dict name -> matrix); tau2: I; sigma2:
+    (K~ - tau2 I) / sigma2 (K~ is linear in tau2 and homogeneous in sigma2)."""
+    n = Kt.shape[0]
+    out = []
+    for name in w.free:
+        if name in ("kappa", "alpha"):
+            out.append(dK_real[name])
+        elif name == "tau2":
+            out.append(np.eye(n))
+        else:
+            out.append((Kt - w.tau2 * np.eye(n)) / w.sigma2)
+    return out
+
+
 def hmatvec(F, leaves, levels, kc, x, dF=None, dleaves=None):
     """K~ x (or K~_j x when dF, dleaves are given) from an exported representation.
 

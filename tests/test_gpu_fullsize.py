@@ -1,7 +1,7 @@
 """GPU checks at full size: the 256 x 256 workload (n = 65536, leaf 256, 8 levels,
 rank 48, theta = (kappa, alpha, tau2, sigma2)) in the launch configuration the
 benchmark times, and the 128 x 128 workload (n = 16384, 6 levels, rank 32,
-theta = (kappa, alpha, tau2)).
+theta = (kappa, alpha, tau2), here with sigma2 free as well).
 
 A dense oracle does not fit at this size, so the checks are
   * sampled outputs the oracle computes one by one: K X, dK/dkappa X, dK/dalpha X
@@ -23,6 +23,7 @@ A dense oracle does not fit at this size, so the checks are
   * the approximation itself against the exact closed form (oracle.spectral):
     reported, with a sanity bound only (the rank-48 error is not pinned).
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -42,7 +43,10 @@ def full(request):
     from synth import WORKLOADS, sample_y, sketch_draws
 
     w = WORKLOADS[request.param]
-    print(f"\n[full-size {w.name}: n={w.n}]", flush=True)
+    if "sigma2" not in w.free:
+        # all four parameters free, so the scale identities below hold on both sizes
+        w = dataclasses.replace(w, free=tuple(w.free) + ("sigma2",))
+    print(f"\n[full-size {w.name}: n={w.n}, free {w.free}]", flush=True)
     m = hmle.Model(w.dim, w.N, w.leaf)
     om = torch.from_numpy(sketch_draws(w)).cuda()
     s = hmle.Sketch(m, om, w.rank, w.oversample, w.theta_full)

@@ -167,3 +167,41 @@ def test_compress_tolerance_keeps_the_leading_directions():
         # same subspace: the projector onto span(V) equals the one onto W[:, :k]
         P1, P2 = V @ V.T, W[:, :k] @ W[:, :k].T
         assert np.max(np.abs(P1 - P2)) < 1e-12
+
+
+def test_level_scale_whitens_alike_blocks():
+    # hand case: geometric mean over the blocks that keep each column
+    d = peeling.level_scale([np.array([1.0, 0.1, 0.05]), np.array([2.0, 0.02, 1e-3])], [2, 3])
+    assert np.allclose(d, [1.0, np.sqrt(10.0 * 100.0), 2000.0], rtol=1e-14)
+    # blocks with one spectrum: Y V d = s_1 U (orthogonal columns of equal norm s_1),
+    # so the sample's R is s_1 I; rounding of Y (u |Y|) grows by s_1 / s_5 = 3e6
+    rng = np.random.default_rng(8)
+    s = np.array([3.0, 1.0, 1e-2, 1e-4, 1e-6])
+    Ys = []
+    for _ in range(2):
+        U, _ = np.linalg.qr(rng.standard_normal((30, s.size)))
+        W, _ = np.linalg.qr(rng.standard_normal((7, s.size)))
+        Ys.append(U @ np.diag(s) @ W.T)
+    Vs = [peeling.compress(Y, rank=5) for Y in Ys]
+    d = peeling.level_scale([peeling.sample_spectrum(Y) for Y in Ys], [5, 5])
+    assert np.allclose(d, s[0] / s, rtol=1e-6)
+    for Y, V in zip(Ys, Vs):
+        G = (Y @ V * d).T @ (Y @ V * d)
+        assert np.max(np.abs(G - s[0] ** 2 * np.eye(5))) <= 1e-8 * s[0] ** 2
+        _, R = peeling.qr_positive(Y @ V * d)
+        assert np.linalg.cond(R) < 1 + 1e-6
+
+
+def test_scaled_compression_leaves_the_construction_unchanged():
+    # a positive column scale common to the blocks of a level gives the same sample up
+    # to that scale in every block, hence the same Q (diag R > 0): K~ and K~_j are the
+    # same matrices (up to the rounding of the unscaled, worse-conditioned R)
+    w = small_workload(N=16, leaf=16, rank=8, oversample=4, sigma2=500.0)
+    Kt, dKt, tree, om = _setup(w)
+    V1 = peeling.sketch_create(Kt, tree, om, w.rank, scaled=True)
+    V0 = peeling.sketch_create(Kt, tree, om, w.rank, scaled=False)
+    r1 = peeling.build(Kt, dKt, tree, om, V1)
+    r0 = peeling.build(Kt, dKt, tree, om, V0)
+    assert np.max(np.abs(r1["Kt"] - r0["Kt"])) <= 1e-12 * np.max(np.abs(r0["Kt"]))
+    for j in range(len(w.free)):
+        assert np.max(np.abs(r1["dKts"][j] - r0["dKts"][j])) <= 1e-7 * np.max(np.abs(r0["dKts"][j]))
