@@ -97,6 +97,18 @@ hm_status hm_model_perm(const hm_model* m, int* perm_host);
 hm_status hm_kapply(hm_model* m, const double* theta_full, const double* X, int ldx, int c, double* Y,
                     int ldy, int which);
 
+/* hm_kapply for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same operator,
+ * arguments, layout and errors as hm_kapply, with the transform scratch taken from
+ * one fixed 64 MiB device array per GPU (held until the process ends) instead of the
+ * model's workspace; the call allocates and frees nothing.  Columns are processed in
+ * blocks of floor(64 MiB / (40 n)) (at most 4096), so n may be at most 1677721:
+ * larger models get HM_E_INVAL.  All calls on one GPU share its array: calls that
+ * overlap in time on one GPU (other streams or threads) race and must not be issued.
+ * The model's stream and device are used; the caller's current device is restored. */
+hm_status hm_kapply_noalloc(hm_model* m, const double* theta_full, const double* X, int ldx, int c, double* Y,
+                            int ldy, int which);
+
 /* --------------------------------------------------------------- sketch ---
  * hm_sketch_create: fix the test matrices for all later iterations (Sec. 3.3:
  * sampling matrices drawn once and kept fixed).  omega: device, levels x ell x n

@@ -74,7 +74,7 @@ static bool finite4(const double* t) {
   return true;
 }
 
-static hm_status check_theta(const double* t) {
+hm_status check_theta(const double* t) {
   if (!t) {
     set_error("theta is NULL");
     return HM_E_INVAL;
@@ -367,9 +367,6 @@ static hm_status iteration_collect(HState* h, double* loglik, double* grad, doub
 
 using namespace hm;
 
-struct hm_model {
-  Model m;
-};
 struct hm_sketch {
   Sketch s;
 };

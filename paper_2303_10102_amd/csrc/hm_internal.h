@@ -186,6 +186,11 @@ inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 hm_status kapply(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK,
                  double* outKap, double* outAlp, int ldo);
 
+// The same K-apply (every row in and out) with its transform scratch supplied by the
+// caller: ws holds 5 * n * cblk doubles, and the columns are processed cblk at a time.
+hm_status kapply_ws(Model* m, double* ws, int cblk, const double theta[4], const double* X, int ldx, int c,
+                    double* outK, double* outKap, double* outAlp, int ldo);
+
 // Generic FP64 GEMM, column-major: C = alpha*op(A)*op(B) + beta*C, batched by strides.
 hm_status gemm(hipStream_t st, bool ta, bool tb, int M, int Nc, int K, double alpha, const double* A,
                int lda, long sA, const double* B, int ldb, long sB, double beta, double* C, int ldc,
@@ -264,7 +269,14 @@ hm_status alg2_fold_nodes(Model* m, const double* W, double* M, long stride, int
 hm_status node_lu(Model* m, const double* S, long sstride, double* Nout, long nstride, double* logdet, int k,
                   int heap0, int cnt);
 hm_status model_tables(Model* m);
+// theta_full[4] checks shared by the entry points (finite; kappa, tau2, sigma2 > 0, alpha >= 0)
+hm_status check_theta(const double* t);
 // time the panel-kernel variants on this model's shapes (panel width kc) and keep the fastest
 hm_status autotune(Model* m, int kc, double* report);
 
 }  // namespace hm
+
+// the public model handle (opaque in hmle.h)
+struct hm_model {
+  hm::Model m;
+};

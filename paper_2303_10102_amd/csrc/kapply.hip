@@ -701,9 +701,11 @@ __global__ void k_nugget(double* Y, int ldy, const double* X, int ldx, int n, in
   Y[t + (long)j * ldy] += tau2 * X[t + (long)j * ldx];
 }
 
-hm_status kapply_multi(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK, int cK,
-                       double* outKap, int cKap, double* outAlp, int cAlp, int ldo, LeafSel in_sel,
-                       LeafSel out_sel) {
+// The K-apply with its transform scratch ws (5 * n * cblk doubles) passed in, columns
+// processed cblk at a time.
+static hm_status kapply_core(Model* m, double* ws, int cblk, const double theta[4], const double* X, int ldx, int c,
+                             double* outK, int cK, double* outKap, int cKap, double* outAlp, int cAlp, int ldo,
+                             LeafSel in_sel, LeafSel out_sel) {
   if (c <= 0) return HM_OK;
   if (cK > c || cKap > c || cAlp > c) {
     set_error("kapply: an output wants more columns than the input has");
@@ -719,9 +721,9 @@ hm_status kapply_multi(Model* m, const double theta[4], const double* X, int ldx
   side_maps(m, out_sel, xout, yout);
   const int Kx = xin.extent(N), Mx = xout.extent(N);
   const int Nyi = two ? yin.extent(N) : 1, Nyo = two ? yout.extent(N) : 1;
-  double* Xh = m->d_ws;                        // x-transformed (compact input y)
-  double* X2 = m->d_ws + (long)n * m->cmax;    // x- and y-transformed (2D)
-  double* X3 = m->d_ws + 2L * n * m->cmax;     // scaled and y-inverse-transformed, one slot per output
+  double* Xh = ws;                        // x-transformed (compact input y)
+  double* X2 = ws + (long)n * cblk;       // x- and y-transformed (2D)
+  double* X3 = ws + 2L * n * cblk;        // scaled and y-inverse-transformed, one slot per output
   double* outs[3] = {outK, outKap, outAlp};
   const int ocols[3] = {outK ? cK : 0, outKap ? cKap : 0, outAlp ? cAlp : 0};
   const bool pf = prof_on(m, PF_DST);
@@ -734,8 +736,8 @@ hm_status kapply_multi(Model* m, const double theta[4], const double* X, int ldx
   const double fl_out = (two ? fy_out * 2.0 * N * N * (double)Nyo : 0.0) + fx_out * 2.0 * Mx * N * (double)Nyo;
   const double per_col = fl_fwd + nout * fl_out;
   if (pf) prof_begin(m, PF_DST);
-  for (int c0 = 0; c0 < c; c0 += m->cmax) {
-    const int cc = std::min(m->cmax, c - c0);
+  for (int c0 = 0; c0 < c; c0 += cblk) {
+    const int cc = std::min(cblk, c - c0);
     x_forward(m, X + (long)c0 * ldx, ldx, Xh, cc, Nyi, xin, yin);
     HM_LAUNCH_CHECK();
     if (two) {
@@ -753,8 +755,8 @@ hm_status kapply_multi(Model* m, const double theta[4], const double* X, int ldx
     }
     if (mo.nq == 0) continue;
     if (two) {
-      // X3 holds one slot of n * cmax doubles per output
-      const long slot = (long)n * m->cmax;
+      // X3 holds one slot of n * cblk doubles per output
+      const long slot = (long)n * cblk;
       y_inverse(m, X2, mo, X3, slot, yout);
       HM_LAUNCH_CHECK();
       mo.in_stride = slot;
@@ -784,6 +786,22 @@ hm_status kapply_multi(Model* m, const double theta[4], const double* X, int ldx
     prof_end(m, PF_DST, per_col * c, passes * 16.0 * n * (double)c + 8.0 * N * (double)N);
   }
   return HM_OK;
+}
+
+hm_status kapply_multi(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK, int cK,
+                       double* outKap, int cKap, double* outAlp, int cAlp, int ldo, LeafSel in_sel,
+                       LeafSel out_sel) {
+  return kapply_core(m, m->d_ws, m->cmax, theta, X, ldx, c, outK, cK, outKap, cKap, outAlp, cAlp, ldo, in_sel,
+                     out_sel);
+}
+
+hm_status kapply_ws(Model* m, double* ws, int cblk, const double theta[4], const double* X, int ldx, int c,
+                    double* outK, double* outKap, double* outAlp, int ldo) {
+  if (cblk < 1) {
+    set_error("kapply: the scratch holds no column block");
+    return HM_E_INVAL;
+  }
+  return kapply_core(m, ws, cblk, theta, X, ldx, c, outK, c, outKap, c, outAlp, c, ldo, sel_all(), sel_all());
 }
 
 hm_status kapply_sel(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK,

@@ -42,6 +42,7 @@ _SIGS = {
     "hm_model_tuning": ([_P, C.POINTER(_I), C.POINTER(C.c_longlong), _I], _I),
     "hm_model_perm": ([_P, C.POINTER(_I)], _I),
     "hm_kapply": ([_P, _D, _P, _I, _I, _P, _I, _I], _I),
+    "hm_kapply_noalloc": ([_P, _D, _P, _I, _I, _P, _I, _I], _I),
     "hm_sketch_create": ([_P, _P, _I, _I, _D, C.POINTER(_P)], _I),
     "hm_sketch_create_tol": ([_P, _P, _I, _I, C.c_double, _D, C.POINTER(_P)], _I),
     "hm_sketch_destroy": ([_P], None),
@@ -150,12 +151,14 @@ class Model:
         _check("hm_model_perm", lib().hm_model_perm(self._h, out))
         return np.frombuffer(out, dtype=np.int32).copy()
 
-    def kapply(self, theta_full, X, which=0):
-        """Y = op X for X a (c, n) float64 CUDA tensor in tree order; op = K, dK/dkappa, dK/dalpha."""
+    def kapply(self, theta_full, X, which=0, out=None, noalloc=False):
+        """Y = op X for X a (c, n) float64 CUDA tensor in tree order; op = K, dK/dkappa, dK/dalpha.
+        noalloc: use hm_kapply_noalloc (fixed per-device scratch, no allocation)."""
         import torch
         c, n = X.shape
-        Y = torch.empty_like(X)
-        _check("hm_kapply", lib().hm_kapply(self._h, _theta(theta_full), _ptr(X), n, c, _ptr(Y), n, which))
+        Y = torch.empty_like(X) if out is None else out
+        fn = "hm_kapply_noalloc" if noalloc else "hm_kapply"
+        _check(fn, getattr(lib(), fn)(self._h, _theta(theta_full), _ptr(X), n, c, _ptr(Y), n, which))
         return Y
 
     def profile_enable(self, family):
