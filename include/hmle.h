@@ -16,8 +16,9 @@
  * Conventions
  *   * Every call returns hm_status; nothing throws across the ABI.  On failure
  *     hm_last_error() describes the cause.
- *   * Device buffers are plain device pointers (hipMalloc'd or from any caching
- *     allocator) owned by the caller; the library never frees them.  Host
+ *   * Device buffers passed in (y, x, omega, X, Y) are plain device pointers
+ *     owned by the caller; the library never frees them.  The library's own device
+ *     memory comes from the context's allocator callbacks (hm_ctx_create).  Host
  *     buffers are plain host pointers owned by the caller.
  *   * All device work is enqueued on the stream given to hm_model_create; calls
  *     that return host scalars synchronise that stream once before returning.
@@ -47,12 +48,29 @@ typedef enum {
   HM_E_DEVICE = 7      /* HIP runtime error */
 } hm_status;
 
+typedef struct hm_ctx hm_ctx;       /* device, stream, device-memory allocator callbacks */
 typedef struct hm_model hm_model;   /* grid, tree ordering, transform tables, stream */
 typedef struct hm_sketch hm_sketch; /* fixed test matrices (drawn once, Sec. 3.3) + frozen compression */
 typedef struct hm_H hm_H;           /* K~(theta), K~_j(theta), factorisation, per-iteration workspace */
 
 /* Last error message of the calling thread (static storage, valid until the next call). */
 const char* hm_last_error(void);
+
+/* -------------------------------------------------------------- context ---
+ * Device memory: every device buffer of a model, of its sketches and of its H
+ * handles (panel sets, leaves, workspaces, setup temporaries) is obtained from
+ * alloc(uctx, bytes) and returned with release(uctx, ptr) -- e.g. a framework's
+ * caching allocator, so that the caller owns and accounts for the memory.  alloc
+ * returns NULL on failure (the call then fails with HM_E_NOMEM); the memory must be
+ * usable by work on `stream` in stream order.  With alloc = release = NULL the
+ * library uses hipMalloc / hipFree.  Pinned host staging (a few KB per H) is not
+ * device memory and is allocated by the library.  The context must outlive every
+ * model created with it; it is not thread-safe. */
+typedef void* (*hm_alloc_fn)(void* uctx, size_t bytes);
+typedef void (*hm_free_fn)(void* uctx, void* ptr);
+hm_status hm_ctx_create(int device, void* stream, hm_alloc_fn alloc, hm_free_fn release, void* uctx,
+                        hm_ctx** out);
+void hm_ctx_destroy(hm_ctx* c);
 
 /* ---------------------------------------------------------------- model ---
  * hm_model_create: the stencil covariance model on a dim-D grid of side N
@@ -64,6 +82,19 @@ const char* hm_last_error(void);
  * device: HIP device ordinal; stream: hipStream_t to enqueue on (NULL = default).
  */
 hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm_model** out);
+/* The same model with its device memory from a context (allocator callbacks, device and
+ * stream of ctx) and the grid given in full (Sec. 2.1 eq. "cov model" with the stencil
+ * operators of Sec. 5.1; observations Sec. 5.1 eq. "projection"):
+ *   dim 1: nx points, ny = 1; dim 2: an nx x ny grid (row-major, x fastest);
+ *   h: grid spacing (> 0) of the Dirichlet stencil (-Laplacian = (1/h^2) x 3-/5-point);
+ *      hm_model_create uses h = 1/(N+1), the unit interval / square;
+ *   nvars: variables per location (1);
+ *   obs_idx, nobs: the observed grid points (observation operator = selection of these
+ *      rows, nobs distinct grid indices), or NULL / nobs = 0 for every point.
+ * Currently nx = ny for dim 2, nvars = 1 and obs_idx = NULL; anything else returns
+ * HM_E_INVAL naming what is not supported. */
+hm_status hm_model_create_spde(hm_ctx* ctx, int dim, int nx, int ny, double h, int nvars, const int* obs_idx,
+                               long long nobs, int leaf, hm_model** out);
 void hm_model_destroy(hm_model* m);
 /* n, levels, leaf size (uniform). Any pointer may be NULL. */
 hm_status hm_model_info(const hm_model* m, int* n, int* levels, int* leaf);
@@ -152,8 +183,11 @@ hm_status hm_factor(hm_H* H);
 /* log|K~| (Sylvester's identity over the factors, Sec. 3.1). Host scalar. */
 hm_status hm_logdet(hm_H* H, double* out);
 /* x = K~^{-1} y (Woodbury, Sec. 3.1) with one step of FP64 refinement against the
- * H-matvec.  y, x: device, n doubles, natural grid order; may alias. */
-hm_status hm_solve(hm_H* H, const double* y, double* x);
+ * H-matvec (two under the mixed precision policy), for nrhs right-hand sides at once.
+ * y, x: device, n x nrhs column-major with leading dimension ld >= n, natural grid
+ * order; x may alias y.  nrhs = 0 does nothing.  Runs on the model's stream without
+ * a host synchronisation; no allocation (up to 16 columns per sweep). */
+hm_status hm_solve(hm_H* H, const double* y, double* x, long long nrhs, long long ld);
 /* L~ (eq. "log-like approximated", including -n/2 log 2pi) and the NLL gradient
  * grad[j] = 1/2 tr(K~^{-1} K~_j) - 1/2 y^T K~^{-1} K~_j K~^{-1} y (= -S~_j,
  * eq. "score approximated").  y: device, grid order.  loglik, grad: host (grad may be NULL). */
@@ -199,6 +233,15 @@ hm_status hm_H_set_precision(hm_H* H, int precision);
  * hm_loglik_grad with grad and hm_fisher then return HM_E_STATE until hm_build. */
 hm_status hm_loglik_grad_adjoint(hm_H* H, const double* theta_full, const double* y, double* loglik,
                                  double* grad);
+/* The two halves of hm_loglik_grad_adjoint, for a forward / backward split (e.g. an
+ * autograd function whose forward pass must not pay for the gradient):
+ * hm_loglik builds K~(theta) only (no derivative matrices), factors it and returns L~
+ * (eq. "log-like approximated"), keeping z = K~^{-1} y; hm_grad_reverse then runs the
+ * reverse sweep for that construction and y and returns grad[p] (the NLL gradient of
+ * the same L~).  hm_grad_reverse returns HM_E_STATE unless the last construction of H
+ * was followed by an evaluation of L~ (hm_loglik, hm_loglik_grad or hm_iteration). */
+hm_status hm_loglik(hm_H* H, const double* theta_full, const double* y, double* loglik);
+hm_status hm_grad_reverse(hm_H* H, double* grad);
 
 /* Export the representation for inspection (tests):
  * what=0: panel set of K~, n x (levels*kc), rows in tree order;
@@ -208,6 +251,33 @@ hm_status hm_loglik_grad_adjoint(hm_H* H, const double* theta_full, const double
  * what=11+j: leaf blocks of K~_j (real parameters), same shape.
  * dst: device buffer of sufficient size. */
 hm_status hm_export(hm_H* H, int what, double* dst);
+
+/* ----------------------------------------------------------------- stats ---
+ * Work counters and per-phase device time of one H handle since its creation or the
+ * last hm_stats_reset (the instrumentation of the measured path): the K-apply column
+ * counts are those of the handle's model (all its sketches and H handles); phase times
+ * are HIP-event times of the enqueued work of each phase on the model's stream (build:
+ * construction of K~ and K~_j; factor: factorisation and log-determinant; loglik: solve,
+ * quadratic forms and the forward-mode traces of the gradient; fisher: the Fisher
+ * terms; reverse: the adjoint sweep; solve: hm_solve).  hm_stats synchronises the
+ * stream and copies min(bytes, sizeof(hm_stats_t)) bytes to out (host). */
+typedef struct {
+  long long kapply_calls;
+  long long kapply_columns;        /* columns of K applied */
+  long long kapply_deriv_columns;  /* columns of dK/dkappa and dK/dalpha applied */
+  long long builds;                /* constructions of K~ */
+  long long deriv_builds;          /*   of which with the derivative matrices K~_j */
+  long long factors;
+  long long loglik_evals;
+  long long grad_evals;            /* forward-mode gradients */
+  long long reverse_sweeps;        /* reverse-mode (adjoint) gradients */
+  long long fisher_evals;
+  long long solve_rhs;             /* right-hand sides solved by hm_solve */
+  double ms_build, ms_factor, ms_loglik, ms_fisher, ms_reverse, ms_solve;
+  long long device_bytes;          /* device memory held by the H handle */
+} hm_stats_t;
+hm_status hm_stats(hm_H* H, void* out, size_t bytes);
+hm_status hm_stats_reset(hm_H* H);
 
 /* ------------------------------------------------------------- profiling ---
  * Roofline instrumentation.  hm_profile_enable(m, family) brackets every later

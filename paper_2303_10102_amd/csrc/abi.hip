@@ -19,6 +19,18 @@ static thread_local std::string g_err;
 void set_error(const std::string& msg) { g_err = msg; }
 const char* get_error() { return g_err.c_str(); }
 
+void* dev_alloc(const Ctx* c, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 8);
+  if (c && c->alloc) return c->alloc(c->uctx, bytes);
+  void* p = nullptr;
+  return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+void dev_free(const Ctx* c, void* p) {
+  if (!p) return;
+  if (c && c->release) c->release(c->uctx, p);
+  else (void)hipFree(p);
+}
+
 constexpr int NSCAL = 512;
 
 // One likelihood iteration's state.  All device memory is allocated in hm_H_create.
@@ -32,6 +44,8 @@ struct HState {
   int realpos[4] = {-1, -1, -1, -1};  // free position -> real derivative slot
   double theta[4] = {0, 0, 0, 0};
   int state = 0;               // 0 empty, 1 built, 2 factored, 3 parameters prepared
+  long long gen = 0;           // incremented by every construction
+  long long z_gen = -1;        // construction that z = K~^{-1} y belongs to
   bool have_deriv = false;     // K~_j of the real parameters built at theta (hm_build, not the adjoint)
   int precision = 0;           // 0 FP64; 1 mixed: FP32 MFMA panel products where the policy allows
   int kc = 0;
@@ -55,11 +69,74 @@ struct HState {
   double* h_scal = nullptr;
   int* h_flags = nullptr;      // pinned copy of the model's device flags
   std::vector<void*> allocs;
+  size_t dev_bytes = 0;        // device memory held (allocs)
+  // multi-column solve buffers (n x solve_w each): right-hand sides, solution, residual, correction
+  int solve_w = 0;
+  double* sb[4] = {nullptr, nullptr, nullptr, nullptr};
+  // per-phase timing (HIP events around each phase's enqueued work) and counters
+  struct Phase {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    hipEvent_t open = nullptr;
+    double ms = 0.0;
+  } ph[6];
+  std::vector<hipEvent_t> ev_free;
+  long long builds = 0, deriv_builds = 0, factors = 0, loglik_evals = 0, grad_evals = 0, fisher_evals = 0,
+            reverse_sweeps = 0, solve_rhs = 0;
 };
 
+enum : int { PH_BUILD = 0, PH_FACTOR = 1, PH_LOGLIK = 2, PH_FISHER = 3, PH_REVERSE = 4, PH_SOLVE = 5, NPH = 6 };
+
+static hipEvent_t ev_get(HState* h) {
+  if (!h->ev_free.empty()) {
+    hipEvent_t e = h->ev_free.back();
+    h->ev_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+// accumulate the finished pairs of every phase (wait: block until each has finished)
+static void phase_drain(HState* h, bool wait) {
+  for (auto& p : h->ph) {
+    size_t keep = 0;
+    for (size_t i = 0; i < p.pending.size(); ++i) {
+      auto pr = p.pending[i];
+      if (wait) (void)hipEventSynchronize(pr.second);
+      float e = 0.0f;
+      if (hipEventQuery(pr.second) == hipSuccess && hipEventElapsedTime(&e, pr.first, pr.second) == hipSuccess) {
+        p.ms += e;
+        h->ev_free.push_back(pr.first);
+        h->ev_free.push_back(pr.second);
+      } else {
+        p.pending[keep++] = pr;
+      }
+    }
+    p.pending.resize(keep);
+  }
+}
+static void phase_begin(HState* h, int ph) {
+  auto& p = h->ph[ph];
+  if (p.pending.size() >= 64) phase_drain(h, true);
+  p.open = ev_get(h);
+  if (p.open) (void)hipEventRecord(p.open, h->m->stream);
+}
+static void phase_end(HState* h, int ph) {
+  auto& p = h->ph[ph];
+  if (!p.open) return;
+  hipEvent_t b = ev_get(h);
+  if (b && hipEventRecord(b, h->m->stream) == hipSuccess) {
+    p.pending.emplace_back(p.open, b);
+  } else {
+    h->ev_free.push_back(p.open);
+    if (b) h->ev_free.push_back(b);
+  }
+  p.open = nullptr;
+}
+
 static hm_status dalloc(HState* h, double** p, size_t doubles) {
-  void* q = nullptr;
-  if (hipMalloc(&q, std::max<size_t>(doubles, 1) * sizeof(double)) != hipSuccess) {
+  void* q = dev_alloc(h->m->ctx, std::max<size_t>(doubles, 1) * sizeof(double));
+  h->dev_bytes += std::max<size_t>(doubles, 1) * sizeof(double);
+  if (!q) {
     set_error("device allocation of " + std::to_string(doubles * 8) + " bytes failed");
     return HM_E_NOMEM;
   }
@@ -112,6 +189,16 @@ __global__ void k_add(double* y, const double* x, int n) {
   if (t < n) y[t] += x[t];
 }
 
+// the same for c columns (leading dimensions ldi, ldo)
+__global__ void k_permute_cols(const double* in, long ldi, double* out, long ldo, const int* perm, int n, int c,
+                               int to_tree) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * c) return;
+  const int t = (int)(e % n), j = (int)(e / n);
+  if (to_tree) out[t + j * ldo] = in[perm[t] + j * ldi];
+  else out[perm[t] + j * ldo] = in[t + j * ldi];
+}
+
 static hm_status permute(Model* m, const double* in, double* out, int to_tree) {
   hipLaunchKernelGGL(k_permute, dim3(ceil_div(m->n, 256)), dim3(256), 0, m->stream, in, out, m->d_perm, m->n,
                      to_tree);
@@ -119,22 +206,25 @@ static hm_status permute(Model* m, const double* in, double* out, int to_tree) {
   return HM_OK;
 }
 
-// z = K~^{-1} ytree with refinement steps against the FP64 H-matvec residual
-// (one step; two when the solve sweep runs with FP32 panels)
-static hm_status solve_refined(HState* h) {
+// z = K~^{-1} y (w columns of ld n, tree order) with refinement steps against the
+// FP64 H-matvec residual (one step; two when the solve sweep runs with FP32 panels);
+// r, v: n x w scratch.
+static hm_status solve_refined_w(HState* h, const double* y, double* z, double* r, double* v, int w) {
   Model* m = h->m;
   const int n = m->n;
-  HM_CHECK(hsolve(h->f, h->ytree, h->z));
+  const long cnt = (long)n * w;
+  HM_CHECK(hsolve(h->f, y, z, w));
   const int steps = m->mixed ? 2 : 1;
   for (int it = 0; it < steps; ++it) {
-    HM_HIP(hipMemcpyAsync(h->r, h->ytree, n * sizeof(double), hipMemcpyDeviceToDevice, m->stream));
-    HM_CHECK(hmatvec(h->f, h->D, h->ps.F, nullptr, h->z, 1, h->r, -1.0, 1.0));   // r = y - K~ z (FP64)
-    HM_CHECK(hsolve(h->f, h->r, h->v));
-    hipLaunchKernelGGL(k_add, dim3(ceil_div(n, 256)), dim3(256), 0, m->stream, h->z, h->v, n);
+    HM_HIP(hipMemcpyAsync(r, y, cnt * sizeof(double), hipMemcpyDeviceToDevice, m->stream));
+    HM_CHECK(hmatvec(h->f, h->D, h->ps.F, nullptr, z, w, r, -1.0, 1.0));   // r = y - K~ z (FP64)
+    HM_CHECK(hsolve(h->f, r, v, w));
+    hipLaunchKernelGGL(k_add, dim3(ceil_div(cnt, 256)), dim3(256), 0, m->stream, z, v, (int)cnt);
     HM_LAUNCH_CHECK();
   }
   return HM_OK;
 }
+static hm_status solve_refined(HState* h) { return solve_refined_w(h, h->ytree, h->z, h->r, h->v, 1); }
 
 // scalar slots in d_scal
 enum : int { SC_LOGDET = 0, SC_YZ = 1, SC_QUAD = 2, SC_LTR = 6, SC_NTR = 10, SC_FIM = 16, SC_ADJ = 110 };
@@ -214,23 +304,31 @@ static hm_status build_enqueue(HState* h, const double* theta_full, bool deriv) 
   HM_CHECK(clear_flags(m));
   const int n = m->n, kc = h->kc;
   const int nr = deriv ? h->nreal : 0;
+  phase_begin(h, PH_BUILD);
   for (int l = 1; l <= m->levels; ++l) {
     const double* XR = h->s->d_XR + (size_t)(l - 1) * kc * n;
     HM_CHECK(level_step(m, h->theta, h->ps, l, XR, kc, h->s->d_k, nr, h->realidx, h->lb, h->nb));
   }
   HM_CHECK(leaf_pass(m, h->theta, h->ps, nr, h->realidx, h->lb, h->nb, h->D, deriv ? h->dDr : nullptr));
+  phase_end(h, PH_BUILD);
+  h->builds += 1;
+  h->deriv_builds += (deriv && h->nreal > 0) ? 1 : 0;
   h->state = 1;
   h->have_deriv = deriv;
+  ++h->gen;
   return HM_OK;
 }
 
 static hm_status factor_enqueue(HState* h) {
   h->m->mixed = h->precision;
   Model* m = h->m;
+  phase_begin(h, PH_FACTOR);
   HM_CHECK(factorize(h->f));
   // log|K~| = sum of leaf and node parts
   HM_CHECK(sum_scalar(m, h->f.logdet_leaf, m->nleaves, 0, h->d_scal + 100, h->d_part));
   HM_CHECK(sum_scalar(m, h->f.logdet_node, (1 << m->levels) - 1, 0, h->d_scal + 101, h->d_part));
+  phase_end(h, PH_FACTOR);
+  h->factors += 1;
   h->state = 2;
   return HM_OK;
 }
@@ -239,12 +337,19 @@ static hm_status loglik_enqueue(HState* h, const double* y, bool want_grad) {
   h->m->mixed = h->precision;
   Model* m = h->m;
   const int n = m->n;
+  phase_begin(h, PH_LOGLIK);
+  h->loglik_evals += 1;
   HM_CHECK(permute(m, y, h->ytree, 1));
   HM_CHECK(solve_refined(h));
   const double* yv[1] = {h->ytree};
   const double* zv[1] = {h->z};
   HM_CHECK(dots(m, yv, 1, zv, 1, n, h->d_scal + SC_YZ, h->d_part));
-  if (!want_grad || h->p == 0) return HM_OK;
+  h->z_gen = h->gen;
+  if (!want_grad || h->p == 0) {
+    phase_end(h, PH_LOGLIK);
+    return HM_OK;
+  }
+  h->grad_evals += 1;
   HM_CHECK(prepare_params(h));
   for (int q = 0; q < h->p; ++q) {
     ParamBufs& pb = h->pb[q];
@@ -262,6 +367,7 @@ static hm_status loglik_enqueue(HState* h, const double* y, bool want_grad) {
   const double* pv[4];
   for (int q = 0; q < h->p; ++q) pv[q] = h->pb[q].PsiP;
   HM_CHECK(dots(m, nv, 1, pv, h->p, ((1L << m->levels) - 1) * ms, h->d_scal + SC_NTR, h->d_part));
+  phase_end(h, PH_LOGLIK);
   return HM_OK;
 }
 
@@ -287,6 +393,8 @@ static hm_status fisher_enqueue(HState* h) {
   h->m->mixed = h->precision;
   Model* m = h->m;
   const int p = h->p;
+  phase_begin(h, PH_FISHER);
+  h->fisher_evals += 1;
   HM_CHECK(prepare_params(h));
   // tau2 before sigma2: sigma2's tangent sweep is a combination of tau2's
   int qt = -1;
@@ -326,6 +434,7 @@ static hm_status fisher_enqueue(HState* h) {
   // term 4: <Vt^i, E^j> over non-root nodes
   for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Vt + s2; B[q] = h->pb[q].E + s2; }
   HM_CHECK(dots(m, A, p, B, p, (nodes - 1) * s2, out + 4 * 16, h->d_part));
+  phase_end(h, PH_FISHER);
   return HM_OK;
 }
 
@@ -358,6 +467,7 @@ static hm_status iteration_enqueue(HState* h, const double* theta_full, const do
 
 static hm_status iteration_collect(HState* h, double* loglik, double* grad, double* fim) {
   HM_CHECK(sync_check(h, true));
+  phase_drain(h, false);
   HM_CHECK(loglik_collect(h, loglik, grad));
   if (fim && h->p > 0) HM_CHECK(fisher_collect(h, fim));
   return HM_OK;
@@ -367,6 +477,9 @@ static hm_status iteration_collect(HState* h, double* loglik, double* grad, doub
 
 using namespace hm;
 
+struct hm_ctx {
+  Ctx c;
+};
 struct hm_sketch {
   Sketch s;
 };
@@ -378,7 +491,9 @@ extern "C" {
 
 const char* hm_last_error(void) { return get_error(); }
 
-hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm_model** out) {
+// A model on an N (x N) Dirichlet grid with spacing h, its device memory from ctx.
+static hm_status model_create(Ctx* ctx, int device, void* stream, int dim, int N, double h, int leaf,
+                              hm_model** out) {
   if (!out) {
     set_error("out is NULL");
     return HM_E_INVAL;
@@ -386,6 +501,10 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
   *out = nullptr;
   if ((dim != 1 && dim != 2) || N < 2 || leaf < 1) {
     set_error("need dim in {1,2}, N >= 2, leaf >= 1");
+    return HM_E_INVAL;
+  }
+  if (!(h > 0.0) || !std::isfinite(h)) {
+    set_error("the grid spacing h must be positive and finite");
     return HM_E_INVAL;
   }
   const long n = (dim == 2) ? (long)N * N : N;
@@ -417,6 +536,9 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
   }
   hm_model* hm_ = new hm_model();
   Model* m = &hm_->m;
+  m->own_ctx.device = device;
+  m->own_ctx.stream = (hipStream_t)stream;
+  m->ctx = ctx ? ctx : &m->own_ctx;
   m->device = device;
   m->stream = (hipStream_t)stream;
   m->dim = dim;
@@ -425,10 +547,13 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
   m->levels = levels;
   m->nleaves = 1 << levels;
   m->nl = (int)(n >> levels);
-  m->h = 1.0 / (N + 1);
+  m->h = h;
   m->cmax = std::max(m->nl, 80);
   bool ok = true;
-  auto A = [&](void** p, size_t bytes) { ok = ok && hipMalloc(p, std::max<size_t>(bytes, 8)) == hipSuccess; };
+  auto A = [&](void** p, size_t bytes) {
+    *p = dev_alloc(m->ctx, bytes);
+    ok = ok && *p;
+  };
   A((void**)&m->d_perm, n * sizeof(int));
   A((void**)&m->d_iperm, n * sizeof(int));
   A((void**)&m->d_mu, (size_t)N * sizeof(double));
@@ -439,7 +564,7 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
   A((void**)&m->d_flags, sizeof(int));
   A((void**)&m->d_ident, (size_t)n * m->nl * sizeof(double));
   if (!ok) {
-    set_error("device allocation failed in hm_model_create");
+    set_error("device allocation failed in model creation");
     hm_model_destroy(hm_);
     return HM_E_NOMEM;
   }
@@ -447,7 +572,7 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
   if (st == HM_OK) st = make_identity_stack(m);
   if (st == HM_OK) st = clear_flags(m);
   if (st == HM_OK && hipStreamSynchronize(m->stream) != hipSuccess) {
-    set_error("hm_model_create: device error");
+    set_error("model creation: device error");
     st = HM_E_DEVICE;
   }
   if (st != HM_OK) {
@@ -458,13 +583,71 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
   return HM_OK;
 }
 
+hm_status hm_ctx_create(int device, void* stream, hm_alloc_fn alloc, hm_free_fn release, void* uctx,
+                        hm_ctx** out) {
+  if (!out) {
+    set_error("out is NULL");
+    return HM_E_INVAL;
+  }
+  *out = nullptr;
+  if ((alloc == nullptr) != (release == nullptr)) {
+    set_error("hm_ctx_create: give both allocator callbacks or neither");
+    return HM_E_INVAL;
+  }
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+    set_error("hm_ctx_create: no such device");
+    return HM_E_INVAL;
+  }
+  hm_ctx* c = new hm_ctx();
+  c->c.device = device;
+  c->c.stream = (hipStream_t)stream;
+  c->c.alloc = alloc;
+  c->c.release = release;
+  c->c.uctx = uctx;
+  *out = c;
+  return HM_OK;
+}
+
+void hm_ctx_destroy(hm_ctx* c) { delete c; }
+
+hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm_model** out) {
+  return model_create(nullptr, device, stream, dim, N, 1.0 / (N + 1), leaf, out);
+}
+
+hm_status hm_model_create_spde(hm_ctx* ctx, int dim, int nx, int ny, double h, int nvars, const int* obs_idx,
+                               long long nobs, int leaf, hm_model** out) {
+  if (!ctx || !out) {
+    set_error("NULL argument");
+    return HM_E_INVAL;
+  }
+  *out = nullptr;
+  if (dim == 1 && ny != 1) {
+    set_error("hm_model_create_spde: a one-dimensional grid has ny = 1");
+    return HM_E_INVAL;
+  }
+  if (dim == 2 && nx != ny) {
+    set_error("hm_model_create_spde: grids with nx != ny are not supported");
+    return HM_E_INVAL;
+  }
+  if (nvars != 1) {
+    set_error("hm_model_create_spde: only nvars = 1 is supported");
+    return HM_E_INVAL;
+  }
+  if (obs_idx != nullptr || nobs != 0) {
+    set_error("hm_model_create_spde: observation selections are not supported");
+    return HM_E_INVAL;
+  }
+  return model_create(&ctx->c, ctx->c.device, ctx->c.stream, dim, nx, h, leaf, out);
+}
+
 void hm_model_destroy(hm_model* mm) {
   if (!mm) return;
   Model* m = &mm->m;
+  (void)hipStreamSynchronize(m->stream);
   for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
   void* ps[] = {m->d_perm, m->d_iperm, m->d_dst, m->d_dsth, m->d_mu, m->d_lam, m->d_ws, m->d_flags, m->d_ident, m->d_red};
-  for (void* p : ps)
-    if (p) (void)hipFree(p);
+  for (void* p : ps) dev_free(m->ctx, p);
   delete mm;
 }
 
@@ -579,7 +762,8 @@ hm_status hm_sketch_create_tol(hm_model* mm, const double* omega, int rank, int 
   s->oversample = oversample;
   s->ell = rank + oversample;
   const int nint = (1 << m->levels) - 1;
-  if (hipMalloc(&s->d_k, nint * sizeof(int)) != hipSuccess) {
+  s->d_k = (int*)dev_alloc(m->ctx, nint * sizeof(int));
+  if (!s->d_k) {
     delete hs;
     set_error("device allocation failed");
     return HM_E_NOMEM;
@@ -596,8 +780,9 @@ hm_status hm_sketch_create_tol(hm_model* mm, const double* omega, int rank, int 
 
 void hm_sketch_destroy(hm_sketch* hs) {
   if (!hs) return;
-  if (hs->s.d_XR) (void)hipFree(hs->s.d_XR);
-  if (hs->s.d_k) (void)hipFree(hs->s.d_k);
+  (void)hipStreamSynchronize(hs->s.m->stream);
+  dev_free(hs->s.m->ctx, hs->s.d_XR);
+  dev_free(hs->s.m->ctx, hs->s.d_k);
   delete hs;
 }
 
@@ -613,9 +798,18 @@ hm_status hm_sketch_ranks(const hm_sketch* hs, int* k_host, int* kc) {
 
 void hm_H_destroy(hm_H* hh) {
   if (!hh) return;
-  for (void* p : hh->h.allocs) (void)hipFree(p);
+  if (hh->h.m) (void)hipStreamSynchronize(hh->h.m->stream);
+  for (void* p : hh->h.allocs) dev_free(hh->h.m->ctx, p);
   if (hh->h.h_scal) (void)hipHostFree(hh->h.h_scal);
   if (hh->h.h_flags) (void)hipHostFree(hh->h.h_flags);
+  for (auto& p : hh->h.ph) {
+    for (auto& pr : p.pending) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+    if (p.open) (void)hipEventDestroy(p.open);
+  }
+  for (hipEvent_t e : hh->h.ev_free) (void)hipEventDestroy(e);
   delete hh;
 }
 
@@ -752,6 +946,8 @@ hm_status hm_H_create(hm_sketch* hs, int p, const int* free_idx, hm_H** out) {
   AL(h->v, (size_t)n);
   AL(h->d_scal, (size_t)NSCAL);
   AL(h->d_part, (size_t)1024 * 16);
+  h->solve_w = std::min(16, solve_max_cols(h->f));
+  for (int q = 0; q < 4; ++q) AL(h->sb[q], (size_t)n * h->solve_w);
 #undef AL
   if (st == HM_OK && (hipHostMalloc((void**)&h->h_scal, NSCAL * sizeof(double), hipHostMallocDefault) != hipSuccess ||
                       hipHostMalloc((void**)&h->h_flags, sizeof(int), hipHostMallocDefault) != hipSuccess)) {
@@ -794,6 +990,7 @@ hm_status hm_factor(hm_H* hh) {
   HM_CHECK(factor_enqueue(h));
   HM_CHECK(fetch_scalars(h, 0, 128));
   HM_CHECK(sync_check(h, true));
+  phase_drain(h, false);
   return HM_OK;
 }
 
@@ -813,21 +1010,37 @@ hm_status hm_logdet(hm_H* hh, double* out) {
   return HM_OK;
 }
 
-hm_status hm_solve(hm_H* hh, const double* y, double* x) {
-  if (!hh || !y || !x) {
+hm_status hm_solve(hm_H* hh, const double* y, double* x, long long nrhs, long long ld) {
+  if (!hh || (nrhs > 0 && (!y || !x))) {
     set_error("NULL argument");
     return HM_E_INVAL;
   }
   HState* h = &hh->h;
+  Model* m = h->m;
+  if (nrhs < 0 || (nrhs > 0 && ld < m->n)) {
+    set_error("hm_solve: need nrhs >= 0 and ld >= n");
+    return HM_E_INVAL;
+  }
   if (h->state < 2) {
     set_error("hm_solve before hm_factor");
     return HM_E_STATE;
   }
-  Model* m = h->m;
   m->mixed = h->precision;
-  HM_CHECK(permute(m, y, h->ytree, 1));
-  HM_CHECK(solve_refined(h));
-  HM_CHECK(permute(m, h->z, x, 0));
+  const int n = m->n;
+  phase_begin(h, PH_SOLVE);
+  for (long long c0 = 0; c0 < nrhs; c0 += h->solve_w) {
+    const int w = (int)std::min<long long>(h->solve_w, nrhs - c0);
+    const long cnt = (long)n * w;
+    hipLaunchKernelGGL(k_permute_cols, dim3(ceil_div(cnt, 256)), dim3(256), 0, m->stream, y + c0 * ld, (long)ld,
+                       h->sb[0], (long)n, m->d_perm, n, w, 1);
+    HM_LAUNCH_CHECK();
+    HM_CHECK(solve_refined_w(h, h->sb[0], h->sb[1], h->sb[2], h->sb[3], w));
+    hipLaunchKernelGGL(k_permute_cols, dim3(ceil_div(cnt, 256)), dim3(256), 0, m->stream, h->sb[1], (long)n,
+                       x + c0 * ld, (long)ld, m->d_perm, n, w, 0);
+    HM_LAUNCH_CHECK();
+  }
+  phase_end(h, PH_SOLVE);
+  h->solve_rhs += nrhs;
   return HM_OK;
 }
 
@@ -845,6 +1058,7 @@ hm_status hm_loglik_grad(hm_H* hh, const double* y, double* loglik, double* grad
   HM_CHECK(loglik_enqueue(h, y, grad != nullptr));
   HM_CHECK(fetch_scalars(h, 0, 128));
   HM_HIP(hipStreamSynchronize(h->m->stream));
+  phase_drain(h, false);
   return loglik_collect(h, loglik, grad);
 }
 
@@ -863,6 +1077,7 @@ hm_status hm_fisher(hm_H* hh, double* fim) {
   HM_CHECK(fisher_enqueue(h));
   HM_CHECK(fetch_scalars(h, 0, 128));
   HM_HIP(hipStreamSynchronize(h->m->stream));
+  phase_drain(h, false);
   return fisher_collect(h, fim);
 }
 
@@ -932,56 +1147,116 @@ hm_status hm_H_set_precision(hm_H* hh, int precision) {
   return HM_OK;
 }
 
-hm_status hm_loglik_grad_adjoint(hm_H* hh, const double* theta_full, const double* y, double* loglik,
-                                 double* grad) {
+hm_status hm_loglik(hm_H* hh, const double* theta_full, const double* y, double* loglik) {
   if (!hh || !y || !loglik) {
     set_error("NULL argument");
     return HM_E_INVAL;
   }
   HState* h = &hh->h;
-  Model* m = h->m;
-  const int n = m->n;
-  // K~ only: the reverse sweep needs no derivative matrices
+  // K~ only: neither L~ nor the reverse sweep needs the derivative matrices
   HM_CHECK(build_enqueue(h, theta_full, false));
   HM_CHECK(factor_enqueue(h));
-  HM_CHECK(permute(m, y, h->ytree, 1));
-  HM_CHECK(solve_refined(h));
-  const double* yv[1] = {h->ytree};
-  const double* zv[1] = {h->z};
-  HM_CHECK(dots(m, yv, 1, zv, 1, n, h->d_scal + SC_YZ, h->d_part));
-  if (grad && h->p > 0) {
-    HM_CHECK(node_prep(h->f));
-    HM_CHECK(adjoint_init(h->f, h->z, h->adj));
-    HM_CHECK(adjoint_sweep(m, h->theta, h->s, h->ps, h->lb, h->nb, h->adj));
-    const long NN = n;
-    const double* wv[1] = {h->adj.wmode};
-    const double* lv[3] = {m->d_lam, m->d_lam + NN, m->d_lam + 2 * NN};
-    HM_CHECK(dots(m, wv, 1, lv, 3, NN, h->d_scal + SC_ADJ, h->d_part));
-    HM_CHECK(sum_scalar(m, h->adj.wmode, NN, 0, h->d_scal + SC_ADJ + 3, h->d_part));
-  }
+  HM_CHECK(loglik_enqueue(h, y, false));
   HM_CHECK(fetch_scalars(h, 0, 128));
   HM_CHECK(sync_check(h, true));
-  const double logdet = h->h_scal[100] + h->h_scal[101];
-  *loglik = -0.5 * n * std::log(2.0 * M_PI) - 0.5 * logdet - 0.5 * h->h_scal[SC_YZ];
-  if (!std::isfinite(*loglik)) {
-    set_error("non-finite log-likelihood");
-    return HM_E_NONFINITE;
+  phase_drain(h, false);
+  return loglik_collect(h, loglik, nullptr);
+}
+
+hm_status hm_grad_reverse(hm_H* hh, double* grad) {
+  if (!hh || !grad) {
+    set_error("NULL argument");
+    return HM_E_INVAL;
   }
-  if (grad) {
-    // w-weighted mode sums: <w, lambda>, <w, dlambda/dkappa>, <w, dlambda/dalpha>, sum w
-    // (lambda: the physics part of the mode multiplier, sigma2 times the unit-scale one,
-    // so de/dsigma2 = lambda / sigma2; de/dtau2 = 1)
-    const double* t = h->h_scal + SC_ADJ;
-    const double sigma2 = h->theta[3];
-    const double tb[4] = {t[1], t[2], t[3], t[0] / sigma2};
-    for (int q = 0; q < h->p; ++q) {
-      grad[q] = tb[h->pidx[q]];
-      if (!std::isfinite(grad[q])) {
-        set_error("non-finite gradient");
-        return HM_E_NONFINITE;
-      }
+  HState* h = &hh->h;
+  Model* m = h->m;
+  if (h->state < 2 || h->z_gen != h->gen) {
+    set_error("hm_grad_reverse: needs the K~^{-1} y of the current factorisation (call hm_loglik first)");
+    return HM_E_STATE;
+  }
+  if (h->p == 0) return HM_OK;
+  m->mixed = h->precision;
+  phase_begin(h, PH_REVERSE);
+  h->reverse_sweeps += 1;
+  HM_CHECK(node_prep(h->f));
+  HM_CHECK(adjoint_init(h->f, h->z, h->adj));
+  HM_CHECK(adjoint_sweep(m, h->theta, h->s, h->ps, h->lb, h->nb, h->adj));
+  const long NN = m->n;
+  const double* wv[1] = {h->adj.wmode};
+  const double* lv[3] = {m->d_lam, m->d_lam + NN, m->d_lam + 2 * NN};
+  HM_CHECK(dots(m, wv, 1, lv, 3, NN, h->d_scal + SC_ADJ, h->d_part));
+  HM_CHECK(sum_scalar(m, h->adj.wmode, NN, 0, h->d_scal + SC_ADJ + 3, h->d_part));
+  phase_end(h, PH_REVERSE);
+  HM_CHECK(fetch_scalars(h, SC_ADJ, 4));
+  HM_CHECK(sync_check(h, true));
+  phase_drain(h, false);
+  // w-weighted mode sums: <w, lambda>, <w, dlambda/dkappa>, <w, dlambda/dalpha>, sum w
+  // (lambda: the physics part of the mode multiplier, sigma2 times the unit-scale one,
+  // so de/dsigma2 = lambda / sigma2; de/dtau2 = 1)
+  const double* t = h->h_scal + SC_ADJ;
+  const double sigma2 = h->theta[3];
+  const double tb[4] = {t[1], t[2], t[3], t[0] / sigma2};
+  for (int q = 0; q < h->p; ++q) {
+    grad[q] = tb[h->pidx[q]];
+    if (!std::isfinite(grad[q])) {
+      set_error("non-finite gradient");
+      return HM_E_NONFINITE;
     }
   }
+  return HM_OK;
+}
+
+hm_status hm_loglik_grad_adjoint(hm_H* hh, const double* theta_full, const double* y, double* loglik,
+                                 double* grad) {
+  HM_CHECK(hm_loglik(hh, theta_full, y, loglik));
+  if (grad) HM_CHECK(hm_grad_reverse(hh, grad));
+  return HM_OK;
+}
+
+hm_status hm_stats(hm_H* hh, void* out, size_t bytes) {
+  if (!hh || !out) {
+    set_error("NULL argument");
+    return HM_E_INVAL;
+  }
+  HState* h = &hh->h;
+  HM_HIP(hipStreamSynchronize(h->m->stream));
+  phase_drain(h, true);
+  hm_stats_t st{};
+  const ModelCounters& c = h->m->cnt;
+  st.kapply_calls = c.kapply_calls;
+  st.kapply_columns = c.kcols_value;
+  st.kapply_deriv_columns = c.kcols_deriv;
+  st.builds = h->builds;
+  st.deriv_builds = h->deriv_builds;
+  st.factors = h->factors;
+  st.loglik_evals = h->loglik_evals;
+  st.grad_evals = h->grad_evals;
+  st.reverse_sweeps = h->reverse_sweeps;
+  st.fisher_evals = h->fisher_evals;
+  st.solve_rhs = h->solve_rhs;
+  st.ms_build = h->ph[PH_BUILD].ms;
+  st.ms_factor = h->ph[PH_FACTOR].ms;
+  st.ms_loglik = h->ph[PH_LOGLIK].ms;
+  st.ms_fisher = h->ph[PH_FISHER].ms;
+  st.ms_reverse = h->ph[PH_REVERSE].ms;
+  st.ms_solve = h->ph[PH_SOLVE].ms;
+  st.device_bytes = (long long)h->dev_bytes;
+  std::memcpy(out, &st, std::min(bytes, sizeof(st)));
+  return HM_OK;
+}
+
+hm_status hm_stats_reset(hm_H* hh) {
+  if (!hh) {
+    set_error("H is NULL");
+    return HM_E_INVAL;
+  }
+  HState* h = &hh->h;
+  HM_HIP(hipStreamSynchronize(h->m->stream));
+  phase_drain(h, true);
+  for (auto& p : h->ph) p.ms = 0.0;
+  h->builds = h->deriv_builds = h->factors = h->loglik_evals = h->grad_evals = h->fisher_evals = 0;
+  h->reverse_sweeps = h->solve_rhs = 0;
+  h->m->cnt = ModelCounters{};
   return HM_OK;
 }
 

@@ -307,8 +307,8 @@ hm_status sketch_build(Sketch* s, const double* omega, const double theta0[4]) {
   std::vector<void*> allocs;
   bool alloc_failed = false;
   auto alloc = [&](size_t doubles) -> double* {
-    void* p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(doubles, 1) * sizeof(double)) != hipSuccess) {
+    void* p = dev_alloc(m->ctx, std::max<size_t>(doubles, 1) * sizeof(double));
+    if (!p) {
       alloc_failed = true;
       return nullptr;
     }
@@ -316,7 +316,7 @@ hm_status sketch_build(Sketch* s, const double* omega, const double theta0[4]) {
     return (double*)p;
   };
   auto cleanup = [&]() {
-    for (void* p : allocs) (void)hipFree(p);
+    for (void* p : allocs) dev_free(m->ctx, p);
   };
   PanelSet ps{};
   ps.bw = r;
@@ -392,9 +392,11 @@ hm_status sketch_build(Sketch* s, const double* omega, const double theta0[4]) {
     s->kc = kc;
   }
   if (st == HM_OK) {
-    void* p = nullptr;
-    if (hipMalloc(&p, (size_t)n * levels * s->kc * sizeof(double)) != hipSuccess) st = HM_E_NOMEM;
-    s->d_XR = (double*)p;
+    s->d_XR = (double*)dev_alloc(m->ctx, (size_t)n * levels * s->kc * sizeof(double));
+    if (!s->d_XR) {
+      set_error("sketch creation: device allocation failed");
+      st = HM_E_NOMEM;
+    }
   }
   if (st == HM_OK) st = fill(m, s->d_XR, (long)n * levels * s->kc, 0.0);
   for (int l = 1; l <= levels && st == HM_OK; ++l) {

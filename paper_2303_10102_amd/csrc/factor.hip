@@ -12,6 +12,7 @@
 // The G_c are formed bottom-up: G = Dbar^{-1} F on every panel, then each node
 // P (deepest first) applies its Woodbury factor to the panels of all its
 // ancestors restricted to P's rows (the basic factorisation of App. C).
+#include <algorithm>
 #include <cmath>
 
 #include "hm_build.h"
@@ -62,23 +63,30 @@ hm_status factorize(FactorCtx& f) {
   return HM_OK;
 }
 
-// z = K~^{-1} x (tree order, one column) by the Woodbury sweep.
-hm_status hsolve(FactorCtx& f, const double* x, double* z) {
+// z = K~^{-1} x (tree order, w columns of ld n; w <= solve_max_cols) by the Woodbury sweep.
+hm_status hsolve(FactorCtx& f, const double* x, double* z, int w) {
   Model* m = f.m;
   const int n = m->n, kc = f.kc, levels = m->levels;
-  HM_CHECK(leaf_gemm(m, f.Dinv, x, n, z, n, 1, 1.0, 0.0, 0, m->nleaves));
+  if (w < 1 || w > solve_max_cols(f)) {
+    set_error("hsolve: column count out of range");
+    return HM_E_INVAL;
+  }
+  HM_CHECK(leaf_gemm(m, f.Dinv, x, n, z, n, w, 1.0, 0.0, 0, m->nleaves));
   PrecScope prec(m);   // solve sweep: FP32 panels under the mixed policy (refined in FP64 by the caller)
-  const long ts = kc, us = 2L * kc;
+  const long ts = (long)kc * w, us = 2L * kc * w;
   for (int d = levels - 1; d >= 0; --d) {
-    ReduceJob r{f.F, n, cs_block(kc), z, n, cs_fixed(0, 1), d + 1, d + 1, f.nT, ts, sel_all()};
+    ReduceJob r{f.F, n, cs_block(kc), z, n, cs_fixed(0, w), d + 1, d + 1, f.nT, ts, sel_all()};
     HM_CHECK(tree_reduce(m, r));
-    HM_CHECK(node_apply_N(m, f.Nn, f.nT, ts, f.nU, us, kc, 1, d));
-    ExpandJob e{f.G, n, cs_block(kc), z, n, cs_fixed(0, 1), f.nU, us, 2 * kc, 2, kc, d + 1, d + 1, -1.0, 1.0,
+    HM_CHECK(node_apply_N(m, f.Nn, f.nT, ts, f.nU, us, kc, w, d));
+    ExpandJob e{f.G, n, cs_block(kc), z, n, cs_fixed(0, w), f.nU, us, 2 * kc, 2, kc, d + 1, d + 1, -1.0, 1.0,
                 sel_all()};
     HM_CHECK(tree_expand(m, e));
   }
   return HM_OK;
 }
+
+// the per-node buffers nT, nU hold kc x (levels - 1) kc blocks, i.e. that many columns
+int solve_max_cols(const FactorCtx& f) { return f.kc * std::max(1, f.m->levels - 1); }
 
 // y = alpha * B x + beta * y for a symmetric HODLR B with leaf blocks Dl and
 // off-diagonal blocks B[a,b] = P1_a P2_b^T + P2_a P1_b^T ... given as the two

@@ -41,7 +41,8 @@ struct FactorCtx {
 };
 
 hm_status factorize(FactorCtx& f);
-hm_status hsolve(FactorCtx& f, const double* x, double* z);
+hm_status hsolve(FactorCtx& f, const double* x, double* z, int w);
+int solve_max_cols(const FactorCtx& f);
 hm_status hmatvec(FactorCtx& f, const double* Dl, const double* Fp, const double* dFp, const double* x, int w,
                   double* y, double alpha, double beta);
 hm_status node_apply_N(Model* m, const double* Nn, const double* T, long ts, double* U, long us, int bw, int w,

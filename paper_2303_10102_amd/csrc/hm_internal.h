@@ -114,7 +114,30 @@ __device__ __forceinline__ TileIdx tile_block() {
   return TileIdx{l % nx, (l / nx) % ny, l / (nx * ny)};
 }
 
+// Device memory of a model and of its sketches and H handles comes from the
+// context's allocator callbacks (e.g. a caching allocator of the caller's framework);
+// without callbacks, hipMalloc / hipFree.
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hm_alloc_fn alloc = nullptr;
+  hm_free_fn release = nullptr;
+  void* uctx = nullptr;
+};
+void* dev_alloc(const Ctx* c, size_t bytes);
+void dev_free(const Ctx* c, void* p);
+
+// Counters of the work done through one model (read by hm_stats).
+struct ModelCounters {
+  long long kcols_value = 0;   // columns of K applied
+  long long kcols_deriv = 0;   // columns of dK/dkappa and dK/dalpha applied
+  long long kapply_calls = 0;
+};
+
 struct Model {
+  Ctx* ctx = nullptr;       // allocator and default stream (own_ctx unless the caller gave one)
+  Ctx own_ctx;
+  ModelCounters cnt;
   int device = 0;
   hipStream_t stream = nullptr;
   int dim = 2, N = 0, n = 0, levels = 0, nl = 0, nleaves = 0;

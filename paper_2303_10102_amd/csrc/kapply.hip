@@ -44,7 +44,7 @@ __global__ void k_perm(int* perm, int* iperm, int n, int N, int dim, int levels,
   iperm[g] = t;
 }
 
-__global__ void k_tables(double* S, double* mu, int N, int dim) {
+__global__ void k_tables(double* S, double* mu, int N, int dim, double h) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   const double scale = sqrt(2.0 / (N + 1));
   if (e < N * N) {
@@ -53,7 +53,6 @@ __global__ void k_tables(double* S, double* mu, int N, int dim) {
     S[e] = scale * sinpi((double)m / (double)(N + 1));
   }
   if (e < N) {
-    const double h = 1.0 / (N + 1);
     double s = sinpi((double)(e + 1) / (2.0 * (N + 1)));
     mu[e] = 4.0 / (h * h) * s * s;
   }
@@ -707,6 +706,9 @@ static hm_status kapply_core(Model* m, double* ws, int cblk, const double theta[
                              double* outK, int cK, double* outKap, int cKap, double* outAlp, int cAlp, int ldo,
                              LeafSel in_sel, LeafSel out_sel) {
   if (c <= 0) return HM_OK;
+  m->cnt.kapply_calls += 1;
+  m->cnt.kcols_value += outK ? cK : 0;
+  m->cnt.kcols_deriv += (outKap ? cKap : 0) + (outAlp ? cAlp : 0);
   if (cK > c || cKap > c || cAlp > c) {
     set_error("kapply: an output wants more columns than the input has");
     return HM_E_INVAL;
@@ -836,7 +838,7 @@ hm_status model_tables(Model* m) {
                      m->dim, m->levels, m->nl);
   HM_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_tables, dim3(ceil_div((long)N * N, 256)), dim3(256), 0, m->stream, m->d_dst, m->d_mu, N,
-                     m->dim);
+                     m->dim, m->h);
   HM_LAUNCH_CHECK();
   if (m->d_dsth) {
     hipLaunchKernelGGL(k_tables_half, dim3(ceil_div((long)N * N, 256)), dim3(256), 0, m->stream, m->d_dsth, N);

@@ -414,10 +414,15 @@ __global__ void __launch_bounds__(256) k_leaf_blocks(const double* P, int ldp, C
 
 hm_status ensure_reduce_ws(Model* m, size_t doubles) {
   if (doubles <= m->red_doubles) return HM_OK;
-  if (m->d_red) HM_HIP(hipFree(m->d_red));
+  // setup calls only; the old buffer may still be read by queued work
+  if (m->d_red) {
+    HM_HIP(hipStreamSynchronize(m->stream));
+    dev_free(m->ctx, m->d_red);
+  }
   m->d_red = nullptr;
   m->red_doubles = 0;
-  if (hipMalloc(&m->d_red, doubles * sizeof(double)) != hipSuccess) {
+  m->d_red = (double*)dev_alloc(m->ctx, doubles * sizeof(double));
+  if (!m->d_red) {
     set_error("tree_reduce workspace allocation failed");
     return HM_E_NOMEM;
   }

@@ -33,8 +33,8 @@ hm_status autotune(Model* m, int kc, double* report) {
   std::vector<void*> allocs;
   bool ok = true;
   auto alloc = [&](size_t doubles) -> double* {
-    void* p = nullptr;
-    if (hipMalloc(&p, doubles * sizeof(double)) != hipSuccess) {
+    void* p = dev_alloc(m->ctx, doubles * sizeof(double));
+    if (!p) {
       ok = false;
       return nullptr;
     }
@@ -50,7 +50,7 @@ hm_status autotune(Model* m, int kc, double* report) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ok) ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
   auto cleanup = [&]() {
-    for (void* p : allocs) (void)hipFree(p);
+    for (void* p : allocs) dev_free(m->ctx, p);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
   };

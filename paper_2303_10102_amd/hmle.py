@@ -34,7 +34,10 @@ _I = C.c_int
 
 _SIGS = {
     "hm_last_error": ([], C.c_char_p),
+    "hm_ctx_create": ([_I, _P, _P, _P, _P, C.POINTER(_P)], _I),
+    "hm_ctx_destroy": ([_P], None),
     "hm_model_create": ([_I, _P, _I, _I, _I, C.POINTER(_P)], _I),
+    "hm_model_create_spde": ([_P, _I, _I, _I, C.c_double, _I, C.POINTER(_I), C.c_longlong, _I, C.POINTER(_P)], _I),
     "hm_model_destroy": ([_P], None),
     "hm_model_info": ([_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)], _I),
     "hm_model_set_stream": ([_P, _P], _I),
@@ -52,13 +55,17 @@ _SIGS = {
     "hm_build": ([_P, _D], _I),
     "hm_factor": ([_P], _I),
     "hm_logdet": ([_P, _D], _I),
-    "hm_solve": ([_P, _P, _P], _I),
+    "hm_solve": ([_P, _P, _P, C.c_longlong, C.c_longlong], _I),
     "hm_loglik_grad": ([_P, _P, _D, _D], _I),
     "hm_fisher": ([_P, _D], _I),
     "hm_iteration": ([_P, _D, _P, _D, _D, _D], _I),
     "hm_H_set_precision": ([_P, _I], _I),
     "hm_iteration_batched": ([_I, C.POINTER(_P), _D, C.POINTER(_P), _D, _D, _D], _I),
     "hm_loglik_grad_adjoint": ([_P, _D, _P, _D, _D], _I),
+    "hm_loglik": ([_P, _D, _P, _D], _I),
+    "hm_grad_reverse": ([_P, _D], _I),
+    "hm_stats": ([_P, _P, C.c_size_t], _I),
+    "hm_stats_reset": ([_P], _I),
     "hm_export": ([_P, _I, _P], _I),
     "hm_profile_enable": ([_P, _I], _I),
     "hm_profile_read": ([_P, _D, C.POINTER(C.c_longlong), _D, _D], _I),
@@ -109,24 +116,86 @@ def _stream_handle(stream):
     return C.c_void_p(s.cuda_stream)
 
 
-class Model:
-    """SPDE stencil covariance model on a dim-D Dirichlet grid of side N."""
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
-    def __init__(self, dim, N, leaf, device=0, stream=None):
+
+class Context:
+    """hm_ctx: device, stream and the allocator of the library's device memory.
+
+    allocator="torch" hands every device buffer of the models, sketches and H handles
+    created with this context to torch's caching allocator (so torch.cuda.memory_allocated
+    accounts for them and the memory is reused by torch after release);
+    allocator="hip" lets the library call hipMalloc / hipFree itself.
+    """
+
+    def __init__(self, device=0, stream=None, allocator="torch"):
+        import torch
+        self.device = int(device)
+        self.stream_handle = int(_stream_handle(stream).value or 0)
+        self._cb = None
+        alloc = free = None
+        if allocator == "torch":
+            def _alloc(uctx, nbytes):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream_handle)
+                except Exception:          # out of memory: the library reports HM_E_NOMEM
+                    return None
+
+            def _free(uctx, ptr):
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+            self._cb = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+            alloc = C.cast(self._cb[0], C.c_void_p)
+            free = C.cast(self._cb[1], C.c_void_p)
+        elif allocator != "hip":
+            raise ValueError("allocator must be 'torch' or 'hip'")
+        h = _P()
+        _check("hm_ctx_create", lib().hm_ctx_create(self.device, C.c_void_p(self.stream_handle), alloc, free, None,
+                                                    C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hm_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Model:
+    """SPDE stencil covariance model on a dim-D Dirichlet grid of side N.
+
+    Device memory comes from a Context (by default one of its own backed by torch's
+    caching allocator); h is the grid spacing (default 1/(N+1), the unit square)."""
+
+    def __init__(self, dim, N, leaf, device=0, stream=None, ctx=None, h=None, allocator="torch"):
         import torch
         self.device = torch.device("cuda", device)
-        h = _P()
+        self.ctx = ctx if ctx is not None else Context(device, stream, allocator)
+        self._own_ctx = ctx is None
+        hh = _P()
+        spacing = 1.0 / (N + 1) if h is None else float(h)
         with torch.cuda.device(device):
-            _check("hm_model_create", lib().hm_model_create(device, _stream_handle(stream), dim, N, leaf, C.byref(h)))
-        self._h = h
+            _check("hm_model_create_spde",
+                   lib().hm_model_create_spde(self.ctx._h, dim, N, N if dim == 2 else 1, spacing, 1, None, 0, leaf,
+                                              C.byref(hh)))
+        self._h = hh
         n, lv, lf = _I(), _I(), _I()
-        _check("hm_model_info", lib().hm_model_info(h, C.byref(n), C.byref(lv), C.byref(lf)))
+        _check("hm_model_info", lib().hm_model_info(hh, C.byref(n), C.byref(lv), C.byref(lf)))
         self.dim, self.N, self.n, self.levels, self.leaf = dim, N, n.value, lv.value, lf.value
+        self.h = spacing
 
     def set_stream(self, stream):
         """Move the model's later work to another torch stream (None = current stream)."""
         _check("hm_model_set_stream", lib().hm_model_set_stream(self._h, _stream_handle(stream)))
         self.stream = stream
+        if self._own_ctx:      # later allocations are used on the new stream
+            self.ctx.stream_handle = int(_stream_handle(stream).value or 0)
 
     def autotune(self, kc):
         """Time the panel-kernel variants on this model's shapes and keep the fastest."""
@@ -176,6 +245,8 @@ class Model:
         if getattr(self, "_h", None):
             lib().hm_model_destroy(self._h)
             self._h = None
+        if getattr(self, "_own_ctx", False) and getattr(self, "ctx", None) is not None:
+            self.ctx.close()
 
     def __del__(self):
         try:
@@ -233,11 +304,13 @@ class HMatrix:
 
     def set_precision(self, precision):
         """'fp64' (default) or 'mixed32' (FP32 MFMA panel products under the FP64 policy)."""
+        self._eval_token = None   # the autograd function re-evaluates if needed
         code = {"fp64": 0, "mixed32": 1}[precision]
         _check("hm_H_set_precision", lib().hm_H_set_precision(self._h, code))
         self.precision = precision
 
     def build(self, theta_full):
+        self._eval_token = None   # the autograd function re-evaluates if needed
         _check("hm_build", lib().hm_build(self._h, _theta(theta_full)))
 
     def factor(self):
@@ -249,12 +322,15 @@ class HMatrix:
         return out.value
 
     def solve(self, y):
+        """K~^{-1} y for y of shape (n,) or (nrhs, n) (each row one right-hand side), grid order."""
         import torch
         x = torch.empty_like(y)
-        _check("hm_solve", lib().hm_solve(self._h, _ptr(y), _ptr(x)))
+        nrhs = 1 if y.dim() == 1 else y.shape[0]
+        _check("hm_solve", lib().hm_solve(self._h, _ptr(y), _ptr(x), nrhs, y.shape[-1]))
         return x
 
     def loglik_grad(self, y):
+        self._eval_token = None   # the autograd function re-evaluates if needed
         ll = C.c_double()
         g = (C.c_double * max(1, self.p))()
         _check("hm_loglik_grad", lib().hm_loglik_grad(self._h, _ptr(y), C.byref(ll), g))
@@ -266,6 +342,7 @@ class HMatrix:
         return np.array(f[:self.p * self.p]).reshape(self.p, self.p)
 
     def iteration(self, theta_full, y):
+        self._eval_token = None   # the autograd function re-evaluates if needed
         ll = C.c_double()
         g = (C.c_double * max(1, self.p))()
         f = (C.c_double * max(1, self.p * self.p))()
@@ -274,11 +351,34 @@ class HMatrix:
 
     def loglik_grad_adjoint(self, theta_full, y):
         """(L~, NLL gradient) by reverse mode through factorisation and construction."""
+        self._eval_token = None   # the autograd function re-evaluates if needed
         ll = C.c_double()
         g = (C.c_double * max(1, self.p))()
         _check("hm_loglik_grad_adjoint",
                lib().hm_loglik_grad_adjoint(self._h, _theta(theta_full), _ptr(y), C.byref(ll), g))
         return ll.value, np.array(g[:self.p])
+
+    def loglik(self, theta_full, y):
+        """L~ alone: K~ built without derivative matrices, factored; keeps K~^{-1} y."""
+        self._eval_token = None   # the autograd function re-evaluates if needed
+        ll = C.c_double()
+        _check("hm_loglik", lib().hm_loglik(self._h, _theta(theta_full), _ptr(y), C.byref(ll)))
+        return ll.value
+
+    def grad_reverse(self):
+        """NLL gradient by the reverse sweep for the last construction and sample."""
+        g = (C.c_double * max(1, self.p))()
+        _check("hm_grad_reverse", lib().hm_grad_reverse(self._h, g))
+        return np.array(g[:self.p])
+
+    def stats(self):
+        """Work counters and per-phase device milliseconds (hm_stats)."""
+        st = _Stats()
+        _check("hm_stats", lib().hm_stats(self._h, C.byref(st), C.sizeof(st)))
+        return {name: getattr(st, name) for name, _ in _Stats._fields_}
+
+    def stats_reset(self):
+        _check("hm_stats_reset", lib().hm_stats_reset(self._h))
 
     def export(self, what):
         import torch
@@ -302,6 +402,14 @@ class HMatrix:
             self.close()
         except Exception:
             pass
+
+
+class _Stats(C.Structure):
+    _fields_ = [(name, C.c_longlong) for name in (
+        "kapply_calls", "kapply_columns", "kapply_deriv_columns", "builds", "deriv_builds", "factors",
+        "loglik_evals", "grad_evals", "reverse_sweeps", "fisher_evals", "solve_rhs")] + \
+        [(name, C.c_double) for name in ("ms_build", "ms_factor", "ms_loglik", "ms_fisher", "ms_reverse",
+                                         "ms_solve")] + [("device_bytes", C.c_longlong)]
 
 
 def place_fields(cost, nstreams):
@@ -383,6 +491,8 @@ class Batch:
         g = (C.c_double * max(1, sum(ps))) () if want_grad else None
         fm = (C.c_double * max(1, sum(p * p for p in ps)))() if want_fim else None
         torch.cuda.current_stream(self.device).synchronize()   # samples written on the current stream
+        for H in self.Hs:
+            H._eval_token = None
         _check("hm_iteration_batched",
                lib().hm_iteration_batched(nf, hs, tho.ctypes.data_as(_D), yp, ll,
                                           g if want_grad else None, fm if want_fim else None))
@@ -462,8 +572,10 @@ def _make_loglik_function():
           theta      float64 CPU tensor of H's p free parameters, in H's order
           y          float64 CUDA tensor (n,), grid order
           theta_full the 4 parameters (kappa, alpha, tau2, sigma2) the others are taken from
-        Returns a 0-d float64 CPU tensor.  d/dtheta comes from hm_loglik_grad_adjoint,
-        d/dy = -K~^{-1} y from the same factorisation.
+        Returns a 0-d float64 CPU tensor.  forward builds and factors K~ only and
+        evaluates L~ (hm_loglik); backward runs the reverse sweep (hm_grad_reverse) for
+        d/dtheta and one solve for d/dy = -K~^{-1} y.  If H was evaluated elsewhere in
+        between, backward first re-evaluates L~ at the saved point.
         """
 
         @staticmethod
@@ -474,18 +586,23 @@ def _make_loglik_function():
                 raise ValueError(f"theta has {th.numel()} entries, H has {H.p} free parameters")
             for q, k in enumerate(H.free_idx):
                 full[k] = float(th[q])
-            ll, g = H.loglik_grad_adjoint(full, y.detach())
-            ctx.dtheta = torch.from_numpy(-g)
-            ctx.z = H.solve(y.detach()) if ctx.needs_input_grad[2] else None
+            yd = y.detach()
+            ll = H.loglik(full, yd)
+            ctx.H, ctx.full, ctx.y = H, full, yd
+            ctx.token = H._eval_token = object()
             return torch.tensor(ll, dtype=torch.float64)
 
         @staticmethod
         def backward(ctx, gout):
+            H = ctx.H
+            if getattr(H, "_eval_token", None) is not ctx.token:
+                H.loglik(ctx.full, ctx.y)
+                H._eval_token = ctx.token
             gt = gy = None
             if ctx.needs_input_grad[1]:
-                gt = gout.detach().cpu().double() * ctx.dtheta
+                gt = gout.detach().cpu().double() * torch.from_numpy(-H.grad_reverse())
             if ctx.needs_input_grad[2]:
-                gy = -gout.detach().to(ctx.z.device, torch.float64) * ctx.z
+                gy = -gout.detach().to(ctx.y.device, torch.float64) * H.solve(ctx.y)
             return None, gt, gy, None
 
     return HLogLik

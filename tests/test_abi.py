@@ -43,3 +43,22 @@ def test_errors_are_reported_without_a_device():
     assert b"dim" in L.hm_last_error()
     assert L.hm_model_create(0, None, 2, 15, 16, C.byref(out)) == 1    # odd side -> non-uniform tree
     assert L.hm_factor(None) == 1
+
+
+def test_context_and_model_arguments_are_checked_without_a_device():
+    from paper_2303_10102_amd import hmle
+    if not hmle.LIBPATH.exists():
+        pytest.skip("libhmle.so not built")
+    import ctypes as C
+    L = hmle.lib()
+    out = C.c_void_p()
+    cb = hmle._ALLOC_FN(lambda u, n: None)
+    # one allocator callback without the other
+    assert L.hm_ctx_create(0, None, C.cast(cb, C.c_void_p), None, None, C.byref(out)) == 1
+    assert b"both" in L.hm_last_error()
+    # a model needs a context
+    assert L.hm_model_create_spde(None, 2, 16, 16, 1.0 / 17, 1, None, 0, 16, C.byref(out)) == 1
+    # a solve needs a handle; statistics need a handle
+    assert L.hm_solve(None, None, None, 0, 0) == 1
+    assert L.hm_stats(None, None, 0) == 1
+    assert L.hm_grad_reverse(None, None) == 1
