@@ -77,8 +77,8 @@ void hm_ctx_destroy(hm_ctx* c);
  * (n = N for dim 1, N*N for dim 2; h = 1/(N+1), Dirichlet boundary).
  * leaf: target leaf size; levels = floor(log2(n/leaf)) (Sec. 5.2 rule).
  * The tree is the recursive coordinate bisection of the grid (Sec. 5.2, KD-tree
- * ordering): split the longer side (x on ties), left child gets floor(side/2).
- * The library requires every split to be even (uniform leaves): else HM_E_INVAL.
+ * ordering): split the longer side (x on ties), left child gets floor(side/2), so
+ * leaves may differ in size (Sec. 3.2: block sizes need not divide); see hm_model_rows.
  * device: HIP device ordinal; stream: hipStream_t to enqueue on (NULL = default).
  */
 hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm_model** out);
@@ -96,8 +96,15 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
 hm_status hm_model_create_spde(hm_ctx* ctx, int dim, int nx, int ny, double h, int nvars, const int* obs_idx,
                                long long nobs, int leaf, hm_model** out);
 void hm_model_destroy(hm_model* m);
-/* n, levels, leaf size (uniform). Any pointer may be NULL. */
+/* n (grid points), levels, leaf size of the stored layout (the largest leaf). Any pointer may be NULL. */
 hm_status hm_model_info(const hm_model* m, int* n, int* levels, int* leaf);
+/* Rows of the tree-ordered layout: 2^levels x leaf.  Equal to n when every bisection is
+ * even; with odd sides the leaves differ in size (the left child gets floor(side/2)) and
+ * each is stored padded to the largest: padding rows are zero in every tree-ordered
+ * vector, panel and sample the library writes, identity in the leaf blocks of K~ and
+ * zero in those of its derivatives, and are ignored on input.  hm_kapply's X, Y,
+ * hm_model_perm and hm_export use this row count. */
+hm_status hm_model_rows(const hm_model* m, int* rows);
 /* Move all later work of the model (and of its sketches and H handles) to another
  * stream; waits for the work already queued on the old one. */
 hm_status hm_model_set_stream(hm_model* m, void* stream);
@@ -118,12 +125,14 @@ hm_status hm_model_autotune(hm_model* m, int kc, double* report);
  * or 1..3 as above; reduce_split_below: workgroup count below which the reduce uses 4
  * wavefronts.  HM_E_INVAL for NULL pointers or values out of range. */
 hm_status hm_model_tuning(hm_model* m, int* expand_variant, long long* reduce_split_below, int set);
-/* Copy the tree->grid permutation (n ints, perm[tree_pos] = grid index) to a host buffer. */
+/* Copy the tree->grid permutation (rows ints, perm[tree_pos] = grid index, -1 on padding
+ * rows) to a host buffer. */
 hm_status hm_model_perm(const hm_model* m, int* perm_host);
 
 /* K-apply of the physics model (the only access to K the method uses, Sec. 3.2):
  * Y = op(theta) X with op = K (which=0), dK/dkappa (1), dK/dalpha (2).
- * X, Y: device, n x c column-major in TREE order with leading dimensions ldx, ldy >= n.
+ * X, Y: device, rows x c column-major in TREE order (hm_model_rows) with leading
+ * dimensions ldx, ldy >= rows; padding rows of X are ignored and those of Y set to zero.
  * Exact direct solves of the Dirichlet stencils (orthonormal sine transforms along x and y). */
 hm_status hm_kapply(hm_model* m, const double* theta_full, const double* X, int ldx, int c, double* Y,
                     int ldy, int which);

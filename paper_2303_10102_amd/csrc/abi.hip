@@ -178,11 +178,13 @@ static hm_status clear_flags(Model* m) {
 }
 
 // y_tree[t] = y_grid[perm[t]]  /  y_grid[perm[t]] = y_tree[t]
+// (padding rows: 0 in tree order, skipped in grid order)
 __global__ void k_permute(const double* in, double* out, const int* perm, int n, int to_tree) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  if (to_tree) out[t] = in[perm[t]];
-  else out[perm[t]] = in[t];
+  const int g = perm[t];
+  if (to_tree) out[t] = g >= 0 ? in[g] : 0.0;
+  else if (g >= 0) out[g] = in[t];
 }
 __global__ void k_add(double* y, const double* x, int n) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -195,8 +197,9 @@ __global__ void k_permute_cols(const double* in, long ldi, double* out, long ldo
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)n * c) return;
   const int t = (int)(e % n), j = (int)(e / n);
-  if (to_tree) out[t + j * ldo] = in[perm[t] + j * ldi];
-  else out[perm[t] + j * ldo] = in[t + j * ldi];
+  const int g = perm[t];
+  if (to_tree) out[t + j * ldo] = g >= 0 ? in[g + j * ldi] : 0.0;
+  else if (g >= 0) out[g + j * ldo] = in[t + j * ldi];
 }
 
 static hm_status permute(Model* m, const double* in, double* out, int to_tree) {
@@ -372,7 +375,7 @@ static hm_status loglik_enqueue(HState* h, const double* y, bool want_grad) {
 }
 
 static hm_status loglik_collect(HState* h, double* loglik, double* grad) {
-  const int n = h->m->n;
+  const int n = h->m->n_real;
   const double logdet = h->h_scal[100] + h->h_scal[101];
   const double yz = h->h_scal[SC_YZ];
   *loglik = -0.5 * n * std::log(2.0 * M_PI) - 0.5 * logdet - 0.5 * yz;
@@ -491,6 +494,31 @@ extern "C" {
 
 const char* hm_last_error(void) { return get_error(); }
 
+struct Rect {
+  int x0, y0, w, h;
+};
+// leaves of the recursive bisection of the N (x N) grid, left to right
+static std::vector<Rect> leaf_rects(int dim, int N, int levels) {
+  std::vector<Rect> r{{0, 0, N, dim == 2 ? N : 1}};
+  for (int d = 0; d < levels; ++d) {
+    std::vector<Rect> nx;
+    nx.reserve(r.size() * 2);
+    for (const Rect& q : r) {
+      if (q.w >= q.h) {
+        const int wl = q.w / 2;
+        nx.push_back({q.x0, q.y0, wl, q.h});
+        nx.push_back({q.x0 + wl, q.y0, q.w - wl, q.h});
+      } else {
+        const int hl = q.h / 2;
+        nx.push_back({q.x0, q.y0, q.w, hl});
+        nx.push_back({q.x0, q.y0 + hl, q.w, q.h - hl});
+      }
+    }
+    r.swap(nx);
+  }
+  return r;
+}
+
 // A model on an N (x N) Dirichlet grid with spacing h, its device memory from ctx.
 static hm_status model_create(Ctx* ctx, int device, void* stream, int dim, int N, double h, int leaf,
                               hm_model** out) {
@@ -517,18 +545,33 @@ static hm_status model_create(Ctx* ctx, int device, void* stream, int dim, int N
     set_error("need n >= 2*leaf");
     return HM_E_INVAL;
   }
-  // every bisection must split evenly (uniform leaves)
+  // The tree (Sec. 5.2, KD-tree ordering): recursive bisection of the grid rectangle,
+  // splitting the longer side (x on ties), the left child taking floor(side / 2) lines.
+  // If every split is even the leaves are equal and the tree position has a closed
+  // form; otherwise every leaf is stored padded to the largest (see Model).
+  std::vector<Rect> leaves = leaf_rects(dim, N, levels);
+  bool uniform = true;
   {
     long w = N, hh = (dim == 2) ? N : 1;
     for (int d = 0; d < levels; ++d) {
-      if (w >= hh) {
-        if (w % 2) { set_error("non-uniform bisection (odd side) is not supported"); return HM_E_INVAL; }
-        w /= 2;
-      } else {
-        if (hh % 2) { set_error("non-uniform bisection (odd side) is not supported"); return HM_E_INVAL; }
-        hh /= 2;
-      }
+      long& side = (w >= hh) ? w : hh;
+      uniform = uniform && side % 2 == 0;
+      side /= 2;
     }
+  }
+  int nlp = 0, nlmin = (int)n;
+  for (const Rect& r : leaves) {
+    nlp = std::max(nlp, r.w * r.h);
+    nlmin = std::min(nlmin, r.w * r.h);
+  }
+  if (nlmin < 1) {
+    set_error("the tree has an empty leaf: choose a larger leaf size");
+    return HM_E_INVAL;
+  }
+  const long rows = (long)nlp << levels;
+  if (rows > (1L << 27)) {
+    set_error("grid too large");
+    return HM_E_INVAL;
   }
   if (hipSetDevice(device) != hipSuccess) {
     set_error("hipSetDevice failed");
@@ -543,10 +586,13 @@ static hm_status model_create(Ctx* ctx, int device, void* stream, int dim, int N
   m->stream = (hipStream_t)stream;
   m->dim = dim;
   m->N = N;
-  m->n = (int)n;
+  m->n = (int)rows;
+  m->n_real = (int)n;
+  m->uniform = uniform;
   m->levels = levels;
   m->nleaves = 1 << levels;
-  m->nl = (int)(n >> levels);
+  m->nl = nlp;
+  m->nl_min = nlmin;
   m->h = h;
   m->cmax = std::max(m->nl, 80);
   bool ok = true;
@@ -554,21 +600,46 @@ static hm_status model_create(Ctx* ctx, int device, void* stream, int dim, int N
     *p = dev_alloc(m->ctx, bytes);
     ok = ok && *p;
   };
-  A((void**)&m->d_perm, n * sizeof(int));
+  A((void**)&m->d_perm, rows * sizeof(int));
   A((void**)&m->d_iperm, n * sizeof(int));
+  if (!uniform) A((void**)&m->d_pad2tree, rows * sizeof(int));
   A((void**)&m->d_mu, (size_t)N * sizeof(double));
   A((void**)&m->d_dst, (size_t)N * N * sizeof(double));
   if (N % 2 == 0) A((void**)&m->d_dsth, (size_t)N * N * sizeof(double));
-  A((void**)&m->d_lam, 3 * (size_t)n * sizeof(double));
-  A((void**)&m->d_ws, 5 * (size_t)n * m->cmax * sizeof(double));   // transform scratch (X, X^, 3 outputs)
+  A((void**)&m->d_lam, 3 * (size_t)rows * sizeof(double));
+  A((void**)&m->d_ws, 5 * (size_t)rows * m->cmax * sizeof(double));   // transform scratch (X, X^, 3 outputs)
   A((void**)&m->d_flags, sizeof(int));
-  A((void**)&m->d_ident, (size_t)n * m->nl * sizeof(double));
+  A((void**)&m->d_ident, (size_t)rows * m->nl * sizeof(double));
   if (!ok) {
     set_error("device allocation failed in model creation");
     hm_model_destroy(hm_);
     return HM_E_NOMEM;
   }
-  hm_status st = model_tables(m);
+  hm_status st = HM_OK;
+  if (!uniform) {
+    // tree tables on the host: leaves in order, points row-major inside a leaf
+    std::vector<int> perm(rows, -1), iperm(n, -1), pad2tree(rows, -1);
+    int real = 0;
+    for (int L = 0; L < (int)leaves.size(); ++L) {
+      const Rect& r = leaves[L];
+      int i = 0;
+      for (int yy = r.y0; yy < r.y0 + r.h; ++yy)
+        for (int xx = r.x0; xx < r.x0 + r.w; ++xx, ++i) {
+          const int g = (dim == 2) ? yy * N + xx : xx;
+          const int p = L * nlp + i;
+          perm[p] = g;
+          iperm[g] = p;
+          pad2tree[p] = real++;
+        }
+    }
+    if (hipMemcpy(m->d_perm, perm.data(), rows * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->d_iperm, iperm.data(), n * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->d_pad2tree, pad2tree.data(), rows * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("model creation: copy of the tree tables failed");
+      st = HM_E_DEVICE;
+    }
+  }
+  if (st == HM_OK) st = model_tables(m);
   if (st == HM_OK) st = make_identity_stack(m);
   if (st == HM_OK) st = clear_flags(m);
   if (st == HM_OK && hipStreamSynchronize(m->stream) != hipSuccess) {
@@ -646,7 +717,8 @@ void hm_model_destroy(hm_model* mm) {
   Model* m = &mm->m;
   (void)hipStreamSynchronize(m->stream);
   for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
-  void* ps[] = {m->d_perm, m->d_iperm, m->d_dst, m->d_dsth, m->d_mu, m->d_lam, m->d_ws, m->d_flags, m->d_ident, m->d_red};
+  void* ps[] = {m->d_perm, m->d_iperm, m->d_pad2tree, m->d_dst, m->d_dsth, m->d_mu, m->d_lam, m->d_ws, m->d_flags,
+                m->d_ident, m->d_red};
   for (void* p : ps) dev_free(m->ctx, p);
   delete mm;
 }
@@ -656,9 +728,18 @@ hm_status hm_model_info(const hm_model* mm, int* n, int* levels, int* leaf) {
     set_error("model is NULL");
     return HM_E_INVAL;
   }
-  if (n) *n = mm->m.n;
+  if (n) *n = mm->m.n_real;
   if (levels) *levels = mm->m.levels;
   if (leaf) *leaf = mm->m.nl;
+  return HM_OK;
+}
+
+hm_status hm_model_rows(const hm_model* mm, int* rows) {
+  if (!mm || !rows) {
+    set_error("NULL argument");
+    return HM_E_INVAL;
+  }
+  *rows = mm->m.n;
   return HM_OK;
 }
 
@@ -708,7 +789,7 @@ hm_status hm_model_perm(const hm_model* mm, int* perm_host) {
   }
   const Model* m = &mm->m;
   HM_HIP(hipStreamSynchronize(m->stream));
-  HM_HIP(hipMemcpy(perm_host, m->d_perm, m->n * sizeof(int), hipMemcpyDeviceToHost));
+  HM_HIP(hipMemcpy(perm_host, m->d_perm, m->n * sizeof(int), hipMemcpyDeviceToHost));   // rows entries
   return HM_OK;
 }
 
@@ -721,7 +802,7 @@ hm_status hm_kapply(hm_model* mm, const double* theta_full, const double* X, int
   Model* m = &mm->m;
   HM_CHECK(check_theta(theta_full));
   if (c < 0 || ldx < m->n || ldy < m->n || which < 0 || which > 2) {
-    set_error("hm_kapply: bad c, leading dimension or operator");
+    set_error("hm_kapply: bad c, leading dimension (rows of the tree layout) or operator");
     return HM_E_INVAL;
   }
   return kapply(m, theta_full, X, ldx, c, which == 0 ? Y : nullptr, which == 1 ? Y : nullptr,
@@ -750,8 +831,8 @@ hm_status hm_sketch_create_tol(hm_model* mm, const double* omega, int rank, int 
     return HM_E_INVAL;
   }
   Model* m = &mm->m;
-  if (rank + oversample > (m->n >> m->levels)) {
-    set_error("rank + oversample exceeds the leaf size");
+  if (rank + oversample > m->nl_min) {
+    set_error("rank + oversample exceeds the smallest leaf size");
     return HM_E_INVAL;
   }
   hm_sketch* hs = new hm_sketch();
@@ -891,9 +972,10 @@ hm_status hm_H_create(hm_sketch* hs, int p, const int* free_idx, hm_H** out) {
       AL(pb.dF, pset);
       AL(pb.dD, lset);
     }
-    if (pb.kind == 2) {          // Xi = G, Y = Dinv, Psi = G^T G
+    if (pb.kind == 2) {          // Xi = G, Y = Dinv (restricted to the real rows), Psi = G^T G
       pb.Xi = f.G;
-      pb.Y = f.Dinv;
+      if (m->uniform) pb.Y = f.Dinv;
+      else AL(pb.Y, lset);
       pb.Psi = h->GtG;
     } else {
       AL(pb.Xi, pset);
@@ -1017,7 +1099,7 @@ hm_status hm_solve(hm_H* hh, const double* y, double* x, long long nrhs, long lo
   }
   HState* h = &hh->h;
   Model* m = h->m;
-  if (nrhs < 0 || (nrhs > 0 && ld < m->n)) {
+  if (nrhs < 0 || (nrhs > 0 && ld < m->n_real)) {
     set_error("hm_solve: need nrhs >= 0 and ld >= n");
     return HM_E_INVAL;
   }
@@ -1181,7 +1263,7 @@ hm_status hm_grad_reverse(hm_H* hh, double* grad) {
   HM_CHECK(node_prep(h->f));
   HM_CHECK(adjoint_init(h->f, h->z, h->adj));
   HM_CHECK(adjoint_sweep(m, h->theta, h->s, h->ps, h->lb, h->nb, h->adj));
-  const long NN = m->n;
+  const long NN = (long)m->N * (m->dim == 2 ? m->N : 1);   // modes of the transforms
   const double* wv[1] = {h->adj.wmode};
   const double* lv[3] = {m->d_lam, m->d_lam + NN, m->d_lam + 2 * NN};
   HM_CHECK(dots(m, wv, 1, lv, 3, NN, h->d_scal + SC_ADJ, h->d_part));

@@ -93,17 +93,37 @@ __global__ void k_merge_lr(MergeJobs jb, int ldo, int n, int w, int l, int level
   out[i + (long)c * ldo] = v;
 }
 
-__global__ void k_ident(double* S, int n, int nl) {
+// stacked identities: S[i, j] = 1 where row i is local row j of its leaf (not padding)
+__global__ void k_ident(double* S, int n, int nl, const int* perm) {
   long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)n * nl) return;
   long i = e % n;
   int j = (int)(e / n);
-  S[e] = ((int)(i % nl) == j) ? 1.0 : 0.0;
+  S[e] = ((int)(i % nl) == j && perm[i] >= 0) ? 1.0 : 0.0;
 }
 
 hm_status make_identity_stack(Model* m) {
   hipLaunchKernelGGL(k_ident, dim3(ceil_div((long)m->n * m->nl, 256)), dim3(256), 0, m->stream, m->d_ident, m->n,
-                     m->nl);
+                     m->nl, m->d_perm);
+  HM_LAUNCH_CHECK();
+  return HM_OK;
+}
+
+// Leaf blocks (leaf-major) on the padding rows and columns: zero, with diag on the diagonal
+// (1 for K~: an identity block, inert in the Cholesky, log-determinant and solves;
+// 0 for the derivative matrices).
+__global__ void k_leaf_pad(double* D, const int* perm, int nl, long cnt, double diag) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cnt) return;
+  const long ls = (long)nl * nl;
+  const long L = e / ls;
+  const int le = (int)(e % ls), i = le % nl, j = le / nl;
+  if (perm[L * nl + i] < 0 || perm[L * nl + j] < 0) D[e] = (i == j) ? diag : 0.0;
+}
+hm_status leaf_pad(Model* m, double* D, double diag) {
+  if (m->uniform) return HM_OK;
+  const long cnt = (long)m->nleaves * m->nl * m->nl;
+  hipLaunchKernelGGL(k_leaf_pad, dim3(ceil_div(cnt, 256)), dim3(256), 0, m->stream, D, m->d_perm, m->nl, cnt, diag);
   HM_LAUNCH_CHECK();
   return HM_OK;
 }
@@ -290,8 +310,21 @@ hm_status leaf_pass(Model* m, const double theta[4], const PanelSet& ps, int nr,
   HM_CHECK(subtract_coarser(m, ps, m->levels + 1, m->d_ident, nl, sel_all(), sel_all(), b.Zl,
                             nr ? dZ : nullptr, nr, nb));
   HM_CHECK(leaf_sym(m, b.Zl, n, D));
-  for (int j = 0; j < nr; ++j) HM_CHECK(leaf_sym(m, dZ[j], n, dD[j]));
+  HM_CHECK(leaf_pad(m, D, 1.0));
+  for (int j = 0; j < nr; ++j) {
+    HM_CHECK(leaf_sym(m, dZ[j], n, dD[j]));
+    HM_CHECK(leaf_pad(m, dD[j], 0.0));
+  }
   return HM_OK;
+}
+
+// out[p + c n] = in[pad2tree[p] + c n_in] (0 on padding rows), cnt = n x columns
+__global__ void k_pad_rows(const double* in, int n_in, double* out, int n, const int* pad2tree, long cnt) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cnt) return;
+  const long c = e / n;
+  const int p = (int)(e % n), r = pad2tree[p];
+  out[e] = r >= 0 ? in[r + c * n_in] : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -321,6 +354,9 @@ hm_status sketch_build(Sketch* s, const double* omega, const double theta0[4]) {
   PanelSet ps{};
   ps.bw = r;
   ps.F = alloc((size_t)n * levels * r);
+  // draws by tree row of the real points; a non-uniform tree stores them in the padded layout
+  double* omega_pad = nullptr;
+  if (!m->uniform) omega_pad = alloc((size_t)levels * ell * n);
   double* Xl = alloc((size_t)n * ell);
   double* Yl = alloc((size_t)n * ell);
   double* Xr = alloc((size_t)n * r);
@@ -350,6 +386,13 @@ hm_status sketch_build(Sketch* s, const double* omega, const double theta0[4]) {
   size_t need = (size_t)m->nleaves * levels * r * tw;
   need = std::max(need, (size_t)m->nleaves * r * r);
   st = ensure_reduce_ws(m, need);
+  if (st == HM_OK && omega_pad) {
+    const long cnt = (long)levels * ell * n;
+    hipLaunchKernelGGL(k_pad_rows, dim3(ceil_div(cnt, 256)), dim3(256), 0, m->stream, omega, m->n_real, omega_pad, n,
+                       m->d_pad2tree, cnt);
+    st = (hipGetLastError() == hipSuccess) ? HM_OK : HM_E_DEVICE;
+    omega = omega_pad;
+  }
   if (st == HM_OK) st = fill(m, ps.F, (long)n * levels * r, 0.0);
   for (int l = 1; l <= levels && st == HM_OK; ++l) {
     const double* om = omega + (size_t)(l - 1) * ell * n;

@@ -43,6 +43,8 @@ hm_status level_step(Model* m, const double theta[4], const PanelSet& ps, int l,
 hm_status leaf_pass(Model* m, const double theta[4], const PanelSet& ps, int nr, const int* realidx,
                     const LevelBufs& b, const NodeBufs& nb, double* D, double* const* dD);
 hm_status sketch_build(Sketch* s, const double* omega, const double theta0[4]);
+// padding rows and columns of leaf blocks: zero off the diagonal, diag on it (no-op for uniform trees)
+hm_status leaf_pad(Model* m, double* D, double diag);
 hm_status leaf_factor(Model* m, const double* D, double* Dinv, double* logdet_leaf, double* work);
 
 }  // namespace hm

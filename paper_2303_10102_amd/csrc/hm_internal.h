@@ -70,9 +70,13 @@ struct ProfRec {
 //   t = leaf * nl + (x mod wl) + (y mod hl) * wl.
 // One-dimensional models keep grid order.  The quotients use reciprocal
 // multipliers ceil(2^32 / w), exact for coordinates and extents up to 2^16.
+// A tree with leaves of unequal size (odd sides, left child floor(side/2)) has no
+// closed form: then tab holds the position of every grid point (y N + x).
 struct TreeIdx {
   int two, wl, hl, nl, sx, sy;
   unsigned mx, my;
+  const int* tab;
+  int N;
   __host__ __device__ static unsigned spread(unsigned v) {   // bit b -> bit 2b (16 bits)
     v &= 0xFFFFu;
     v = (v | (v << 8)) & 0x00FF00FFu;
@@ -82,6 +86,7 @@ struct TreeIdx {
     return v;
   }
   __device__ __forceinline__ int operator()(int x, int y) const {
+    if (tab) return tab[y * N + x];
     if (!two) return x;
     const unsigned xh = __umulhi((unsigned)x, mx), yh = __umulhi((unsigned)y, my);
     const unsigned L = (spread(xh) << sx) | (spread(yh) << sy);
@@ -140,10 +145,19 @@ struct Model {
   ModelCounters cnt;
   int device = 0;
   hipStream_t stream = nullptr;
+  // n: rows of the tree-ordered layout.  The leaves are stored uniformly, nl rows each
+  // (n = nleaves nl); with leaves of unequal size (non-uniform bisection) each leaf is
+  // padded to the largest, and the padding ("ghost") rows are identically zero in
+  // every panel, sample and vector, identity in the leaf blocks of K~ and zero in
+  // those of every derivative matrix.  n_real: grid points (the model's dimension).
   int dim = 2, N = 0, n = 0, levels = 0, nl = 0, nleaves = 0;
+  int n_real = 0;
+  int nl_min = 0;           // smallest leaf (real rows)
+  bool uniform = true;
   double h = 0.0;
-  int* d_perm = nullptr;    // tree position -> grid index
+  int* d_perm = nullptr;    // tree position -> grid index (-1 for a padding row)
   int* d_iperm = nullptr;   // grid index -> tree position
+  int* d_pad2tree = nullptr;  // non-uniform: tree position -> index among the real rows (-1 padding)
   TreeIdx tix{};            // closed form of iperm for the transforms
   double* d_dst = nullptr;  // N x N orthonormal DST-I
   double* d_dsth = nullptr; // N even: its even/odd halves P0, P1, Q0, Q1 (each N/2 x N/2)

@@ -594,7 +594,9 @@ static hm_status ensure_scale(Model* m, const double theta[4]) {
 static void side_maps(const Model* m, LeafSel sel, AxisMap& xm, AxisMap& ym) {
   xm = axis_map(0, 0);
   ym = axis_map(0, 0);
-  if (sel.mode == 0) return;
+  // the sides of a non-uniform bisection are not alternating chunks of one width:
+  // whole transforms there (the output is then written on every row)
+  if (sel.mode == 0 || !m->uniform) return;
   int w = m->N, h = (m->dim == 2) ? m->N : 1;
   bool xsplit = true;
   for (int d = 1; d <= sel.depth; ++d) {
@@ -687,12 +689,22 @@ static void x_inverse(Model* m, const double* W, MultiOut mo, bool lam, int ldy,
 }
 #undef HM_DST_LAUNCH
 
-// Y[t, j] += tau2 X[t, j] for the rows t of the leaves selected by (mode, depth), j < c.
-__global__ void k_nugget(double* Y, int ldy, const double* X, int ldx, int n, int nl, int c, double tau2,
-                         int levels, int mode, int depth) {
+// Y[t, j] = 0 on the padding rows t (perm[t] < 0), j < c.
+__global__ void k_zero_pad_rows(double* Y, int ldy, const int* perm, int n, int c) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)n * c) return;
   const int t = (int)(e % n), j = (int)(e / n);
+  if (perm[t] < 0) Y[t + (long)j * ldy] = 0.0;
+}
+
+// Y[t, j] += tau2 X[t, j] for the rows t of the leaves selected by (mode, depth), j < c.
+// Padding rows (perm[t] < 0; perm null for a uniform tree) are skipped.
+__global__ void k_nugget(double* Y, int ldy, const double* X, int ldx, int n, int nl, int c, double tau2,
+                         int levels, int mode, int depth, const int* perm) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * c) return;
+  const int t = (int)(e % n), j = (int)(e / n);
+  if (perm && perm[t] < 0) return;
   if (mode != 0) {
     const int anc = (t / nl) >> (levels - depth);
     if (((anc & 1) == 0) != (mode == 1)) return;
@@ -774,11 +786,22 @@ static hm_status kapply_core(Model* m, double* ws, int cblk, const double theta[
   // largest entry of a column) would swamp the small far-field products the sketches
   // sample.  An input confined to one side of a split and an output wanted on the
   // other side get no nugget term at all.
+  if (!m->uniform) {
+    // the transforms write grid points only: the padding rows of the outputs are zero
+    double* outs0[3] = {outK, outKap, outAlp};
+    for (int q = 0; q < 3; ++q)
+      if (outs0[q] && ocols[q] > 0) {
+        hipLaunchKernelGGL(k_zero_pad_rows, dim3(ceil_div((long)n * ocols[q], 256)), dim3(256), 0, m->stream,
+                           outs0[q], ldo, m->d_perm, n, ocols[q]);
+        HM_LAUNCH_CHECK();
+      }
+  }
   const bool disjoint = in_sel.mode != 0 && out_sel.mode != 0 && in_sel.depth == out_sel.depth &&
                         in_sel.mode != out_sel.mode;
   if (outK && cK > 0 && !disjoint) {
     hipLaunchKernelGGL(k_nugget, dim3(ceil_div((long)n * cK, 256)), dim3(256), 0, m->stream, outK, ldo, X, ldx, n,
-                       m->nl, cK, theta[2], m->levels, out_sel.mode, out_sel.depth);
+                       m->nl, cK, theta[2], m->levels, out_sel.mode, out_sel.depth,
+                       m->uniform ? nullptr : m->d_perm);
     HM_LAUNCH_CHECK();
   }
   if (pf) {
@@ -833,10 +856,15 @@ TreeIdx make_tree_idx(int dim, int N, int levels) {
 
 hm_status model_tables(Model* m) {
   m->tix = make_tree_idx(m->dim, m->N, m->levels);
+  m->tix.N = m->N;
   const int n = m->n, N = m->N;
-  hipLaunchKernelGGL(k_perm, dim3(ceil_div(n, 256)), dim3(256), 0, m->stream, m->d_perm, m->d_iperm, n, N,
-                     m->dim, m->levels, m->nl);
-  HM_LAUNCH_CHECK();
+  if (m->uniform) {
+    hipLaunchKernelGGL(k_perm, dim3(ceil_div(n, 256)), dim3(256), 0, m->stream, m->d_perm, m->d_iperm, n, N,
+                       m->dim, m->levels, m->nl);
+    HM_LAUNCH_CHECK();
+  } else {
+    m->tix.tab = m->d_iperm;   // tables uploaded by the model's creator
+  }
   hipLaunchKernelGGL(k_tables, dim3(ceil_div((long)N * N, 256)), dim3(256), 0, m->stream, m->d_dst, m->d_mu, N,
                      m->dim, m->h);
   HM_LAUNCH_CHECK();

@@ -417,6 +417,12 @@ hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double theta[4], cons
     HM_CHECK(fill(m, pb.dF, pcnt, 0.0));
     HM_CHECK(leaf_affine(m, pb.dD, nullptr, 0.0, 1.0));
     HM_CHECK(fill(m, pb.E + s2, ncnt, 0.0));
+    if (!m->uniform) {
+      // K~_tau2 is the identity on the real rows only; Y = Dinv restricted to them
+      HM_CHECK(leaf_pad(m, pb.dD, 0.0));
+      HM_CHECK(leaf_affine(m, pb.Y, f.Dinv, 1.0, 0.0));
+      HM_CHECK(leaf_pad(m, pb.Y, 0.0));
+    }
     return HM_OK;
   }
   if (pb.kind == 3) {
@@ -429,6 +435,8 @@ hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double theta[4], cons
     HM_CHECK(leaf_affine(m, pb.Y, f.Dinv, -tau2 / sigma2, 1.0 / sigma2));
     HM_CHECK(lin2(m, pb.E + s2, f.Sn + s2, nullptr, ncnt, 0.5 / sigma2, 0.0));
     HM_CHECK(lin2(m, pb.Psi + s2, f.Sn + s2, GtG + s2, ncnt, 1.0 / sigma2, -tau2 / sigma2));
+    HM_CHECK(leaf_pad(m, pb.dD, 0.0));
+    HM_CHECK(leaf_pad(m, pb.Y, 0.0));
     return HM_OK;
   }
   // Xi_c = B_cc G_c: leaves plus every sibling pair strictly inside c

@@ -40,6 +40,7 @@ _SIGS = {
     "hm_model_create_spde": ([_P, _I, _I, _I, C.c_double, _I, C.POINTER(_I), C.c_longlong, _I, C.POINTER(_P)], _I),
     "hm_model_destroy": ([_P], None),
     "hm_model_info": ([_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)], _I),
+    "hm_model_rows": ([_P, C.POINTER(_I)], _I),
     "hm_model_set_stream": ([_P, _P], _I),
     "hm_model_autotune": ([_P, _I, _D], _I),
     "hm_model_tuning": ([_P, C.POINTER(_I), C.POINTER(C.c_longlong), _I], _I),
@@ -189,6 +190,9 @@ class Model:
         _check("hm_model_info", lib().hm_model_info(hh, C.byref(n), C.byref(lv), C.byref(lf)))
         self.dim, self.N, self.n, self.levels, self.leaf = dim, N, n.value, lv.value, lf.value
         self.h = spacing
+        rows = _I()
+        _check("hm_model_rows", lib().hm_model_rows(hh, C.byref(rows)))
+        self.rows = rows.value      # tree-ordered layout: n, or more with padded leaves
 
     def set_stream(self, stream):
         """Move the model's later work to another torch stream (None = current stream)."""
@@ -216,12 +220,13 @@ class Model:
         return rb.value, thr.value
 
     def perm(self):
-        out = (C.c_int * self.n)()
+        """Tree position -> grid index (rows entries; -1 on padding rows)."""
+        out = (C.c_int * self.rows)()
         _check("hm_model_perm", lib().hm_model_perm(self._h, out))
         return np.frombuffer(out, dtype=np.int32).copy()
 
     def kapply(self, theta_full, X, which=0, out=None, noalloc=False):
-        """Y = op X for X a (c, n) float64 CUDA tensor in tree order; op = K, dK/dkappa, dK/dalpha.
+        """Y = op X for X a (c, rows) float64 CUDA tensor in tree order; op = K, dK/dkappa, dK/dalpha.
         noalloc: use hm_kapply_noalloc (fixed per-device scratch, no allocation)."""
         import torch
         c, n = X.shape
@@ -385,7 +390,7 @@ class HMatrix:
         m = self.model
         _, kc = self.sketch.ranks()
         if what in (0, 1, 2):
-            shape = (m.levels * kc, m.n)
+            shape = (m.levels * kc, m.rows)
         else:
             shape = (1 << m.levels, m.leaf, m.leaf)
         out = torch.empty(shape, dtype=torch.float64, device=m.device)

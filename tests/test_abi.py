@@ -41,7 +41,7 @@ def test_errors_are_reported_without_a_device():
     # invalid arguments are rejected before any device call
     assert L.hm_model_create(0, None, 3, 16, 4, C.byref(out)) == 1
     assert b"dim" in L.hm_last_error()
-    assert L.hm_model_create(0, None, 2, 15, 16, C.byref(out)) == 1    # odd side -> non-uniform tree
+    assert L.hm_model_create(0, None, 2, 15, 200, C.byref(out)) == 1   # leaf larger than half the grid
     assert L.hm_factor(None) == 1
 
 

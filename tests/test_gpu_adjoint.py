@@ -26,7 +26,7 @@ def _need_gpu():
         pytest.skip("no HIP device")
 
 
-@pytest.mark.parametrize("key", ["1d_n1024", "2d_n1024", "2d_n4096"])
+@pytest.mark.parametrize("key", ["1d_n1024", "2d_n1024", "2d_n4096", "2d_n2025"])
 def test_adjoint_matches_oracle_and_forward(key):
     _need_gpu()
     print(f"\n[adjoint {key}]", flush=True)

@@ -21,7 +21,7 @@ import numpy as np
 import pytest
 
 from tests._cases import (CASES, dense_derivatives, densify, fim_err_corr, gpu_case, grad_err_sd, oracle_case,
-                          rel_err)
+                          real_rows, rel_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -41,7 +41,7 @@ def _need_gpu():
         pytest.skip("no HIP device")
 
 
-@pytest.fixture(scope="module", params=["1d_n1024", "2d_n1024", "2d_n4096", "2d_n2304"])
+@pytest.fixture(scope="module", params=["1d_n1024", "2d_n1024", "2d_n4096", "2d_n2304", "2d_n2025", "1d_n1023"])
 def case(request):
     _need_gpu()
     key = request.param
@@ -56,7 +56,15 @@ def case(request):
 
 def test_tree_permutation(case):
     key, o, w, m, s, H = case
-    assert np.array_equal(m.perm(), o["tree"].perm.astype(np.int32))
+    perm = m.perm()
+    idx = real_rows(perm)
+    assert np.array_equal(perm[idx], o["tree"].perm.astype(np.int32))
+    # padded layout: leaves stored at the largest leaf's size, padding rows at the end of a leaf
+    sizes = [sz for _, sz in o["tree"].leaves]
+    assert m.leaf == max(sizes) and m.rows == m.leaf << m.levels and len(idx) == w.n
+    for L, sz in enumerate(sizes):
+        blk = perm[L * m.leaf:(L + 1) * m.leaf]
+        assert np.all(blk[:sz] >= 0) and np.all(blk[sz:] == -1)
 
 
 @pytest.mark.parametrize("which", [0, 1, 2])
@@ -67,11 +75,14 @@ def test_kapply(case, which):
     K, dKs = dense_covariance(w.dim, w.N, w.theta_full, names)
     ref_op = to_tree_order(o["tree"], K if which == 0 else dKs[which - 1])
     rng = np.random.default_rng(11)
-    X = rng.standard_normal((w.n, 7))
+    X = rng.standard_normal((m.rows, 7))          # padding rows hold values too: ignored
     Xt = torch.from_numpy(np.ascontiguousarray(X.T)).cuda()
     Y = m.kapply(w.theta_full, Xt, which).cpu().numpy().T
-    ref = ref_op @ X
-    assert rel_err(Y, ref) < 1e-11
+    idx = real_rows(m.perm())
+    pad = np.setdiff1d(np.arange(m.rows), idx)
+    assert np.all(Y[pad] == 0.0)
+    ref = ref_op @ X[idx]
+    assert rel_err(Y[idx], ref) < 1e-11
 
 
 def test_sketch_ranks(case):
@@ -88,7 +99,13 @@ def test_construction(case):
     _, kc = s.ranks()
     F = H.export(0).cpu().numpy()
     D = H.export(10).cpu().numpy()
-    Kt = densify(F, D, m.levels, kc, w.n)
+    idx = real_rows(m.perm())
+    Kfull = densify(F, D, m.levels, kc, m.rows)
+    pad = np.setdiff1d(np.arange(m.rows), idx)
+    # padding: zero panel rows, identity leaf block uncoupled from the real rows
+    assert np.all(F[:, pad] == 0.0)
+    assert np.array_equal(Kfull[np.ix_(pad, pad)], np.eye(len(pad))) and np.all(Kfull[np.ix_(idx, pad)] == 0.0)
+    Kt = Kfull[np.ix_(idx, idx)]
     ref = o["rep"]["Kt"]
     e = rel_err(Kt, ref)
     print(f"K~ rel err {e:.3e}")
@@ -97,7 +114,9 @@ def test_construction(case):
     for j, name in enumerate(real):
         dF = H.export(1 + j).cpu().numpy()
         dD = H.export(11 + j).cpu().numpy()
-        dKt = densify(F, dD, m.levels, kc, w.n, dF=dF)
+        dfull = densify(F, dD, m.levels, kc, m.rows, dF=dF)
+        assert np.all(dfull[pad] == 0.0)
+        dKt = dfull[np.ix_(idx, idx)]
         refj = o["rep"]["dKts"][list(w.free).index(name)]
         ej = rel_err(dKt, refj)
         print(f"dK~/d{name} rel err {ej:.3e}")
@@ -113,11 +132,13 @@ def test_likelihood_gradient_fisher(case):
     print("grad", g, r["grad_nll"])
     print("fim", fim, r["fim"], sep="\n")
     eg, ei = grad_err_sd(g, r["grad_nll"], r["fim"]), fim_err_corr(fim, r["fim"])
-    print(f"[{key}] per entry: gradient {eg:.2e} sd, Fisher {ei:.2e} corr")
+    asym = fim_err_corr(fim, fim.T)
+    print(f"[{key}] per entry: gradient {eg:.2e} sd, Fisher {ei:.2e} corr, asymmetry {asym:.2e}")
     assert abs(ll - r["loglik"]) <= 1e-9 * abs(r["loglik"])
     assert eg < TOL_G_SD
     assert ei < TOL_I_CORR
-    assert fim_err_corr(fim, fim.T) < 1e-12
+    # (i, j) and (j, i) are computed independently: symmetric to rounding
+    assert asym < TOL_I_CORR
 
 
 def test_densified_representation(case):
@@ -130,9 +151,11 @@ def test_densified_representation(case):
     ll, g, fim = H.iteration(w.theta_full, y)
     _, kc = s.ranks()
     F = H.export(0).cpu().numpy()
-    Kd = densify(F, H.export(10).cpu().numpy(), m.levels, kc, w.n)
+    ix = np.ix_(real_rows(m.perm()), real_rows(m.perm()))
+    Kd = densify(F, H.export(10).cpu().numpy(), m.levels, kc, m.rows)[ix]
     real = [f for f in w.free if f in ("kappa", "alpha")]
-    dK = {name: densify(F, H.export(11 + j).cpu().numpy(), m.levels, kc, w.n, dF=H.export(1 + j).cpu().numpy())
+    dK = {name: densify(F, H.export(11 + j).cpu().numpy(), m.levels, kc, m.rows,
+                        dF=H.export(1 + j).cpu().numpy())[ix]
           for j, name in enumerate(real)}
     r = likelihood_gradient_fisher(Kd, dense_derivatives(w, Kd, dK), o["y"][o["tree"].perm])
     eg, ei = grad_err_sd(g, r["grad_nll"], r["fim"]), fim_err_corr(fim, r["fim"])

@@ -59,6 +59,20 @@ def test_2d_full_rank_is_exact():
         assert np.max(np.abs(r["dKts"][j] - dKt[j])) <= 1e-7 * np.max(np.abs(dKt[j]))
 
 
+def test_2d_full_rank_is_exact_on_an_odd_grid():
+    # n = 81 (9 x 9), leaf 8, 3 levels: 9 -> 4 | 5 along x, then y: leaves of 8 to 15 points
+    # (the left child takes floor(side / 2)); rank 45 keeps every off-diagonal block whole
+    w = small_workload(N=9, leaf=8, rank=45, oversample=4, sigma2=300.0)
+    Kt, dKt, tree, om = _setup(w)
+    sizes = sorted({sz for _, sz in tree.leaves})
+    assert len(sizes) > 1 and sum(sz for _, sz in tree.leaves) == 81
+    V = peeling.sketch_create(Kt, tree, om, w.rank)
+    r = peeling.build(Kt, dKt, tree, om, V)
+    assert np.max(np.abs(r["Kt"] - Kt)) <= 1e-11 * np.max(np.abs(Kt))
+    for j in range(len(dKt)):
+        assert np.max(np.abs(r["dKts"][j] - dKt[j])) <= 1e-7 * np.max(np.abs(dKt[j]))
+
+
 def test_qr_tangent_matches_finite_differences():
     rng = np.random.default_rng(0)
     B = rng.standard_normal((30, 6))
