@@ -72,6 +72,17 @@ hm_status hm_ctx_create(int device, void* stream, hm_alloc_fn alloc, hm_free_fn 
                         hm_ctx** out);
 void hm_ctx_destroy(hm_ctx* c);
 
+/* A caller-supplied covariance operator (the paper's black-box access to K, Sec. 3.2;
+ * Sec. 2.1 eq. "general physical model"): Y = op_which(theta) X for c columns, where
+ * which = 0 applies K_op(theta_full[0], theta_full[1]), 1 its derivative in
+ * theta_full[0], 2 its derivative in theta_full[1].  X, Y: device, n x c column-major
+ * (ld ldx, ldy) in the caller's point order; the work is enqueued on `stream` (the
+ * model's) and must not synchronise with the host when it can be avoided.  Return 0,
+ * or nonzero for failure (the library call then fails with HM_E_DEVICE).  K_op must be
+ * symmetric (and its derivatives), positive semidefinite. */
+typedef int (*hm_op_fn)(void* uctx, int which, const double* theta_full, const double* X, long long ldx,
+                        long long c, double* Y, long long ldy, void* stream);
+
 /* ---------------------------------------------------------------- model ---
  * hm_model_create: the stencil covariance model on a dim-D grid of side N
  * (n = N for dim 1, N*N for dim 2; h = 1/(N+1), Dirichlet boundary).
@@ -95,12 +106,26 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
  * HM_E_INVAL naming what is not supported. */
 hm_status hm_model_create_spde(hm_ctx* ctx, int dim, int nx, int ny, double h, int nvars, const int* obs_idx,
                                long long nobs, int leaf, hm_model** out);
+/* A model on n scattered points with a caller-supplied operator: K(theta) =
+ * sigma2 K_op(theta0, theta1) + tau2 I with theta_full = (theta0, theta1, tau2, sigma2)
+ * (tau2 > 0, sigma2 > 0; theta0, theta1 as the operator defines them, finite).
+ * coords: host, n x dim row-major (dim 1 or 2).  The tree is the KD-tree of the
+ * points (Sec. 5.2): a node's points are split along the longer side of their bounding
+ * box (x on ties), the floor(m/2) with the smallest coordinate (ties: the other
+ * coordinate, then the point index) going left; points inside a leaf keep increasing
+ * index; leaves are stored padded to the largest (hm_model_rows).  levels =
+ * floor(log2(n / leaf)).  op and uctx must stay valid while the model lives.  Every
+ * other call works on such a model as on the stencil model (sketches, H handles,
+ * gradients -- the reverse sweep applies the operator's derivatives --, Fisher). */
+hm_status hm_model_create_op(hm_ctx* ctx, int dim, const double* coords, int n, int leaf, hm_op_fn op, void* uctx,
+                             hm_model** out);
 void hm_model_destroy(hm_model* m);
 /* n (grid points), levels, leaf size of the stored layout (the largest leaf). Any pointer may be NULL. */
 hm_status hm_model_info(const hm_model* m, int* n, int* levels, int* leaf);
 /* Rows of the tree-ordered layout: 2^levels x leaf.  Equal to n when every bisection is
- * even; with odd sides the leaves differ in size (the left child gets floor(side/2)) and
- * each is stored padded to the largest: padding rows are zero in every tree-ordered
+ * even and the leaves hold a multiple of four points; otherwise (odd sides: the left
+ * child gets floor(side/2); scattered points) each leaf is stored padded to the largest
+ * leaf rounded up to a multiple of four: padding rows are zero in every tree-ordered
  * vector, panel and sample the library writes, identity in the leaf blocks of K~ and
  * zero in those of its derivatives, and are ignored on input.  hm_kapply's X, Y,
  * hm_model_perm and hm_export use this row count. */

@@ -174,3 +174,55 @@ def to_tree_order(tree: Tree, M: np.ndarray) -> np.ndarray:
     if M.shape[0] == M.shape[1] == tree.n:
         return M[np.ix_(p, p)]
     return M[p]
+
+
+class PointTree:
+    """KD-tree of a scattered point set (Sec. 5.2, "KD-tree binary spatial
+    partitioning"), with the interface of Tree: nodes[d] = (offset, size) of the 2^d
+    nodes at depth d, perm[i] = point index of tree position i.
+
+    Rule: a node's points are split along the longer side of their bounding box (x on
+    ties); the floor(m/2) points with the smallest coordinate along it go left (ties:
+    the other coordinate, then the point index).  Points inside a leaf are listed in
+    increasing index.
+    """
+
+    def __init__(self, coords, levels: int):
+        xy = np.asarray(coords, dtype=np.float64)
+        if xy.ndim == 1:
+            xy = xy[:, None]
+        self.levels = levels
+        groups = [np.arange(xy.shape[0])]
+        self.groups = [groups]
+        for _ in range(levels):
+            nxt = []
+            for g in groups:
+                pts = xy[g]
+                axis = 0
+                if xy.shape[1] == 2 and len(g):
+                    ext = pts.max(axis=0) - pts.min(axis=0)
+                    axis = 1 if ext[1] > ext[0] else 0
+                other = 1 - axis if xy.shape[1] == 2 else axis
+                order = np.lexsort((g, pts[:, other], pts[:, axis]))   # last key is the primary one
+                srt = g[order]
+                half = len(g) // 2
+                nxt += [srt[:half], srt[half:]]
+            groups = nxt
+            self.groups.append(groups)
+        self.nodes = []
+        for gs in self.groups:
+            off, lst = 0, []
+            for g in gs:
+                lst.append((off, len(g)))
+                off += len(g)
+            self.nodes.append(lst)
+        self.perm = np.concatenate([np.sort(g) for g in self.groups[-1]]).astype(np.int64)
+        self.n = len(self.perm)
+
+    def rows(self, d: int, i: int) -> slice:
+        off, sz = self.nodes[d][i]
+        return slice(off, off + sz)
+
+    @property
+    def leaves(self):
+        return self.nodes[-1]

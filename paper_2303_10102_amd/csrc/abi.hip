@@ -151,7 +151,7 @@ static bool finite4(const double* t) {
   return true;
 }
 
-hm_status check_theta(const double* t) {
+hm_status check_theta(const Model* m, const double* t) {
   if (!t) {
     set_error("theta is NULL");
     return HM_E_INVAL;
@@ -160,7 +160,11 @@ hm_status check_theta(const double* t) {
     set_error("theta has a non-finite entry");
     return HM_E_NONFINITE;
   }
-  if (!(t[0] > 0.0) || !(t[1] >= 0.0) || !(t[2] > 0.0) || !(t[3] > 0.0)) {
+  if (!(t[2] > 0.0) || !(t[3] > 0.0)) {
+    set_error("theta must satisfy tau2 > 0, sigma2 > 0");
+    return HM_E_INVAL;
+  }
+  if (!m->op && (!(t[0] > 0.0) || !(t[1] >= 0.0))) {
     set_error("theta must satisfy kappa > 0, alpha >= 0, tau2 > 0, sigma2 > 0");
     return HM_E_INVAL;
   }
@@ -299,7 +303,7 @@ static hm_status sync_check(HState* h, bool factored) {
 
 static hm_status build_enqueue(HState* h, const double* theta_full, bool deriv) {
   h->m->mixed = h->precision;
-  HM_CHECK(check_theta(theta_full));
+  HM_CHECK(check_theta(h->m, theta_full));
   Model* m = h->m;
   h->state = 0;
   h->have_deriv = false;
@@ -519,6 +523,46 @@ static std::vector<Rect> leaf_rects(int dim, int N, int levels) {
   return r;
 }
 
+// Leaves of the KD-tree of a point set (xy: n x dim row-major): a node's points are
+// split along the longer side of their bounding box (x on ties), the floor(m/2) with
+// the smallest coordinate (ties: the other coordinate, then the index) going left;
+// each leaf lists its points in increasing index.
+static std::vector<std::vector<int>> point_leaves(int dim, const double* xy, int n, int levels) {
+  std::vector<std::vector<int>> nodes(1);
+  nodes[0].resize(n);
+  for (int i = 0; i < n; ++i) nodes[0][i] = i;
+  auto c = [&](int i, int a) { return xy[(size_t)i * dim + a]; };
+  for (int d = 0; d < levels; ++d) {
+    std::vector<std::vector<int>> nx;
+    nx.reserve(nodes.size() * 2);
+    for (std::vector<int>& v : nodes) {
+      int axis = 0;
+      if (dim == 2 && !v.empty()) {
+        double x0 = c(v[0], 0), x1 = x0, y0 = c(v[0], 1), y1 = y0;
+        for (int i : v) {
+          x0 = std::min(x0, c(i, 0));
+          x1 = std::max(x1, c(i, 0));
+          y0 = std::min(y0, c(i, 1));
+          y1 = std::max(y1, c(i, 1));
+        }
+        axis = (y1 - y0 > x1 - x0) ? 1 : 0;
+      }
+      const int other = (dim == 2) ? 1 - axis : axis;
+      std::sort(v.begin(), v.end(), [&](int a, int b) {
+        if (c(a, axis) != c(b, axis)) return c(a, axis) < c(b, axis);
+        if (c(a, other) != c(b, other)) return c(a, other) < c(b, other);
+        return a < b;
+      });
+      const size_t half = v.size() / 2;
+      nx.emplace_back(v.begin(), v.begin() + half);
+      nx.emplace_back(v.begin() + half, v.end());
+    }
+    nodes.swap(nx);
+  }
+  for (std::vector<int>& v : nodes) std::sort(v.begin(), v.end());
+  return nodes;
+}
+
 // A model on an N (x N) Dirichlet grid with spacing h, its device memory from ctx.
 static hm_status model_create(Ctx* ctx, int device, void* stream, int dim, int N, double h, int leaf,
                               hm_model** out) {
@@ -567,6 +611,12 @@ static hm_status model_create(Ctx* ctx, int device, void* stream, int dim, int N
   if (nlmin < 1) {
     set_error("the tree has an empty leaf: choose a larger leaf size");
     return HM_E_INVAL;
+  }
+  // the panel reduce reads rows in groups of four inside a leaf: a leaf size that is
+  // not a multiple of four is stored padded to the next one
+  if (nlp % 4) {
+    nlp = (nlp + 3) / 4 * 4;
+    uniform = false;
   }
   const long rows = (long)nlp << levels;
   if (rows > (1L << 27)) {
@@ -686,6 +736,108 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
   return model_create(nullptr, device, stream, dim, N, 1.0 / (N + 1), leaf, out);
 }
 
+hm_status hm_model_create_op(hm_ctx* ctx, int dim, const double* coords, int n, int leaf, hm_op_fn op, void* uctx,
+                             hm_model** out) {
+  if (!ctx || !coords || !op || !out) {
+    set_error("NULL argument");
+    return HM_E_INVAL;
+  }
+  *out = nullptr;
+  if ((dim != 1 && dim != 2) || n < 2 || leaf < 1 || n > (1 << 26)) {
+    set_error("need dim in {1,2}, 2 <= n <= 2^26, leaf >= 1");
+    return HM_E_INVAL;
+  }
+  for (long i = 0; i < (long)n * dim; ++i)
+    if (!std::isfinite(coords[i])) {
+      set_error("hm_model_create_op: non-finite coordinate");
+      return HM_E_NONFINITE;
+    }
+  const int levels = (int)std::floor(std::log2((double)n / leaf) + 1e-12);
+  if (levels < 1 || levels > 20) {
+    set_error("need n >= 2*leaf");
+    return HM_E_INVAL;
+  }
+  std::vector<std::vector<int>> leaves = point_leaves(dim, coords, n, levels);
+  int nlp = 0, nlmin = n;
+  for (const auto& v : leaves) {
+    nlp = std::max(nlp, (int)v.size());
+    nlmin = std::min(nlmin, (int)v.size());
+  }
+  nlp = (nlp + 3) / 4 * 4;   // rows of a leaf in groups of four (see model_create)
+  const long rows = (long)nlp << levels;
+  if (rows > (1L << 27)) {
+    set_error("too many points");
+    return HM_E_INVAL;
+  }
+  if (hipSetDevice(ctx->c.device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return HM_E_DEVICE;
+  }
+  hm_model* hm_ = new hm_model();
+  Model* m = &hm_->m;
+  m->ctx = &ctx->c;
+  m->device = ctx->c.device;
+  m->stream = ctx->c.stream;
+  m->dim = dim;
+  m->N = 0;
+  m->n = (int)rows;
+  m->n_real = n;
+  m->uniform = false;
+  m->levels = levels;
+  m->nleaves = 1 << levels;
+  m->nl = nlp;
+  m->nl_min = nlmin;
+  m->h = 0.0;
+  m->cmax = std::max(m->nl, 80);
+  m->op = op;
+  m->op_ctx = uctx;
+  bool ok = true;
+  auto A = [&](void** p, size_t bytes) {
+    *p = dev_alloc(m->ctx, bytes);
+    ok = ok && *p;
+  };
+  A((void**)&m->d_perm, rows * sizeof(int));
+  A((void**)&m->d_iperm, (size_t)n * sizeof(int));
+  A((void**)&m->d_pad2tree, rows * sizeof(int));
+  A((void**)&m->d_ws, 5 * (size_t)rows * m->cmax * sizeof(double));
+  A((void**)&m->d_flags, sizeof(int));
+  A((void**)&m->d_ident, (size_t)rows * m->nl * sizeof(double));
+  A((void**)&m->d_opws, OPWS_DOUBLES * sizeof(double));
+  if (!ok) {
+    set_error("device allocation failed in model creation");
+    hm_model_destroy(hm_);
+    return HM_E_NOMEM;
+  }
+  std::vector<int> perm(rows, -1), iperm(n, -1), pad2tree(rows, -1);
+  int real = 0;
+  for (int L = 0; L < (int)leaves.size(); ++L)
+    for (int i = 0; i < (int)leaves[L].size(); ++i) {
+      const int g = leaves[L][i], p = L * nlp + i;
+      perm[p] = g;
+      iperm[g] = p;
+      pad2tree[p] = real++;
+    }
+  hm_status st = HM_OK;
+  if (hipMemcpy(m->d_perm, perm.data(), rows * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->d_iperm, iperm.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->d_pad2tree, pad2tree.data(), rows * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("model creation: copy of the tree tables failed");
+    st = HM_E_DEVICE;
+  }
+  if (st == HM_OK) st = make_identity_stack(m);
+  if (st == HM_OK) st = clear_flags(m);
+  if (st == HM_OK && hipStreamSynchronize(m->stream) != hipSuccess) {
+    set_error("model creation: device error");
+    st = HM_E_DEVICE;
+  }
+  if (st != HM_OK) {
+    hm_model_destroy(hm_);
+    return st;
+  }
+  *out = hm_;
+  return HM_OK;
+}
+
 hm_status hm_model_create_spde(hm_ctx* ctx, int dim, int nx, int ny, double h, int nvars, const int* obs_idx,
                                long long nobs, int leaf, hm_model** out) {
   if (!ctx || !out) {
@@ -718,7 +870,7 @@ void hm_model_destroy(hm_model* mm) {
   (void)hipStreamSynchronize(m->stream);
   for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
   void* ps[] = {m->d_perm, m->d_iperm, m->d_pad2tree, m->d_dst, m->d_dsth, m->d_mu, m->d_lam, m->d_ws, m->d_flags,
-                m->d_ident, m->d_red};
+                m->d_ident, m->d_red, m->d_opws};
   for (void* p : ps) dev_free(m->ctx, p);
   delete mm;
 }
@@ -800,7 +952,7 @@ hm_status hm_kapply(hm_model* mm, const double* theta_full, const double* X, int
     return HM_E_INVAL;
   }
   Model* m = &mm->m;
-  HM_CHECK(check_theta(theta_full));
+  HM_CHECK(check_theta(m, theta_full));
   if (c < 0 || ldx < m->n || ldy < m->n || which < 0 || which > 2) {
     set_error("hm_kapply: bad c, leading dimension (rows of the tree layout) or operator");
     return HM_E_INVAL;
@@ -825,7 +977,7 @@ hm_status hm_sketch_create_tol(hm_model* mm, const double* omega, int rank, int 
     set_error("rank_tol must lie in [0, 1)");
     return HM_E_INVAL;
   }
-  HM_CHECK(check_theta(theta0_full));
+  HM_CHECK(check_theta(&mm->m, theta0_full));
   if (rank < 1 || rank > 64 || oversample < 0 || rank + oversample > 80) {
     set_error("need 1 <= rank <= 64 and rank + oversample <= 80");
     return HM_E_INVAL;
@@ -1263,11 +1415,17 @@ hm_status hm_grad_reverse(hm_H* hh, double* grad) {
   HM_CHECK(node_prep(h->f));
   HM_CHECK(adjoint_init(h->f, h->z, h->adj));
   HM_CHECK(adjoint_sweep(m, h->theta, h->s, h->ps, h->lb, h->nb, h->adj));
-  const long NN = (long)m->N * (m->dim == 2 ? m->N : 1);   // modes of the transforms
-  const double* wv[1] = {h->adj.wmode};
-  const double* lv[3] = {m->d_lam, m->d_lam + NN, m->d_lam + 2 * NN};
-  HM_CHECK(dots(m, wv, 1, lv, 3, NN, h->d_scal + SC_ADJ, h->d_part));
-  HM_CHECK(sum_scalar(m, h->adj.wmode, NN, 0, h->d_scal + SC_ADJ + 3, h->d_part));
+  if (m->op) {
+    // the operator's vector-Jacobian products were summed directly (see kvjp)
+    HM_HIP(hipMemcpyAsync(h->d_scal + SC_ADJ, h->adj.wmode, 4 * sizeof(double), hipMemcpyDeviceToDevice,
+                          m->stream));
+  } else {
+    const long NN = (long)m->N * (m->dim == 2 ? m->N : 1);   // modes of the transforms
+    const double* wv[1] = {h->adj.wmode};
+    const double* lv[3] = {m->d_lam, m->d_lam + NN, m->d_lam + 2 * NN};
+    HM_CHECK(dots(m, wv, 1, lv, 3, NN, h->d_scal + SC_ADJ, h->d_part));
+    HM_CHECK(sum_scalar(m, h->adj.wmode, NN, 0, h->d_scal + SC_ADJ + 3, h->d_part));
+  }
   phase_end(h, PH_REVERSE);
   HM_CHECK(fetch_scalars(h, SC_ADJ, 4));
   HM_CHECK(sync_check(h, true));

@@ -154,6 +154,11 @@ struct Model {
   int n_real = 0;
   int nl_min = 0;           // smallest leaf (real rows)
   bool uniform = true;
+  // caller-supplied operator (hm_model_create_op): K = sigma2 K_op + tau2 I, applied
+  // through op in the caller's point order; d_opws: its reductions' scratch
+  hm_op_fn op = nullptr;
+  void* op_ctx = nullptr;
+  double* d_opws = nullptr;
   double h = 0.0;
   int* d_perm = nullptr;    // tree position -> grid index (-1 for a padding row)
   int* d_iperm = nullptr;   // grid index -> tree position
@@ -306,8 +311,10 @@ hm_status alg2_fold_nodes(Model* m, const double* W, double* M, long stride, int
 hm_status node_lu(Model* m, const double* S, long sstride, double* Nout, long nstride, double* logdet, int k,
                   int heap0, int cnt);
 hm_status model_tables(Model* m);
-// theta_full[4] checks shared by the entry points (finite; kappa, tau2, sigma2 > 0, alpha >= 0)
-hm_status check_theta(const double* t);
+// theta_full[4] checks shared by the entry points (finite; tau2, sigma2 > 0; for the
+// stencil model kappa > 0, alpha >= 0)
+hm_status check_theta(const Model* m, const double* t);
+constexpr int OPWS_DOUBLES = 1024 * 16 + 16;   // d_opws: dot partials + 4 results
 // time the panel-kernel variants on this model's shapes (panel width kc) and keep the fastest
 hm_status autotune(Model* m, int kc, double* report);
 

@@ -17,6 +17,7 @@
 
 #include "gemm_core.h"
 #include "hm_internal.h"
+#include "hm_trace.h"
 
 namespace hm {
 
@@ -712,6 +713,71 @@ __global__ void k_nugget(double* Y, int ldy, const double* X, int ldx, int n, in
   Y[t + (long)j * ldy] += tau2 * X[t + (long)j * ldx];
 }
 
+// outK += tau2 X on the rows where the input and the wanted output overlap
+static hm_status add_nugget(Model* m, const double theta[4], const double* X, int ldx, double* outK, int cK, int ldo,
+                            LeafSel in_sel, LeafSel out_sel) {
+  const bool disjoint = in_sel.mode != 0 && out_sel.mode != 0 && in_sel.depth == out_sel.depth &&
+                        in_sel.mode != out_sel.mode;
+  if (!outK || cK <= 0 || disjoint) return HM_OK;
+  const int n = m->n;
+  hipLaunchKernelGGL(k_nugget, dim3(ceil_div((long)n * cK, 256)), dim3(256), 0, m->stream, outK, ldo, X, ldx, n, m->nl,
+                     cK, theta[2], m->levels, out_sel.mode, out_sel.depth, m->uniform ? nullptr : m->d_perm);
+  HM_LAUNCH_CHECK();
+  return HM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// caller-supplied operator (hm_model_create_op): the columns are gathered into the
+// caller's point order, the operator (and its derivatives) applied, and the results
+// scattered back to tree order scaled by sigma2 (K = sigma2 K_op + tau2 I).
+// ---------------------------------------------------------------------------
+// Xn[i + j nr] = X[iperm[i] + j ldx]
+__global__ void k_gather_nat(const double* X, long ldx, double* Xn, const int* iperm, int nr, int c) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)nr * c) return;
+  const int i = (int)(e % nr), j = (int)(e / nr);
+  Xn[e] = X[iperm[i] + j * ldx];
+}
+// Y[t + j ldy] = s Yn[perm[t] + j nr] (0 on padding rows)
+__global__ void k_scatter_tree(const double* Yn, double* Y, long ldy, const int* perm, int n, int nr, int c, double s) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * c) return;
+  const int t = (int)(e % n), j = (int)(e / n), g = perm[t];
+  Y[t + j * ldy] = g >= 0 ? s * Yn[g + (long)j * nr] : 0.0;
+}
+
+static hm_status op_call(Model* m, int which, const double theta[4], const double* Xn, int c, double* Yn) {
+  const int rc = m->op(m->op_ctx, which, theta, Xn, m->n_real, c, Yn, m->n_real, (void*)m->stream);
+  if (rc != 0) {
+    set_error("the covariance operator callback failed (code " + std::to_string(rc) + ")");
+    return HM_E_DEVICE;
+  }
+  HM_LAUNCH_CHECK();
+  return HM_OK;
+}
+
+static hm_status op_kapply(Model* m, double* ws, int cblk, const double theta[4], const double* X, int ldx, int c,
+                           double* const outs[3], const int ocols[3], int ldo) {
+  const int n = m->n, nr = m->n_real;
+  double* Xn = ws;
+  double* Yn = ws + (long)n * cblk;
+  for (int c0 = 0; c0 < c; c0 += cblk) {
+    const int cc = std::min(cblk, c - c0);
+    hipLaunchKernelGGL(k_gather_nat, dim3(ceil_div((long)nr * cc, 256)), dim3(256), 0, m->stream, X + (long)c0 * ldx,
+                       (long)ldx, Xn, m->d_iperm, nr, cc);
+    HM_LAUNCH_CHECK();
+    for (int q = 0; q < 3; ++q) {
+      const int oc = std::min(cc, ocols[q] - c0);
+      if (!outs[q] || oc <= 0) continue;
+      HM_CHECK(op_call(m, q, theta, Xn, oc, Yn));
+      hipLaunchKernelGGL(k_scatter_tree, dim3(ceil_div((long)n * oc, 256)), dim3(256), 0, m->stream, Yn,
+                         outs[q] + (long)c0 * ldo, (long)ldo, m->d_perm, n, nr, oc, theta[3]);
+      HM_LAUNCH_CHECK();
+    }
+  }
+  return HM_OK;
+}
+
 // The K-apply with its transform scratch ws (5 * n * cblk doubles) passed in, columns
 // processed cblk at a time.
 static hm_status kapply_core(Model* m, double* ws, int cblk, const double theta[4], const double* X, int ldx, int c,
@@ -724,6 +790,12 @@ static hm_status kapply_core(Model* m, double* ws, int cblk, const double theta[
   if (cK > c || cKap > c || cAlp > c) {
     set_error("kapply: an output wants more columns than the input has");
     return HM_E_INVAL;
+  }
+  if (m->op) {
+    double* const outs_op[3] = {outK, outKap, outAlp};
+    const int ocols_op[3] = {outK ? cK : 0, outKap ? cKap : 0, outAlp ? cAlp : 0};
+    HM_CHECK(op_kapply(m, ws, cblk, theta, X, ldx, c, outs_op, ocols_op, ldo));
+    return add_nugget(m, theta, X, ldx, outK, cK, ldo, in_sel, out_sel);
   }
   HM_CHECK(ensure_scale(m, theta));
   const int n = m->n, N = m->N;
@@ -796,14 +868,7 @@ static hm_status kapply_core(Model* m, double* ws, int cblk, const double theta[
         HM_LAUNCH_CHECK();
       }
   }
-  const bool disjoint = in_sel.mode != 0 && out_sel.mode != 0 && in_sel.depth == out_sel.depth &&
-                        in_sel.mode != out_sel.mode;
-  if (outK && cK > 0 && !disjoint) {
-    hipLaunchKernelGGL(k_nugget, dim3(ceil_div((long)n * cK, 256)), dim3(256), 0, m->stream, outK, ldo, X, ldx, n,
-                       m->nl, cK, theta[2], m->levels, out_sel.mode, out_sel.depth,
-                       m->uniform ? nullptr : m->d_perm);
-    HM_LAUNCH_CHECK();
-  }
+  HM_CHECK(add_nugget(m, theta, X, ldx, outK, cK, ldo, in_sel, out_sel));
   if (pf) {
     // bytes: each pass reads and writes its n x c block once (compact where the maps halve it), plus S
     const double frac_in = (double)Kx * Nyi / NN, frac_out = (double)Mx * Nyo / NN;
@@ -891,9 +956,45 @@ __global__ void k_mode_dot(const double* A, const double* B, long NN, int cc, do
   wmode[e] += s;
 }
 
+// wmode[0..3] += (sigma2 <Yb, K_op X>, sigma2 <Yb, d0 K_op X>, sigma2 <Yb, d1 K_op X>, <Yb, X>)
+__global__ void k_accum4(double* w, const double* d, double s) {
+  const int q = threadIdx.x;
+  if (q < 4) w[q] += (q < 3 ? s : 1.0) * d[q];
+}
+
+// For an operator model the vector-Jacobian product has no mode structure: every
+// parameter's term <Ybar, dK/dtheta_j X> is formed from the operator's derivative
+// products (three operator applications per column block).
+static hm_status kvjp_op(Model* m, const double theta[4], const double* X, int ldx, const double* Yb, int ldb, int c,
+                         double* wmode) {
+  const int n = m->n, nr = m->n_real, cblk = m->cmax;
+  double* Xn = m->d_ws;
+  double* Bn = m->d_ws + (long)n * cblk;
+  double* Yq[3] = {m->d_ws + 2L * n * cblk, m->d_ws + 3L * n * cblk, m->d_ws + 4L * n * cblk};
+  for (int c0 = 0; c0 < c; c0 += cblk) {
+    const int cc = std::min(cblk, c - c0);
+    const long cnt = (long)nr * cc;
+    hipLaunchKernelGGL(k_gather_nat, dim3(ceil_div(cnt, 256)), dim3(256), 0, m->stream, X + (long)c0 * ldx, (long)ldx,
+                       Xn, m->d_iperm, nr, cc);
+    HM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_gather_nat, dim3(ceil_div(cnt, 256)), dim3(256), 0, m->stream, Yb + (long)c0 * ldb,
+                       (long)ldb, Bn, m->d_iperm, nr, cc);
+    HM_LAUNCH_CHECK();
+    for (int q = 0; q < 3; ++q) HM_CHECK(op_call(m, q, theta, Xn, cc, Yq[q]));
+    const double* A[1] = {Bn};
+    const double* B[4] = {Yq[0], Yq[1], Yq[2], Xn};
+    double* out = m->d_opws + 1024 * 16;
+    HM_CHECK(dots(m, A, 1, B, 4, cnt, out, m->d_opws));
+    hipLaunchKernelGGL(k_accum4, dim3(1), dim3(64), 0, m->stream, wmode, out, theta[3]);
+    HM_LAUNCH_CHECK();
+  }
+  return HM_OK;
+}
+
 hm_status kvjp(Model* m, const double theta[4], const double* X, int ldx, const double* Yb, int ldb, int c,
                double* wmode) {
   if (c <= 0) return HM_OK;
+  if (m->op) return kvjp_op(m, theta, X, ldx, Yb, ldb, c, wmode);
   HM_CHECK(ensure_scale(m, theta));
   const int n = m->n, N = m->N;
   const int Ny = (m->dim == 2) ? N : 1;

@@ -57,7 +57,7 @@ extern "C" hm_status hm_kapply_noalloc(hm_model* mm, const double* theta_full, c
     return HM_E_INVAL;
   }
   Model* m = &mm->m;
-  HM_CHECK(check_theta(theta_full));
+  HM_CHECK(check_theta(m, theta_full));
   if (c < 0 || ldx < m->n || ldy < m->n || which < 0 || which > 2) {
     set_error("hm_kapply_noalloc: bad c, leading dimension or operator");
     return HM_E_INVAL;

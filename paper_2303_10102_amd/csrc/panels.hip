@@ -232,7 +232,9 @@ k_reduce_direct(RedArgs a) {
   const int ngrp = (rend - rbeg + 15) >> 4;
   auto load_grp = [&](int t, Grp& u) {
     const int rr = rbeg + 16 * min(t, ngrp - 1) + 4 * lk;
-    const long rl = (rr + 3 < a.nl) ? rr : 0;   // a group of 4 rows inside the leaf
+    // a group of 4 rows inside the leaf (the layout keeps nl a multiple of 4, so a
+    // group never straddles the leaf's end; past the range it reads rows 0..3)
+    const long rl = (rr + 3 < a.nl) ? rr : 0;
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
       const double* pa = Ac[i] + rl;

@@ -38,6 +38,7 @@ _SIGS = {
     "hm_ctx_destroy": ([_P], None),
     "hm_model_create": ([_I, _P, _I, _I, _I, C.POINTER(_P)], _I),
     "hm_model_create_spde": ([_P, _I, _I, _I, C.c_double, _I, C.POINTER(_I), C.c_longlong, _I, C.POINTER(_P)], _I),
+    "hm_model_create_op": ([_P, _I, _D, _I, _I, _P, _P, C.POINTER(_P)], _I),
     "hm_model_destroy": ([_P], None),
     "hm_model_info": ([_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)], _I),
     "hm_model_rows": ([_P, C.POINTER(_I)], _I),
@@ -143,8 +144,13 @@ class Context:
                 except Exception:          # out of memory: the library reports HM_E_NOMEM
                     return None
 
+            release = torch.cuda.caching_allocator_delete
+
             def _free(uctx, ptr):
-                torch.cuda.caching_allocator_delete(int(ptr))
+                try:
+                    release(int(ptr))
+                except Exception:         # interpreter shutdown: torch has already gone
+                    pass
 
             self._cb = (_ALLOC_FN(_alloc), _FREE_FN(_free))
             alloc = C.cast(self._cb[0], C.c_void_p)
@@ -258,6 +264,97 @@ class Model:
             self.close()
         except Exception:
             pass
+
+
+_OP_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.POINTER(C.c_double), C.c_void_p, C.c_longlong,
+                     C.c_longlong, C.c_void_p, C.c_longlong, C.c_void_p)
+
+
+class _DLDevice(C.Structure):
+    _fields_ = [("device_type", C.c_int32), ("device_id", C.c_int32)]
+
+
+class _DLDataType(C.Structure):
+    _fields_ = [("code", C.c_uint8), ("bits", C.c_uint8), ("lanes", C.c_uint16)]
+
+
+class _DLTensor(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("device", _DLDevice), ("ndim", C.c_int32), ("dtype", _DLDataType),
+                ("shape", C.POINTER(C.c_int64)), ("strides", C.POINTER(C.c_int64)), ("byte_offset", C.c_uint64)]
+
+
+class _DLManagedTensor(C.Structure):
+    _fields_ = [("dl_tensor", _DLTensor), ("manager_ctx", C.c_void_p), ("deleter", C.c_void_p)]
+
+
+def device_view(ptr, c, ld, n, device):
+    """A (c, n) float64 torch view of the column-major n x c device block at ptr with
+    leading dimension ld (no copy), through DLPack; the memory stays the caller's."""
+    import torch
+    shape = (C.c_int64 * 2)(c, n)
+    strides = (C.c_int64 * 2)(ld, 1)
+    dev_type = 10 if torch.version.hip else 2        # kDLROCM / kDLCUDA
+    mt = _DLManagedTensor(_DLTensor(C.c_void_p(ptr), _DLDevice(dev_type, device), 2, _DLDataType(2, 64, 1),
+                                    shape, strides, 0), None, None)
+    keep = (shape, strides, mt)
+    C.pythonapi.PyCapsule_New.restype = C.py_object
+    C.pythonapi.PyCapsule_New.argtypes = [C.c_void_p, C.c_char_p, C.c_void_p]
+    cap = C.pythonapi.PyCapsule_New(C.addressof(mt), b"dltensor", None)
+    t = torch.from_dlpack(cap)
+    t._hmle_keep = keep          # the DLPack structs live as long as the view
+    return t
+
+
+class OpModel(Model):
+    """A model on scattered points with a caller-supplied covariance operator
+    (hm_model_create_op): K(theta) = sigma2 K_op(theta0, theta1) + tau2 I.
+
+    op(which, theta_full, X, Y): X, Y are (c, n) float64 CUDA views in the caller's point
+    order; write Y = K_op X (which 0), dK_op/dtheta0 X (1) or dK_op/dtheta1 X (2).  It
+    runs on the model's stream (made current while it runs)."""
+
+    def __init__(self, coords, leaf, op, device=0, stream=None, ctx=None, allocator="torch"):
+        import torch
+        self.device = torch.device("cuda", device)
+        self.ctx = ctx if ctx is not None else Context(device, stream, allocator)
+        self._own_ctx = ctx is None
+        xy = np.ascontiguousarray(np.asarray(coords, dtype=np.float64))
+        if xy.ndim == 1:
+            xy = xy[:, None]
+        n, dim = xy.shape
+        self._op = op
+        dev = int(device)
+
+        def _cb(uctx, which, theta, X, ldx, c, Y, ldy, stream_h):
+            try:
+                th = [theta[i] for i in range(4)]
+                Xv = device_view(X, int(c), int(ldx), n, dev)
+                Yv = device_view(Y, int(c), int(ldy), n, dev)
+                if stream_h:
+                    with torch.cuda.stream(torch.cuda.ExternalStream(int(stream_h), device=self.device)):
+                        op(int(which), th, Xv, Yv)
+                else:                     # the null stream
+                    with torch.cuda.stream(torch.cuda.default_stream(self.device)):
+                        op(int(which), th, Xv, Yv)
+                return 0
+            except Exception as exc:      # reported as HM_E_DEVICE by the library
+                import traceback
+                traceback.print_exception(exc)
+                return 1
+
+        self._cb = _OP_FN(_cb)
+        hh = _P()
+        with torch.cuda.device(device):
+            _check("hm_model_create_op", lib().hm_model_create_op(self.ctx._h, dim, xy.ctypes.data_as(_D), n, leaf,
+                                                                  C.cast(self._cb, C.c_void_p), None, C.byref(hh)))
+        self._h = hh
+        nn, lv, lf = _I(), _I(), _I()
+        _check("hm_model_info", lib().hm_model_info(hh, C.byref(nn), C.byref(lv), C.byref(lf)))
+        self.dim, self.N, self.n, self.levels, self.leaf = dim, 0, nn.value, lv.value, lf.value
+        self.h = None
+        rows = _I()
+        _check("hm_model_rows", lib().hm_model_rows(hh, C.byref(rows)))
+        self.rows = rows.value
 
 
 class Sketch:

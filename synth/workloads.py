@@ -166,3 +166,68 @@ def sketch_draws(w: Workload) -> np.ndarray:
     """
     rng = np.random.default_rng(w.sketch_seed)
     return rng.standard_normal((w.levels, w.ell, w.n))
+
+
+def scattered_points(n: int, seed: int, dim: int = 2) -> np.ndarray:
+    """n points drawn uniformly in the unit square (or interval), seeded (n x dim)."""
+    return np.random.default_rng(seed).random((n, dim))
+
+
+def scattered_sample(n: int, seed: int, scale: float) -> np.ndarray:
+    """A seeded sample vector of n standard normals times scale (an observation vector
+    for likelihood evaluations at scattered points)."""
+    return scale * np.random.default_rng(seed).standard_normal(n)
+
+
+@dataclass(frozen=True)
+class OpWorkload:
+    """A likelihood problem on scattered points with a caller-supplied covariance
+    operator K = sigma2 K_op(theta0, theta1) + tau2 I (the operator itself is the
+    caller's: here the anisotropic Matern-3/2 kernel, range theta0, y-stretch theta1)."""
+    name: str
+    dim: int
+    n: int
+    leaf: int
+    rank: int
+    oversample: int
+    theta0: float
+    theta1: float
+    tau2: float
+    sigma2: float
+    free: tuple
+    coord_seed: int
+    data_seed: int
+    sketch_seed: int
+
+    @property
+    def levels(self) -> int:
+        return int(math.floor(math.log2(self.n / self.leaf)))
+
+    @property
+    def ell(self) -> int:
+        return self.rank + self.oversample
+
+    @property
+    def theta_full(self) -> np.ndarray:
+        return np.array([self.theta0, self.theta1, self.tau2, self.sigma2], dtype=np.float64)
+
+    @property
+    def free_idx(self) -> tuple:
+        return tuple(PARAM_NAMES.index(f) for f in self.free)
+
+    def coords(self) -> np.ndarray:
+        return scattered_points(self.n, self.coord_seed, self.dim)
+
+    def sample(self) -> np.ndarray:
+        return scattered_sample(self.n, self.data_seed, math.sqrt(self.sigma2 + self.tau2))
+
+
+OP_WORKLOADS = {
+    # 1500 points uniform in the unit square, leaf 64 (4 levels), rank 24 + 10; range 0.3
+    # and nugget 0.2 keep the rank-24 approximation positive definite
+    "op2d_n1500": OpWorkload("op2d_n1500", 2, 1500, 64, 24, 10, 0.3, 1.3, 0.2, 1.0,
+                             ("kappa", "alpha", "tau2", "sigma2"), 11, 12, 13),
+    # 1000 points uniform on the unit interval, leaf 64 (3 levels)
+    "op1d_n1000": OpWorkload("op1d_n1000", 1, 1000, 64, 16, 10, 0.05, 1.0, 1e-2, 2.0,
+                             ("kappa", "tau2", "sigma2"), 21, 22, 23),
+}

@@ -36,6 +36,10 @@ CASES = {
     # odd sides: 45 x 45 (n = 2025, leaf 64, 4 levels): 45 -> 22 | 23 -> 11 | 11, 11 | 12,
     # leaves of 121 to 144 points, stored padded to 144 rows
     "2d_n2025": small_workload(N=45, leaf=64, rank=16, sigma2=1.0e3, name="2d_n2025"),
+    # 1D with 1000 points (leaf 64, 3 levels): equal leaves of 125 points, stored padded to
+    # 128 rows (leaf rows come in groups of four)
+    "1d_n1000": small_workload(dim=1, N=1000, leaf=64, rank=16, kappa=10.0, alpha=0.01, tau2=1e-4, sigma2=1.0e4,
+                               free=("kappa", "alpha", "tau2", "sigma2"), name="1d_n1000"),
     # 1D with 1023 points (leaf 64, 3 levels): leaves of 127 and 128 points
     "1d_n1023": small_workload(dim=1, N=1023, leaf=64, rank=16, kappa=10.0, alpha=0.01, tau2=1e-4, sigma2=1.0e4,
                                free=("kappa", "alpha", "tau2", "sigma2"), name="1d_n1023"),

@@ -41,7 +41,8 @@ def _need_gpu():
         pytest.skip("no HIP device")
 
 
-@pytest.fixture(scope="module", params=["1d_n1024", "2d_n1024", "2d_n4096", "2d_n2304", "2d_n2025", "1d_n1023"])
+@pytest.fixture(scope="module", params=["1d_n1024", "2d_n1024", "2d_n4096", "2d_n2304", "2d_n2025", "1d_n1023",
+                                        "1d_n1000"])
 def case(request):
     _need_gpu()
     key = request.param
@@ -59,9 +60,10 @@ def test_tree_permutation(case):
     perm = m.perm()
     idx = real_rows(perm)
     assert np.array_equal(perm[idx], o["tree"].perm.astype(np.int32))
-    # padded layout: leaves stored at the largest leaf's size, padding rows at the end of a leaf
+    # padded layout: leaves stored at the largest leaf's size rounded up to a multiple of
+    # four, padding rows at the end of a leaf
     sizes = [sz for _, sz in o["tree"].leaves]
-    assert m.leaf == max(sizes) and m.rows == m.leaf << m.levels and len(idx) == w.n
+    assert m.leaf == (max(sizes) + 3) // 4 * 4 and m.rows == m.leaf << m.levels and len(idx) == w.n
     for L, sz in enumerate(sizes):
         blk = perm[L * m.leaf:(L + 1) * m.leaf]
         assert np.all(blk[:sz] >= 0) and np.all(blk[sz:] == -1)
