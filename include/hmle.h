@@ -119,6 +119,19 @@ hm_status hm_model_create_spde(hm_ctx* ctx, int dim, int nx, int ny, double h, i
  * gradients -- the reverse sweep applies the operator's derivatives --, Fisher). */
 hm_status hm_model_create_op(hm_ctx* ctx, int dim, const double* coords, int n, int leaf, hm_op_fn op, void* uctx,
                              hm_model** out);
+/* The advection-diffusion-reaction model (Sec. 5.3, eqs. "ad1", "ad2"; latent Matern
+ * source, Sec. 5.1 eq. "latent covariance" with the mass lumped) on an N x N grid of
+ * the unit square (h = 1/(N+1), Dirichlet, central differences, constant coefficients):
+ *   L u = -kd Lap u + (vx, vy) . grad u + c u,   B = kappa^2 I - Lap,
+ *   K = sigma2 L^{-1} B^{-2} L^{-T} + tau2 I,   theta_full = (kappa, c, tau2, sigma2)
+ * (kappa > 0, c >= 0).  L is not symmetric: the K-apply solves with L and with L^T.
+ * The library applies K by direct transforms (a diagonal similarity makes each axis'
+ * operator symmetric): accepted while the cell Peclet number |v| h / (2 kd) < 1 and
+ * rho^(N-1) stays in [1e-3, 1e3], rho = sqrt((1 - P) / (1 + P)) per axis, P the cell
+ * Peclet number with sign; else HM_E_INVAL.  2 <= N <= 1024.  An operator model in
+ * every other respect (hm_model_create_op): the tree is the KD-tree of the grid points,
+ * kappa and c are the two parameters with derivative matrices. */
+hm_status hm_model_create_adr(hm_ctx* ctx, int N, double kd, double vx, double vy, int leaf, hm_model** out);
 void hm_model_destroy(hm_model* m);
 /* n (grid points), levels, leaf size of the stored layout (the largest leaf). Any pointer may be NULL. */
 hm_status hm_model_info(const hm_model* m, int* n, int* levels, int* leaf);

@@ -484,9 +484,6 @@ static hm_status iteration_collect(HState* h, double* loglik, double* grad, doub
 
 using namespace hm;
 
-struct hm_ctx {
-  Ctx c;
-};
 struct hm_sketch {
   Sketch s;
 };
@@ -736,9 +733,13 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
   return model_create(nullptr, device, stream, dim, N, 1.0 / (N + 1), leaf, out);
 }
 
-hm_status hm_model_create_op(hm_ctx* ctx, int dim, const double* coords, int n, int leaf, hm_op_fn op, void* uctx,
-                             hm_model** out) {
-  if (!ctx || !coords || !op || !out) {
+}  // extern "C"
+
+namespace hm {
+
+hm_status model_create_op(Ctx* cx, int dim, const double* coords, int n, int leaf, hm_op_fn op, void* uctx,
+                          bool builtin, hm_model** out) {
+  if (!cx || !coords || !op || !out) {
     set_error("NULL argument");
     return HM_E_INVAL;
   }
@@ -769,15 +770,16 @@ hm_status hm_model_create_op(hm_ctx* ctx, int dim, const double* coords, int n, 
     set_error("too many points");
     return HM_E_INVAL;
   }
-  if (hipSetDevice(ctx->c.device) != hipSuccess) {
+  if (hipSetDevice(cx->device) != hipSuccess) {
     set_error("hipSetDevice failed");
     return HM_E_DEVICE;
   }
   hm_model* hm_ = new hm_model();
   Model* m = &hm_->m;
-  m->ctx = &ctx->c;
-  m->device = ctx->c.device;
-  m->stream = ctx->c.stream;
+  m->ctx = cx;
+  m->device = cx->device;
+  m->stream = cx->stream;
+  m->op_builtin = builtin;
   m->dim = dim;
   m->N = 0;
   m->n = (int)rows;
@@ -838,6 +840,19 @@ hm_status hm_model_create_op(hm_ctx* ctx, int dim, const double* coords, int n, 
   return HM_OK;
 }
 
+}  // namespace hm
+
+extern "C" {
+
+hm_status hm_model_create_op(hm_ctx* ctx, int dim, const double* coords, int n, int leaf, hm_op_fn op, void* uctx,
+                             hm_model** out) {
+  if (!ctx) {
+    set_error("NULL argument");
+    return HM_E_INVAL;
+  }
+  return model_create_op(&ctx->c, dim, coords, n, leaf, op, uctx, false, out);
+}
+
 hm_status hm_model_create_spde(hm_ctx* ctx, int dim, int nx, int ny, double h, int nvars, const int* obs_idx,
                                long long nobs, int leaf, hm_model** out) {
   if (!ctx || !out) {
@@ -868,6 +883,7 @@ void hm_model_destroy(hm_model* mm) {
   if (!mm) return;
   Model* m = &mm->m;
   (void)hipStreamSynchronize(m->stream);
+  if (m->op_release) m->op_release(m);
   for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
   void* ps[] = {m->d_perm, m->d_iperm, m->d_pad2tree, m->d_dst, m->d_dsth, m->d_mu, m->d_lam, m->d_ws, m->d_flags,
                 m->d_ident, m->d_red, m->d_opws};
@@ -1171,7 +1187,7 @@ hm_status hm_H_create(hm_sketch* hs, int p, const int* free_idx, hm_H** out) {
   AL(h->adj.Fb, pset);
   AL(h->adj.Gs, pset);
   AL(h->adj.Zb, (size_t)n * nl);
-  AL(h->adj.wmode, (size_t)n);
+  AL(h->adj.wmode, 3 * (size_t)n + 8);   // per-mode weights (an operator's may use two sets and a sum)
   AL(h->adj.tmpK, nk);
   AL(h->adj.uT, nodes * tw);
   AL(h->ytree, (size_t)n);
@@ -1415,7 +1431,9 @@ hm_status hm_grad_reverse(hm_H* hh, double* grad) {
   HM_CHECK(node_prep(h->f));
   HM_CHECK(adjoint_init(h->f, h->z, h->adj));
   HM_CHECK(adjoint_sweep(m, h->theta, h->s, h->ps, h->lb, h->nb, h->adj));
-  if (m->op) {
+  if (m->op_vjp_final) {
+    HM_CHECK(m->op_vjp_final(m, h->theta, h->adj.wmode, h->d_scal + SC_ADJ));
+  } else if (m->op) {
     // the operator's vector-Jacobian products were summed directly (see kvjp)
     HM_HIP(hipMemcpyAsync(h->d_scal + SC_ADJ, h->adj.wmode, 4 * sizeof(double), hipMemcpyDeviceToDevice,
                           m->stream));

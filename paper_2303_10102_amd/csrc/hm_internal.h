@@ -159,6 +159,13 @@ struct Model {
   hm_op_fn op = nullptr;
   void* op_ctx = nullptr;
   double* d_opws = nullptr;
+  bool op_builtin = false;                 // a library operator: its status and message pass through
+  void (*op_release)(Model*) = nullptr;    // frees a library operator's state
+  // a library operator's own vector-Jacobian product: per-mode weights accumulated into
+  // wmode by op_vjp, turned into the four sums of kvjp (see there) by op_vjp_final
+  hm_status (*op_vjp)(Model*, const double* theta, const double* X, int ldx, const double* Yb, int ldb, int c,
+                      double* wmode) = nullptr;
+  hm_status (*op_vjp_final)(Model*, const double* theta, const double* wmode, double* out4) = nullptr;
   double h = 0.0;
   int* d_perm = nullptr;    // tree position -> grid index (-1 for a padding row)
   int* d_iperm = nullptr;   // grid index -> tree position
@@ -314,13 +321,19 @@ hm_status model_tables(Model* m);
 // theta_full[4] checks shared by the entry points (finite; tau2, sigma2 > 0; for the
 // stencil model kappa > 0, alpha >= 0)
 hm_status check_theta(const Model* m, const double* t);
+// an operator model (the points' KD-tree, padded leaves) with op applying K_op
+hm_status model_create_op(Ctx* cx, int dim, const double* coords, int n, int leaf, hm_op_fn op, void* uctx,
+                          bool builtin, hm_model** out);
 constexpr int OPWS_DOUBLES = 1024 * 16 + 16;   // d_opws: dot partials + 4 results
 // time the panel-kernel variants on this model's shapes (panel width kc) and keep the fastest
 hm_status autotune(Model* m, int kc, double* report);
 
 }  // namespace hm
 
-// the public model handle (opaque in hmle.h)
+// the public context and model handles (opaque in hmle.h)
+struct hm_ctx {
+  hm::Ctx c;
+};
 struct hm_model {
   hm::Model m;
 };

@@ -732,7 +732,7 @@ static hm_status add_nugget(Model* m, const double theta[4], const double* X, in
 // scattered back to tree order scaled by sigma2 (K = sigma2 K_op + tau2 I).
 // ---------------------------------------------------------------------------
 // Xn[i + j nr] = X[iperm[i] + j ldx]
-__global__ void k_gather_nat(const double* X, long ldx, double* Xn, const int* iperm, int nr, int c) {
+__global__ void __launch_bounds__(256) k_gather_nat(const double* X, long ldx, double* Xn, const int* iperm, int nr, int c) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)nr * c) return;
   const int i = (int)(e % nr), j = (int)(e / nr);
@@ -748,6 +748,7 @@ __global__ void k_scatter_tree(const double* Yn, double* Y, long ldy, const int*
 
 static hm_status op_call(Model* m, int which, const double theta[4], const double* Xn, int c, double* Yn) {
   const int rc = m->op(m->op_ctx, which, theta, Xn, m->n_real, c, Yn, m->n_real, (void*)m->stream);
+  if (rc != 0 && m->op_builtin) return (hm_status)rc;
   if (rc != 0) {
     set_error("the covariance operator callback failed (code " + std::to_string(rc) + ")");
     return HM_E_DEVICE;
@@ -759,6 +760,7 @@ static hm_status op_call(Model* m, int which, const double theta[4], const doubl
 static hm_status op_kapply(Model* m, double* ws, int cblk, const double theta[4], const double* X, int ldx, int c,
                            double* const outs[3], const int ocols[3], int ldo) {
   const int n = m->n, nr = m->n_real;
+  cblk = std::min(cblk, m->cmax);   // operators see at most cmax columns at a time
   double* Xn = ws;
   double* Yn = ws + (long)n * cblk;
   for (int c0 = 0; c0 < c; c0 += cblk) {
@@ -962,6 +964,14 @@ __global__ void k_accum4(double* w, const double* d, double s) {
   if (q < 4) w[q] += (q < 3 ? s : 1.0) * d[q];
 }
 
+// columns of a tree-ordered block gathered into the operator's point order (ld n_real)
+hm_status kvjp_gather(Model* m, const double* X, int ldx, double* Xn, int c) {
+  hipLaunchKernelGGL(k_gather_nat, dim3(ceil_div((long)m->n_real * c, 256)), dim3(256), 0, m->stream, X, (long)ldx, Xn,
+                     m->d_iperm, m->n_real, c);
+  HM_LAUNCH_CHECK();
+  return HM_OK;
+}
+
 // For an operator model the vector-Jacobian product has no mode structure: every
 // parameter's term <Ybar, dK/dtheta_j X> is formed from the operator's derivative
 // products (three operator applications per column block).
@@ -994,6 +1004,7 @@ static hm_status kvjp_op(Model* m, const double theta[4], const double* X, int l
 hm_status kvjp(Model* m, const double theta[4], const double* X, int ldx, const double* Yb, int ldb, int c,
                double* wmode) {
   if (c <= 0) return HM_OK;
+  if (m->op_vjp) return m->op_vjp(m, theta, X, ldx, Yb, ldb, c, wmode);
   if (m->op) return kvjp_op(m, theta, X, ldx, Yb, ldb, c, wmode);
   HM_CHECK(ensure_scale(m, theta));
   const int n = m->n, N = m->N;

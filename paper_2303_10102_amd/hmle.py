@@ -39,6 +39,7 @@ _SIGS = {
     "hm_model_create": ([_I, _P, _I, _I, _I, C.POINTER(_P)], _I),
     "hm_model_create_spde": ([_P, _I, _I, _I, C.c_double, _I, C.POINTER(_I), C.c_longlong, _I, C.POINTER(_P)], _I),
     "hm_model_create_op": ([_P, _I, _D, _I, _I, _P, _P, C.POINTER(_P)], _I),
+    "hm_model_create_adr": ([_P, _I, C.c_double, C.c_double, C.c_double, _I, C.POINTER(_P)], _I),
     "hm_model_destroy": ([_P], None),
     "hm_model_info": ([_P, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I)], _I),
     "hm_model_rows": ([_P, C.POINTER(_I)], _I),
@@ -352,6 +353,29 @@ class OpModel(Model):
         _check("hm_model_info", lib().hm_model_info(hh, C.byref(nn), C.byref(lv), C.byref(lf)))
         self.dim, self.N, self.n, self.levels, self.leaf = dim, 0, nn.value, lv.value, lf.value
         self.h = None
+        rows = _I()
+        _check("hm_model_rows", lib().hm_model_rows(hh, C.byref(rows)))
+        self.rows = rows.value
+
+
+class AdrModel(Model):
+    """The advection-diffusion-reaction model (hm_model_create_adr) on an N x N grid:
+    K = sigma2 L^{-1} B^{-2} L^{-T} + tau2 I with theta_full = (kappa, c, tau2, sigma2)."""
+
+    def __init__(self, N, leaf, kd, vx, vy, device=0, stream=None, ctx=None, allocator="torch"):
+        import torch
+        self.device = torch.device("cuda", device)
+        self.ctx = ctx if ctx is not None else Context(device, stream, allocator)
+        self._own_ctx = ctx is None
+        hh = _P()
+        with torch.cuda.device(device):
+            _check("hm_model_create_adr", lib().hm_model_create_adr(self.ctx._h, int(N), float(kd), float(vx),
+                                                                    float(vy), int(leaf), C.byref(hh)))
+        self._h = hh
+        nn, lv, lf = _I(), _I(), _I()
+        _check("hm_model_info", lib().hm_model_info(hh, C.byref(nn), C.byref(lv), C.byref(lf)))
+        self.dim, self.N, self.n, self.levels, self.leaf = 2, int(N), nn.value, lv.value, lf.value
+        self.h = 1.0 / (N + 1)
         rows = _I()
         _check("hm_model_rows", lib().hm_model_rows(hh, C.byref(rows)))
         self.rows = rows.value

@@ -231,3 +231,73 @@ OP_WORKLOADS = {
     "op1d_n1000": OpWorkload("op1d_n1000", 1, 1000, 64, 16, 10, 0.05, 1.0, 1e-2, 2.0,
                              ("kappa", "tau2", "sigma2"), 21, 22, 23),
 }
+
+
+@dataclass(frozen=True)
+class AdrWorkload:
+    """The advection-diffusion-reaction model on an N x N grid of the unit square:
+    K = sigma2 L^{-1} B^{-2} L^{-T} + tau2 I, L = -kd Lap + v . grad + c, B = kappa^2 - Lap,
+    theta = (kappa, c, tau2, sigma2) in the slots of (theta0, theta1, tau2, sigma2)."""
+    name: str
+    N: int
+    leaf: int
+    rank: int
+    oversample: int
+    kd: float
+    vx: float
+    vy: float
+    kappa: float
+    c: float
+    tau2: float
+    sigma2: float
+    free: tuple
+    data_seed: int
+    sketch_seed: int
+    dim: int = 2
+
+    @property
+    def n(self) -> int:
+        return self.N * self.N
+
+    @property
+    def levels(self) -> int:
+        return int(math.floor(math.log2(self.n / self.leaf)))
+
+    @property
+    def ell(self) -> int:
+        return self.rank + self.oversample
+
+    @property
+    def theta_full(self) -> np.ndarray:
+        return np.array([self.kappa, self.c, self.tau2, self.sigma2], dtype=np.float64)
+
+    def sample(self) -> np.ndarray:
+        """y = sigma L^{-1} B^{-1} w + tau eps (w then eps from default_rng(data_seed)), by
+        sparse solves on the host (grid order, x fastest)."""
+        N, h = self.N, 1.0 / (self.N + 1)
+        one = np.ones(N)
+        T1 = sp.diags([-one[:-1], 2 * one, -one[:-1]], [-1, 0, 1]) / (h * h)
+        G1 = sp.diags([-one[:-1], one[:-1]], [-1, 1]) / (2 * h)
+        I1 = sp.identity(N)
+        lap = sp.kron(I1, T1) + sp.kron(T1, I1)
+        Lop = (self.kd * lap + self.vx * sp.kron(I1, G1) + self.vy * sp.kron(G1, I1)
+               + self.c * sp.identity(N * N)).tocsc()
+        Bop = (self.kappa ** 2 * sp.identity(N * N) + lap).tocsc()
+        rng = np.random.default_rng(self.data_seed)
+        w = rng.standard_normal(N * N)
+        eps = rng.standard_normal(N * N)
+        return math.sqrt(self.sigma2) * spla.spsolve(Lop, spla.spsolve(Bop, w)) + math.sqrt(self.tau2) * eps
+
+
+ADR_WORKLOADS = {
+    # 32 x 32 (n = 1024), leaf 64, rank 16 + 10; advection (2.5, 1) with kd = 1: cell Peclet
+    # numbers 0.038 and 0.015; sigma2 gives unit mean physics variance, nugget 0.05
+    "adr_n1024": AdrWorkload("adr_n1024", 32, 64, 16, 10, 1.0, 2.5, 1.0, 10.0, 1.0, 0.05, 5.0e9,
+                             ("kappa", "alpha", "tau2", "sigma2"), 31, 32),
+    # odd sides: 45 x 45 (leaves of 121-144 points)
+    "adr_n2025": AdrWorkload("adr_n2025", 45, 64, 16, 10, 1.0, 2.5, 1.0, 10.0, 1.0, 0.05, 1.0e10,
+                             ("kappa", "alpha", "tau2", "sigma2"), 33, 34),
+    # 256 x 256 (n = 65536), leaf 256, rank 48 + 10: the headline grid with this model
+    "adr_n65536": AdrWorkload("adr_n65536", 256, 256, 48, 10, 1.0, 2.5, 1.0, 20.0, 1.0, 0.05, 1.0e11,
+                              ("kappa", "alpha", "tau2", "sigma2"), 35, 36),
+}
