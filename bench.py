@@ -93,9 +93,10 @@ def cpu_baseline(sample_key="2d_n4096", full_n=65536):
     }
 
 
-def batched_run(steps, count=64):
+def batched_run(steps, count=64, mixed=True):
     """The batched workload: `count` independent fields (sides 64..256, per-field theta),
-    one iteration of every field per step, streams chosen by the autotuner."""
+    one iteration of every field per step, streams chosen by the autotuner; then the same
+    batch under the mixed-precision policy."""
     import numpy as np
     import torch
     from paper_2303_10102_amd import hmle
@@ -134,8 +135,60 @@ def batched_run(steps, count=64):
         "streams": tune["best_streams"], "tuning_ms": {str(k): 1e3 * v for k, v in tune["batch_s"].items()},
         "steps": steps, "setup_s": setup, "all_finite": bool(np.all(np.isfinite(ll))),
     }
+    if mixed:
+        for o in objs:
+            o[2].set_precision("mixed32")
+        b.iteration(thetas, ys)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            llm, gm, fm = b.iteration(thetas, ys)
+        torch.cuda.synchronize()
+        dmx = (time.perf_counter() - t0) / steps
+        # per entry against the FP64 path, in standard deviations / correlation units
+        eg = max(float(np.max(np.abs(gm[f] - g[f]) / np.sqrt(np.diag(fim[f])))) for f in range(len(fields)))
+        ei = max(float(np.max(np.abs(fm[f] - fim[f]) / np.outer(np.sqrt(np.diag(fim[f])), np.sqrt(np.diag(fim[f])))))
+                 for f in range(len(fields)))
+        el = max(abs(llm[f] - ll[f]) / abs(ll[f]) for f in range(len(fields)))
+        out["mixed32"] = {"field_iters_per_s": len(fields) / dmx, "ms_per_batch_iter": 1e3 * dmx,
+                          "speedup_vs_fp64_batch": dt / dmx,
+                          "max_err_vs_fp64": {"loglik_rel": el, "grad_sd": eg, "fim_corr": ei}}
     for m, s, H in objs:
         H.close(); s.close(); m.close()
+    return out
+
+
+def adr_run(steps):
+    """One likelihood iteration (K~, K~_kappa, K~_c, factor, L~, gradient, 4 x 4 Fisher) of the
+    advection-diffusion-reaction model on the 256 x 256 grid (non-symmetric L)."""
+    import torch
+    from paper_2303_10102_amd import hmle
+    from synth import ADR_WORKLOADS, sketch_draws
+    w = ADR_WORKLOADS["adr_n65536"]
+    print(f"[bench] adr: {w.name}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    m = hmle.AdrModel(w.N, w.leaf, w.kd, w.vx, w.vy, device=0)
+    y = torch.from_numpy(w.sample()).cuda()
+    s = hmle.Sketch(m, torch.from_numpy(sketch_draws(w)).cuda(), w.rank, w.oversample, w.theta_full)
+    H = hmle.HMatrix(s, w.free)
+    m.autotune(s.ranks()[1])
+    H.iteration(w.theta_full, y)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    H.stats_reset()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ll, g, fim = H.iteration(w.theta_full, y)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    st = H.stats()
+    out = {"workload": f"{w.name}: {w.N}x{w.N}, kd {w.kd}, v ({w.vx}, {w.vy}), leaf {w.leaf}, rank {w.rank}, "
+                       f"theta = (kappa, c, tau2, sigma2)",
+           "iters_per_s": 1.0 / dt, "ms_per_iter": 1e3 * dt, "steps": steps, "setup_s": setup,
+           "ms_per_phase": {k[3:]: v / steps for k, v in st.items() if k.startswith("ms_")},
+           "kapply_columns_per_iter": (st["kapply_columns"] + st["kapply_deriv_columns"]) / steps,
+           "loglik": ll, "grad_nll": [float(v) for v in g]}
+    H.close(); s.close(); m.close()
     return out
 
 
@@ -192,8 +245,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="2d_n65536")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batched", action="store_true",
-                    help="also run the 64-field batched workload (adds about a minute of setup)")
+    ap.add_argument("--batched-steps", type=int, default=3,
+                    help="also time the 64-field batched workload, FP64 and mixed (0 = skip)")
+    ap.add_argument("--adr-steps", type=int, default=3,
+                    help="also time the advection-diffusion-reaction model on the 256^2 grid (0 = skip)")
     ap.add_argument("--mixed-steps", type=int, default=5,
                     help="also time the mixed-precision policy and report both paths' errors (0 = skip)")
     ap.add_argument("--adjoint-steps", type=int, default=5,
@@ -301,13 +356,33 @@ def main():
         dm = (time.perf_counter() - t0) / args.mixed_steps
         H.set_precision("fp64")
         H.iteration(theta, y)
-        d = np.sqrt(np.diag(ex["fim"]))
-        err = lambda l_, g_, f_: {"eps_L": abs(l_ - ex["loglik"]) / abs(ex["loglik"]),
-                                  "grad_max_err_in_sd": float(np.max(np.abs(g_ - ex["grad_nll"]) / d)),
-                                  "fim_max_err_corr": float(np.max(np.abs(f_ - ex["fim"]) / np.outer(d, d)))}
+        def err(l_, g_, f_, ref):
+            d = np.sqrt(np.diag(ref["fim"]))
+            return {"eps_L": abs(l_ - ref["loglik"]) / abs(ref["loglik"]),
+                    "grad_max_err_in_sd": float(np.max(np.abs(g_ - ref["grad_nll"]) / d)),
+                    "fim_max_err_corr": float(np.max(np.abs(f_ - ref["fim"]) / np.outer(d, d)))}
+        dfp = np.sqrt(np.diag(fim))
         rec["mixed32"] = {"ms_per_iter": 1e3 * dm, "speedup_vs_fp64": ms / (1e3 * dm),
-                          "steps": args.mixed_steps, "error_fp64_vs_exact": err(ll, g, fim),
-                          "error_mixed_vs_exact": err(llm, gm, fm)}
+                          "steps": args.mixed_steps, "error_fp64_vs_exact": err(ll, g, fim, ex),
+                          "error_mixed_vs_exact": err(llm, gm, fm, ex),
+                          "mixed_vs_fp64_H": {"loglik_rel": abs(llm - ll) / abs(ll),
+                                              "grad_sd": float(np.max(np.abs(gm - g) / dfp)),
+                                              "fim_corr": float(np.max(np.abs(fm - fim) / np.outer(dfp, dfp)))}}
+        # the physics-dominated regime (sigma2 = 6.4e4: mean field variance ~0.12 of the nugget)
+        thp = theta.copy()
+        thp[3] = 6.4e4
+        exp_ = spectral_quantities(w.dim, w.N, thp, y.cpu().numpy(), w.free)
+        l64, g64, f64 = H.iteration(thp, y)
+        H.set_precision("mixed32")
+        l32, g32, f32 = H.iteration(thp, y)
+        H.set_precision("fp64")
+        d64 = np.sqrt(np.diag(f64))
+        rec["mixed32"]["physics_regime_sigma2_6.4e4"] = {
+            "error_fp64_vs_exact": err(l64, g64, f64, exp_), "error_mixed_vs_exact": err(l32, g32, f32, exp_),
+            "mixed_vs_fp64_H": {"loglik_rel": abs(l32 - l64) / abs(l64),
+                                "grad_sd": float(np.max(np.abs(g32 - g64) / d64)),
+                                "fim_corr": float(np.max(np.abs(f32 - f64) / np.outer(d64, d64)))}}
+        H.iteration(theta, y)
     if args.adjoint_steps > 0:
         # L~ and gradient only, by the adjoint (no derivative matrices, no Fisher)
         H.loglik_grad_adjoint(theta, y)
@@ -323,11 +398,16 @@ def main():
                                       "grad_nll": [float(v) for v in ga]}
     if args.mle:
         rec["mle"] = mle_run(w)
-    if args.batched:
+    if args.batched_steps > 0 or args.adr_steps > 0:
+        H.close(); s.close(); m.close()
         del H, s, m
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
-        rec["batched"] = batched_run(max(1, args.steps // 2))
+    if args.batched_steps > 0:
+        rec["batched"] = batched_run(args.batched_steps)
+        torch.cuda.empty_cache()
+    if args.adr_steps > 0:
+        rec["adr"] = adr_run(args.adr_steps)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline()
