@@ -238,6 +238,68 @@ def mle_run(w_head):
     return out
 
 
+SCALING_SIDES = (32, 45, 64, 91, 128, 181, 256, 362, 512)
+SCALING_RANKS = (32, 64)
+
+
+def scaling_run(steps, sides=SCALING_SIDES, ranks=SCALING_RANKS):
+    """Cost against n, the shapes of Sec. 5.2.1: per grid side N (n = N^2 from 2^10 to 2^18,
+    leaf 256, levels floor(log2(n / 256))) and off-diagonal rank r, one likelihood iteration
+    of the headline model (theta = (kappa, alpha, tau2, sigma2) all free) split into
+      * K-apply columns per iteration (K and the two real derivatives; O(log n) per the paper),
+      * construction time, its K-apply part (the sine-transform family's event time) and the
+        rest (the H linear algebra of the construction),
+      * factorisation + log-determinant,
+      * L~, solve, quadratic forms and the traces tr(K~^-1 K~_j) of the score,
+      * the Fisher traces tr(K~^-1 K~_i K~^-1 K~_j),
+    from hm_stats' per-phase event times, averaged over `steps` iterations after one warm-up."""
+    import torch
+    from paper_2303_10102_amd import hmle
+    from synth import Workload, sample_y, sketch_draws
+    rows = []
+    for r in ranks:
+        for N in sides:
+            w = Workload(f"2d_N{N}_r{r}", 2, N, 256, r, 10, 20.0, 2e-4, 1e-3, 1.0,
+                         ("kappa", "alpha", "tau2", "sigma2"), 7, 107)
+            print(f"[bench] scaling: N={N} n={w.n} rank={r}", file=sys.stderr, flush=True)
+            m = hmle.Model(w.dim, w.N, w.leaf, device=0)
+            y = torch.from_numpy(sample_y(w)).cuda()
+            om = torch.from_numpy(sketch_draws(w)).cuda()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s = hmle.Sketch(m, om, w.rank, w.oversample, w.theta_full)
+            torch.cuda.synchronize()
+            t_sketch = time.perf_counter() - t0
+            del om
+            H = hmle.HMatrix(s, w.free)
+            kc = s.ranks()[1]
+            m.autotune(kc)
+            H.iteration(w.theta_full, y)
+            torch.cuda.synchronize()
+            H.stats_reset()
+            m.profile_enable("dst")
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                H.iteration(w.theta_full, y)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            kap = m.profile_read()["ms"] / steps
+            m.profile_enable(None)
+            st = H.stats()
+            build = st["ms_build"] / steps
+            rows.append({"N": N, "n": w.n, "levels": m.levels, "rank": r, "kept_rank": int(kc),
+                         "kapply_columns": (st["kapply_columns"] + st["kapply_deriv_columns"]) / steps,
+                         "ms_iter": 1e3 * dt, "ms_build": build, "ms_build_kapply": kap,
+                         "ms_build_linalg": build - kap, "ms_factor": st["ms_factor"] / steps,
+                         "ms_loglik_score": st["ms_loglik"] / steps, "ms_fisher": st["ms_fisher"] / steps,
+                         "sketch_create_s": t_sketch, "device_bytes": st["device_bytes"]})
+            print(f"[bench] scaling: {rows[-1]}", file=sys.stderr, flush=True)
+            H.close(); s.close(); m.close()
+            del H, s, m, y
+            torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,11 +320,18 @@ def main():
                          "regime (sigma2 = 6.4e4; kappa, tau2, sigma2 free; start 1.3 x the truth)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 512 MiB streaming kernel (reference dispatch for HBM counters)")
+    ap.add_argument("--scaling", type=int, default=0, metavar="STEPS",
+                    help="instead of the benchmark, print the cost-against-n sweep (grid sides "
+                         f"{SCALING_SIDES}, ranks {SCALING_RANKS}) timed over STEPS iterations each")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU (--gpus 1); the path is not sharded over "
                                    "several GPUs", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.scaling > 0:
+        print(json.dumps({"scaling_sweep": scaling_run(args.scaling), "steps": args.scaling,
+                          "model": "2D SPDE, kappa 20, alpha 2e-4, tau2 1e-3, sigma2 1, leaf 256"}))
+        return
 
     import numpy as np
     import torch

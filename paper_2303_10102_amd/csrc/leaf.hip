@@ -45,14 +45,20 @@ hm_status leaf_sym(Model* m, const double* Z, int ldz, double* D) {
   return HM_OK;
 }
 
-constexpr int CNB = 32;      // Cholesky block width
-constexpr int NLMAX = 512;   // largest leaf handled
+// Block widths of the leaf Cholesky and the largest leaf each handles: the panel of
+// the block column (all rows below the diagonal block, CB + 1 doubles per row) is
+// held in LDS, 135 KB at width 32 and 512 rows, 153 KB at width 16 and 1152 rows.
+constexpr int CNB = 32;
+constexpr int NLMAX = 512;
+constexpr int CNB_WIDE = 16;
+constexpr int NLMAX_WIDE = 1152;
 
 // Right-looking blocked Cholesky of every leaf, one block column per launch:
 // k_chol_panel factors the diagonal block and solves the rows below it (the
 // panel is held in LDS); the trailing update A22 -= L21 L21^T is a batched
 // MFMA GEMM over all leaves.  logdet[L] accumulates 2 sum log L_ii; a
 // non-positive pivot sets a flag and is replaced by 1 so the kernel completes.
+template <int CNB, int NLMAX>
 __global__ void __launch_bounds__(256) k_chol_panel(double* W, int nl, int jb, double* logdet, int* flags) {
   __shared__ double panel[NLMAX * (CNB + 1)];   // rows jb..nl-1 of the block column
   const int L = blockIdx.x;
@@ -100,6 +106,7 @@ __global__ void __launch_bounds__(256) k_chol_panel(double* W, int nl, int jb, d
 // Inverse of each CNB x CNB diagonal block of the lower factor, written into the
 // same position of Linv.  One workgroup per (block, leaf); thread c < nb solves
 // column c by forward substitution with the block in LDS.
+template <int CNB>
 __global__ void __launch_bounds__(64) k_tri_inv_diag(const double* Lf, double* Linv, int nl) {
   __shared__ double B[CNB * (CNB + 1)];
   __shared__ double X[CNB * (CNB + 1)];
@@ -135,38 +142,48 @@ __global__ void __launch_bounds__(64) k_tri_inv_diag(const double* Lf, double* L
 //   inv([[A, 0], [B, C]]) = [[A^-1, 0], [-C^-1 B A^-1, C^-1]]   (two batched GEMMs per merge).
 hm_status leaf_factor(Model* m, const double* D, double* Dinv, double* logdet_leaf, double* work) {
   const int nl = m->nl;
-  if (nl > NLMAX) {
-    set_error("leaf size exceeds 512");
+  if (nl > NLMAX_WIDE) {
+    set_error("leaf size exceeds 1152");
     return HM_E_INVAL;
   }
+  const bool wide = nl > NLMAX;              // long panels: narrower block columns
+  const int cb = wide ? CNB_WIDE : CNB;
   const long ls = (long)nl * nl;
   const long sz = (long)m->nleaves * ls;
   const int nlv = m->nleaves;
   HM_HIP(hipMemcpyAsync(work, D, sz * sizeof(double), hipMemcpyDeviceToDevice, m->stream));
-  for (int jb = 0; jb < nl; jb += CNB) {
-    hipLaunchKernelGGL(k_chol_panel, dim3(nlv), dim3(256), 0, m->stream, work, nl, jb, logdet_leaf, m->d_flags);
+  for (int jb = 0; jb < nl; jb += cb) {
+    if (wide)
+      hipLaunchKernelGGL((k_chol_panel<CNB_WIDE, NLMAX_WIDE>), dim3(nlv), dim3(256), 0, m->stream, work, nl, jb,
+                         logdet_leaf, m->d_flags);
+    else
+      hipLaunchKernelGGL((k_chol_panel<CNB, NLMAX>), dim3(nlv), dim3(256), 0, m->stream, work, nl, jb,
+                         logdet_leaf, m->d_flags);
     HM_LAUNCH_CHECK();
-    const int j2 = jb + CNB;
+    const int j2 = jb + cb;
     if (j2 < nl) {
       const int r2 = nl - j2;
       const double* L21 = work + j2 + (long)jb * nl;
-      HM_CHECK(gemm(m->stream, false, true, r2, r2, CNB, -1.0, L21, nl, ls, L21, nl, ls, 1.0,
+      HM_CHECK(gemm(m->stream, false, true, r2, r2, cb, -1.0, L21, nl, ls, L21, nl, ls, 1.0,
                     work + j2 + (long)j2 * nl, nl, ls, nlv));
     }
   }
   // Linv (lower) in Dinv
   HM_CHECK(fill(m, Dinv, sz, 0.0));
-  const int nblk = ceil_div(nl, CNB);
-  hipLaunchKernelGGL(k_tri_inv_diag, dim3(nblk, nlv), dim3(64), 0, m->stream, work, Dinv, nl);
+  const int nblk = ceil_div(nl, cb);
+  if (wide)
+    hipLaunchKernelGGL(k_tri_inv_diag<CNB_WIDE>, dim3(nblk, nlv), dim3(64), 0, m->stream, work, Dinv, nl);
+  else
+    hipLaunchKernelGGL(k_tri_inv_diag<CNB>, dim3(nblk, nlv), dim3(64), 0, m->stream, work, Dinv, nl);
   HM_LAUNCH_CHECK();
   // groups: [start, size); merge neighbours pairwise until one group spans the leaf
   std::vector<int> gs, gz;
   for (int k = 0; k < nblk; ++k) {
-    gs.push_back(k * CNB);
-    gz.push_back(std::min(CNB, nl - k * CNB));
+    gs.push_back(k * cb);
+    gz.push_back(std::min(cb, nl - k * cb));
   }
   double* T = m->d_ws;   // scratch for B A^{-1}: needs nleaves * s1 * s0 <= nleaves * nl^2 / 4
-  const long tneed = (long)nlv * (nl / 2 + CNB) * (nl / 2 + CNB);
+  const long tneed = (long)nlv * (nl / 2 + cb) * (nl / 2 + cb);
   if (tneed > 3L * m->n * m->cmax) {
     set_error("leaf_factor: scratch too small");
     return HM_E_INVAL;

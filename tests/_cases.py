@@ -40,6 +40,10 @@ CASES = {
     # 128 rows (leaf rows come in groups of four)
     "1d_n1000": small_workload(dim=1, N=1000, leaf=64, rank=16, kappa=10.0, alpha=0.01, tau2=1e-4, sigma2=1.0e4,
                                free=("kappa", "alpha", "tau2", "sigma2"), name="1d_n1000"),
+    # 2D 51 x 51 with leaves above 512 rows (leaf 600, 2 levels): 51 -> 25 | 26 on both axes,
+    # leaves of 625 to 676 points, stored padded to 676 rows; the leaf Cholesky takes its
+    # narrow-block path (16-column block columns, a ragged last one of 4)
+    "2d_n2601": small_workload(N=51, leaf=600, rank=16, sigma2=1.0e3, name="2d_n2601"),
     # 1D with 1023 points (leaf 64, 3 levels): leaves of 127 and 128 points
     "1d_n1023": small_workload(dim=1, N=1023, leaf=64, rank=16, kappa=10.0, alpha=0.01, tau2=1e-4, sigma2=1.0e4,
                                free=("kappa", "alpha", "tau2", "sigma2"), name="1d_n1023"),

@@ -42,7 +42,7 @@ def _need_gpu():
 
 
 @pytest.fixture(scope="module", params=["1d_n1024", "2d_n1024", "2d_n4096", "2d_n2304", "2d_n2025", "1d_n1023",
-                                        "1d_n1000"])
+                                        "1d_n1000", "2d_n2601"])
 def case(request):
     _need_gpu()
     key = request.param
