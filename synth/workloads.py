@@ -301,3 +301,84 @@ ADR_WORKLOADS = {
     "adr_n65536": AdrWorkload("adr_n65536", 256, 256, 48, 10, 1.0, 2.5, 1.0, 20.0, 1.0, 0.05, 1.0e11,
                               ("kappa", "alpha", "tau2", "sigma2"), 35, 36),
 }
+
+
+@dataclass(frozen=True)
+class SelWorkload:
+    """Observations of a subset of the stencil field's grid points (the observation
+    operator a selection): the physics on the full grid of side N, the nugget on the
+    observations.  obs_kind "regular": nodes stride*s + offset on each axis (s = 0, 1, ...);
+    "random": n_obs distinct nodes drawn with numpy.random.default_rng(obs_seed), sorted."""
+    name: str
+    dim: int
+    N: int
+    obs_kind: str
+    stride: int
+    offset: int
+    n_obs: int
+    obs_seed: int
+    leaf: int
+    rank: int
+    oversample: int
+    kappa: float
+    alpha: float
+    tau2: float
+    sigma2: float
+    free: tuple
+    data_seed: int
+    sketch_seed: int
+
+    def obs(self) -> np.ndarray:
+        """Observed grid indices (x fastest in 2D), in observation order."""
+        if self.obs_kind == "regular":
+            s = np.arange(self.offset, self.N, self.stride)
+            if self.dim == 1:
+                return s.astype(np.int64)
+            return (s[None, :] + self.N * s[:, None]).ravel().astype(np.int64)   # y outer, x inner
+        full = self.N ** self.dim
+        rng = np.random.default_rng(self.obs_seed)
+        return np.sort(rng.choice(full, size=self.n_obs, replace=False)).astype(np.int64)
+
+    @property
+    def n(self) -> int:
+        return int(self.obs().size)
+
+    @property
+    def levels(self) -> int:
+        return int(math.floor(math.log2(self.n / self.leaf)))
+
+    @property
+    def ell(self) -> int:
+        return self.rank + self.oversample
+
+    @property
+    def theta_full(self) -> np.ndarray:
+        return np.array([self.kappa, self.alpha, self.tau2, self.sigma2], dtype=np.float64)
+
+    @property
+    def free_idx(self) -> tuple:
+        return tuple(PARAM_NAMES.index(f) for f in self.free)
+
+    def field(self) -> Workload:
+        """The full-grid workload with the same parameters and data seed."""
+        return Workload(self.name + "_grid", self.dim, self.N, self.leaf, self.rank, self.oversample, self.kappa,
+                        self.alpha, self.tau2, self.sigma2, self.free, self.data_seed, self.sketch_seed)
+
+    def sample(self) -> np.ndarray:
+        """A draw of the full field (sample_y) read at the observed nodes."""
+        return sample_y(self.field())[self.obs()]
+
+
+SEL_WORKLOADS = {
+    # the 256^2 headline field observed on the regular 64 x 64 subgrid of nodes 4 s + 1
+    # (n = 4096, leaf 256, 4 levels, rank 48 + 10; physics at 256^2)
+    "sel_n4096": SelWorkload("sel_n4096", 2, 256, "regular", 4, 1, 0, 0, 256, 48, 10, 20.0, 2e-4, 1e-3, 1.0,
+                             ("kappa", "alpha", "tau2", "sigma2"), 41, 42),
+    # 1500 random nodes of a 48 x 48 grid (partial, irregular observations), leaf 64,
+    # rank 16 + 10, physics-dominated scale
+    "sel_n1500": SelWorkload("sel_n1500", 2, 48, "random", 0, 0, 1500, 43, 64, 16, 10, 20.0, 2e-4, 1e-3, 1.0e3,
+                             ("kappa", "alpha", "tau2", "sigma2"), 44, 45),
+    # 1D: 700 random points of a 1000-point line, leaf 64
+    "sel1d_n700": SelWorkload("sel1d_n700", 1, 1000, "random", 0, 0, 700, 46, 64, 16, 10, 10.0, 0.01, 1e-4, 1.0e4,
+                              ("kappa", "alpha", "tau2", "sigma2"), 47, 48),
+}
