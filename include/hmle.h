@@ -100,10 +100,18 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
  *   h: grid spacing (> 0) of the Dirichlet stencil (-Laplacian = (1/h^2) x 3-/5-point);
  *      hm_model_create uses h = 1/(N+1), the unit interval / square;
  *   nvars: variables per location (1);
- *   obs_idx, nobs: the observed grid points (observation operator = selection of these
- *      rows, nobs distinct grid indices), or NULL / nobs = 0 for every point.
- * Currently nx = ny for dim 2, nvars = 1 and obs_idx = NULL; anything else returns
- * HM_E_INVAL naming what is not supported. */
+ *   obs_idx, nobs: the observed grid points, or NULL / nobs = 0 for every point.  With a
+ *      selection (host array of nobs distinct grid indices, read during the call; the
+ *      observation operator Phi of eq. "projection" reads these nodes, Sec. 5.2.1 forms
+ *      its smaller data sets this way) the model is K = sigma2 Phi A^{-1} B^{-1} B^{-T}
+ *      A^{-T} Phi^T + tau2 I of dimension nobs: the physics on the full grid, the nugget
+ *      on the observations.  Its tree is the KD-tree of the observed nodes' (x, y) grid
+ *      positions (as hm_model_create_op), observation order = obs_idx order, leaves padded
+ *      (hm_model_rows); each K-apply spreads its columns onto the full grid, applies the
+ *      full-grid transforms and reads the observed nodes back.  Needs nobs >= 2 leaf and
+ *      the full grid valid for leaf; out-of-range or repeated indices: HM_E_INVAL.
+ * Currently nx = ny for dim 2 and nvars = 1; anything else returns HM_E_INVAL naming
+ * what is not supported. */
 hm_status hm_model_create_spde(hm_ctx* ctx, int dim, int nx, int ny, double h, int nvars, const int* obs_idx,
                                long long nobs, int leaf, hm_model** out);
 /* A model on n scattered points with a caller-supplied operator: K(theta) =

@@ -560,9 +560,13 @@ static std::vector<std::vector<int>> point_leaves(int dim, const double* xy, int
   return nodes;
 }
 
+}  // extern "C"
+
+namespace hm {
+
 // A model on an N (x N) Dirichlet grid with spacing h, its device memory from ctx.
-static hm_status model_create(Ctx* ctx, int device, void* stream, int dim, int N, double h, int leaf,
-                              hm_model** out) {
+hm_status model_create(Ctx* ctx, int device, void* stream, int dim, int N, double h, int leaf,
+                       hm_model** out) {
   if (!out) {
     set_error("out is NULL");
     return HM_E_INVAL;
@@ -700,6 +704,10 @@ static hm_status model_create(Ctx* ctx, int device, void* stream, int dim, int N
   *out = hm_;
   return HM_OK;
 }
+
+}  // namespace hm
+
+extern "C" {
 
 hm_status hm_ctx_create(int device, void* stream, hm_alloc_fn alloc, hm_free_fn release, void* uctx,
                         hm_ctx** out) {
@@ -873,8 +881,15 @@ hm_status hm_model_create_spde(hm_ctx* ctx, int dim, int nx, int ny, double h, i
     return HM_E_INVAL;
   }
   if (obs_idx != nullptr || nobs != 0) {
-    set_error("hm_model_create_spde: observation selections are not supported");
-    return HM_E_INVAL;
+    if (!obs_idx || nobs <= 0) {
+      set_error("hm_model_create_spde: obs_idx and nobs must be given together");
+      return HM_E_INVAL;
+    }
+    if (!(h > 0.0) || !std::isfinite(h)) {
+      set_error("hm_model_create_spde: need h > 0");
+      return HM_E_INVAL;
+    }
+    return model_create_selection(&ctx->c, dim, nx, h, obs_idx, (long)nobs, leaf, out);
   }
   return model_create(&ctx->c, ctx->c.device, ctx->c.stream, dim, nx, h, leaf, out);
 }
@@ -1187,7 +1202,7 @@ hm_status hm_H_create(hm_sketch* hs, int p, const int* free_idx, hm_H** out) {
   AL(h->adj.Fb, pset);
   AL(h->adj.Gs, pset);
   AL(h->adj.Zb, (size_t)n * nl);
-  AL(h->adj.wmode, 3 * (size_t)n + 8);   // per-mode weights (an operator's may use two sets and a sum)
+  AL(h->adj.wmode, (size_t)wmode_doubles(m));   // per-mode weights (an operator's may use two sets and a sum)
   AL(h->adj.tmpK, nk);
   AL(h->adj.uT, nodes * tw);
   AL(h->ytree, (size_t)n);

@@ -196,7 +196,7 @@ hm_status adjoint_sweep(Model* m, const double theta[4], const Sketch* s, const 
                         const NodeBufs& nb, AdjBufs& a) {
   const int n = m->n, nl = m->nl, levels = m->levels, kc = ps.bw;
   const long s2 = (long)kc * kc;
-  HM_CHECK(fill(m, a.wmode, 3L * n + 8, 0.0));
+  HM_CHECK(fill(m, a.wmode, wmode_doubles(m), 0.0));
   // leaf pass
   HM_CHECK(kvjp(m, theta, m->d_ident, n, a.Zb, n, nl, a.wmode));
   HM_CHECK(subtract_adjoint(m, ps.F, kc, levels + 1, m->d_ident, nl, sel_all(), a.Zb, sel_all(), a.Fb, -1.0, nb.t,

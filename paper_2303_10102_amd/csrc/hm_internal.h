@@ -10,6 +10,7 @@
 //     x are 2x+1 and 2x+2) with a fixed stride per node.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -166,6 +167,7 @@ struct Model {
   hm_status (*op_vjp)(Model*, const double* theta, const double* X, int ldx, const double* Yb, int ldb, int c,
                       double* wmode) = nullptr;
   hm_status (*op_vjp_final)(Model*, const double* theta, const double* wmode, double* out4) = nullptr;
+  long op_wmode = 0;        // doubles of per-mode weights op_vjp needs, if above the default 3 n + 8
   double h = 0.0;
   int* d_perm = nullptr;    // tree position -> grid index (-1 for a padding row)
   int* d_iperm = nullptr;   // grid index -> tree position
@@ -324,6 +326,13 @@ hm_status check_theta(const Model* m, const double* t);
 // an operator model (the points' KD-tree, padded leaves) with op applying K_op
 hm_status model_create_op(Ctx* cx, int dim, const double* coords, int n, int leaf, hm_op_fn op, void* uctx,
                           bool builtin, hm_model** out);
+// the stencil model on a full grid (side N, spacing h)
+hm_status model_create(Ctx* ctx, int device, void* stream, int dim, int N, double h, int leaf, hm_model** out);
+// an observed subset of the stencil model's grid points (select.hip)
+hm_status model_create_selection(Ctx* cx, int dim, int N, double h, const int* obs, long nobs, int leaf,
+                                 hm_model** out);
+// length of the per-mode weight buffer of the reverse sweep
+inline long wmode_doubles(const Model* m) { return std::max(3L * m->n + 8, m->op_wmode); }
 constexpr int OPWS_DOUBLES = 1024 * 16 + 16;   // d_opws: dot partials + 4 results
 // time the panel-kernel variants on this model's shapes (panel width kc) and keep the fastest
 hm_status autotune(Model* m, int kc, double* report);

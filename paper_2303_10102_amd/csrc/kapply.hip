@@ -578,7 +578,7 @@ k_dst_inv_fold(const double* Ph, const double* W, MultiOut mo, TreeIdx tix,
   tile_store2(DstStScatterUnfold<AM>{mo.y_of(q), ldy, tix, cg, N, H, m0, ym}, e, o);
 }
 
-static hm_status ensure_scale(Model* m, const double theta[4]) {
+hm_status ensure_scale(Model* m, const double theta[4]) {
   bool same = true;
   for (int i = 0; i < 4; ++i) same = same && (m->lam_key[i] == theta[i]);
   if (same) return HM_OK;

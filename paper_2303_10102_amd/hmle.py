@@ -179,19 +179,27 @@ class Model:
     """SPDE stencil covariance model on a dim-D Dirichlet grid of side N.
 
     Device memory comes from a Context (by default one of its own backed by torch's
-    caching allocator); h is the grid spacing (default 1/(N+1), the unit square)."""
+    caching allocator); h is the grid spacing (default 1/(N+1), the unit square).
+    obs: optional grid indices (x fastest in 2D) of the observed nodes; the model is then
+    the observed subset (n = len(obs), observation order = obs), the physics on the full
+    grid and the nugget on the observations."""
 
-    def __init__(self, dim, N, leaf, device=0, stream=None, ctx=None, h=None, allocator="torch"):
+    def __init__(self, dim, N, leaf, device=0, stream=None, ctx=None, h=None, allocator="torch", obs=None):
         import torch
         self.device = torch.device("cuda", device)
         self.ctx = ctx if ctx is not None else Context(device, stream, allocator)
         self._own_ctx = ctx is None
         hh = _P()
         spacing = 1.0 / (N + 1) if h is None else float(h)
+        if obs is None:
+            oidx, nobs = None, 0
+        else:
+            self._obs = np.ascontiguousarray(np.asarray(obs), dtype=np.int32)
+            oidx, nobs = self._obs.ctypes.data_as(C.POINTER(C.c_int)), int(self._obs.size)
         with torch.cuda.device(device):
             _check("hm_model_create_spde",
-                   lib().hm_model_create_spde(self.ctx._h, dim, N, N if dim == 2 else 1, spacing, 1, None, 0, leaf,
-                                              C.byref(hh)))
+                   lib().hm_model_create_spde(self.ctx._h, dim, N, N if dim == 2 else 1, spacing, 1, oidx, nobs,
+                                              leaf, C.byref(hh)))
         self._h = hh
         n, lv, lf = _I(), _I(), _I()
         _check("hm_model_info", lib().hm_model_info(hh, C.byref(n), C.byref(lv), C.byref(lf)))

@@ -62,3 +62,20 @@ def test_context_and_model_arguments_are_checked_without_a_device():
     assert L.hm_solve(None, None, None, 0, 0) == 1
     assert L.hm_stats(None, None, 0) == 1
     assert L.hm_grad_reverse(None, None) == 1
+
+
+def test_observation_selection_is_checked_without_a_device():
+    from paper_2303_10102_amd import hmle
+    if not hmle.LIBPATH.exists():
+        pytest.skip("libhmle.so not built")
+    import ctypes as C
+    L = hmle.lib()
+    out = C.c_void_p()
+    ctx = C.c_void_p(1)          # never dereferenced: the selection is rejected first
+    bad = [((C.c_int * 3)(0, 5, 5), 3, b"repeated"), ((C.c_int * 3)(0, 5, 256), 3, b"outside"),
+           ((C.c_int * 3)(0, 5, -1), 3, b"outside"), ((C.c_int * 1)(0), 1, b"nobs")]
+    for idx, nobs, msg in bad:
+        assert L.hm_model_create_spde(ctx, 2, 16, 16, 1.0 / 17, 1, idx, nobs, 4, C.byref(out)) == 1
+        assert msg in L.hm_last_error(), L.hm_last_error()
+    # an index array without a count
+    assert L.hm_model_create_spde(ctx, 2, 16, 16, 1.0 / 17, 1, (C.c_int * 2)(0, 1), 0, 4, C.byref(out)) == 1
