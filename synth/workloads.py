@@ -382,3 +382,83 @@ SEL_WORKLOADS = {
     "sel1d_n700": SelWorkload("sel1d_n700", 1, 1000, "random", 0, 0, 700, 46, 64, 16, 10, 10.0, 0.01, 1e-4, 1.0e4,
                               ("kappa", "alpha", "tau2", "sigma2"), 47, 48),
 }
+
+
+BIV_PARAM_NAMES = ("kappa", "alpha", "tau2", "sigma2", "tau2_2")
+
+
+@dataclass(frozen=True)
+class BivWorkload:
+    """Bivariate co-kriging on an N x N (or N) Dirichlet grid: y1 = sigma B^-1 w + tau1 eps1,
+    y2 = sigma A^-1 B^-1 w + tau2 eps2 at every node, stacked y = (y1; y2);
+    theta_full = (kappa, alpha, tau2_1, sigma2, tau2_2)."""
+    name: str
+    dim: int
+    N: int
+    leaf: int
+    rank: int
+    oversample: int
+    kappa: float
+    alpha: float
+    tau2: float
+    sigma2: float
+    tau2_2: float
+    free: tuple
+    data_seed: int
+    sketch_seed: int
+
+    @property
+    def n_loc(self) -> int:
+        return self.N if self.dim == 1 else self.N * self.N
+
+    @property
+    def n(self) -> int:
+        return 2 * self.n_loc
+
+    @property
+    def levels(self) -> int:
+        return int(math.floor(math.log2(self.n / self.leaf)))
+
+    @property
+    def ell(self) -> int:
+        return self.rank + self.oversample
+
+    @property
+    def theta_full(self) -> np.ndarray:
+        return np.array([self.kappa, self.alpha, self.tau2, self.sigma2, self.tau2_2], dtype=np.float64)
+
+    @property
+    def free_idx(self) -> tuple:
+        return tuple(BIV_PARAM_NAMES.index(f) for f in self.free)
+
+    def sample(self) -> np.ndarray:
+        """w, eps1, eps2 drawn from default_rng(data_seed) in that order (natural order)."""
+        rng = np.random.default_rng(self.data_seed)
+        wv = rng.standard_normal(self.n_loc)
+        e1 = rng.standard_normal(self.n_loc)
+        e2 = rng.standard_normal(self.n_loc)
+        T = _lap(self.dim, self.N)
+        I = sp.identity(self.n_loc, format="csc")
+        A = (I + self.alpha * T).tocsc()
+        B = (self.kappa ** 2 * I + T).tocsc()
+        u = spla.spsolve(B, wv)
+        v = spla.spsolve(A, u)
+        s = math.sqrt(self.sigma2)
+        return np.r_[s * u + math.sqrt(self.tau2) * e1, s * v + math.sqrt(self.tau2_2) * e2]
+
+
+BIV_WORKLOADS = {
+    # 24 x 24 locations x 2 variables (n = 1152), leaf 128 (3 levels), rank 16 + 10
+    "biv_n1152": BivWorkload("biv_n1152", 2, 24, 128, 16, 10, 20.0, 2e-4, 1e-3, 2.0e3, 2e-3,
+                             ("kappa", "alpha", "tau2", "sigma2", "tau2_2"), 51, 52),
+    # odd sides: 21 x 21 x 2 (n = 882), leaf 96 (3 levels), uneven location leaves
+    "biv_n882": BivWorkload("biv_n882", 2, 21, 96, 16, 10, 20.0, 2e-4, 1e-3, 2.0e3, 2e-3,
+                            ("kappa", "alpha", "tau2", "sigma2", "tau2_2"), 53, 54),
+    # 1D: 500 locations x 2 (n = 1000), leaf 64 (3 levels), two free nuggets and kappa
+    "biv1d_n1000": BivWorkload("biv1d_n1000", 1, 500, 64, 16, 10, 10.0, 0.01, 1e-4, 1.0e4, 3e-4,
+                               ("kappa", "tau2", "sigma2", "tau2_2"), 55, 56),
+    # the co-kriging workload: 362 x 362 x 2 (n = 262088), leaf 512 (8 levels, leaves of up to
+    # 2 x 529 rows), rank 64 + 10, theta = (kappa, alpha, tau2_1, sigma2, tau2_2)
+    "biv_n262088": BivWorkload("biv_n262088", 2, 362, 512, 64, 10, 20.0, 2e-4, 1e-3, 1.0, 2e-3,
+                               ("kappa", "alpha", "tau2", "sigma2", "tau2_2"), 57, 58),
+}
