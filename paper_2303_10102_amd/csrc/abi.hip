@@ -38,11 +38,11 @@ struct HState {
   Sketch* s = nullptr;
   Model* m = nullptr;
   int p = 0;
-  int pidx[4] = {0, 0, 0, 0};
+  int pidx[5] = {0, 0, 0, 0, 0};
   int nreal = 0;
   int realidx[2] = {-1, -1};   // parameter kind (0 kappa, 1 alpha) of each real derivative
-  int realpos[4] = {-1, -1, -1, -1};  // free position -> real derivative slot
-  double theta[4] = {0, 0, 0, 0};
+  int realpos[5] = {-1, -1, -1, -1, -1};  // free position -> real derivative slot
+  double theta[5] = {0, 0, 0, 0, 0};     // theta_full; [4] the second nugget (bivariate model)
   int state = 0;               // 0 empty, 1 built, 2 factored, 3 parameters prepared
   long long gen = 0;           // incremented by every construction
   long long z_gen = -1;        // construction that z = K~^{-1} y belongs to
@@ -53,7 +53,7 @@ struct HState {
   double* D = nullptr;
   double* dDr[2] = {nullptr, nullptr};
   FactorCtx f;
-  ParamBufs pb[4];
+  ParamBufs pb[5];
   LevelBufs lb;
   NodeBufs nb;
   AdjBufs adj;
@@ -145,26 +145,22 @@ static hm_status dalloc(HState* h, double** p, size_t doubles) {
   return HM_OK;
 }
 
-static bool finite4(const double* t) {
-  for (int i = 0; i < 4; ++i)
-    if (!std::isfinite(t[i])) return false;
-  return true;
-}
-
 hm_status check_theta(const Model* m, const double* t) {
   if (!t) {
     set_error("theta is NULL");
     return HM_E_INVAL;
   }
-  if (!finite4(t)) {
-    set_error("theta has a non-finite entry");
-    return HM_E_NONFINITE;
-  }
-  if (!(t[2] > 0.0) || !(t[3] > 0.0)) {
-    set_error("theta must satisfy tau2 > 0, sigma2 > 0");
+  for (int i = 0; i < nparams(m); ++i)
+    if (!std::isfinite(t[i])) {
+      set_error("theta has a non-finite entry");
+      return HM_E_NONFINITE;
+    }
+  if (!(t[2] > 0.0) || !(t[3] > 0.0) || (m->nvars == 2 && !(t[4] > 0.0))) {
+    set_error(m->nvars == 2 ? "theta must satisfy tau2_1 > 0, sigma2 > 0, tau2_2 > 0"
+                            : "theta must satisfy tau2 > 0, sigma2 > 0");
     return HM_E_INVAL;
   }
-  if (!m->op && (!(t[0] > 0.0) || !(t[1] >= 0.0))) {
+  if ((!m->op || m->nvars == 2) && (!(t[0] > 0.0) || !(t[1] >= 0.0))) {
     set_error("theta must satisfy kappa > 0, alpha >= 0, tau2 > 0, sigma2 > 0");
     return HM_E_INVAL;
   }
@@ -234,7 +230,31 @@ static hm_status solve_refined_w(HState* h, const double* y, double* z, double* 
 static hm_status solve_refined(HState* h) { return solve_refined_w(h, h->ytree, h->z, h->r, h->v, 1); }
 
 // scalar slots in d_scal
-enum : int { SC_LOGDET = 0, SC_YZ = 1, SC_QUAD = 2, SC_LTR = 6, SC_NTR = 10, SC_FIM = 16, SC_ADJ = 110 };
+// scalar slots (device d_scal / pinned h_scal): per free parameter (up to 5) quadratic
+// forms, leaf and node traces; the two log-determinant parts; five Fisher terms of
+// 5 x 5 entries; the reverse sweep's five sums
+enum : int { SC_YZ = 1, SC_QUAD = 2, SC_LTR = 8, SC_NTR = 14, SC_LD = 20, SC_FIM = 24, SC_FT = 25, SC_ITER_END = 150,
+             SC_ADJ = 160 };
+
+// out[i nb + j] = <A_i, B_j> for up to 5 x 5 operands (the dot kernels take 4 x 4 at once)
+static hm_status dots_any(Model* m, const double* const* A, int na, const double* const* B, int nb, long len,
+                          double* out, double* part) {
+  if (na <= 4 && nb <= 4) return dots(m, A, na, B, nb, len, out, part);
+  for (int i = 0; i < na; ++i) {
+    HM_CHECK(dots(m, A + i, 1, B, std::min(nb, 4), len, out + i * nb, part));
+    if (nb > 4) HM_CHECK(dots(m, A + i, 1, B + 4, nb - 4, len, out + i * nb + 4, part));
+  }
+  return HM_OK;
+}
+static hm_status dots_leafT_any(Model* m, const double* const* A, int na, const double* const* B, int nb,
+                                double* out, double* part) {
+  if (na <= 4 && nb <= 4) return dots_leafT(m, A, na, B, nb, out, part);
+  for (int i = 0; i < na; ++i) {
+    HM_CHECK(dots_leafT(m, A + i, 1, B, std::min(nb, 4), out + i * nb, part));
+    if (nb > 4) HM_CHECK(dots_leafT(m, A + i, 1, B + 4, nb - 4, out + i * nb + 4, part));
+  }
+  return HM_OK;
+}
 
 static hm_status need_deriv(HState* h, const char* who) {
   if (h->nreal > 0 && !h->have_deriv) {
@@ -307,7 +327,8 @@ static hm_status build_enqueue(HState* h, const double* theta_full, bool deriv) 
   Model* m = h->m;
   h->state = 0;
   h->have_deriv = false;
-  std::memcpy(h->theta, theta_full, sizeof(h->theta));
+  std::memcpy(h->theta, theta_full, nparams(m) * sizeof(double));
+  if (m->nvars == 1) h->theta[4] = h->theta[2];
   HM_CHECK(clear_flags(m));
   const int n = m->n, kc = h->kc;
   const int nr = deriv ? h->nreal : 0;
@@ -332,8 +353,8 @@ static hm_status factor_enqueue(HState* h) {
   phase_begin(h, PH_FACTOR);
   HM_CHECK(factorize(h->f));
   // log|K~| = sum of leaf and node parts
-  HM_CHECK(sum_scalar(m, h->f.logdet_leaf, m->nleaves, 0, h->d_scal + 100, h->d_part));
-  HM_CHECK(sum_scalar(m, h->f.logdet_node, (1 << m->levels) - 1, 0, h->d_scal + 101, h->d_part));
+  HM_CHECK(sum_scalar(m, h->f.logdet_leaf, m->nleaves, 0, h->d_scal + SC_LD, h->d_part));
+  HM_CHECK(sum_scalar(m, h->f.logdet_node, (1 << m->levels) - 1, 0, h->d_scal + SC_LD + 1, h->d_part));
   phase_end(h, PH_FACTOR);
   h->factors += 1;
   h->state = 2;
@@ -371,16 +392,16 @@ static hm_status loglik_enqueue(HState* h, const double* y, bool want_grad) {
   // node part of every trace: <N_P, PsiP^j> summed over internal nodes
   const long ms = 4L * h->kc * h->kc;
   const double* nv[1] = {h->f.Nn};
-  const double* pv[4];
+  const double* pv[5];
   for (int q = 0; q < h->p; ++q) pv[q] = h->pb[q].PsiP;
-  HM_CHECK(dots(m, nv, 1, pv, h->p, ((1L << m->levels) - 1) * ms, h->d_scal + SC_NTR, h->d_part));
+  HM_CHECK(dots_any(m, nv, 1, pv, h->p, ((1L << m->levels) - 1) * ms, h->d_scal + SC_NTR, h->d_part));
   phase_end(h, PH_LOGLIK);
   return HM_OK;
 }
 
 static hm_status loglik_collect(HState* h, double* loglik, double* grad) {
   const int n = h->m->n_real;
-  const double logdet = h->h_scal[100] + h->h_scal[101];
+  const double logdet = h->h_scal[SC_LD] + h->h_scal[SC_LD + 1];
   const double yz = h->h_scal[SC_YZ];
   *loglik = -0.5 * n * std::log(2.0 * M_PI) - 0.5 * logdet - 0.5 * yz;
   if (!std::isfinite(*loglik)) {
@@ -403,11 +424,11 @@ static hm_status fisher_enqueue(HState* h) {
   phase_begin(h, PH_FISHER);
   h->fisher_evals += 1;
   HM_CHECK(prepare_params(h));
-  // tau2 before sigma2: sigma2's tangent sweep is a combination of tau2's
+  // tau2 before sigma2: sigma2's tangent sweep is a combination of tau2's (one nugget)
   int qt = -1;
   for (int q = 0; q < p; ++q)
-    if (h->pb[q].kind == 2) qt = q;
-  int order[4], no = 0;
+    if (h->pb[q].kind == 2 && m->nvars == 1) qt = q;
+  int order[5], no = 0;
   for (int q = 0; q < p; ++q)
     if (h->pb[q].kind != 3) order[no++] = q;
   for (int q = 0; q < p; ++q)
@@ -424,23 +445,23 @@ static hm_status fisher_enqueue(HState* h) {
   const long pset = (long)n * levels * kc;
   const long s2 = (long)kc * kc;
   const long nint = (1 << levels) - 1, nodes = (2L << levels) - 1;
-  const double *A[4], *B[4];
+  const double *A[5], *B[5];
   double* out = h->d_scal + SC_FIM;
   // term 0: 1/2 sum_L tr(Y^i_L Y^j_L)  (Y^j transposed is dD_j Dinv)
   for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Y; B[q] = h->pb[q].Y; }
-  HM_CHECK(dots_leafT(m, A, p, B, p, out + 0 * 16, h->d_part));
+  HM_CHECK(dots_leafT_any(m, A, p, B, p, out + 0 * SC_FT, h->d_part));
   // term 1: -1/2 <Lam^i, PsiP^j>
   for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Lam; B[q] = h->pb[q].PsiP; }
-  HM_CHECK(dots(m, A, p, B, p, nint * 4 * s2, out + 1 * 16, h->d_part));
+  HM_CHECK(dots_any(m, A, p, B, p, nint * 4 * s2, out + 1 * SC_FT, h->d_part));
   // term 2: <Gh^i, Xi^j>
   for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Gh; B[q] = h->pb[q].Xi; }
-  HM_CHECK(dots(m, A, p, B, p, pset, out + 2 * 16, h->d_part));
+  HM_CHECK(dots_any(m, A, p, B, p, pset, out + 2 * SC_FT, h->d_part));
   // term 3: <Hh^i, dF^j>
   for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Hh; B[q] = h->pb[q].dF; }
-  HM_CHECK(dots(m, A, p, B, p, pset, out + 3 * 16, h->d_part));
+  HM_CHECK(dots_any(m, A, p, B, p, pset, out + 3 * SC_FT, h->d_part));
   // term 4: <Vt^i, E^j> over non-root nodes
   for (int q = 0; q < p; ++q) { A[q] = h->pb[q].Vt + s2; B[q] = h->pb[q].E + s2; }
-  HM_CHECK(dots(m, A, p, B, p, (nodes - 1) * s2, out + 4 * 16, h->d_part));
+  HM_CHECK(dots_any(m, A, p, B, p, (nodes - 1) * s2, out + 4 * SC_FT, h->d_part));
   phase_end(h, PH_FISHER);
   return HM_OK;
 }
@@ -451,7 +472,7 @@ static hm_status fisher_collect(HState* h, double* fim) {
   for (int i = 0; i < p; ++i)
     for (int j = 0; j < p; ++j) {
       const int q = i * p + j;
-      fim[q] = 0.5 * t[q] - 0.5 * t[16 + q] + t[32 + q] + t[48 + q] + t[64 + q];
+      fim[q] = 0.5 * t[q] - 0.5 * t[SC_FT + q] + t[2 * SC_FT + q] + t[3 * SC_FT + q] + t[4 * SC_FT + q];
       if (!std::isfinite(fim[q])) {
         set_error("non-finite Fisher information");
         return HM_E_NONFINITE;
@@ -468,7 +489,7 @@ static hm_status iteration_enqueue(HState* h, const double* theta_full, const do
   HM_CHECK(factor_enqueue(h));
   HM_CHECK(loglik_enqueue(h, y, want_grad));
   if (want_fim && h->p > 0) HM_CHECK(fisher_enqueue(h));
-  HM_CHECK(fetch_scalars(h, 0, 128));
+  HM_CHECK(fetch_scalars(h, 0, SC_ITER_END));
   return HM_OK;
 }
 
@@ -746,13 +767,13 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
 namespace hm {
 
 hm_status model_create_op(Ctx* cx, int dim, const double* coords, int n, int leaf, hm_op_fn op, void* uctx,
-                          bool builtin, hm_model** out) {
+                          bool builtin, hm_model** out, int nv) {
   if (!cx || !coords || !op || !out) {
     set_error("NULL argument");
     return HM_E_INVAL;
   }
   *out = nullptr;
-  if ((dim != 1 && dim != 2) || n < 2 || leaf < 1 || n > (1 << 26)) {
+  if ((dim != 1 && dim != 2) || n < 2 || leaf < 1 || nv < 1 || nv > 2 || (long)nv * n > (1 << 26)) {
     set_error("need dim in {1,2}, 2 <= n <= 2^26, leaf >= 1");
     return HM_E_INVAL;
   }
@@ -761,16 +782,17 @@ hm_status model_create_op(Ctx* cx, int dim, const double* coords, int n, int lea
       set_error("hm_model_create_op: non-finite coordinate");
       return HM_E_NONFINITE;
     }
-  const int levels = (int)std::floor(std::log2((double)n / leaf) + 1e-12);
+  // the tree bisects the points; each point contributes nv rows (its variables)
+  const int levels = (int)std::floor(std::log2((double)nv * n / leaf) + 1e-12);
   if (levels < 1 || levels > 20) {
     set_error("need n >= 2*leaf");
     return HM_E_INVAL;
   }
   std::vector<std::vector<int>> leaves = point_leaves(dim, coords, n, levels);
-  int nlp = 0, nlmin = n;
+  int nlp = 0, nlmin = nv * n;
   for (const auto& v : leaves) {
-    nlp = std::max(nlp, (int)v.size());
-    nlmin = std::min(nlmin, (int)v.size());
+    nlp = std::max(nlp, nv * (int)v.size());
+    nlmin = std::min(nlmin, nv * (int)v.size());
   }
   nlp = (nlp + 3) / 4 * 4;   // rows of a leaf in groups of four (see model_create)
   const long rows = (long)nlp << levels;
@@ -791,7 +813,9 @@ hm_status model_create_op(Ctx* cx, int dim, const double* coords, int n, int lea
   m->dim = dim;
   m->N = 0;
   m->n = (int)rows;
-  m->n_real = n;
+  m->n_real = nv * n;
+  m->nvars = nv;
+  m->nsplit = n;
   m->uniform = false;
   m->levels = levels;
   m->nleaves = 1 << levels;
@@ -807,7 +831,7 @@ hm_status model_create_op(Ctx* cx, int dim, const double* coords, int n, int lea
     ok = ok && *p;
   };
   A((void**)&m->d_perm, rows * sizeof(int));
-  A((void**)&m->d_iperm, (size_t)n * sizeof(int));
+  A((void**)&m->d_iperm, (size_t)nv * n * sizeof(int));
   A((void**)&m->d_pad2tree, rows * sizeof(int));
   A((void**)&m->d_ws, 5 * (size_t)rows * m->cmax * sizeof(double));
   A((void**)&m->d_flags, sizeof(int));
@@ -818,18 +842,20 @@ hm_status model_create_op(Ctx* cx, int dim, const double* coords, int n, int lea
     hm_model_destroy(hm_);
     return HM_E_NOMEM;
   }
-  std::vector<int> perm(rows, -1), iperm(n, -1), pad2tree(rows, -1);
+  // a point's nv rows are adjacent (variable 1 first); natural index v n + point
+  std::vector<int> perm(rows, -1), iperm((size_t)nv * n, -1), pad2tree(rows, -1);
   int real = 0;
   for (int L = 0; L < (int)leaves.size(); ++L)
-    for (int i = 0; i < (int)leaves[L].size(); ++i) {
-      const int g = leaves[L][i], p = L * nlp + i;
-      perm[p] = g;
-      iperm[g] = p;
-      pad2tree[p] = real++;
-    }
+    for (int i = 0; i < (int)leaves[L].size(); ++i)
+      for (int v = 0; v < nv; ++v) {
+        const int g = v * n + leaves[L][i], p = L * nlp + nv * i + v;
+        perm[p] = g;
+        iperm[g] = p;
+        pad2tree[p] = real++;
+      }
   hm_status st = HM_OK;
   if (hipMemcpy(m->d_perm, perm.data(), rows * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(m->d_iperm, iperm.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->d_iperm, iperm.data(), (size_t)nv * n * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(m->d_pad2tree, pad2tree.data(), rows * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
     set_error("model creation: copy of the tree tables failed");
     st = HM_E_DEVICE;
@@ -876,9 +902,16 @@ hm_status hm_model_create_spde(hm_ctx* ctx, int dim, int nx, int ny, double h, i
     set_error("hm_model_create_spde: grids with nx != ny are not supported");
     return HM_E_INVAL;
   }
-  if (nvars != 1) {
-    set_error("hm_model_create_spde: only nvars = 1 is supported");
+  if (nvars != 1 && nvars != 2) {
+    set_error("hm_model_create_spde: nvars must be 1 or 2");
     return HM_E_INVAL;
+  }
+  if (nvars == 2) {
+    if (obs_idx != nullptr || nobs != 0) {
+      set_error("hm_model_create_spde: observation selections of the bivariate model are not supported");
+      return HM_E_INVAL;
+    }
+    return model_create_bivariate(&ctx->c, dim, nx, h, leaf, out);
   }
   if (obs_idx != nullptr || nobs != 0) {
     if (!obs_idx || nobs <= 0) {
@@ -1078,7 +1111,7 @@ void hm_H_destroy(hm_H* hh) {
 }
 
 hm_status hm_H_create(hm_sketch* hs, int p, const int* free_idx, hm_H** out) {
-  if (!hs || !out || (p > 0 && !free_idx) || p < 0 || p > 4) {
+  if (!hs || !out || (p > 0 && !free_idx) || p < 0 || p > nparams(hs->s.m)) {
     set_error("bad arguments to hm_H_create");
     return HM_E_INVAL;
   }
@@ -1090,12 +1123,14 @@ hm_status hm_H_create(hm_sketch* hs, int p, const int* free_idx, hm_H** out) {
   Model* m = h->m;
   h->p = p;
   h->kc = hs->s.kc;
-  bool seen[4] = {false, false, false, false};
+  bool seen[5] = {false, false, false, false, false};
+  const int np = nparams(m);
   for (int q = 0; q < p; ++q) {
     int k = free_idx[q];
-    if (k < 0 || k > 3 || seen[k]) {
+    if (k < 0 || k >= np || seen[k]) {
       delete hh;
-      set_error("free_idx entries must be distinct values in 0..3");
+      set_error(np == 5 ? "free_idx entries must be distinct values in 0..4" :
+                          "free_idx entries must be distinct values in 0..3");
       return HM_E_INVAL;
     }
     seen[k] = true;
@@ -1155,7 +1190,7 @@ hm_status hm_H_create(hm_sketch* hs, int p, const int* free_idx, hm_H** out) {
       AL(pb.dF, pset);
       AL(pb.dD, lset);
     }
-    if (pb.kind == 2) {          // Xi = G, Y = Dinv (restricted to the real rows), Psi = G^T G
+    if (pb.kind == 2 && m->nvars == 1) {   // Xi = G, Y = Dinv (restricted to the real rows), Psi = G^T G
       pb.Xi = f.G;
       if (m->uniform) pb.Y = f.Dinv;
       else AL(pb.Y, lset);
@@ -1253,7 +1288,7 @@ hm_status hm_factor(hm_H* hh) {
     return HM_E_STATE;
   }
   HM_CHECK(factor_enqueue(h));
-  HM_CHECK(fetch_scalars(h, 0, 128));
+  HM_CHECK(fetch_scalars(h, 0, SC_ITER_END));
   HM_CHECK(sync_check(h, true));
   phase_drain(h, false);
   return HM_OK;
@@ -1271,7 +1306,7 @@ hm_status hm_logdet(hm_H* hh, double* out) {
   }
   HM_CHECK(fetch_scalars(h, 100, 2));
   HM_HIP(hipStreamSynchronize(h->m->stream));
-  *out = h->h_scal[100] + h->h_scal[101];
+  *out = h->h_scal[SC_LD] + h->h_scal[SC_LD + 1];
   return HM_OK;
 }
 
@@ -1321,7 +1356,7 @@ hm_status hm_loglik_grad(hm_H* hh, const double* y, double* loglik, double* grad
   }
   if (grad && h->p > 0) HM_CHECK(need_deriv(h, "hm_loglik_grad"));
   HM_CHECK(loglik_enqueue(h, y, grad != nullptr));
-  HM_CHECK(fetch_scalars(h, 0, 128));
+  HM_CHECK(fetch_scalars(h, 0, SC_ITER_END));
   HM_HIP(hipStreamSynchronize(h->m->stream));
   phase_drain(h, false);
   return loglik_collect(h, loglik, grad);
@@ -1340,7 +1375,7 @@ hm_status hm_fisher(hm_H* hh, double* fim) {
   if (h->p == 0) return HM_OK;
   HM_CHECK(need_deriv(h, "hm_fisher"));
   HM_CHECK(fisher_enqueue(h));
-  HM_CHECK(fetch_scalars(h, 0, 128));
+  HM_CHECK(fetch_scalars(h, 0, SC_ITER_END));
   HM_HIP(hipStreamSynchronize(h->m->stream));
   phase_drain(h, false);
   return fisher_collect(h, fim);
@@ -1366,6 +1401,10 @@ hm_status hm_iteration_batched(int nf, hm_H* const* hs, const double* thetas, co
   for (int f = 0; f < nf; ++f) {
     if (!hs[f] || !ys[f]) {
       set_error("hm_iteration_batched: field " + std::to_string(f) + " has a NULL handle or sample");
+      return HM_E_INVAL;
+    }
+    if (hs[f]->h.m->nvars != 1) {
+      set_error("hm_iteration_batched: fields take four-entry theta (one variable per location)");
       return HM_E_INVAL;
     }
     for (int g = 0; g < f; ++g)
@@ -1422,7 +1461,7 @@ hm_status hm_loglik(hm_H* hh, const double* theta_full, const double* y, double*
   HM_CHECK(build_enqueue(h, theta_full, false));
   HM_CHECK(factor_enqueue(h));
   HM_CHECK(loglik_enqueue(h, y, false));
-  HM_CHECK(fetch_scalars(h, 0, 128));
+  HM_CHECK(fetch_scalars(h, 0, SC_ITER_END));
   HM_CHECK(sync_check(h, true));
   phase_drain(h, false);
   return loglik_collect(h, loglik, nullptr);
@@ -1449,8 +1488,9 @@ hm_status hm_grad_reverse(hm_H* hh, double* grad) {
   if (m->op_vjp_final) {
     HM_CHECK(m->op_vjp_final(m, h->theta, h->adj.wmode, h->d_scal + SC_ADJ));
   } else if (m->op) {
-    // the operator's vector-Jacobian products were summed directly (see kvjp)
-    HM_HIP(hipMemcpyAsync(h->d_scal + SC_ADJ, h->adj.wmode, 4 * sizeof(double), hipMemcpyDeviceToDevice,
+    // the operator's vector-Jacobian products were summed directly (see kvjp; the fifth
+    // sum, the second variable's part of <Ybar, X>, for the bivariate model)
+    HM_HIP(hipMemcpyAsync(h->d_scal + SC_ADJ, h->adj.wmode, 5 * sizeof(double), hipMemcpyDeviceToDevice,
                           m->stream));
   } else {
     const long NN = (long)m->N * (m->dim == 2 ? m->N : 1);   // modes of the transforms
@@ -1460,15 +1500,17 @@ hm_status hm_grad_reverse(hm_H* hh, double* grad) {
     HM_CHECK(sum_scalar(m, h->adj.wmode, NN, 0, h->d_scal + SC_ADJ + 3, h->d_part));
   }
   phase_end(h, PH_REVERSE);
-  HM_CHECK(fetch_scalars(h, SC_ADJ, 4));
+  HM_CHECK(fetch_scalars(h, SC_ADJ, 5));
   HM_CHECK(sync_check(h, true));
   phase_drain(h, false);
   // w-weighted mode sums: <w, lambda>, <w, dlambda/dkappa>, <w, dlambda/dalpha>, sum w
   // (lambda: the physics part of the mode multiplier, sigma2 times the unit-scale one,
-  // so de/dsigma2 = lambda / sigma2; de/dtau2 = 1)
+  // so de/dsigma2 = lambda / sigma2; de/dtau2 = 1).  Bivariate model: sum w splits into
+  // the two variables' nuggets, t[4] the second variable's part.
   const double* t = h->h_scal + SC_ADJ;
   const double sigma2 = h->theta[3];
-  const double tb[4] = {t[1], t[2], t[3], t[0] / sigma2};
+  const bool two = m->nvars == 2;
+  const double tb[5] = {t[1], t[2], two ? t[3] - t[4] : t[3], t[0] / sigma2, two ? t[4] : 0.0};
   for (int q = 0; q < h->p; ++q) {
     grad[q] = tb[h->pidx[q]];
     if (!std::isfinite(grad[q])) {

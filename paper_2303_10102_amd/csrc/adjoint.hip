@@ -192,7 +192,7 @@ hm_status adjoint_init(FactorCtx& f, const double* z, AdjBufs& a) {
   return HM_OK;
 }
 
-hm_status adjoint_sweep(Model* m, const double theta[4], const Sketch* s, const PanelSet& ps, const LevelBufs& lb,
+hm_status adjoint_sweep(Model* m, const double* theta, const Sketch* s, const PanelSet& ps, const LevelBufs& lb,
                         const NodeBufs& nb, AdjBufs& a) {
   const int n = m->n, nl = m->nl, levels = m->levels, kc = ps.bw;
   const long s2 = (long)kc * kc;

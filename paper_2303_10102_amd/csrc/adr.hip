@@ -171,7 +171,7 @@ __global__ void k_adr_final(double* out4, const double* d, const double* tau_sum
 
 hm_status kvjp_gather(Model* m, const double* X, int ldx, double* Xn, int c);
 
-static hm_status adr_vjp(Model* m, const double theta[4], const double* X, int ldx, const double* Yb, int ldb, int c,
+static hm_status adr_vjp(Model* m, const double* theta, const double* X, int ldx, const double* Yb, int ldb, int c,
                          double* wmode) {
   AdrOp* a = (AdrOp*)m->op_ctx;
   hipStream_t st = m->stream;
@@ -221,7 +221,7 @@ static hm_status adr_vjp(Model* m, const double theta[4], const double* X, int l
   return HM_OK;
 }
 
-static hm_status adr_vjp_final(Model* m, const double theta[4], const double* wmode, double* out4) {
+static hm_status adr_vjp_final(Model* m, const double* theta, const double* wmode, double* out4) {
   AdrOp* a = (AdrOp*)m->op_ctx;
   const long NN = (long)a->N * a->N;
   const double* wk[1] = {wmode};

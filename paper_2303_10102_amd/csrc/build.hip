@@ -221,7 +221,7 @@ static hm_status qr_tangent(Model* m, const double* Q, const double* dY, int w, 
 
 // One level of the construction.  XR: n x w test matrix (right-children rows).
 // Writes panel block l of ps (and of its tangents when nr > 0).
-hm_status level_step(Model* m, const double theta[4], const PanelSet& ps, int l, const double* XR, int w,
+hm_status level_step(Model* m, const double* theta, const PanelSet& ps, int l, const double* XR, int w,
                      const int* kblk, int nr, const int* realidx, const LevelBufs& b, const NodeBufs& nb) {
   const int n = m->n;
   const LeafSel left{1, l}, right{2, l};
@@ -297,7 +297,7 @@ hm_status level_step(Model* m, const double theta[4], const PanelSet& ps, int l,
 }
 
 // Leaf pass: D = sym((K - sum H) S), dD_j likewise (S = stacked identities).
-hm_status leaf_pass(Model* m, const double theta[4], const PanelSet& ps, int nr, const int* realidx,
+hm_status leaf_pass(Model* m, const double* theta, const PanelSet& ps, int nr, const int* realidx,
                     const LevelBufs& b, const NodeBufs& nb, double* D, double* const* dD) {
   const int n = m->n, nl = m->nl;
   double* dZ[2] = {b.dZl[0], b.dZl[1]};
@@ -331,7 +331,7 @@ __global__ void k_pad_rows(const double* in, int n_in, double* out, int n, const
 // sketch creation: per level, ell-wide sample -> compression V -> level step
 // with the compressed test matrix (value only), into a temporary panel set.
 // ---------------------------------------------------------------------------
-hm_status sketch_build(Sketch* s, const double* omega, const double theta0[4]) {
+hm_status sketch_build(Sketch* s, const double* omega, const double* theta0) {
   Model* m = s->m;
   const int n = m->n, levels = m->levels, ell = s->ell, r = s->rank;
   const int nodes = (1 << (levels + 1)) - 1;

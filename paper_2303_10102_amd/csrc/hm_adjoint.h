@@ -20,10 +20,10 @@ struct AdjBufs {
 hm_status adjoint_init(FactorCtx& f, const double* z, AdjBufs& a);
 // Reverse sweep through the leaf pass and the levels (deepest first); accumulates
 // the mode weights from which the parameter adjoints follow.
-hm_status adjoint_sweep(Model* m, const double theta[4], const Sketch* s, const PanelSet& ps, const LevelBufs& lb,
+hm_status adjoint_sweep(Model* m, const double* theta, const Sketch* s, const PanelSet& ps, const LevelBufs& lb,
                         const NodeBufs& nb, AdjBufs& a);
 // <Ybar, dK/dtheta_j X> for all j through the per-mode weights (kapply.hip).
-hm_status kvjp(Model* m, const double theta[4], const double* X, int ldx, const double* Yb, int ldb, int c,
+hm_status kvjp(Model* m, const double* theta, const double* X, int ldx, const double* Yb, int ldb, int c,
                double* wmode);
 
 }  // namespace hm

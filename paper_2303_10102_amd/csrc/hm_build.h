@@ -38,11 +38,11 @@ hm_status make_identity_stack(Model* m);
 // wt: columns of X that also get the tangent subtraction (default: all w)
 hm_status subtract_coarser(Model* m, const PanelSet& ps, int l, const double* X, int w, LeafSel xsel,
                            LeafSel ysel, double* Y, double* const* dY, int nr, const NodeBufs& nb, int wt = -1);
-hm_status level_step(Model* m, const double theta[4], const PanelSet& ps, int l, const double* XR, int w,
+hm_status level_step(Model* m, const double* theta, const PanelSet& ps, int l, const double* XR, int w,
                      const int* kblk, int nr, const int* realidx, const LevelBufs& b, const NodeBufs& nb);
-hm_status leaf_pass(Model* m, const double theta[4], const PanelSet& ps, int nr, const int* realidx,
+hm_status leaf_pass(Model* m, const double* theta, const PanelSet& ps, int nr, const int* realidx,
                     const LevelBufs& b, const NodeBufs& nb, double* D, double* const* dD);
-hm_status sketch_build(Sketch* s, const double* omega, const double theta0[4]);
+hm_status sketch_build(Sketch* s, const double* omega, const double* theta0);
 // padding rows and columns of leaf blocks: zero off the diagonal, diag on it (no-op for uniform trees)
 hm_status leaf_pad(Model* m, double* D, double diag);
 hm_status leaf_factor(Model* m, const double* D, double* Dinv, double* logdet_leaf, double* work);

@@ -154,6 +154,11 @@ struct Model {
   int dim = 2, N = 0, n = 0, levels = 0, nl = 0, nleaves = 0;
   int n_real = 0;
   int nl_min = 0;           // smallest leaf (real rows)
+  // variables per location: 2 for the bivariate model, whose natural index is
+  // v * nsplit + location (rows with natural index >= nsplit belong to variable 2 and
+  // take the second nugget, theta_full[4]); 1 otherwise (nsplit = n_real)
+  int nvars = 1;
+  long nsplit = 0;
   bool uniform = true;
   // caller-supplied operator (hm_model_create_op): K = sigma2 K_op + tau2 I, applied
   // through op in the caller's point order; d_opws: its reductions' scratch
@@ -234,12 +239,12 @@ inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
 // K-apply: outputs (any may be null) = {K, dK/dkappa, dK/dalpha} X, tree order in and out.
 // X: n x c (ld ldx); outputs n x c (ld ldo). c <= m->cmax.
-hm_status kapply(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK,
+hm_status kapply(Model* m, const double* theta, const double* X, int ldx, int c, double* outK,
                  double* outKap, double* outAlp, int ldo);
 
 // The same K-apply (every row in and out) with its transform scratch supplied by the
 // caller: ws holds 5 * n * cblk doubles, and the columns are processed cblk at a time.
-hm_status kapply_ws(Model* m, double* ws, int cblk, const double theta[4], const double* X, int ldx, int c,
+hm_status kapply_ws(Model* m, double* ws, int cblk, const double* theta, const double* X, int ldx, int c,
                     double* outK, double* outKap, double* outAlp, int ldo);
 
 // Generic FP64 GEMM, column-major: C = alpha*op(A)*op(B) + beta*C, batched by strides.
@@ -268,11 +273,11 @@ inline LeafSel sel_all() { return LeafSel{0, 1}; }
 // K-apply for an input that vanishes outside the rows of in_sel, whose output is
 // needed only on the rows of out_sel (one side of a split, or all rows); output
 // rows outside out_sel are left unwritten.  Same result on the needed rows.
-hm_status kapply_sel(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK,
+hm_status kapply_sel(Model* m, const double* theta, const double* X, int ldx, int c, double* outK,
                      double* outKap, double* outAlp, int ldo, LeafSel in_sel, LeafSel out_sel);
 // The same with per-output column counts: outK gets the first cK columns of K X, outKap /
 // outAlp the first cKap / cAlp columns of the tangents (one pass of forward transforms).
-hm_status kapply_multi(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK, int cK,
+hm_status kapply_multi(Model* m, const double* theta, const double* X, int ldx, int c, double* outK, int cK,
                        double* outKap, int cKap, double* outAlp, int cAlp, int ldo, LeafSel in_sel,
                        LeafSel out_sel);
 
@@ -324,8 +329,13 @@ hm_status model_tables(Model* m);
 // stencil model kappa > 0, alpha >= 0)
 hm_status check_theta(const Model* m, const double* t);
 // an operator model (the points' KD-tree, padded leaves) with op applying K_op
+// nv rows per point (co-located variables, natural index v * n + point), the tree over the points
 hm_status model_create_op(Ctx* cx, int dim, const double* coords, int n, int leaf, hm_op_fn op, void* uctx,
-                          bool builtin, hm_model** out);
+                          bool builtin, hm_model** out, int nv = 1);
+// the bivariate co-kriging model (bivariate.hip)
+hm_status model_create_bivariate(Ctx* cx, int dim, int N, double h, int leaf, hm_model** out);
+// entries of theta_full: 5 for the bivariate model (second nugget last), else 4
+inline int nparams(const Model* m) { return m->nvars == 2 ? 5 : 4; }
 // the stencil model on a full grid (side N, spacing h)
 hm_status model_create(Ctx* ctx, int device, void* stream, int dim, int N, double h, int leaf, hm_model** out);
 // an observed subset of the stencil model's grid points (select.hip)

@@ -10,9 +10,9 @@ hm_status dots(Model* m, const double* const* A, int na, const double* const* B,
 hm_status dots_leafT(Model* m, const double* const* A, int na, const double* const* B, int nb, double* out,
                      double* partial);
 hm_status sum_scalar(Model* m, const double* x, long len, int diag_nl, double* out, double* partial);
-hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double theta[4], const double* tF_prefix,
+hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double* theta, const double* tF_prefix,
                         const double* GtG);
-hm_status scale_sweep(FactorCtx& f, ParamBufs& ps, const ParamBufs& pt, const double theta[4]);
+hm_status scale_sweep(FactorCtx& f, ParamBufs& ps, const ParamBufs& pt, const double* theta);
 hm_status tangent_sweep(FactorCtx& f, ParamBufs& pb);
 hm_status node_prep(FactorCtx& f);
 hm_status node_psi(FactorCtx& f, ParamBufs& pb, double* xtmp);

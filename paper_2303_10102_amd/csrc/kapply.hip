@@ -578,7 +578,7 @@ k_dst_inv_fold(const double* Ph, const double* W, MultiOut mo, TreeIdx tix,
   tile_store2(DstStScatterUnfold<AM>{mo.y_of(q), ldy, tix, cg, N, H, m0, ym}, e, o);
 }
 
-hm_status ensure_scale(Model* m, const double theta[4]) {
+hm_status ensure_scale(Model* m, const double* theta) {
   bool same = true;
   for (int i = 0; i < 4; ++i) same = same && (m->lam_key[i] == theta[i]);
   if (same) return HM_OK;
@@ -699,29 +699,33 @@ __global__ void k_zero_pad_rows(double* Y, int ldy, const int* perm, int n, int 
 }
 
 // Y[t, j] += tau2 X[t, j] for the rows t of the leaves selected by (mode, depth), j < c.
-// Padding rows (perm[t] < 0; perm null for a uniform tree) are skipped.
+// Padding rows (perm[t] < 0; perm null for a uniform tree) are skipped; rows whose
+// natural index is >= split (the second variable of the bivariate model) take tau2b.
 __global__ void k_nugget(double* Y, int ldy, const double* X, int ldx, int n, int nl, int c, double tau2,
-                         int levels, int mode, int depth, const int* perm) {
+                         double tau2b, long split, int levels, int mode, int depth, const int* perm) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)n * c) return;
   const int t = (int)(e % n), j = (int)(e / n);
-  if (perm && perm[t] < 0) return;
+  const int g = perm ? perm[t] : 0;
+  if (g < 0) return;
   if (mode != 0) {
     const int anc = (t / nl) >> (levels - depth);
     if (((anc & 1) == 0) != (mode == 1)) return;
   }
-  Y[t + (long)j * ldy] += tau2 * X[t + (long)j * ldx];
+  Y[t + (long)j * ldy] += (g >= split ? tau2b : tau2) * X[t + (long)j * ldx];
 }
 
 // outK += tau2 X on the rows where the input and the wanted output overlap
-static hm_status add_nugget(Model* m, const double theta[4], const double* X, int ldx, double* outK, int cK, int ldo,
+static hm_status add_nugget(Model* m, const double* theta, const double* X, int ldx, double* outK, int cK, int ldo,
                             LeafSel in_sel, LeafSel out_sel) {
   const bool disjoint = in_sel.mode != 0 && out_sel.mode != 0 && in_sel.depth == out_sel.depth &&
                         in_sel.mode != out_sel.mode;
   if (!outK || cK <= 0 || disjoint) return HM_OK;
   const int n = m->n;
+  const bool two = m->nvars == 2;
   hipLaunchKernelGGL(k_nugget, dim3(ceil_div((long)n * cK, 256)), dim3(256), 0, m->stream, outK, ldo, X, ldx, n, m->nl,
-                     cK, theta[2], m->levels, out_sel.mode, out_sel.depth, m->uniform ? nullptr : m->d_perm);
+                     cK, theta[2], two ? theta[4] : theta[2], two ? m->nsplit : (long)m->n_real, m->levels,
+                     out_sel.mode, out_sel.depth, m->uniform ? nullptr : m->d_perm);
   HM_LAUNCH_CHECK();
   return HM_OK;
 }
@@ -746,7 +750,7 @@ __global__ void k_scatter_tree(const double* Yn, double* Y, long ldy, const int*
   Y[t + j * ldy] = g >= 0 ? s * Yn[g + (long)j * nr] : 0.0;
 }
 
-static hm_status op_call(Model* m, int which, const double theta[4], const double* Xn, int c, double* Yn) {
+static hm_status op_call(Model* m, int which, const double* theta, const double* Xn, int c, double* Yn) {
   const int rc = m->op(m->op_ctx, which, theta, Xn, m->n_real, c, Yn, m->n_real, (void*)m->stream);
   if (rc != 0 && m->op_builtin) return (hm_status)rc;
   if (rc != 0) {
@@ -757,7 +761,7 @@ static hm_status op_call(Model* m, int which, const double theta[4], const doubl
   return HM_OK;
 }
 
-static hm_status op_kapply(Model* m, double* ws, int cblk, const double theta[4], const double* X, int ldx, int c,
+static hm_status op_kapply(Model* m, double* ws, int cblk, const double* theta, const double* X, int ldx, int c,
                            double* const outs[3], const int ocols[3], int ldo) {
   const int n = m->n, nr = m->n_real;
   cblk = std::min(cblk, m->cmax);   // operators see at most cmax columns at a time
@@ -782,7 +786,7 @@ static hm_status op_kapply(Model* m, double* ws, int cblk, const double theta[4]
 
 // The K-apply with its transform scratch ws (5 * n * cblk doubles) passed in, columns
 // processed cblk at a time.
-static hm_status kapply_core(Model* m, double* ws, int cblk, const double theta[4], const double* X, int ldx, int c,
+static hm_status kapply_core(Model* m, double* ws, int cblk, const double* theta, const double* X, int ldx, int c,
                              double* outK, int cK, double* outKap, int cKap, double* outAlp, int cAlp, int ldo,
                              LeafSel in_sel, LeafSel out_sel) {
   if (c <= 0) return HM_OK;
@@ -880,14 +884,14 @@ static hm_status kapply_core(Model* m, double* ws, int cblk, const double theta[
   return HM_OK;
 }
 
-hm_status kapply_multi(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK, int cK,
+hm_status kapply_multi(Model* m, const double* theta, const double* X, int ldx, int c, double* outK, int cK,
                        double* outKap, int cKap, double* outAlp, int cAlp, int ldo, LeafSel in_sel,
                        LeafSel out_sel) {
   return kapply_core(m, m->d_ws, m->cmax, theta, X, ldx, c, outK, cK, outKap, cKap, outAlp, cAlp, ldo, in_sel,
                      out_sel);
 }
 
-hm_status kapply_ws(Model* m, double* ws, int cblk, const double theta[4], const double* X, int ldx, int c,
+hm_status kapply_ws(Model* m, double* ws, int cblk, const double* theta, const double* X, int ldx, int c,
                     double* outK, double* outKap, double* outAlp, int ldo) {
   if (cblk < 1) {
     set_error("kapply: the scratch holds no column block");
@@ -896,12 +900,12 @@ hm_status kapply_ws(Model* m, double* ws, int cblk, const double theta[4], const
   return kapply_core(m, ws, cblk, theta, X, ldx, c, outK, c, outKap, c, outAlp, c, ldo, sel_all(), sel_all());
 }
 
-hm_status kapply_sel(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK,
+hm_status kapply_sel(Model* m, const double* theta, const double* X, int ldx, int c, double* outK,
                      double* outKap, double* outAlp, int ldo, LeafSel in_sel, LeafSel out_sel) {
   return kapply_multi(m, theta, X, ldx, c, outK, c, outKap, c, outAlp, c, ldo, in_sel, out_sel);
 }
 
-hm_status kapply(Model* m, const double theta[4], const double* X, int ldx, int c, double* outK,
+hm_status kapply(Model* m, const double* theta, const double* X, int ldx, int c, double* outK,
                  double* outKap, double* outAlp, int ldo) {
   return kapply_sel(m, theta, X, ldx, c, outK, outKap, outAlp, ldo, sel_all(), sel_all());
 }
@@ -959,9 +963,16 @@ __global__ void k_mode_dot(const double* A, const double* B, long NN, int cc, do
 }
 
 // wmode[0..3] += (sigma2 <Yb, K_op X>, sigma2 <Yb, d0 K_op X>, sigma2 <Yb, d1 K_op X>, <Yb, X>)
-__global__ void k_accum4(double* w, const double* d, double s) {
+// and, nq = 5, wmode[4] += <Yb, X> over the second variable's rows (bivariate model)
+__global__ void k_accum(double* w, const double* d, double s, int nq) {
   const int q = threadIdx.x;
-  if (q < 4) w[q] += (q < 3 ? s : 1.0) * d[q];
+  if (q < nq) w[q] += (q < 3 ? s : 1.0) * d[q];
+}
+// Xs[i + j nr] = X[i + j nr] on the rows i >= split, else 0
+__global__ void k_rows_from(double* Xs, const double* X, int nr, long split, int c) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)nr * c) return;
+  Xs[e] = (e % nr) >= split ? X[e] : 0.0;
 }
 
 // columns of a tree-ordered block gathered into the operator's point order (ld n_real)
@@ -975,7 +986,7 @@ hm_status kvjp_gather(Model* m, const double* X, int ldx, double* Xn, int c) {
 // For an operator model the vector-Jacobian product has no mode structure: every
 // parameter's term <Ybar, dK/dtheta_j X> is formed from the operator's derivative
 // products (three operator applications per column block).
-static hm_status kvjp_op(Model* m, const double theta[4], const double* X, int ldx, const double* Yb, int ldb, int c,
+static hm_status kvjp_op(Model* m, const double* theta, const double* X, int ldx, const double* Yb, int ldb, int c,
                          double* wmode) {
   const int n = m->n, nr = m->n_real, cblk = m->cmax;
   double* Xn = m->d_ws;
@@ -995,13 +1006,22 @@ static hm_status kvjp_op(Model* m, const double theta[4], const double* X, int l
     const double* B[4] = {Yq[0], Yq[1], Yq[2], Xn};
     double* out = m->d_opws + 1024 * 16;
     HM_CHECK(dots(m, A, 1, B, 4, cnt, out, m->d_opws));
-    hipLaunchKernelGGL(k_accum4, dim3(1), dim3(64), 0, m->stream, wmode, out, theta[3]);
+    const int nq = m->nvars == 2 ? 5 : 4;
+    if (nq == 5) {
+      // the second variable's rows of X (in Yq[0], read above) for its nugget's sum
+      hipLaunchKernelGGL(k_rows_from, dim3(ceil_div(cnt, 256)), dim3(256), 0, m->stream, Yq[0], Xn, nr, m->nsplit,
+                         cc);
+      HM_LAUNCH_CHECK();
+      const double* B2[1] = {Yq[0]};
+      HM_CHECK(dots(m, A, 1, B2, 1, cnt, out + 4, m->d_opws));
+    }
+    hipLaunchKernelGGL(k_accum, dim3(1), dim3(64), 0, m->stream, wmode, out, theta[3], nq);
     HM_LAUNCH_CHECK();
   }
   return HM_OK;
 }
 
-hm_status kvjp(Model* m, const double theta[4], const double* X, int ldx, const double* Yb, int ldb, int c,
+hm_status kvjp(Model* m, const double* theta, const double* X, int ldx, const double* Yb, int ldb, int c,
                double* wmode) {
   if (c <= 0) return HM_OK;
   if (m->op_vjp) return m->op_vjp(m, theta, X, ldx, Yb, ldb, c, wmode);

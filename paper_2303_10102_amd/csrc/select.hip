@@ -17,11 +17,11 @@
 
 namespace hm {
 
-hm_status kapply_ws(Model* m, double* ws, int cblk, const double theta[4], const double* X, int ldx, int c,
+hm_status kapply_ws(Model* m, double* ws, int cblk, const double* theta, const double* X, int ldx, int c,
                     double* outK, double* outKap, double* outAlp, int ldo);
-hm_status kvjp(Model* m, const double theta[4], const double* X, int ldx, const double* Yb, int ldb, int c,
+hm_status kvjp(Model* m, const double* theta, const double* X, int ldx, const double* Yb, int ldb, int c,
                double* wmode);
-hm_status ensure_scale(Model* m, const double theta[4]);
+hm_status ensure_scale(Model* m, const double* theta);
 
 struct SelOp {
   hm_model* grid = nullptr;    // the full-grid stencil model

@@ -47,6 +47,42 @@ __global__ void k_leaf_affine(double* out, const double* A, int nl, long cnt, do
   out[e] = v;
 }
 
+// Per-row coefficients of the bivariate model's nugget structure: row t of the tree
+// order takes c0 (first variable), c1 (second variable: natural index >= split) or 0
+// (padding row).
+__device__ __forceinline__ double row_coef(const int* perm, long t, long split, double c0, double c1) {
+  const int g = perm[t];
+  return g < 0 ? 0.0 : (g >= split ? c1 : c0);
+}
+// panel set (ld n): out[t + j n] = coef(t) in[t + j n]
+__global__ void k_rows_coef(double* out, const double* in, long n, long cnt, const int* perm, long split, double c0,
+                            double c1) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < cnt) out[e] = row_coef(perm, e % n, split, c0, c1) * in[e];
+}
+// leaf-major: out_L = a A_L + diag(coef(rows of L))   (A may be null)
+__global__ void k_leaf_diag_coef(double* out, const double* A, int nl, long cnt, const int* perm, long split,
+                                 double a, double c0, double c1) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cnt) return;
+  const long ls = (long)nl * nl, L = e / ls;
+  const int le = (int)(e % ls), i = le % nl, j = le / nl;
+  double v = A ? a * A[e] : 0.0;
+  if (i == j) v += row_coef(perm, L * nl + i, split, c0, c1);
+  out[e] = v;
+}
+// leaf-major: out_L = a Dinv_L diag(coef(columns of L)) + b I on the real rows
+__global__ void k_leaf_col_coef(double* out, const double* Dinv, int nl, long cnt, const int* perm, long split,
+                                double a, double c0, double c1, double b) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cnt) return;
+  const long ls = (long)nl * nl, L = e / ls;
+  const int le = (int)(e % ls), i = le % nl, j = le / nl;
+  double v = a * Dinv[e] * row_coef(perm, L * nl + j, split, c0, c1);
+  if (i == j && perm[L * nl + i] >= 0) v += b;
+  out[e] = v;
+}
+
 static hm_status lin2(Model* m, double* out, const double* x1, const double* x2, long cnt, double a1, double a2) {
   hipLaunchKernelGGL(k_lin2, dim3(ceil_div(cnt, 256)), dim3(256), 0, m->stream, out, x1, x2, cnt, a1, a2);
   HM_LAUNCH_CHECK();
@@ -402,7 +438,7 @@ hm_status node_lam(FactorCtx& f, ParamBufs& pb, double* tbuf, double* dsbuf) {
 // ---------------------------------------------------------------------------
 // per-parameter work
 // ---------------------------------------------------------------------------
-hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double theta[4], const double* tF_prefix,
+hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double* theta, const double* tF_prefix,
                         const double* GtG) {
   Model* m = f.m;
   PrecScope prec(m);   // trace panels: FP32 under the mixed policy
@@ -411,6 +447,50 @@ hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double theta[4], cons
   const long s2 = (long)kc * kc;
   const long ncnt = ((2L << levels) - 2) * s2;   // per-node arrays, non-root nodes (from offset s2)
   const double tau2 = theta[2], sigma2 = theta[3];
+  if (m->nvars == 2 && pb.kind >= 2) {
+    // bivariate model: K~ = sigma2-scaled physics + diag(T), T = tau2_1 on the first
+    // variable's rows, tau2_2 on the second's (M_v: the rows of variable v)
+    const long lcnt = (long)m->nleaves * m->nl * m->nl;
+    const long split = m->nsplit;
+    const int* perm = m->d_perm;
+    const dim3 gp(ceil_div(pcnt, 256)), gl(ceil_div(lcnt, 256));
+    const ReduceJob rp{f.G, n, cs_block(kc), pb.Xi, n, cs_block(kc), 1, levels, pb.Psi, s2, sel_all()};
+    if (pb.kind == 2 || pb.kind == 4) {
+      // K~_tau2_v = M_v: no panels; dD = M_v, Xi = M_v G, Y = Dinv M_v, Psi = G^T M_v G, E = 0
+      const double c0 = pb.kind == 2 ? 1.0 : 0.0, c1 = 1.0 - c0;
+      HM_CHECK(fill(m, pb.dF, pcnt, 0.0));
+      hipLaunchKernelGGL(k_leaf_diag_coef, gl, dim3(256), 0, m->stream, pb.dD, nullptr, m->nl, lcnt, perm, split, 0.0,
+                         c0, c1);
+      HM_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_rows_coef, gp, dim3(256), 0, m->stream, pb.Xi, f.G, (long)n, pcnt, perm, split, c0, c1);
+      HM_LAUNCH_CHECK();
+      hipLaunchKernelGGL(k_leaf_col_coef, gl, dim3(256), 0, m->stream, pb.Y, f.Dinv, m->nl, lcnt, perm, split, 1.0, c0,
+                         c1, 0.0);
+      HM_LAUNCH_CHECK();
+      HM_CHECK(fill(m, pb.E + s2, ncnt, 0.0));
+      HM_CHECK(tree_reduce(m, rp));
+      return HM_OK;
+    }
+    // K~_sigma2 = (K~ - T) / sigma2: dF = F / (2 sigma2), dD = (D - T) / sigma2,
+    // Xi = (F - T G) / sigma2, Y = (I - Dinv T) / sigma2, E = S / (2 sigma2),
+    // Psi = (S - G^T T G) / sigma2
+    const double t1 = theta[2], t2 = theta[4];
+    HM_CHECK(lin2(m, pb.dF, f.F, nullptr, pcnt, 0.5 / sigma2, 0.0));
+    hipLaunchKernelGGL(k_leaf_diag_coef, gl, dim3(256), 0, m->stream, pb.dD, f.D, m->nl, lcnt, perm, split,
+                       1.0 / sigma2, -t1 / sigma2, -t2 / sigma2);
+    HM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_rows_coef, gp, dim3(256), 0, m->stream, pb.Xi, f.G, (long)n, pcnt, perm, split, t1, t2);
+    HM_LAUNCH_CHECK();
+    HM_CHECK(tree_reduce(m, rp));                                   // G^T T G
+    HM_CHECK(lin2(m, pb.Psi + s2, f.Sn + s2, pb.Psi + s2, ncnt, 1.0 / sigma2, -1.0 / sigma2));
+    HM_CHECK(lin2(m, pb.Xi, f.F, pb.Xi, pcnt, 1.0 / sigma2, -1.0 / sigma2));
+    hipLaunchKernelGGL(k_leaf_col_coef, gl, dim3(256), 0, m->stream, pb.Y, f.Dinv, m->nl, lcnt, perm, split,
+                       -1.0 / sigma2, t1, t2, 1.0 / sigma2);
+    HM_LAUNCH_CHECK();
+    HM_CHECK(lin2(m, pb.E + s2, f.Sn + s2, nullptr, ncnt, 0.5 / sigma2, 0.0));
+    HM_CHECK(leaf_pad(m, pb.dD, 0.0));
+    return HM_OK;
+  }
   if (pb.kind == 2) {
     // K~_tau2 = I: no panels, identity leaves.  Xi = G, Y = Dinv and Psi = G^T G are
     // aliases set at creation; E = dF^T G = 0.
@@ -469,7 +549,7 @@ hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double theta[4], cons
 // sigma2 from tau2: with H_c = K~_c^{-1} G_c, dG_tau2 = -H and
 //   dG_sigma2 = K~_c^{-1}(F/(2 sigma2) - (F - tau2 G)/sigma2) = -G/(2 sigma2) - (tau2/sigma2) dG_tau2,
 //   W_sigma2 = dG_sigma2^T F = -S/(2 sigma2) - (tau2/sigma2) W_tau2.
-hm_status scale_sweep(FactorCtx& f, ParamBufs& ps, const ParamBufs& pt, const double theta[4]) {
+hm_status scale_sweep(FactorCtx& f, ParamBufs& ps, const ParamBufs& pt, const double* theta) {
   Model* m = f.m;
   const int n = m->n, kc = f.kc, levels = m->levels;
   const long pcnt = (long)n * levels * kc;

@@ -14,7 +14,7 @@ from pathlib import Path
 import numpy as np
 
 LIBPATH = Path(__file__).resolve().with_name("libhmle.so")
-PARAM_NAMES = ("kappa", "alpha", "tau2", "sigma2")
+PARAM_NAMES = ("kappa", "alpha", "tau2", "sigma2", "tau2_2")   # tau2_2: bivariate model only
 
 _lib = None
 
@@ -102,8 +102,11 @@ def _check(func, st):
 
 
 def _theta(t):
-    arr = (C.c_double * 4)(*[float(x) for x in t])
-    return arr
+    """theta_full as a C array: 4 entries, or 5 for the bivariate model (second nugget last)."""
+    vals = [float(x) for x in t]
+    if len(vals) not in (4, 5):
+        raise ValueError("theta_full has 4 entries (5 for the bivariate model)")
+    return (C.c_double * len(vals))(*vals)
 
 
 def _ptr(t):
@@ -182,9 +185,12 @@ class Model:
     caching allocator); h is the grid spacing (default 1/(N+1), the unit square).
     obs: optional grid indices (x fastest in 2D) of the observed nodes; the model is then
     the observed subset (n = len(obs), observation order = obs), the physics on the full
-    grid and the nugget on the observations."""
+    grid and the nugget on the observations.
+    nvars=2: the bivariate co-kriging model (y1 = B^-1 w, y2 = A^-1 B^-1 w at every node,
+    stacked (y1; y2), n = 2 N^dim), theta_full = (kappa, alpha, tau2_1, sigma2, tau2_2)."""
 
-    def __init__(self, dim, N, leaf, device=0, stream=None, ctx=None, h=None, allocator="torch", obs=None):
+    def __init__(self, dim, N, leaf, device=0, stream=None, ctx=None, h=None, allocator="torch", obs=None,
+                 nvars=1):
         import torch
         self.device = torch.device("cuda", device)
         self.ctx = ctx if ctx is not None else Context(device, stream, allocator)
@@ -198,8 +204,9 @@ class Model:
             oidx, nobs = self._obs.ctypes.data_as(C.POINTER(C.c_int)), int(self._obs.size)
         with torch.cuda.device(device):
             _check("hm_model_create_spde",
-                   lib().hm_model_create_spde(self.ctx._h, dim, N, N if dim == 2 else 1, spacing, 1, oidx, nobs,
-                                              leaf, C.byref(hh)))
+                   lib().hm_model_create_spde(self.ctx._h, dim, N, N if dim == 2 else 1, spacing, int(nvars), oidx,
+                                              nobs, leaf, C.byref(hh)))
+        self.nvars = int(nvars)
         self._h = hh
         n, lv, lf = _I(), _I(), _I()
         _check("hm_model_info", lib().hm_model_info(hh, C.byref(n), C.byref(lv), C.byref(lf)))
