@@ -192,6 +192,83 @@ def adr_run(steps):
     return out
 
 
+def biv_run(steps):
+    """The bivariate co-kriging workload: 362 x 362 nodes x 2 variables (n = 262088), leaf 512
+    (8 levels, leaves of up to 1058 rows), rank 64 + 10, theta = (kappa, alpha, tau2_1, sigma2,
+    tau2_2) all free: one iteration (K~ and the two real derivative matrices, factor, L~, 5
+    scores, 5 x 5 Fisher) in FP64 and under the mixed policy, and L~ + scores by reverse mode;
+    errors per entry of both paths against the exact per-mode closed form, and of the mixed
+    path against the FP64 one."""
+    import numpy as np
+    import torch
+    from oracle.bivariate import spectral_quantities
+    from paper_2303_10102_amd import hmle
+    from synth import BIV_WORKLOADS, sketch_draws
+    w = BIV_WORKLOADS["biv_n262088"]
+    print(f"[bench] bivariate: {w.name}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    m = hmle.Model(w.dim, w.N, w.leaf, device=0, nvars=2)
+    yh = w.sample()
+    y = torch.from_numpy(yh).cuda()
+    om = torch.from_numpy(sketch_draws(w)).cuda()
+    s = hmle.Sketch(m, om, w.rank, w.oversample, w.theta_full)
+    del om
+    H = hmle.HMatrix(s, w.free)
+    m.autotune(s.ranks()[1])
+    ll, g, fim = H.iteration(w.theta_full, y)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    print(f"[bench] bivariate: set up in {setup:.1f} s", file=sys.stderr, flush=True)
+    H.stats_reset()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ll, g, fim = H.iteration(w.theta_full, y)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    st = H.stats()
+    H.set_precision("mixed32")
+    H.iteration(w.theta_full, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        llm, gm, fm = H.iteration(w.theta_full, y)
+    torch.cuda.synchronize()
+    dm = (time.perf_counter() - t0) / steps
+    H.set_precision("fp64")
+    H.loglik_grad_adjoint(w.theta_full, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        lla, ga = H.loglik_grad_adjoint(w.theta_full, y)
+    torch.cuda.synchronize()
+    da = (time.perf_counter() - t0) / steps
+    ex = spectral_quantities(w.dim, w.N, w.theta_full, yh, w.free)
+
+    def err(l_, g_, f_, ref):
+        d = np.sqrt(np.diag(ref["fim"]))
+        return {"eps_L": abs(l_ - ref["loglik"]) / abs(ref["loglik"]),
+                "grad_max_err_in_sd": float(np.max(np.abs(g_ - ref["grad_nll"]) / d)),
+                "fim_max_err_corr": float(np.max(np.abs(f_ - ref["fim"]) / np.outer(d, d)))}
+
+    d64 = np.sqrt(np.diag(fim))
+    out = {"workload": f"{w.name}: {w.N}x{w.N} nodes x 2 variables, n={w.n}, leaf {w.leaf} ({m.levels} levels, "
+                       f"{m.leaf} rows per stored leaf), rank {w.rank}, theta = (kappa, alpha, tau2_1, sigma2, tau2_2)",
+           "iters_per_s": 1.0 / dt, "ms_per_iter": 1e3 * dt, "steps": steps, "setup_s": setup,
+           "ms_per_phase": {k[3:]: v / steps for k, v in st.items() if k.startswith("ms_")},
+           "kapply_columns_per_iter": (st["kapply_columns"] + st["kapply_deriv_columns"]) / steps,
+           "mixed32": {"ms_per_iter": 1e3 * dm, "speedup_vs_fp64": dt / dm,
+                       "mixed_vs_fp64_H": {"loglik_rel": abs(llm - ll) / abs(ll),
+                                           "grad_sd": float(np.max(np.abs(gm - g) / d64)),
+                                           "fim_corr": float(np.max(np.abs(fm - fim) / np.outer(d64, d64)))},
+                       "error_mixed_vs_exact": err(llm, gm, fm, ex)},
+           "adjoint_loglik_grad": {"ms_per_iter": 1e3 * da,
+                                   "max_diff_vs_forward_sd": float(np.max(np.abs(ga - g) / d64))},
+           "error_fp64_vs_exact": err(ll, g, fim, ex),
+           "loglik": ll, "grad_nll": [float(v) for v in g], "fim_diag": [float(fim[i, i]) for i in range(len(g))]}
+    H.close(); s.close(); m.close()
+    return out
+
+
 def mle_run(w_head):
     """Time-to-estimate of maximum-likelihood fits (paper_2303_10102_amd.mle) on the headline
     grid with the field's variance about 0.12 of the nugget's (sigma2 = 6.4e4), where kappa,
@@ -311,6 +388,8 @@ def main():
                     help="also time the 64-field batched workload, FP64 and mixed (0 = skip)")
     ap.add_argument("--adr-steps", type=int, default=3,
                     help="also time the advection-diffusion-reaction model on the 256^2 grid (0 = skip)")
+    ap.add_argument("--biv-steps", type=int, default=2,
+                    help="also time the bivariate co-kriging workload (362^2 x 2, rank 64, 5 parameters; 0 = skip)")
     ap.add_argument("--mixed-steps", type=int, default=5,
                     help="also time the mixed-precision policy and report both paths' errors (0 = skip)")
     ap.add_argument("--adjoint-steps", type=int, default=5,
@@ -467,7 +546,7 @@ def main():
                                       "grad_nll": [float(v) for v in ga]}
     if args.mle:
         rec["mle"] = mle_run(w)
-    if args.batched_steps > 0 or args.adr_steps > 0:
+    if args.batched_steps > 0 or args.adr_steps > 0 or args.biv_steps > 0:
         H.close(); s.close(); m.close()
         del H, s, m
         torch.cuda.synchronize()
@@ -477,6 +556,10 @@ def main():
         torch.cuda.empty_cache()
     if args.adr_steps > 0:
         rec["adr"] = adr_run(args.adr_steps)
+        torch.cuda.empty_cache()
+    if args.biv_steps > 0:
+        rec["bivariate"] = biv_run(args.biv_steps)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline()

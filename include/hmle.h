@@ -99,7 +99,16 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
  *   dim 1: nx points, ny = 1; dim 2: an nx x ny grid (row-major, x fastest);
  *   h: grid spacing (> 0) of the Dirichlet stencil (-Laplacian = (1/h^2) x 3-/5-point);
  *      hm_model_create uses h = 1/(N+1), the unit interval / square;
- *   nvars: variables per location (1);
+ *   nvars: variables per location.  1: the model above.  2: bivariate co-kriging (the
+ *      2 x 2 block covariance of co-located variables, the analogue of Sec. 5.2's
+ *      bivariate model, eq. "kphichi"): one latent noise w drives y1 = sigma B^{-1} w +
+ *      tau1 eps1 and y2 = sigma A^{-1} B^{-1} w + tau2 eps2 at every node, so
+ *      K = sigma2 [[C, C A^{-T}], [A^{-1} C, A^{-1} C A^{-T}]] + diag(tau2_1 I, tau2_2 I),
+ *      C = B^{-1} B^{-T}; n = 2 x nodes, vectors stacked (y1; y2); theta_full has FIVE
+ *      entries (kappa, alpha, tau2_1, sigma2, tau2_2) in every call on such a model
+ *      (free_idx values 0..4); the tree bisects the nodes (KD rule of hm_model_create_op)
+ *      with each node's two rows adjacent; levels = floor(log2(n / leaf)).  No selection.
+ *      hm_iteration_batched takes univariate fields only;
  *   obs_idx, nobs: the observed grid points, or NULL / nobs = 0 for every point.  With a
  *      selection (host array of nobs distinct grid indices, read during the call; the
  *      observation operator Phi of eq. "projection" reads these nodes, Sec. 5.2.1 forms
@@ -110,8 +119,8 @@ hm_status hm_model_create(int device, void* stream, int dim, int N, int leaf, hm
  *      (hm_model_rows); each K-apply spreads its columns onto the full grid, applies the
  *      full-grid transforms and reads the observed nodes back.  Needs nobs >= 2 leaf and
  *      the full grid valid for leaf; out-of-range or repeated indices: HM_E_INVAL.
- * Currently nx = ny for dim 2 and nvars = 1; anything else returns HM_E_INVAL naming
- * what is not supported. */
+ * Currently nx = ny for dim 2; anything else returns HM_E_INVAL naming what is not
+ * supported. */
 hm_status hm_model_create_spde(hm_ctx* ctx, int dim, int nx, int ny, double h, int nvars, const int* obs_idx,
                                long long nobs, int leaf, hm_model** out);
 /* A model on n scattered points with a caller-supplied operator: K(theta) =
@@ -223,7 +232,7 @@ hm_status hm_sketch_ranks(const hm_sketch* s, int* k_host, int* kc);
 
 /* ------------------------------------------------------------------ H ---
  * hm_H_create: allocate K~ and its p derivative matrices for the free parameters
- * free_idx[0..p-1] (indices into theta_full, distinct, p <= 4).  All device memory
+ * free_idx[0..p-1] (indices into theta_full, distinct, p <= 4; p <= 5 for the bivariate model).  All device memory
  * of the iteration is allocated here; build/factor/... allocate nothing. */
 hm_status hm_H_create(hm_sketch* s, int p, const int* free_idx, hm_H** out);
 void hm_H_destroy(hm_H* H);

@@ -98,3 +98,69 @@ def grid_locations(dim: int, N: int) -> np.ndarray:
         return np.arange(N, dtype=np.float64)
     g = np.arange(N * N)
     return np.stack([g % N, g // N], axis=1).astype(np.float64)
+
+
+def spectral_quantities(dim: int, N: int, theta_full, y: np.ndarray, free=PARAMS):
+    """Exact L, NLL gradient and Fisher matrix of the bivariate model at any size.
+
+    In the orthonormal sine basis every mode e is an independent 2 x 2 block
+        Kh_e = sigma2 / b^2 [[1, r], [r, r^2]] + diag(tau2_1, tau2_2),  r = 1/a,
+    (a = 1 + alpha mu, b = kappa^2 + mu), so with yh_e = (S y1, S y2)_e
+        L = -n/2 log 2 pi - 1/2 sum log det Kh_e - 1/2 sum yh_e^T Kh_e^-1 yh_e,
+        g_j = 1/2 sum tr(Kh^-1 dKh_j) - 1/2 sum yh^T Kh^-1 dKh_j Kh^-1 yh,
+        I_ij = 1/2 sum tr(Kh^-1 dKh_i Kh^-1 dKh_j)."""
+    import math
+
+    import scipy.fft as sfft
+
+    kappa, alpha, t1, s2, t2 = [float(t) for t in theta_full]
+    h = 1.0 / (N + 1)
+    mu1 = (4.0 / (h * h)) * np.sin(np.arange(1, N + 1) * math.pi * h / 2.0) ** 2
+    mu = mu1 if dim == 1 else (mu1[None, :] + mu1[:, None]).ravel()
+    nl = mu.size
+    a = 1.0 + alpha * mu
+    b = kappa * kappa + mu
+    r = 1.0 / a
+    q = 1.0 / (b * b)
+
+    def dst(v):
+        return sfft.dst(v, type=1, norm="ortho") if dim == 1 else sfft.dstn(v.reshape(N, N), type=1,
+                                                                             norm="ortho").ravel()
+
+    y = np.asarray(y, dtype=np.float64)
+    u, v = dst(y[:nl]), dst(y[nl:])
+    # blocks as (p11, p12, p22) per mode
+    K = (s2 * q + t1, s2 * q * r, s2 * q * r * r + t2)
+    dr = -mu * r * r
+    dq = -4.0 * kappa * q / b
+    dK = {"kappa": (s2 * dq, s2 * dq * r, s2 * dq * r * r),
+          "alpha": (0.0 * mu, s2 * q * dr, s2 * q * 2.0 * r * dr),
+          "tau2": (np.ones(nl), 0.0 * mu, 0.0 * mu),
+          "sigma2": (q, q * r, q * r * r),
+          "tau2_2": (0.0 * mu, 0.0 * mu, np.ones(nl))}
+    det = K[0] * K[2] - K[1] * K[1]
+    Ki = (K[2] / det, -K[1] / det, K[0] / det)
+
+    def mul(A, B):       # 2 x 2 symmetric-input products per mode, general result (11, 12, 21, 22)
+        return (A[0] * B[0] + A[1] * B[1], A[0] * B[1] + A[1] * B[2],
+                A[1] * B[0] + A[2] * B[1], A[1] * B[1] + A[2] * B[2])
+
+    z1, z2 = Ki[0] * u + Ki[1] * v, Ki[1] * u + Ki[2] * v      # Kh^-1 yh
+    ll = -0.5 * 2 * nl * math.log(2.0 * math.pi) - 0.5 * float(np.sum(np.log(det))) \
+        - 0.5 * float(np.sum(u * z1 + v * z2))
+    M = {}
+    g = []
+    for f in free:
+        d = dK[f]
+        P = mul(Ki, d)                                           # Kh^-1 dKh
+        M[f] = P
+        quad = z1 * (d[0] * z1 + d[1] * z2) + z2 * (d[1] * z1 + d[2] * z2)
+        g.append(0.5 * float(np.sum(P[0] + P[3])) - 0.5 * float(np.sum(quad)))
+    p = len(free)
+    fim = np.empty((p, p))
+    for i, fi in enumerate(free):
+        for j, fj in enumerate(free):
+            A, B = M[fi], M[fj]
+            tr = A[0] * B[0] + A[1] * B[2] + A[2] * B[1] + A[3] * B[3]
+            fim[i, j] = 0.5 * float(np.sum(tr))
+    return {"loglik": ll, "grad_nll": np.array(g), "fim": fim}

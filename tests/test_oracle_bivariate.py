@@ -87,3 +87,17 @@ def test_symmetric_positive_definite_and_pair_tree():
     assert t.n == 200 and sorted(t.perm.tolist()) == list(range(200))
     assert np.array_equal(t.perm[0::2], base.perm) and np.array_equal(t.perm[1::2], base.perm + 100)
     assert [sz for _, sz in t.leaves] == [2 * sz for _, sz in base.leaves]
+
+
+def test_closed_form_likelihood_matches_the_dense_one():
+    from oracle.bivariate import spectral_quantities
+    from oracle.exact import likelihood_gradient_fisher
+    for dim, N in ((2, 8), (1, 25)):
+        K, dK = bivariate_covariance(dim, N, THETA)
+        y = np.random.default_rng(8).standard_normal(K.shape[0])
+        d = likelihood_gradient_fisher(K, dK, y)
+        s = spectral_quantities(dim, N, THETA, y)
+        assert abs(s["loglik"] - d["loglik"]) <= 1e-11 * abs(d["loglik"])
+        sd = np.sqrt(np.diag(d["fim"]))
+        assert np.max(np.abs(s["grad_nll"] - d["grad_nll"]) / sd) <= 1e-9
+        assert np.max(np.abs(s["fim"] - d["fim"]) / np.outer(sd, sd)) <= 1e-10
