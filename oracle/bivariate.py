@@ -164,3 +164,37 @@ def spectral_quantities(dim: int, N: int, theta_full, y: np.ndarray, free=PARAMS
             tr = A[0] * B[0] + A[1] * B[2] + A[2] * B[1] + A[3] * B[3]
             fim[i, j] = 0.5 * float(np.sum(tr))
     return {"loglik": ll, "grad_nll": np.array(g), "fim": fim}
+
+
+def apply_bivariate(dim: int, N: int, theta_full, X: np.ndarray, which: str = "K") -> np.ndarray:
+    """K X or dK/dtheta X (which in "K", "kappa", "alpha") by sparse solves, natural order,
+    X of shape (2 n_loc,) or (2 n_loc, c).  With u = B^{-2}(x1 + A^{-1} x2) (A, B symmetric):
+        K_op x = (u, A^{-1} u);
+        d/dkappa: u -> -4 kappa B^{-3}(x1 + A^{-1} x2) in both blocks;
+        d/dalpha: with dA^{-1} = -A^{-1} T A^{-1}, v = x1 + A^{-1} x2,
+            (B^{-2} dA^{-1} x2,  dA^{-1} B^{-2} v + A^{-1} B^{-2} dA^{-1} x2)."""
+    import scipy.sparse.linalg as spla
+
+    kappa, alpha, t1, s2, t2 = [float(t) for t in theta_full]
+    T = neg_laplacian(dim, N)
+    nl = T.shape[0]
+    eye = sp.identity(nl, format="csc")
+    A = spla.splu((eye + alpha * T).tocsc())
+    B = spla.splu((kappa * kappa * eye + T).tocsc())
+    X = np.asarray(X, dtype=np.float64)
+    x1, x2 = X[:nl], X[nl:]
+    Ai2 = A.solve(x2)
+    v = x1 + Ai2
+    if which == "K":
+        u = B.solve(B.solve(v))
+        return np.concatenate([s2 * u + t1 * x1, s2 * A.solve(u) + t2 * x2])
+    if which == "kappa":
+        u = -4.0 * kappa * B.solve(B.solve(B.solve(v)))
+        return s2 * np.concatenate([u, A.solve(u)])
+    if which == "alpha":
+        dAi2 = -A.solve(T @ Ai2)
+        y1 = B.solve(B.solve(dAi2))
+        w = B.solve(B.solve(v))
+        y2 = -A.solve(T @ A.solve(w)) + A.solve(y1)
+        return s2 * np.concatenate([y1, y2])
+    raise ValueError(which)

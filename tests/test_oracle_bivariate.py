@@ -101,3 +101,13 @@ def test_closed_form_likelihood_matches_the_dense_one():
         sd = np.sqrt(np.diag(d["fim"]))
         assert np.max(np.abs(s["grad_nll"] - d["grad_nll"]) / sd) <= 1e-9
         assert np.max(np.abs(s["fim"] - d["fim"]) / np.outer(sd, sd)) <= 1e-10
+
+
+def test_sparse_apply_matches_the_dense_assembly():
+    from oracle.bivariate import apply_bivariate
+    for dim, N in ((2, 9), (1, 30)):
+        K, dK = bivariate_covariance(dim, N, THETA)
+        X = np.random.default_rng(9).standard_normal((K.shape[0], 3))
+        for which, M in (("K", K), ("kappa", dK[0]), ("alpha", dK[1])):
+            Y = apply_bivariate(dim, N, THETA, X, which)
+            assert np.abs(Y - M @ X).max() <= 1e-12 * np.abs(M @ X).max(), (dim, which)
