@@ -21,8 +21,9 @@
 
 namespace hm {
 
-hm_status sketch_compress(Model* m, const double* Y, int ldy, int ell, int l, int rank, double tol, double* W,
+hm_status sketch_compress(Model* m, const double* Y, int ldy, int ell, int l, int rank, double tol, double* S,
                           double* R, double* V, int kc, int* d_k, double* d_sig);
+size_t qr_stack_doubles(int n, int nint, int ell);
 hm_status leaf_sym(Model* m, const double* Z, int ldz, double* D);
 
 __global__ void k_fill(double* p, long cnt, double v) {
@@ -360,7 +361,7 @@ hm_status sketch_build(Sketch* s, const double* omega, const double* theta0) {
   double* Xl = alloc((size_t)n * ell);
   double* Yl = alloc((size_t)n * ell);
   double* Xr = alloc((size_t)n * r);
-  double* Wqr = alloc((size_t)n / 2 * ell);
+  double* Sqr = alloc(2 * qr_stack_doubles(n, nint, ell));   // stacked R factors of the chunked QR
   double* Rq = alloc((size_t)(nint) * ell * ell);
   double* Vb = alloc((size_t)nint * ell * r);   // V per parent heap index, ell x r
   double* sig = alloc((size_t)nint * ell);
@@ -403,7 +404,7 @@ hm_status sketch_build(Sketch* s, const double* omega, const double* theta0) {
     if ((st = subtract_coarser(m, ps, l, Xl, ell, LeafSel{2, l}, LeafSel{1, l}, Yl, nullptr, 0, nb)) != HM_OK)
       break;
     const int heap0 = (1 << (l - 1)) - 1;
-    if ((st = sketch_compress(m, Yl, n, ell, l, r, s->rank_tol, Wqr, Rq, Vb + (size_t)heap0 * ell * r, r,
+    if ((st = sketch_compress(m, Yl, n, ell, l, r, s->rank_tol, Sqr, Rq, Vb + (size_t)heap0 * ell * r, r,
                               s->d_k + heap0,
                               sig + (size_t)heap0 * ell)) != HM_OK)
       break;

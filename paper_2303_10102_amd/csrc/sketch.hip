@@ -24,65 +24,77 @@ namespace hm {
 
 constexpr int ELLMAX = 80;
 
-__device__ double block_sum(double v, double* red) {
-  const int tid = threadIdx.x;
-  red[tid] = v;
+// R factors of the level's samples by a tall-skinny Householder QR: each block's rows are
+// cut into chunks of CH, every chunk is factored in LDS by one workgroup, the chunks' R
+// factors are stacked and factored again, until one R per block remains (the same R up
+// to row signs as a Householder QR of the whole block, since R^T R = Y^T Y).
+//
+// One workgroup per (block, chunk): rows [c CH, min((c + 1) CH, mrows)) of block blk's
+// column-major matrix Y + blk * bstride (ld ldy, ell columns).  Thread t holds row t in
+// LDS.  Step j: the column norm by a wavefront reduction, the reflector v, the products
+// d_col = tau v^T A[:, col] for every later column at once (four row groups, then a sum
+// over the groups), and the rank-one update of every row.  A column that is already zero
+// needs no reflection.  R (ell x ell, rows past the chunk's row count zero) is written to
+// rows c ell .. c ell + ell - 1 of Rout + blk * rstride (ld ldr).
+template <int CH, int ELLM>
+__global__ void __launch_bounds__(CH) k_qr_chunk(const double* Y, long ldy, long bstride, long mrows, int nch,
+                                                 double* Rout, long ldr, long rstride, int ell) {
+  constexpr int G = CH / 64;
+  constexpr int LDA = ELLM + 1;
+  __shared__ double A[CH * LDA];   // row t at A + t LDA
+  __shared__ double V[CH];
+  __shared__ double D[ELLM];
+  __shared__ double part[G * ELLM];
+  const int blk = blockIdx.x / nch, c = blockIdx.x % nch;
+  const long row0 = (long)c * CH;
+  const int m = (int)min((long)CH, mrows - row0);
+  const double* Yb = Y + blk * bstride + row0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int col = 0; col < ell; ++col) A[tid * LDA + col] = (tid < m) ? Yb[tid + col * ldy] : 0.0;
   __syncthreads();
-  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if (tid < off) red[tid] += red[tid + off];
+  const int jmax = min(m, ell);
+  for (int j = 0; j < jmax; ++j) {
+    const double x = (tid >= j && tid < m) ? A[tid * LDA + j] : 0.0;
+    double s = x * x;
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) part[wave] = s;
     __syncthreads();
-  }
-  double r = red[0];
-  __syncthreads();
-  return r;
-}
-
-// Householder QR of Y[a rows, 0:ell] for every block P at depth l-1 (left child
-// a = 2P+1).  W: scratch copy, |a| x ell per block (ld |a|).  R: ell x ell per P.
-__global__ void __launch_bounds__(256) k_house_qr(const double* Y, int ldy, double* W, double* R, int ell,
-                                                  int l, int n) {
-  __shared__ double red[256];
-  const int pi = blockIdx.x;                 // block index at depth l-1
-  const int m = n >> l;                      // rows of a left child at depth l
-  const long r0 = (long)(2 * pi) * m;        // first row of a
-  double* w = W + (long)pi * m * ell;
-  double* Rp = R + (long)pi * ell * ell;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (long e = tid; e < (long)m * ell; e += nt) {
-    int i = e % m, c = e / m;
-    w[e] = Y[r0 + i + (long)c * ldy];
-  }
-  for (int e = tid; e < ell * ell; e += nt) Rp[e] = 0.0;
-  __syncthreads();
-  for (int j = 0; j < ell && j < m; ++j) {
-    double* x = w + (long)j * m;
-    double s = 0.0;
-    for (int i = j + tid; i < m; i += nt) s += x[i] * x[i];
-    s = block_sum(s, red);
-    const double alpha = x[j];
+    s = 0.0;
+    for (int g = 0; g < G; ++g) s += part[g];
+    const double alpha = A[j * LDA + j];
     const double nx = sqrt(s);
-    if (nx == 0.0) continue;  // zero column: R(j, .) stays zero in this column
+    if (nx == 0.0) {   // the same for every thread: no reflection, row j of R is row j of A
+      __syncthreads();
+      continue;
+    }
     const double sg = (alpha >= 0.0) ? 1.0 : -1.0;
     const double v0 = alpha + sg * nx;
-    const double vtv = s - alpha * alpha + v0 * v0;
-    const double tau = 2.0 / vtv;
+    const double tau = 2.0 / (s - alpha * alpha + v0 * v0);
+    V[tid] = (tid > j && tid < m) ? x : (tid == j ? v0 : 0.0);
     __syncthreads();
-    if (tid == 0) {
-      x[j] = v0;  // v stored in place (rows j..m-1)
-      Rp[j + j * ell] = -sg * nx;
-    }
-    __syncthreads();
-    for (int c = j + 1; c < ell; ++c) {
-      double* y = w + (long)c * m;
+    for (int col = j + 1 + lane; col < ell; col += 64) {
       double d = 0.0;
-      for (int i = j + tid; i < m; i += nt) d += x[i] * y[i];
-      d = block_sum(d, red);
-      const double f = tau * d;
-      for (int i = j + tid; i < m; i += nt) y[i] -= f * x[i];
-      __syncthreads();
-      if (tid == 0) Rp[j + c * ell] = y[j];
-      __syncthreads();
+      for (int t = j + wave; t < m; t += G) d += V[t] * A[t * LDA + col];
+      part[wave * ELLM + col] = d;
     }
+    __syncthreads();
+    for (int col = j + 1 + tid; col < ell; col += CH) {
+      double d = 0.0;
+      for (int g = 0; g < G; ++g) d += part[g * ELLM + col];
+      D[col] = tau * d;
+    }
+    __syncthreads();
+    if (tid >= j && tid < m) {
+      const double vt = V[tid];
+      for (int col = j + 1; col < ell; ++col) A[tid * LDA + col] -= D[col] * vt;
+      if (tid == j) A[j * LDA + j] = -sg * nx;
+    }
+    __syncthreads();
+  }
+  double* Rb = Rout + blk * rstride + (long)c * ell;
+  for (int e = tid; e < ell * ell; e += CH) {
+    const int i = e % ell, col = e / ell;
+    Rb[i + (long)col * ldr] = (i <= col && i < jmax) ? A[i * LDA + col] : 0.0;
   }
 }
 
@@ -219,15 +231,60 @@ __global__ void __launch_bounds__(64) k_level_scale(double* V, const double* sig
   }
 }
 
-hm_status sketch_compress(Model* m, const double* Y, int ldy, int ell, int l, int rank, double tol, double* W,
+// Rows of the sample factored per chunk (at least 2 ell, so that every round at least
+// halves the number of chunks: two stacked R factors fit one chunk) and the scratch the
+// stacked R factors need (two halves of qr_stack_doubles each).
+static int qr_chunk_rows(int ell) { return ell <= 72 ? 256 : 192; }
+size_t qr_stack_doubles(int n, int nint, int ell) {
+  return ((size_t)n / 2 / 128 + (size_t)nint + 1) * ell * ell;
+}
+
+hm_status sketch_compress(Model* m, const double* Y, int ldy, int ell, int l, int rank, double tol, double* S,
                           double* R, double* V, int kc, int* d_k, double* d_sig) {
   if (ell > ELLMAX) {
     set_error("rank + oversample exceeds 80");
     return HM_E_INVAL;
   }
   const int nb = 1 << (l - 1);
-  hipLaunchKernelGGL(k_house_qr, dim3(nb), dim3(256), 0, m->stream, Y, ldy, W, R, ell, l, m->n);
-  HM_LAUNCH_CHECK();
+  // R of each block's left-child rows (block pi: rows 2 pi mrows .. 2 pi mrows + mrows)
+  const int CH = qr_chunk_rows(ell);
+  const size_t half = qr_stack_doubles(m->n, (1 << m->levels) - 1, ell);
+  const double* src = Y;
+  long rows = m->n >> l, bstride = 2 * rows, ld = ldy;
+  for (int round = 0;; ++round) {
+    if (round >= 64 || 2 * ell > CH) {
+      set_error("sketch QR: the chunk rounds do not converge");
+      return HM_E_INVAL;
+    }
+    const int nch = (int)((rows + CH - 1) / CH);
+    double* dst;
+    long ldr, rstride;
+    if (nch == 1) {
+      dst = R;
+      ldr = ell;
+      rstride = (long)ell * ell;
+    } else {
+      dst = S + (round & 1) * half;
+      ldr = (long)nch * ell;
+      rstride = ldr * ell;
+      if ((size_t)nb * rstride > half) {
+        set_error("sketch QR: stack scratch too small");
+        return HM_E_INVAL;
+      }
+    }
+    if (CH == 256)
+      hipLaunchKernelGGL((k_qr_chunk<256, 72>), dim3(nb * nch), dim3(256), 0, m->stream, src, ld, bstride, rows, nch,
+                         dst, ldr, rstride, ell);
+    else
+      hipLaunchKernelGGL((k_qr_chunk<192, 80>), dim3(nb * nch), dim3(192), 0, m->stream, src, ld, bstride, rows, nch,
+                         dst, ldr, rstride, ell);
+    HM_LAUNCH_CHECK();
+    if (nch == 1) break;
+    src = dst;
+    ld = ldr;
+    bstride = rstride;
+    rows = (long)nch * ell;
+  }
   hipLaunchKernelGGL(k_jacobi_svd, dim3(nb), dim3(256), 0, m->stream, R, ell, rank, tol, V, kc, d_k, d_sig,
                      m->d_flags);
   HM_LAUNCH_CHECK();
