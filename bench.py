@@ -502,6 +502,15 @@ def main():
             llm, gm, fm = H.iteration(theta, y)
         torch.cuda.synchronize()
         dm = (time.perf_counter() - t0) / args.mixed_steps
+        # BF16 operands in the trace panels (policy 2)
+        H.set_precision("mixedbf16")
+        llb, gb, fb = H.iteration(theta, y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.mixed_steps):
+            llb, gb, fb = H.iteration(theta, y)
+        torch.cuda.synchronize()
+        db = (time.perf_counter() - t0) / args.mixed_steps
         H.set_precision("fp64")
         H.iteration(theta, y)
         def err(l_, g_, f_, ref):
@@ -516,6 +525,12 @@ def main():
                           "mixed_vs_fp64_H": {"loglik_rel": abs(llm - ll) / abs(ll),
                                               "grad_sd": float(np.max(np.abs(gm - g) / dfp)),
                                               "fim_corr": float(np.max(np.abs(fm - fim) / np.outer(dfp, dfp)))}}
+        rec["mixedbf16"] = {"ms_per_iter": 1e3 * db, "speedup_vs_fp64": ms / (1e3 * db),
+                            "steps": args.mixed_steps, "policy": "mixed32 with BF16 operands in the trace panels",
+                            "error_bf16_vs_exact": err(llb, gb, fb, ex),
+                            "bf16_vs_fp64_H": {"loglik_rel": abs(llb - ll) / abs(ll),
+                                               "grad_sd": float(np.max(np.abs(gb - g) / dfp)),
+                                               "fim_corr": float(np.max(np.abs(fb - fim) / np.outer(dfp, dfp)))}}
         # the physics-dominated regime (sigma2 = 6.4e4: mean field variance ~0.12 of the nugget)
         thp = theta.copy()
         thp[3] = 6.4e4
@@ -523,8 +538,15 @@ def main():
         l64, g64, f64 = H.iteration(thp, y)
         H.set_precision("mixed32")
         l32, g32, f32 = H.iteration(thp, y)
+        H.set_precision("mixedbf16")
+        lb6, gb6, fb6 = H.iteration(thp, y)
         H.set_precision("fp64")
         d64 = np.sqrt(np.diag(f64))
+        rec["mixedbf16"]["physics_regime_sigma2_6.4e4"] = {
+            "error_bf16_vs_exact": err(lb6, gb6, fb6, exp_),
+            "bf16_vs_fp64_H": {"loglik_rel": abs(lb6 - l64) / abs(l64),
+                               "grad_sd": float(np.max(np.abs(gb6 - g64) / d64)),
+                               "fim_corr": float(np.max(np.abs(fb6 - f64) / np.outer(d64, d64)))}}
         rec["mixed32"]["physics_regime_sigma2_6.4e4"] = {
             "error_fp64_vs_exact": err(l64, g64, f64, exp_), "error_mixed_vs_exact": err(l32, g32, f32, exp_),
             "mixed_vs_fp64_H": {"loglik_rel": abs(l32 - l64) / abs(l64),

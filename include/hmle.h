@@ -282,7 +282,10 @@ hm_status hm_iteration_batched(int nf, hm_H* const* hs, const double* thetas, co
  * accumulation (operands rounded from the FP64 storage); the K-apply, QR and Alg. 2,
  * leaf Cholesky and inverse, per-node factors, the log-determinant sum, the solve's
  * refinement residuals (FP64 H-matvec, two steps) and every scalar reduction stay
- * FP64.  Invalidates the current factors (state returns to empty). */
+ * FP64.  2 = mixed with BF16 trace panels: as 1, and the panel products of the score
+ * and Fisher traces (parameter preparation, tangent sweeps, panel products) take BF16
+ * operands (rounded to nearest even) with FP32 accumulation; L~ is that of policy 1.
+ * Invalidates the current factors (state returns to empty). */
 hm_status hm_H_set_precision(hm_H* H, int precision);
 
 /* L~ and the NLL gradient for the free parameters by reverse mode (adjoint):

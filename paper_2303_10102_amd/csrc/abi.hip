@@ -1441,8 +1441,8 @@ hm_status hm_iteration_batched(int nf, hm_H* const* hs, const double* thetas, co
 }
 
 hm_status hm_H_set_precision(hm_H* hh, int precision) {
-  if (!hh || precision < 0 || precision > 1) {
-    set_error("precision must be 0 (FP64) or 1 (mixed FP32 panel products)");
+  if (!hh || precision < 0 || precision > 2) {
+    set_error("precision must be 0 (FP64), 1 (mixed: FP32 panel products) or 2 (mixed with BF16 trace panels)");
     return HM_E_INVAL;
   }
   hh->h.precision = precision;

@@ -210,7 +210,7 @@ __device__ __forceinline__ void tile_store2(const ST& st, const TileAcc& e, cons
 // ---------------------------------------------------------------------------
 // Precision trait of the panel kernels that feed MFMA operands directly:
 // P = 0 FP64 (v_mfma_f64_16x16x4_f64), P = 1 FP32 operands with FP32 accumulation
-// (v_mfma_f32_16x16x4_f32) for the mixed-precision policy.  Both take lane l's
+// (v_mfma_f32_16x16x4_f32) for the mixed-precision policy, P = 2 BF16 operands (below).  Both take lane l's
 // operands as A[l % 16][l / 16] and B[l / 16][l % 16]; their accumulators differ:
 // element v of lane l is D[4 v + l / 16][l % 16] (FP64) and D[4 (l / 16) + v][l % 16] (FP32).
 // ---------------------------------------------------------------------------
@@ -232,6 +232,30 @@ struct MfmaPrec<1> {
   using V = hm_v4f;
   static __device__ __forceinline__ V zero() { return V{0.0f, 0.0f, 0.0f, 0.0f}; }
   static __device__ __forceinline__ V mfma(T a, T b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ __forceinline__ int row(int v, int lk) { return 4 * lk + v; }
+};
+// P = 2: BF16 operands with FP32 accumulation (v_mfma_f32_16x16x16_bf16): lane l supplies
+// four consecutive k, A[l % 16][4 (l / 16) + q] and B[4 (l / 16) + q][l % 16], q = 0..3, so
+// one instruction covers 16 k; the accumulator is laid out as for FP32.  Operands are
+// rounded to nearest even from FP32.
+typedef short hm_v4bf __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ short bf16_rne(float f) {
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (short)0x7fc0;   // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+__device__ __forceinline__ hm_v4bf bf16x4(float a, float b, float c, float d) {
+  return hm_v4bf{bf16_rne(a), bf16_rne(b), bf16_rne(c), bf16_rne(d)};
+}
+template <>
+struct MfmaPrec<2> {
+  using T = float;   // staging type (LDS); operands are packed to BF16 per instruction
+  using V = hm_v4f;
+  static __device__ __forceinline__ V zero() { return V{0.0f, 0.0f, 0.0f, 0.0f}; }
+  static __device__ __forceinline__ V mfma16(hm_v4bf a, hm_v4bf b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
   static __device__ __forceinline__ int row(int v, int lk) { return 4 * lk + v; }
 };
 

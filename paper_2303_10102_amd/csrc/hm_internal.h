@@ -191,7 +191,8 @@ struct Model {
   double* d_red = nullptr;      // per-leaf partials of tree_reduce
   size_t red_doubles = 0;
   // precision policy of the panel products (tree_reduce / tree_expand):
-  // mixed = 1 allows FP32 MFMA in the phases that open a PrecScope; panel_prec is
+  // mixed = 1 allows FP32 MFMA in the phases that open a PrecScope (2: BF16 in the trace
+  // phases as well); panel_prec is
   // the precision in effect (0 FP64, 1 FP32 operands with FP32 accumulation).
   int mixed = 0;
   int panel_prec = 0;
@@ -205,11 +206,14 @@ struct Model {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
 };
-// Marks a phase whose panel products may run in FP32 when the mixed policy is on.
+// Marks a phase whose panel products may run in reduced precision: FP32 when a mixed
+// policy is on (mixed = 1 or 2); in the trace phases (trace = true) BF16 under policy 2.
 struct PrecScope {
   Model* m;
   int saved;
-  explicit PrecScope(Model* mm) : m(mm), saved(mm->panel_prec) { m->panel_prec = m->mixed ? 1 : 0; }
+  explicit PrecScope(Model* mm, bool trace = false) : m(mm), saved(mm->panel_prec) {
+    m->panel_prec = (m->mixed == 2 && trace) ? 2 : (m->mixed ? 1 : 0);
+  }
   ~PrecScope() { m->panel_prec = saved; }
 };
 // profiling helpers (no-ops unless the family is enabled)

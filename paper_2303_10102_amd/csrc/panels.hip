@@ -250,18 +250,36 @@ k_reduce_direct(RedArgs a) {
   };
   auto mma_grp = [&](int t, const Grp& u) {
     const int rr = rbeg + 16 * t + 4 * lk;
+    if constexpr (P == 2) {
+      // the lane's four rows are the four k of one BF16 instruction
+      auto pick = [&](bool ok, const double (&v)[4], int q) { return (ok && rr + q < rend) ? (float)v[q] : 0.0f; };
+      hm_v4bf av[MB], xv[NB];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const bool rok = rr + q < rend;
-      T av[MB], xv[NB];
+      for (int i = 0; i < MB; ++i)
+        av[i] = bf16x4(pick(aok[i], u.ar[i], 0), pick(aok[i], u.ar[i], 1), pick(aok[i], u.ar[i], 2),
+                       pick(aok[i], u.ar[i], 3));
 #pragma unroll
-      for (int i = 0; i < MB; ++i) av[i] = (aok[i] && rok) ? (T)u.ar[i][q] : (T)0;
-#pragma unroll
-      for (int j = 0; j < NB; ++j) xv[j] = (xok[j] && rok) ? (T)u.xr[j][q] : (T)0;
+      for (int j = 0; j < NB; ++j)
+        xv[j] = bf16x4(pick(xok[j], u.xr[j], 0), pick(xok[j], u.xr[j], 1), pick(xok[j], u.xr[j], 2),
+                       pick(xok[j], u.xr[j], 3));
 #pragma unroll
       for (int i = 0; i < MB; ++i)
 #pragma unroll
-        for (int j = 0; j < NB; ++j) acc[i][j] = MP::mfma(av[i], xv[j], acc[i][j]);
+        for (int j = 0; j < NB; ++j) acc[i][j] = MP::mfma16(av[i], xv[j], acc[i][j]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool rok = rr + q < rend;
+        T av[MB], xv[NB];
+#pragma unroll
+        for (int i = 0; i < MB; ++i) av[i] = (aok[i] && rok) ? (T)u.ar[i][q] : (T)0;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) xv[j] = (xok[j] && rok) ? (T)u.xr[j][q] : (T)0;
+#pragma unroll
+        for (int i = 0; i < MB; ++i)
+#pragma unroll
+          for (int j = 0; j < NB; ++j) acc[i][j] = MP::mfma(av[i], xv[j], acc[i][j]);
+      }
     }
   };
   if (ngrp > 0) {
@@ -484,7 +502,8 @@ hm_status tree_reduce(Model* m, const ReduceJob& j) {
     // over four wavefronts instead of two
     const long wgs = (long)grid.x * grid.y * grid.z;
     const bool four = wgs < m->tune_reduce_nw4;
-    if (m->panel_prec == 1) launch_reduce_prec<1>(m, mb, nb, four, grid, a);
+    if (m->panel_prec == 2) launch_reduce_prec<2>(m, mb, nb, four, grid, a);
+    else if (m->panel_prec == 1) launch_reduce_prec<1>(m, mb, nb, four, grid, a);
     else launch_reduce_prec<0>(m, mb, nb, four, grid, a);
   }
   HM_LAUNCH_CHECK();
@@ -634,7 +653,9 @@ __global__ void __launch_bounds__(64 * NWV) k_expand_direct(ExpArgs a) {
     for (int r = 0; r < RB; ++r)
 #pragma unroll
       for (int s = 0; s < EXK / 4; ++s) {
-        const int k = k0 + 4 * s + lk;
+        // FP64 / FP32: k = 4 s + lk (one k per instruction); BF16: the four consecutive k
+        // 16 (s / 4) + 4 lk + s % 4 of one 16-deep instruction
+        const int k = k0 + (P == 2 ? 16 * (s >> 2) + 4 * lk + (s & 3) : 4 * s + lk);
         u.av[r][s] = Ab[rowc[r] + (long)(k < wk ? k : 0) * a.lda];
       }
     const double* Tb = exp_T(a, src, L, d);
@@ -661,19 +682,43 @@ __global__ void __launch_bounds__(64 * NWV) k_expand_direct(ExpArgs a) {
   };
   auto mfma_unit = [&](const Unit& u, int k0, const T* buf) {
     const int kn = min(EXK, wk - k0);
+    if constexpr (P == 2) {
 #pragma unroll
-    for (int s = 0; s < EXK / 4; ++s) {
-      if (4 * s < kn) {
-        const int kk = 4 * s + lk;
-        const bool kok = kk < kn;
-        T av[RB];
+      for (int c = 0; c < EXK / 16; ++c) {
+        if (16 * c < kn) {
+          const int kb = 16 * c + 4 * lk;   // this lane's first k of the instruction
+          hm_v4bf av[RB];
 #pragma unroll
-        for (int r = 0; r < RB; ++r) av[r] = kok ? (T)u.av[r][s] : (T)0;
+          for (int r = 0; r < RB; ++r) {
+            float x[4];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          const T tv = buf[kk * 65 + b * 16 + li];
+            for (int q = 0; q < 4; ++q) x[q] = (kb + q < kn) ? (float)u.av[r][4 * c + q] : 0.0f;
+            av[r] = bf16x4(x[0], x[1], x[2], x[3]);
+          }
 #pragma unroll
-          for (int r = 0; r < RB; ++r) acc[r][b] = MP::mfma(tv, av[r], acc[r][b]);
+          for (int b = 0; b < NB; ++b) {
+            const T* tp = buf + kb * 65 + b * 16 + li;   // k >= kn is staged as zero
+            const hm_v4bf tv = bf16x4(tp[0], tp[65], tp[130], tp[195]);
+#pragma unroll
+            for (int r = 0; r < RB; ++r) acc[r][b] = MP::mfma16(tv, av[r], acc[r][b]);
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < EXK / 4; ++s) {
+        if (4 * s < kn) {
+          const int kk = 4 * s + lk;
+          const bool kok = kk < kn;
+          T av[RB];
+#pragma unroll
+          for (int r = 0; r < RB; ++r) av[r] = kok ? (T)u.av[r][s] : (T)0;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const T tv = buf[kk * 65 + b * 16 + li];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) acc[r][b] = MP::mfma(tv, av[r], acc[r][b]);
+          }
         }
       }
     }
@@ -797,7 +842,11 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
   const int rb = (var == 2) ? 2 : 1, nwv = (var == 3) ? 8 : 4;
   const int nsel = count_selected(m->nleaves, m->levels, j.sel);
   dim3 grid(ceil_div(m->nl, 16 * rb * nwv), ceil_div(yhi - ylo, 16 * nb), nsel);
-  if (m->panel_prec == 1) {
+  if (m->panel_prec == 2) {
+    if (var == 2) launch_expand_direct<2, 2, 4>(m, nb, grid, a, ea, eb);
+    else if (var == 3) launch_expand_direct<2, 1, 8>(m, nb, grid, a, ea, eb);
+    else launch_expand_direct<2, 1, 4>(m, nb, grid, a, ea, eb);
+  } else if (m->panel_prec == 1) {
     if (var == 2) launch_expand_direct<1, 2, 4>(m, nb, grid, a, ea, eb);
     else if (var == 3) launch_expand_direct<1, 1, 8>(m, nb, grid, a, ea, eb);
     else launch_expand_direct<1, 1, 4>(m, nb, grid, a, ea, eb);

@@ -210,7 +210,9 @@ __global__ void __launch_bounds__(256) k_jacobi_svd(const double* R, int ell, in
 }
 
 // Common column scale of one level (see the header): V of nb blocks (ell x kc each,
-// stride ell*kc), sorted singular values sig (ell per block), kept ranks k.
+// stride ell*kc), sorted singular values sig (ell per block), kept ranks k.  One
+// workgroup per block: each forms the level's factors d_j (a sum over the nb blocks)
+// and scales its own block.
 __global__ void __launch_bounds__(64) k_level_scale(double* V, const double* sig, const int* kk, int nb, int ell,
                                                     int kc) {
   __shared__ double d[ELLMAX];
@@ -225,10 +227,8 @@ __global__ void __launch_bounds__(64) k_level_scale(double* V, const double* sig
     d[j] = cnt ? exp(acc / cnt) : 1.0;
   }
   __syncthreads();
-  for (long e = threadIdx.x; e < (long)nb * ell * kc; e += blockDim.x) {
-    const int j = (int)((e / ell) % kc);
-    V[e] *= d[j];
-  }
+  double* Vb = V + (long)blockIdx.x * ell * kc;
+  for (int e = threadIdx.x; e < ell * kc; e += blockDim.x) Vb[e] *= d[e / ell];
 }
 
 // Rows of the sample factored per chunk (at least 2 ell, so that every round at least
@@ -288,7 +288,7 @@ hm_status sketch_compress(Model* m, const double* Y, int ldy, int ell, int l, in
   hipLaunchKernelGGL(k_jacobi_svd, dim3(nb), dim3(256), 0, m->stream, R, ell, rank, tol, V, kc, d_k, d_sig,
                      m->d_flags);
   HM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_level_scale, dim3(1), dim3(64), 0, m->stream, V, d_sig, d_k, nb, ell, kc);
+  hipLaunchKernelGGL(k_level_scale, dim3(nb), dim3(64), 0, m->stream, V, d_sig, d_k, nb, ell, kc);
   HM_LAUNCH_CHECK();
   return HM_OK;
 }

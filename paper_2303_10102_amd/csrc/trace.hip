@@ -441,7 +441,7 @@ hm_status node_lam(FactorCtx& f, ParamBufs& pb, double* tbuf, double* dsbuf) {
 hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double* theta, const double* tF_prefix,
                         const double* GtG) {
   Model* m = f.m;
-  PrecScope prec(m);   // trace panels: FP32 under the mixed policy
+  PrecScope prec(m, true);   // trace panels: FP32 (BF16 under policy 2) under the mixed policies
   const int n = m->n, kc = f.kc, levels = m->levels;
   const long pcnt = (long)n * levels * kc;
   const long s2 = (long)kc * kc;
@@ -565,7 +565,7 @@ hm_status scale_sweep(FactorCtx& f, ParamBufs& ps, const ParamBufs& pt, const do
 //   K~_c^{-1} X = Dbar_c^{-1} X - sum_{P in subtree(c)} G_P N_P G_P^T X.
 hm_status tangent_sweep(FactorCtx& f, ParamBufs& pb) {
   Model* m = f.m;
-  PrecScope prec(m);   // trace panels: FP32 under the mixed policy
+  PrecScope prec(m, true);   // trace panels: FP32 (BF16 under policy 2) under the mixed policies
   const int n = m->n, kc = f.kc, levels = m->levels;
   const long pcnt = (long)n * levels * kc;
   double* R = f.tmp_panel;
@@ -591,7 +591,7 @@ hm_status tangent_sweep(FactorCtx& f, ParamBufs& pb) {
 // Gh_c = dG_c N_P[c,c],  Hh_c = dG_c N_P[c,sib] S_sib
 hm_status panel_products(FactorCtx& f, ParamBufs& pb) {
   Model* m = f.m;
-  PrecScope prec(m);   // trace panels: FP32 under the mixed policy
+  PrecScope prec(m, true);   // trace panels: FP32 (BF16 under policy 2) under the mixed policies
   const int n = m->n, kc = f.kc, levels = m->levels;
   const long s2 = (long)kc * kc;
   ExpandJob e1{pb.dG, n, cs_block(kc), pb.Gh, n, cs_block(kc), f.Ncc, s2, kc, 0, 0, 1, levels, 1.0, 0.0, sel_all()};

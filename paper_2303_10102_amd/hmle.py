@@ -444,9 +444,10 @@ class HMatrix:
         self.model = sketch.model
 
     def set_precision(self, precision):
-        """'fp64' (default) or 'mixed32' (FP32 MFMA panel products under the FP64 policy)."""
+        """'fp64' (default), 'mixed32' (FP32 MFMA panel products where the policy allows) or
+        'mixedbf16' (as mixed32, with BF16 operands in the score and Fisher trace panels)."""
         self._eval_token = None   # the autograd function re-evaluates if needed
-        code = {"fp64": 0, "mixed32": 1}[precision]
+        code = {"fp64": 0, "mixed32": 1, "mixedbf16": 2}[precision]
         _check("hm_H_set_precision", lib().hm_H_set_precision(self._h, code))
         self.precision = precision
 
