@@ -146,24 +146,25 @@ hm_status subtract_coarser(Model* m, const PanelSet& ps, int l, const double* X,
   PrecScope prec(m);   // coarser-level subtraction: FP32 under the mixed policy
   const int bw = ps.bw;
   const long ts = (long)bw * w;   // t_c: bw x w per node; its first wt columns serve the tangents
-  ReduceJob r{ps.F, m->n, cs_block(bw), X, m->n, cs_fixed(0, w), 1, l - 1, nb.t, ts, xsel};
-  HM_CHECK(tree_reduce(m, r));
-  ExpandJob e{ps.F, m->n, cs_block(bw), Y, m->n, cs_fixed(0, w), nb.t, ts, bw, 1, 0, 1, l - 1, -1.0, 1.0, ysel};
-  HM_CHECK(tree_expand(m, e));
-  if (dY) {
-    for (int j = 0; j < nr; ++j) {
-      // dt_c: bw x wt, stored with t's node stride so that one expand reads both
-      ReduceJob rd{ps.dF[j], m->n, cs_block(bw), X, m->n, cs_fixed(0, wt), 1, l - 1, nb.dt[j], ts, xsel};
-      HM_CHECK(tree_reduce(m, rd));
-      // dY -= dF t + F dt in one launch
-      ExpandJob e{ps.dF[j], m->n, cs_block(bw), dY[j], m->n, cs_fixed(0, wt), nb.t, ts, bw, 1, 0, 1, l - 1, -1.0,
-                  1.0, ysel};
-      e.A2 = ps.F;
-      e.T2 = nb.dt[j];
-      e.alpha2 = -1.0;
-      HM_CHECK(tree_expand(m, e));
-    }
+  // the value and tangent parts are independent: one launch of reduces (t_c = F_c^T X,
+  // dt_c = dF_c^T X), then one of expands (Y -= F t; dY_j -= dF_j t + F dt_j)
+  const int nj = dY ? 1 + nr : 1;
+  ReduceJob rj[3];
+  ExpandJob ej[3];
+  rj[0] = ReduceJob{ps.F, m->n, cs_block(bw), X, m->n, cs_fixed(0, w), 1, l - 1, nb.t, ts, xsel};
+  ej[0] = ExpandJob{ps.F, m->n, cs_block(bw), Y, m->n, cs_fixed(0, w), nb.t, ts, bw, 1, 0, 1, l - 1, -1.0, 1.0, ysel};
+  for (int j = 0; j + 1 < nj; ++j) {
+    // dt_c: bw x wt, stored with t's node stride so that one expand reads both
+    rj[1 + j] = ReduceJob{ps.dF[j], m->n, cs_block(bw), X, m->n, cs_fixed(0, wt), 1, l - 1, nb.dt[j], ts, xsel};
+    ExpandJob e{ps.dF[j], m->n, cs_block(bw), dY[j], m->n, cs_fixed(0, wt), nb.t, ts, bw, 1, 0, 1, l - 1, -1.0,
+                1.0, ysel};
+    e.A2 = ps.F;
+    e.T2 = nb.dt[j];
+    e.alpha2 = -1.0;
+    ej[1 + j] = e;
   }
+  HM_CHECK(tree_reduce_multi(m, rj, nj));
+  HM_CHECK(tree_expand_multi(m, ej, nj));
   return HM_OK;
 }
 
@@ -198,25 +199,38 @@ static hm_status cholqr3(Model* m, const double* Y, int w, int l, const int* kbl
   return HM_OK;
 }
 
-// Alg. 2 for every left child at depth l: dQ = dY R^{-1} - Q M,
-// M = triu(W) + strict_tril(W)^T, W = Q^T dY R^{-1}.  dQ -> out (left rows).
-static hm_status qr_tangent(Model* m, const double* Q, const double* dY, int w, int l, double* out,
-                            const NodeBufs& nb) {
+// Alg. 2 for every left child at depth l and every tangent j < nr (at most two):
+// dQ_j = dY_j R^{-1} - Q M_j,  M_j = triu(W_j) + strict_tril(W_j)^T,  W_j = Q^T dY_j R^{-1}.
+// dQ_j -> out[j] (left rows).  The tangents share each launch: per left child a, tangent
+// j's node blocks sit in heap slot a + j (slot a + 1, the right sibling, is free at this
+// depth), G_j^T = dY_j^T Q is reduced directly, so that W_a^T and W_{a+1}^T are one
+// product R^{-T} [G_0^T G_1^T] of adjacent blocks.
+static hm_status qr_tangents(Model* m, const double* Q, double* const* dY, int nr, int w, int l,
+                             double* const* out, const NodeBufs& nb) {
+  if (nr <= 0) return HM_OK;
   const LeafSel left{1, l};
   const long s2 = (long)w * w;
   const int heap0 = (1 << l) - 1;
   const int cnt = 1 << (l - 1);
-  ReduceJob r{Q, m->n, cs_fixed(0, w), dY, m->n, cs_fixed(0, w), l, l, nb.g, s2, left};
-  HM_CHECK(tree_reduce(m, r));
-  HM_CHECK(gemm(m->stream, false, false, w, w, w, 1.0, nb.g + heap0 * s2, w, 2 * s2, nb.rinv + heap0 * s2, w,
+  ReduceJob rj[2];
+  ExpandJob ej[2];
+  for (int j = 0; j < nr; ++j) {
+    // right children are left unwritten: their slots hold the other tangent's blocks
+    rj[j] = ReduceJob{dY[j], m->n, cs_fixed(0, w), Q, m->n, cs_fixed(0, w), l, l, nb.g + j * s2, s2, left, true};
+    // out = dY R^{-1} - Q M in one launch per tangent (both tangents in one launch)
+    ExpandJob e{dY[j], m->n, cs_fixed(0, w), out[j], m->n, cs_fixed(0, w), nb.rinv, s2, w, 0, 0, l, l, 1.0, 0.0,
+                left};
+    e.A2 = Q;
+    e.T2 = nb.mfold + j * s2;
+    e.alpha2 = -1.0;
+    ej[j] = e;
+  }
+  HM_CHECK(tree_reduce_multi(m, rj, nr));
+  // [W_0^T W_1^T] = R^{-T} [G_0^T G_1^T] per left child (node stride two slots)
+  HM_CHECK(gemm(m->stream, true, false, w, nr * w, w, 1.0, nb.rinv + heap0 * s2, w, 2 * s2, nb.g + heap0 * s2, w,
                 2 * s2, 0.0, nb.w + heap0 * s2, w, 2 * s2, cnt));
-  HM_CHECK(alg2_fold_nodes(m, nb.w, nb.mfold, s2, w, heap0, 2 * cnt));
-  // out = dY R^{-1} - Q M in one launch
-  ExpandJob e{dY, m->n, cs_fixed(0, w), out, m->n, cs_fixed(0, w), nb.rinv, s2, w, 0, 0, l, l, 1.0, 0.0, left};
-  e.A2 = Q;
-  e.T2 = nb.mfold;
-  e.alpha2 = -1.0;
-  HM_CHECK(tree_expand(m, e));
+  HM_CHECK(alg2_fold_nodes(m, nb.w, nb.mfold, s2, w, heap0, 2 * cnt, true));
+  HM_CHECK(tree_expand_multi(m, ej, nr));
   return HM_OK;
 }
 
@@ -259,7 +273,7 @@ hm_status level_step(Model* m, const double* theta, const PanelSet& ps, int l, c
     for (int j = 0; j < nr; ++j) HM_CHECK(fill(m, b.XdS[j], (long)n * w, 0.0));
   }
   HM_CHECK(cholqr3(m, b.Y, w, l, kblk, b.XS, b.Qt, nb));
-  for (int j = 0; j < nr; ++j) HM_CHECK(qr_tangent(m, b.XS, dY[j], w, l, b.XdS[j], nb));
+  HM_CHECK(qr_tangents(m, b.XS, dY, nr, w, l, b.XdS, nb));
   // ---- pass 2: C = B^T Q on the right-children rows
   double* dZ[2] = {b.dZ[0], b.dZ[1]};
   tangent_outputs(dZ, &kap, &alp);

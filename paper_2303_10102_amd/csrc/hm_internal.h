@@ -294,8 +294,15 @@ struct ReduceJob {
   int d0, d1;
   double* out; long out_stride;
   LeafSel sel;
+  // true: nodes without selected rows are left unwritten (their sum is zero); false:
+  // every node of the depths is written
+  bool only_selected = false;
 };
 hm_status tree_reduce(Model* m, const ReduceJob& j);
+// Up to three independent jobs with the same row operand layout (A's lda and columns),
+// depths, selection and output stride in one launch of the products and one of the
+// tree sums; other job lists run one job after another.  Same results as separate calls.
+hm_status tree_reduce_multi(Model* m, const ReduceJob* js, int nj);
 
 // For every row i of a selected leaf L:
 //   Y[i, yc(d)] = beta*Y + alpha * sum_{d in [d0,d1]} A[i, ac(d)] * T_{s(c_d)}[r0 + 0:wk, 0:wy(d)]
@@ -317,6 +324,9 @@ struct ExpandJob {
   double alpha2 = 0.0;
 };
 hm_status tree_expand(Model* m, const ExpandJob& j);
+// Up to three independent jobs (their own A, Y, output columns, T and second source;
+// everything else shared) in one launch; other job lists run one after another.
+hm_status tree_expand_multi(Model* m, const ExpandJob* js, int nj);
 
 // out[L rows, 0:w] (+)= Dm_L * X[L rows, 0:w], Dm leaf-major
 hm_status leaf_gemm(Model* m, const double* Dm, const double* X, int ldx, double* Y, int ldy, int w,
@@ -325,7 +335,8 @@ hm_status leaf_gemm(Model* m, const double* Dm, const double* X, int ldx, double
 // per-node small dense kernels (small.hip); nodes heap0 + i*hstep, i < cnt
 hm_status chol_inv_nodes(Model* m, const double* G, long gstride, double* R, double* Rinv, long rstride,
                          int k, const int* d_kblk, int heap0, int hstep, int cnt, int shift, long mrows);
-hm_status alg2_fold_nodes(Model* m, const double* W, double* M, long stride, int k, int heap0, int cnt);
+hm_status alg2_fold_nodes(Model* m, const double* W, double* M, long stride, int k, int heap0, int cnt,
+                          bool trans = false);
 hm_status node_lu(Model* m, const double* S, long sstride, double* Nout, long nstride, double* logdet, int k,
                   int heap0, int cnt);
 hm_status model_tables(Model* m);

@@ -166,7 +166,32 @@ struct RedArgs {
   double* out; long out_stride;
   double* partial; long pstride;  // per (leaf, depth) stride = wa * max wx
   int sel_mode, sel_depth;
+  int only_sel = 0;   // the tree sums skip nodes without selected leaves
+  // Up to two further independent jobs in the same launch (grid.z = jobs x nz of the
+  // products, grid.z = jobs of the tree sums): each has its own operands, output, X
+  // columns and partial area; everything else is shared.
+  int nz = 0;
+  const double* jA[2] = {nullptr, nullptr};
+  const double* jX[2] = {nullptr, nullptr};
+  double* jout[2] = {nullptr, nullptr};
+  ColSpec jxc[2] = {};
+  double* jpart[2] = {nullptr, nullptr};
+  long jpst[2] = {0, 0};
 };
+// the arguments of job q (0: the launch's own)
+__device__ __forceinline__ RedArgs red_job(const RedArgs& a0, int q) {
+  RedArgs a = a0;
+  if (q > 0) {
+    const bool s = q > 1;
+    a.A = s ? a0.jA[1] : a0.jA[0];
+    a.X = s ? a0.jX[1] : a0.jX[0];
+    a.out = s ? a0.jout[1] : a0.jout[0];
+    a.xc = s ? a0.jxc[1] : a0.jxc[0];
+    a.partial = s ? a0.jpart[1] : a0.jpart[0];
+    a.pstride = s ? a0.jpst[1] : a0.jpst[0];
+  }
+  return a;
+}
 
 // Reduce with both tall operands fed straight into the matrix cores (P = 0 FP64,
 // P = 1 FP32 operands and accumulation for the mixed-precision policy).  For
@@ -179,15 +204,17 @@ struct RedArgs {
 // wavefronts per SIMD leave room for two row groups of operands in flight.
 template <int P, int MB, int NB, int NW>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2, MB * NB > 4 ? 2 : 4)))
-k_reduce_direct(RedArgs a) {
+k_reduce_direct(RedArgs a0) {
   using MP = MfmaPrec<P>;
   using T = typename MP::T;
   __shared__ double red[(NW - 1) * MB * NB * 4 * 64];
-  // grid.z enumerates (selected leaf, depth), depth fastest
+  // grid.z enumerates (job, selected leaf, depth), depth fastest
   const TileIdx tb = tile_block();
+  const int q = tb.z / a0.nz, zz = tb.z - q * a0.nz;
+  const RedArgs a = red_job(a0, q);
   const int ndep = a.d1 - a.d0 + 1;
-  const int L = selected_leaf(tb.z / ndep, a.levels, a.sel_mode, a.sel_depth);
-  const int d = a.d0 + tb.z % ndep;
+  const int L = selected_leaf(zz / ndep, a.levels, a.sel_mode, a.sel_depth);
+  const int d = a.d0 + zz % ndep;
   const int wa = a.ac.w0, wx = a.xc.w(d);
   const int m0 = tb.x * (16 * MB), n0 = tb.y * (16 * NB);
   if (m0 >= wa || n0 >= wx) return;
@@ -347,8 +374,9 @@ static void launch_reduce_prec(Model* m, int mb, int nb, bool four, dim3 grid, c
 // four wavefronts of a block split the node's leaves (each issuing eight
 // independent loads per step), then combine through LDS; partials of unselected
 // leaves are never read.
-__global__ void __launch_bounds__(256) k_reduce_tree(RedArgs a, int dlast) {
+__global__ void __launch_bounds__(256) k_reduce_tree(RedArgs a0, int dlast) {
   __shared__ double red[4][64];
+  const RedArgs a = red_job(a0, (int)blockIdx.z);   // grid.z enumerates the jobs
   const int ndep = a.d1 - a.d0 + 1;
   // node enumeration: depth d contributes 2^d nodes, starting at depth d0
   int t = blockIdx.y;
@@ -358,6 +386,11 @@ __global__ void __launch_bounds__(256) k_reduce_tree(RedArgs a, int dlast) {
     ++d;
   }
   const int idx = t;
+  if (a.only_sel && a.sel_mode != 0 && d >= a.sel_depth) {
+    // below the selection depth a node's leaves are all selected or all not
+    const bool left = ((idx >> (d - a.sel_depth)) & 1) == 0;
+    if (left != (a.sel_mode == 1)) return;
+  }
   const int wa = a.ac.w0, wx = a.xc.w(d);
   const int ne = wa * wx;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -450,23 +483,72 @@ hm_status ensure_reduce_ws(Model* m, size_t doubles) {
   return HM_OK;
 }
 
-hm_status tree_reduce(Model* m, const ReduceJob& j) {
-  if (j.d0 < 1 || j.d1 > m->levels || j.d0 > j.d1) {
-    set_error("tree_reduce: bad depth range");
-    return HM_E_INVAL;
+// Jobs that can share one launch: same row operand layout, depths, selection and
+// output stride, products only (no identity operand), at most three.
+static bool reduce_jobs_compatible(Model* m, const ReduceJob* js, int nj) {
+  if (nj < 2 || nj > 3) return false;
+  auto is_ident = [&](const double* p) { return p == m->d_ident; };
+  for (int q = 0; q < nj; ++q) {
+    const ReduceJob& a = js[q];
+    const ReduceJob& b = js[0];
+    if (is_ident(a.A) || is_ident(a.X)) return false;
+    if (a.lda != b.lda || a.ldx != b.ldx || a.d0 != b.d0 || a.d1 != b.d1 || a.out_stride != b.out_stride ||
+        a.sel.mode != b.sel.mode || a.sel.depth != b.sel.depth || a.ac.base != b.ac.base ||
+        a.ac.stride != b.ac.stride || a.ac.w0 != b.ac.w0 || a.ac.grow != b.ac.grow ||
+        a.only_selected != b.only_selected)
+      return false;
   }
-  if (!sel_valid(m, j.sel)) {
-    set_error("tree_reduce: bad leaf selection");
-    return HM_E_INVAL;
+  return true;
+}
+
+hm_status tree_reduce(Model* m, const ReduceJob& j) { return tree_reduce_multi(m, &j, 1); }
+
+hm_status tree_reduce_multi(Model* m, const ReduceJob* js, int nj) {
+  if (nj <= 0) return HM_OK;
+  if (nj > 3) {
+    for (int q = 0; q < nj; ++q) HM_CHECK(tree_reduce_multi(m, js + q, 1));
+    return HM_OK;
+  }
+  const ReduceJob& j = js[0];
+  for (int q = 0; q < nj; ++q) {
+    if (js[q].d0 < 1 || js[q].d1 > m->levels || js[q].d0 > js[q].d1) {
+      set_error("tree_reduce: bad depth range");
+      return HM_E_INVAL;
+    }
+    if (!sel_valid(m, js[q].sel)) {
+      set_error("tree_reduce: bad leaf selection");
+      return HM_E_INVAL;
+    }
   }
   const int ndep = j.d1 - j.d0 + 1;
-  int wxmax = 0;
-  for (int d = j.d0; d <= j.d1; ++d) wxmax = std::max(wxmax, j.xc.w(d));
   const int wa = j.ac.w0;
+  // per-job widest X block and partial area (leaves x depths x wa x wx)
+  int wxq[3] = {0, 0, 0};
+  size_t offq[3] = {0, 0, 0};
+  size_t need = 0;
+  for (int q = 0; q < nj; ++q) {
+    for (int d = js[q].d0; d <= js[q].d1; ++d) wxq[q] = std::max(wxq[q], js[q].xc.w(d));
+    offq[q] = need;
+    need += (size_t)m->nleaves * ndep * wa * wxq[q];
+  }
+  if (nj > 1 && (!reduce_jobs_compatible(m, js, nj) || need > m->red_doubles)) {
+    for (int q = 0; q < nj; ++q) HM_CHECK(tree_reduce_multi(m, js + q, 1));
+    return HM_OK;
+  }
+  int wxmax = 0;
+  for (int q = 0; q < nj; ++q) wxmax = std::max(wxmax, wxq[q]);
   if (wa <= 0 || wxmax <= 0) return HM_OK;
   RedArgs a{j.A, j.lda, j.ac, j.X, j.ldx, j.xc, j.d0, j.d1, m->levels, m->nl, j.out, j.out_stride,
-            m->d_red, (long)wa * wxmax, j.sel.mode, j.sel.depth};
-  size_t need = (size_t)m->nleaves * ndep * wa * wxmax;
+            m->d_red, (long)wa * wxq[0], j.sel.mode, j.sel.depth};
+  a.only_sel = j.only_selected ? 1 : 0;
+  for (int q = 1; q < nj; ++q) {
+    a.jA[q - 1] = js[q].A;
+    a.jX[q - 1] = js[q].X;
+    a.jout[q - 1] = js[q].out;
+    a.jxc[q - 1] = js[q].xc;
+    a.jpart[q - 1] = m->d_red + offq[q];
+    a.jpst[q - 1] = (long)wa * wxq[q];
+  }
   if (need > m->red_doubles) {
     set_error("tree_reduce: partial workspace too small (" + std::to_string(need) + " > " +
               std::to_string(m->red_doubles) + ")");
@@ -477,8 +559,10 @@ hm_status tree_reduce(Model* m, const ReduceJob& j) {
   auto is_ident = [&](const double* p, const ColSpec& c) {
     return p == m->d_ident && c.base == 0 && c.stride == 0 && c.w0 == m->nl && c.grow == 0;
   };
-  const bool xid = is_ident(j.X, j.xc) && j.sel.mode == 0;
-  const bool aid = is_ident(j.A, j.ac) && j.sel.mode == 0 && j.xc.grow == 0;
+  const bool xid = nj == 1 && is_ident(j.X, j.xc) && j.sel.mode == 0;
+  const bool aid = nj == 1 && is_ident(j.A, j.ac) && j.sel.mode == 0 && j.xc.grow == 0;
+  const int nsel = count_selected(m->nleaves, m->levels, j.sel);
+  a.nz = nsel * ndep;
   if (xid || aid) {
     // sums of leaf blocks (no product): A[c]^T S[c] (xid) or S[c]^T X[c] (aid)
     const double* P = xid ? j.A : j.X;
@@ -496,8 +580,7 @@ hm_status tree_reduce(Model* m, const ReduceJob& j) {
       return (nbk % 3 == 0) ? 3 : (nbk % 2 == 0 ? 2 : 3);
     };
     const int mb = blocks(wa), nb = blocks(wxmax);
-    const int nsel = count_selected(m->nleaves, m->levels, j.sel);
-    dim3 grid(ceil_div(wa, 16 * mb), ceil_div(wxmax, 16 * nb), nsel * ndep);
+    dim3 grid(ceil_div(wa, 16 * mb), ceil_div(wxmax, 16 * nb), a.nz * nj);
     // few workgroups (e.g. one depth of per-leaf products): split each leaf's rows
     // over four wavefronts instead of two
     const long wgs = (long)grid.x * grid.y * grid.z;
@@ -508,16 +591,18 @@ hm_status tree_reduce(Model* m, const ReduceJob& j) {
   }
   HM_LAUNCH_CHECK();
   if (pf) {
-    const double rows = (double)count_selected(m->nleaves, m->levels, j.sel) * m->nl;
+    const double rows = (double)nsel * m->nl;
     double fl = 0.0, by = 0.0;
-    for (int d = j.d0; d <= j.d1; ++d) {
-      if (xid || aid) {   // a copy of the non-identity operand's leaf blocks
-        by += 16.0 * rows * (xid ? wa : j.xc.w(d));
-        continue;
+    for (int q = 0; q < nj; ++q)
+      for (int d = j.d0; d <= j.d1; ++d) {
+        const int wx = js[q].xc.w(d);
+        if (xid || aid) {   // a copy of the non-identity operand's leaf blocks
+          by += 16.0 * rows * (xid ? wa : wx);
+          continue;
+        }
+        fl += 2.0 * rows * wa * wx;
+        by += 8.0 * (rows * wa + rows * wx + (rows / m->nl) * wa * wx);
       }
-      fl += 2.0 * rows * wa * j.xc.w(d);
-      by += 8.0 * (rows * wa + rows * j.xc.w(d) + (rows / m->nl) * wa * j.xc.w(d));
-    }
     prof_end(m, PF_REDUCE, fl, by);
   }
   const int dlast = std::min(j.d1, m->levels - 1);
@@ -525,10 +610,10 @@ hm_status tree_reduce(Model* m, const ReduceJob& j) {
     int nodes = 0, nemax = 0;
     for (int d = j.d0; d <= dlast; ++d) {
       nodes += 1 << d;
-      nemax = std::max(nemax, wa * j.xc.w(d));
+      for (int q = 0; q < nj; ++q) nemax = std::max(nemax, wa * js[q].xc.w(d));
     }
     if (nemax > 0) {
-      dim3 g2(ceil_div(nemax, 64), nodes);
+      dim3 g2(ceil_div(nemax, 64), nodes, nj);
       hipLaunchKernelGGL(k_reduce_tree, g2, dim3(256), 0, m->stream, a, dlast);
       HM_LAUNCH_CHECK();
     }
@@ -548,7 +633,34 @@ struct ExpArgs {
   int ylo, yhi;  // union of the output columns
   int sel_mode, sel_depth;
   const double* A2; const double* T2; double t2_scale;   // second source (A2 null: none)
+  // Up to two further independent jobs in the same launch (grid.z = jobs x nz): their
+  // own A, Y, output columns, T and second source; everything else is shared.
+  int nz = 0;
+  const double* jA[2] = {nullptr, nullptr};
+  double* jY[2] = {nullptr, nullptr};
+  ColSpec jyc[2] = {};
+  int jyhi[2] = {0, 0};
+  const double* jT[2] = {nullptr, nullptr};
+  const double* jA2[2] = {nullptr, nullptr};
+  const double* jT2[2] = {nullptr, nullptr};
+  double jt2s[2] = {0.0, 0.0};
 };
+// the arguments of job q (0: the launch's own)
+__device__ __forceinline__ ExpArgs exp_job(const ExpArgs& a0, int q) {
+  ExpArgs a = a0;
+  if (q > 0) {
+    const bool s = q > 1;
+    a.A = s ? a0.jA[1] : a0.jA[0];
+    a.Y = s ? a0.jY[1] : a0.jY[0];
+    a.yc = s ? a0.jyc[1] : a0.jyc[0];
+    a.yhi = s ? a0.jyhi[1] : a0.jyhi[0];
+    a.T = s ? a0.jT[1] : a0.jT[0];
+    a.A2 = s ? a0.jA2[1] : a0.jA2[0];
+    a.T2 = s ? a0.jT2[1] : a0.jT2[0];
+    a.t2_scale = s ? a0.jt2s[1] : a0.jt2s[0];
+  }
+  return a;
+}
 
 // Expand with the tall operand fed straight into the matrix cores (P = 0 FP64,
 // P = 1 FP32 operands and accumulation for the mixed-precision policy).  The
@@ -605,19 +717,22 @@ __device__ __forceinline__ const double* exp_T(const ExpArgs& a, int src, int L,
 }
 
 template <int P, int NB, int RB, int NWV>
-__global__ void __launch_bounds__(64 * NWV) k_expand_direct(ExpArgs a) {
+__global__ void __launch_bounds__(64 * NWV) k_expand_direct(ExpArgs a0) {
   constexpr int NT = 64 * NWV;
   constexpr int EXT = EXK * 64 / NT;
   constexpr int CS = NT / EXK;   // T columns staged per pass of the workgroup
   using MP = MfmaPrec<P>;
   using T = typename MP::T;
   __shared__ T Ts[2][EXK * 65];
-  // grid.z enumerates the selected leaves
+  // grid.z enumerates (job, selected leaf)
   const TileIdx tb = tile_block();
-  const int L = selected_leaf(tb.z, a.levels, a.sel_mode, a.sel_depth);
+  const int q = tb.z / a0.nz;
+  const ExpArgs a = exp_job(a0, q);
+  const int L = selected_leaf(tb.z - q * a0.nz, a.levels, a.sel_mode, a.sel_depth);
   constexpr int TW = 16 * NB;   // tile width in output columns
   const int m0 = tb.x * (16 * RB * NWV);
   const int j0 = a.ylo + tb.y * TW;
+  if (j0 >= a.yhi) return;   // a job narrower than the launch's widest
   const long r0 = (long)L * a.nl;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
@@ -797,39 +912,101 @@ static void launch_expand_direct(Model* m, int nb, dim3 grid, const ExpArgs& a, 
   else hipExtLaunchKernelGGL((k_expand_direct<P, 4, RB, NWV>), grid, blk, 0, m->stream, ea, eb, 0, a);
 }
 
-hm_status tree_expand(Model* m, const ExpandJob& j) {
-  if (j.d0 < 1 || j.d1 > m->levels || j.d0 > j.d1) {
-    set_error("tree_expand: bad depth range");
-    return HM_E_INVAL;
+// Jobs that can share one launch: same A layout, T layout, depths, scaling and
+// selection, and the same first output column; at most three.
+static bool expand_jobs_compatible(const ExpandJob* js, int nj, const int* ylo) {
+  if (nj < 2 || nj > 3) return false;
+  const ExpandJob& b = js[0];
+  for (int q = 1; q < nj; ++q) {
+    const ExpandJob& a = js[q];
+    if (a.lda != b.lda || a.ldy != b.ldy || a.t_stride != b.t_stride || a.ldt != b.ldt || a.tmode != b.tmode ||
+        a.half_off != b.half_off || a.d0 != b.d0 || a.d1 != b.d1 || a.alpha != b.alpha || a.beta != b.beta ||
+        a.sel.mode != b.sel.mode || a.sel.depth != b.sel.depth || a.ac.base != b.ac.base ||
+        a.ac.stride != b.ac.stride || a.ac.w0 != b.ac.w0 || a.ac.grow != b.ac.grow || ylo[q] != ylo[0])
+      return false;
   }
-  if (!sel_valid(m, j.sel)) {
-    set_error("tree_expand: bad leaf selection");
-    return HM_E_INVAL;
+  return true;
+}
+
+hm_status tree_expand(Model* m, const ExpandJob& j) { return tree_expand_multi(m, &j, 1); }
+
+hm_status tree_expand_multi(Model* m, const ExpandJob* js, int nj) {
+  if (nj <= 0) return HM_OK;
+  if (nj > 3) {
+    for (int q = 0; q < nj; ++q) HM_CHECK(tree_expand_multi(m, js + q, 1));
+    return HM_OK;
   }
-  int ylo = 1 << 30, yhi = -1;
-  for (int d = j.d0; d <= j.d1; ++d) {
-    if (j.yc.w(d) <= 0) continue;
-    ylo = std::min(ylo, j.yc.c0(d));
-    yhi = std::max(yhi, j.yc.c0(d) + j.yc.w(d));
+  int ylo[3], yhi[3];
+  for (int q = 0; q < nj; ++q) {
+    const ExpandJob& j = js[q];
+    if (j.d0 < 1 || j.d1 > m->levels || j.d0 > j.d1) {
+      set_error("tree_expand: bad depth range");
+      return HM_E_INVAL;
+    }
+    if (!sel_valid(m, j.sel)) {
+      set_error("tree_expand: bad leaf selection");
+      return HM_E_INVAL;
+    }
+    if (j.A2 && (!j.T2 || j.alpha == 0.0)) {
+      set_error("tree_expand: a second source needs its T blocks and a nonzero alpha");
+      return HM_E_INVAL;
+    }
+    ylo[q] = 1 << 30;
+    yhi[q] = -1;
+    for (int d = j.d0; d <= j.d1; ++d) {
+      if (j.yc.w(d) <= 0) continue;
+      ylo[q] = std::min(ylo[q], j.yc.c0(d));
+      yhi[q] = std::max(yhi[q], j.yc.c0(d) + j.yc.w(d));
+    }
   }
-  if (yhi <= ylo) return HM_OK;
-  if (j.A2 && (!j.T2 || j.alpha == 0.0)) {
-    set_error("tree_expand: a second source needs its T blocks and a nonzero alpha");
-    return HM_E_INVAL;
+  if (nj > 1) {
+    bool empty = false;
+    for (int q = 0; q < nj; ++q) empty = empty || yhi[q] <= ylo[q];
+    if (empty || !expand_jobs_compatible(js, nj, ylo)) {
+      for (int q = 0; q < nj; ++q) HM_CHECK(tree_expand_multi(m, js + q, 1));
+      return HM_OK;
+    }
+  }
+  const ExpandJob& j = js[0];
+  if (yhi[0] <= ylo[0]) return HM_OK;
+  int wmax = 0;
+  bool fixed = true;   // every job's output columns are one range shared by all depths
+  for (int q = 0; q < nj; ++q) {
+    wmax = std::max(wmax, yhi[q] - ylo[0]);
+    fixed = fixed && js[q].yc.stride == 0 && js[q].yc.grow == 0;
   }
   ExpArgs a{j.A, j.lda, j.ac, j.Y, j.ldy, j.yc, j.T, j.t_stride, j.ldt, j.tmode, j.half_off,
-            j.d0, j.d1, m->levels, m->nl, j.alpha, j.beta, ylo, yhi, j.sel.mode, j.sel.depth,
+            j.d0, j.d1, m->levels, m->nl, j.alpha, j.beta, ylo[0], yhi[0], j.sel.mode, j.sel.depth,
             j.A2, j.T2, j.A2 ? j.alpha2 / j.alpha : 0.0};
+  for (int q = 1; q < nj; ++q) {
+    a.jA[q - 1] = js[q].A;
+    a.jY[q - 1] = js[q].Y;
+    a.jyc[q - 1] = js[q].yc;
+    a.jyhi[q - 1] = yhi[q];
+    a.jT[q - 1] = js[q].T;
+    a.jA2[q - 1] = js[q].A2;
+    a.jT2[q - 1] = js[q].T2;
+    a.jt2s[q - 1] = js[q].A2 ? js[q].alpha2 / js[q].alpha : 0.0;
+  }
   const bool pf = prof_on(m, PF_EXPAND);
   hipEvent_t ea = nullptr, eb = nullptr;
   if (pf) prof_begin_launch(m, PF_EXPAND, ea, eb);
   // output blocks of 16 columns per tile: a launch narrower than 64 columns runs
   // fewer MFMA blocks; a wide output made of panel blocks (cs_block / cs_prefix of a
   // width that is a multiple of 16) is tiled at that width, so no tile straddles two
-  // blocks with different segment sets
+  // blocks with different segment sets; a wide output of one column range for all
+  // depths takes 48 or 64 columns, whichever pads the jobs' widths less
   int nb;
-  if (yhi - ylo <= 64) {
-    nb = ceil_div(yhi - ylo, 16);
+  if (wmax <= 64) {
+    nb = ceil_div(wmax, 16);
+  } else if (fixed) {
+    long pad3 = 0, pad4 = 0;
+    for (int q = 0; q < nj; ++q) {
+      const int w = yhi[q] - ylo[0];
+      pad3 += 48L * ceil_div(w, 48) - w;
+      pad4 += 64L * ceil_div(w, 64) - w;
+    }
+    nb = pad3 < pad4 ? 3 : 4;
   } else {
     const int bw = (j.yc.stride > 0 && j.yc.stride == j.yc.w0 && j.yc.grow == 0) ? j.yc.w0
                    : (j.yc.w0 == 0 && j.yc.stride == 0 && j.yc.grow > 0 ? j.yc.grow : 0);
@@ -841,7 +1018,8 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
   const int var = m->tune_expand_rb ? m->tune_expand_rb : 1;
   const int rb = (var == 2) ? 2 : 1, nwv = (var == 3) ? 8 : 4;
   const int nsel = count_selected(m->nleaves, m->levels, j.sel);
-  dim3 grid(ceil_div(m->nl, 16 * rb * nwv), ceil_div(yhi - ylo, 16 * nb), nsel);
+  a.nz = nsel;
+  dim3 grid(ceil_div(m->nl, 16 * rb * nwv), ceil_div(wmax, 16 * nb), nsel * nj);
   if (m->panel_prec == 2) {
     if (var == 2) launch_expand_direct<2, 2, 4>(m, nb, grid, a, ea, eb);
     else if (var == 3) launch_expand_direct<2, 1, 8>(m, nb, grid, a, ea, eb);
@@ -858,17 +1036,18 @@ hm_status tree_expand(Model* m, const ExpandJob& j) {
   HM_LAUNCH_CHECK();
   if (pf) {
     const int wk = j.ac.w0;
-    const double rows = (double)count_selected(m->nleaves, m->levels, j.sel) * m->nl;
-    const double nsel = rows / m->nl;
-    const double nsrc = j.A2 ? 2.0 : 1.0;   // a second source doubles the products
+    const double rows = (double)nsel * m->nl;
     double fl = 0.0, by = 0.0;
-    for (int d = j.d0; d <= j.d1; ++d) {
-      const int wy = j.yc.w(d);
-      if (wy <= 0) continue;
-      fl += nsrc * 2.0 * rows * wk * wy;
-      by += nsrc * 8.0 * (rows * wk + std::min(nsel, (double)(1 << d)) * wk * wy);
+    for (int q = 0; q < nj; ++q) {
+      const double nsrc = js[q].A2 ? 2.0 : 1.0;   // a second source doubles the products
+      for (int d = j.d0; d <= j.d1; ++d) {
+        const int wy = js[q].yc.w(d);
+        if (wy <= 0) continue;
+        fl += nsrc * 2.0 * rows * wk * wy;
+        by += nsrc * 8.0 * (rows * wk + std::min((double)nsel, (double)(1 << d)) * wk * wy);
+      }
+      by += 8.0 * rows * (yhi[q] - ylo[q]) * (j.beta == 0.0 ? 1.0 : 2.0);
     }
-    by += 8.0 * rows * (yhi - ylo) * (j.beta == 0.0 ? 1.0 : 2.0);
     prof_end(m, PF_EXPAND, fl, by);
   }
   return HM_OK;

@@ -111,14 +111,17 @@ __global__ void __launch_bounds__(256) k_chol_inv(const double* G, long gstride,
   }
 }
 
-// M = triu(W) + strict_tril(W)^T, W k x k (ld k) per node; zero outside k_P.
-__global__ void k_alg2_fold(const double* W, double* M, long stride, int k, int heap0) {
+// M = triu(W) + strict_tril(W)^T, W k x k (ld k) per node; zero outside k_P.  trans:
+// the node holds W^T instead of W.
+__global__ void k_alg2_fold(const double* W, double* M, long stride, int k, int heap0, int trans) {
   const int node = heap0 + blockIdx.x;
   const double* w = W + node * stride;
   double* mm = M + node * stride;
   for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
-    int i = e % k, j = e / k;
-    mm[e] = (i <= j) ? w[i + j * k] + ((i < j) ? w[j + i * k] : 0.0) : 0.0;
+    const int i = e % k, j = e / k;
+    const double wij = trans ? w[j + i * k] : w[i + j * k];
+    const double wji = trans ? w[i + j * k] : w[j + i * k];
+    mm[e] = (i <= j) ? wij + ((i < j) ? wji : 0.0) : 0.0;
   }
 }
 
@@ -254,8 +257,8 @@ hm_status chol_inv_nodes(Model* m, const double* G, long gstride, double* R, dou
   return HM_OK;
 }
 
-hm_status alg2_fold_nodes(Model* m, const double* W, double* M, long stride, int k, int heap0, int cnt) {
-  hipLaunchKernelGGL(k_alg2_fold, dim3(cnt), dim3(256), 0, m->stream, W, M, stride, k, heap0);
+hm_status alg2_fold_nodes(Model* m, const double* W, double* M, long stride, int k, int heap0, int cnt, bool trans) {
+  hipLaunchKernelGGL(k_alg2_fold, dim3(cnt), dim3(256), 0, m->stream, W, M, stride, k, heap0, trans ? 1 : 0);
   HM_LAUNCH_CHECK();
   return HM_OK;
 }
