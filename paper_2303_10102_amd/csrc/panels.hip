@@ -167,10 +167,11 @@ struct RedArgs {
   double* partial; long pstride;  // per (leaf, depth) stride = wa * max wx
   int sel_mode, sel_depth;
   int only_sel = 0;   // the tree sums skip nodes without selected leaves
-  // Up to two further independent jobs in the same launch (grid.z = jobs x nz of the
-  // products, grid.z = jobs of the tree sums): each has its own operands, output, X
-  // columns and partial area; everything else is shared.
-  int nz = 0;
+  // Up to two further independent jobs in the same launch (grid.z = nj x the products'
+  // (leaf, depth) count, job fastest so that every XCD's share of the tiles mixes the
+  // jobs; grid.z = jobs of the tree sums): each has its own operands, output, X columns
+  // and partial area; everything else is shared.
+  int nj = 1;
   const double* jA[2] = {nullptr, nullptr};
   const double* jX[2] = {nullptr, nullptr};
   double* jout[2] = {nullptr, nullptr};
@@ -208,9 +209,9 @@ k_reduce_direct(RedArgs a0) {
   using MP = MfmaPrec<P>;
   using T = typename MP::T;
   __shared__ double red[(NW - 1) * MB * NB * 4 * 64];
-  // grid.z enumerates (job, selected leaf, depth), depth fastest
+  // grid.z enumerates (selected leaf, depth, job), job fastest, then depth
   const TileIdx tb = tile_block();
-  const int q = tb.z / a0.nz, zz = tb.z - q * a0.nz;
+  const int zz = tb.z / a0.nj, q = tb.z - zz * a0.nj;
   const RedArgs a = red_job(a0, q);
   const int ndep = a.d1 - a.d0 + 1;
   const int L = selected_leaf(zz / ndep, a.levels, a.sel_mode, a.sel_depth);
@@ -562,7 +563,7 @@ hm_status tree_reduce_multi(Model* m, const ReduceJob* js, int nj) {
   const bool xid = nj == 1 && is_ident(j.X, j.xc) && j.sel.mode == 0;
   const bool aid = nj == 1 && is_ident(j.A, j.ac) && j.sel.mode == 0 && j.xc.grow == 0;
   const int nsel = count_selected(m->nleaves, m->levels, j.sel);
-  a.nz = nsel * ndep;
+  a.nj = nj;
   if (xid || aid) {
     // sums of leaf blocks (no product): A[c]^T S[c] (xid) or S[c]^T X[c] (aid)
     const double* P = xid ? j.A : j.X;
@@ -580,7 +581,7 @@ hm_status tree_reduce_multi(Model* m, const ReduceJob* js, int nj) {
       return (nbk % 3 == 0) ? 3 : (nbk % 2 == 0 ? 2 : 3);
     };
     const int mb = blocks(wa), nb = blocks(wxmax);
-    dim3 grid(ceil_div(wa, 16 * mb), ceil_div(wxmax, 16 * nb), a.nz * nj);
+    dim3 grid(ceil_div(wa, 16 * mb), ceil_div(wxmax, 16 * nb), nsel * ndep * nj);
     // few workgroups (e.g. one depth of per-leaf products): split each leaf's rows
     // over four wavefronts instead of two
     const long wgs = (long)grid.x * grid.y * grid.z;
@@ -633,9 +634,10 @@ struct ExpArgs {
   int ylo, yhi;  // union of the output columns
   int sel_mode, sel_depth;
   const double* A2; const double* T2; double t2_scale;   // second source (A2 null: none)
-  // Up to two further independent jobs in the same launch (grid.z = jobs x nz): their
+  // Up to two further independent jobs in the same launch (grid.z = nj x the selected
+  // leaves, job fastest so that every XCD's share of the tiles mixes the jobs): their
   // own A, Y, output columns, T and second source; everything else is shared.
-  int nz = 0;
+  int nj = 1;
   const double* jA[2] = {nullptr, nullptr};
   double* jY[2] = {nullptr, nullptr};
   ColSpec jyc[2] = {};
@@ -724,11 +726,11 @@ __global__ void __launch_bounds__(64 * NWV) k_expand_direct(ExpArgs a0) {
   using MP = MfmaPrec<P>;
   using T = typename MP::T;
   __shared__ T Ts[2][EXK * 65];
-  // grid.z enumerates (job, selected leaf)
+  // grid.z enumerates (selected leaf, job), job fastest
   const TileIdx tb = tile_block();
-  const int q = tb.z / a0.nz;
+  const int zl = tb.z / a0.nj, q = tb.z - zl * a0.nj;
   const ExpArgs a = exp_job(a0, q);
-  const int L = selected_leaf(tb.z - q * a0.nz, a.levels, a.sel_mode, a.sel_depth);
+  const int L = selected_leaf(zl, a.levels, a.sel_mode, a.sel_depth);
   constexpr int TW = 16 * NB;   // tile width in output columns
   const int m0 = tb.x * (16 * RB * NWV);
   const int j0 = a.ylo + tb.y * TW;
@@ -1018,7 +1020,7 @@ hm_status tree_expand_multi(Model* m, const ExpandJob* js, int nj) {
   const int var = m->tune_expand_rb ? m->tune_expand_rb : 1;
   const int rb = (var == 2) ? 2 : 1, nwv = (var == 3) ? 8 : 4;
   const int nsel = count_selected(m->nleaves, m->levels, j.sel);
-  a.nz = nsel;
+  a.nj = nj;
   dim3 grid(ceil_div(m->nl, 16 * rb * nwv), ceil_div(wmax, 16 * nb), nsel * nj);
   if (m->panel_prec == 2) {
     if (var == 2) launch_expand_direct<2, 2, 4>(m, nb, grid, a, ea, eb);

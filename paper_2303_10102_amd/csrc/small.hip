@@ -11,6 +11,7 @@
 #include <cmath>
 
 #include "hm_internal.h"
+#include "gemm_core.h"
 
 namespace hm {
 
@@ -36,78 +37,113 @@ __device__ __forceinline__ void axpy_strided(double* dst, long ds, const double*
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky + triangular inverse of G (k x k, ld k), one node per workgroup.
-// shift: if nonzero, G + s I with s = 11 (m k + k (k+1)) u ||.||_F^2, m = rows of
-// the sketched block (shifted Cholesky-QR of Fukaya et al.); ||Y||_F^2 = tr(G).
-// Zero columns (k_P < k) are kept as identity so padding stays exactly zero.
+// Cholesky + triangular inverse of G (k x k, ld k), one node per workgroup of two
+// wavefronts.  shift: if nonzero, G + s I with s = 11 (m k + k (k+1)) u ||.||_F^2,
+// m = rows of the sketched block (shifted Cholesky-QR of Fukaya et al.);
+// ||Y||_F^2 = tr(G).  Zero columns (k_P < k) are kept as identity so padding stays
+// exactly zero.
+//
+// Right-looking Cholesky fused with the forward elimination of L Y = I.  With
+// d_j = A(j, j) after step j - 1 and l_ij = A(i, j) / sqrt(d_j), step j does
+//   A(i, l) -= A(i, j) A(l, j) / d_j          (j < l <= i)
+//   Y(i, c) -= A(i, j) / d_j * Y(j, c)        (i > j)
+// and L^{-1}(i, c) = Y(i, c) / sqrt(d_i).  Both updates need only column j of A,
+// which is broadcast through LDS: lane x of wavefront 0 holds row x of A, lane x of
+// wavefront 1 column x of Y, in registers (KP >= k entries; rows and columns
+// k..KP-1 an identity block that changes nothing).  A step is one barrier and
+// KP - j - 1 broadcast reads, each feeding one fused multiply-add per lane.  A pivot
+// that is not positive is flagged and taken as 1.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_chol_inv(const double* G, long gstride, double* R, double* Rinv,
+template <int KP>
+__global__ void __launch_bounds__(128) k_chol_inv(const double* G, long gstride, double* R, double* Rinv,
                                                   long rstride, int k, const int* kblk, int heap0, int hstep,
                                                   int shift, long mrows, int* flags) {
-  __shared__ double A[KMAX * KMAX];
+  __shared__ double colj[2][64];
+  __shared__ double dd[64];
   const int node = heap0 + blockIdx.x * hstep;
   // kept rank of the block whose left child is this node (kblk indexed by parent)
   const int kp = kblk ? kblk[(node - 1) >> 1] : k;
   const double* g = G + node * gstride;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int e = tid; e < k * k; e += nt) {
-    int i = e % k, j = e / k;
-    double v = g[e];
-    if (i >= kp || j >= kp) v = (i == j) ? 1.0 : 0.0;
-    A[e] = v;
+  const int lane = threadIdx.x & 63;
+  const bool rows = threadIdx.x < 64;   // wavefront 0: rows of A; wavefront 1: columns of Y
+  const bool real = lane < kp;
+  double s = 0.0;
+  if (shift && rows) {
+    double t = real ? g[lane + (long)lane * k] : 0.0;
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+    s = 11.0 * ((double)mrows * kp + (double)kp * (kp + 1)) * 1.1102230246251565e-16 * t;
   }
-  __syncthreads();
-  if (shift) {
-    __shared__ double tr;
-    if (tid == 0) {
-      double t = 0.0;
-      for (int i = 0; i < kp; ++i) t += A[i + i * k];
-      tr = 11.0 * ((double)mrows * kp + (double)kp * (kp + 1)) * 1.1102230246251565e-16 * t;
+  double X[KP];
+#pragma unroll
+  for (int l = 0; l < KP; ++l) {
+    double v;
+    if (rows) {
+      v = (real && l < kp) ? g[lane + (long)l * k] : (lane == l ? 1.0 : 0.0);
+      if (real && l == lane) v += s;
+    } else {
+      v = (l == lane) ? 1.0 : 0.0;
     }
-    __syncthreads();
-    for (int i = tid; i < kp; i += nt) A[i + i * k] += tr;
-    __syncthreads();
+    X[l] = v;
   }
-  // Right-looking Cholesky fused with the forward elimination of L Y = I, one barrier
-  // per column.  Step j reads column j of the Schur-updated A (final after step j-1)
-  // and row j of Y, and writes only columns / rows past j, so nothing it reads is
-  // written in the same step.  With d_j = A(j, j), l_ij = A(i, j) / sqrt(d_j):
-  //   A(i, l) -= A(i, j) A(l, j) / d_j          (j < l <= i)
-  //   Y(i, c) -= A(i, j) / d_j * Y(j, c)        (i > j, c <= j)
-  // and L^{-1}(i, c) = Y(i, c) / sqrt(d_i).  A pivot that is not positive is flagged
-  // and taken as 1.
-  __shared__ double Y[KMAX * KMAX];
-  for (int e = tid; e < k * k; e += nt) Y[e] = (e % k == e / k) ? 1.0 : 0.0;
-  __syncthreads();
-  // Lane i of every wavefront owns row i (k <= 64); wavefront w takes the columns
-  // congruent to w modulo the wavefront count, so the pivot-row operand is a broadcast.
+  double myd = 1.0;
   bool bad = false;
-  const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
-  for (int j = 0; j < k; ++j) {
-    double d = A[j + j * k];
-    if (!(d > 0.0)) { bad = true; d = 1.0; }
-    const double rd = 1.0 / d;
-    const int i = lane;
-    if (i > j && i < k) {
-      const double f = A[i + j * k] * rd;
-      axpy_strided(A + i, k, A + (long)j * k, 1, f, j + 1 + wave, i + 1, nw);   // column j is not written
-      axpy_strided(Y + i, k, Y + j, k, f, wave, j + 1, nw);                     // row j is not written
+  // the two wavefronts run their own copy of the step loop (the same barriers), so
+  // that each step's broadcast reads form one straight run of code
+  if (rows) {
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+      double* cb = colj[j & 1];
+      cb[lane] = X[j];
+      __syncthreads();
+      double d = cb[j];
+      if (!(d > 0.0)) {
+        bad = true;
+        d = 1.0;
+      }
+      if (lane == j) myd = d;
+      const double f = X[j] * (1.0 / d);   // the row's multiplier A(x, j) / d_j
+#pragma unroll
+      for (int l = j + 1; l < KP; ++l) {
+        const double al = X[l] - f * cb[l];
+        X[l] = (l <= lane) ? al : X[l];
+      }
+#pragma unroll
+      for (int l = j + 1; l < KP; ++l) asm volatile("" : "+v"(X[l]));
     }
-    __syncthreads();
+  } else {
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+      const double* cb = colj[j & 1];
+      __syncthreads();
+      double d = cb[j];
+      if (!(d > 0.0)) d = 1.0;
+      if (lane == j) myd = d;
+      const double rd = 1.0 / d;
+      const double f = X[j];   // Y(j, x)
+#pragma unroll
+      for (int l = j + 1; l < KP; ++l) X[l] -= (cb[l] * rd) * f;
+#pragma unroll
+      for (int l = j + 1; l < KP; ++l) asm volatile("" : "+v"(X[l]));
+    }
   }
-  if (bad && tid == 0) atomicOr(flags, (int)DF_QR_FAIL);
-  // R = L^T (upper), Rinv = (L^{-1})^T
-  double* Ro = R + node * rstride;
-  double* Ri = Rinv + node * rstride;
-  for (int e = tid; e < k * k; e += nt) {
-    const int i = e % k, j = e / k;
-    double dj = A[j + j * k], di = A[i + i * k];
-    if (!(dj > 0.0)) dj = 1.0;
-    if (!(di > 0.0)) di = 1.0;
-    // R(i, j) = L(j, i) for i <= j
-    Ro[e] = (i < j) ? A[j + i * k] / sqrt(di) : (i == j ? sqrt(di) : 0.0);
-    // Rinv(i, j) = L^{-1}(j, i) = Y(j, i) / sqrt(d_j) for j >= i
-    Ri[e] = (j >= i) ? Y[j + i * k] / sqrt(dj) : 0.0;
+  if (bad && threadIdx.x == 0) atomicOr(flags, (int)DF_QR_FAIL);
+  if (rows) dd[lane] = myd;
+  __syncthreads();
+  if (lane < k) {
+    if (rows) {
+      // R = L^T (upper): column j of R is row j of L, held by lane j
+      double* Ro = R + node * rstride + (long)lane * k;
+      const double sj = sqrt(myd);
+#pragma unroll
+      for (int i = 0; i < KP; ++i)
+        if (i < k) Ro[i] = (i < lane) ? X[i] / sqrt(dd[i]) : (i == lane ? sj : 0.0);
+    } else {
+      // Rinv = (L^{-1})^T: Rinv(i, j) = Y(j, i) / sqrt(d_j) for j >= i; row i held by lane i
+      double* Ri = Rinv + node * rstride + lane;
+#pragma unroll
+      for (int j = 0; j < KP; ++j)
+        if (j < k) Ri[(long)j * k] = (j >= lane) ? X[j] / sqrt(dd[j]) : 0.0;
+    }
   }
 }
 
@@ -132,116 +168,186 @@ __global__ void k_alg2_fold(const double* W, double* M, long stride, int k, int 
 //   M_P^{-1} = [[I + S_b Sig^{-1} S_a, -S_b Sig^{-1}], [-Sig^{-1} S_a, Sig^{-1}]],
 //   N_P = M_P^{-1} J = [[-S_b Sig^{-1}, I + S_b Sig^{-1} S_a], [Sig^{-1}, -Sig^{-1} S_a]] = (J + S_P)^{-1}.
 // logdet_P = log det M_P (> 0 required, else the node is flagged not SPD).
+//
+// One node per workgroup of four wavefronts.  The k x k products run on the FP64
+// matrix cores from LDS (leading dimension KP + 1, odd, so that column reads hit
+// distinct banks); k..KP-1 is a zero border of S_a and S_b, i.e. an identity block of
+// Sig that pivots on itself and changes nothing.
 // ---------------------------------------------------------------------------
+// C tile (ti, tj) of A B (KP x KP, ld LD, in LDS) into a 16 x 16 accumulator:
+// element v of lane l is C(16 ti + 4 v + l / 16, 16 tj + l % 16)
+template <int KP>
+__device__ __forceinline__ hm_v4d node_mm_tile(const double* A, const double* B, int ti, int tj, int lane) {
+  constexpr int LD = KP + 1;
+  const int li = lane & 15, lk = lane >> 4;
+  hm_v4d acc = MfmaPrec<0>::zero();
+#pragma unroll
+  for (int kk = 0; kk < KP; kk += 4)
+    acc = MfmaPrec<0>::mfma(A[(16 * ti + li) + (kk + lk) * LD], B[(kk + lk) + (16 * tj + li) * LD], acc);
+  return acc;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int KP>
 __global__ void __launch_bounds__(256) k_node_lu(const double* S, long sstride, double* Nout, long nstride,
                                                  double* logdet, int k, int heap0, int* flags) {
-  __shared__ double Sa[KMAX * KMAX];
-  __shared__ double Sb[KMAX * KMAX];
-  __shared__ double A[KMAX * KMAX];     // Sig, eliminated in place
-  __shared__ double Si[KMAX * KMAX];    // the accumulated row operations, then Sig^{-1}
-  __shared__ int piv[KMAX];
+  constexpr int LD = KP + 1, NT = KP / 16;
+  __shared__ double Sa[KP * LD];
+  __shared__ double Sb[KP * LD];
+  __shared__ double Sg[KP * LD];   // Sig, then Sig^{-1}
+  __shared__ double Si[KP * LD];   // the accumulated row operations, then S_b Sig^{-1}
+  __shared__ double mul[2][64];
+  __shared__ double prow[2][64];   // pivot row of wavefront 0 (Sig) and 1 (row operations)
+  __shared__ int piv[64];
+  __shared__ double pval[64];
   const int P = heap0 + blockIdx.x;
   const int a = 2 * P + 1, b = 2 * P + 2;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int kk = k * k;
-  for (int e = tid; e < kk; e += nt) {
-    Sa[e] = S[a * sstride + e];
-    Sb[e] = S[b * sstride + e];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int e = tid; e < KP * KP; e += 256) {
+    const int i = e % KP, j = e / KP;
+    const bool in = i < k && j < k;
+    Sa[i + j * LD] = in ? S[a * sstride + i + (long)j * k] : 0.0;
+    Sb[i + j * LD] = in ? S[b * sstride + i + (long)j * k] : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < kk; e += nt) {
-    int i = e % k, j = e / k;
-    double v = (i == j) ? 1.0 : 0.0;
-    for (int l = 0; l < k; ++l) v -= Sa[i + l * k] * Sb[l + j * k];
-    A[e] = v;
+  const int li = lane & 15, lk = lane >> 4;
+  // Sig = I - S_a S_b
+  for (int t = wave; t < NT * NT; t += 4) {
+    const int ti = t % NT, tj = t / NT;
+    const hm_v4d acc = node_mm_tile<KP>(Sa, Sb, ti, tj, lane);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * ti + 4 * v + lk, c = 16 * tj + li;
+      Sg[r + c * LD] = (r == c ? 1.0 : 0.0) - acc[v];
+    }
   }
-  for (int e = tid; e < kk; e += nt) Si[e] = (e % k == e / k) ? 1.0 : 0.0;
   __syncthreads();
-  // Gauss-Jordan elimination with partial pivoting on [Sig | I], one barrier per
-  // column.  Every wavefront finds the pivot of column j itself (the largest |A(i, j)|
-  // over rows not yet used, ties to the lower row; lane i holds row i), so no barrier
-  // separates the search from the update; the pivot row p is only read in step j.
-  // All other rows are eliminated: A(i, c) -= A(i, j) / A(p, j) A(p, c) for c > j and
-  // the same on Y = Si, after which Sig^{-1}(j, :) = Y(p_j, :) / A(p_j, j) and
-  // det Sig = sign(pivot permutation) * prod_j A(p_j, j).
-  const int lane = tid & 63;
-  bool used = lane >= k;
-  __shared__ double pval[KMAX];
-  for (int j = 0; j < k; ++j) {
-    double best = -1.0;
-    int bi = KMAX;
-    if (!used) {
-      best = fabs(A[lane + j * k]);
-      if (!(best <= INFINITY)) best = INFINITY;   // NaN ranks first: the order stays total
-      bi = lane;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
-    const int p = bi;
-    if (lane == p) used = true;
-    const double pv = A[p + j * k];
-    if (tid == 0) { piv[j] = p; pval[j] = pv; }
-    const double rp = (pv != 0.0) ? 1.0 / pv : 0.0;
-    // lane i owns row i; wavefront w takes columns congruent to w (pivot row: broadcast)
-    if (lane < k && lane != p) {
-      const double f = A[lane + j * k] * rp;
-      const int wave = tid >> 6, nw = nt >> 6;
-      axpy_strided(A + lane, k, A + p, k, f, j + 1 + wave, k, nw);   // row p is not written
-      axpy_strided(Si + lane, k, Si + p, k, f, wave, k, nw);
+  // Gauss-Jordan elimination with partial pivoting on [Sig | I]: lane i of wavefront 0
+  // holds row i of Sig, lane i of wavefront 1 row i of the row operations Y.  Step j:
+  // wavefront 0 finds the pivot p_j (the largest |Sig(i, j)| over rows not yet used,
+  // ties to the lower row) and the multipliers Sig(i, j) / Sig(p_j, j); every other
+  // row subtracts its multiple of row p_j, broadcast through LDS by its owner.  Then
+  // Sig^{-1}(j, :) = Y(p_j, :) / Sig(p_j, j) and det Sig = sign(pivot permutation) *
+  // prod_j Sig(p_j, j).
+  // Wavefront 0 keeps only the columns not yet eliminated, shifted so that X[0] is
+  // column j at step j (every register index stays a constant).
+  double X[KP];
+#pragma unroll
+  for (int c = 0; c < KP; ++c) X[c] = (wave == 0 && lane < KP) ? Sg[lane + c * LD] : (lane == c ? 1.0 : 0.0);
+  bool used = lane >= KP;
+#pragma unroll 1
+  for (int j = 0; j < KP; ++j) {
+    if (wave == 0) {
+      double best = -1.0;
+      int bi = 64;
+      if (!used) {
+        best = fabs(X[0]);
+        if (!(best <= INFINITY)) best = INFINITY;   // NaN ranks first: the order stays total
+        bi = lane;
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      const int p = __builtin_amdgcn_readfirstlane(bi);
+      const double pv = readlane_d(X[0], p);
+      const double rp = (pv != 0.0) ? 1.0 / pv : 0.0;
+      mul[j & 1][lane] = (lane != p) ? X[0] * rp : 0.0;
+      if (lane == p) used = true;
+      if (lane == 0) {
+        piv[j] = p;
+        pval[j] = pv;
+      }
     }
     __syncthreads();
+    if (wave < 2) {
+      const int p = piv[j];
+      const double f = mul[j & 1][lane];   // 0 on the pivot row
+      double* rb = prow[wave];
+      if (lane == p) {
+#pragma unroll
+        for (int c = 0; c < KP; ++c) rb[c] = X[c];
+      }
+      if (wave == 0) {
+        // columns j+1.. (X[1..]) minus f times the pivot row's, shifted down by one
+#pragma unroll
+        for (int c = 0; c + 1 < KP; ++c) X[c] = X[c + 1] - f * rb[c + 1];
+        X[KP - 1] = 0.0;
+      } else {
+#pragma unroll
+        for (int c = 0; c < KP; ++c) X[c] -= f * rb[c];
+      }
+#pragma unroll
+      for (int c = 0; c < KP; ++c) asm volatile("" : "+v"(X[c]));
+    }
   }
-  // Sig^{-1}(j, c) = Y(p_j, c) / A(p_j, j), into A (column j of A is read no more)
-  for (int e = tid; e < kk; e += nt) {
-    const int j = e % k, c = e / k;
-    A[e] = Si[piv[j] + c * k] / pval[j];
+  // Y rows into LDS; then Sig^{-1}(j, c) = Y(p_j, c) / Sig(p_j, j) into Sg
+  if (wave == 1 && lane < KP) {
+#pragma unroll
+    for (int c = 0; c < KP; ++c) Si[lane + c * LD] = X[c];
   }
   __syncthreads();
-  for (int e = tid; e < kk; e += nt) Si[e] = A[e];
-  if (tid == 0) {
+  for (int e = tid; e < KP * KP; e += 256) {
+    const int j = e % KP, c = e / KP;
+    Sg[j + c * LD] = Si[piv[j] + c * LD] / pval[j];
+  }
+  if (wave == 3) {
     // log |det| and the sign: pivot signs times the parity of the pivot permutation
+    // (its inversion count), over the first k steps (the border pivots on itself)
     double ls = 0.0;
-    int neg = 0;
-    for (int j = 0; j < k; ++j) {
-      ls += log(fabs(pval[j]));
-      if (pval[j] < 0.0) ++neg;
+    int odd = 0;
+    if (lane < k) {
+      ls = log(fabs(pval[lane]));
+      int inv = pval[lane] < 0.0 ? 1 : 0;
+      const int pl = piv[lane];
+      for (int q = lane + 1; q < k; ++q) inv += piv[q] < pl ? 1 : 0;
+      odd = inv & 1;
     }
-    unsigned long long seen = 0ull;   // k <= 64
-    int cycles = 0;
-    for (int j = 0; j < k; ++j) {
-      if ((seen >> j) & 1ull) continue;
-      ++cycles;
-      for (int q = j; !((seen >> q) & 1ull); q = piv[q]) seen |= 1ull << q;
+    for (int off = 32; off > 0; off >>= 1) {
+      ls += __shfl_xor(ls, off, 64);
+      odd ^= __shfl_xor(odd, off, 64);
     }
-    const bool positive = (((k - cycles) + neg) % 2) == 0;
-    logdet[P] = ls;
-    if (!positive || !isfinite(ls)) atomicOr(flags, (int)DF_NOT_SPD_NODE);
+    if (lane == 0) {
+      logdet[P] = ls;
+      if (odd || !isfinite(ls)) atomicOr(flags, (int)DF_NOT_SPD_NODE);
+    }
   }
   __syncthreads();
-  // P1 = S_b Sig^{-1} -> A (LU no longer needed)
-  for (int e = tid; e < kk; e += nt) {
-    int i = e % k, j = e / k;
-    double v = 0.0;
-    for (int l = 0; l < k; ++l) v += Sb[i + l * k] * Si[l + j * k];
-    A[e] = v;
+  // P1 = S_b Sig^{-1} -> Si (the row operations are no longer needed)
+  for (int t = wave; t < NT * NT; t += 4) {
+    const int ti = t % NT, tj = t / NT;
+    const hm_v4d acc = node_mm_tile<KP>(Sb, Sg, ti, tj, lane);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Si[(16 * ti + 4 * v + lk) + (16 * tj + li) * LD] = acc[v];
   }
   __syncthreads();
   const int m = 2 * k;
   double* No = Nout + P * nstride;
-  for (int e = tid; e < kk; e += nt) {
-    int i = e % k, j = e / k;
-    double n12 = (i == j) ? 1.0 : 0.0, n22 = 0.0;
-    for (int l = 0; l < k; ++l) {
-      n12 += A[i + l * k] * Sa[l + j * k];
-      n22 -= Si[i + l * k] * Sa[l + j * k];
+  for (int e = tid; e < k * k; e += 256) {
+    const int i = e % k, j = e / k;
+    No[i + (long)j * m] = -Si[i + j * LD];          // N11 = -S_b Sig^{-1}
+    No[(k + i) + (long)j * m] = Sg[i + j * LD];     // N21 = Sig^{-1}
+  }
+  for (int t = wave; t < 2 * NT * NT; t += 4) {
+    const int which = t / (NT * NT), tt = t % (NT * NT);
+    const int ti = tt % NT, tj = tt / NT;
+    // which 0: N12 = I + P1 S_a;  which 1: N22 = -Sig^{-1} S_a
+    const hm_v4d acc = node_mm_tile<KP>(which ? Sg : Si, Sa, ti, tj, lane);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 16 * ti + 4 * v + lk, j = 16 * tj + li;
+      if (i < k && j < k) {
+        if (which) No[(k + i) + (long)(k + j) * m] = -acc[v];
+        else No[i + (long)(k + j) * m] = (i == j ? 1.0 : 0.0) + acc[v];
+      }
     }
-    No[i + (long)j * m] = -A[e];                 // N11 = -S_b Sig^{-1}
-    No[i + (long)(k + j) * m] = n12;             // N12 = I + S_b Sig^{-1} S_a
-    No[(k + i) + (long)j * m] = Si[e];           // N21 = Sig^{-1}
-    No[(k + i) + (long)(k + j) * m] = n22;       // N22 = -Sig^{-1} S_a
   }
 }
 
@@ -251,8 +357,18 @@ hm_status chol_inv_nodes(Model* m, const double* G, long gstride, double* R, dou
     set_error("panel width exceeds the per-node LDS limit (64)");
     return HM_E_INVAL;
   }
-  hipLaunchKernelGGL(k_chol_inv, dim3(cnt), dim3(256), 0, m->stream, G, gstride, R, Rinv, rstride, k, d_kblk,
-                     heap0, hstep, shift, mrows, m->d_flags);
+  if (k <= 16)
+    hipLaunchKernelGGL(k_chol_inv<16>, dim3(cnt), dim3(128), 0, m->stream, G, gstride, R, Rinv, rstride, k, d_kblk,
+                       heap0, hstep, shift, mrows, m->d_flags);
+  else if (k <= 32)
+    hipLaunchKernelGGL(k_chol_inv<32>, dim3(cnt), dim3(128), 0, m->stream, G, gstride, R, Rinv, rstride, k, d_kblk,
+                       heap0, hstep, shift, mrows, m->d_flags);
+  else if (k <= 48)
+    hipLaunchKernelGGL(k_chol_inv<48>, dim3(cnt), dim3(128), 0, m->stream, G, gstride, R, Rinv, rstride, k, d_kblk,
+                       heap0, hstep, shift, mrows, m->d_flags);
+  else
+    hipLaunchKernelGGL(k_chol_inv<64>, dim3(cnt), dim3(128), 0, m->stream, G, gstride, R, Rinv, rstride, k, d_kblk,
+                       heap0, hstep, shift, mrows, m->d_flags);
   HM_LAUNCH_CHECK();
   return HM_OK;
 }
@@ -269,8 +385,18 @@ hm_status node_lu(Model* m, const double* S, long sstride, double* Nout, long ns
     set_error("panel width exceeds the per-node LDS limit (64)");
     return HM_E_INVAL;
   }
-  hipLaunchKernelGGL(k_node_lu, dim3(cnt), dim3(256), 0, m->stream, S, sstride, Nout, nstride, logdet, k, heap0,
-                     m->d_flags);
+  if (k <= 16)
+    hipLaunchKernelGGL(k_node_lu<16>, dim3(cnt), dim3(256), 0, m->stream, S, sstride, Nout, nstride, logdet, k,
+                       heap0, m->d_flags);
+  else if (k <= 32)
+    hipLaunchKernelGGL(k_node_lu<32>, dim3(cnt), dim3(256), 0, m->stream, S, sstride, Nout, nstride, logdet, k,
+                       heap0, m->d_flags);
+  else if (k <= 48)
+    hipLaunchKernelGGL(k_node_lu<48>, dim3(cnt), dim3(256), 0, m->stream, S, sstride, Nout, nstride, logdet, k,
+                       heap0, m->d_flags);
+  else
+    hipLaunchKernelGGL(k_node_lu<64>, dim3(cnt), dim3(256), 0, m->stream, S, sstride, Nout, nstride, logdet, k,
+                       heap0, m->d_flags);
   HM_LAUNCH_CHECK();
   return HM_OK;
 }
