@@ -18,23 +18,99 @@
 #include "hm_build.h"
 #include "hm_factor.h"
 #include "hm_internal.h"
+#include "gemm_core.h"
 
 namespace hm {
 
-// U_P = N_P [T_a; T_b] for all internal nodes P at depth d (T_c: bw x w, per node
-// stride ts; N_P: 2bw x 2bw; U_P: 2bw x w, per node stride us, ld 2bw).
+// U_P = N_P [T_a; T_b] for every internal node P at depths d0..d1 (T_c: bw x w(d), per
+// node stride ts; N_P: 2bw x 2bw; U_P: 2bw x w(d), per node stride us, ld 2bw), with
+// w(d) = wa + wb d.  One launch: a 1D grid over the 64 x 64 tiles of every node of
+// every depth, each tile one K = 2bw product whose B rows come from T_a (k < bw) and
+// T_b (k >= bw).
+struct NodeApplyArgs {
+  const double* Nn; const double* T; long ts; double* U; long us;
+  int bw, wa, wb, d0, d1;
+  int tstart[32];   // first tile of depth d0 + i (tstart[d1 - d0 + 1] = total)
+};
+struct NaA {   // N_P, column-major 2bw x 2bw
+  const double* p; int ld, m0, M;
+  static constexpr bool kfast = false;
+  static constexpr int NR = 1;
+  __device__ bool load(int i, int k, double (&v)[1]) const {
+    const int r0 = m0 + i;
+    const bool ok = r0 < M;
+    v[0] = p[(ok ? r0 : 0) + (long)k * ld];
+    return ok;
+  }
+  __device__ double fin(const double (&v)[1]) const { return v[0]; }
+};
+struct NaB {   // [T_a; T_b], each bw x Nc column-major (ld bw)
+  const double* pa; const double* pb; int bw, n0, Nc;
+  static constexpr bool kfast = true;
+  static constexpr int NR = 1;
+  __device__ bool load(int k, int j, double (&v)[1]) const {
+    const int c0 = n0 + j;
+    const bool ok = c0 < Nc;
+    const int c = ok ? c0 : 0;
+    v[0] = (k < bw) ? pa[k + (long)c * bw] : pb[(k - bw) + (long)c * bw];
+    return ok;
+  }
+  __device__ double fin(const double (&v)[1]) const { return v[0]; }
+};
+struct NaC {   // plain store with bounds
+  double* p; int ld, m0, n0, M, Nc;
+  __device__ void operator()(int i, int j, double v) const {
+    const int r = m0 + i, c = n0 + j;
+    if (r < M && c < Nc) p[r + (long)c * ld] = v;
+  }
+};
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_node_apply(NodeApplyArgs a) {
+  __shared__ double smem[GSMEM];
+  const int t = tile_block().x;
+  int i = 0;
+  while (i < a.d1 - a.d0 && t >= a.tstart[i + 1]) ++i;
+  const int d = a.d0 + i;
+  const int w = a.wa + a.wb * d, m2 = 2 * a.bw;
+  const int mt = (m2 + GBM - 1) / GBM, nt = (w + GBN - 1) / GBN;
+  const int r = t - a.tstart[i];
+  const int node = r / (mt * nt), rt = r % (mt * nt);
+  const int P = (1 << d) - 1 + node;
+  const int m0 = (rt % mt) * GBM, n0 = (rt / mt) * GBN;
+  NaA la{a.Nn + P * 4L * a.bw * a.bw, m2, m0, m2};
+  NaB lb{a.T + (2L * P + 1) * a.ts, a.T + (2L * P + 2) * a.ts, a.bw, n0, w};
+  TileAcc acc;
+  tile_zero(acc);
+  tile_gemm(la, lb, 0, m2, acc, smem);
+  tile_store(NaC{a.U + P * a.us, m2, m0, n0, m2, w}, acc);
+}
+
+hm_status node_apply_range(Model* m, const double* Nn, const double* T, long ts, double* U, long us, int bw, int wa,
+                           int wb, int d0, int d1) {
+  if (d1 < d0) return HM_OK;
+  if (d1 - d0 + 1 >= 32) {
+    set_error("node_apply: too many depths");
+    return HM_E_INVAL;
+  }
+  NodeApplyArgs a{Nn, T, ts, U, us, bw, wa, wb, d0, d1, {}};
+  const int mt = ceil_div(2 * bw, GBM);
+  long tot = 0;
+  for (int d = d0; d <= d1; ++d) {
+    a.tstart[d - d0] = (int)tot;
+    const int w = wa + wb * d;
+    if (w > 0) tot += (long)(1 << d) * mt * ceil_div(w, GBN);
+  }
+  a.tstart[d1 - d0 + 1] = (int)tot;
+  if (tot <= 0) return HM_OK;
+  hipLaunchKernelGGL(k_node_apply, dim3((unsigned)tot), dim3(GCfg::NT), 0, m->stream, a);
+  HM_LAUNCH_CHECK();
+  return HM_OK;
+}
+
+// U_P = N_P [T_a; T_b] for all internal nodes P at depth d (w columns)
 hm_status node_apply_N(Model* m, const double* Nn, const double* T, long ts, double* U, long us, int bw, int w,
                        int d) {
   if (w <= 0) return HM_OK;
-  const int P0 = (1 << d) - 1, cnt = 1 << d;
-  const long ns = 4L * bw * bw;
-  const int m2 = 2 * bw;
-  // U = N[:, 0:bw] T_a + N[:, bw:2bw] T_b
-  HM_CHECK(gemm(m->stream, false, false, m2, w, bw, 1.0, Nn + P0 * ns, m2, ns, T + (2L * P0 + 1) * ts, bw, 2 * ts,
-                0.0, U + P0 * us, m2, us, cnt));
-  HM_CHECK(gemm(m->stream, false, false, m2, w, bw, 1.0, Nn + P0 * ns + (long)bw * m2, m2, ns,
-                T + (2L * P0 + 2) * ts, bw, 2 * ts, 1.0, U + P0 * us, m2, us, cnt));
-  return HM_OK;
+  return node_apply_range(m, Nn, T, ts, U, us, bw, w, 0, d, d);
 }
 
 hm_status factorize(FactorCtx& f) {
@@ -47,13 +123,21 @@ hm_status factorize(FactorCtx& f) {
   const long ts = (long)kc * (levels - 1) * kc;  // T_c: kc x (d kc), d <= levels-1
   const long us = 2L * kc * (levels - 1) * kc;
   for (int d = levels - 1; d >= 0; --d) {
+    // S_c = F_c^T G_c (node blocks) and, for the Woodbury update of the ancestors'
+    // panels, T_c = F_c^T G_c[prefix]: independent products of one launch (S in FP64:
+    // it feeds the node factor)
     ReduceJob rs{f.F, n, cs_block(kc), f.G, n, cs_block(kc), d + 1, d + 1, f.Sn, s2, sel_all()};
-    HM_CHECK(tree_reduce(m, rs));
+    ReduceJob rt{f.F, n, cs_block(kc), f.G, n, cs_prefix(kc), d + 1, d + 1, f.nT, ts, sel_all()};
+    if (d >= 1 && m->mixed == 0) {   // under the mixed policies T_c is an FP32 product
+      const ReduceJob rj[2] = {rs, rt};
+      HM_CHECK(tree_reduce_multi(m, rj, 2));
+    } else {
+      HM_CHECK(tree_reduce(m, rs));
+    }
     HM_CHECK(node_lu(m, f.Sn, s2, f.Nn, 4 * s2, f.logdet_node, kc, (1 << d) - 1, 1 << d));
     if (d >= 1) {
       PrecScope prec(m);   // Woodbury panel updates: FP32 under the mixed policy
-      ReduceJob rt{f.F, n, cs_block(kc), f.G, n, cs_prefix(kc), d + 1, d + 1, f.nT, ts, sel_all()};
-      HM_CHECK(tree_reduce(m, rt));
+      if (m->mixed != 0) HM_CHECK(tree_reduce(m, rt));
       HM_CHECK(node_apply_N(m, f.Nn, f.nT, ts, f.nU, us, kc, d * kc, d));
       ExpandJob e{f.G, n, cs_block(kc), f.G, n, cs_prefix(kc), f.nU, us, 2 * kc, 2, kc, d + 1, d + 1, -1.0, 1.0,
                   sel_all()};
@@ -99,14 +183,15 @@ hm_status hmatvec(FactorCtx& f, const double* Dl, const double* Fp, const double
   HM_CHECK(leaf_gemm(m, Dl, x, n, y, n, w, alpha, beta, 0, m->nleaves));
   const long ts = (long)kc * w;
   ReduceJob r{Fp, n, cs_block(kc), x, n, cs_fixed(0, w), 1, levels, f.nT, ts, sel_all()};
-  HM_CHECK(tree_reduce(m, r));
   if (!dFp) {
+    HM_CHECK(tree_reduce(m, r));
     ExpandJob e{Fp, n, cs_block(kc), y, n, cs_fixed(0, w), f.nT, ts, kc, 1, 0, 1, levels, alpha, 1.0, sel_all()};
     HM_CHECK(tree_expand(m, e));
     return HM_OK;
   }
   ReduceJob rd{dFp, n, cs_block(kc), x, n, cs_fixed(0, w), 1, levels, f.nU, ts, sel_all()};
-  HM_CHECK(tree_reduce(m, rd));
+  const ReduceJob rj[2] = {r, rd};   // independent: one launch
+  HM_CHECK(tree_reduce_multi(m, rj, 2));
   ExpandJob e{dFp, n, cs_block(kc), y, n, cs_fixed(0, w), f.nT, ts, kc, 1, 0, 1, levels, alpha, 1.0, sel_all()};
   e.A2 = Fp;
   e.T2 = f.nU;

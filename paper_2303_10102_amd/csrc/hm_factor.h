@@ -47,5 +47,8 @@ hm_status hmatvec(FactorCtx& f, const double* Dl, const double* Fp, const double
                   double* y, double alpha, double beta);
 hm_status node_apply_N(Model* m, const double* Nn, const double* T, long ts, double* U, long us, int bw, int w,
                        int d);
+// the same for every depth d0..d1 in one launch, with w(d) = wa + wb d columns at depth d
+hm_status node_apply_range(Model* m, const double* Nn, const double* T, long ts, double* U, long us, int bw, int wa,
+                           int wb, int d0, int d1);
 
 }  // namespace hm

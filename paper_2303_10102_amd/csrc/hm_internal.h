@@ -300,8 +300,8 @@ struct ReduceJob {
 };
 hm_status tree_reduce(Model* m, const ReduceJob& j);
 // Up to three independent jobs with the same row operand layout (A's lda and columns),
-// depths, selection and output stride in one launch of the products and one of the
-// tree sums; other job lists run one job after another.  Same results as separate calls.
+// depths and selection in one launch of the products and one of the tree sums; other
+// job lists run one job after another.  Same results as separate calls.
 hm_status tree_reduce_multi(Model* m, const ReduceJob* js, int nj);
 
 // For every row i of a selected leaf L:

@@ -175,6 +175,7 @@ struct RedArgs {
   const double* jA[2] = {nullptr, nullptr};
   const double* jX[2] = {nullptr, nullptr};
   double* jout[2] = {nullptr, nullptr};
+  long jost[2] = {0, 0};
   ColSpec jxc[2] = {};
   double* jpart[2] = {nullptr, nullptr};
   long jpst[2] = {0, 0};
@@ -187,6 +188,7 @@ __device__ __forceinline__ RedArgs red_job(const RedArgs& a0, int q) {
     a.A = s ? a0.jA[1] : a0.jA[0];
     a.X = s ? a0.jX[1] : a0.jX[0];
     a.out = s ? a0.jout[1] : a0.jout[0];
+    a.out_stride = s ? a0.jost[1] : a0.jost[0];
     a.xc = s ? a0.jxc[1] : a0.jxc[0];
     a.partial = s ? a0.jpart[1] : a0.jpart[0];
     a.pstride = s ? a0.jpst[1] : a0.jpst[0];
@@ -484,8 +486,8 @@ hm_status ensure_reduce_ws(Model* m, size_t doubles) {
   return HM_OK;
 }
 
-// Jobs that can share one launch: same row operand layout, depths, selection and
-// output stride, products only (no identity operand), at most three.
+// Jobs that can share one launch: same row operand layout, depths and selection,
+// products only (no identity operand), at most three.
 static bool reduce_jobs_compatible(Model* m, const ReduceJob* js, int nj) {
   if (nj < 2 || nj > 3) return false;
   auto is_ident = [&](const double* p) { return p == m->d_ident; };
@@ -493,8 +495,7 @@ static bool reduce_jobs_compatible(Model* m, const ReduceJob* js, int nj) {
     const ReduceJob& a = js[q];
     const ReduceJob& b = js[0];
     if (is_ident(a.A) || is_ident(a.X)) return false;
-    if (a.lda != b.lda || a.ldx != b.ldx || a.d0 != b.d0 || a.d1 != b.d1 || a.out_stride != b.out_stride ||
-        a.sel.mode != b.sel.mode || a.sel.depth != b.sel.depth || a.ac.base != b.ac.base ||
+    if (a.lda != b.lda || a.ldx != b.ldx || a.d0 != b.d0 || a.d1 != b.d1 || a.sel.mode != b.sel.mode || a.sel.depth != b.sel.depth || a.ac.base != b.ac.base ||
         a.ac.stride != b.ac.stride || a.ac.w0 != b.ac.w0 || a.ac.grow != b.ac.grow ||
         a.only_selected != b.only_selected)
       return false;
@@ -546,6 +547,7 @@ hm_status tree_reduce_multi(Model* m, const ReduceJob* js, int nj) {
     a.jA[q - 1] = js[q].A;
     a.jX[q - 1] = js[q].X;
     a.jout[q - 1] = js[q].out;
+    a.jost[q - 1] = js[q].out_stride;
     a.jxc[q - 1] = js[q].xc;
     a.jpart[q - 1] = m->d_red + offq[q];
     a.jpst[q - 1] = (long)wa * wxq[q];

@@ -576,7 +576,8 @@ hm_status tangent_sweep(FactorCtx& f, ParamBufs& pb) {
     const long us = 2L * kc * (levels - 1) * kc;
     ReduceJob r{f.G, n, cs_block(kc), R, n, cs_prefix(kc), 2, levels, f.nT, ts, sel_all()};
     HM_CHECK(tree_reduce(m, r));
-    for (int dP = 1; dP <= levels - 1; ++dP) HM_CHECK(node_apply_N(m, f.Nn, f.nT, ts, f.nU, us, kc, dP * kc, dP));
+    // U_P = N_P [T_a; T_b] for every depth 1..levels-1 at once (widths dP kc)
+    HM_CHECK(node_apply_range(m, f.Nn, f.nT, ts, f.nU, us, kc, 0, kc, 1, levels - 1));
     ExpandJob e{f.G, n, cs_block(kc), pb.dG, n, cs_prefix(kc), f.nU, us, 2 * kc, 2, kc, 2, levels, -1.0, 1.0,
                 sel_all()};
     HM_CHECK(tree_expand(m, e));
