@@ -539,10 +539,10 @@ hm_status param_prepare(FactorCtx& f, ParamBufs& pb, const double* theta, const 
   HM_CHECK(gemm(m->stream, false, false, nl, nl, nl, 1.0, f.Dinv, nl, ls, pb.dD, nl, ls, 0.0, pb.Y, nl, ls,
                 m->nleaves));
   // E_c = dF_c^T G_c,  Psi_c = G_c^T Xi_c  (all non-root nodes)
-  ReduceJob re{pb.dF, n, cs_block(kc), f.G, n, cs_block(kc), 1, levels, pb.E, s2, sel_all()};
-  HM_CHECK(tree_reduce(m, re));
-  ReduceJob rp{f.G, n, cs_block(kc), pb.Xi, n, cs_block(kc), 1, levels, pb.Psi, s2, sel_all()};
-  HM_CHECK(tree_reduce(m, rp));
+  const ReduceJob rj[2] = {
+      ReduceJob{pb.dF, n, cs_block(kc), f.G, n, cs_block(kc), 1, levels, pb.E, s2, sel_all()},
+      ReduceJob{f.G, n, cs_block(kc), pb.Xi, n, cs_block(kc), 1, levels, pb.Psi, s2, sel_all()}};
+  HM_CHECK(tree_reduce_multi(m, rj, 2));   // independent: one launch
   return HM_OK;
 }
 
@@ -595,10 +595,10 @@ hm_status panel_products(FactorCtx& f, ParamBufs& pb) {
   PrecScope prec(m, true);   // trace panels: FP32 (BF16 under policy 2) under the mixed policies
   const int n = m->n, kc = f.kc, levels = m->levels;
   const long s2 = (long)kc * kc;
-  ExpandJob e1{pb.dG, n, cs_block(kc), pb.Gh, n, cs_block(kc), f.Ncc, s2, kc, 0, 0, 1, levels, 1.0, 0.0, sel_all()};
-  HM_CHECK(tree_expand(m, e1));
-  ExpandJob e2{pb.dG, n, cs_block(kc), pb.Hh, n, cs_block(kc), f.Nx, s2, kc, 0, 0, 1, levels, 1.0, 0.0, sel_all()};
-  HM_CHECK(tree_expand(m, e2));
+  const ExpandJob ej[2] = {
+      ExpandJob{pb.dG, n, cs_block(kc), pb.Gh, n, cs_block(kc), f.Ncc, s2, kc, 0, 0, 1, levels, 1.0, 0.0, sel_all()},
+      ExpandJob{pb.dG, n, cs_block(kc), pb.Hh, n, cs_block(kc), f.Nx, s2, kc, 0, 0, 1, levels, 1.0, 0.0, sel_all()}};
+  HM_CHECK(tree_expand_multi(m, ej, 2));   // independent: one launch
   return HM_OK;
 }
 
