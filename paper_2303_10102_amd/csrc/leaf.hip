@@ -103,6 +103,69 @@ __global__ void __launch_bounds__(256) k_chol_panel(double* W, int nl, int jb, d
   }
 }
 
+// The same step for leaves of at most 256 rows, with the panel in registers: thread i
+// holds row jb + i of the block column.  Step t broadcasts column t of the diagonal
+// block (rows < nb) through LDS, one barrier per step; every row then scales its
+// entry t by the pivot and updates its entries u in (t, nb) with one multiply-add each.
+template <int CB>
+__global__ void __launch_bounds__(256) k_chol_panel_r(double* W, int nl, int jb, double* logdet, int* flags) {
+  __shared__ double colt[2][CB];
+  __shared__ double red[4];
+  const int L = blockIdx.x;
+  double* A = W + (long)L * nl * nl;
+  const int i = threadIdx.x;
+  const int nb = min(CB, nl - jb), rows = nl - jb;
+  const bool act = i < rows;
+  double R[CB];
+#pragma unroll
+  for (int t = 0; t < CB; ++t) R[t] = (act && t < nb) ? A[(jb + i) + (long)(jb + t) * nl] : 0.0;
+  double myl = 0.0;   // 2 log of this row's pivot (rows < nb)
+  bool bad = false;
+#pragma unroll
+  for (int t = 0; t < CB; ++t) {
+    if (t < nb) {
+      double* cb = colt[t & 1];
+      if (i < nb) cb[i] = R[t];
+      __syncthreads();
+      double d = cb[t];
+      if (!(d > 0.0)) {
+        bad = true;
+        d = 1.0;
+      }
+      const double piv = sqrt(d), rp = 1.0 / piv;
+      if (i == t) {
+        R[t] = piv;
+        myl = 2.0 * log(piv);
+      } else if (i > t) {
+        R[t] = R[t] / piv;
+      }
+      const double lt = R[t];
+      // branch-free: entries u >= nb of the broadcast are stale and never selected
+#pragma unroll
+      for (int u = t + 1; u < CB; ++u) {
+        const double v = R[u] - lt * (cb[u] * rp);
+        R[u] = (u < nb && i >= u) ? v : R[u];
+      }
+#pragma unroll
+      for (int u = t + 1; u < CB; ++u) asm volatile("" : "+v"(R[u]));
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int t = 0; t < CB; ++t)
+      if (t < nb) A[(jb + i) + (long)(jb + t) * nl] = (i >= t) ? R[t] : 0.0;
+  }
+  // log det contribution: the pivots' logs, summed over the block
+  double ls = (i < nb) ? myl : 0.0;
+  for (int off = 32; off > 0; off >>= 1) ls += __shfl_xor(ls, off, 64);
+  if ((i & 63) == 0) red[i >> 6] = ls;
+  __syncthreads();
+  if (i == 0) {
+    logdet[L] = (jb == 0 ? 0.0 : logdet[L]) + ((red[0] + red[1]) + (red[2] + red[3]));
+    if (bad) atomicOr(flags, (int)DF_NOT_SPD_LEAF);
+  }
+}
+
 // Inverse of each CNB x CNB diagonal block of the lower factor, written into the
 // same position of Linv.  One workgroup per (block, leaf); thread c < nb solves
 // column c by forward substitution with the block in LDS.
@@ -156,6 +219,9 @@ hm_status leaf_factor(Model* m, const double* D, double* Dinv, double* logdet_le
     if (wide)
       hipLaunchKernelGGL((k_chol_panel<CNB_WIDE, NLMAX_WIDE>), dim3(nlv), dim3(256), 0, m->stream, work, nl, jb,
                          logdet_leaf, m->d_flags);
+    else if (nl <= 256)
+      hipLaunchKernelGGL((k_chol_panel_r<CNB>), dim3(nlv), dim3(256), 0, m->stream, work, nl, jb, logdet_leaf,
+                         m->d_flags);
     else
       hipLaunchKernelGGL((k_chol_panel<CNB, NLMAX>), dim3(nlv), dim3(256), 0, m->stream, work, nl, jb,
                          logdet_leaf, m->d_flags);
