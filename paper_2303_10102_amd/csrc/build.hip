@@ -208,6 +208,10 @@ static hm_status cholqr3(Model* m, const double* Y, int w, int l, const int* kbl
 static hm_status qr_tangents(Model* m, const double* Q, double* const* dY, int nr, int w, int l,
                              double* const* out, const NodeBufs& nb) {
   if (nr <= 0) return HM_OK;
+  if (nr > 2 || nb.mfold == nb.w) {   // the fold reads W^T while it writes M
+    set_error("qr_tangents: at most two tangents, with separate W and M node buffers");
+    return HM_E_INVAL;
+  }
   const LeafSel left{1, l};
   const long s2 = (long)w * w;
   const int heap0 = (1 << l) - 1;
