@@ -197,7 +197,8 @@ __device__ __forceinline__ RedArgs red_job(const RedArgs& a0, int q) {
 }
 
 // Reduce with both tall operands fed straight into the matrix cores (P = 0 FP64,
-// P = 1 FP32 operands and accumulation for the mixed-precision policy).  For
+// P = 1 FP32 operands and accumulation for the mixed-precision policy, P = 2 BF16
+// operands with FP32 accumulation for its trace panels).  For
 // out = A^T X the MFMA's k index runs over rows; lane l of k-group l/16 takes the
 // four consecutive rows 4 (l/16) .. 4 (l/16) + 3 of a 16-row group, one per
 // MFMA step, so each lane reads 32 contiguous bytes of one column and a 16-lane
@@ -495,9 +496,9 @@ static bool reduce_jobs_compatible(Model* m, const ReduceJob* js, int nj) {
     const ReduceJob& a = js[q];
     const ReduceJob& b = js[0];
     if (is_ident(a.A) || is_ident(a.X)) return false;
-    if (a.lda != b.lda || a.ldx != b.ldx || a.d0 != b.d0 || a.d1 != b.d1 || a.sel.mode != b.sel.mode || a.sel.depth != b.sel.depth || a.ac.base != b.ac.base ||
-        a.ac.stride != b.ac.stride || a.ac.w0 != b.ac.w0 || a.ac.grow != b.ac.grow ||
-        a.only_selected != b.only_selected)
+    if (a.lda != b.lda || a.ldx != b.ldx || a.d0 != b.d0 || a.d1 != b.d1 || a.sel.mode != b.sel.mode ||
+        a.sel.depth != b.sel.depth || a.ac.base != b.ac.base || a.ac.stride != b.ac.stride ||
+        a.ac.w0 != b.ac.w0 || a.ac.grow != b.ac.grow || a.only_selected != b.only_selected)
       return false;
   }
   return true;
@@ -667,7 +668,8 @@ __device__ __forceinline__ ExpArgs exp_job(const ExpArgs& a0, int q) {
 }
 
 // Expand with the tall operand fed straight into the matrix cores (P = 0 FP64,
-// P = 1 FP32 operands and accumulation for the mixed-precision policy).  The
+// P = 1 FP32 operands and accumulation for the mixed-precision policy, P = 2 BF16
+// operands with FP32 accumulation for its trace panels).  The
 // product is formed transposed, D = T^T A^T (16 output columns x 16 rows per
 // MFMA block), so that
 //   * the B operand of v_mfma_f64_16x16x4 (lane l: row l%16, k l/16) is read from
