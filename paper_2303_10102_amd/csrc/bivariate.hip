@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "hm_internal.h"
+#include "gemm_core.h"
 
 namespace hm {
 
@@ -28,13 +29,128 @@ struct BivOp {
   long NN = 0;
   double h = 0.0;
   double* S = nullptr;         // N x N orthonormal sine transform (symmetric)
+  double* Ph = nullptr;        // N even: 2 x (H x H), Ph[par](q, i) = S(2q + par, i), H = N / 2
   double* mu = nullptr;        // NN eigenvalues of -Laplacian (x fastest)
   double* w[3] = {nullptr, nullptr, nullptr};   // NN x 2 cmax work buffers
 };
 
+// Folded transforms (N even, H = N / 2).  The sine transform's columns i and N-1-i
+// differ by the sign (-1)^p of row p: S(p, N-1-i) = (-1)^p S(p, i).  So the rows of
+// parity par of S X need only the H sums X(i) + (-1)^par X(N-1-i), i < H, and each
+// pass is two H x H products instead of one N x N product.
+struct BvHalfA {   // A(q, i) = Ph_par(q, i), q = m0 + row
+  const double* p; int H, m0;
+  static constexpr bool kfast = false;
+  static constexpr int NR = 1;
+  __device__ bool load(int i, int k, double (&v)[1]) const {
+    const int r = m0 + i;
+    const bool ok = r < H;
+    v[0] = p[(ok ? r : 0) + (long)k * H];
+    return ok;
+  }
+  __device__ double fin(const double (&v)[1]) const { return v[0]; }
+};
+struct BvFoldB {   // B(i, c) = X(i, c) + sgn X(N-1-i, c), X: N x R (ld N), c = n0 + col
+  const double* X; int N; long n0, R; double sgn;
+  static constexpr bool kfast = true;
+  static constexpr int NR = 2;
+  __device__ bool load(int k, int j, double (&v)[2]) const {
+    const long c = n0 + j;
+    const bool ok = c < R;
+    const double* xc = X + (ok ? c : 0) * (long)N;
+    v[0] = xc[k];
+    v[1] = xc[N - 1 - k];
+    return ok;
+  }
+  __device__ double fin(const double (&v)[2]) const { return v[0] + sgn * v[1]; }
+};
+struct BvStRows {   // Y(2 (m0 + i) + par, n0 + j), ld N
+  double* Y; int N, H, m0; long n0, R; int par;
+  __device__ void operator()(int i, int j, double v) const {
+    const int r = m0 + i;
+    const long c = n0 + j;
+    if (r < H && c < R) Y[2 * r + par + c * N] = v;
+  }
+};
+// Y = S X along the first axis: X, Y N x R (ld N).  grid.x: 2 ht (parity major), grid.y: R tiles
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_biv_fold_rows(const double* Ph, const double* X, double* Y, int N, long R) {
+  __shared__ double smem[GSMEM];
+  const TileIdx tb = tile_block();
+  const int H = N / 2, ht = (H + GBM - 1) / GBM;
+  const int par = tb.x >= ht ? 1 : 0;
+  const int m0 = (tb.x - par * ht) * GBM;
+  const long n0 = (long)tb.y * GBN;
+  TileAcc acc;
+  tile_zero(acc);
+  tile_gemm(BvHalfA{Ph + (long)par * H * H, H, m0}, BvFoldB{X, N, n0, R, par ? -1.0 : 1.0}, 0, H, acc, smem);
+  tile_store(BvStRows{Y, N, H, m0, n0, R, par}, acc);
+}
+struct BvFoldA {   // A(p, y) = T(p, y) + sgn T(p, N-1-y), T: N x N (ld N)
+  const double* T; int N, m0; double sgn;
+  static constexpr bool kfast = false;
+  static constexpr int NR = 2;
+  __device__ bool load(int i, int k, double (&v)[2]) const {
+    const int r = m0 + i;
+    const bool ok = r < N;
+    const int rr = ok ? r : 0;
+    v[0] = T[rr + (long)k * N];
+    v[1] = T[rr + (long)(N - 1 - k) * N];
+    return ok;
+  }
+  __device__ double fin(const double (&v)[2]) const { return v[0] + sgn * v[1]; }
+};
+struct BvHalfB {   // B(y, q) = S(y, 2q + par) = Ph_par(q, y), q = n0 + col
+  const double* p; int H, n0;
+  static constexpr bool kfast = false;
+  static constexpr int NR = 1;
+  __device__ bool load(int k, int j, double (&v)[1]) const {
+    const int c = n0 + j;
+    const bool ok = c < H;
+    v[0] = p[(ok ? c : 0) + (long)k * H];
+    return ok;
+  }
+  __device__ double fin(const double (&v)[1]) const { return v[0]; }
+};
+struct BvStCols {   // Y(m0 + i, 2 (n0 + j) + par), ld N
+  double* Y; int N, H, m0, n0, par;
+  __device__ void operator()(int i, int j, double v) const {
+    const int r = m0 + i, c = n0 + j;
+    if (r < N && c < H) Y[r + (long)(2 * c + par) * N] = v;
+  }
+};
+// Y_z = T_z S along the second axis for every slice z (N x N, stride NN).
+// grid.x: row tiles, grid.y: 2 ht (parity major), grid.z: slices
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_biv_fold_cols(const double* Ph, const double* T, double* Y, int N, long NN) {
+  __shared__ double smem[GSMEM];
+  const TileIdx tb = tile_block();
+  const int H = N / 2, ht = (H + GBN - 1) / GBN;
+  const int par = tb.y >= ht ? 1 : 0;
+  const int m0 = tb.x * GBM, n0 = (tb.y - par * ht) * GBN;
+  TileAcc acc;
+  tile_zero(acc);
+  tile_gemm(BvFoldA{T + tb.z * NN, N, m0, par ? -1.0 : 1.0}, BvHalfB{Ph + (long)par * H * H, H, n0}, 0, H, acc,
+            smem);
+  tile_store(BvStCols{Y + tb.z * NN, N, H, m0, n0, par}, acc);
+}
+
 // Y (NN x c', ld NN) = (S (x) S) X in 2D, S X in 1D; tmp: NN x c'
 static hm_status biv_transform(const BivOp* b, hipStream_t st, const double* X, double* Y, double* tmp, int cp) {
   const int N = b->N;
+  if (b->Ph) {
+    const int H = N / 2;
+    const long R = (long)cp * (b->dim == 1 ? 1 : N);   // columns of the first-axis product
+    double* first = b->dim == 1 ? Y : tmp;
+    hipLaunchKernelGGL(k_biv_fold_rows, dim3(2 * ceil_div(H, GBM), ceil_div(R, GBN)), dim3(GCfg::NT), 0, st, b->Ph,
+                       X, first, N, R);
+    HM_LAUNCH_CHECK();
+    if (b->dim == 1) return HM_OK;
+    hipLaunchKernelGGL(k_biv_fold_cols, dim3(ceil_div(N, GBM), 2 * ceil_div(H, GBN), cp), dim3(GCfg::NT), 0, st,
+                       b->Ph, tmp, Y, N, b->NN);
+    HM_LAUNCH_CHECK();
+    return HM_OK;
+  }
   if (b->dim == 1) return gemm(st, false, false, N, cp, N, 1.0, b->S, N, 0, X, N, 0, 0.0, Y, N, 0, 1);
   HM_CHECK(gemm(st, false, false, N, N * cp, N, 1.0, b->S, N, 0, X, N, 0, 0.0, tmp, N, 0, 1));
   return gemm(st, false, false, N, N, N, 1.0, tmp, N, b->NN, b->S, N, 0, 0.0, Y, N, b->NN, cp);
@@ -94,7 +210,7 @@ static int biv_apply(void* uctx, int which, const double* theta, const double* X
 static void biv_release(Model* m) {
   BivOp* b = (BivOp*)m->op_ctx;
   if (!b) return;
-  double* bufs[] = {b->S, b->mu, b->w[0], b->w[1], b->w[2]};
+  double* bufs[] = {b->S, b->Ph, b->mu, b->w[0], b->w[1], b->w[2]};
   for (double* p : bufs) dev_free(m->ctx, p);
   delete b;
   m->op_ctx = nullptr;
@@ -145,6 +261,8 @@ hm_status model_create_bivariate(Ctx* cx, int dim, int N, double h, int leaf, hm
     ok = ok && *p;
   };
   A(&b->S, (size_t)N * N);
+  const int H = N / 2;
+  if (N % 2 == 0) A(&b->Ph, (size_t)2 * H * H);
   A(&b->mu, (size_t)NN);
   for (int q = 0; q < 3; ++q) A(&b->w[q], (size_t)NN * 2 * m->cmax);
   if (!ok) {
@@ -152,7 +270,12 @@ hm_status model_create_bivariate(Ctx* cx, int dim, int N, double h, int leaf, hm
     set_error("device allocation failed in the bivariate model");
     return HM_E_NOMEM;
   }
-  if (hipMemcpy(b->S, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+  std::vector<double> Ph(b->Ph ? (size_t)2 * H * H : 0);
+  for (int par = 0; par < 2 && b->Ph; ++par)
+    for (int q = 0; q < H; ++q)
+      for (int i = 0; i < H; ++i) Ph[(size_t)par * H * H + q + (size_t)i * H] = S[(size_t)(2 * q + par) + (size_t)i * N];
+  if ((b->Ph && hipMemcpy(b->Ph, Ph.data(), Ph.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) ||
+      hipMemcpy(b->S, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->mu, mu.data(), mu.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
     hm_model_destroy(mm);
     set_error("bivariate model: copy of the tables failed");
