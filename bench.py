@@ -82,10 +82,20 @@ def cpu_baseline(sample_key="2d_n4096", full_n=65536):
     dt = time.perf_counter() - t0
     scale = (full_n / w.n) ** 3
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": 1.0 / (dt * scale),
         "unit": "iters/s",
         "cores": threads,
+        "cpu": cpu,
         "kind": "oracle",
         "sample": f"one oracle iteration (dense assembly, peeling replay, dense L/grad/FIM) on the "
                   f"{w.N}x{w.N} grid (n={w.n}) took {dt:.2f} s; extrapolated to n={full_n} by n^3 "
