@@ -335,7 +335,8 @@ static hm_status build_enqueue(HState* h, const double* theta_full, bool deriv) 
   phase_begin(h, PH_BUILD);
   for (int l = 1; l <= m->levels; ++l) {
     const double* XR = h->s->d_XR + (size_t)(l - 1) * kc * n;
-    HM_CHECK(level_step(m, h->theta, h->ps, l, XR, kc, h->s->d_k, nr, h->realidx, h->lb, h->nb));
+    HM_CHECK(level_step(m, h->theta, h->ps, l, XR, kc, h->s->d_k, nr, h->realidx, h->lb, h->nb,
+                        h->s->kblk.data()));
   }
   HM_CHECK(leaf_pass(m, h->theta, h->ps, nr, h->realidx, h->lb, h->nb, h->D, deriv ? h->dDr : nullptr));
   phase_end(h, PH_BUILD);

@@ -241,7 +241,8 @@ static hm_status qr_tangents(Model* m, const double* Q, double* const* dY, int n
 // One level of the construction.  XR: n x w test matrix (right-children rows).
 // Writes panel block l of ps (and of its tangents when nr > 0).
 hm_status level_step(Model* m, const double* theta, const PanelSet& ps, int l, const double* XR, int w,
-                     const int* kblk, int nr, const int* realidx, const LevelBufs& b, const NodeBufs& nb) {
+                     const int* kblk, int nr, const int* realidx, const LevelBufs& b, const NodeBufs& nb,
+                     const int* kblk_host) {
   const int n = m->n;
   const LeafSel left{1, l}, right{2, l};
   double* dY[2] = {b.dY[0], b.dY[1]};
@@ -264,7 +265,12 @@ hm_status level_step(Model* m, const double* theta, const PanelSet& ps, int l, c
     ycat = ycat && dY[j] == b.Y + (long)(j + 1) * n * w;
     xcat = xcat && b.XdS[j] == b.XS + (long)(j + 1) * n * w;
   }
-  if (ycat) {
+  // the mask zeroes columns past each block's kept rank; with the ranks known on the host
+  // and every block of this level at full width it has nothing to do
+  bool full = kblk_host != nullptr;
+  for (int P = (1 << (l - 1)) - 1; full && P < (1 << l) - 1; ++P) full = kblk_host[P] >= w;
+  if (full) {
+  } else if (ycat) {
     HM_CHECK(mask_cols(m, b.Y, (1 + nr) * w, w, l, kblk, 1));
   } else {
     HM_CHECK(mask_cols(m, b.Y, w, w, l, kblk, 1));

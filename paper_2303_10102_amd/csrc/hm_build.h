@@ -39,7 +39,8 @@ hm_status make_identity_stack(Model* m);
 hm_status subtract_coarser(Model* m, const PanelSet& ps, int l, const double* X, int w, LeafSel xsel,
                            LeafSel ysel, double* Y, double* const* dY, int nr, const NodeBufs& nb, int wt = -1);
 hm_status level_step(Model* m, const double* theta, const PanelSet& ps, int l, const double* XR, int w,
-                     const int* kblk, int nr, const int* realidx, const LevelBufs& b, const NodeBufs& nb);
+                     const int* kblk, int nr, const int* realidx, const LevelBufs& b, const NodeBufs& nb,
+                     const int* kblk_host = nullptr);
 hm_status leaf_pass(Model* m, const double* theta, const PanelSet& ps, int nr, const int* realidx,
                     const LevelBufs& b, const NodeBufs& nb, double* D, double* const* dD);
 hm_status sketch_build(Sketch* s, const double* omega, const double* theta0);
