@@ -167,6 +167,10 @@ struct RedArgs {
   double* partial; long pstride;  // per (leaf, depth) stride = wa * max wx
   int sel_mode, sel_depth;
   int only_sel = 0;   // the tree sums skip nodes without selected leaves
+  // partials per leaf group: at depth d one partial per min(grp, leaves of a node)
+  // consecutive leaves, stored at the group's first leaf (grp 1: per leaf; every
+  // selection) -- the stacked-identity path writes groups, the product path leaves
+  int grp = 1;
   // Up to two further independent jobs in the same launch (grid.z = nj x the products'
   // (leaf, depth) count, job fastest so that every XCD's share of the tiles mixes the
   // jobs; grid.z = jobs of the tree sums): each has its own operands, output, X columns
@@ -398,29 +402,49 @@ __global__ void __launch_bounds__(256) k_reduce_tree(RedArgs a0, int dlast) {
   const int wa = a.ac.w0, wx = a.xc.w(d);
   const int ne = wa * wx;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int e = blockIdx.x * 64 + lane;
-  if (blockIdx.x * 64 >= ne) return;
   const int span = 1 << (a.levels - d);
   const int L0 = idx * span;
+  const int G = a.grp < span ? a.grp : span;   // partials at every G-th leaf of the node
+  const int nk = span / G;
   const long stride = (long)ndep * a.pstride;
+  if (a.grp > 1) {
+    // grouped partials (at most nleaves / grp per node): 256 elements per block, each
+    // thread sums its element over the node's groups alone
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= ne) return;
+    const double* base = a.partial + (long)(d - a.d0) * a.pstride + e;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int k = 0;
+    for (; k + 3 < nk; k += 4) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] += base[(long)(L0 + (k + q) * G) * stride];
+    }
+    for (; k < nk; ++k) acc[0] += base[(long)(L0 + k * G) * stride];
+    const int heap = (1 << d) - 1 + idx;
+    a.out[heap * a.out_stride + e] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    return;
+  }
+  const int e = blockIdx.x * 64 + lane;
+  if (blockIdx.x * 64 >= ne) return;
   const double* base = a.partial + (long)(d - a.d0) * a.pstride + e;
   double s = 0.0;
   if (e < ne) {
-    // wave wv takes leaves L0 + wv, L0 + wv + 4, ...
+    // wave wv takes groups wv, wv + 4, ... of the node (first leaf L0 + k G)
     double acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-    int L = L0 + wv;
-    const int Lend = L0 + span;
-    for (; L + 28 < Lend; L += 32) {
+    int k = wv;
+    for (; k + 28 < nk; k += 32) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int Lq = L + 4 * q;
+        const int Lq = L0 + (k + 4 * q) * G;
         if (leaf_selected(Lq, a.levels, a.sel_mode, a.sel_depth)) acc[q] += base[(long)Lq * stride];
       }
     }
-    for (; L < Lend; L += 4)
+    for (; k < nk; k += 4) {
+      const int L = L0 + k * G;
       if (leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) acc[0] += base[(long)L * stride];
+    }
 #pragma unroll
     for (int q = 0; q < 8; ++q) s += acc[q];
   }
@@ -433,26 +457,52 @@ __global__ void __launch_bounds__(256) k_reduce_tree(RedArgs a0, int dlast) {
 }
 
 // Reduce against the stacked identity S (the leaf pass): A[c]^T S[c] is the sum over
-// the leaves of c of A's leaf blocks (transposed), no product needed.  Per (leaf,
-// depth) the block is copied, through an LDS transpose when `trans`, into the same
-// partial layout the product path writes (element (i, j) at i + j * rows_out);
-// k_reduce_tree then sums the partials over each node.
+// the leaves of c of A's leaf blocks (transposed), no product needed.  A workgroup sums
+// the blocks of a group of G(d) = min(grp, 2^(levels-d)) consecutive leaves (one node's
+// at the deep depths) and writes the sum, through an LDS transpose when `trans`, into
+// the partial layout of the product path at the group's first leaf (element (i, j) at
+// i + j * rows_out), or at the leaf depth straight into the leaf's output;
+// k_reduce_tree then sums the groups of each node.  grid.z enumerates (depth, group),
+// depth-major, nleaves / G(d) groups per depth.
 __global__ void __launch_bounds__(256) k_leaf_blocks(const double* P, int ldp, ColSpec pc, int d0, int d1,
-                                                     int levels, int nl, int w, int trans, double* out,
-                                                     long out_stride, double* partial, long pstride) {
+                                                     int levels, int nl, int nleaves, int w, int trans, int grp,
+                                                     double* out, long out_stride, double* partial, long pstride) {
   __shared__ double tile[64][65];
   const int ndep = d1 - d0 + 1;
-  const int L = blockIdx.z / ndep;
-  const int d = d0 + blockIdx.z % ndep;
+  int d = d0, zr = blockIdx.z;
+  for (;;) {
+    const int span = 1 << (levels - d);
+    const int ng = nleaves / (grp < span ? grp : span);
+    if (zr < ng || d >= d1) break;
+    zr -= ng;
+    ++d;
+  }
+  const int span = 1 << (levels - d);
+  const int G = grp < span ? grp : span;
+  const int L0 = zr * G;
   const int j0 = blockIdx.x * 64, m0 = blockIdx.y * 64;
-  const double* src = P + (long)L * nl + (long)pc.c0(d) * ldp;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int t = 0; t < G; ++t) {
+    const double* src = P + (long)(L0 + t) * nl + (long)pc.c0(d) * ldp;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      const int jj = e % 64, cc = e / 64;
+      const int j = j0 + jj, mm = m0 + cc;
+      if (j < nl && mm < w) acc[q] += src[j + (long)mm * ldp];
+    }
+  }
+#pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int e = threadIdx.x + 256 * q;
-    const int jj = e % 64, cc = e / 64;
-    const int j = j0 + jj, mm = m0 + cc;
-    tile[cc][jj] = (j < nl && mm < w) ? src[j + (long)mm * ldp] : 0.0;
+    tile[e / 64][e % 64] = acc[q];
   }
   __syncthreads();
+  const int L = L0;
+  // the leaf depth (groups of one) goes straight to the output; every other depth through
+  // the partials, which k_reduce_tree sums (one group per node when G covers it)
   double* dst = (d == levels) ? out + ((1 << d) - 1 + L) * out_stride
                               : partial + ((long)L * ndep + (d - d0)) * pstride;
   for (int q = 0; q < 16; ++q) {
@@ -573,9 +623,13 @@ hm_status tree_reduce_multi(Model* m, const ReduceJob* js, int nj) {
     const int ldp = xid ? j.lda : j.ldx;
     const ColSpec pc = xid ? j.ac : j.xc;
     const int w = xid ? wa : j.xc.w0;
-    dim3 g(ceil_div(m->nl, 64), ceil_div(w, 64), m->nleaves * ndep);
-    hipLaunchKernelGGL(k_leaf_blocks, g, dim3(256), 0, m->stream, P, ldp, pc, j.d0, j.d1, m->levels, m->nl, w,
-                       xid ? 1 : 0, j.out, j.out_stride, m->d_red, (long)wa * wxmax);
+    // leaf groups of up to 8: a copy per leaf is cheap, the partials it saves are not
+    a.grp = 8;
+    long zc = 0;
+    for (int d = j.d0; d <= j.d1; ++d) zc += m->nleaves / std::min(a.grp, 1 << (m->levels - d));
+    dim3 g(ceil_div(m->nl, 64), ceil_div(w, 64), (unsigned)zc);
+    hipLaunchKernelGGL(k_leaf_blocks, g, dim3(256), 0, m->stream, P, ldp, pc, j.d0, j.d1, m->levels, m->nl,
+                       m->nleaves, w, xid ? 1 : 0, a.grp, j.out, j.out_stride, m->d_red, (long)wa * wxmax);
   } else {
     // output tile sized to the widths: MB x NB blocks of 16
     auto blocks = [](int w) {   // up to 3 x 3 blocks per tile keeps two wavefronts per SIMD
@@ -617,7 +671,7 @@ hm_status tree_reduce_multi(Model* m, const ReduceJob* js, int nj) {
       for (int q = 0; q < nj; ++q) nemax = std::max(nemax, wa * js[q].xc.w(d));
     }
     if (nemax > 0) {
-      dim3 g2(ceil_div(nemax, 64), nodes, nj);
+      dim3 g2(ceil_div(nemax, a.grp > 1 ? 256 : 64), nodes, nj);
       hipLaunchKernelGGL(k_reduce_tree, g2, dim3(256), 0, m->stream, a, dlast);
       HM_LAUNCH_CHECK();
     }
