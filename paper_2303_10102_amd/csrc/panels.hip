@@ -171,6 +171,7 @@ struct RedArgs {
   // consecutive leaves, stored at the group's first leaf (grp 1: per leaf; every
   // selection) -- the stacked-identity path writes groups, the product path leaves
   int grp = 1;
+  int wide = 0;   // tree sums: 256 elements per block, one thread per element (else 64, four waves per node's leaves)
   // Up to two further independent jobs in the same launch (grid.z = nj x the products'
   // (leaf, depth) count, job fastest so that every XCD's share of the tiles mixes the
   // jobs; grid.z = jobs of the tree sums): each has its own operands, output, X columns
@@ -407,21 +408,26 @@ __global__ void __launch_bounds__(256) k_reduce_tree(RedArgs a0, int dlast) {
   const int G = a.grp < span ? a.grp : span;   // partials at every G-th leaf of the node
   const int nk = span / G;
   const long stride = (long)ndep * a.pstride;
-  if (a.grp > 1) {
-    // grouped partials (at most nleaves / grp per node): 256 elements per block, each
-    // thread sums its element over the node's groups alone
+  if (a.wide) {
+    // 256 elements per block, each thread sums its element over the node's groups alone
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= ne) return;
     const double* base = a.partial + (long)(d - a.d0) * a.pstride + e;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int k = 0;
-    for (; k + 3 < nk; k += 4) {
+    for (; k + 7 < nk; k += 8) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] += base[(long)(L0 + (k + q) * G) * stride];
+      for (int q = 0; q < 8; ++q) {
+        const int Lq = L0 + (k + q) * G;
+        if (leaf_selected(Lq, a.levels, a.sel_mode, a.sel_depth)) acc[q] += base[(long)Lq * stride];
+      }
     }
-    for (; k < nk; ++k) acc[0] += base[(long)(L0 + k * G) * stride];
+    for (; k < nk; ++k) {
+      const int L = L0 + k * G;
+      if (leaf_selected(L, a.levels, a.sel_mode, a.sel_depth)) acc[0] += base[(long)L * stride];
+    }
     const int heap = (1 << d) - 1 + idx;
-    a.out[heap * a.out_stride + e] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    a.out[heap * a.out_stride + e] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     return;
   }
   const int e = blockIdx.x * 64 + lane;
@@ -671,7 +677,11 @@ hm_status tree_reduce_multi(Model* m, const ReduceJob* js, int nj) {
       for (int q = 0; q < nj; ++q) nemax = std::max(nemax, wa * js[q].xc.w(d));
     }
     if (nemax > 0) {
-      dim3 g2(ceil_div(nemax, a.grp > 1 ? 256 : 64), nodes, nj);
+      // one thread per element pays off for the grouped partials (few per node); with a
+      // partial per leaf the shallow nodes' sums need the four waves (measured slower
+      // otherwise: tree sums 1.29 -> 1.74 ms per iteration)
+      a.wide = a.grp > 1 ? 1 : 0;
+      dim3 g2(ceil_div(nemax, a.wide ? 256 : 64), nodes, nj);
       hipLaunchKernelGGL(k_reduce_tree, g2, dim3(256), 0, m->stream, a, dlast);
       HM_LAUNCH_CHECK();
     }
