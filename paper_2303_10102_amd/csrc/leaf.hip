@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256) k_chol_panel(double* W, int nl, int jb, d
 // The same step for leaves of at most 256 rows, with the panel in registers: thread i
 // holds row jb + i of the block column.  Step t broadcasts column t of the diagonal
 // block (rows < nb) through LDS, one barrier per step; every row then scales its
-// entry t by the pivot and updates its entries u in (t, nb) with one multiply-add each.
+// entry t by the pivot and updates its entries right of t with one multiply-add each.
 template <int CB>
 __global__ void __launch_bounds__(256) k_chol_panel_r(double* W, int nl, int jb, double* logdet, int* flags) {
   __shared__ double colt[2][CB];
@@ -140,12 +140,17 @@ __global__ void __launch_bounds__(256) k_chol_panel_r(double* W, int nl, int jb,
         R[t] = R[t] / piv;
       }
       const double lt = R[t];
-      // branch-free: entries u >= nb of the broadcast are stale and never selected
+      // Every row updates every entry right of t: an entry above the diagonal (u > i)
+      // or past the panel (u >= nb, stale broadcast) never feeds an entry on or below
+      // the diagonal and is never written out.  The broadcast reads are all issued
+      // before the first multiply-add (the empty asm takes each value).
+      double c_[CB];
 #pragma unroll
-      for (int u = t + 1; u < CB; ++u) {
-        const double v = R[u] - lt * (cb[u] * rp);
-        R[u] = (u < nb && i >= u) ? v : R[u];
-      }
+      for (int u = t + 1; u < CB; ++u) c_[u] = cb[u];
+#pragma unroll
+      for (int u = t + 1; u < CB; ++u) asm volatile("" : "+v"(c_[u]));
+#pragma unroll
+      for (int u = t + 1; u < CB; ++u) R[u] -= lt * (c_[u] * rp);
 #pragma unroll
       for (int u = t + 1; u < CB; ++u) asm volatile("" : "+v"(R[u]));
     }

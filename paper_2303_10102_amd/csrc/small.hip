@@ -36,6 +36,31 @@ __device__ __forceinline__ void axpy_strided(double* dst, long ds, const double*
   for (; c < c1; c += step) dst[c * ds] -= f * src[c * ss];
 }
 
+// X[l] -= f b[l] for l = l0..KP-1 (b in LDS, the same for every lane).  The reads of a
+// range are all issued before its first multiply-add (the empty asm takes each value),
+// so one LDS latency is paid per range rather than per pair of entries; KP = 64 runs
+// as two ranges to stay within the register file.
+template <int KP>
+__device__ __forceinline__ void axpy_row_batched(double (&X)[KP], const double* b, double f, int l0) {
+  constexpr int SP = KP > 48 ? KP / 2 : KP;
+  double c[KP];
+  const int l1 = l0 > SP ? l0 : SP;
+#pragma unroll
+  for (int l = l0; l < SP; ++l) c[l] = b[l];
+#pragma unroll
+  for (int l = l0; l < SP; ++l) asm volatile("" : "+v"(c[l]));
+#pragma unroll
+  for (int l = l0; l < SP; ++l) X[l] -= f * c[l];
+#pragma unroll
+  for (int l = l1; l < KP; ++l) c[l] = b[l];
+#pragma unroll
+  for (int l = l1; l < KP; ++l) asm volatile("" : "+v"(c[l]));
+#pragma unroll
+  for (int l = l1; l < KP; ++l) X[l] -= f * c[l];
+#pragma unroll
+  for (int l = l0; l < KP; ++l) asm volatile("" : "+v"(X[l]));
+}
+
 // ---------------------------------------------------------------------------
 // Cholesky + triangular inverse of G (k x k, ld k), one node per workgroup of two
 // wavefronts.  shift: if nonzero, G + s I with s = 11 (m k + k (k+1)) u ||.||_F^2,
@@ -44,22 +69,30 @@ __device__ __forceinline__ void axpy_strided(double* dst, long ds, const double*
 // exactly zero.
 //
 // Right-looking Cholesky fused with the forward elimination of L Y = I.  With
-// d_j = A(j, j) after step j - 1 and l_ij = A(i, j) / sqrt(d_j), step j does
-//   A(i, l) -= A(i, j) A(l, j) / d_j          (j < l <= i)
-//   Y(i, c) -= A(i, j) / d_j * Y(j, c)        (i > j)
-// and L^{-1}(i, c) = Y(i, c) / sqrt(d_i).  Both updates need only column j of A,
-// which is broadcast through LDS: lane x of wavefront 0 holds row x of A, lane x of
-// wavefront 1 column x of Y, in registers (KP >= k entries; rows and columns
-// k..KP-1 an identity block that changes nothing).  A step is one barrier and
-// KP - j - 1 broadcast reads, each feeding one fused multiply-add per lane.  A pivot
-// that is not positive is flagged and taken as 1.
+// d_j = A(j, j) after step j - 1, f_ij = A(i, j) / d_j and l_ij = A(i, j) / sqrt(d_j),
+// step j does
+//   A(i, l) -= f_ij A(l, j)          (j < l <= i)
+//   Y(i, c) -= f_ij Y(j, c)          (i > j)
+// and L^{-1}(i, c) = Y(i, c) / sqrt(d_i).  Lane x of wavefront 0 holds row x of A, lane
+// x of wavefront 1 column x of Y, in registers (KP >= k entries; rows and columns
+// k..KP-1 an identity block that changes nothing).  Step j broadcasts column j of A
+// through LDS; the rows' wavefront forms the multipliers f_xj and publishes them, and
+// the Y wavefront applies step j one barrier later, so each wavefront's step is one
+// broadcast read and one fused multiply-add per entry.  The rows' wavefront updates the
+// whole row: entries right of the diagonal never feed an entry on or left of it (the
+// update of A(i, l), l <= i, reads A(i, j) and A(l, j) with j < l), so they may hold
+// anything and are not written out.  A pivot that is not positive is flagged and
+// taken as 1.  R is staged through LDS so that its columns leave as contiguous stores.
 // ---------------------------------------------------------------------------
 template <int KP>
 __global__ void __launch_bounds__(128) k_chol_inv(const double* G, long gstride, double* R, double* Rinv,
                                                   long rstride, int k, const int* kblk, int heap0, int hstep,
                                                   int shift, long mrows, int* flags) {
-  __shared__ double colj[2][64];
-  __shared__ double dd[64];
+  constexpr int LDR = KP + 1;
+  __shared__ double colj[2][64];   // column j of A
+  __shared__ double fj[2][64];     // multipliers f_xj of step j
+  __shared__ double sqd[64];       // sqrt(d_x)
+  __shared__ double Rs[KP * LDR];  // R(i, x) at i + x LDR
   const int node = heap0 + blockIdx.x * hstep;
   // kept rank of the block whose left child is this node (kblk indexed by parent)
   const int kp = kblk ? kblk[(node - 1) >> 1] : k;
@@ -101,49 +134,42 @@ __global__ void __launch_bounds__(128) k_chol_inv(const double* G, long gstride,
         d = 1.0;
       }
       if (lane == j) myd = d;
-      const double f = X[j] * (1.0 / d);   // the row's multiplier A(x, j) / d_j
-#pragma unroll
-      for (int l = j + 1; l < KP; ++l) {
-        const double al = X[l] - f * cb[l];
-        X[l] = (l <= lane) ? al : X[l];
-      }
-#pragma unroll
-      for (int l = j + 1; l < KP; ++l) asm volatile("" : "+v"(X[l]));
+      const double f = X[j] * (1.0 / d);
+      fj[j & 1][lane] = f;
+      axpy_row_batched<KP>(X, cb, f, j + 1);
     }
   } else {
 #pragma unroll
     for (int j = 0; j < KP; ++j) {
-      const double* cb = colj[j & 1];
       __syncthreads();
-      double d = cb[j];
-      if (!(d > 0.0)) d = 1.0;
-      if (lane == j) myd = d;
-      const double rd = 1.0 / d;
-      const double f = X[j];   // Y(j, x)
-#pragma unroll
-      for (int l = j + 1; l < KP; ++l) X[l] -= (cb[l] * rd) * f;
-#pragma unroll
-      for (int l = j + 1; l < KP; ++l) asm volatile("" : "+v"(X[l]));
+      if (j > 0) {   // step j - 1, its multipliers published before this barrier
+        const double y = X[j - 1];
+        axpy_row_batched<KP>(X, fj[(j - 1) & 1], y, j);
+      }
     }
+    // step KP - 1 updates no entry
   }
   if (bad && threadIdx.x == 0) atomicOr(flags, (int)DF_QR_FAIL);
-  if (rows) dd[lane] = myd;
+  if (rows) sqd[lane] = sqrt(myd);
   __syncthreads();
-  if (lane < k) {
-    if (rows) {
-      // R = L^T (upper): column j of R is row j of L, held by lane j
-      double* Ro = R + node * rstride + (long)lane * k;
-      const double sj = sqrt(myd);
+  if (rows) {
+    // R = L^T (upper): column x of R is row x of L, held by lane x
+    const double sx = sqrt(myd);
 #pragma unroll
-      for (int i = 0; i < KP; ++i)
-        if (i < k) Ro[i] = (i < lane) ? X[i] / sqrt(dd[i]) : (i == lane ? sj : 0.0);
-    } else {
-      // Rinv = (L^{-1})^T: Rinv(i, j) = Y(j, i) / sqrt(d_j) for j >= i; row i held by lane i
-      double* Ri = Rinv + node * rstride + lane;
+    for (int i = 0; i < KP; ++i)
+      if (lane < KP) Rs[i + lane * LDR] = (i < lane) ? X[i] / sqd[i] : (i == lane ? sx : 0.0);
+  } else if (lane < k) {
+    // Rinv = (L^{-1})^T: Rinv(i, j) = Y(j, i) / sqrt(d_j) for j >= i; row i held by lane i
+    double* Ri = Rinv + node * rstride + lane;
 #pragma unroll
-      for (int j = 0; j < KP; ++j)
-        if (j < k) Ri[(long)j * k] = (j >= lane) ? X[j] / sqrt(dd[j]) : 0.0;
-    }
+    for (int j = 0; j < KP; ++j)
+      if (j < k) Ri[(long)j * k] = (j >= lane) ? X[j] / sqd[j] : 0.0;
+  }
+  __syncthreads();
+  double* Ro = R + node * rstride;
+  for (int e = threadIdx.x; e < k * k; e += 128) {
+    const int i = e % k, x = e / k;
+    Ro[e] = Rs[i + x * LDR];
   }
 }
 
@@ -275,14 +301,38 @@ __global__ void __launch_bounds__(256) k_node_lu(const double* S, long sstride, 
 #pragma unroll
         for (int c = 0; c < KP; ++c) rb[c] = X[c];
       }
+      // the pivot lane's stores are ordered before every lane's reads (a wavefront-scope
+      // release and acquire: without them the compiler may hoist the other lanes' reads
+      // above the stores, as it sees no dependence between lanes)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // the pivot row's entries are all read before the first multiply-add (the empty
+      // asm takes each value), so one LDS latency is paid per half row
+      constexpr int SP = KP > 32 ? KP / 2 : KP;
+      double c_[KP];
+#pragma unroll
+      for (int c = 0; c < SP; ++c) c_[c] = rb[c];
+#pragma unroll
+      for (int c = 0; c < SP; ++c) asm volatile("" : "+v"(c_[c]));
+#pragma unroll
+      for (int c = SP; c < KP; ++c) c_[c] = rb[c];
       if (wave == 0) {
         // columns j+1.. (X[1..]) minus f times the pivot row's, shifted down by one
 #pragma unroll
-        for (int c = 0; c + 1 < KP; ++c) X[c] = X[c + 1] - f * rb[c + 1];
+        for (int c = 0; c + 1 < SP; ++c) X[c] = X[c + 1] - f * c_[c + 1];
+#pragma unroll
+        for (int c = SP; c < KP; ++c) asm volatile("" : "+v"(c_[c]));
+#pragma unroll
+        for (int c = SP - 1; c + 1 < KP; ++c) X[c] = X[c + 1] - f * c_[c + 1];
         X[KP - 1] = 0.0;
       } else {
 #pragma unroll
-        for (int c = 0; c < KP; ++c) X[c] -= f * rb[c];
+        for (int c = 0; c < SP; ++c) X[c] -= f * c_[c];
+#pragma unroll
+        for (int c = SP; c < KP; ++c) asm volatile("" : "+v"(c_[c]));
+#pragma unroll
+        for (int c = SP; c < KP; ++c) X[c] -= f * c_[c];
       }
 #pragma unroll
       for (int c = 0; c < KP; ++c) asm volatile("" : "+v"(X[c]));
