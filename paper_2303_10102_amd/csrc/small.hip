@@ -12,6 +12,7 @@
 
 #include "hm_internal.h"
 #include "gemm_core.h"
+#include "wave_ops.h"
 
 namespace hm {
 
@@ -213,13 +214,6 @@ __device__ __forceinline__ hm_v4d node_mm_tile(const double* A, const double* B,
   return acc;
 }
 
-__device__ __forceinline__ double readlane_d(double v, int src) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
 template <int KP>
 __global__ void __launch_bounds__(256) k_node_lu(const double* S, long sstride, double* Nout, long nstride,
                                                  double* logdet, int k, int heap0, int* flags) {
@@ -277,12 +271,7 @@ __global__ void __launch_bounds__(256) k_node_lu(const double* S, long sstride, 
         if (!(best <= INFINITY)) best = INFINITY;   // NaN ranks first: the order stays total
         bi = lane;
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      const int p = __builtin_amdgcn_readfirstlane(bi);
+      const int p = __builtin_amdgcn_readfirstlane(wave_argmax(best, bi));
       const double pv = readlane_d(X[0], p);
       const double rp = (pv != 0.0) ? 1.0 / pv : 0.0;
       mul[j & 1][lane] = (lane != p) ? X[0] * rp : 0.0;
