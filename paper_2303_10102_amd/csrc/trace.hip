@@ -421,11 +421,11 @@ hm_status node_lam(FactorCtx& f, ParamBufs& pb, double* tbuf, double* dsbuf) {
   hipLaunchKernelGGL(k_node_dS, dim3(ceil_div((nodes - 1) * s2, 256)), dim3(256), 0, m->stream, pb.E, pb.W, dsbuf,
                      kc, nodes);
   HM_LAUNCH_CHECK();
-  // T = [N[:,0:k] dS_a, N[:,k:2k] dS_b]
-  HM_CHECK(gemm(m->stream, false, false, m2, kc, kc, 1.0, f.Nn, m2, ms, dsbuf + s2, kc, 2 * s2, 0.0, tbuf, m2, ms,
-                nint));
-  HM_CHECK(gemm(m->stream, false, false, m2, kc, kc, 1.0, f.Nn + (long)kc * m2, m2, ms, dsbuf + 2 * s2, kc, 2 * s2,
-                0.0, tbuf + (long)kc * m2, m2, ms, nint));
+  // T = [N[:,0:k] dS_a, N[:,k:2k] dS_b]: one batch over (P, half h), b = 2P + h, whose
+  // operands sit at uniform strides: the column half of N_P and of T at b (2 k^2) (a
+  // half is k columns of 2k rows), dS of child 2P + 1 + h at (b + 1) k^2
+  HM_CHECK(gemm(m->stream, false, false, m2, kc, kc, 1.0, f.Nn, m2, 2 * s2, dsbuf + s2, kc, s2, 0.0, tbuf, m2,
+                2 * s2, 2 * nint));
   HM_CHECK(gemm(m->stream, false, false, m2, m2, m2, 1.0, tbuf, m2, ms, f.Nn, m2, ms, 0.0, pb.Lam, m2, ms, nint));
   // Vt_a = W_b^T N21,  Vt_b = W_a^T N12
   HM_CHECK(gemm(m->stream, true, false, kc, kc, kc, 1.0, pb.W + 2 * s2, kc, 2 * s2, f.Nn + kc, m2, ms, 0.0,
